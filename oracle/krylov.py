@@ -1,0 +1,138 @@
+"""Block-triangular preconditioner and FGMRES (oracle).
+
+The preconditioner is the paper's P_L (eq. lpre): with K = [A B1^T; B2 -C],
+    P_L^{-1} [r_u; r_p] = [z_u; z_p],  z_u = Atilde^{-1} r_u,
+    z_p = Stilde^{-1} (B2 z_u - r_p),
+where Atilde^{-1} is one AMG V-cycle on A and Stilde = (1/theta + 1/kappa)
+diag(M_p) (eq. lpreschur).  The Krylov method is right-preconditioned
+flexible GMRES(m) with classical Gram-Schmidt and one re-orthogonalisation
+(CGS2) and Givens rotations; the paper itself uses BiCGStab here.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from . import amg
+
+
+def split(r, n):
+    r = r.reshape(n, 4)
+    return r[:, 0:3].ravel(), r[:, 3].copy()
+
+
+def join(zu, zp, n):
+    z = np.empty((n, 4))
+    z[:, 0:3] = zu.reshape(n, 3)
+    z[:, 3] = zp
+    return z.ravel()
+
+
+class BlockPreconditioner:
+    """P_L^{-1} with Atilde^{-1} given as a callable on displacement vectors."""
+
+    def __init__(self, a_inv, B2, s, n):
+        self.a_inv, self.B2, self.s, self.n = a_inv, B2, s, n
+
+    def __call__(self, r):
+        ru, rp = split(r, self.n)
+        zu = self.a_inv(ru)
+        zp = (self.B2 @ zu - rp) / self.s
+        return join(zu, zp, self.n)
+
+
+def amg_preconditioner(A, B2, s, n, prm=amg.AmgParams()):
+    comp = np.tile(np.arange(3), n)
+    H = amg.setup(A, comp, prm)
+    return BlockPreconditioner(lambda r: amg.vcycle(H, r, prm), B2, s, n), H
+
+
+@dataclasses.dataclass
+class SolveInfo:
+    iterations: int = 0
+    restarts: int = 0
+    rel_residual: float = np.inf
+    converged: bool = False
+    breakdown: bool = False
+    history: list = dataclasses.field(default_factory=list)
+
+
+def fgmres(K, precond, b, x0=None, m=50, maxit=500, tol=1e-8):
+    """Solve K x = b to ||b - K x||_2 <= tol ||b||_2.
+
+    Per restart cycle: v_0 = r/||r||; for j: z_j = M^{-1} v_j, w = K z_j,
+    two classical Gram-Schmidt passes against v_0..v_j, h_{j+1,j} = ||w||;
+    Givens rotations c = h_jj / sqrt(h_jj^2 + h_{j+1,j}^2),
+    s = h_{j+1,j} / sqrt(...) reduce the Hessenberg matrix; the cycle ends
+    when |g_{j+1}| <= tol ||b||, on breakdown (h_{j+1,j} <= 1e-14 ||w_0||)
+    or after m steps; x += Z y.  The true residual is recomputed after every
+    cycle and decides convergence.
+    """
+    n = b.shape[0]
+    x = np.zeros(n) if x0 is None else x0.copy()
+    info = SolveInfo()
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        x[:] = 0.0
+        info.rel_residual, info.converged = 0.0, True
+        return x, info
+    r = b - K @ x
+    beta = np.linalg.norm(r)
+    info.rel_residual = beta / bnorm
+    if beta <= tol * bnorm:
+        info.converged = True
+        return x, info
+    while info.iterations < maxit:
+        V = np.zeros((m + 1, n))
+        Z = np.zeros((m, n))
+        H = np.zeros((m + 1, m))
+        cs, sn = np.zeros(m), np.zeros(m)
+        g = np.zeros(m + 1)
+        V[0] = r / beta
+        g[0] = beta
+        j_end = 0
+        for j in range(m):
+            Z[j] = precond(V[j])
+            w = K @ Z[j]
+            w0 = np.linalg.norm(w)
+            h = V[:j + 1] @ w
+            w = w - V[:j + 1].T @ h
+            h2 = V[:j + 1] @ w
+            w = w - V[:j + 1].T @ h2
+            H[:j + 1, j] = h + h2
+            H[j + 1, j] = np.linalg.norm(w)
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            d = np.hypot(H[j, j], H[j + 1, j])
+            hj1 = H[j + 1, j]
+            cs[j], sn[j] = H[j, j] / d, hj1 / d
+            H[j, j] = d
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            info.iterations += 1
+            info.history.append(abs(g[j + 1]) / bnorm)
+            j_end = j + 1
+            if abs(g[j + 1]) <= tol * bnorm or info.iterations >= maxit:
+                break
+            if hj1 <= 1e-14 * w0:
+                info.breakdown = True
+                break
+            V[j + 1] = w / hj1
+        y = np.zeros(j_end)
+        for i in range(j_end - 1, -1, -1):
+            y[i] = (g[i] - H[i, i + 1:j_end] @ y[i + 1:]) / H[i, i]
+        x = x + Z[:j_end].T @ y
+        r = b - K @ x
+        beta = np.linalg.norm(r)
+        info.rel_residual = beta / bnorm
+        if beta <= tol * bnorm:
+            info.converged = True
+            break
+        if info.breakdown:
+            break
+        info.restarts += 1
+    return x, info

@@ -1,0 +1,66 @@
+"""Newton's method for the stabilised solid problem (oracle).
+
+Section "Newton's Method": assemble K(v_k), solve K dv = -R(v_k) to a
+relative residual eps_1, update v_{k+1} = v_k + dv and stop when
+||dv_k||_M <= eps_2 ||dv_0||_M (eq. newstop in the mass-matrix form with
+M = diag(M1, M2)).  Loads are applied in increments lambda = k / n_inc,
+each starting from the previous converged state.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from . import amg, fe, krylov
+
+
+@dataclasses.dataclass
+class NewtonParams:
+    eps2: float = 1e-10
+    max_iter: int = 25
+    lin_tol: float = 1e-8
+    restart: int = 50
+    lin_maxit: int = 500
+    amg: amg.AmgParams = dataclasses.field(default_factory=amg.AmgParams)
+
+
+def linear_system(disc: fe.Discretization, v, load):
+    """Dirichlet-eliminated K (CSR), right-hand side -R, blocks A, B2, s."""
+    R, val = disc.assemble(v, load)
+    R, val = disc.apply_dirichlet(R, val)
+    K = disc.csr(val)
+    A, B2, s = disc.blocks(val)
+    return K, -R, A, B2, s
+
+
+def newton_step(disc, v, load, prm: NewtonParams):
+    """One Newton update; returns (v_new, ||dv||_M, solve info)."""
+    K, b, A, B2, s = linear_system(disc, v.ravel(), load)
+    M, _ = krylov.amg_preconditioner(A, B2, s, disc.n, prm.amg)
+    dv, info = krylov.fgmres(K, M, b, m=prm.restart, maxit=prm.lin_maxit, tol=prm.lin_tol)
+    return v.ravel() + dv, disc.mass_norm(dv), info
+
+
+def solve_increment(disc, v, load, prm: NewtonParams, log=None):
+    v = v.ravel().copy()
+    n0 = None
+    for k in range(prm.max_iter):
+        v, nrm, info = newton_step(disc, v, load, prm)
+        if log is not None:
+            log.append(dict(load=load, it=k, dv_M=nrm, krylov=info.iterations,
+                            rel_res=info.rel_residual))
+        if n0 is None:
+            n0 = nrm
+        if nrm <= prm.eps2 * n0 or n0 == 0.0:
+            return v, True, k + 1
+    return v, False, prm.max_iter
+
+
+def load_run(disc, n_inc, prm: NewtonParams, log=None):
+    v = np.zeros(4 * disc.n)
+    for k in range(1, n_inc + 1):
+        v, ok, _ = solve_increment(disc, v, k / n_inc, prm, log)
+        if not ok:
+            raise RuntimeError(f"Newton did not converge at increment {k}")
+    return v

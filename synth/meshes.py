@@ -1,0 +1,288 @@
+"""Structured tetrahedral meshes and boundary data for the solid sub-problem.
+
+The paper meshes its artery with an external mesh generator (Section
+"Coarse and fine meshes"); those meshes are not available, so these seeded
+lattice meshes stand in for them:
+
+* a unit cube of N^3 hexahedra, each split into the six Kuhn tetrahedra that
+  share the hexahedron's main diagonal (conforming across hexahedra);
+* a thick-walled two-layer tube (media inside, adventitia outside), periodic
+  in the circumferential direction, split the same way in index space.
+
+Every function is deterministic given its arguments (jitter and random
+states use ``numpy.random.default_rng(seed)``).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+# The six axis permutations; tetrahedron k of a hexahedron walks from corner
+# (0,0,0) along axis perm[0], then perm[1], to corner (1,1,1).
+KUHN_PERMS = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
+
+
+def _kuhn_offsets():
+    """Corner offsets (6 tets x 4 corners x 3) of the Kuhn split of a unit hex."""
+    out = np.zeros((6, 4, 3), dtype=np.int64)
+    for t, perm in enumerate(KUHN_PERMS):
+        c = np.zeros(3, dtype=np.int64)
+        out[t, 0] = c
+        c = c.copy(); c[perm[0]] = 1; out[t, 1] = c
+        c = c.copy(); c[perm[1]] = 1; out[t, 2] = c
+        out[t, 3] = (1, 1, 1)
+    return out
+
+
+def _signed_volume6(X, tets):
+    x0 = X[tets[:, 0]]
+    d = np.stack([X[tets[:, 1]] - x0, X[tets[:, 2]] - x0, X[tets[:, 3]] - x0], axis=2)
+    return np.linalg.det(d)
+
+
+def _orient(X, tets):
+    """Swap the last two corners of every negatively oriented tetrahedron."""
+    vol6 = _signed_volume6(X, tets)
+    neg = vol6 < 0
+    tets = tets.copy()
+    tets[neg, 2], tets[neg, 3] = tets[neg, 3].copy(), tets[neg, 2].copy()
+    return tets
+
+
+def _lattice_tets(shape, node_id, periodic_axis=None):
+    """Kuhn tetrahedra of a lattice of hexahedra.
+
+    shape: number of hexahedra per axis (n0, n1, n2).
+    node_id(i0, i1, i2) -> node index arrays (with wrap on ``periodic_axis``).
+    Elements are ordered hexahedron by hexahedron (axis 0 fastest), six
+    tetrahedra per hexahedron in KUHN_PERMS order.
+    """
+    n0, n1, n2 = shape
+    i2, i1, i0 = np.meshgrid(np.arange(n2), np.arange(n1), np.arange(n0), indexing="ij")
+    base = np.stack([i0.ravel(), i1.ravel(), i2.ravel()], axis=1)  # (nhex, 3)
+    offs = _kuhn_offsets()
+    tets = np.empty((base.shape[0], 6, 4), dtype=np.int64)
+    for t in range(6):
+        for a in range(4):
+            c = base + offs[t, a]
+            tets[:, t, a] = node_id(c[:, 0], c[:, 1], c[:, 2])
+    hex_ijk = base
+    return tets.reshape(-1, 4), np.repeat(hex_ijk, 6, axis=0)
+
+
+def cube_mesh(N: int, jitter: float = 0.0, seed: int = 0, side: float = 1.0):
+    """Unit cube [0,side]^3 of N^3 hexahedra split into 6N^3 tetrahedra.
+
+    Node (i,j,k) has index i + (N+1)*(j + (N+1)*k) and reference position
+    side*(i,j,k)/N.  ``jitter`` moves every interior node by
+    U(-jitter*h, jitter*h)^3, h = side/N (boundary nodes stay on their faces).
+    """
+    n1 = N + 1
+    k, j, i = np.meshgrid(np.arange(n1), np.arange(n1), np.arange(n1), indexing="ij")
+    lattice = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1).astype(np.int32)
+    h = side / N
+    X = lattice.astype(np.float64) * h
+    if jitter > 0.0:
+        rng = np.random.default_rng(seed)
+        d = rng.uniform(-jitter * h, jitter * h, size=X.shape)
+        interior = np.all((lattice > 0) & (lattice < N), axis=1)
+        X[interior] += d[interior]
+
+    def node_id(a, b, c):
+        return a + n1 * (b + n1 * c)
+
+    tets, hex_ijk = _lattice_tets((N, N, N), node_id)
+    tets = _orient(X, tets)
+    return dict(X=X, tets=tets.astype(np.int32), mat_id=np.zeros(len(tets), np.int32),
+                lattice=lattice, hex_ijk=hex_ijk.astype(np.int32), h=h)
+
+
+def tube_radii(r_in=0.71, media=0.26, adventitia=0.13, n_media=5, n_adv=3):
+    """Radial node positions: n_media equal media cells then n_adv adventitia cells."""
+    rm = r_in + media * np.arange(n_media + 1) / n_media
+    ra = r_in + media + adventitia * np.arange(1, n_adv + 1) / n_adv
+    return np.concatenate([rm, ra])
+
+
+def tube_mesh(n_theta=64, n_media=5, n_adv=3, n_z=128, r_in=0.71, media=0.26,
+              adventitia=0.13, length=5.0, alpha_media_deg=29.0, alpha_adv_deg=62.0):
+    """Two-layer thick-walled tube, periodic in theta, axis = z.
+
+    Lattice index (a, b, c) = (theta, radial, axial); node index
+    a + n_theta*(b + (n_r+1)*c).  Material id 0 (media) for radial cells
+    b < n_media, 1 (adventitia) otherwise.  The fibre vectors of each element
+    are cos(alpha) e_theta +/- sin(alpha) e_z of the local cylindrical basis at
+    the element centroid.
+    """
+    n_r = n_media + n_adv
+    radii = tube_radii(r_in, media, adventitia, n_media, n_adv)
+    c, b, a = np.meshgrid(np.arange(n_z + 1), np.arange(n_r + 1), np.arange(n_theta), indexing="ij")
+    lattice = np.stack([a.ravel(), b.ravel(), c.ravel()], axis=1).astype(np.int32)
+    theta = 2.0 * math.pi * lattice[:, 0] / n_theta
+    r = radii[lattice[:, 1]]
+    z = length * lattice[:, 2] / n_z
+    X = np.stack([r * np.cos(theta), r * np.sin(theta), z], axis=1)
+
+    def node_id(ia, ib, ic):
+        return (ia % n_theta) + n_theta * (ib + (n_r + 1) * ic)
+
+    tets, hex_ijk = _lattice_tets((n_theta, n_r, n_z), node_id)
+    tets = _orient(X, tets)
+    mat_id = (hex_ijk[:, 1] >= n_media).astype(np.int32)
+    cen = X[tets].mean(axis=1)
+    rr = np.hypot(cen[:, 0], cen[:, 1])
+    e_t = np.stack([-cen[:, 1] / rr, cen[:, 0] / rr, np.zeros_like(rr)], axis=1)
+    e_z = np.tile(np.array([0.0, 0.0, 1.0]), (len(tets), 1))
+    alpha = np.where(mat_id == 0, math.radians(alpha_media_deg), math.radians(alpha_adv_deg))[:, None]
+    fib = np.stack([np.cos(alpha) * e_t + np.sin(alpha) * e_z,
+                    np.cos(alpha) * e_t - np.sin(alpha) * e_z], axis=1)
+    return dict(X=X, tets=tets.astype(np.int32), mat_id=mat_id, lattice=lattice,
+                hex_ijk=hex_ijk.astype(np.int32), fibres=fib, radii=radii)
+
+
+def boundary_faces(tets):
+    """Triangles (sorted node triples) that belong to exactly one tetrahedron."""
+    f = np.concatenate([tets[:, [1, 2, 3]], tets[:, [0, 2, 3]], tets[:, [0, 1, 3]], tets[:, [0, 1, 2]]])
+    f = np.sort(f, axis=1)
+    uniq, cnt = np.unique(f, axis=0, return_counts=True)
+    return uniq[cnt == 1].astype(np.int32)
+
+
+@dataclasses.dataclass
+class Problem:
+    """One solid sub-problem: mesh, materials, Dirichlet mask and dead traction."""
+    X: np.ndarray            # f64 [n,3] reference coordinates
+    tets: np.ndarray         # i32 [m,4] positively oriented
+    mat_id: np.ndarray       # i32 [m]
+    materials: list          # list of dicts (model, c10, c01, kappa, k1, k2)
+    dir_mask: np.ndarray     # u8 [n,4]: 1 = dof fixed to zero
+    tris: np.ndarray         # i32 [k,3] loaded boundary triangles
+    traction: np.ndarray     # f64 [k,3] nominal traction at load factor 1
+    lattice: np.ndarray      # i32 [n,3] lattice index of each node
+    fibres: np.ndarray | None = None   # f64 [m,2,3] (anisotropic model)
+    name: str = ""
+
+    @property
+    def n_nodes(self):
+        return self.X.shape[0]
+
+    @property
+    def n_tets(self):
+        return self.tets.shape[0]
+
+    @property
+    def n_dofs(self):
+        return 4 * self.X.shape[0]
+
+
+def mooney_rivlin(c10=0.5, c01=0.1, kappa=1e4):
+    return dict(model=0, c10=float(c10), c01=float(c01), kappa=float(kappa), k1=0.0, k2=0.0)
+
+
+def artery_layer(c10, k1, k2, kappa=1e5):
+    return dict(model=1, c10=float(c10), c01=0.0, kappa=float(kappa), k1=float(k1), k2=float(k2))
+
+
+def cube_problem(N=8, kappa=1e4, c10=0.5, c01=0.1, traction=(0.0, 0.0, 0.05), jitter=0.0,
+                 seed=0, materials=None):
+    """Cube clamped (u=0) on x=0, dead traction on the face x=1; p free everywhere."""
+    m = cube_mesh(N, jitter=jitter, seed=seed)
+    lat = m["lattice"]
+    n = len(lat)
+    dm = np.zeros((n, 4), np.uint8)
+    dm[lat[:, 0] == 0, 0:3] = 1
+    bf = boundary_faces(m["tets"])
+    on_x1 = np.all(lat[bf][:, :, 0] == N, axis=1)
+    tris = bf[on_x1]
+    tr = np.tile(np.asarray(traction, np.float64), (len(tris), 1))
+    mats = materials if materials is not None else [mooney_rivlin(c10, c01, kappa)]
+    return Problem(m["X"], m["tets"], m["mat_id"], mats, dm, tris, tr, lat, None,
+                   name=f"cube{N}")
+
+
+def uniaxial_problem(N=2, kappa=1e4, c10=0.5, c01=0.1, stress=0.05, materials=None,
+                     fibres=None):
+    """Cube with roller supports (u_x=0 on x=0, u_y=0 on y=0, u_z=0 on z=0) and
+    a dead normal traction ``stress`` in +x on x=1: a homogeneous state."""
+    m = cube_mesh(N)
+    lat = m["lattice"]
+    n = len(lat)
+    dm = np.zeros((n, 4), np.uint8)
+    for c in range(3):
+        dm[lat[:, c] == 0, c] = 1
+    bf = boundary_faces(m["tets"])
+    tris = bf[np.all(lat[bf][:, :, 0] == N, axis=1)]
+    tr = np.tile(np.array([stress, 0.0, 0.0]), (len(tris), 1))
+    mats = materials if materials is not None else [mooney_rivlin(c10, c01, kappa)]
+    fib = None
+    if fibres is not None:
+        fib = np.tile(np.asarray(fibres, np.float64)[None], (len(m["tets"]), 1, 1))
+    return Problem(m["X"], m["tets"], m["mat_id"], mats, dm, tris, tr, lat, fib,
+                   name=f"uniaxial{N}")
+
+
+ARTERY_MEDIA = dict(c10=3.0, k1=2.3632, k2=0.8393)
+ARTERY_ADVENTITIA = dict(c10=0.3, k1=0.562, k2=0.7112)
+
+
+def tube_problem(n_theta=64, n_media=5, n_adv=3, n_z=128, kappa=1e5, p_int=13.3, **kw):
+    """Artery tube: u=0 on both ends z=0 and z=length; dead internal pressure
+    p_int * e_r(centroid) on the inner surface (per unit reference area)."""
+    m = tube_mesh(n_theta, n_media, n_adv, n_z, **kw)
+    lat = m["lattice"]
+    n = len(lat)
+    dm = np.zeros((n, 4), np.uint8)
+    ends = (lat[:, 2] == 0) | (lat[:, 2] == n_z)
+    dm[ends, 0:3] = 1
+    bf = boundary_faces(m["tets"])
+    inner = np.all(lat[bf][:, :, 1] == 0, axis=1)
+    tris = bf[inner]
+    cen = m["X"][tris].mean(axis=1)
+    rr = np.hypot(cen[:, 0], cen[:, 1])
+    er = np.stack([cen[:, 0] / rr, cen[:, 1] / rr, np.zeros_like(rr)], axis=1)
+    tr = p_int * er
+    mats = [artery_layer(kappa=kappa, **ARTERY_MEDIA), artery_layer(kappa=kappa, **ARTERY_ADVENTITIA)]
+    return Problem(m["X"], m["tets"], m["mat_id"], mats, dm, tris, tr, lat, m["fibres"],
+                   name=f"tube{n_theta}x{n_media + n_adv}x{n_z}")
+
+
+def random_state(prob: Problem, seed: int, u_scale=0.02, p_scale=0.1):
+    """Seeded smooth-ish random state v [n,4] that satisfies the Dirichlet mask."""
+    rng = np.random.default_rng(seed)
+    n = prob.n_nodes
+    X = prob.X
+    ext = X.max(axis=0) - X.min(axis=0)
+    # a random affine field plus small nodal noise keeps every element far from inversion
+    Fm = rng.uniform(-1, 1, size=(3, 3)) * u_scale / max(ext.max(), 1e-12)
+    v = np.zeros((n, 4))
+    v[:, 0:3] = X @ Fm.T + rng.uniform(-1, 1, size=(n, 3)) * u_scale * 0.1
+    v[:, 3] = rng.uniform(-1, 1, size=n) * p_scale
+    v[prob.dir_mask.astype(bool)] = 0.0
+    return v
+
+
+def config_problem(name: str, kappa=None, N=None):
+    """The solid workloads, by name:
+
+    * ``cube8``  : 8^3 cube, Mooney-Rivlin c10=0.5 c01=0.1 kappa=1e4, clamped
+      at x=0, dead traction (0,0,0.05) on x=1 (2,916 dofs);
+    * ``cube48`` : the same physics on 48^3 hexahedra (470,596 dofs);
+    * ``cube96`` : the same on 96^3 hexahedra (3,650,692 dofs);
+    * ``tube``   : the two-layer artery tube 64 x 8 x 128 (297,216 dofs),
+      kappa=1e5, internal dead pressure 13.3 at load factor 1.
+    """
+    if name.startswith("cube"):
+        n = N if N is not None else int(name[4:])
+        return cube_problem(n, kappa=1e4 if kappa is None else kappa)
+    if name == "tube":
+        return tube_problem(kappa=1e5 if kappa is None else kappa)
+    if name.startswith("tube_small"):
+        return tube_problem(n_theta=16, n_z=8, kappa=1e5 if kappa is None else kappa)
+    raise ValueError(name)
+
+
+__all__ = ["Problem", "cube_mesh", "tube_mesh", "boundary_faces", "cube_problem",
+           "tube_problem", "uniaxial_problem", "random_state", "config_problem",
+           "mooney_rivlin", "artery_layer", "KUHN_PERMS"]

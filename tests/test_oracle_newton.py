@@ -1,0 +1,96 @@
+"""End-to-end pins of the oracle's Newton solve.
+
+A cube on rollers under a dead uniaxial traction sigma has a homogeneous
+solution F = diag(l1, l2, l3), p = -kappa (J - 1), which P1 elements
+represent exactly.  Its stretches make the potential per unit reference
+volume  Pi = Psi_dev(C) + kappa/2 (J-1)^2 - sigma (l1 - 1)  stationary
+(the energies of eq. mmreng and eq. areng written in principal stretches);
+an independent three-unknown Newton solve of grad Pi = 0 fixes them.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import amg, fe, newton
+
+
+def _pi(l, law, mat, alpha, sigma):
+    l1, l2, l3 = l
+    J = l1 * l2 * l3
+    I1 = l1 ** 2 + l2 ** 2 + l3 ** 2
+    I2 = (l1 * l2) ** 2 + (l2 * l3) ** 2 + (l3 * l1) ** 2
+    psi = 0.5 * mat["c10"] * (I1 * J ** (-2 / 3) - 3)
+    if law == "mr":
+        psi += 0.5 * mat["c01"] * (I2 * J ** (-4 / 3) - 3)
+    else:
+        J4 = J ** (-2 / 3) * (np.cos(alpha) ** 2 * l1 ** 2 + np.sin(alpha) ** 2 * l2 ** 2)
+        if J4 > 1:
+            psi += 2 * mat["k1"] / (2 * mat["k2"]) * (np.exp(mat["k2"] * (J4 - 1) ** 2) - 1)
+    return psi + 0.5 * mat["kappa"] * (J - 1) ** 2 - sigma * (l1 - 1)
+
+
+def _stretches(law, mat, alpha, sigma):
+    l = np.ones(3)
+    for s in np.linspace(0.0, sigma, 21)[1:]:   # load continuation
+        l = _newton3(l, law, mat, alpha, s)
+    return l
+
+
+def _newton3(l, law, mat, alpha, sigma):
+    h = 1e-5
+    for _ in range(50):
+        g = np.zeros(3)
+        H = np.zeros((3, 3))
+        for i in range(3):
+            e = np.zeros(3); e[i] = h
+            g[i] = (_pi(l + e, law, mat, alpha, sigma) - _pi(l - e, law, mat, alpha, sigma)) / (2 * h)
+            for j in range(3):
+                f = np.zeros(3); f[j] = h
+                H[i, j] = (_pi(l + e + f, law, mat, alpha, sigma) - _pi(l + e - f, law, mat, alpha, sigma)
+                           - _pi(l - e + f, law, mat, alpha, sigma) + _pi(l - e - f, law, mat, alpha, sigma)) / (4 * h * h)
+        dl = np.linalg.solve(H, -g)
+        l = l + dl
+        if np.abs(dl).max() < 1e-13:
+            break
+    return l
+
+
+@pytest.mark.parametrize("law", ["mr", "artery"])
+def test_uniaxial_homogeneous_solution(law):
+    sigma = 0.4 if law == "mr" else 2.0
+    alpha = np.radians(29.0)
+    if law == "mr":
+        mat = synth.meshes.mooney_rivlin(0.5, 0.1, 1e3)
+        prob = synth.uniaxial_problem(2, stress=sigma, materials=[mat])
+    else:
+        mat = synth.meshes.artery_layer(3.0, 2.3632, 0.8393, 1e3)
+        fib = [[np.cos(alpha), np.sin(alpha), 0.0], [np.cos(alpha), -np.sin(alpha), 0.0]]
+        prob = synth.uniaxial_problem(2, stress=sigma, materials=[mat], fibres=fib)
+    lam = _stretches(law, mat, alpha, sigma)
+    d = fe.Discretization(prob)
+    prm = newton.NewtonParams(eps2=1e-12, lin_tol=1e-12, amg=amg.AmgParams(max_coarse=50))
+    v = np.zeros(4 * d.n)
+    for k in range(1, 5):
+        v, ok, _ = newton.solve_increment(d, v, k / 4, prm)
+        assert ok
+    v = v.reshape(-1, 4)
+    corner = np.flatnonzero(np.all(prob.lattice == 2, axis=1))[0]
+    got = 1.0 + v[corner, 0:3] / prob.X[corner]
+    assert np.allclose(got, lam, rtol=0, atol=1e-9)
+    J = np.prod(lam)
+    assert np.allclose(v[:, 3], -mat["kappa"] * (J - 1), rtol=1e-8, atol=1e-10)
+    if law == "artery":
+        assert abs(lam[1] - lam[2]) > 1e-4   # the fibres break the transverse symmetry
+
+
+def test_newton_converges_quadratically():
+    prob = synth.cube_problem(4)
+    d = fe.Discretization(prob)
+    log = []
+    prm = newton.NewtonParams(lin_tol=1e-12)
+    newton.solve_increment(d, np.zeros(4 * d.n), 1.0, prm, log)
+    r = [e["dv_M"] for e in log]
+    assert len(r) <= 6
+    # log(e_{k+1}) / log(e_k) relative to the first step approaches 2
+    ratios = [np.log(r[k + 1] / r[0]) / np.log(r[k] / r[0]) for k in range(1, len(r) - 1) if r[k + 1] > 1e-14 * r[0]]
+    assert ratios and min(ratios) > 1.7
