@@ -1,0 +1,257 @@
+/*
+ * hfsi.h — C ABI of the MI355X solid-mechanics hot path.
+ *
+ * One Newton step of the stabilised equal-order (P1-P1) displacement-pressure
+ * hyperelastic solid (Langer & Yang, "Numerical simulation of fluid-structure
+ * interaction problems with hyperelastic models I", Sections "The structure
+ * sub-problem", "Stabilization for the structure sub-problem" and "Newton's
+ * Method"): assemble the residual R and the consistent tangent
+ * K = [A B1^T; B2 -C] (eq. globsys), build an algebraic multigrid hierarchy on
+ * the displacement block A, solve K dv = -R with FGMRES right-preconditioned by
+ * the block-triangular P_L of eq. lpre, and update the state.
+ *
+ * Conventions shared by every call
+ *  - Every call returns hfsi_status: 0 on success, 1 (HFSI_NOT_CONVERGED) is a
+ *    warning, negative values are errors.  No C++ exception crosses the ABI;
+ *    hfsi_last_error() returns a message for the last failing call.
+ *  - "host" pointers are read during the call only and stay owned by the
+ *    caller.  "device" pointers are caller-owned device memory of the
+ *    context's device (e.g. PyTorch tensors), contiguous, fp64 unless stated.
+ *  - Dofs are node-interleaved: dof 4*i + c, c = 0,1,2 the displacement
+ *    components and c = 3 the pressure of node i (n nodes, N = 4n dofs).
+ *  - All device work is queued on the stream given to hfsi_create.  Calls
+ *    that fill an *_info struct synchronise that stream before returning.
+ *  - One context per host thread; contexts are independent.
+ *  - Call order: set_mesh -> set_materials -> set_bc, then any of
+ *    assemble / amg_setup / krylov_amg_solve / newton_step.  Out-of-order
+ *    calls return HFSI_E_ORDER.
+ *  - Index type is int32: meshes whose matrices exceed 2^31-1 stored
+ *    entries are rejected with HFSI_E_ARG.
+ */
+#ifndef HFSI_H
+#define HFSI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HFSI_OK = 0,
+  HFSI_NOT_CONVERGED = 1, /* warning: iteration limit reached            */
+  HFSI_E_ARG = -1,        /* invalid argument or unsupported size          */
+  HFSI_E_HIP = -2,        /* HIP runtime error                             */
+  HFSI_E_OOM = -3,        /* device allocation failed                      */
+  HFSI_E_ORDER = -4,      /* call sequence violated                        */
+  HFSI_E_INVERTED = -5,   /* an element has J <= 0 (message names it)      */
+  HFSI_E_BREAKDOWN = -6,  /* Krylov breakdown without convergence          */
+  HFSI_E_NAN = -7,        /* NaN/Inf in a residual or update               */
+  HFSI_E_CAPACITY = -8    /* a fixed-capacity internal table overflowed    */
+} hfsi_status;
+
+typedef struct hfsi_ctx hfsi_ctx;
+
+/* Material record (Section "Nonlinear hyperelastic modeling").
+ * model 0: modified Mooney-Rivlin, energy c10/2 (J1-3) + c01/2 (J2-3)
+ *          + kappa/2 (J-1)^2 (eq. mmreng);
+ * model 1: two-layer artery layer, neo-Hookean c10/2 (J1-3) plus the
+ *          exponential fibre energy k1/(2 k2) sum_{i=4,6} (exp(k2 (J_i-1)^2)-1)
+ *          active while J_i > 1, plus kappa/2 (J-1)^2 (eq. areng).
+ * theta: the Schur-complement parameter of eq. lpreschur; <= 0 selects the
+ *        linear shear modulus mu^l of the stabilisation paragraph. */
+typedef struct {
+  size_t struct_size; /* = sizeof(hfsi_material)                      */
+  int32_t model;
+  double c10, c01, kappa, k1, k2;
+  double theta;
+} hfsi_material;
+
+/* Views of the assembled tangent owned by the context; valid until the next
+ * assemble, set_* or destroy.  K is block-CSR over nodes with dense 4x4
+ * blocks (row-major, rows/cols = components 0..3); A is scalar CSR over the
+ * 3n displacement dofs (dof 3*i + c) after Dirichlet elimination. */
+typedef struct {
+  int32_t n_block_rows;     /* n                                           */
+  int32_t n_blocks;         /* stored 4x4 blocks                           */
+  const int32_t* block_ptr; /* device [n+1]                                */
+  const int32_t* block_col; /* device [n_blocks], ascending per row        */
+  const double* block_val;  /* device [n_blocks*16]                        */
+  int32_t a_rows;           /* 3n                                          */
+  int32_t a_nnz;
+  const int32_t* a_ptr;     /* device [3n+1]                               */
+  const int32_t* a_col;     /* device [a_nnz]                              */
+  const double* a_val;      /* device [a_nnz]                              */
+  const double* schur_diag; /* device [n]: (1/theta+1/kappa) diag(M_p)     */
+} hfsi_csr_view;
+
+typedef struct {
+  size_t struct_size;
+  double seconds;       /* assembly wall time on the stream (HIP events)   */
+  int32_t n_colours;    /* element colours used for atomic-free assembly   */
+  double min_J;         /* smallest element J = det F                      */
+} hfsi_assembly_info;
+
+/* AMG parameters.  smoother: 0 = l1-Jacobi, 1 = Chebyshev (degree 2 on
+ * D^{-1}A over [lmax/30, 1.1 lmax], lmax from 10 Lanczos steps).
+ * precision: 0 = fp64 V-cycle, 1 = fp32 V-cycle (coarsest solve stays fp64).
+ * interp: 0 = classical, 1 = learned correction on level 0 (needs MLP
+ * weights and lattice coordinates), with classical fallback when the
+ * measured convergence factor exceeds fallback_rho. */
+typedef struct {
+  size_t struct_size;
+  double strength_theta; /* default 0.5                                    */
+  int32_t max_coarse;    /* default 500                                    */
+  int32_t max_levels;    /* default 25                                     */
+  uint64_t seed;         /* PMIS weight seed, default 12345                */
+  int32_t smoother;
+  int32_t nu_pre, nu_post;
+  int32_t precision;
+  int32_t interp;
+  double fallback_rho;   /* default 0.5                                    */
+} hfsi_amg_params;
+
+typedef struct {
+  size_t struct_size;
+  int32_t levels;
+  int32_t rows[32];      /* rows per level                                 */
+  int64_t nnz[32];       /* stored entries per level                       */
+  double op_complexity;
+  double grid_complexity;
+  double seconds;
+  double rho;            /* convergence factor measured by the judge (or -1) */
+  int32_t learned_used;  /* 1 if the learned level-0 interpolation is kept */
+  int32_t pmis_rounds;   /* PMIS rounds summed over levels                 */
+} hfsi_amg_info;
+
+typedef struct {
+  size_t struct_size;
+  double tol;           /* relative residual ||b-Kx||/||b||, default 1e-8   */
+  int32_t restart;      /* m, default 50                                   */
+  int32_t max_iter;     /* default 500                                     */
+} hfsi_solve_params;
+
+typedef struct {
+  size_t struct_size;
+  int32_t iterations;
+  int32_t restarts;
+  double rel_residual;  /* true ||b - K x|| / ||b|| at exit                */
+  int32_t converged;
+  int32_t breakdown;
+  double seconds;
+} hfsi_solve_info;
+
+typedef struct {
+  size_t struct_size;
+  hfsi_amg_params amg;
+  hfsi_solve_params solve;
+} hfsi_newton_params;
+
+typedef struct {
+  size_t struct_size;
+  double dv_mass_norm;  /* ||dv||_M, M = diag(M1, M2) consistent masses    */
+  double residual_norm; /* ||R||_2 of the state before the update          */
+  int32_t krylov_iterations;
+  double rel_residual;
+  double t_assemble, t_setup, t_solve, t_total;
+  int32_t amg_levels;
+} hfsi_newton_info;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`; `stream` is a hipStream_t (NULL =
+ * the null stream) on which every later call queues its work. */
+hfsi_status hfsi_create(hfsi_ctx** out, int device, void* stream);
+hfsi_status hfsi_destroy(hfsi_ctx* ctx);
+const char* hfsi_last_error(const hfsi_ctx* ctx);
+int32_t hfsi_abi_version(void);
+
+/* Mesh (Section "Stabilization for the structure sub-problem": P1 elements on
+ * a tetrahedral triangulation).  host X [n][3] reference coordinates; host
+ * tets [m][4] node indices of positively oriented tetrahedra; host mat_id [m]
+ * material index; host lattice [n][3] integer lattice coordinates of each
+ * node or NULL (the learned interpolation needs them); host fibres [m][2][3]
+ * unit fibre directions a_01, a_02 (eq. arinv46) or NULL for isotropic meshes.
+ * Builds geometry, the node-block sparsity pattern and an element colouring.
+ * Errors: HFSI_E_ARG on bad sizes, indices or non-positive volumes. */
+hfsi_status hfsi_set_mesh(hfsi_ctx* ctx, int64_t n_nodes, const double* X, int64_t n_tets,
+                          const int32_t* tets, const int32_t* mat_id, const int32_t* lattice,
+                          const double* fibres);
+
+/* Material table (eq. mmreng, eq. areng); host array of n_mat records. */
+hfsi_status hfsi_set_materials(hfsi_ctx* ctx, int32_t n_mat, const hfsi_material* mats);
+
+/* Boundary data (eq. elasbnd): host dir_mask [n][4], 1 = dof fixed to zero;
+ * host tris [k][3] loaded boundary triangles with host traction [k][3], the
+ * dead nominal traction per unit reference area at load factor 1. */
+hfsi_status hfsi_set_bc(hfsi_ctx* ctx, const uint8_t* dir_mask, int64_t n_tris, const int32_t* tris,
+                        const double* traction);
+
+/* --------------------------------------------------------------- hot path */
+
+/* Residual and consistent tangent at device state v [N] for load factor
+ * `load` (eq. stabweakelas, linearised as eq. linsys / eq. globsys).  Writes
+ * device R [N] (internal minus external forces, zero on fixed dofs) and the
+ * Dirichlet-eliminated K (unit diagonal and zero row/column on fixed dofs),
+ * A, B2 and the Schur diagonal into context storage described by *K (may be
+ * NULL).  HFSI_E_INVERTED when some element has J <= 0. */
+hfsi_status hfsi_assemble_residual_tangent(hfsi_ctx* ctx, const double* v, double load, double* R,
+                                           hfsi_csr_view* K, hfsi_assembly_info* info);
+
+/* AMG hierarchy on the displacement block A of the last assembly (the AMG
+ * cycles of eq. lpre; Galerkin coarse operators as in "AMG methods for the
+ * mixed problems"). */
+hfsi_status hfsi_amg_setup(hfsi_ctx* ctx, const hfsi_amg_params* prm, hfsi_amg_info* info);
+
+/* Solve K x = b (device b, device x [N]; x is the initial guess on entry)
+ * with FGMRES(m) right-preconditioned by P_L^{-1} = [Atilde^{-1} 0;
+ * Stilde^{-1} B2 Atilde^{-1}  -Stilde^{-1}] (eq. lpre, eq. lpreschur), Atilde^{-1}
+ * one V-cycle of the hierarchy.  HFSI_NOT_CONVERGED if max_iter is reached. */
+hfsi_status hfsi_krylov_amg_solve(hfsi_ctx* ctx, const double* b, double* x, const hfsi_solve_params* prm,
+                                  hfsi_solve_info* info);
+
+/* One Newton iteration at load factor `load` (Section "Newton's Method"):
+ * assemble, set up AMG, solve K dv = -R, v += dv in place (device v [N]),
+ * report ||dv||_M for the stopping rule eq. newstop. */
+hfsi_status hfsi_newton_step(hfsi_ctx* ctx, double* v, double load, const hfsi_newton_params* prm,
+                             hfsi_newton_info* info);
+
+/* ------------------------------------------------ inspection and testing */
+
+/* AMG setup on a caller-given scalar CSR matrix instead of the assembled A
+ * (host arrays; comp [n] the unknown component of each row).  Used to feed
+ * identical inputs to the GPU and the CPU oracle level by level. */
+hfsi_status hfsi_amg_setup_csr(hfsi_ctx* ctx, int32_t n, const int32_t* ptr, const int32_t* col,
+                               const double* val, const int32_t* comp, const hfsi_amg_params* prm,
+                               hfsi_amg_info* info);
+
+/* Copy level `level` of the current hierarchy to host buffers.  which: 0 = A
+ * (ptr [rows+1], col, val), 1 = P, 2 = strength flags (u8 per A entry, in
+ * val_u8), 3 = C/F state (int8 per row in val_u8: +1 C, -1 F), 4 = component
+ * per row (int32 in col).  Pass NULL buffers to query sizes in *rows, *cols,
+ * *nnz. */
+hfsi_status hfsi_amg_export(hfsi_ctx* ctx, int32_t level, int32_t which, int32_t* rows, int32_t* cols,
+                            int64_t* nnz, int32_t* ptr, int32_t* col, double* val, uint8_t* val_u8);
+
+/* One V-cycle z = Atilde^{-1} r on device vectors of length rows(level 0),
+ * in the hierarchy's precision (inputs and outputs fp64). */
+hfsi_status hfsi_vcycle(hfsi_ctx* ctx, const double* r, double* z);
+
+/* y = P_L^{-1} r (device [N]) and y = K x (device [N]). */
+hfsi_status hfsi_apply_preconditioner(hfsi_ctx* ctx, const double* r, double* y);
+hfsi_status hfsi_apply_tangent(hfsi_ctx* ctx, const double* x, double* y);
+
+/* Copy the last assembled tangent to host buffers (any may be NULL): the
+ * block pattern and values of K (sizes from hfsi_csr_view: n+1, n_blocks,
+ * 16*n_blocks), the CSR of A (3n+1, a_nnz, a_nnz) and the Schur diagonal (n). */
+hfsi_status hfsi_export_tangent(hfsi_ctx* ctx, int32_t* block_ptr, int32_t* block_col, double* block_val,
+                                int32_t* a_ptr, int32_t* a_col, double* a_val, double* schur);
+
+/* ||dv||_M for a device vector dv [N]. */
+hfsi_status hfsi_mass_norm(hfsi_ctx* ctx, const double* dv, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HFSI_H */

@@ -1,0 +1,233 @@
+// Shared internals of the hfsi HIP library: error handling, device buffers,
+// the context object and small device utilities (scan, reductions).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "hfsi.h"
+
+namespace hfsi {
+
+// Every internal failure is thrown as Error and turned into a status code at
+// the ABI boundary (see HFSI_ABI_BEGIN / HFSI_ABI_END).
+struct Error : std::runtime_error {
+  hfsi_status code;
+  Error(hfsi_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] inline void fail(hfsi_status c, const std::string& m) { throw Error(c, m); }
+
+#define HIP_CHECK(expr)                                                                     \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      ::hfsi::fail(e_ == hipErrorOutOfMemory ? HFSI_E_OOM : HFSI_E_HIP,                     \
+                   std::string(#expr) + ": " + hipGetErrorString(e_) + " at " + __FILE__ + \
+                       ":" + std::to_string(__LINE__));                                     \
+  } while (0)
+
+#define HIP_LAUNCH_CHECK() HIP_CHECK(hipGetLastError())
+
+// Device buffer owned by the context.  Allocation is synchronous and only
+// happens at set-up or when a buffer must grow.
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  // (re)allocate to at least cnt elements; contents are not preserved
+  void ensure(size_t cnt) {
+    if (cnt <= n && p) return;
+    release();
+    size_t bytes = (cnt ? cnt : 1) * sizeof(T);
+    HIP_CHECK(hipMalloc(&p, bytes));
+    n = cnt;
+  }
+  void upload(const T* h, size_t cnt, hipStream_t s) {
+    ensure(cnt);
+    if (cnt) HIP_CHECK(hipMemcpyAsync(p, h, cnt * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  void zero(size_t cnt, hipStream_t s) {
+    ensure(cnt);
+    if (cnt) HIP_CHECK(hipMemsetAsync(p, 0, cnt * sizeof(T), s));
+  }
+  std::vector<T> download(size_t cnt, hipStream_t s) const {
+    std::vector<T> h(cnt);
+    if (cnt) {
+      HIP_CHECK(hipMemcpyAsync(h.data(), p, cnt * sizeof(T), hipMemcpyDeviceToHost, s));
+      HIP_CHECK(hipStreamSynchronize(s));
+    }
+    return h;
+  }
+};
+
+inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
+
+// --------------------------------------------------------------- CSR matrix
+template <class V>
+struct Csr {
+  int rows = 0, cols = 0;
+  int64_t nnz = 0;
+  DevBuf<int> ptr, col;
+  DevBuf<V> val;
+};
+
+// ------------------------------------------------------------- AMG level
+struct Level {
+  int n = 0;
+  Csr<double> A;           // fp64 operator
+  DevBuf<float> A32;       // fp32 copy of A.val (mixed precision)
+  DevBuf<int> comp;        // unknown component of each row
+  DevBuf<uint8_t> strong;  // strength flag per A entry
+  DevBuf<int8_t> state;    // +1 C, -1 F
+  DevBuf<int> cidx;        // coarse index of C points (exclusive scan)
+  Csr<double> P, R;        // interpolation and restriction (R = P^T)
+  DevBuf<float> P32, R32;
+  DevBuf<double> dinv;     // smoother diagonal (l1 or plain), fp64
+  DevBuf<float> dinv32;
+  double lmax = 0.0;       // Chebyshev upper eigenvalue estimate
+  // V-cycle vectors (fp64 and fp32 variants used according to precision)
+  DevBuf<double> x, b, r, t;
+  DevBuf<float> xf, bf, rf, tf;
+};
+
+struct Hierarchy {
+  std::vector<Level> L;
+  int nc = 0;                 // coarsest size
+  DevBuf<double> coarse_inv;  // explicit inverse of the coarsest operator
+  DevBuf<double> cwork;
+  int precision = 0;
+  int smoother = 0;
+  int nu_pre = 2, nu_post = 2;
+  bool ready = false;
+};
+
+// ----------------------------------------------------------- MLP weights
+struct MlpWeights {
+  bool loaded = false;
+  DevBuf<uint16_t> w_bf16;   // bf16 weights of the three layers (packed)
+  DevBuf<float> b_f32;       // biases
+  DevBuf<float> w_master;    // fp32 master weights for training
+};
+
+}  // namespace hfsi
+
+// ------------------------------------------------------------- the context
+struct hfsi_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int stage = 0;  // 0 created, 1 mesh, 2 materials, 3 bc, 4 assembled, 5 amg ready
+
+  // mesh (elements stored in colour order; perm[k] = original element index)
+  int n = 0, m = 0;
+  hfsi::DevBuf<double> X;      // [n*3]
+  hfsi::DevBuf<int> tets;      // [4*m] SoA: tets[a*m + e]
+  hfsi::DevBuf<int> mat;       // [m]
+  hfsi::DevBuf<double> G;      // [12*m] SoA: G[(a*3+J)*m + e]
+  hfsi::DevBuf<double> V, h;   // [m]
+  hfsi::DevBuf<double> fib;    // [6*m] SoA or empty
+  hfsi::DevBuf<int> lattice;   // [3*n] or empty
+  bool has_fib = false, has_lattice = false;
+  std::vector<int> perm;       // colour order -> original element
+  std::vector<int> colour_ptr; // element ranges per colour
+  // node-block pattern
+  int nb = 0;
+  hfsi::DevBuf<int> nptr, ncol;  // [n+1], [nb]
+  hfsi::DevBuf<int> slot;        // [16*m] SoA: slot[(a*4+b)*m + e]
+  hfsi::DevBuf<int> diag_blk;    // [n]
+  hfsi::DevBuf<int> brow;        // [nb] block row of each block
+  hfsi::DevBuf<double> Kval;     // [16*nb]
+  hfsi::DevBuf<double> Mval;     // [nb] scalar P1 mass on the node pattern
+  // materials
+  int n_mat = 0;
+  hfsi::DevBuf<double> mtab;     // [n_mat * 8]: model,c10,c01,kappa,k1,k2,mu_l,theta
+  std::vector<double> mtab_h;
+  // boundary
+  hfsi::DevBuf<uint8_t> dir;     // [4n]
+  hfsi::DevBuf<double> fext;     // [3n] nodal load at load factor 1
+  hfsi::DevBuf<double> schur;    // [n]
+  // A block (scalar CSR over 3n dofs) and its source positions in Kval
+  hfsi::Csr<double> A;
+  hfsi::DevBuf<int> a_src;
+  // hierarchy
+  hfsi::Hierarchy H;
+  // Krylov workspace
+  hfsi::DevBuf<double> kv;       // basis V [(m+1) * N]
+  hfsi::DevBuf<double> kz;       // Z [m * N]
+  hfsi::DevBuf<double> kw, kr, ktmp, kdv;
+  hfsi::DevBuf<double> kred;     // reduction partials
+  hfsi::DevBuf<double> kh;       // Hessenberg / Givens state on device
+  double* pinned = nullptr;      // host-pinned scalars
+  hfsi::DevBuf<double> scal;     // device scalars
+  hfsi::DevBuf<int> iscal;       // device integer scalars
+  hfsi::MlpWeights mlp;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace hfsi {
+
+// ------------------------------------------------------------------ scans
+// Exclusive prefix sum of `n` int32 values; out may alias in.  Returns the
+// total (synchronises the stream).
+int64_t exclusive_scan(const int* in, int* out, int n, hipStream_t s);
+// Same without reading back the total.
+void exclusive_scan_async(const int* in, int* out, int n, hipStream_t s);
+
+// Sum of a device double array (synchronises).
+double device_sum(hfsi_ctx* c, const double* x, int n);
+
+// Elapsed milliseconds between two events recorded on the context stream.
+float elapsed_ms(hfsi_ctx* c);
+
+void require_stage(hfsi_ctx* c, int st, const char* what);
+
+// internal entry points implemented in the .hip files
+void assemble(hfsi_ctx* c, const double* v, double load, double* R, hfsi_assembly_info* info);
+void build_a_pattern(hfsi_ctx* c);
+void amg_setup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info);
+void vcycle_apply(hfsi_ctx* c, const double* r, double* z);
+void precond_apply(hfsi_ctx* c, const double* r, double* z);
+void tangent_apply(hfsi_ctx* c, const double* x, double* y);
+void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_params& prm,
+                  hfsi_solve_info* info);
+double mass_norm(hfsi_ctx* c, const double* dv);
+
+}  // namespace hfsi
+
+#define HFSI_ABI_BEGIN(ctx)                     \
+  if (!(ctx)) return HFSI_E_ARG;                \
+  try {                                         \
+    HIP_CHECK(hipSetDevice((ctx)->device));
+
+#define HFSI_ABI_END(ctx)                       \
+  }                                             \
+  catch (const ::hfsi::Error& e) {              \
+    (ctx)->err = e.what();                      \
+    return e.code;                              \
+  }                                             \
+  catch (const std::exception& e) {             \
+    (ctx)->err = e.what();                      \
+    return HFSI_E_HIP;                          \
+  }                                             \
+  return HFSI_OK;

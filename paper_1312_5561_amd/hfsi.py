@@ -1,0 +1,297 @@
+"""ctypes binding of libhfsi.so (argument marshalling only).
+
+Every method of :class:`Context` forwards to the C function of the same name
+(``hfsi_<name>``) declared in include/hfsi.h.  Device vectors are torch
+tensors (fp64, contiguous, on the context's device); PyTorch provides device
+memory and the stream, all arithmetic runs in the library's HIP kernels.
+The binding raises if the library has not been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhfsi.so")
+
+STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "E_ARG", -2: "E_HIP", -3: "E_OOM", -4: "E_ORDER",
+          -5: "E_INVERTED", -6: "E_BREAKDOWN", -7: "E_NAN", -8: "E_CAPACITY"}
+
+
+class HfsiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hfsi {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Material(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("model", C.c_int32), ("c10", C.c_double), ("c01", C.c_double),
+                ("kappa", C.c_double), ("k1", C.c_double), ("k2", C.c_double), ("theta", C.c_double)]
+
+
+class CsrView(C.Structure):
+    _fields_ = [("n_block_rows", C.c_int32), ("n_blocks", C.c_int32), ("block_ptr", C.c_void_p),
+                ("block_col", C.c_void_p), ("block_val", C.c_void_p), ("a_rows", C.c_int32), ("a_nnz", C.c_int32),
+                ("a_ptr", C.c_void_p), ("a_col", C.c_void_p), ("a_val", C.c_void_p), ("schur_diag", C.c_void_p)]
+
+
+class AssemblyInfo(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("seconds", C.c_double), ("n_colours", C.c_int32),
+                ("min_J", C.c_double)]
+
+
+class AmgParams(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("strength_theta", C.c_double), ("max_coarse", C.c_int32),
+                ("max_levels", C.c_int32), ("seed", C.c_uint64), ("smoother", C.c_int32), ("nu_pre", C.c_int32),
+                ("nu_post", C.c_int32), ("precision", C.c_int32), ("interp", C.c_int32),
+                ("fallback_rho", C.c_double)]
+
+
+class AmgInfo(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("levels", C.c_int32), ("rows", C.c_int32 * 32),
+                ("nnz", C.c_int64 * 32), ("op_complexity", C.c_double), ("grid_complexity", C.c_double),
+                ("seconds", C.c_double), ("rho", C.c_double), ("learned_used", C.c_int32),
+                ("pmis_rounds", C.c_int32)]
+
+
+class SolveParams(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("tol", C.c_double), ("restart", C.c_int32),
+                ("max_iter", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("iterations", C.c_int32), ("restarts", C.c_int32),
+                ("rel_residual", C.c_double), ("converged", C.c_int32), ("breakdown", C.c_int32),
+                ("seconds", C.c_double)]
+
+
+class NewtonParams(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("amg", AmgParams), ("solve", SolveParams)]
+
+
+class NewtonInfo(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("dv_mass_norm", C.c_double), ("residual_norm", C.c_double),
+                ("krylov_iterations", C.c_int32), ("rel_residual", C.c_double), ("t_assemble", C.c_double),
+                ("t_setup", C.c_double), ("t_solve", C.c_double), ("t_total", C.c_double),
+                ("amg_levels", C.c_int32)]
+
+
+def amg_params(theta=0.5, max_coarse=500, max_levels=25, seed=12345, smoother=0, nu_pre=2, nu_post=2,
+               precision=0, interp=0, fallback_rho=0.5):
+    return AmgParams(C.sizeof(AmgParams), theta, max_coarse, max_levels, seed, smoother, nu_pre, nu_post,
+                     precision, interp, fallback_rho)
+
+
+def solve_params(tol=1e-8, restart=50, max_iter=500):
+    return SolveParams(C.sizeof(SolveParams), tol, restart, max_iter)
+
+
+def newton_params(amg=None, solve=None):
+    return NewtonParams(C.sizeof(NewtonParams), amg or amg_params(), solve or solve_params())
+
+
+_lib = None
+
+
+def load():
+    """Load libhfsi.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_1312_5561_amd.build` first")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "hfsi_create": [C.POINTER(vp), C.c_int, vp],
+        "hfsi_destroy": [vp],
+        "hfsi_set_mesh": [vp, i64, vp, i64, vp, vp, vp, vp],
+        "hfsi_set_materials": [vp, i32, vp],
+        "hfsi_set_bc": [vp, vp, i64, vp, vp],
+        "hfsi_assemble_residual_tangent": [vp, vp, dbl, vp, C.POINTER(CsrView), C.POINTER(AssemblyInfo)],
+        "hfsi_amg_setup": [vp, C.POINTER(AmgParams), C.POINTER(AmgInfo)],
+        "hfsi_krylov_amg_solve": [vp, vp, vp, C.POINTER(SolveParams), C.POINTER(SolveInfo)],
+        "hfsi_newton_step": [vp, vp, dbl, C.POINTER(NewtonParams), C.POINTER(NewtonInfo)],
+        "hfsi_amg_setup_csr": [vp, i32, vp, vp, vp, vp, C.POINTER(AmgParams), C.POINTER(AmgInfo)],
+        "hfsi_amg_export": [vp, i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64), vp, vp, vp, vp],
+        "hfsi_vcycle": [vp, vp, vp],
+        "hfsi_apply_preconditioner": [vp, vp, vp],
+        "hfsi_apply_tangent": [vp, vp, vp],
+        "hfsi_mass_norm": [vp, vp, C.POINTER(dbl)],
+        "hfsi_export_tangent": [vp, vp, vp, vp, vp, vp, vp, vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name, None)
+        if f is None:
+            continue
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.hfsi_last_error.argtypes = [vp]
+    lib.hfsi_last_error.restype = C.c_char_p
+    lib.hfsi_abi_version.restype = C.c_int32
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    """Address of a numpy array or torch tensor (None -> NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+class Context:
+    """One hfsi context bound to a torch CUDA (HIP) device and stream."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.lib = load()
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = C.c_void_p()
+        self._check(self.lib.hfsi_create(C.byref(h), device, C.c_void_p(stream.cuda_stream)), None)
+        self.h = h
+        self.n = 0
+
+    def _check(self, code, h=0):
+        if code < 0:
+            msg = self.lib.hfsi_last_error(h if h is not None else self.h)
+            raise HfsiError(code, msg.decode() if msg else "")
+        return code
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hfsi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- set-up
+    def set_mesh(self, X, tets, mat_id, lattice=None, fibres=None):
+        X = np.ascontiguousarray(X, np.float64)
+        tets = np.ascontiguousarray(tets, np.int32)
+        mat_id = np.ascontiguousarray(mat_id, np.int32)
+        lat = None if lattice is None else np.ascontiguousarray(lattice, np.int32)
+        fib = None if fibres is None else np.ascontiguousarray(fibres, np.float64)
+        self._check(self.lib.hfsi_set_mesh(self.h, X.shape[0], _ptr(X), tets.shape[0], _ptr(tets), _ptr(mat_id),
+                                           _ptr(lat), _ptr(fib)))
+        self.n = X.shape[0]
+
+    def set_materials(self, materials):
+        arr = (Material * len(materials))()
+        for k, m in enumerate(materials):
+            arr[k] = Material(C.sizeof(Material), int(m["model"]), m["c10"], m.get("c01", 0.0), m["kappa"],
+                              m.get("k1", 0.0), m.get("k2", 0.0), m.get("theta", 0.0))
+        self._check(self.lib.hfsi_set_materials(self.h, len(materials), arr))
+
+    def set_bc(self, dir_mask, tris, traction):
+        dm = np.ascontiguousarray(dir_mask, np.uint8)
+        tr = np.ascontiguousarray(tris, np.int32)
+        tc = np.ascontiguousarray(traction, np.float64)
+        self._check(self.lib.hfsi_set_bc(self.h, _ptr(dm), tr.shape[0], _ptr(tr), _ptr(tc)))
+
+    def set_problem(self, prob, theta=None):
+        """Convenience: set_mesh + set_materials + set_bc from a synth.Problem."""
+        self.set_mesh(prob.X, prob.tets, prob.mat_id, prob.lattice, prob.fibres)
+        mats = [dict(m, theta=theta or 0.0) for m in prob.materials]
+        self.set_materials(mats)
+        self.set_bc(prob.dir_mask, prob.tris, prob.traction)
+
+    # ---- hot path
+    def assemble_residual_tangent(self, v, load, R):
+        view = CsrView()
+        info = AssemblyInfo(C.sizeof(AssemblyInfo))
+        self._check(self.lib.hfsi_assemble_residual_tangent(self.h, _ptr(v), load, _ptr(R), C.byref(view),
+                                                            C.byref(info)))
+        return view, info
+
+    def amg_setup(self, prm=None):
+        prm = prm or amg_params()
+        info = AmgInfo(C.sizeof(AmgInfo))
+        self._check(self.lib.hfsi_amg_setup(self.h, C.byref(prm), C.byref(info)))
+        return info
+
+    def amg_setup_csr(self, ptr, col, val, comp, prm=None):
+        prm = prm or amg_params()
+        info = AmgInfo(C.sizeof(AmgInfo))
+        ptr = np.ascontiguousarray(ptr, np.int32)
+        col = np.ascontiguousarray(col, np.int32)
+        val = np.ascontiguousarray(val, np.float64)
+        comp = np.ascontiguousarray(comp, np.int32)
+        self._check(self.lib.hfsi_amg_setup_csr(self.h, len(ptr) - 1, _ptr(ptr), _ptr(col), _ptr(val), _ptr(comp),
+                                                C.byref(prm), C.byref(info)))
+        return info
+
+    def krylov_amg_solve(self, b, x, prm=None):
+        prm = prm or solve_params()
+        info = SolveInfo(C.sizeof(SolveInfo))
+        code = self._check(self.lib.hfsi_krylov_amg_solve(self.h, _ptr(b), _ptr(x), C.byref(prm), C.byref(info)))
+        return info, code
+
+    def newton_step(self, v, load, prm=None):
+        prm = prm or newton_params()
+        info = NewtonInfo(C.sizeof(NewtonInfo))
+        code = self._check(self.lib.hfsi_newton_step(self.h, _ptr(v), load, C.byref(prm), C.byref(info)))
+        return info, code
+
+    # ---- inspection
+    def amg_export(self, level, which):
+        """Level data as numpy: which 0 -> (ptr, col, val) of A, 1 -> P,
+        2 -> strength flags, 3 -> C/F state, 4 -> components."""
+        rows, cols, nnz = C.c_int32(), C.c_int32(), C.c_int64()
+        self._check(self.lib.hfsi_amg_export(self.h, level, which, C.byref(rows), C.byref(cols), C.byref(nnz),
+                                             None, None, None, None))
+        r, k = rows.value, nnz.value
+        if which in (0, 1):
+            ptr = np.zeros(r + 1, np.int32)
+            col = np.zeros(max(k, 1), np.int32)
+            val = np.zeros(max(k, 1), np.float64)
+            self._check(self.lib.hfsi_amg_export(self.h, level, which, C.byref(rows), C.byref(cols), C.byref(nnz),
+                                                 _ptr(ptr), _ptr(col), _ptr(val), None))
+            return ptr, col[:k], val[:k], cols.value
+        if which in (2, 3):
+            buf = np.zeros(max(k, 1), np.uint8)
+            self._check(self.lib.hfsi_amg_export(self.h, level, which, C.byref(rows), C.byref(cols), C.byref(nnz),
+                                                 None, None, None, _ptr(buf)))
+            out = buf[:k]
+            return out.view(np.int8) if which == 3 else out
+        col = np.zeros(max(k, 1), np.int32)
+        self._check(self.lib.hfsi_amg_export(self.h, level, which, C.byref(rows), C.byref(cols), C.byref(nnz),
+                                             None, _ptr(col), None, None))
+        return col[:k]
+
+    def vcycle(self, r, z):
+        self._check(self.lib.hfsi_vcycle(self.h, _ptr(r), _ptr(z)))
+
+    def apply_preconditioner(self, r, y):
+        self._check(self.lib.hfsi_apply_preconditioner(self.h, _ptr(r), _ptr(y)))
+
+    def apply_tangent(self, x, y):
+        self._check(self.lib.hfsi_apply_tangent(self.h, _ptr(x), _ptr(y)))
+
+    def mass_norm(self, dv):
+        out = C.c_double()
+        self._check(self.lib.hfsi_mass_norm(self.h, _ptr(dv), C.byref(out)))
+        return out.value
+
+    def export_tangent(self, view):
+        """Host copies of the block matrix K, of A and of the Schur diagonal."""
+        n, nb = view.n_block_rows, view.n_blocks
+        out = dict(block_ptr=np.zeros(n + 1, np.int32), block_col=np.zeros(nb, np.int32),
+                   block_val=np.zeros(16 * nb), a_ptr=np.zeros(view.a_rows + 1, np.int32),
+                   a_col=np.zeros(view.a_nnz, np.int32), a_val=np.zeros(view.a_nnz), schur=np.zeros(n))
+        self._check(self.lib.hfsi_export_tangent(self.h, *[_ptr(out[k]) for k in (
+            "block_ptr", "block_col", "block_val", "a_ptr", "a_col", "a_val", "schur")]))
+        out["block_val"] = out["block_val"].reshape(nb, 4, 4)
+        return out
