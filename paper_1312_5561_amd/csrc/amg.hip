@@ -1,0 +1,929 @@
+// Algebraic multigrid set-up on the displacement block A (the AMG cycles
+// that realise Atilde^{-1} in eq. lpre; Galerkin coarse operators as in the
+// paper's "AMG methods for the mixed problems").
+//
+//  * strength, unknown-based: j in S_i iff j != i, comp(j) == comp(i) and
+//    -a_ij sgn(a_ii) >= theta m_i, m_i = max_{k != i, same comp} -a_ik sgn(a_ii) > 0
+//  * PMIS in synchronous rounds; key_i = (lambda_i << 40) | top 40 bits of
+//    SplitMix64(seed, level * 2^40 + i), ties broken by index
+//  * modified classical interpolation on same-component strong couplings
+//  * R = P^T by counting sort, A_c = R (A P) by a wavefront-per-row hashed
+//    sparse product whose accumulation order is fixed (deterministic)
+//  * l1-Jacobi diagonal or D^{-1} with a Lanczos estimate for Chebyshev
+//  * coarsest level: explicit inverse by Gauss-Jordan with partial pivoting
+#include <algorithm>
+#include <cmath>
+
+#include "common.hpp"
+
+using namespace hfsi;
+
+namespace {
+
+constexpr int8_t ST_U = 0, ST_C = 1, ST_F = -1;
+
+// ------------------------------------------------------------ strength
+__global__ void k_strength(int n, const int* __restrict__ ptr, const int* __restrict__ col,
+                           const double* __restrict__ val, const int* __restrict__ comp, double theta,
+                           uint8_t* __restrict__ strong) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int lo = ptr[i], hi = ptr[i + 1], ci = comp[i];
+  double aii = 0.0;
+  for (int e = lo; e < hi; ++e)
+    if (col[e] == i) aii = val[e];
+  const double sg = aii < 0.0 ? -1.0 : 1.0;
+  double mi = -INFINITY;
+  for (int e = lo; e < hi; ++e) {
+    int j = col[e];
+    if (j != i && comp[j] == ci) mi = fmax(mi, -val[e] * sg);
+  }
+  const double thr = theta * mi;
+  for (int e = lo; e < hi; ++e) {
+    int j = col[e];
+    strong[e] = (j != i && comp[j] == ci && mi > 0.0 && -val[e] * sg >= thr) ? 1 : 0;
+  }
+}
+
+__global__ void k_lambda(int n, const int* __restrict__ ptr, const int* __restrict__ col,
+                         const uint8_t* __restrict__ strong, int* __restrict__ lam) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int e = ptr[i]; e < ptr[i + 1]; ++e)
+    if (strong[e]) atomicAdd(&lam[col[e]], 1);
+}
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_pmis_init(int n, const int* __restrict__ lam, uint64_t seed, int level, uint64_t* __restrict__ key,
+                            int8_t* __restrict__ state) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t h = splitmix64(seed, ((uint64_t)level << 40) | (uint64_t)i) >> 24;
+  key[i] = ((uint64_t)lam[i] << 40) | h;
+  state[i] = lam[i] == 0 ? ST_F : ST_U;
+}
+
+// j beats i when (key_j, j) > (key_i, i)
+__global__ void k_pmis_select(int n, const int* __restrict__ ptr, const int* __restrict__ col,
+                              const uint8_t* __restrict__ strong, const uint64_t* __restrict__ key,
+                              const int8_t* __restrict__ state, int* __restrict__ notmax) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || state[i] != ST_U) return;
+  const uint64_t ki = key[i];
+  for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
+    if (!strong[e]) continue;
+    const int j = col[e];
+    if (state[j] != ST_U) continue;
+    const uint64_t kj = key[j];
+    if (kj > ki || (kj == ki && j > i)) notmax[i] = 1;
+    else notmax[j] = 1;
+  }
+}
+
+__global__ void k_pmis_mark_c(int n, const int* __restrict__ notmax, int8_t* __restrict__ state) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (state[i] == ST_U && !notmax[i]) state[i] = ST_C;
+}
+
+__global__ void k_pmis_mark_f(int n, const int* __restrict__ ptr, const int* __restrict__ col,
+                              const uint8_t* __restrict__ strong, int8_t* __restrict__ state,
+                              int* __restrict__ remaining) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || state[i] != ST_U) return;
+  for (int e = ptr[i]; e < ptr[i + 1]; ++e)
+    if (strong[e] && state[col[e]] == ST_C) {
+      state[i] = ST_F;
+      return;
+    }
+  atomicAdd(remaining, 1);
+}
+
+__global__ void k_is_c(int n, const int8_t* __restrict__ state, int* __restrict__ flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flag[i] = state[i] == ST_C ? 1 : 0;
+}
+
+__global__ void k_coarse_comp(int n, const int8_t* __restrict__ state, const int* __restrict__ cidx,
+                              const int* __restrict__ comp, int* __restrict__ ccomp) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && state[i] == ST_C) ccomp[cidx[i]] = comp[i];
+}
+
+// ------------------------------------------------------------ interpolation
+__global__ void k_interp_count(int n, const int* __restrict__ ptr, const int* __restrict__ col,
+                               const uint8_t* __restrict__ strong, const int8_t* __restrict__ state,
+                               int* __restrict__ cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (state[i] == ST_C) { cnt[i] = 1; return; }
+  int k = 0;
+  for (int e = ptr[i]; e < ptr[i + 1]; ++e)
+    if (strong[e] && state[col[e]] == ST_C) ++k;
+  cnt[i] = k;
+}
+
+__device__ __forceinline__ int find_in(const int* __restrict__ a, int lo, int hi, int key) {
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// w_ij = -(a_ij + sum_{k in F*} a_ik abar_kj / sum_{m in C_i} abar_km)
+//        / (a_ii + sum_{weak same comp} a_in + sum_{k in F \ F*} a_ik),
+// every sum in ascending column order of the rows involved.
+__global__ void k_interp_fill(int n, const int* __restrict__ ptr, const int* __restrict__ col,
+                              const double* __restrict__ val, const uint8_t* __restrict__ strong,
+                              const int8_t* __restrict__ state, const int* __restrict__ comp,
+                              const int* __restrict__ cidx, const int* __restrict__ pptr, int* __restrict__ pcol,
+                              double* __restrict__ pval) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int p0 = pptr[i], p1 = pptr[i + 1];
+  if (state[i] == ST_C) {
+    pcol[p0] = cidx[i];
+    pval[p0] = 1.0;
+    return;
+  }
+  if (p1 == p0) return;
+  const int lo = ptr[i], hi = ptr[i + 1], ci = comp[i];
+  int q = p0;
+  double aii = 0.0;
+  for (int e = lo; e < hi; ++e) {
+    const int j = col[e];
+    if (j == i) aii = val[e];
+    if (strong[e] && state[j] == ST_C) {
+      pcol[q] = j;  // fine index for now
+      pval[q] = 0.0;
+      ++q;
+    }
+  }
+  double den = aii;
+  for (int e = lo; e < hi; ++e) {
+    const int k = col[e];
+    if (k == i || comp[k] != ci) continue;
+    const double a = val[e];
+    if (strong[e] && state[k] == ST_C) {
+      pval[find_in(pcol, p0, p1, k)] += a;
+    } else if (strong[e]) {
+      const int klo = ptr[k], khi = ptr[k + 1];
+      double akk = 0.0;
+      for (int f = klo; f < khi; ++f)
+        if (col[f] == k) akk = val[f];
+      const double sk = akk < 0.0 ? -1.0 : 1.0;
+      double s = 0.0;
+      for (int f = klo; f < khi; ++f) {
+        const int mm = col[f];
+        const int pos = find_in(pcol, p0, p1, mm);
+        if (pos < p1 && pcol[pos] == mm) {
+          const double v = val[f];
+          s += (v * sk < 0.0) ? v : 0.0;
+        }
+      }
+      if (s != 0.0) {
+        for (int f = klo; f < khi; ++f) {
+          const int mm = col[f];
+          const int pos = find_in(pcol, p0, p1, mm);
+          if (pos < p1 && pcol[pos] == mm) {
+            const double v = val[f];
+            const double ab = (v * sk < 0.0) ? v : 0.0;
+            pval[pos] += a * ab / s;
+          }
+        }
+      } else {
+        den += a;
+      }
+    } else {
+      den += a;
+    }
+  }
+  for (int t = p0; t < p1; ++t) {
+    pval[t] = -pval[t] / den;
+    pcol[t] = cidx[pcol[t]];
+  }
+}
+
+// ------------------------------------------------------------ transpose
+__global__ void k_count_cols(int n, const int* __restrict__ ptr, const int* __restrict__ col, int* __restrict__ cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int e = ptr[i]; e < ptr[i + 1]; ++e) atomicAdd(&cnt[col[e]], 1);
+}
+
+__global__ void k_transpose_fill(int n, const int* __restrict__ ptr, const int* __restrict__ col,
+                                 const double* __restrict__ val, const int* __restrict__ tptr, int* __restrict__ cur,
+                                 int* __restrict__ tcol, double* __restrict__ tval) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
+    const int J = col[e];
+    const int pos = tptr[J] + atomicAdd(&cur[J], 1);
+    tcol[pos] = i;
+    tval[pos] = val[e];
+  }
+}
+
+// insertion sort of each row by column (rows of a transpose are short)
+__global__ void k_sort_rows(int n, const int* __restrict__ ptr, int* __restrict__ col, double* __restrict__ val) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int lo = ptr[i], hi = ptr[i + 1];
+  for (int a = lo + 1; a < hi; ++a) {
+    const int c = col[a];
+    const double v = val[a];
+    int b = a - 1;
+    while (b >= lo && col[b] > c) {
+      col[b + 1] = col[b];
+      val[b + 1] = val[b];
+      --b;
+    }
+    col[b + 1] = c;
+    val[b + 1] = v;
+  }
+}
+
+// ------------------------------------------------------------ SpGEMM C = A B
+// upper bound of row i of C: sum over k in A_i of nnz(B_k)
+__global__ void k_spgemm_ub(int n, const int* __restrict__ ap, const int* __restrict__ ac, const int* __restrict__ bp,
+                            int* __restrict__ ub) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  long s = 0;
+  for (int e = ap[i]; e < ap[i + 1]; ++e) s += bp[ac[e] + 1] - bp[ac[e]];
+  ub[i] = (int)min(s, (long)INT32_MAX);
+}
+
+__device__ __forceinline__ unsigned hslot(int key, int mask) { return ((unsigned)key * 2654435761u) & (unsigned)mask; }
+
+// One wavefront per row.  For each k of A_i in ascending order, the lanes
+// insert the columns of B_k (distinct within a row of B) into an LDS hash
+// table; the value of every C entry is therefore accumulated in ascending k,
+// independently of scheduling.  SMALL rows: ub <= TBL*3/4 in the "small"
+// pass, the rest in the "large" pass.  NUMERIC = false counts entries.
+template <int TBL, bool NUMERIC>
+__global__ void __launch_bounds__(64)
+k_spgemm(int n, const int* __restrict__ ap, const int* __restrict__ ac, const double* __restrict__ av,
+         const int* __restrict__ bp, const int* __restrict__ bc, const double* __restrict__ bv,
+         const int* __restrict__ sel, int sel_lo, int sel_hi, int* __restrict__ cnt, const int* __restrict__ cp,
+         int* __restrict__ cc, double* __restrict__ cv, int* __restrict__ overflow) {
+  __shared__ int keys[TBL];
+  __shared__ double vals[NUMERIC ? TBL : 1];
+  __shared__ int ckeys[NUMERIC ? (TBL * 3) / 4 + 64 : 1];
+  __shared__ int ninsert;
+  const int lane = threadIdx.x;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const int s = sel[i];
+    if (s < sel_lo || s > sel_hi) continue;
+    for (int t = lane; t < TBL; t += 64) {
+      keys[t] = -1;
+      if (NUMERIC) vals[t] = 0.0;
+    }
+    if (lane == 0) ninsert = 0;
+    __syncthreads();
+    bool bad = false;
+    for (int e = ap[i]; e < ap[i + 1]; ++e) {
+      const int k = ac[e];
+      const double a = NUMERIC ? av[e] : 0.0;
+      for (int q = bp[k] + lane; q < bp[k + 1]; q += 64) {
+        const int j = bc[q];
+        unsigned h = hslot(j, TBL - 1);
+        int probes = 0;
+        while (true) {
+          const int old = atomicCAS(&keys[h], -1, j);
+          if (old == -1) {
+            if (!NUMERIC) atomicAdd(&ninsert, 1);
+            break;
+          }
+          if (old == j) break;
+          h = (h + 1) & (TBL - 1);
+          if (++probes >= TBL) { bad = true; break; }
+        }
+        if (NUMERIC && !bad) vals[h] += a * bv[q];
+      }
+      __syncthreads();
+    }
+    if (bad) atomicOr(overflow, 1);
+    if (!NUMERIC) {
+      __syncthreads();
+      if (lane == 0) {
+        cnt[i] = ninsert;
+        if (ninsert > (TBL * 3) / 4) atomicOr(overflow, 4);  // the numeric pass could not hold it
+      }
+      __syncthreads();
+      continue;
+    }
+    // compact the keys, then place every entry by its rank
+    if (lane == 0) ninsert = 0;
+    __syncthreads();
+    for (int t = lane; t < TBL; t += 64) {
+      const int key = keys[t];
+      if (key >= 0) {
+        const int pos = atomicAdd(&ninsert, 1);
+        if (pos < (TBL * 3) / 4 + 64) ckeys[pos] = key;
+      }
+    }
+    __syncthreads();
+    const int nk = ninsert;
+    const int base = cp[i];
+    if (nk != cp[i + 1] - base || nk > (TBL * 3) / 4 + 64) {
+      if (lane == 0) atomicOr(overflow, 2);
+      __syncthreads();
+      continue;
+    }
+    for (int t = lane; t < TBL; t += 64) {
+      const int key = keys[t];
+      if (key < 0) continue;
+      int r = 0;
+      for (int u = 0; u < nk; ++u) r += ckeys[u] < key ? 1 : 0;
+      cc[base + r] = key;
+      cv[base + r] = vals[t];
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ smoother data
+__global__ void k_l1_diag(int n, const int* __restrict__ ptr, const double* __restrict__ val, double* __restrict__ d,
+                          float* __restrict__ d32) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int e = ptr[i]; e < ptr[i + 1]; ++e) s += fabs(val[e]);
+  d[i] = 1.0 / s;
+  d32[i] = (float)(1.0 / s);
+}
+
+__global__ void k_inv_diag(int n, const int* __restrict__ ptr, const int* __restrict__ col,
+                           const double* __restrict__ val, double* __restrict__ d, float* __restrict__ d32) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a = 0.0;
+  for (int e = ptr[i]; e < ptr[i + 1]; ++e)
+    if (col[e] == i) a = val[e];
+  d[i] = 1.0 / a;
+  d32[i] = (float)(1.0 / a);
+}
+
+__global__ void k_to_f32(long n, const double* __restrict__ x, float* __restrict__ y) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (float)x[i];
+}
+
+// ------------------------------------------------------------ coarse inverse
+__global__ void k_dense_from_csr(int n, const int* __restrict__ ptr, const int* __restrict__ col,
+                                 const double* __restrict__ val, double* __restrict__ M) {
+  // M is n x 2n: [A | I]
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double* row = M + (size_t)i * 2 * n;
+  for (int j = 0; j < 2 * n; ++j) row[j] = (j == n + i) ? 1.0 : 0.0;
+  for (int e = ptr[i]; e < ptr[i + 1]; ++e) row[col[e]] = val[e];
+}
+
+// Gauss-Jordan elimination with partial pivoting in one workgroup.
+__global__ void __launch_bounds__(1024) k_gauss_jordan(int n, double* __restrict__ M, double* __restrict__ inv,
+                                                        int* __restrict__ singular) {
+  __shared__ double red_v[1024];
+  __shared__ int red_i[1024];
+  __shared__ double prow[1];
+  const int t = threadIdx.x, nt = blockDim.x, w = 2 * n;
+  for (int k = 0; k < n; ++k) {
+    double best = -1.0;
+    int bi = k;
+    for (int r = k + t; r < n; r += nt) {
+      double a = fabs(M[(size_t)r * w + k]);
+      if (a > best || (a == best && r < bi)) { best = a; bi = r; }
+    }
+    red_v[t] = best;
+    red_i[t] = bi;
+    __syncthreads();
+    for (int o = nt / 2; o > 0; o >>= 1) {
+      if (t < o) {
+        double a = red_v[t + o];
+        int ai = red_i[t + o];
+        if (a > red_v[t] || (a == red_v[t] && ai < red_i[t])) { red_v[t] = a; red_i[t] = ai; }
+      }
+      __syncthreads();
+    }
+    const int p = red_i[0];
+    if (red_v[0] == 0.0) {
+      if (t == 0) *singular = 1;
+      return;
+    }
+    if (p != k)
+      for (int j = t; j < w; j += nt) {
+        double x = M[(size_t)k * w + j];
+        M[(size_t)k * w + j] = M[(size_t)p * w + j];
+        M[(size_t)p * w + j] = x;
+      }
+    __syncthreads();
+    if (t == 0) prow[0] = 1.0 / M[(size_t)k * w + k];
+    __syncthreads();
+    const double ip = prow[0];
+    for (int j = t; j < w; j += nt) M[(size_t)k * w + j] *= ip;
+    __syncthreads();
+    // eliminate column k from every other row
+    for (long q = t; q < (long)n * (w - k); q += nt) {
+      const int r = (int)(q / (w - k));
+      const int j = k + (int)(q % (w - k));
+      if (r == k) continue;
+      const double f = M[(size_t)r * w + k];
+      if (j == k) continue;
+      M[(size_t)r * w + j] -= f * M[(size_t)k * w + j];
+    }
+    __syncthreads();
+    for (int r = t; r < n; r += nt)
+      if (r != k) M[(size_t)r * w + k] = 0.0;
+    __syncthreads();
+  }
+  for (long q = t; q < (long)n * n; q += nt) {
+    const int r = (int)(q / n), j = (int)(q % n);
+    inv[q] = M[(size_t)r * w + n + j];
+  }
+}
+
+// ------------------------------------------------------------ Lanczos
+__global__ void k_lanczos_init(int n, uint64_t seed, int stream, double* __restrict__ q) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t z = splitmix64(seed, ((uint64_t)stream << 40) | (uint64_t)i);
+  q[i] = 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+}
+
+// w = Dm A (Dm q) - beta q_prev, with Dm = |diag|^{-1/2}
+__global__ void k_lanczos_apply(int n, const int* __restrict__ ptr, const int* __restrict__ col,
+                                const double* __restrict__ val, const double* __restrict__ dinv,
+                                const double* __restrict__ q, const double* __restrict__ qp, double beta,
+                                double* __restrict__ w) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
+    const int j = col[e];
+    s += val[e] * sqrt(fabs(dinv[j])) * q[j];
+  }
+  w[i] = sqrt(fabs(dinv[i])) * s - beta * qp[i];
+}
+
+__global__ void k_dot_partial(int n, const double* __restrict__ x, const double* __restrict__ y,
+                              double* __restrict__ part) {
+  __shared__ double sh[256];
+  double a = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) a += x[i] * y[i];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_axpy_inplace(int n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += a * x[i];
+}
+
+__global__ void k_scale_copy(int n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i];
+}
+
+// largest eigenvalue of the symmetric tridiagonal (alpha, beta) by bisection
+// on Sturm sequence counts (single thread; k <= 32)
+__global__ void k_tridiag_max(int k, const double* __restrict__ alpha, const double* __restrict__ beta,
+                              double* __restrict__ out) {
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < k; ++i) {
+    double r = (i > 0 ? fabs(beta[i - 1]) : 0.0) + (i < k - 1 ? fabs(beta[i]) : 0.0);
+    lo = fmin(lo, alpha[i] - r);
+    hi = fmax(hi, alpha[i] + r);
+  }
+  for (int it = 0; it < 200; ++it) {
+    const double x = 0.5 * (lo + hi);
+    int cnt = 0;  // eigenvalues < x
+    double d = 1.0;
+    for (int i = 0; i < k; ++i) {
+      const double b2 = i > 0 ? beta[i - 1] * beta[i - 1] : 0.0;
+      d = alpha[i] - x - (i > 0 ? b2 / d : 0.0);
+      if (d == 0.0) d = -1e-300;
+      if (d < 0.0) ++cnt;
+    }
+    if (cnt >= k) hi = x; else lo = x;
+    if (hi - lo <= 1e-15 * fmax(fabs(lo), fabs(hi))) break;
+  }
+  out[0] = 0.5 * (lo + hi);
+}
+
+}  // namespace
+
+namespace hfsi {
+
+namespace {
+
+double dot_dev(hfsi_ctx* c, const double* x, const double* y, int n) {
+  const int nb = 256;
+  c->kred.ensure(2 * nb);
+  k_dot_partial<<<nb, 256, 0, c->stream>>>(n, x, y, c->kred.p + nb);
+  HIP_LAUNCH_CHECK();
+  return device_sum(c, c->kred.p + nb, nb);
+}
+
+// Largest Ritz value of `steps` Lanczos steps on D^{-1/2} A D^{-1/2}.
+double lanczos_max(hfsi_ctx* c, Level& L, int steps, uint64_t seed, int level) {
+  const int n = L.n;
+  hipStream_t s = c->stream;
+  DevBuf<double> q, qp, w, ab;
+  q.ensure(n); qp.zero(n, s); w.ensure(n);
+  ab.ensure(80);
+  k_lanczos_init<<<div_up(n, 256), 256, 0, s>>>(n, seed, 1000 + level, q.p);
+  HIP_LAUNCH_CHECK();
+  double nq = std::sqrt(dot_dev(c, q.p, q.p, n));
+  k_scale_copy<<<div_up(n, 256), 256, 0, s>>>(n, 1.0 / nq, q.p, q.p);
+  HIP_LAUNCH_CHECK();
+  std::vector<double> alpha, beta;
+  double b = 0.0;
+  // |diag|^{-1} for the scaling
+  DevBuf<double> dabs;
+  DevBuf<float> dummy;
+  dabs.ensure(n); dummy.ensure(n);
+  k_inv_diag<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, dabs.p, dummy.p);
+  HIP_LAUNCH_CHECK();
+  for (int it = 0; it < std::min(steps, n); ++it) {
+    k_lanczos_apply<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, dabs.p, q.p, qp.p, b, w.p);
+    HIP_LAUNCH_CHECK();
+    const double a = dot_dev(c, q.p, w.p, n);
+    k_axpy_inplace<<<div_up(n, 256), 256, 0, s>>>(n, -a, q.p, w.p);
+    HIP_LAUNCH_CHECK();
+    alpha.push_back(a);
+    b = std::sqrt(dot_dev(c, w.p, w.p, n));
+    if (b <= 1e-14 * std::fabs(a)) break;
+    beta.push_back(b);
+    std::swap(q.p, qp.p);  // qp <- q
+    k_scale_copy<<<div_up(n, 256), 256, 0, s>>>(n, 1.0 / b, w.p, q.p);
+    HIP_LAUNCH_CHECK();
+  }
+  const int k = (int)alpha.size();
+  std::vector<double> buf(64, 0.0);
+  for (int i = 0; i < k; ++i) buf[i] = alpha[i];
+  for (int i = 0; i + 1 < k && i < (int)beta.size(); ++i) buf[32 + i] = beta[i];
+  ab.upload(buf.data(), 64, s);
+  k_tridiag_max<<<1, 1, 0, s>>>(k, ab.p, ab.p + 32, ab.p + 64);
+  HIP_LAUNCH_CHECK();
+  double lmax = 0.0;
+  HIP_CHECK(hipMemcpyAsync(&lmax, ab.p + 64, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  return lmax;
+}
+
+void transpose(hfsi_ctx* c, const Csr<double>& P, Csr<double>& R) {
+  hipStream_t s = c->stream;
+  R.rows = P.cols;
+  R.cols = P.rows;
+  R.nnz = P.nnz;
+  DevBuf<int> cnt, cur;
+  cnt.zero(R.rows + 1, s);
+  k_count_cols<<<div_up(P.rows, 256), 256, 0, s>>>(P.rows, P.ptr.p, P.col.p, cnt.p);
+  HIP_LAUNCH_CHECK();
+  R.ptr.ensure(R.rows + 1);
+  exclusive_scan_async(cnt.p, R.ptr.p, R.rows + 1, s);
+  cur.zero(R.rows, s);
+  R.col.ensure(R.nnz);
+  R.val.ensure(R.nnz);
+  k_transpose_fill<<<div_up(P.rows, 256), 256, 0, s>>>(P.rows, P.ptr.p, P.col.p, P.val.p, R.ptr.p, cur.p, R.col.p,
+                                                       R.val.p);
+  HIP_LAUNCH_CHECK();
+  k_sort_rows<<<div_up(R.rows, 256), 256, 0, s>>>(R.rows, R.ptr.p, R.col.p, R.val.p);
+  HIP_LAUNCH_CHECK();
+}
+
+// C = A B with the structural pattern (no numerical dropping).
+void spgemm(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>& Cm) {
+  hipStream_t s = c->stream;
+  const int n = A.rows;
+  Cm.rows = n;
+  Cm.cols = B.cols;
+  DevBuf<int> ub, cnt, flag;
+  ub.ensure(n);
+  cnt.zero(n + 1, s);
+  flag.zero(1, s);
+  k_spgemm_ub<<<div_up(n, 256), 256, 0, s>>>(n, A.ptr.p, A.col.p, B.ptr.p, ub.p);
+  HIP_LAUNCH_CHECK();
+  constexpr int TS = 2048, TL = 8192;
+  const int grid = std::min(n, 1 << 16);
+  // symbolic: rows with ub <= 3/4 TS use the small table, others the large one
+  k_spgemm<TS, false><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, nullptr, B.ptr.p, B.col.p, nullptr, ub.p, 0,
+                                          TS * 3 / 4, cnt.p, nullptr, nullptr, nullptr, flag.p);
+  HIP_LAUNCH_CHECK();
+  k_spgemm<TL, false><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, nullptr, B.ptr.p, B.col.p, nullptr, ub.p,
+                                          TS * 3 / 4 + 1, INT32_MAX, cnt.p, nullptr, nullptr, nullptr, flag.p);
+  HIP_LAUNCH_CHECK();
+  Cm.ptr.ensure(n + 1);
+  int64_t nnz = exclusive_scan(cnt.p, Cm.ptr.p, n + 1, s);
+  int fl = 0;
+  HIP_CHECK(hipMemcpyAsync(&fl, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  if (fl) fail(HFSI_E_CAPACITY, "sparse product: a row exceeds the hash table");
+  if (nnz > INT32_MAX) fail(HFSI_E_ARG, "sparse product exceeds int32 indexing");
+  Cm.nnz = nnz;
+  Cm.col.ensure(nnz);
+  Cm.val.ensure(nnz);
+  // numeric: dispatch on the exact row count
+  k_spgemm<TS, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 0,
+                                         TS * 3 / 4, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p);
+  HIP_LAUNCH_CHECK();
+  k_spgemm<TL, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p,
+                                         TS * 3 / 4 + 1, TL * 3 / 4, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p);
+  HIP_LAUNCH_CHECK();
+  HIP_CHECK(hipMemcpyAsync(&fl, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  if (fl) fail(HFSI_E_CAPACITY, "sparse product: a row has more than 6144 entries");
+}
+
+void smoother_data(hfsi_ctx* c, Level& L, const hfsi_amg_params& prm, int level) {
+  hipStream_t s = c->stream;
+  L.dinv.ensure(L.n);
+  L.dinv32.ensure(L.n);
+  if (prm.smoother == 0) {
+    k_l1_diag<<<div_up(L.n, 256), 256, 0, s>>>(L.n, L.A.ptr.p, L.A.val.p, L.dinv.p, L.dinv32.p);
+    HIP_LAUNCH_CHECK();
+  } else {
+    k_inv_diag<<<div_up(L.n, 256), 256, 0, s>>>(L.n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.dinv.p, L.dinv32.p);
+    HIP_LAUNCH_CHECK();
+    L.lmax = lanczos_max(c, L, 10, prm.seed, level);
+  }
+}
+
+void alloc_vectors(Level& L) {
+  L.x.ensure(L.n); L.b.ensure(L.n); L.r.ensure(L.n); L.t.ensure(L.n);
+  L.xf.ensure(L.n); L.bf.ensure(L.n); L.rf.ensure(L.n); L.tf.ensure(L.n);
+}
+
+void copy_csr(hfsi_ctx* c, const Csr<double>& src, Csr<double>& dst) {
+  dst.rows = src.rows;
+  dst.cols = src.cols;
+  dst.nnz = src.nnz;
+  dst.ptr.ensure(src.rows + 1);
+  dst.col.ensure(src.nnz);
+  dst.val.ensure(src.nnz);
+  HIP_CHECK(hipMemcpyAsync(dst.ptr.p, src.ptr.p, sizeof(int) * (src.rows + 1), hipMemcpyDeviceToDevice, c->stream));
+  HIP_CHECK(hipMemcpyAsync(dst.col.p, src.col.p, sizeof(int) * src.nnz, hipMemcpyDeviceToDevice, c->stream));
+  HIP_CHECK(hipMemcpyAsync(dst.val.p, src.val.p, sizeof(double) * src.nnz, hipMemcpyDeviceToDevice, c->stream));
+}
+
+__global__ void k_comp_mod3(int n, int* __restrict__ comp) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) comp[i] = i % 3;
+}
+
+}  // namespace
+
+// Build levels 1.. from level 0 (whose A and comp are already set).
+void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {
+  hipStream_t s = c->stream;
+  Hierarchy& H = c->H;
+  H.ready = false;
+  H.precision = prm.precision;
+  H.smoother = prm.smoother;
+  H.nu_pre = prm.nu_pre;
+  H.nu_post = prm.nu_post;
+  HIP_CHECK(hipEventRecord(c->ev0, s));
+  int rounds_total = 0;
+  DevBuf<int> lam, notmax, flag, rem;
+  DevBuf<uint64_t> key;
+  rem.ensure(1);
+  for (int l = 0;; ++l) {
+    Level& L = H.L[l];
+    const int n = L.n;
+    alloc_vectors(L);
+    smoother_data(c, L, prm, l);
+    if (n <= prm.max_coarse || l + 1 >= prm.max_levels || l + 1 >= 32) break;
+    // strength and PMIS
+    L.strong.ensure(L.A.nnz);
+    k_strength<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.comp.p, prm.strength_theta,
+                                              L.strong.p);
+    HIP_LAUNCH_CHECK();
+    lam.zero(n, s);
+    k_lambda<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.strong.p, lam.p);
+    HIP_LAUNCH_CHECK();
+    key.ensure(n);
+    L.state.ensure(n);
+    k_pmis_init<<<div_up(n, 256), 256, 0, s>>>(n, lam.p, prm.seed, l, key.p, L.state.p);
+    HIP_LAUNCH_CHECK();
+    notmax.ensure(n);
+    for (int round = 0;; ++round) {
+      if (round > n + 1) fail(HFSI_E_HIP, "PMIS did not terminate");
+      HIP_CHECK(hipMemsetAsync(notmax.p, 0, sizeof(int) * n, s));
+      HIP_CHECK(hipMemsetAsync(rem.p, 0, sizeof(int), s));
+      k_pmis_select<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.strong.p, key.p, L.state.p, notmax.p);
+      HIP_LAUNCH_CHECK();
+      k_pmis_mark_c<<<div_up(n, 256), 256, 0, s>>>(n, notmax.p, L.state.p);
+      HIP_LAUNCH_CHECK();
+      k_pmis_mark_f<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.strong.p, L.state.p, rem.p);
+      HIP_LAUNCH_CHECK();
+      int left = 0;
+      HIP_CHECK(hipMemcpyAsync(&left, rem.p, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_CHECK(hipStreamSynchronize(s));
+      ++rounds_total;
+      if (left == 0) break;
+    }
+    // coarse numbering
+    flag.ensure(n + 1);
+    HIP_CHECK(hipMemsetAsync(flag.p + n, 0, sizeof(int), s));
+    k_is_c<<<div_up(n, 256), 256, 0, s>>>(n, L.state.p, flag.p);
+    HIP_LAUNCH_CHECK();
+    L.cidx.ensure(n + 1);
+    const int nc = (int)exclusive_scan(flag.p, L.cidx.p, n + 1, s);
+    if (nc == 0 || nc > 0.9 * n) break;
+    // interpolation
+    DevBuf<int> cnt;
+    cnt.ensure(n + 1);
+    HIP_CHECK(hipMemsetAsync(cnt.p + n, 0, sizeof(int), s));
+    k_interp_count<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.strong.p, L.state.p, cnt.p);
+    HIP_LAUNCH_CHECK();
+    L.P.rows = n;
+    L.P.cols = nc;
+    L.P.ptr.ensure(n + 1);
+    L.P.nnz = exclusive_scan(cnt.p, L.P.ptr.p, n + 1, s);
+    L.P.col.ensure(L.P.nnz);
+    L.P.val.ensure(L.P.nnz);
+    k_interp_fill<<<div_up(n, 128), 128, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p, L.state.p, L.comp.p,
+                                                 L.cidx.p, L.P.ptr.p, L.P.col.p, L.P.val.p);
+    HIP_LAUNCH_CHECK();
+    transpose(c, L.P, L.R);
+    // Galerkin product
+    Csr<double> AP;
+    spgemm(c, L.A, L.P, AP);
+    H.L.emplace_back();
+    Level& Lc = H.L.back();
+    Level& Lf = H.L[l];  // reference may move with emplace_back
+    spgemm(c, Lf.R, AP, Lc.A);
+    Lc.n = nc;
+    Lc.comp.ensure(nc);
+    k_coarse_comp<<<div_up(n, 256), 256, 0, s>>>(n, Lf.state.p, Lf.cidx.p, Lf.comp.p, Lc.comp.p);
+    HIP_LAUNCH_CHECK();
+    if (prm.precision == 1) {
+      Lf.P32.ensure(Lf.P.nnz);
+      Lf.R32.ensure(Lf.R.nnz);
+      k_to_f32<<<div_up(Lf.P.nnz, 256), 256, 0, s>>>(Lf.P.nnz, Lf.P.val.p, Lf.P32.p);
+      k_to_f32<<<div_up(Lf.R.nnz, 256), 256, 0, s>>>(Lf.R.nnz, Lf.R.val.p, Lf.R32.p);
+      HIP_LAUNCH_CHECK();
+    }
+  }
+  // fp32 operator copies
+  if (prm.precision == 1)
+    for (auto& L : H.L) {
+      L.A32.ensure(L.A.nnz);
+      k_to_f32<<<div_up(L.A.nnz, 256), 256, 0, s>>>(L.A.nnz, L.A.val.p, L.A32.p);
+      HIP_LAUNCH_CHECK();
+    }
+  // coarsest level: explicit inverse
+  Level& Lc = H.L.back();
+  const int nc = Lc.n;
+  if (nc > 4096) fail(HFSI_E_CAPACITY, "coarsest level larger than 4096 rows (coarsening stalled)");
+  H.nc = nc;
+  DevBuf<double> M;
+  DevBuf<int> sing;
+  M.ensure(2 * (size_t)nc * nc);
+  sing.zero(1, s);
+  H.coarse_inv.ensure((size_t)nc * nc);
+  H.cwork.ensure(2 * (size_t)nc);
+  k_dense_from_csr<<<div_up(nc, 256), 256, 0, s>>>(nc, Lc.A.ptr.p, Lc.A.col.p, Lc.A.val.p, M.p);
+  HIP_LAUNCH_CHECK();
+  k_gauss_jordan<<<1, 1024, 0, s>>>(nc, M.p, H.coarse_inv.p, sing.p);
+  HIP_LAUNCH_CHECK();
+  HIP_CHECK(hipEventRecord(c->ev1, s));
+  int sg = 0;
+  HIP_CHECK(hipMemcpyAsync(&sg, sing.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  if (sg) fail(HFSI_E_BREAKDOWN, "coarsest AMG operator is singular");
+  H.ready = true;
+  if (info) {
+    info->levels = (int)H.L.size();
+    double nnz0 = (double)H.L[0].A.nnz, rows0 = (double)H.L[0].n, sn = 0, sr = 0;
+    for (size_t l = 0; l < H.L.size() && l < 32; ++l) {
+      info->rows[l] = H.L[l].n;
+      info->nnz[l] = H.L[l].A.nnz;
+      sn += (double)H.L[l].A.nnz;
+      sr += H.L[l].n;
+    }
+    info->op_complexity = sn / nnz0;
+    info->grid_complexity = sr / rows0;
+    info->seconds = elapsed_ms(c) * 1e-3;
+    info->pmis_rounds = rounds_total;
+    info->rho = -1.0;
+    info->learned_used = 0;
+  }
+}
+
+void amg_setup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {
+  Hierarchy& H = c->H;
+  H.L.clear();
+  H.L.emplace_back();
+  Level& L0 = H.L[0];
+  copy_csr(c, c->A, L0.A);
+  L0.n = c->A.rows;
+  L0.comp.ensure(L0.n);
+  k_comp_mod3<<<div_up(L0.n, 256), 256, 0, c->stream>>>(L0.n, L0.comp.p);
+  HIP_LAUNCH_CHECK();
+  build_hierarchy(c, prm, info);
+}
+
+void check_amg_params(const hfsi_amg_params* p) {
+  if (!p || p->struct_size != sizeof(hfsi_amg_params)) fail(HFSI_E_ARG, "amg params: struct_size mismatch");
+  if (!(p->strength_theta > 0.0 && p->strength_theta <= 1.0)) fail(HFSI_E_ARG, "amg params: theta in (0,1]");
+  if (p->max_coarse < 1 || p->max_levels < 1) fail(HFSI_E_ARG, "amg params: bad level limits");
+  if (p->smoother < 0 || p->smoother > 1 || p->nu_pre < 0 || p->nu_post < 0 || p->nu_pre + p->nu_post < 1)
+    fail(HFSI_E_ARG, "amg params: bad smoother");
+  if (p->precision < 0 || p->precision > 1) fail(HFSI_E_ARG, "amg params: bad precision");
+}
+
+}  // namespace hfsi
+
+extern "C" hfsi_status hfsi_amg_setup(hfsi_ctx* c, const hfsi_amg_params* prm, hfsi_amg_info* info) {
+  HFSI_ABI_BEGIN(c)
+  require_stage(c, 4, "amg_setup");
+  hfsi::check_amg_params(prm);
+  if (info && info->struct_size != sizeof(hfsi_amg_info)) fail(HFSI_E_ARG, "amg info: struct_size mismatch");
+  hfsi::amg_setup_level0(c, *prm, info);
+  HFSI_ABI_END(c)
+}
+
+extern "C" hfsi_status hfsi_amg_setup_csr(hfsi_ctx* c, int32_t n, const int32_t* ptr, const int32_t* col,
+                                          const double* val, const int32_t* comp, const hfsi_amg_params* prm,
+                                          hfsi_amg_info* info) {
+  HFSI_ABI_BEGIN(c)
+  hfsi::check_amg_params(prm);
+  if (n <= 0 || !ptr || !col || !val || !comp) fail(HFSI_E_ARG, "amg_setup_csr: bad arguments");
+  if (info && info->struct_size != sizeof(hfsi_amg_info)) fail(HFSI_E_ARG, "amg info: struct_size mismatch");
+  const int64_t nnz = ptr[n];
+  if (ptr[0] != 0 || nnz < n) fail(HFSI_E_ARG, "amg_setup_csr: bad row pointer");
+  for (int i = 0; i < n; ++i) {
+    if (ptr[i + 1] < ptr[i]) fail(HFSI_E_ARG, "amg_setup_csr: row pointer not monotone");
+    for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
+      if (col[e] < 0 || col[e] >= n) fail(HFSI_E_ARG, "amg_setup_csr: column out of range");
+      if (e > ptr[i] && col[e] <= col[e - 1]) fail(HFSI_E_ARG, "amg_setup_csr: columns not strictly ascending");
+    }
+  }
+  hfsi::Hierarchy& H = c->H;
+  H.L.clear();
+  H.L.emplace_back();
+  hfsi::Level& L0 = H.L[0];
+  L0.n = n;
+  L0.A.rows = L0.A.cols = n;
+  L0.A.nnz = nnz;
+  L0.A.ptr.upload(ptr, n + 1, c->stream);
+  L0.A.col.upload(col, nnz, c->stream);
+  L0.A.val.upload(val, nnz, c->stream);
+  L0.comp.upload(comp, n, c->stream);
+  hfsi::build_hierarchy(c, *prm, info);
+  HFSI_ABI_END(c)
+}
+
+extern "C" hfsi_status hfsi_amg_export(hfsi_ctx* c, int32_t level, int32_t which, int32_t* rows, int32_t* cols,
+                                       int64_t* nnz, int32_t* ptr, int32_t* col, double* val, uint8_t* val_u8) {
+  HFSI_ABI_BEGIN(c)
+  hfsi::Hierarchy& H = c->H;
+  if (!H.ready) fail(HFSI_E_ORDER, "amg_export: no hierarchy");
+  if (level < 0 || level >= (int)H.L.size()) fail(HFSI_E_ARG, "amg_export: level out of range");
+  hfsi::Level& L = H.L[level];
+  const bool last = level == (int)H.L.size() - 1;
+  hipStream_t s = c->stream;
+  auto cp = [&](void* dst, const void* src, size_t bytes) {
+    if (dst && bytes) HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+  };
+  if (which == 0 || which == 1) {
+    if (which == 1 && last) fail(HFSI_E_ARG, "amg_export: the coarsest level has no P");
+    const hfsi::Csr<double>& M = which == 0 ? L.A : L.P;
+    if (rows) *rows = M.rows;
+    if (cols) *cols = M.cols;
+    if (nnz) *nnz = M.nnz;
+    cp(ptr, M.ptr.p, sizeof(int) * (M.rows + 1));
+    cp(col, M.col.p, sizeof(int) * M.nnz);
+    cp(val, M.val.p, sizeof(double) * M.nnz);
+  } else if (which == 2 || which == 3) {
+    if (last) fail(HFSI_E_ARG, "amg_export: the coarsest level has no splitting");
+    if (rows) *rows = L.n;
+    if (cols) *cols = 0;
+    const int64_t k = which == 2 ? L.A.nnz : L.n;
+    if (nnz) *nnz = k;
+    cp(val_u8, which == 2 ? (const void*)L.strong.p : (const void*)L.state.p, (size_t)k);
+  } else if (which == 4) {
+    if (rows) *rows = L.n;
+    if (cols) *cols = 0;
+    if (nnz) *nnz = L.n;
+    cp(col, L.comp.p, sizeof(int) * L.n);
+  } else {
+    fail(HFSI_E_ARG, "amg_export: unknown item");
+  }
+  HIP_CHECK(hipStreamSynchronize(s));
+  HFSI_ABI_END(c)
+}

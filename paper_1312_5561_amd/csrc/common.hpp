@@ -206,6 +206,8 @@ void require_stage(hfsi_ctx* c, int st, const char* what);
 void assemble(hfsi_ctx* c, const double* v, double load, double* R, hfsi_assembly_info* info);
 void build_a_pattern(hfsi_ctx* c);
 void amg_setup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info);
+void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info);
+void check_amg_params(const hfsi_amg_params* p);
 void vcycle_apply(hfsi_ctx* c, const double* r, double* z);
 void precond_apply(hfsi_ctx* c, const double* r, double* z);
 void tangent_apply(hfsi_ctx* c, const double* x, double* y);

@@ -1,0 +1,729 @@
+// V-cycle, block-triangular preconditioner, FGMRES and the Newton step.
+//
+//  * V-cycle (fp64 or fp32 vectors and operators, coarsest solve in fp64):
+//    nu_pre smoothing sweeps from a zero guess, residual, restriction by R,
+//    recursion, prolongation x += P x_c, nu_post sweeps.
+//  * P_L^{-1} of eq. lpre: z_u = Atilde^{-1} r_u (one V-cycle on A),
+//    z_p = Stilde^{-1} (B2 z_u - r_p) with Stilde = (1/theta + 1/kappa) diag(M_p)
+//    (eq. lpreschur); B2 is read from the pressure row of the 4x4 blocks of K.
+//  * right-preconditioned FGMRES(m): classical Gram-Schmidt with one
+//    re-orthogonalisation, Givens rotations on the device, one host
+//    synchronisation per iteration for the convergence test, true residual
+//    recomputed after every cycle.
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+
+#include "common.hpp"
+
+using namespace hfsi;
+
+namespace {
+
+enum { OP_SPMV = 0, OP_RESID = 1, OP_JACOBI = 2, OP_ADD = 3, OP_CHEB = 4 };
+
+// y = f(A x) with G lanes per row.
+template <class T, int G, int OP>
+__global__ void __launch_bounds__(256)
+k_csr(int n, const int* __restrict__ ptr, const int* __restrict__ col, const T* __restrict__ val,
+      const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ dinv, T* __restrict__ y,
+      T* __restrict__ d, T c1, T c2) {
+  const int gid = (blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  if (gid >= n) return;
+  T s = 0;
+  const int hi = ptr[gid + 1];
+  for (int e = ptr[gid] + lane; e < hi; e += G) s += val[e] * x[col[e]];
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+  if (lane != 0) return;
+  if (OP == OP_SPMV) y[gid] = s;
+  else if (OP == OP_RESID) y[gid] = b[gid] - s;
+  else if (OP == OP_JACOBI) y[gid] = x[gid] + dinv[gid] * (b[gid] - s);
+  else if (OP == OP_ADD) y[gid] += s;
+  else {  // Chebyshev step: d = c1 d + c2 D^{-1}(b - A x), y = x + d
+    const T dn = c1 * d[gid] + c2 * dinv[gid] * (b[gid] - s);
+    d[gid] = dn;
+    y[gid] = x[gid] + dn;
+  }
+}
+
+template <class T, int OP>
+void csr_launch(int G, int n, const int* ptr, const int* col, const T* val, const T* x, const T* b, const T* dinv,
+                T* y, T* d, T c1, T c2, hipStream_t s) {
+  if (n <= 0) return;
+  const long threads = (long)n * G;
+  const int grid = div_up(threads, 256);
+  switch (G) {
+    case 4: k_csr<T, 4, OP><<<grid, 256, 0, s>>>(n, ptr, col, val, x, b, dinv, y, d, c1, c2); break;
+    case 8: k_csr<T, 8, OP><<<grid, 256, 0, s>>>(n, ptr, col, val, x, b, dinv, y, d, c1, c2); break;
+    case 16: k_csr<T, 16, OP><<<grid, 256, 0, s>>>(n, ptr, col, val, x, b, dinv, y, d, c1, c2); break;
+    case 32: k_csr<T, 32, OP><<<grid, 256, 0, s>>>(n, ptr, col, val, x, b, dinv, y, d, c1, c2); break;
+    default: k_csr<T, 64, OP><<<grid, 256, 0, s>>>(n, ptr, col, val, x, b, dinv, y, d, c1, c2); break;
+  }
+  HIP_LAUNCH_CHECK();
+}
+
+inline int lanes_for(int64_t nnz, int rows) {
+  const double avg = rows ? (double)nnz / rows : 1.0;
+  if (avg <= 8) return 4;
+  if (avg <= 24) return 8;
+  if (avg <= 64) return 16;
+  if (avg <= 160) return 32;
+  return 64;
+}
+
+template <class T>
+__global__ void k_scale_vec(int n, const T* __restrict__ d, const T* __restrict__ b, T* __restrict__ x, T c) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = c * d[i] * b[i];
+}
+
+template <class T>
+__global__ void k_cheb_first(int n, const T* __restrict__ dinv, const T* __restrict__ b, T* __restrict__ x,
+                             T* __restrict__ d, T c2) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T dn = c2 * dinv[i] * b[i];
+  d[i] = dn;
+  x[i] = dn;
+}
+
+template <class Tin, class Tout>
+__global__ void k_cast(int n, const Tin* __restrict__ x, Tout* __restrict__ y) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (Tout)x[i];
+}
+
+// coarse solve: y = Ainv b, one wavefront per row
+__global__ void k_dense_gemv(int n, const double* __restrict__ M, const double* __restrict__ x, double* __restrict__ y) {
+  const int row = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
+  const int lane = threadIdx.x % 64;
+  if (row >= n) return;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64) s += M[(size_t)row * n + j] * x[j];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) y[row] = s;
+}
+
+// ---- block matrix K (4x4 blocks), 16 lanes per node row
+template <int OP>
+__global__ void __launch_bounds__(256)
+k_bsr4(int n, const int* __restrict__ bptr, const int* __restrict__ bcol, const double* __restrict__ bval,
+       const double* __restrict__ x, const double* __restrict__ b, double* __restrict__ y) {
+  const int gid = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int lane = threadIdx.x & 15;
+  if (gid >= n) return;
+  const int c = lane & 3;
+  double s = 0.0;
+  for (int q = bptr[gid]; q < bptr[gid + 1]; ++q) s += bval[16 * (size_t)q + lane] * x[4 * bcol[q] + c];
+  s += __shfl_xor(s, 1, 16);
+  s += __shfl_xor(s, 2, 16);
+  if (c == 0) {
+    const int r = lane >> 2;
+    if (OP == OP_SPMV) y[4 * gid + r] = s;
+    else y[4 * gid + r] = b[4 * gid + r] - s;
+  }
+}
+
+// r_u (node-interleaved fp64) -> level-0 right-hand side in T
+template <class T>
+__global__ void k_split_u(int n, const double* __restrict__ r, T* __restrict__ bu) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * n) return;
+  const int i = t / 3, c = t - 3 * i;
+  bu[t] = (T)r[4 * i + c];
+}
+
+// z_p = (B2 z_u - r_p) / s, z_u copied into the node-interleaved output
+template <class T>
+__global__ void __launch_bounds__(256)
+k_pl_combine(int n, const int* __restrict__ bptr, const int* __restrict__ bcol, const double* __restrict__ bval,
+             const T* __restrict__ zu, const double* __restrict__ r, const double* __restrict__ schur,
+             double* __restrict__ z) {
+  const int gid = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int lane = threadIdx.x & 15;
+  if (gid >= n) return;
+  double s = 0.0;
+  for (int q = bptr[gid] + lane; q < bptr[gid + 1]; q += 16) {
+    const int j = bcol[q];
+    const double* blk = bval + 16 * (size_t)q + 12;
+    s += blk[0] * (double)zu[3 * j] + blk[1] * (double)zu[3 * j + 1] + blk[2] * (double)zu[3 * j + 2];
+  }
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
+  if (lane == 0) z[4 * gid + 3] = (s - r[4 * gid + 3]) / schur[gid];
+  else if (lane < 4) z[4 * gid + lane - 1] = (double)zu[3 * gid + lane - 1];
+}
+
+// ---- Krylov vector kernels
+constexpr int RED_BLOCKS = 512;
+
+// partial dot products of up to 8 basis vectors with w per block
+__global__ void __launch_bounds__(256)
+k_mdot(long N, int k, const double* __restrict__ V, long ldv, const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double sh[8][256];
+  const int i0 = blockIdx.y * 8;
+  const int kk = min(8, k - i0);
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long)gridDim.x * 256) {
+    const double we = w[e];
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+      if (t < kk) acc[t] += V[(i0 + t) * ldv + e] * we;
+  }
+#pragma unroll
+  for (int t = 0; t < 8; ++t) sh[t][threadIdx.x] = acc[t];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+#pragma unroll
+      for (int t = 0; t < 8; ++t) sh[t][threadIdx.x] += sh[t][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x < kk) part[(long)(i0 + threadIdx.x) * gridDim.x + blockIdx.x] = sh[threadIdx.x][0];
+}
+
+// out[i] (+)= sum_b part[i*nb + b]
+__global__ void k_reduce_rows(int k, int nb, const double* __restrict__ part, double* __restrict__ out, int accumulate) {
+  __shared__ double sh[256];
+  const int i = blockIdx.x;
+  if (i >= k) return;
+  double a = 0.0;
+  for (int t = threadIdx.x; t < nb; t += 256) a += part[(long)i * nb + t];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = accumulate ? out[i] + sh[0] : sh[0];
+}
+
+// w += sgn * sum_{i<k} V_i h_i
+__global__ void __launch_bounds__(256)
+k_vupdate(long N, int k, const double* __restrict__ V, long ldv, const double* __restrict__ h, double sgn,
+          double* __restrict__ w) {
+  __shared__ double hs[64];
+  if (threadIdx.x < k) hs[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= N) return;
+  double s = 0.0;
+  for (int i = 0; i < k; ++i) s += V[i * ldv + e] * hs[i];
+  w[e] += sgn * s;
+}
+
+__global__ void k_norm_partial(long N, const double* __restrict__ x, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double a = 0.0;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < N; i += (long)gridDim.x * 256) a += x[i] * x[i];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_norm_final(int nb, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double a = 0.0;
+  for (int t = threadIdx.x; t < nb; t += 256) a += part[t];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sqrt(sh[0]);
+}
+
+// y = x / *s
+__global__ void k_div_scalar(long N, const double* __restrict__ x, const double* __restrict__ s, double* __restrict__ y) {
+  long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < N) y[i] = x[i] / s[0];
+}
+
+__global__ void k_axpy(long N, double a, const double* __restrict__ x, double* __restrict__ y) {
+  long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < N) y[i] += a * x[i];
+}
+
+// Krylov state layout in kh: H (m+1) x m column-major at 0, cs at HS, sn at HS+m,
+// g at HS+2m, y at HS+3m+1.
+struct KState {
+  int m;
+  __host__ __device__ long HS() const { return (long)(m + 1) * m; }
+  __host__ __device__ long cs() const { return HS(); }
+  __host__ __device__ long sn() const { return HS() + m; }
+  __host__ __device__ long g() const { return HS() + 2 * m; }
+  __host__ __device__ long y() const { return HS() + 3 * m + 1; }
+  __host__ __device__ long size() const { return HS() + 4 * m + 2; }
+};
+
+__global__ void k_kinit(double* __restrict__ kh, int m, const double* __restrict__ beta) {
+  KState st{m};
+  for (long t = 0; t < st.size(); ++t) kh[t] = 0.0;
+  kh[st.g()] = beta[0];
+}
+
+// Column j of H holds h (j+1 entries) and H[j+1][j] = hnorm.  Apply the
+// previous rotations, form rotation j, update g; report |g_{j+1}|.
+__global__ void k_givens(double* __restrict__ kh, int m, int j, const double* __restrict__ hnorm,
+                         double* __restrict__ report) {
+  KState st{m};
+  double* H = kh;
+  double* cs = kh + st.cs();
+  double* sn = kh + st.sn();
+  double* g = kh + st.g();
+  double* col = H + (long)j * (m + 1);
+  col[j + 1] = hnorm[0];
+  for (int i = 0; i < j; ++i) {
+    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double d = hypot(col[j], col[j + 1]);
+  const double hj1 = col[j + 1];
+  cs[j] = col[j] / d;
+  sn[j] = hj1 / d;
+  col[j] = d;
+  col[j + 1] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  report[0] = fabs(g[j + 1]);
+  report[1] = hj1;
+}
+
+// back substitution H y = g on the first k columns
+__global__ void k_backsolve(double* __restrict__ kh, int m, int k) {
+  KState st{m};
+  const double* H = kh;
+  const double* g = kh + st.g();
+  double* y = kh + st.y();
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int t = i + 1; t < k; ++t) s -= H[(long)t * (m + 1) + i] * y[t];
+    y[i] = s / H[(long)i * (m + 1) + i];
+  }
+}
+
+__global__ void k_store_col(double* __restrict__ kh, int m, int j, const double* __restrict__ h) {
+  const int i = threadIdx.x;
+  if (i <= j) kh[(long)j * (m + 1) + i] = h[i];
+}
+
+}  // namespace
+
+namespace hfsi {
+
+namespace {
+
+template <class T>
+struct LevelView {
+  const T* A;
+  const T* P;
+  const T* R;
+  const T* dinv;
+  T *x, *t, *b, *r;
+};
+
+template <class T>
+LevelView<T> view(Level& L, bool last);
+
+template <>
+LevelView<double> view<double>(Level& L, bool last) {
+  return {L.A.val.p, last ? nullptr : L.P.val.p, last ? nullptr : L.R.val.p, L.dinv.p, L.x.p, L.t.p, L.b.p, L.r.p};
+}
+template <>
+LevelView<float> view<float>(Level& L, bool last) {
+  return {L.A32.p, last ? nullptr : L.P32.p, last ? nullptr : L.R32.p, L.dinv32.p, L.xf.p, L.tf.p, L.bf.p, L.rf.p};
+}
+
+// smoothing sweeps on level L; x holds the current iterate (in buffer xa),
+// returns the buffer that holds the result (xa or xb).
+template <class T>
+T* smooth(hfsi_ctx* c, Level& L, const LevelView<T>& v, const T* b, T* xa, T* xb, int nu, bool zero_start) {
+  hipStream_t s = c->stream;
+  const int n = L.n;
+  const int G = lanes_for(L.A.nnz, n);
+  const Hierarchy& H = c->H;
+  if (H.smoother == 0) {
+    for (int k = 0; k < nu; ++k) {
+      if (zero_start && k == 0) {
+        k_scale_vec<T><<<div_up(n, 256), 256, 0, s>>>(n, v.dinv, b, xa, (T)1);
+        HIP_LAUNCH_CHECK();
+        continue;
+      }
+      csr_launch<T, OP_JACOBI>(G, n, L.A.ptr.p, L.A.col.p, v.A, xa, b, v.dinv, xb, nullptr, 0, 0, s);
+      std::swap(xa, xb);
+    }
+    return xa;
+  }
+  // Chebyshev of degree 2 on D^{-1} A over [lmax/30, 1.1 lmax], nu times
+  const double hi = 1.1 * L.lmax, lo = L.lmax / 30.0;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  const double rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
+  T* d = v.r;  // direction vector (the residual buffer is free during smoothing)
+  for (int k = 0; k < nu; ++k) {
+    if (zero_start && k == 0) {
+      k_cheb_first<T><<<div_up(n, 256), 256, 0, s>>>(n, v.dinv, b, xa, d, (T)(1.0 / theta));
+      HIP_LAUNCH_CHECK();
+    } else {
+      csr_launch<T, OP_CHEB>(G, n, L.A.ptr.p, L.A.col.p, v.A, xa, b, v.dinv, xb, d, (T)0, (T)(1.0 / theta), s);
+      std::swap(xa, xb);
+    }
+    csr_launch<T, OP_CHEB>(G, n, L.A.ptr.p, L.A.col.p, v.A, xa, b, v.dinv, xb, d, (T)(rho1 * rho0),
+                           (T)(2.0 * rho1 / delta), s);
+    std::swap(xa, xb);
+  }
+  return xa;
+}
+
+// V-cycle on level l with right-hand side in L.b; returns the buffer holding x.
+template <class T>
+T* vcycle_rec(hfsi_ctx* c, int l) {
+  Hierarchy& H = c->H;
+  hipStream_t s = c->stream;
+  Level& L = H.L[l];
+  const bool last = l == (int)H.L.size() - 1;
+  LevelView<T> v = view<T>(L, last);
+  const int n = L.n;
+  if (last) {
+    double* bw = H.cwork.p;
+    double* xw = H.cwork.p + n;
+    const double* bd;
+    if (std::is_same<T, double>::value) {
+      bd = (const double*)v.b;
+    } else {
+      k_cast<T, double><<<div_up(n, 256), 256, 0, s>>>(n, v.b, bw);
+      HIP_LAUNCH_CHECK();
+      bd = bw;
+    }
+    k_dense_gemv<<<div_up((long)n * 64, 256), 256, 0, s>>>(n, H.coarse_inv.p, bd, xw);
+    HIP_LAUNCH_CHECK();
+    k_cast<double, T><<<div_up(n, 256), 256, 0, s>>>(n, xw, v.x);
+    HIP_LAUNCH_CHECK();
+    return v.x;
+  }
+  T* x = v.x;
+  if (H.nu_pre > 0) {
+    x = smooth<T>(c, L, v, v.b, v.x, v.t, H.nu_pre, true);
+  } else {
+    HIP_CHECK(hipMemsetAsync(v.x, 0, sizeof(T) * n, s));
+  }
+  T* other = x == v.x ? v.t : v.x;
+  const int G = lanes_for(L.A.nnz, n);
+  csr_launch<T, OP_RESID>(G, n, L.A.ptr.p, L.A.col.p, v.A, x, v.b, nullptr, v.r, nullptr, 0, 0, s);
+  Level& Lc = H.L[l + 1];
+  LevelView<T> vc = view<T>(Lc, l + 1 == (int)H.L.size() - 1);
+  csr_launch<T, OP_SPMV>(lanes_for(L.R.nnz, L.R.rows), L.R.rows, L.R.ptr.p, L.R.col.p, v.R, v.r, nullptr, nullptr,
+                         vc.b, nullptr, 0, 0, s);
+  T* xc = vcycle_rec<T>(c, l + 1);
+  csr_launch<T, OP_ADD>(lanes_for(L.P.nnz, n), n, L.P.ptr.p, L.P.col.p, v.P, xc, nullptr, nullptr, x, nullptr, 0, 0,
+                        s);
+  if (H.nu_post > 0) x = smooth<T>(c, L, v, v.b, x, other, H.nu_post, false);
+  return x;
+}
+
+}  // namespace
+
+// z (3n fp64 or level-0 rows) = one V-cycle applied to r (device fp64, rows of level 0)
+void vcycle_apply(hfsi_ctx* c, const double* r, double* z) {
+  Hierarchy& H = c->H;
+  if (!H.ready) fail(HFSI_E_ORDER, "vcycle: no AMG hierarchy");
+  Level& L0 = H.L[0];
+  const int n = L0.n;
+  hipStream_t s = c->stream;
+  if (H.precision == 0) {
+    HIP_CHECK(hipMemcpyAsync(L0.b.p, r, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    double* x = vcycle_rec<double>(c, 0);
+    HIP_CHECK(hipMemcpyAsync(z, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  } else {
+    k_cast<double, float><<<div_up(n, 256), 256, 0, s>>>(n, r, L0.bf.p);
+    HIP_LAUNCH_CHECK();
+    float* x = vcycle_rec<float>(c, 0);
+    k_cast<float, double><<<div_up(n, 256), 256, 0, s>>>(n, x, z);
+    HIP_LAUNCH_CHECK();
+  }
+}
+
+void precond_apply(hfsi_ctx* c, const double* r, double* z) {
+  Hierarchy& H = c->H;
+  if (!H.ready) fail(HFSI_E_ORDER, "preconditioner: no AMG hierarchy");
+  Level& L0 = H.L[0];
+  const int n = c->n;
+  if (L0.n != 3 * n) fail(HFSI_E_ORDER, "preconditioner: hierarchy was not built on the assembled A");
+  hipStream_t s = c->stream;
+  const int grid16 = div_up((long)n * 16, 256);
+  if (H.precision == 0) {
+    k_split_u<double><<<div_up(3 * n, 256), 256, 0, s>>>(n, r, L0.b.p);
+    HIP_LAUNCH_CHECK();
+    double* zu = vcycle_rec<double>(c, 0);
+    k_pl_combine<double><<<grid16, 256, 0, s>>>(n, c->nptr.p, c->ncol.p, c->Kval.p, zu, r, c->schur.p, z);
+  } else {
+    k_split_u<float><<<div_up(3 * n, 256), 256, 0, s>>>(n, r, L0.bf.p);
+    HIP_LAUNCH_CHECK();
+    float* zu = vcycle_rec<float>(c, 0);
+    k_pl_combine<float><<<grid16, 256, 0, s>>>(n, c->nptr.p, c->ncol.p, c->Kval.p, zu, r, c->schur.p, z);
+  }
+  HIP_LAUNCH_CHECK();
+}
+
+void tangent_apply(hfsi_ctx* c, const double* x, double* y) {
+  k_bsr4<OP_SPMV><<<div_up((long)c->n * 16, 256), 256, 0, c->stream>>>(c->n, c->nptr.p, c->ncol.p, c->Kval.p, x,
+                                                                         nullptr, y);
+  HIP_LAUNCH_CHECK();
+}
+
+namespace {
+
+void residual(hfsi_ctx* c, const double* b, const double* x, double* r) {
+  k_bsr4<OP_RESID><<<div_up((long)c->n * 16, 256), 256, 0, c->stream>>>(c->n, c->nptr.p, c->ncol.p, c->Kval.p, x, b,
+                                                                          r);
+  HIP_LAUNCH_CHECK();
+}
+
+// ||x|| into the device scalar *out (no synchronisation)
+void norm_dev(hfsi_ctx* c, const double* x, long N, double* out) {
+  k_norm_partial<<<RED_BLOCKS, 256, 0, c->stream>>>(N, x, c->kred.p);
+  HIP_LAUNCH_CHECK();
+  k_norm_final<<<1, 256, 0, c->stream>>>(RED_BLOCKS, c->kred.p, out);
+  HIP_LAUNCH_CHECK();
+}
+
+double read_scalar(hfsi_ctx* c, const double* dev) {
+  HIP_CHECK(hipMemcpyAsync(c->pinned, dev, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_CHECK(hipStreamSynchronize(c->stream));
+  return c->pinned[0];
+}
+
+// h[0..k) = V[0..k)^T w  (device)
+void mdot(hfsi_ctx* c, long N, int k, const double* V, const double* w, double* h, int accumulate) {
+  dim3 grid(RED_BLOCKS, div_up(k, 8));
+  k_mdot<<<grid, 256, 0, c->stream>>>(N, k, V, N, w, c->kred.p + 2 * RED_BLOCKS);
+  HIP_LAUNCH_CHECK();
+  k_reduce_rows<<<k, 256, 0, c->stream>>>(k, RED_BLOCKS, c->kred.p + 2 * RED_BLOCKS, h, accumulate);
+  HIP_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_params& prm, hfsi_solve_info* info) {
+  const long N = 4L * c->n;
+  const int m = prm.restart;
+  hipStream_t s = c->stream;
+  c->kv.ensure((size_t)(m + 1) * N);
+  c->kz.ensure((size_t)m * N);
+  c->kw.ensure(N);
+  c->kr.ensure(N);
+  KState st{m};
+  c->kh.ensure(st.size() + 256);
+  c->kred.ensure(2 * RED_BLOCKS + (size_t)RED_BLOCKS * (m + 8));
+  c->scal.ensure(16);
+  double* sc = c->scal.p;  // 0 bnorm, 1 beta, 2 w0, 3 hnorm, 4-5 report
+  double* hbuf = c->kh.p + st.size();  // h and h2 (2 x 64)
+  HIP_CHECK(hipEventRecord(c->ev0, s));
+  norm_dev(c, b, N, sc + 0);
+  const double bnorm = read_scalar(c, sc + 0);
+  int its = 0, restarts = 0;
+  bool converged = false, breakdown = false;
+  double rel = 0.0;
+  if (bnorm == 0.0) {
+    HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * N, s));
+    converged = true;
+  } else {
+    residual(c, b, x, c->kr.p);
+    norm_dev(c, c->kr.p, N, sc + 1);
+    double beta = read_scalar(c, sc + 1);
+    rel = beta / bnorm;
+    converged = beta <= prm.tol * bnorm;
+    const int gN = div_up(N, 256);
+    while (!converged && its < prm.max_iter) {
+      double* V = c->kv.p;
+      double* Z = c->kz.p;
+      k_div_scalar<<<gN, 256, 0, s>>>(N, c->kr.p, sc + 1, V);
+      HIP_LAUNCH_CHECK();
+      k_kinit<<<1, 1, 0, s>>>(c->kh.p, m, sc + 1);
+      HIP_LAUNCH_CHECK();
+      int jend = 0;
+      for (int j = 0; j < m; ++j) {
+        double* vj = V + (long)j * N;
+        double* zj = Z + (long)j * N;
+        precond_apply(c, vj, zj);
+        tangent_apply(c, zj, c->kw.p);
+        norm_dev(c, c->kw.p, N, sc + 2);
+        // CGS2
+        mdot(c, N, j + 1, V, c->kw.p, hbuf, 0);
+        k_vupdate<<<gN, 256, 0, s>>>(N, j + 1, V, N, hbuf, -1.0, c->kw.p);
+        HIP_LAUNCH_CHECK();
+        mdot(c, N, j + 1, V, c->kw.p, hbuf + 64, 0);
+        k_vupdate<<<gN, 256, 0, s>>>(N, j + 1, V, N, hbuf + 64, -1.0, c->kw.p);
+        HIP_LAUNCH_CHECK();
+        k_reduce_rows<<<j + 1, 256, 0, s>>>(j + 1, 1, hbuf + 64, hbuf, 1);  // h += h2
+        HIP_LAUNCH_CHECK();
+        k_store_col<<<1, 64, 0, s>>>(c->kh.p, m, j, hbuf);
+        HIP_LAUNCH_CHECK();
+        norm_dev(c, c->kw.p, N, sc + 3);
+        k_givens<<<1, 1, 0, s>>>(c->kh.p, m, j, sc + 3, sc + 4);
+        HIP_LAUNCH_CHECK();
+        HIP_CHECK(hipMemcpyAsync(c->pinned, sc + 2, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        const double w0 = c->pinned[0], gabs = c->pinned[2], hj1 = c->pinned[3];
+        ++its;
+        jend = j + 1;
+        if (!std::isfinite(gabs)) fail(HFSI_E_NAN, "FGMRES: non-finite residual estimate");
+        if (gabs <= prm.tol * bnorm || its >= prm.max_iter) break;
+        if (hj1 <= 1e-14 * w0) {
+          breakdown = true;
+          break;
+        }
+        k_div_scalar<<<gN, 256, 0, s>>>(N, c->kw.p, sc + 3, V + (long)(j + 1) * N);
+        HIP_LAUNCH_CHECK();
+      }
+      k_backsolve<<<1, 1, 0, s>>>(c->kh.p, m, jend);
+      HIP_LAUNCH_CHECK();
+      k_vupdate<<<gN, 256, 0, s>>>(N, jend, Z, N, c->kh.p + st.y(), 1.0, x);
+      HIP_LAUNCH_CHECK();
+      residual(c, b, x, c->kr.p);
+      norm_dev(c, c->kr.p, N, sc + 1);
+      beta = read_scalar(c, sc + 1);
+      rel = beta / bnorm;
+      if (!std::isfinite(beta)) fail(HFSI_E_NAN, "FGMRES: non-finite residual");
+      if (beta <= prm.tol * bnorm) {
+        converged = true;
+        break;
+      }
+      if (breakdown) break;
+      ++restarts;
+    }
+  }
+  HIP_CHECK(hipEventRecord(c->ev1, s));
+  if (info) {
+    info->iterations = its;
+    info->restarts = restarts;
+    info->rel_residual = rel;
+    info->converged = converged ? 1 : 0;
+    info->breakdown = breakdown ? 1 : 0;
+    info->seconds = elapsed_ms(c) * 1e-3;
+  }
+  if (breakdown && !converged) fail(HFSI_E_BREAKDOWN, "FGMRES breakdown before convergence");
+}
+
+}  // namespace hfsi
+
+namespace {
+void check_solve_params(const hfsi_solve_params* p) {
+  if (!p || p->struct_size != sizeof(hfsi_solve_params)) fail(HFSI_E_ARG, "solve params: struct_size mismatch");
+  if (!(p->tol > 0) || p->restart < 1 || p->restart > 60 || p->max_iter < 1)
+    fail(HFSI_E_ARG, "solve params: need tol > 0, 1 <= restart <= 60, max_iter >= 1");
+}
+}  // namespace
+
+extern "C" hfsi_status hfsi_vcycle(hfsi_ctx* c, const double* r, double* z) {
+  HFSI_ABI_BEGIN(c)
+  if (!r || !z) fail(HFSI_E_ARG, "vcycle: null vector");
+  hfsi::vcycle_apply(c, r, z);
+  HIP_CHECK(hipStreamSynchronize(c->stream));
+  HFSI_ABI_END(c)
+}
+
+extern "C" hfsi_status hfsi_apply_preconditioner(hfsi_ctx* c, const double* r, double* y) {
+  HFSI_ABI_BEGIN(c)
+  require_stage(c, 4, "apply_preconditioner");
+  if (!r || !y) fail(HFSI_E_ARG, "apply_preconditioner: null vector");
+  hfsi::precond_apply(c, r, y);
+  HIP_CHECK(hipStreamSynchronize(c->stream));
+  HFSI_ABI_END(c)
+}
+
+extern "C" hfsi_status hfsi_apply_tangent(hfsi_ctx* c, const double* x, double* y) {
+  HFSI_ABI_BEGIN(c)
+  require_stage(c, 4, "apply_tangent");
+  if (!x || !y) fail(HFSI_E_ARG, "apply_tangent: null vector");
+  hfsi::tangent_apply(c, x, y);
+  HIP_CHECK(hipStreamSynchronize(c->stream));
+  HFSI_ABI_END(c)
+}
+
+extern "C" hfsi_status hfsi_krylov_amg_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_params* prm,
+                                             hfsi_solve_info* info) {
+  HFSI_ABI_BEGIN(c)
+  require_stage(c, 4, "krylov_amg_solve");
+  check_solve_params(prm);
+  if (!b || !x) fail(HFSI_E_ARG, "krylov_amg_solve: null vector");
+  if (info && info->struct_size != sizeof(hfsi_solve_info)) fail(HFSI_E_ARG, "solve info: struct_size mismatch");
+  hfsi_solve_info tmp{sizeof(hfsi_solve_info)};
+  hfsi_solve_info* inf = info ? info : &tmp;
+  hfsi::fgmres_solve(c, b, x, *prm, inf);
+  if (!inf->converged) return HFSI_NOT_CONVERGED;
+  HFSI_ABI_END(c)
+}
+
+namespace {
+__global__ void k_negate(long N, const double* __restrict__ x, double* __restrict__ y) {
+  long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < N) y[i] = -x[i];
+}
+}  // namespace
+
+extern "C" hfsi_status hfsi_newton_step(hfsi_ctx* c, double* v, double load, const hfsi_newton_params* prm,
+                                        hfsi_newton_info* info) {
+  HFSI_ABI_BEGIN(c)
+  require_stage(c, 3, "newton_step");
+  if (!v) fail(HFSI_E_ARG, "newton_step: null state");
+  if (!prm || prm->struct_size != sizeof(hfsi_newton_params)) fail(HFSI_E_ARG, "newton params: struct_size mismatch");
+  if (info && info->struct_size != sizeof(hfsi_newton_info)) fail(HFSI_E_ARG, "newton info: struct_size mismatch");
+  hfsi::check_amg_params(&prm->amg);
+  check_solve_params(&prm->solve);
+  const long N = 4L * c->n;
+  hipStream_t s = c->stream;
+  c->kdv.ensure(N);
+  c->ktmp.ensure(N);
+  hipEvent_t t0, t1;
+  HIP_CHECK(hipEventCreate(&t0));
+  HIP_CHECK(hipEventCreate(&t1));
+  HIP_CHECK(hipEventRecord(t0, s));
+  hfsi_assembly_info ai{sizeof(hfsi_assembly_info)};
+  hfsi::assemble(c, v, load, c->ktmp.p, &ai);
+  c->stage = 4;
+  c->scal.ensure(16);
+  c->kred.ensure(2 * RED_BLOCKS);
+  hfsi::norm_dev(c, c->ktmp.p, N, c->scal.p + 6);
+  const double rnorm = hfsi::read_scalar(c, c->scal.p + 6);
+  if (!std::isfinite(rnorm)) fail(HFSI_E_NAN, "newton_step: non-finite residual");
+  hfsi_amg_info mi{sizeof(hfsi_amg_info)};
+  hfsi::amg_setup_level0(c, prm->amg, &mi);
+  // b = -R, dv = 0
+  k_negate<<<div_up(N, 256), 256, 0, s>>>(N, c->ktmp.p, c->ktmp.p);
+  HIP_LAUNCH_CHECK();
+  HIP_CHECK(hipMemsetAsync(c->kdv.p, 0, sizeof(double) * N, s));
+  hfsi_solve_info si{sizeof(hfsi_solve_info)};
+  hfsi::fgmres_solve(c, c->ktmp.p, c->kdv.p, prm->solve, &si);
+  k_axpy<<<div_up(N, 256), 256, 0, s>>>(N, 1.0, c->kdv.p, v);
+  HIP_LAUNCH_CHECK();
+  const double dvm = hfsi::mass_norm(c, c->kdv.p);
+  HIP_CHECK(hipEventRecord(t1, s));
+  HIP_CHECK(hipEventSynchronize(t1));
+  float ms = 0.f;
+  HIP_CHECK(hipEventElapsedTime(&ms, t0, t1));
+  HIP_CHECK(hipEventDestroy(t0));
+  HIP_CHECK(hipEventDestroy(t1));
+  if (!std::isfinite(dvm)) fail(HFSI_E_NAN, "newton_step: non-finite update");
+  if (info) {
+    info->dv_mass_norm = dvm;
+    info->residual_norm = rnorm;
+    info->krylov_iterations = si.iterations;
+    info->rel_residual = si.rel_residual;
+    info->t_assemble = ai.seconds;
+    info->t_setup = mi.seconds;
+    info->t_solve = si.seconds;
+    info->t_total = ms * 1e-3;
+    info->amg_levels = mi.levels;
+  }
+  if (!si.converged) return HFSI_NOT_CONVERGED;
+  HFSI_ABI_END(c)
+}
