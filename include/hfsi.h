@@ -251,6 +251,21 @@ hfsi_status hfsi_export_tangent(hfsi_ctx* ctx, int32_t* block_ptr, int32_t* bloc
 /* ||dv||_M for a device vector dv [N]. */
 hfsi_status hfsi_mass_norm(hfsi_ctx* ctx, const double* dv, double* out);
 
+/* ------------------------------------------------------------ measurement */
+
+/* Launch one hot-path kernel `reps` times back to back on the context stream,
+ * bracketed by HIP events, and report the average duration of one launch in
+ * *avg_ms and the algorithmic bytes one launch must move in *bytes (the
+ * minimum traffic of its inputs and outputs).  kernel:
+ *   0 = level-0 smoother sweep (hierarchy precision), 1 = level-0 residual,
+ *   2 = tangent SpMV y = K x (fp64 4x4 blocks), 3 = element assembly
+ *   (all colours), 9 = plain device copy of `bytes_hint` bytes (counter
+ *   calibration).  Needs the state the kernel reads (assembled K, hierarchy).
+ * Work buffers are context-owned; results are discarded, except that kernel
+ * 3 leaves the zero-state tangent in the context (assemble again after it). */
+hfsi_status hfsi_time_kernel(hfsi_ctx* ctx, int32_t kernel, int32_t reps, int64_t bytes_hint, double* avg_ms,
+                             double* bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -459,6 +459,36 @@ void assemble(hfsi_ctx* c, const double* v, double load, double* R, hfsi_assembl
   }
 }
 
+// Per element: gradients (96 B), volume and size (16 B), connectivity (16 B),
+// material id (4 B), fibres (48 B, anisotropic meshes); per node the state
+// (32 B); the tangent values (8 B per scalar entry) and the residual (8 B per
+// dof) written once.
+double assembly_bytes(hfsi_ctx* c) {
+  const double per_elem = 96.0 + 16.0 + 16.0 + 4.0 + (c->has_fib ? 48.0 : 0.0);
+  return c->m * per_elem + c->n * 32.0 + 16.0 * c->nb * 8.0 + 4.0 * c->n * 8.0;
+}
+
+// The colour launches of one assembly at the zero state (timing only).
+void assemble_kernels_only(hfsi_ctx* c) {
+  hipStream_t s = c->stream;
+  const long N = 4L * c->n;
+  c->kdv.ensure(N);
+  c->ktmp.ensure(N);
+  c->iscal.ensure(16);
+  c->scal.ensure(16);
+  HIP_CHECK(hipMemsetAsync(c->kdv.p, 0, sizeof(double) * N, s));
+  HIP_CHECK(hipMemsetAsync(c->ktmp.p, 0, sizeof(double) * N, s));
+  HIP_CHECK(hipMemsetAsync(c->Kval.p, 0, sizeof(double) * 16 * (size_t)c->nb, s));
+  for (size_t q = 0; q + 1 < c->colour_ptr.size(); ++q) {
+    int e0 = c->colour_ptr[q], e1 = c->colour_ptr[q + 1];
+    k_element<<<div_up(e1 - e0, 128), 128, 0, s>>>(e0, e1, c->m, c->tets.p, c->mat.p, c->mtab.p, c->G.p, c->V.p,
+                                                   c->h.p, c->has_fib ? c->fib.p : nullptr, c->slot.p, c->kdv.p,
+                                                   c->ktmp.p, c->Kval.p, 1, (unsigned long long*)c->scal.p,
+                                                   c->iscal.p);
+    HIP_LAUNCH_CHECK();
+  }
+}
+
 double mass_norm(hfsi_ctx* c, const double* dv) {
   const int nb = 256;
   c->kred.ensure(2 * nb);

@@ -214,6 +214,9 @@ void tangent_apply(hfsi_ctx* c, const double* x, double* y);
 void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_params& prm,
                   hfsi_solve_info* info);
 double mass_norm(hfsi_ctx* c, const double* dv);
+// minimum bytes one assembly must move; the element kernels alone (timing)
+double assembly_bytes(hfsi_ctx* c);
+void assemble_kernels_only(hfsi_ctx* c);
 
 }  // namespace hfsi
 

@@ -12,6 +12,7 @@
 //    recomputed after every cycle.
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <type_traits>
 
 #include "common.hpp"
@@ -669,6 +670,92 @@ __global__ void k_negate(long N, const double* __restrict__ x, double* __restric
   if (i < N) y[i] = -x[i];
 }
 }  // namespace
+
+namespace {
+__global__ void k_copy4(long n4, const float4* __restrict__ x, float4* __restrict__ y) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (long)gridDim.x * blockDim.x) y[i] = x[i];
+}
+}  // namespace
+
+extern "C" hfsi_status hfsi_time_kernel(hfsi_ctx* c, int32_t kernel, int32_t reps, int64_t bytes_hint, double* avg_ms,
+                                        double* bytes) {
+  HFSI_ABI_BEGIN(c)
+  if (reps < 1 || !avg_ms || !bytes) fail(HFSI_E_ARG, "time_kernel: bad arguments");
+  hipStream_t s = c->stream;
+  hfsi::Hierarchy& H = c->H;
+  std::function<void()> launch;
+  double b = 0.0;
+  hfsi::DevBuf<char> tmp;
+  if (kernel == 0 || kernel == 1) {
+    if (!H.ready) fail(HFSI_E_ORDER, "time_kernel: no hierarchy");
+    hfsi::Level& L = H.L[0];
+    const int n = L.n;
+    const int G = lanes_for(L.A.nnz, n);
+    const double ts = H.precision == 1 ? 4.0 : 8.0;
+    const double nnz = (double)L.A.nnz;
+    if (kernel == 0) {
+      // val + col per entry; ptr, x_i, b, dinv read and y written per row
+      b = nnz * (ts + 4.0) + n * (4.0 + 4.0 * ts);
+      if (H.smoother == 1) b += n * 2.0 * ts;  // Chebyshev direction read + write
+    } else {
+      b = nnz * (ts + 4.0) + n * (4.0 + 2.0 * ts);
+    }
+    launch = [&, n, G, kernel]() {
+      if (H.precision == 0) {
+        if (kernel == 1)
+          csr_launch<double, OP_RESID>(G, n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.x.p, L.b.p, nullptr, L.r.p, nullptr,
+                                       0, 0, s);
+        else if (H.smoother == 0)
+          csr_launch<double, OP_JACOBI>(G, n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.x.p, L.b.p, L.dinv.p, L.t.p,
+                                        nullptr, 0, 0, s);
+        else
+          csr_launch<double, OP_CHEB>(G, n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.x.p, L.b.p, L.dinv.p, L.t.p, L.r.p,
+                                      0.5, 0.5, s);
+      } else {
+        if (kernel == 1)
+          csr_launch<float, OP_RESID>(G, n, L.A.ptr.p, L.A.col.p, L.A32.p, L.xf.p, L.bf.p, nullptr, L.rf.p, nullptr,
+                                      0, 0, s);
+        else if (H.smoother == 0)
+          csr_launch<float, OP_JACOBI>(G, n, L.A.ptr.p, L.A.col.p, L.A32.p, L.xf.p, L.bf.p, L.dinv32.p, L.tf.p,
+                                       nullptr, 0, 0, s);
+        else
+          csr_launch<float, OP_CHEB>(G, n, L.A.ptr.p, L.A.col.p, L.A32.p, L.xf.p, L.bf.p, L.dinv32.p, L.tf.p, L.rf.p,
+                                     0.5f, 0.5f, s);
+      }
+    };
+  } else if (kernel == 2) {
+    require_stage(c, 4, "time_kernel");
+    const long N = 4L * c->n;
+    c->kw.ensure(N);
+    c->kr.ensure(N);
+    HIP_CHECK(hipMemsetAsync(c->kw.p, 0, sizeof(double) * N, s));
+    b = (double)c->nb * (128.0 + 4.0) + (double)c->n * (4.0 + 32.0 + 32.0);
+    launch = [&]() { tangent_apply(c, c->kw.p, c->kr.p); };
+  } else if (kernel == 3) {
+    require_stage(c, 4, "time_kernel");
+    b = hfsi::assembly_bytes(c);
+    launch = [&]() { hfsi::assemble_kernels_only(c); };
+  } else if (kernel == 9) {
+    if (bytes_hint < 16) fail(HFSI_E_ARG, "time_kernel: copy needs bytes_hint >= 16");
+    const long n4 = bytes_hint / 16;
+    tmp.ensure(2 * n4 * 16);
+    HIP_CHECK(hipMemsetAsync(tmp.p, 0, 2 * n4 * 16, s));
+    b = 2.0 * n4 * 16;
+    launch = [&, n4]() {
+      k_copy4<<<2048, 256, 0, s>>>(n4, (const float4*)tmp.p, (float4*)(tmp.p + n4 * 16));
+      HIP_LAUNCH_CHECK();
+    };
+  } else {
+    fail(HFSI_E_ARG, "time_kernel: unknown kernel id");
+  }
+  launch();  // warm-up
+  HIP_CHECK(hipEventRecord(c->ev0, s));
+  for (int r = 0; r < reps; ++r) launch();
+  HIP_CHECK(hipEventRecord(c->ev1, s));
+  *avg_ms = hfsi::elapsed_ms(c) / reps;
+  *bytes = b;
+  HFSI_ABI_END(c)
+}
 
 extern "C" hfsi_status hfsi_newton_step(hfsi_ctx* c, double* v, double load, const hfsi_newton_params* prm,
                                         hfsi_newton_info* info) {

@@ -121,6 +121,7 @@ def load():
         "hfsi_apply_tangent": [vp, vp, vp],
         "hfsi_mass_norm": [vp, vp, C.POINTER(dbl)],
         "hfsi_export_tangent": [vp, vp, vp, vp, vp, vp, vp, vp],
+        "hfsi_time_kernel": [vp, i32, i32, i64, C.POINTER(dbl), C.POINTER(dbl)],
     }
     for name, args in sig.items():
         f = getattr(lib, name, None)
@@ -284,6 +285,12 @@ class Context:
         out = C.c_double()
         self._check(self.lib.hfsi_mass_norm(self.h, _ptr(dv), C.byref(out)))
         return out.value
+
+    def time_kernel(self, kernel, reps, bytes_hint=0):
+        """(average ms per launch, algorithmic bytes per launch) of a hot kernel."""
+        ms, nbytes = C.c_double(), C.c_double()
+        self._check(self.lib.hfsi_time_kernel(self.h, kernel, reps, bytes_hint, C.byref(ms), C.byref(nbytes)))
+        return ms.value, nbytes.value
 
     def export_tangent(self, view):
         """Host copies of the block matrix K, of A and of the Schur diagonal."""
