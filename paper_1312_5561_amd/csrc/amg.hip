@@ -174,28 +174,29 @@ __global__ void k_interp_fill(int n, const int* __restrict__ ptr, const int* __r
     if (strong[e] && state[k] == ST_C) {
       pval[find_in(pcol, p0, p1, k)] += a;
     } else if (strong[e]) {
+      // one merge of row k with the sorted C_i list: a_kk and the sums of the
+      // negative and the positive couplings to C_i (both in ascending order)
       const int klo = ptr[k], khi = ptr[k + 1];
-      double akk = 0.0;
-      for (int f = klo; f < khi; ++f)
-        if (col[f] == k) akk = val[f];
-      const double sk = akk < 0.0 ? -1.0 : 1.0;
-      double s = 0.0;
-      for (int f = klo; f < khi; ++f) {
+      double akk = 0.0, s_neg = 0.0, s_pos = 0.0;
+      for (int f = klo, b = p0; f < khi; ++f) {
         const int mm = col[f];
-        const int pos = find_in(pcol, p0, p1, mm);
-        if (pos < p1 && pcol[pos] == mm) {
+        if (mm == k) akk = val[f];
+        while (b < p1 && pcol[b] < mm) ++b;
+        if (b < p1 && pcol[b] == mm) {
           const double v = val[f];
-          s += (v * sk < 0.0) ? v : 0.0;
+          if (v < 0.0) s_neg += v;
+          else if (v > 0.0) s_pos += v;
         }
       }
+      const double sk = akk < 0.0 ? -1.0 : 1.0;
+      const double s = sk > 0.0 ? s_neg : s_pos;  // abar keeps the sign opposite to a_kk
       if (s != 0.0) {
-        for (int f = klo; f < khi; ++f) {
+        for (int f = klo, b = p0; f < khi; ++f) {
           const int mm = col[f];
-          const int pos = find_in(pcol, p0, p1, mm);
-          if (pos < p1 && pcol[pos] == mm) {
+          while (b < p1 && pcol[b] < mm) ++b;
+          if (b < p1 && pcol[b] == mm) {
             const double v = val[f];
-            const double ab = (v * sk < 0.0) ? v : 0.0;
-            pval[pos] += a * ab / s;
+            if (v * sk < 0.0) pval[b] += a * v / s;
           }
         }
       } else {
@@ -282,7 +283,11 @@ k_spgemm(int n, const int* __restrict__ ap, const int* __restrict__ ac, const do
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
     const int s = sel[i];
     if (s < sel_lo || s > sel_hi) continue;
-    for (int t = lane; t < TBL; t += 64) {
+    // table of T = pow2 >= 2 s slots (s = upper bound or exact count of the row)
+    int T = 64;
+    while (T < 2 * s && T < TBL) T <<= 1;
+    const int mask = T - 1;
+    for (int t = lane; t < T; t += 64) {
       keys[t] = -1;
       if (NUMERIC) vals[t] = 0.0;
     }
@@ -294,7 +299,7 @@ k_spgemm(int n, const int* __restrict__ ap, const int* __restrict__ ac, const do
       const double a = NUMERIC ? av[e] : 0.0;
       for (int q = bp[k] + lane; q < bp[k + 1]; q += 64) {
         const int j = bc[q];
-        unsigned h = hslot(j, TBL - 1);
+        unsigned h = hslot(j, mask);
         int probes = 0;
         while (true) {
           const int old = atomicCAS(&keys[h], -1, j);
@@ -303,8 +308,8 @@ k_spgemm(int n, const int* __restrict__ ap, const int* __restrict__ ac, const do
             break;
           }
           if (old == j) break;
-          h = (h + 1) & (TBL - 1);
-          if (++probes >= TBL) { bad = true; break; }
+          h = (h + 1) & mask;
+          if (++probes >= T) { bad = true; break; }
         }
         if (NUMERIC && !bad) vals[h] += a * bv[q];
       }
@@ -323,7 +328,7 @@ k_spgemm(int n, const int* __restrict__ ap, const int* __restrict__ ac, const do
     // compact the keys, then place every entry by its rank
     if (lane == 0) ninsert = 0;
     __syncthreads();
-    for (int t = lane; t < TBL; t += 64) {
+    for (int t = lane; t < T; t += 64) {
       const int key = keys[t];
       if (key >= 0) {
         const int pos = atomicAdd(&ninsert, 1);
@@ -338,7 +343,7 @@ k_spgemm(int n, const int* __restrict__ ap, const int* __restrict__ ac, const do
       __syncthreads();
       continue;
     }
-    for (int t = lane; t < TBL; t += 64) {
+    for (int t = lane; t < T; t += 64) {
       const int key = keys[t];
       if (key < 0) continue;
       int r = 0;
@@ -431,13 +436,12 @@ __global__ void __launch_bounds__(1024) k_gauss_jordan(int n, double* __restrict
     for (int j = t; j < w; j += nt) M[(size_t)k * w + j] *= ip;
     __syncthreads();
     // eliminate column k from every other row
-    for (long q = t; q < (long)n * (w - k); q += nt) {
-      const int r = (int)(q / (w - k));
-      const int j = k + (int)(q % (w - k));
+    // (32 rows x 32 columns of threads; columns of row k are read coalesced)
+    for (int r = t >> 5; r < n; r += nt >> 5) {
       if (r == k) continue;
       const double f = M[(size_t)r * w + k];
-      if (j == k) continue;
-      M[(size_t)r * w + j] -= f * M[(size_t)k * w + j];
+      if (f == 0.0) continue;
+      for (int j = k + 1 + (t & 31); j < w; j += 32) M[(size_t)r * w + j] -= f * M[(size_t)k * w + j];
     }
     __syncthreads();
     for (int r = t; r < n; r += nt)
@@ -459,18 +463,27 @@ __global__ void k_lanczos_init(int n, uint64_t seed, int stream, double* __restr
 }
 
 // w = Dm A (Dm q) - beta q_prev, with Dm = |diag|^{-1/2}
+// 16 lanes per row; dm = |diag A|^{-1/2}
 __global__ void k_lanczos_apply(int n, const int* __restrict__ ptr, const int* __restrict__ col,
-                                const double* __restrict__ val, const double* __restrict__ dinv,
+                                const double* __restrict__ val, const double* __restrict__ dm,
                                 const double* __restrict__ q, const double* __restrict__ qp, double beta,
                                 double* __restrict__ w) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int lane = threadIdx.x & 15;
   if (i >= n) return;
   double s = 0.0;
-  for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
+  for (int e = ptr[i] + lane; e < ptr[i + 1]; e += 16) {
     const int j = col[e];
-    s += val[e] * sqrt(fabs(dinv[j])) * q[j];
+    s += val[e] * (dm[j] * q[j]);
   }
-  w[i] = sqrt(fabs(dinv[i])) * s - beta * qp[i];
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
+  if (lane == 0) w[i] = dm[i] * s - beta * qp[i];
+}
+
+__global__ void k_rsqrt_abs(int n, const double* __restrict__ dinv, double* __restrict__ dm) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dm[i] = sqrt(fabs(dinv[i]));
 }
 
 __global__ void k_dot_partial(int n, const double* __restrict__ x, const double* __restrict__ y,
@@ -557,8 +570,11 @@ double lanczos_max(hfsi_ctx* c, Level& L, int steps, uint64_t seed, int level) {
   dabs.ensure(n); dummy.ensure(n);
   k_inv_diag<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, dabs.p, dummy.p);
   HIP_LAUNCH_CHECK();
+  k_rsqrt_abs<<<div_up(n, 256), 256, 0, s>>>(n, dabs.p, dabs.p);  // dabs <- |diag|^{-1/2}
+  HIP_LAUNCH_CHECK();
   for (int it = 0; it < std::min(steps, n); ++it) {
-    k_lanczos_apply<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, dabs.p, q.p, qp.p, b, w.p);
+    k_lanczos_apply<<<div_up((long)n * 16, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, dabs.p, q.p, qp.p,
+                                                               b, w.p);
     HIP_LAUNCH_CHECK();
     const double a = dot_dev(c, q.p, w.p, n);
     k_axpy_inplace<<<div_up(n, 256), 256, 0, s>>>(n, -a, q.p, w.p);

@@ -376,6 +376,14 @@ __global__ void k_gather(int nnz, const int* __restrict__ src, const double* __r
   if (t < nnz) val[t] = Kval[src[t]];
 }
 
+// compact copy of B2: the pressure row, displacement columns, of every block
+__global__ void k_extract_b2(int nb, const double* __restrict__ Kval, double* __restrict__ b2) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * nb) return;
+  const int q = t / 3, c = t - 3 * q;
+  b2[t] = Kval[16 * (size_t)q + 12 + c];
+}
+
 // mass norm partials: sum over blocks (i,j) of M_ij sum_c dv_ic dv_jc
 __global__ void k_massnorm(int nb, const int* __restrict__ brow, const int* __restrict__ bcol,
                            const double* __restrict__ M, const double* __restrict__ dv, double* __restrict__ part) {
@@ -443,6 +451,9 @@ void assemble(hfsi_ctx* c, const double* v, double load, double* R, hfsi_assembl
   k_dirichlet_K<<<div_up(16 * (long)c->nb, 256), 256, 0, s>>>(c->nb, c->brow.p, c->ncol.p, c->dir.p, c->Kval.p);
   HIP_LAUNCH_CHECK();
   k_gather<<<div_up(c->A.nnz, 256), 256, 0, s>>>((int)c->A.nnz, c->a_src.p, c->Kval.p, c->A.val.p);
+  HIP_LAUNCH_CHECK();
+  c->b2.ensure(3 * (size_t)c->nb);
+  k_extract_b2<<<div_up(3L * c->nb, 256), 256, 0, s>>>(c->nb, c->Kval.p, c->b2.p);
   HIP_LAUNCH_CHECK();
   HIP_CHECK(hipEventRecord(c->ev1, s));
   int inv = 0;

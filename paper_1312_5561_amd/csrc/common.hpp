@@ -159,6 +159,7 @@ struct hfsi_ctx {
   hfsi::DevBuf<int> brow;        // [nb] block row of each block
   hfsi::DevBuf<double> Kval;     // [16*nb]
   hfsi::DevBuf<double> Mval;     // [nb] scalar P1 mass on the node pattern
+  hfsi::DevBuf<double> b2;       // [3*nb] pressure row (B2 part) of every block
   // materials
   int n_mat = 0;
   hfsi::DevBuf<double> mtab;     // [n_mat * 8]: model,c10,c01,kappa,k1,k2,mu_l,theta

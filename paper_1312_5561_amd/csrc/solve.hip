@@ -140,7 +140,7 @@ __global__ void k_split_u(int n, const double* __restrict__ r, T* __restrict__ b
 // z_p = (B2 z_u - r_p) / s, z_u copied into the node-interleaved output
 template <class T>
 __global__ void __launch_bounds__(256)
-k_pl_combine(int n, const int* __restrict__ bptr, const int* __restrict__ bcol, const double* __restrict__ bval,
+k_pl_combine(int n, const int* __restrict__ bptr, const int* __restrict__ bcol, const double* __restrict__ b2,
              const T* __restrict__ zu, const double* __restrict__ r, const double* __restrict__ schur,
              double* __restrict__ z) {
   const int gid = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
@@ -149,7 +149,7 @@ k_pl_combine(int n, const int* __restrict__ bptr, const int* __restrict__ bcol, 
   double s = 0.0;
   for (int q = bptr[gid] + lane; q < bptr[gid + 1]; q += 16) {
     const int j = bcol[q];
-    const double* blk = bval + 16 * (size_t)q + 12;
+    const double* blk = b2 + 3 * (size_t)q;
     s += blk[0] * (double)zu[3 * j] + blk[1] * (double)zu[3 * j + 1] + blk[2] * (double)zu[3 * j + 2];
   }
 #pragma unroll
@@ -464,12 +464,12 @@ void precond_apply(hfsi_ctx* c, const double* r, double* z) {
     k_split_u<double><<<div_up(3 * n, 256), 256, 0, s>>>(n, r, L0.b.p);
     HIP_LAUNCH_CHECK();
     double* zu = vcycle_rec<double>(c, 0);
-    k_pl_combine<double><<<grid16, 256, 0, s>>>(n, c->nptr.p, c->ncol.p, c->Kval.p, zu, r, c->schur.p, z);
+    k_pl_combine<double><<<grid16, 256, 0, s>>>(n, c->nptr.p, c->ncol.p, c->b2.p, zu, r, c->schur.p, z);
   } else {
     k_split_u<float><<<div_up(3 * n, 256), 256, 0, s>>>(n, r, L0.bf.p);
     HIP_LAUNCH_CHECK();
     float* zu = vcycle_rec<float>(c, 0);
-    k_pl_combine<float><<<grid16, 256, 0, s>>>(n, c->nptr.p, c->ncol.p, c->Kval.p, zu, r, c->schur.p, z);
+    k_pl_combine<float><<<grid16, 256, 0, s>>>(n, c->nptr.p, c->ncol.p, c->b2.p, zu, r, c->schur.p, z);
   }
   HIP_LAUNCH_CHECK();
 }
