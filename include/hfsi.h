@@ -251,6 +251,74 @@ hfsi_status hfsi_export_tangent(hfsi_ctx* ctx, int32_t* block_ptr, int32_t* bloc
 /* ||dv||_M for a device vector dv [N]. */
 hfsi_status hfsi_mass_norm(hfsi_ctx* ctx, const double* dv, double* out);
 
+/* ------------------------------------------------ learned interpolation */
+
+/* The learned level-0 interpolation (no counterpart in the paper, whose AMG
+ * uses its own coarsening): a 64-64-64-27 network with ReLU, weights and
+ * activations in bfloat16 on MFMA with fp32 accumulation, adds a correction
+ * to the classical weights w_ij of the strong C points of every F point, by
+ * the slot of j in the 3x3x3 lattice box of node(i).  Inputs: the
+ * same-component couplings a_ij/a_ii in the box, the C flags, log10(kappa)/6,
+ * two material constants and the one-hot component.  With a zero last layer
+ * the result equals classical interpolation exactly.
+ *
+ * Parameters are one host fp32 array of HFSI_MLP_NPARAM values: W1 [64x64]
+ * (row = input), b1 [64], W2 [64x64], b2 [64], W3 [64x32] (columns 27..31
+ * unused), b3 [32].  The context keeps fp32 master weights, their bf16 copy
+ * and the Adam moments. */
+#define HFSI_MLP_NPARAM 10400
+
+typedef struct {
+  size_t struct_size;
+  int32_t batch;                 /* samples per Adam step                  */
+  double lr, beta1, beta2, eps;  /* Adam (Kingma & Ba 2015)                */
+} hfsi_train_params;
+
+typedef struct {
+  size_t struct_size;
+  int64_t samples;               /* training-set size                      */
+  double loss_first, loss_last;  /* masked MSE of the first / last batch   */
+  int32_t steps;
+  double seconds;
+} hfsi_train_info;
+
+hfsi_status hfsi_mlp_set_weights(hfsi_ctx* ctx, const float* w /* host [HFSI_MLP_NPARAM] */);
+hfsi_status hfsi_mlp_get_weights(hfsi_ctx* ctx, float* w /* host [HFSI_MLP_NPARAM] */);
+/* host m [HFSI_MLP_NPARAM] and v: Adam moments; *step: Adam steps taken */
+hfsi_status hfsi_mlp_adam_state(hfsi_ctx* ctx, float* m, float* v, int64_t* step);
+
+/* Network output for m host feature rows X [m][64] -> host out [m][32] (fp32);
+ * optional host copies of the bf16 input and hidden activations [m][64]. */
+hfsi_status hfsi_mlp_forward(hfsi_ctx* ctx, int32_t m, const float* X, float* out, uint16_t* x_bf16,
+                             uint16_t* h1_bf16, uint16_t* h2_bf16);
+
+/* Masked MSE loss sum(mask (wcl + out - wstar)^2) / sum(mask) of m host rows
+ * (mask, wcl, wstar [m][32]) and its gradient (host [HFSI_MLP_NPARAM]). */
+hfsi_status hfsi_mlp_loss_grad(hfsi_ctx* ctx, int32_t m, const float* X, const float* mask, const float* wcl,
+                               const float* wstar, float* grad, double* loss);
+
+/* Append the level-0 samples of the current classical hierarchy (needs
+ * lattice coordinates) to the context's training set: features, mask,
+ * classical weights and the local ideal-interpolation target.  *n_failed
+ * counts samples whose local system was singular or too large (target 0). */
+hfsi_status hfsi_mlp_collect(hfsi_ctx* ctx, int32_t* n_added, int32_t* n_failed);
+hfsi_status hfsi_mlp_clear(hfsi_ctx* ctx);
+/* Copy rows [first, first+count) of the training set to host arrays (any may
+ * be NULL); *total receives the set size. */
+hfsi_status hfsi_mlp_samples(hfsi_ctx* ctx, int64_t first, int64_t count, int64_t* total, float* X, float* mask,
+                             float* wcl, float* wstar);
+
+/* Adam training on the collected set: host order [n_order] lists the sample
+ * of every position (epochs x permutation, chosen by the caller); one step
+ * per `batch` consecutive positions. */
+hfsi_status hfsi_mlp_train(hfsi_ctx* ctx, const hfsi_train_params* prm, const int32_t* order, int64_t n_order,
+                           hfsi_train_info* info);
+
+/* Convergence factor of the current hierarchy: rho = (||e_k||_A/||e_0||_A)^(1/k)
+ * for k stationary V-cycles e <- e - V(A e) from the SplitMix64 vector of
+ * `seed` (stream 0, values in [-1,1)). */
+hfsi_status hfsi_amg_convergence_factor(hfsi_ctx* ctx, int32_t cycles, uint64_t seed, double* rho);
+
 /* ------------------------------------------------------------ measurement */
 
 /* Launch one hot-path kernel `reps` times back to back on the context stream,

@@ -774,6 +774,7 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
     k_interp_fill<<<div_up(n, 128), 128, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p, L.state.p, L.comp.p,
                                                  L.cidx.p, L.P.ptr.p, L.P.col.p, L.P.val.p);
     HIP_LAUNCH_CHECK();
+    if (l == 0 && prm.interp == 1) learned_correction(c, L);
     transpose(c, L.P, L.R);
     // Galerkin product
     Csr<double> AP;
@@ -822,6 +823,22 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
   HIP_CHECK(hipStreamSynchronize(s));
   if (sg) fail(HFSI_E_BREAKDOWN, "coarsest AMG operator is singular");
   H.ready = true;
+  double rho = -1.0;
+  if (prm.interp == 1) {
+    // judge: keep the learned interpolation only if the V-cycle converges fast
+    rho = convergence_factor(c, 10, 777);
+    if (!(rho <= prm.fallback_rho)) {
+      hfsi_amg_params cl = prm;
+      cl.interp = 0;
+      H.L.resize(1);
+      build_hierarchy(c, cl, info);
+      if (info) {
+        info->rho = rho;
+        info->learned_used = 0;
+      }
+      return;
+    }
+  }
   if (info) {
     info->levels = (int)H.L.size();
     double nnz0 = (double)H.L[0].A.nnz, rows0 = (double)H.L[0].n, sn = 0, sr = 0;
@@ -835,8 +852,8 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
     info->grid_complexity = sr / rows0;
     info->seconds = elapsed_ms(c) * 1e-3;
     info->pmis_rounds = rounds_total;
-    info->rho = -1.0;
-    info->learned_used = 0;
+    info->rho = rho;
+    info->learned_used = prm.interp == 1 ? 1 : 0;
   }
 }
 
@@ -860,6 +877,7 @@ void check_amg_params(const hfsi_amg_params* p) {
   if (p->smoother < 0 || p->smoother > 1 || p->nu_pre < 0 || p->nu_post < 0 || p->nu_pre + p->nu_post < 1)
     fail(HFSI_E_ARG, "amg params: bad smoother");
   if (p->precision < 0 || p->precision > 1) fail(HFSI_E_ARG, "amg params: bad precision");
+  if (p->interp < 0 || p->interp > 1) fail(HFSI_E_ARG, "amg params: interp must be 0 (classical) or 1 (learned)");
 }
 
 }  // namespace hfsi

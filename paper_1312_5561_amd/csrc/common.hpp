@@ -122,14 +122,6 @@ struct Hierarchy {
   bool ready = false;
 };
 
-// ----------------------------------------------------------- MLP weights
-struct MlpWeights {
-  bool loaded = false;
-  DevBuf<uint16_t> w_bf16;   // bf16 weights of the three layers (packed)
-  DevBuf<float> b_f32;       // biases
-  DevBuf<float> w_master;    // fp32 master weights for training
-};
-
 }  // namespace hfsi
 
 // ------------------------------------------------------------- the context
@@ -182,7 +174,7 @@ struct hfsi_ctx {
   double* pinned = nullptr;      // host-pinned scalars
   hfsi::DevBuf<double> scal;     // device scalars
   hfsi::DevBuf<int> iscal;       // device integer scalars
-  hfsi::MlpWeights mlp;
+  void* mlp_impl = nullptr;      // learned-interpolation state (mlp.hip)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
@@ -215,6 +207,12 @@ void tangent_apply(hfsi_ctx* c, const double* x, double* y);
 void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_params& prm,
                   hfsi_solve_info* info);
 double mass_norm(hfsi_ctx* c, const double* dv);
+// learned interpolation: correct level-0 P in place; free the state
+void learned_correction(hfsi_ctx* c, Level& L);
+void mlp_free(hfsi_ctx* c);
+// rho = (||e_k||_A / ||e_0||_A)^{1/k} of k stationary V-cycles from a
+// SplitMix64 start vector
+double convergence_factor(hfsi_ctx* c, int cycles, uint64_t seed);
 // minimum bytes one assembly must move; the element kernels alone (timing)
 double assembly_bytes(hfsi_ctx* c);
 void assemble_kernels_only(hfsi_ctx* c);

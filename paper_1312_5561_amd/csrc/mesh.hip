@@ -252,6 +252,7 @@ extern "C" hfsi_status hfsi_destroy(hfsi_ctx* c) {
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->pinned) (void)hipHostFree(c->pinned);
+  hfsi::mlp_free(c);
   delete c;
   return HFSI_OK;
 }

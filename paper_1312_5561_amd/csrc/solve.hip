@@ -624,6 +624,68 @@ void check_solve_params(const hfsi_solve_params* p) {
 }
 }  // namespace
 
+namespace {
+__global__ void k_uniform_pm1(int n, uint64_t seed, double* __restrict__ e) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t z = seed + ((uint64_t)i + 1) * 0x9E3779B97F4A7C15ull;  // SplitMix64 output i, stream 0
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  e[i] = 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+}
+
+__global__ void k_dot_part(int n, const double* __restrict__ x, const double* __restrict__ y, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double a = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) a += x[i] * y[i];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+}  // namespace
+
+namespace hfsi {
+double convergence_factor(hfsi_ctx* c, int cycles, uint64_t seed) {
+  Hierarchy& H = c->H;
+  if (!H.ready) fail(HFSI_E_ORDER, "convergence factor: no hierarchy");
+  Level& L = H.L[0];
+  const int n = L.n;
+  hipStream_t s = c->stream;
+  DevBuf<double> e, t, z, part;
+  e.ensure(n); t.ensure(n); z.ensure(n); part.ensure(256);
+  k_uniform_pm1<<<div_up(n, 256), 256, 0, s>>>(n, seed, e.p);
+  HIP_LAUNCH_CHECK();
+  const int G = lanes_for(L.A.nnz, n);
+  auto anorm2 = [&]() {
+    csr_launch<double, OP_SPMV>(G, n, L.A.ptr.p, L.A.col.p, L.A.val.p, e.p, nullptr, nullptr, t.p, nullptr, 0, 0, s);
+    k_dot_part<<<256, 256, 0, s>>>(n, e.p, t.p, part.p);
+    HIP_LAUNCH_CHECK();
+    return device_sum(c, part.p, 256);
+  };
+  const double n0 = anorm2();
+  for (int k = 0; k < cycles; ++k) {
+    csr_launch<double, OP_SPMV>(G, n, L.A.ptr.p, L.A.col.p, L.A.val.p, e.p, nullptr, nullptr, t.p, nullptr, 0, 0, s);
+    vcycle_apply(c, t.p, z.p);
+    k_axpy<<<div_up(n, 256), 256, 0, s>>>(n, -1.0, z.p, e.p);
+    HIP_LAUNCH_CHECK();
+  }
+  const double nk = anorm2();
+  return std::pow(std::sqrt(std::fabs(nk) / n0), 1.0 / cycles);
+}
+}  // namespace hfsi
+
+extern "C" hfsi_status hfsi_amg_convergence_factor(hfsi_ctx* c, int32_t cycles, uint64_t seed, double* rho) {
+  HFSI_ABI_BEGIN(c)
+  if (cycles < 1 || !rho) fail(HFSI_E_ARG, "convergence_factor: bad arguments");
+  *rho = hfsi::convergence_factor(c, cycles, seed);
+  HFSI_ABI_END(c)
+}
+
 extern "C" hfsi_status hfsi_vcycle(hfsi_ctx* c, const double* r, double* z) {
   HFSI_ABI_BEGIN(c)
   if (!r || !z) fail(HFSI_E_ARG, "vcycle: null vector");

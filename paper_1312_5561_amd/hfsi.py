@@ -78,6 +78,23 @@ class NewtonInfo(C.Structure):
                 ("amg_levels", C.c_int32)]
 
 
+class TrainParams(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("batch", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double)]
+
+
+class TrainInfo(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("samples", C.c_int64), ("loss_first", C.c_double),
+                ("loss_last", C.c_double), ("steps", C.c_int32), ("seconds", C.c_double)]
+
+
+MLP_NPARAM = 10400
+
+
+def train_params(batch=1024, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    return TrainParams(C.sizeof(TrainParams), batch, lr, beta1, beta2, eps)
+
+
 def amg_params(theta=0.5, max_coarse=500, max_levels=25, seed=12345, smoother=0, nu_pre=2, nu_post=2,
                precision=0, interp=0, fallback_rho=0.5):
     return AmgParams(C.sizeof(AmgParams), theta, max_coarse, max_levels, seed, smoother, nu_pre, nu_post,
@@ -122,6 +139,16 @@ def load():
         "hfsi_mass_norm": [vp, vp, C.POINTER(dbl)],
         "hfsi_export_tangent": [vp, vp, vp, vp, vp, vp, vp, vp],
         "hfsi_time_kernel": [vp, i32, i32, i64, C.POINTER(dbl), C.POINTER(dbl)],
+        "hfsi_mlp_set_weights": [vp, vp],
+        "hfsi_mlp_get_weights": [vp, vp],
+        "hfsi_mlp_adam_state": [vp, vp, vp, C.POINTER(i64)],
+        "hfsi_mlp_forward": [vp, i32, vp, vp, vp, vp, vp],
+        "hfsi_mlp_loss_grad": [vp, i32, vp, vp, vp, vp, vp, C.POINTER(dbl)],
+        "hfsi_mlp_collect": [vp, C.POINTER(i32), C.POINTER(i32)],
+        "hfsi_mlp_clear": [vp],
+        "hfsi_mlp_samples": [vp, i64, i64, C.POINTER(i64), vp, vp, vp, vp],
+        "hfsi_mlp_train": [vp, C.POINTER(TrainParams), vp, i64, C.POINTER(TrainInfo)],
+        "hfsi_amg_convergence_factor": [vp, i32, C.c_uint64, C.POINTER(dbl)],
     }
     for name, args in sig.items():
         f = getattr(lib, name, None)
@@ -285,6 +312,70 @@ class Context:
         out = C.c_double()
         self._check(self.lib.hfsi_mass_norm(self.h, _ptr(dv), C.byref(out)))
         return out.value
+
+    # ---- learned interpolation
+    def mlp_set_weights(self, w):
+        w = np.ascontiguousarray(w, np.float32)
+        assert w.size == MLP_NPARAM
+        self._check(self.lib.hfsi_mlp_set_weights(self.h, _ptr(w)))
+
+    def mlp_get_weights(self):
+        w = np.zeros(MLP_NPARAM, np.float32)
+        self._check(self.lib.hfsi_mlp_get_weights(self.h, _ptr(w)))
+        return w
+
+    def mlp_adam_state(self):
+        m = np.zeros(MLP_NPARAM, np.float32)
+        v = np.zeros(MLP_NPARAM, np.float32)
+        step = C.c_int64()
+        self._check(self.lib.hfsi_mlp_adam_state(self.h, _ptr(m), _ptr(v), C.byref(step)))
+        return m, v, step.value
+
+    def mlp_forward(self, X):
+        X = np.ascontiguousarray(X, np.float32)
+        m = X.shape[0]
+        out = np.zeros((m, 32), np.float32)
+        xo, h1, h2 = (np.zeros((m, 64), np.uint16) for _ in range(3))
+        self._check(self.lib.hfsi_mlp_forward(self.h, m, _ptr(X), _ptr(out), _ptr(xo), _ptr(h1), _ptr(h2)))
+        return out, xo, h1, h2
+
+    def mlp_loss_grad(self, X, mask, wcl, wstar):
+        arrs = [np.ascontiguousarray(a, np.float32) for a in (X, mask, wcl, wstar)]
+        g = np.zeros(MLP_NPARAM, np.float32)
+        loss = C.c_double()
+        self._check(self.lib.hfsi_mlp_loss_grad(self.h, arrs[0].shape[0], *[_ptr(a) for a in arrs], _ptr(g),
+                                                C.byref(loss)))
+        return loss.value, g
+
+    def mlp_collect(self):
+        a, f = C.c_int32(), C.c_int32()
+        self._check(self.lib.hfsi_mlp_collect(self.h, C.byref(a), C.byref(f)))
+        return a.value, f.value
+
+    def mlp_clear(self):
+        self._check(self.lib.hfsi_mlp_clear(self.h))
+
+    def mlp_samples(self, first=0, count=None):
+        tot = C.c_int64()
+        self._check(self.lib.hfsi_mlp_samples(self.h, 0, 0, C.byref(tot), None, None, None, None))
+        count = tot.value - first if count is None else count
+        X = np.zeros((count, 64), np.float32)
+        mask, wcl, wst = (np.zeros((count, 32), np.float32) for _ in range(3))
+        self._check(self.lib.hfsi_mlp_samples(self.h, first, count, C.byref(tot), _ptr(X), _ptr(mask), _ptr(wcl),
+                                              _ptr(wst)))
+        return X, mask, wcl, wst
+
+    def mlp_train(self, order, prm=None):
+        order = np.ascontiguousarray(order, np.int32)
+        prm = prm or train_params()
+        info = TrainInfo(C.sizeof(TrainInfo))
+        self._check(self.lib.hfsi_mlp_train(self.h, C.byref(prm), _ptr(order), order.size, C.byref(info)))
+        return info
+
+    def amg_convergence_factor(self, cycles=10, seed=777):
+        rho = C.c_double()
+        self._check(self.lib.hfsi_amg_convergence_factor(self.h, cycles, seed, C.byref(rho)))
+        return rho.value
 
     def time_kernel(self, kernel, reps, bytes_hint=0):
         """(average ms per launch, algorithmic bytes per launch) of a hot kernel."""

@@ -1,0 +1,127 @@
+"""Train the learned-interpolation network on AMG set-ups the method itself
+generates (GPU: set-ups, targets, forward, backward and Adam all run in the
+HIP library).
+
+Set-up k (seed 1000 + k): jittered Kuhn cube (interior nodes moved by
+U(-0.1h, 0.1h)^3), kappa = 10^U(3,6), c10 and c01 scaled by U(0.7, 1.3), the
+tangent taken after `newton_per_inc` Newton steps of each load increment up to
+a random increment 1..5 (of 5).  Samples: every level-0 F point with a strong
+C neighbour; target: the local ideal interpolation.
+
+    python -m paper_1312_5561_amd.train_mlp --setups 200 --out gpurun_out/mlp_cube.npz
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FORMAT_VERSION = 1
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "mlp_cube.npz")
+
+
+def init_weights(seed=0):
+    """He-normal hidden layers, zero last layer (starts as classical)."""
+    r = np.random.default_rng(seed)
+    w1 = r.normal(0, np.sqrt(2.0 / 64), (64, 64))
+    w2 = r.normal(0, np.sqrt(2.0 / 64), (64, 64))
+    parts = [w1, np.zeros(64), w2, np.zeros(64), np.zeros((64, 32)), np.zeros(32)]
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
+def setup_problem(k, N):
+    import synth
+    r = np.random.default_rng(1000 + k)
+    kappa = 10.0 ** r.uniform(3, 6)
+    c10 = 0.5 * r.uniform(0.7, 1.3)
+    c01 = 0.1 * r.uniform(0.7, 1.3)
+    prob = synth.cube_problem(N, kappa=kappa, c10=c10, c01=c01, jitter=0.1, seed=1000 + k)
+    inc = int(r.integers(1, 6))
+    return prob, inc
+
+
+def collect(ctx_factory, n_setups, N, newton_per_inc=2, first=0, log=print):
+    """Build the training set in a fresh context; returns the context."""
+    import torch
+    from paper_1312_5561_amd import hfsi
+    ctx = ctx_factory()
+    total, failed = 0, 0
+    prm = hfsi.newton_params(amg=hfsi.amg_params(smoother=1, precision=1, max_coarse=100),
+                             solve=hfsi.solve_params(max_iter=2000))
+    for k in range(first, first + n_setups):
+        prob, inc = setup_problem(k, N)
+        ctx.set_problem(prob)
+        v = torch.zeros(prob.n_dofs, dtype=torch.float64, device="cuda")
+        for q in range(1, inc + 1):
+            for _ in range(newton_per_inc):
+                ctx.newton_step(v, q / 5.0, prm)
+        R = torch.zeros_like(v)
+        ctx.assemble_residual_tangent(v, inc / 5.0, R)
+        ctx.amg_setup(hfsi.amg_params(smoother=1, precision=1, max_coarse=100))
+        a, f = ctx.mlp_collect()
+        total += a
+        failed += f
+        if (k - first) % 25 == 0:
+            log(f"[train] set-up {k}: {a} samples (total {total}, failed targets {failed})")
+    return ctx, total, failed
+
+
+def train(ctx, epochs, batch=1024, lr=1e-3, seed=7, weights=None, log=print):
+    from paper_1312_5561_amd import hfsi
+    ns = ctx.mlp_samples()[0].shape[0]
+    ctx.mlp_set_weights(init_weights(seed) if weights is None else weights)
+    r = np.random.default_rng(seed)
+    order = np.concatenate([r.permutation(ns) for _ in range(epochs)]).astype(np.int32)
+    info = ctx.mlp_train(order, hfsi.train_params(batch=batch, lr=lr))
+    log(f"[train] {info.steps} Adam steps on {ns} samples: loss {info.loss_first:.3e} -> {info.loss_last:.3e} "
+        f"in {info.seconds:.1f} s")
+    return info
+
+
+def save(path, ctx, meta):
+    w = ctx.mlp_get_weights()
+    m, v, step = ctx.mlp_adam_state()
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    np.savez(path, weights=w, adam_m=m, adam_v=v, step=np.int64(step), version=np.int64(FORMAT_VERSION),
+             meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
+
+
+def load(path):
+    """(weights, meta) from a checkpoint written by save()."""
+    with np.load(path, allow_pickle=False) as z:
+        if int(z["version"]) != FORMAT_VERSION:
+            raise ValueError(f"unsupported checkpoint version {int(z['version'])}")
+        return z["weights"].astype(np.float32), json.loads(bytes(z["meta"]).decode())
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--setups", type=int, default=200)
+    ap.add_argument("--N", type=int, default=8)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--out", default="gpurun_out/mlp_cube.npz")
+    args = ap.parse_args()
+    from paper_1312_5561_amd import hfsi
+    t0 = time.time()
+    ctx, total, failed = collect(lambda: hfsi.Context(0), args.setups, args.N,
+                                 log=lambda s: print(s, flush=True))
+    print(f"[train] collected {total} samples ({failed} failed targets) in {time.time() - t0:.1f} s", flush=True)
+    info = train(ctx, args.epochs, args.batch, args.lr, log=lambda s: print(s, flush=True))
+    meta = dict(setups=args.setups, N=args.N, epochs=args.epochs, batch=args.batch, lr=args.lr, samples=total,
+                failed_targets=failed, loss_first=info.loss_first, loss_last=info.loss_last, steps=info.steps)
+    save(args.out, ctx, meta)
+    print(json.dumps(meta), flush=True)
+
+
+if __name__ == "__main__":
+    main()
