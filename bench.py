@@ -10,9 +10,11 @@ FGMRES with the block preconditioner to ||b-Kx|| <= 1e-8 ||b||, update and
 mass norm.  All arithmetic runs in the HIP library; inputs are resident in
 device memory before the timed region.
 
-value = dofs * steps / elapsed for the mixed-precision path (fp32 V-cycle
-inside fp64 FGMRES, classical interpolation); the plain fp64 path is timed
-the same way and reported beside it.
+value = dofs * steps / elapsed for the learned path: level-0 interpolation
+corrected by the trained network (kept only when the V-cycle's measured
+convergence factor passes the judge, classical otherwise) and an fp32
+V-cycle inside fp64 FGMRES.  Classical fp32 and plain fp64 are timed the same
+way and reported beside it.
 """
 from __future__ import annotations
 
@@ -39,12 +41,32 @@ def parse():
     ap.add_argument("--N", type=int, default=48, help="hexahedra per cube edge")
     ap.add_argument("--kappa", type=float, default=1e4)
     ap.add_argument("--smoother", type=int, default=1, help="0 l1-Jacobi, 1 Chebyshev")
-    ap.add_argument("--restart", type=int, default=50)
+    ap.add_argument("--restart", type=int, default=200)
     ap.add_argument("--max-iter", type=int, default=3000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain fp64 comparison")
     ap.add_argument("--roofline-reps", type=int, default=50)
+    ap.add_argument("--interp", choices=("learned", "classical"), default="learned")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1312_5561_amd", "weights", "mlp_cube.npz"))
+    ap.add_argument("--fallback-rho", type=float, default=0.5)
     return ap.parse_args()
+
+
+def measured_traffic(kernel_tag):
+    """Calibrated HBM bytes per launch from the committed PMC summary, or None
+    when the kernel source changed after the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "cube48_level0_smoother_traffic.md")
+    src = os.path.join(ROOT, "paper_1312_5561_amd", "csrc", "solve.hip")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for line in open(path):
+        if line.startswith("traffic ") and f"kernel={kernel_tag} " in line:
+            kv = dict(t.split("=", 1) for t in line.split()[1:])
+            if kv.get("solve_hip_sha256_16") == sha:
+                return float(kv["bytes_per_launch"])
+    return None
 
 
 def run_steps(ctx, v0, v, prm, steps, torch):
@@ -114,43 +136,56 @@ def main():
     ctx = hfsi.Context(0)
     ctx.set_problem(prob)
     v = torch.zeros(ndofs, dtype=torch.float64, device="cuda")
-    amg32 = hfsi.amg_params(precision=1, smoother=args.smoother)
-    amg64 = hfsi.amg_params(precision=0, smoother=args.smoother)
     sp = hfsi.solve_params(tol=1e-8, restart=args.restart, max_iter=args.max_iter)
-    p32 = hfsi.newton_params(amg=amg32, solve=sp)
-    p64 = hfsi.newton_params(amg=amg64, solve=sp)
+    learned = args.interp == "learned"
+    if learned:
+        from paper_1312_5561_amd import train_mlp
+        w, wmeta = train_mlp.load(args.weights)
+        ctx.mlp_set_weights(w)
+    p_main = hfsi.newton_params(amg=hfsi.amg_params(precision=1, smoother=args.smoother, interp=1 if learned else 0,
+                                                    fallback_rho=args.fallback_rho), solve=sp)
+    p_c32 = hfsi.newton_params(amg=hfsi.amg_params(precision=1, smoother=args.smoother), solve=sp)
+    p64 = hfsi.newton_params(amg=hfsi.amg_params(precision=0, smoother=args.smoother), solve=sp)
     # untimed: converge the load increments 0.2 .. 0.8
     for k in range(1, int(round(0.8 * 5)) + 1):
         n0 = None
         for _ in range(25):
-            info, _ = ctx.newton_step(v, k / 5.0, p32)
+            info, _ = ctx.newton_step(v, k / 5.0, p_c32)
             n0 = info.dv_mass_norm if n0 is None else n0
             if info.dv_mass_norm <= 1e-10 * n0:
                 break
     v0 = v.clone()
     print(f"[bench] prepared state: {ndofs} dofs", file=sys.stderr, flush=True)
 
-    # mixed precision (value)
-    run_steps(ctx, v0, v, p32, args.warmup, torch)
-    dt32, inf32 = run_steps(ctx, v0, v, p32, args.steps, torch)
-    v32 = v.clone()
-    print(f"[bench] fp32 V-cycle: {dt32 / args.steps * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
     res = {}
+
+    def timed(prm, label):
+        run_steps(ctx, v0, v, prm, args.warmup, torch)
+        dt, inf = run_steps(ctx, v0, v, prm, args.steps, torch)
+        print(f"[bench] {label}: {dt / args.steps * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
+        return dt, inf, (v - v0).clone()
+
+    # headline: learned interpolation (or classical with --interp classical), fp32 V-cycle
+    dt_main, inf_main, d_main = timed(p_main, "learned fp32" if learned else "classical fp32")
+    judge = {}
+    if learned:
+        info = ctx.amg_setup(p_main.amg)
+        judge = {"rho_learned": info.rho, "learned_used": bool(info.learned_used), "fallback_rho": args.fallback_rho}
+        info_c = ctx.amg_setup(p_c32.amg)
+        judge["rho_classical"] = ctx.amg_convergence_factor(10, 777)
+        dt_c32, inf_c32, d_c32 = timed(p_c32, "classical fp32")
+        res["classical_fp32"] = {"value": ndofs * args.steps / dt_c32, "unit": "dofs/s",
+                                 "ms_per_step": dt_c32 / args.steps * 1e3, **summarize(inf_c32)}
     if not args.no_fp64:
-        run_steps(ctx, v0, v, p64, max(1, args.warmup // 2), torch)
-        dt64, inf64 = run_steps(ctx, v0, v, p64, args.steps, torch)
-        v64 = v.clone()
-        d32 = (v32 - v0).double()
-        d64 = (v64 - v0).double()
-        err = float(torch.linalg.norm(d32 - d64) / torch.linalg.norm(d64))
+        dt64, inf64, d64 = timed(p64, "plain fp64")
+        err = float(torch.linalg.norm(d_main - d64) / torch.linalg.norm(d64))
         res["fp64_plain"] = {"value": ndofs * args.steps / dt64, "unit": "dofs/s",
                              "ms_per_step": dt64 / args.steps * 1e3, **summarize(inf64)}
-        res["fp32_vs_fp64_update_rel_err"] = err
-        print(f"[bench] fp64: {dt64 / args.steps * 1e3:.1f} ms/step, update rel diff {err:.2e}", file=sys.stderr,
-              flush=True)
-        # leave the mixed-precision hierarchy in place for the roofline timing
-        v.copy_(v0)
-        ctx.newton_step(v, 1.0, p32)
+        res["update_rel_err_vs_fp64"] = err
+        res["speedup_vs_fp64_plain"] = dt64 / dt_main
+    # leave an fp32 classical hierarchy in place for the roofline timing
+    v.copy_(v0)
+    ctx.newton_step(v, 1.0, p_c32)
 
     # roofline of the dominant kernel: the level-0 smoother sweep (fp32)
     ms, nbytes = ctx.time_kernel(0, args.roofline_reps)
@@ -158,7 +193,8 @@ def main():
     sweep = "l1-Jacobi sweep (OP_JACOBI)" if args.smoother == 0 else "Chebyshev step (OP_CHEB)"
     roof = {"kernel": f"level-0 {sweep}, fp32 CSR, k_csr<float,16,...>", "bound": "hbm",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None, "avg_us": ms * 1e3, "bytes_per_launch": nbytes}
+            "traffic": measured_traffic("k_csr<float,16,4>") if args.smoother == 1 else None,
+            "avg_us": ms * 1e3, "bytes_per_launch": nbytes}
     extra = {}
     for kid, name in ((1, "level-0 residual fp32"), (2, "tangent SpMV fp64 4x4 blocks"), (3, "element assembly")):
         kms, kb = ctx.time_kernel(kid, 20 if kid != 3 else 3)
@@ -168,12 +204,12 @@ def main():
 
     out = {
         "metric": METRIC,
-        "value": ndofs * args.steps / dt32,
+        "value": ndofs * args.steps / dt_main,
         "unit": "dofs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt32 / args.steps * 1e3,
+        "ms_per_step": dt_main / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -181,9 +217,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"cube{args.N} Mooney-Rivlin kappa={args.kappa:g}: one Newton step at load 1.0 from "
                                f"the converged load-0.8 state, FGMRES to 1e-8", "dofs": ndofs,
-                   "interp": "classical", "precision": "fp32 V-cycle in fp64 FGMRES",
+                   "interp": args.interp, "precision": "fp32 V-cycle in fp64 FGMRES", "restart": args.restart,
                    "smoother": "l1-Jacobi" if args.smoother == 0 else "Chebyshev"},
-        "breakdown": summarize(inf32),
+        "breakdown": summarize(inf_main),
+        **({"judge": judge} if judge else {}),
         **res,
         "roofline": roof,
         "kernels": extra,

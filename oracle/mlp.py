@@ -110,8 +110,13 @@ def samples(A, comp, state, S_ptr, S_idx, P, lattice, matfeat):
     return np.array(rows, np.int64), np.array(X), np.array(mask), np.array(wcl)
 
 
-def ideal_target(A, comp, state, S_ptr, S_idx, lattice, i):
-    """w*_i on the 27 slots (zero outside C_i)."""
+def ideal_target(A, comp, state, S_ptr, S_idx, lattice, i, classical_sum=None):
+    """w*_i on the 27 slots (zero outside C_i).
+
+    With classical_sum given, w*_i is rescaled to that row sum: the local
+    system drops every coupling outside F_loc, so its raw solution does not
+    reproduce constants; the classical weights do (for zero row sums), and
+    an interpolation that loses them slows the V-cycle down."""
     lo, hi = A.indptr[i], A.indptr[i + 1]
     cols = A.indices[lo:hi]
     S_set = set(S_idx[S_ptr[i]:S_ptr[i + 1]].tolist())
@@ -121,6 +126,12 @@ def ideal_target(A, comp, state, S_ptr, S_idx, lattice, i):
     Ac = A[Floc][:, Ci].toarray()
     Xs = np.linalg.solve(Ad, -Ac)
     wi = Xs[Floc.index(i)]
+    if classical_sum is not None:
+        s = 0.0
+        for w in wi:
+            s += w
+        if abs(s) > 1e-12:
+            wi = wi * (classical_sum / s)
     out = np.zeros(NOUT)
     for j, w in zip(Ci, wi):
         out[slot_of(lattice[j // 3] - lattice[i // 3])] = w

@@ -102,11 +102,12 @@ constexpr int LMAX = 32, CMAX = 27;
 __global__ void __launch_bounds__(64)
 k_ideal_target(int ns, const int* __restrict__ rows, const int* __restrict__ ap, const int* __restrict__ ac,
                const double* __restrict__ av, const int* __restrict__ comp, const int8_t* __restrict__ state,
-               const uint8_t* __restrict__ strong, const int* __restrict__ lat, float* __restrict__ wstar,
-               int* __restrict__ fail) {
+               const uint8_t* __restrict__ strong, const int* __restrict__ lat, const float* __restrict__ wcl,
+               float* __restrict__ wstar, int* __restrict__ fail) {
   __shared__ int Fl[LMAX], Cl[CMAX];
   __shared__ double Mx[LMAX][LMAX + CMAX];
   __shared__ int nF, nC, ipos, bad;
+  __shared__ double scale;
   const int lane = threadIdx.x;
   for (int m = blockIdx.x; m < ns; m += gridDim.x) {
     const int i = rows[m], ci = comp[i];
@@ -181,13 +182,21 @@ k_ideal_target(int ns, const int* __restrict__ rows, const int* __restrict__ ap,
       }
     }
     __syncthreads();
+    // rescale to the classical row sum (constants are then reproduced as by
+    // the classical weights; the local system alone drops outer couplings)
+    if (lane == 0 && !bad) {
+      double si = 0.0, sc = 0.0;
+      for (int t = 0; t < NC; ++t) si += Mx[ipos][LMAX + t];
+      for (int t = 0; t < NOUT; ++t) sc += (double)wcl[(size_t)m * NOUTP + t];
+      scale = fabs(si) > 1e-12 ? sc / si : 1.0;
+    }
     if (lane < NOUTP) wstar[(size_t)m * NOUTP + lane] = 0.f;
     __syncthreads();
     if (bad) {
       if (lane == 0) atomicAdd(fail, 1);
     } else if (lane < NC) {
       const int s = slot_of(lat, i / 3, Cl[lane] / 3);
-      if (s >= 0) wstar[(size_t)m * NOUTP + s] = (float)Mx[ipos][LMAX + lane];
+      if (s >= 0) wstar[(size_t)m * NOUTP + s] = (float)(Mx[ipos][LMAX + lane] * scale);
     }
     __syncthreads();
   }
@@ -627,7 +636,7 @@ extern "C" hfsi_status hfsi_mlp_collect(hfsi_ctx* c, int32_t* n_added, int32_t* 
     HIP_CHECK(hipMemcpyAsync(S.wcl.p + S.ns * NOUTP, smp.wcl.p, sizeof(float) * ns * NOUTP, hipMemcpyDeviceToDevice, s));
     k_ideal_target<<<(int)std::min<long>(ns, 65536), 64, 0, s>>>((int)ns, smp.rows.p, L.A.ptr.p, L.A.col.p, L.A.val.p,
                                                                  L.comp.p, L.state.p, L.strong.p, c->lattice.p,
-                                                                 S.wst.p + S.ns * NOUTP, fl.p);
+                                                                 smp.wcl.p, S.wst.p + S.ns * NOUTP, fl.p);
     HIP_LAUNCH_CHECK();
   }
   int nf = 0;

@@ -206,7 +206,7 @@ __global__ void k_reduce_rows(int k, int nb, const double* __restrict__ part, do
 __global__ void __launch_bounds__(256)
 k_vupdate(long N, int k, const double* __restrict__ V, long ldv, const double* __restrict__ h, double sgn,
           double* __restrict__ w) {
-  __shared__ double hs[64];
+  __shared__ double hs[256];
   if (threadIdx.x < k) hs[threadIdx.x] = h[threadIdx.x];
   __syncthreads();
   const long e = (long)blockIdx.x * 256 + threadIdx.x;
@@ -522,7 +522,7 @@ void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_para
   c->kw.ensure(N);
   c->kr.ensure(N);
   KState st{m};
-  c->kh.ensure(st.size() + 256);
+  c->kh.ensure(st.size() + 512);
   c->kred.ensure(2 * RED_BLOCKS + (size_t)RED_BLOCKS * (m + 8));
   c->scal.ensure(16);
   double* sc = c->scal.p;  // 0 bnorm, 1 beta, 2 w0, 3 hnorm, 4-5 report
@@ -561,12 +561,12 @@ void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_para
         mdot(c, N, j + 1, V, c->kw.p, hbuf, 0);
         k_vupdate<<<gN, 256, 0, s>>>(N, j + 1, V, N, hbuf, -1.0, c->kw.p);
         HIP_LAUNCH_CHECK();
-        mdot(c, N, j + 1, V, c->kw.p, hbuf + 64, 0);
-        k_vupdate<<<gN, 256, 0, s>>>(N, j + 1, V, N, hbuf + 64, -1.0, c->kw.p);
+        mdot(c, N, j + 1, V, c->kw.p, hbuf + 256, 0);
+        k_vupdate<<<gN, 256, 0, s>>>(N, j + 1, V, N, hbuf + 256, -1.0, c->kw.p);
         HIP_LAUNCH_CHECK();
-        k_reduce_rows<<<j + 1, 256, 0, s>>>(j + 1, 1, hbuf + 64, hbuf, 1);  // h += h2
+        k_reduce_rows<<<j + 1, 256, 0, s>>>(j + 1, 1, hbuf + 256, hbuf, 1);  // h += h2
         HIP_LAUNCH_CHECK();
-        k_store_col<<<1, 64, 0, s>>>(c->kh.p, m, j, hbuf);
+        k_store_col<<<1, 256, 0, s>>>(c->kh.p, m, j, hbuf);
         HIP_LAUNCH_CHECK();
         norm_dev(c, c->kw.p, N, sc + 3);
         k_givens<<<1, 1, 0, s>>>(c->kh.p, m, j, sc + 3, sc + 4);
@@ -619,8 +619,8 @@ void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_para
 namespace {
 void check_solve_params(const hfsi_solve_params* p) {
   if (!p || p->struct_size != sizeof(hfsi_solve_params)) fail(HFSI_E_ARG, "solve params: struct_size mismatch");
-  if (!(p->tol > 0) || p->restart < 1 || p->restart > 60 || p->max_iter < 1)
-    fail(HFSI_E_ARG, "solve params: need tol > 0, 1 <= restart <= 60, max_iter >= 1");
+  if (!(p->tol > 0) || p->restart < 1 || p->restart > 256 || p->max_iter < 1)
+    fail(HFSI_E_ARG, "solve params: need tol > 0, 1 <= restart <= 256, max_iter >= 1");
 }
 }  // namespace
 

@@ -102,8 +102,51 @@ def load(path):
         return z["weights"].astype(np.float32), json.loads(bytes(z["meta"]).decode())
 
 
+def evaluate(path, cases=((8, 9001), (8, 9002), (16, 9003), (24, 9004), (48, 9005)), log=print):
+    """Held-out comparison of learned and classical level-0 interpolation:
+    jittered cube (seed s, kappa = 10^U(3,6)), two Newton steps per increment
+    0.2..0.8, tangent at load 1.0, set-up with the judge disabled, FGMRES(50)."""
+    import torch
+    import synth
+    from paper_1312_5561_amd import hfsi
+    w, meta = load(path)
+    rows = []
+    for N, seed in cases:
+        r = np.random.default_rng(seed)
+        kappa = 10 ** r.uniform(3, 6)
+        prob = synth.cube_problem(N, kappa=kappa, jitter=0.1, seed=seed)
+        ctx = hfsi.Context(0)
+        ctx.set_problem(prob)
+        ctx.mlp_set_weights(w)
+        v = torch.zeros(prob.n_dofs, dtype=torch.float64, device="cuda")
+        p = hfsi.newton_params(amg=hfsi.amg_params(smoother=1, precision=1), solve=hfsi.solve_params(max_iter=3000))
+        for q in range(1, 5):
+            for _ in range(2):
+                ctx.newton_step(v, q / 5.0, p)
+        R = torch.zeros_like(v)
+        ctx.assemble_residual_tangent(v, 1.0, R)
+        b = -R
+        res = {}
+        for interp in (0, 1):
+            info = ctx.amg_setup(hfsi.amg_params(smoother=1, precision=1, interp=interp, fallback_rho=1.0))
+            rho = ctx.amg_convergence_factor(10, 777)
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t = time.time()
+            si, _ = ctx.krylov_amg_solve(b, x, hfsi.solve_params(max_iter=3000))
+            torch.cuda.synchronize()
+            res[interp] = dict(rho=rho, its=si.iterations, ms=(time.time() - t) * 1e3, opc=info.op_complexity)
+        line = (f"N={N} kappa={kappa:.2e} classical rho={res[0]['rho']:.3f} its={res[0]['its']} "
+                f"t={res[0]['ms']:.0f}ms opc={res[0]['opc']:.2f} | learned rho={res[1]['rho']:.3f} "
+                f"its={res[1]['its']} t={res[1]['ms']:.0f}ms opc={res[1]['opc']:.2f}")
+        log(line)
+        rows.append((N, kappa, res))
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--evaluate", default=None, help="checkpoint to compare against classical interpolation")
     ap.add_argument("--setups", type=int, default=200)
     ap.add_argument("--N", type=int, default=8)
     ap.add_argument("--epochs", type=int, default=30)
@@ -112,6 +155,9 @@ def main():
     ap.add_argument("--out", default="gpurun_out/mlp_cube.npz")
     args = ap.parse_args()
     from paper_1312_5561_amd import hfsi
+    if args.evaluate:
+        evaluate(args.evaluate, log=lambda s: print(s, flush=True))
+        return
     t0 = time.time()
     ctx, total, failed = collect(lambda: hfsi.Context(0), args.setups, args.N,
                                  log=lambda s: print(s, flush=True))

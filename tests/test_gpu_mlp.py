@@ -105,8 +105,12 @@ def test_collect_matches_oracle(lib):
     assert np.array_equal(mask[:, :27], mo)
     assert np.allclose(wcl[:, :27], wo, rtol=1e-6, atol=1e-7)
     for m in range(0, added, 37):
-        t = mlp.ideal_target(A, comp, st, S_ptr, S_idx, prob.lattice, rows[m])
+        csum = 0.0
+        for s in range(27):
+            csum += float(wcl[m, s])
+        t = mlp.ideal_target(A, comp, st, S_ptr, S_idx, prob.lattice, rows[m], classical_sum=csum)
         assert np.allclose(wst[m, :27], t, rtol=1e-5, atol=1e-6)
+        assert abs(t.sum() - csum) <= 1e-9 * max(1.0, abs(csum))
 
 
 def test_zero_last_layer_is_classical_and_fallback(lib):
