@@ -695,6 +695,16 @@ void copy_csr(hfsi_ctx* c, const Csr<double>& src, Csr<double>& dst) {
   HIP_CHECK(hipMemcpyAsync(dst.val.p, src.val.p, sizeof(double) * src.nnz, hipMemcpyDeviceToDevice, c->stream));
 }
 
+__global__ void k_block3(int nb, const double* __restrict__ Kval, double* __restrict__ b3d, float* __restrict__ b3f) {
+  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 9L * nb) return;
+  const long q = t / 9;
+  const int rc = (int)(t - 9 * q), r = rc / 3, cc = rc % 3;
+  const double v = Kval[16 * q + 4 * r + cc];
+  b3d[t] = v;
+  b3f[t] = (float)v;
+}
+
 __global__ void k_comp_mod3(int n, int* __restrict__ comp) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) comp[i] = i % 3;
@@ -866,6 +876,15 @@ void amg_setup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* in
   L0.n = c->A.rows;
   L0.comp.ensure(L0.n);
   k_comp_mod3<<<div_up(L0.n, 256), 256, 0, c->stream>>>(L0.n, L0.comp.p);
+  HIP_LAUNCH_CHECK();
+  // 3x3 node-block copy of A (entries removed from the CSR by the Dirichlet
+  // elimination are exact zeros in the eliminated tangent)
+  L0.bptr = c->nptr.p;
+  L0.bcol = c->ncol.p;
+  L0.nbr = c->n;
+  L0.b3d.ensure(9 * (size_t)c->nb);
+  L0.b3f.ensure(9 * (size_t)c->nb);
+  k_block3<<<div_up(9L * c->nb, 256), 256, 0, c->stream>>>(c->nb, c->Kval.p, L0.b3d.p, L0.b3f.p);
   HIP_LAUNCH_CHECK();
   build_hierarchy(c, prm, info);
 }

@@ -106,6 +106,13 @@ struct Level {
   DevBuf<double> dinv;     // smoother diagonal (l1 or plain), fp64
   DevBuf<float> dinv32;
   double lmax = 0.0;       // Chebyshev upper eigenvalue estimate
+  // level 0 built from the assembled tangent: the same operator as 3x3 node
+  // blocks (one column index per 9 values) for the smoother and residual
+  const int* bptr = nullptr;  // node-block row pointer (context-owned)
+  const int* bcol = nullptr;
+  int nbr = 0;                // node rows
+  DevBuf<double> b3d;         // [9 * blocks]
+  DevBuf<float> b3f;
   // V-cycle vectors (fp64 and fp32 variants used according to precision)
   DevBuf<double> x, b, r, t;
   DevBuf<float> xf, bf, rf, tf;

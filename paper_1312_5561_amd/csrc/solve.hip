@@ -65,6 +65,47 @@ void csr_launch(int G, int n, const int* ptr, const int* col, const T* val, cons
   HIP_LAUNCH_CHECK();
 }
 
+// Same operations on a 3x3 node-block matrix: 8 lanes per node row, each lane
+// a strided subset of the row's blocks (9 values + one column index), then a
+// shuffle reduction of the three row sums; lanes 0..2 finish rows 3i..3i+2.
+template <class T, int OP>
+__global__ void __launch_bounds__(256)
+k_b3(int nn, const int* __restrict__ bptr, const int* __restrict__ bcol, const T* __restrict__ B,
+     const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ dinv, T* __restrict__ y,
+     T* __restrict__ d, T c1, T c2) {
+  const int node = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const int lane = threadIdx.x & 7;
+  if (node >= nn) return;
+  T s0 = 0, s1 = 0, s2 = 0;
+  const int hi = bptr[node + 1];
+  for (int q = bptr[node] + lane; q < hi; q += 8) {
+    const int j = 3 * bcol[q];
+    const T* v = B + 9 * (size_t)q;
+    const T x0 = x[j], x1 = x[j + 1], x2 = x[j + 2];
+    s0 += v[0] * x0 + v[1] * x1 + v[2] * x2;
+    s1 += v[3] * x0 + v[4] * x1 + v[5] * x2;
+    s2 += v[6] * x0 + v[7] * x1 + v[8] * x2;
+  }
+#pragma unroll
+  for (int o = 4; o > 0; o >>= 1) {
+    s0 += __shfl_xor(s0, o, 8);
+    s1 += __shfl_xor(s1, o, 8);
+    s2 += __shfl_xor(s2, o, 8);
+  }
+  if (lane >= 3) return;
+  const int row = 3 * node + lane;
+  const T s = lane == 0 ? s0 : (lane == 1 ? s1 : s2);
+  if (OP == OP_SPMV) y[row] = s;
+  else if (OP == OP_RESID) y[row] = b[row] - s;
+  else if (OP == OP_JACOBI) y[row] = x[row] + dinv[row] * (b[row] - s);
+  else if (OP == OP_ADD) y[row] += s;
+  else {
+    const T dn = c1 * d[row] + c2 * dinv[row] * (b[row] - s);
+    d[row] = dn;
+    y[row] = x[row] + dn;
+  }
+}
+
 inline int lanes_for(int64_t nnz, int rows) {
   const double avg = rows ? (double)nnz / rows : 1.0;
   if (avg <= 8) return 4;
@@ -267,48 +308,67 @@ struct KState {
 
 __global__ void k_kinit(double* __restrict__ kh, int m, const double* __restrict__ beta) {
   KState st{m};
-  for (long t = 0; t < st.size(); ++t) kh[t] = 0.0;
-  kh[st.g()] = beta[0];
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < st.size(); t += (long)gridDim.x * blockDim.x)
+    kh[t] = t == st.g() ? beta[0] : 0.0;
 }
 
 // Column j of H holds h (j+1 entries) and H[j+1][j] = hnorm.  Apply the
 // previous rotations, form rotation j, update g; report |g_{j+1}|.
-__global__ void k_givens(double* __restrict__ kh, int m, int j, const double* __restrict__ hnorm,
-                         double* __restrict__ report) {
+// (one block of 256 threads: the column and the rotations are staged in LDS,
+// the sequential sweep over the previous rotations runs on one thread)
+__global__ void __launch_bounds__(256) k_givens(double* __restrict__ kh, int m, int j, const double* __restrict__ hnorm,
+                                                double* __restrict__ report) {
+  __shared__ double sc[258], scs[257], ssn[257];
   KState st{m};
-  double* H = kh;
   double* cs = kh + st.cs();
   double* sn = kh + st.sn();
   double* g = kh + st.g();
-  double* col = H + (long)j * (m + 1);
-  col[j + 1] = hnorm[0];
-  for (int i = 0; i < j; ++i) {
-    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-    col[i] = t;
+  double* col = kh + (long)j * (m + 1);
+  for (int t = threadIdx.x; t <= j; t += blockDim.x) sc[t] = col[t];
+  for (int t = threadIdx.x; t < j; t += blockDim.x) {
+    scs[t] = cs[t];
+    ssn[t] = sn[t];
   }
-  const double d = hypot(col[j], col[j + 1]);
-  const double hj1 = col[j + 1];
-  cs[j] = col[j] / d;
-  sn[j] = hj1 / d;
-  col[j] = d;
-  col[j + 1] = 0.0;
-  g[j + 1] = -sn[j] * g[j];
-  g[j] = cs[j] * g[j];
-  report[0] = fabs(g[j + 1]);
-  report[1] = hj1;
+  if (threadIdx.x == 0) sc[j + 1] = hnorm[0];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < j; ++i) {
+      const double t = scs[i] * sc[i] + ssn[i] * sc[i + 1];
+      sc[i + 1] = -ssn[i] * sc[i] + scs[i] * sc[i + 1];
+      sc[i] = t;
+    }
+    const double d = hypot(sc[j], sc[j + 1]);
+    const double hj1 = sc[j + 1];
+    cs[j] = sc[j] / d;
+    sn[j] = hj1 / d;
+    sc[j] = d;
+    sc[j + 1] = 0.0;
+    const double gj = g[j];
+    g[j + 1] = -sn[j] * gj;
+    g[j] = cs[j] * gj;
+    report[0] = fabs(g[j + 1]);
+    report[1] = hj1;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t <= j + 1; t += blockDim.x) col[t] = sc[t];
 }
 
-// back substitution H y = g on the first k columns
-__global__ void k_backsolve(double* __restrict__ kh, int m, int k) {
+// back substitution H y = g on the first k columns, column by column:
+// y_i = s_i / H_ii, then s_t -= H_ti y_i for t < i (parallel over t)
+__global__ void __launch_bounds__(256) k_backsolve(double* __restrict__ kh, int m, int k) {
+  __shared__ double s[257];
   KState st{m};
   const double* H = kh;
   const double* g = kh + st.g();
   double* y = kh + st.y();
+  for (int t = threadIdx.x; t < k; t += blockDim.x) s[t] = g[t];
+  __syncthreads();
   for (int i = k - 1; i >= 0; --i) {
-    double s = g[i];
-    for (int t = i + 1; t < k; ++t) s -= H[(long)t * (m + 1) + i] * y[t];
-    y[i] = s / H[(long)i * (m + 1) + i];
+    const double yi = s[i] / H[(long)i * (m + 1) + i];
+    __syncthreads();
+    for (int t = threadIdx.x; t < i; t += blockDim.x) s[t] -= H[(long)i * (m + 1) + t] * yi;
+    if (threadIdx.x == 0) y[i] = yi;
+    __syncthreads();
   }
 }
 
@@ -330,6 +390,7 @@ struct LevelView {
   const T* R;
   const T* dinv;
   T *x, *t, *b, *r;
+  const T* B3;  // 3x3 node blocks of level 0 (or null)
 };
 
 template <class T>
@@ -337,11 +398,25 @@ LevelView<T> view(Level& L, bool last);
 
 template <>
 LevelView<double> view<double>(Level& L, bool last) {
-  return {L.A.val.p, last ? nullptr : L.P.val.p, last ? nullptr : L.R.val.p, L.dinv.p, L.x.p, L.t.p, L.b.p, L.r.p};
+  return {L.A.val.p, last ? nullptr : L.P.val.p, last ? nullptr : L.R.val.p, L.dinv.p, L.x.p, L.t.p, L.b.p, L.r.p,
+          L.bptr ? L.b3d.p : nullptr};
 }
 template <>
 LevelView<float> view<float>(Level& L, bool last) {
-  return {L.A32.p, last ? nullptr : L.P32.p, last ? nullptr : L.R32.p, L.dinv32.p, L.xf.p, L.tf.p, L.bf.p, L.rf.p};
+  return {L.A32.p, last ? nullptr : L.P32.p, last ? nullptr : L.R32.p, L.dinv32.p, L.xf.p, L.tf.p, L.bf.p, L.rf.p,
+          L.bptr ? L.b3f.p : nullptr};
+}
+
+// y = f(A x) on level L with the node-block operator when the level has one
+template <class T, int OP>
+void level_op(Level& L, const LevelView<T>& v, const T* x, const T* b, T* y, T* d, T c1, T c2, hipStream_t s) {
+  if (L.bptr) {
+    k_b3<T, OP><<<div_up((long)L.nbr * 8, 256), 256, 0, s>>>(L.nbr, L.bptr, L.bcol, v.B3, x, b, v.dinv, y, d, c1,
+                                                              c2);
+    HIP_LAUNCH_CHECK();
+  } else {
+    csr_launch<T, OP>(lanes_for(L.A.nnz, L.n), L.n, L.A.ptr.p, L.A.col.p, v.A, x, b, v.dinv, y, d, c1, c2, s);
+  }
 }
 
 // smoothing sweeps on level L; x holds the current iterate (in buffer xa),
@@ -350,7 +425,6 @@ template <class T>
 T* smooth(hfsi_ctx* c, Level& L, const LevelView<T>& v, const T* b, T* xa, T* xb, int nu, bool zero_start) {
   hipStream_t s = c->stream;
   const int n = L.n;
-  const int G = lanes_for(L.A.nnz, n);
   const Hierarchy& H = c->H;
   if (H.smoother == 0) {
     for (int k = 0; k < nu; ++k) {
@@ -359,7 +433,7 @@ T* smooth(hfsi_ctx* c, Level& L, const LevelView<T>& v, const T* b, T* xa, T* xb
         HIP_LAUNCH_CHECK();
         continue;
       }
-      csr_launch<T, OP_JACOBI>(G, n, L.A.ptr.p, L.A.col.p, v.A, xa, b, v.dinv, xb, nullptr, 0, 0, s);
+      level_op<T, OP_JACOBI>(L, v, xa, b, xb, nullptr, 0, 0, s);
       std::swap(xa, xb);
     }
     return xa;
@@ -374,11 +448,10 @@ T* smooth(hfsi_ctx* c, Level& L, const LevelView<T>& v, const T* b, T* xa, T* xb
       k_cheb_first<T><<<div_up(n, 256), 256, 0, s>>>(n, v.dinv, b, xa, d, (T)(1.0 / theta));
       HIP_LAUNCH_CHECK();
     } else {
-      csr_launch<T, OP_CHEB>(G, n, L.A.ptr.p, L.A.col.p, v.A, xa, b, v.dinv, xb, d, (T)0, (T)(1.0 / theta), s);
+      level_op<T, OP_CHEB>(L, v, xa, b, xb, d, (T)0, (T)(1.0 / theta), s);
       std::swap(xa, xb);
     }
-    csr_launch<T, OP_CHEB>(G, n, L.A.ptr.p, L.A.col.p, v.A, xa, b, v.dinv, xb, d, (T)(rho1 * rho0),
-                           (T)(2.0 * rho1 / delta), s);
+    level_op<T, OP_CHEB>(L, v, xa, b, xb, d, (T)(rho1 * rho0), (T)(2.0 * rho1 / delta), s);
     std::swap(xa, xb);
   }
   return xa;
@@ -417,8 +490,7 @@ T* vcycle_rec(hfsi_ctx* c, int l) {
     HIP_CHECK(hipMemsetAsync(v.x, 0, sizeof(T) * n, s));
   }
   T* other = x == v.x ? v.t : v.x;
-  const int G = lanes_for(L.A.nnz, n);
-  csr_launch<T, OP_RESID>(G, n, L.A.ptr.p, L.A.col.p, v.A, x, v.b, nullptr, v.r, nullptr, 0, 0, s);
+  level_op<T, OP_RESID>(L, v, x, v.b, v.r, nullptr, 0, 0, s);
   Level& Lc = H.L[l + 1];
   LevelView<T> vc = view<T>(Lc, l + 1 == (int)H.L.size() - 1);
   csr_launch<T, OP_SPMV>(lanes_for(L.R.nnz, L.R.rows), L.R.rows, L.R.ptr.p, L.R.col.p, v.R, v.r, nullptr, nullptr,
@@ -548,7 +620,7 @@ void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_para
       double* Z = c->kz.p;
       k_div_scalar<<<gN, 256, 0, s>>>(N, c->kr.p, sc + 1, V);
       HIP_LAUNCH_CHECK();
-      k_kinit<<<1, 1, 0, s>>>(c->kh.p, m, sc + 1);
+      k_kinit<<<64, 256, 0, s>>>(c->kh.p, m, sc + 1);
       HIP_LAUNCH_CHECK();
       int jend = 0;
       for (int j = 0; j < m; ++j) {
@@ -569,7 +641,7 @@ void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_para
         k_store_col<<<1, 256, 0, s>>>(c->kh.p, m, j, hbuf);
         HIP_LAUNCH_CHECK();
         norm_dev(c, c->kw.p, N, sc + 3);
-        k_givens<<<1, 1, 0, s>>>(c->kh.p, m, j, sc + 3, sc + 4);
+        k_givens<<<1, 256, 0, s>>>(c->kh.p, m, j, sc + 3, sc + 4);
         HIP_LAUNCH_CHECK();
         HIP_CHECK(hipMemcpyAsync(c->pinned, sc + 2, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
@@ -585,7 +657,7 @@ void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_para
         k_div_scalar<<<gN, 256, 0, s>>>(N, c->kw.p, sc + 3, V + (long)(j + 1) * N);
         HIP_LAUNCH_CHECK();
       }
-      k_backsolve<<<1, 1, 0, s>>>(c->kh.p, m, jend);
+      k_backsolve<<<1, 256, 0, s>>>(c->kh.p, m, jend);
       HIP_LAUNCH_CHECK();
       k_vupdate<<<gN, 256, 0, s>>>(N, jend, Z, N, c->kh.p + st.y(), 1.0, x);
       HIP_LAUNCH_CHECK();
@@ -752,37 +824,25 @@ extern "C" hfsi_status hfsi_time_kernel(hfsi_ctx* c, int32_t kernel, int32_t rep
     if (!H.ready) fail(HFSI_E_ORDER, "time_kernel: no hierarchy");
     hfsi::Level& L = H.L[0];
     const int n = L.n;
-    const int G = lanes_for(L.A.nnz, n);
     const double ts = H.precision == 1 ? 4.0 : 8.0;
-    const double nnz = (double)L.A.nnz;
-    if (kernel == 0) {
-      // val + col per entry; ptr, x_i, b, dinv read and y written per row
-      b = nnz * (ts + 4.0) + n * (4.0 + 4.0 * ts);
-      if (H.smoother == 1) b += n * 2.0 * ts;  // Chebyshev direction read + write
-    } else {
-      b = nnz * (ts + 4.0) + n * (4.0 + 2.0 * ts);
-    }
-    launch = [&, n, G, kernel]() {
+    // per scalar row: Chebyshev reads x_i, b, D^-1, d and writes d, y; Jacobi
+    // reads x_i, b, D^-1 and writes y; the residual reads b and writes y
+    const double per_row = kernel == 1 ? 2.0 * ts : (H.smoother == 1 ? 6.0 * ts : 4.0 * ts);
+    if (L.bptr)  // 3x3 node blocks: 9 values + one column index per block, one pointer per node row
+      b = (double)c->nb * (9.0 * ts + 4.0) + (double)L.nbr * 4.0 + n * per_row;
+    else
+      b = (double)L.A.nnz * (ts + 4.0) + n * (4.0 + per_row);
+    launch = [&, kernel]() {
       if (H.precision == 0) {
-        if (kernel == 1)
-          csr_launch<double, OP_RESID>(G, n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.x.p, L.b.p, nullptr, L.r.p, nullptr,
-                                       0, 0, s);
-        else if (H.smoother == 0)
-          csr_launch<double, OP_JACOBI>(G, n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.x.p, L.b.p, L.dinv.p, L.t.p,
-                                        nullptr, 0, 0, s);
-        else
-          csr_launch<double, OP_CHEB>(G, n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.x.p, L.b.p, L.dinv.p, L.t.p, L.r.p,
-                                      0.5, 0.5, s);
+        auto v = hfsi::view<double>(L, false);
+        if (kernel == 1) hfsi::level_op<double, OP_RESID>(L, v, L.x.p, L.b.p, L.r.p, nullptr, 0, 0, s);
+        else if (H.smoother == 0) hfsi::level_op<double, OP_JACOBI>(L, v, L.x.p, L.b.p, L.t.p, nullptr, 0, 0, s);
+        else hfsi::level_op<double, OP_CHEB>(L, v, L.x.p, L.b.p, L.t.p, L.r.p, 0.5, 0.5, s);
       } else {
-        if (kernel == 1)
-          csr_launch<float, OP_RESID>(G, n, L.A.ptr.p, L.A.col.p, L.A32.p, L.xf.p, L.bf.p, nullptr, L.rf.p, nullptr,
-                                      0, 0, s);
-        else if (H.smoother == 0)
-          csr_launch<float, OP_JACOBI>(G, n, L.A.ptr.p, L.A.col.p, L.A32.p, L.xf.p, L.bf.p, L.dinv32.p, L.tf.p,
-                                       nullptr, 0, 0, s);
-        else
-          csr_launch<float, OP_CHEB>(G, n, L.A.ptr.p, L.A.col.p, L.A32.p, L.xf.p, L.bf.p, L.dinv32.p, L.tf.p, L.rf.p,
-                                     0.5f, 0.5f, s);
+        auto v = hfsi::view<float>(L, false);
+        if (kernel == 1) hfsi::level_op<float, OP_RESID>(L, v, L.xf.p, L.bf.p, L.rf.p, nullptr, 0, 0, s);
+        else if (H.smoother == 0) hfsi::level_op<float, OP_JACOBI>(L, v, L.xf.p, L.bf.p, L.tf.p, nullptr, 0, 0, s);
+        else hfsi::level_op<float, OP_CHEB>(L, v, L.xf.p, L.bf.p, L.tf.p, L.rf.p, 0.5f, 0.5f, s);
       }
     };
   } else if (kernel == 2) {
