@@ -212,6 +212,109 @@ __global__ void k_interp_fill(int n, const int* __restrict__ ptr, const int* __r
   }
 }
 
+// The same weights with 16 lanes per row: the C_i list and the numerators
+// live in LDS, the rows of strong F neighbours are scanned lane-parallel
+// (their sums s are tree-reduced; every other sum keeps the row order).
+constexpr int CI_MAX = 64;
+__global__ void __launch_bounds__(256)
+k_interp_fill16(int n, const int* __restrict__ ptr, const int* __restrict__ col, const double* __restrict__ val,
+                const uint8_t* __restrict__ strong, const int8_t* __restrict__ state, const int* __restrict__ comp,
+                const int* __restrict__ cidx, const int* __restrict__ pptr, int* __restrict__ pcol,
+                double* __restrict__ pval, int* __restrict__ overflow) {
+  __shared__ int s_col[16][CI_MAX];
+  __shared__ double s_num[16][CI_MAX];
+  const int g = threadIdx.x >> 4, lane = threadIdx.x & 15;
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  if (i >= n) return;  // whole group
+  const int p0 = pptr[i], p1 = pptr[i + 1], nc = p1 - p0;
+  if (state[i] == ST_C) {
+    if (lane == 0) {
+      pcol[p0] = cidx[i];
+      pval[p0] = 1.0;
+    }
+    return;
+  }
+  if (nc == 0) return;
+  if (nc > CI_MAX) {
+    if (lane == 0) atomicOr(overflow, 1);
+    return;
+  }
+  int* sc = s_col[g];
+  double* sn = s_num[g];
+  const int lo = ptr[i], hi = ptr[i + 1], ci = comp[i];
+  // strong C neighbours in row order (group prefix over 16-entry chunks)
+  double aii = 0.0;
+  int q = 0;
+  const int gshift = (threadIdx.x & 63) & ~15;
+  for (int base = lo; base < hi; base += 16) {
+    const int e = base + lane;
+    bool isc = false;
+    int j = -1;
+    if (e < hi) {
+      j = col[e];
+      if (j == i) aii = val[e];
+      isc = strong[e] && state[j] == ST_C;
+    }
+    const unsigned gm = (unsigned)((__ballot(isc) >> gshift) & 0xFFFFull);
+    if (isc) {
+      const int at = q + __popc(gm & ((1u << lane) - 1u));
+      sc[at] = j;
+      sn[at] = 0.0;
+    }
+    q += __popc(gm);
+  }
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) aii += __shfl_xor(aii, o, 16);
+  double den = aii;
+  for (int e = lo; e < hi; ++e) {
+    const int k = col[e];
+    if (k == i || comp[k] != ci) continue;
+    const double a = val[e];
+    if (strong[e] && state[k] == ST_C) {
+      if (lane == 0) sn[find_in(sc, 0, nc, k)] += a;
+    } else if (strong[e]) {
+      const int klo = ptr[k], khi = ptr[k + 1];
+      double akk = 0.0, s_neg = 0.0, s_pos = 0.0;
+      for (int f = klo + lane; f < khi; f += 16) {
+        const int mm = col[f];
+        const double v = val[f];
+        if (mm == k) akk = v;
+        const int pos = find_in(sc, 0, nc, mm);
+        if (pos < nc && sc[pos] == mm) {
+          if (v < 0.0) s_neg += v;
+          else if (v > 0.0) s_pos += v;
+        }
+      }
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) {
+        akk += __shfl_xor(akk, o, 16);
+        s_neg += __shfl_xor(s_neg, o, 16);
+        s_pos += __shfl_xor(s_pos, o, 16);
+      }
+      const double sk = akk < 0.0 ? -1.0 : 1.0;
+      const double s = sk > 0.0 ? s_neg : s_pos;
+      if (s != 0.0) {
+        for (int f = klo + lane; f < khi; f += 16) {
+          const int mm = col[f];
+          const int pos = find_in(sc, 0, nc, mm);
+          if (pos < nc && sc[pos] == mm) {
+            const double v = val[f];
+            if (v * sk < 0.0) sn[pos] += a * v / s;  // distinct columns: one lane per slot
+          }
+        }
+      } else {
+        den += a;
+      }
+    } else {
+      den += a;
+    }
+  }
+  for (int t = lane; t < nc; t += 16) {
+    pval[p0 + t] = -sn[t] / den;
+    pcol[p0 + t] = cidx[sc[t]];
+  }
+}
+
 // ------------------------------------------------------------ transpose
 __global__ void k_count_cols(int n, const int* __restrict__ ptr, const int* __restrict__ col, int* __restrict__ cnt) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -391,6 +494,63 @@ __global__ void k_dense_from_csr(int n, const int* __restrict__ ptr, const int* 
   double* row = M + (size_t)i * 2 * n;
   for (int j = 0; j < 2 * n; ++j) row[j] = (j == n + i) ? 1.0 : 0.0;
   for (int e = ptr[i]; e < ptr[i + 1]; ++e) row[col[e]] = val[e];
+}
+
+// Pivot step k of Gauss-Jordan with partial pivoting on M = [A | I] (n x 2n):
+// select the row of largest |M_rk|, r >= k (smallest index on ties), swap it
+// into row k and divide the row by its pivot.
+__global__ void __launch_bounds__(256) k_gj_pivot(int n, int k, double* __restrict__ M, int* __restrict__ singular) {
+  __shared__ double rv[256];
+  __shared__ int ri[256];
+  if (*singular) return;
+  const int t = threadIdx.x, w = 2 * n;
+  double best = -1.0;
+  int bi = k;
+  for (int r = k + t; r < n; r += 256) {
+    const double a = fabs(M[(size_t)r * w + k]);
+    if (a > best) { best = a; bi = r; }
+  }
+  rv[t] = best;
+  ri[t] = bi;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o && (rv[t + o] > rv[t] || (rv[t + o] == rv[t] && ri[t + o] < ri[t]))) {
+      rv[t] = rv[t + o];
+      ri[t] = ri[t + o];
+    }
+    __syncthreads();
+  }
+  const int p = ri[0];
+  if (!(rv[0] > 0.0)) {
+    if (t == 0) *singular = 1;
+    return;
+  }
+  const double ip = 1.0 / M[(size_t)p * w + k];
+  __syncthreads();
+  for (int j = k + t; j < w; j += 256) {
+    const double xk = M[(size_t)k * w + j], xp = M[(size_t)p * w + j];
+    M[(size_t)k * w + j] = xp * ip;
+    if (p != k) M[(size_t)p * w + j] = xk;
+  }
+}
+
+// M_rj -= M_rk M_kj for r != k, j > k (column k itself is never read again)
+__global__ void k_gj_elim(int n, int k, double* __restrict__ M, const int* __restrict__ singular) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long cols = 2L * n - k - 1;
+  if (t >= (long)n * cols || *singular) return;
+  const int r = (int)(t / cols);
+  const int j = k + 1 + (int)(t - (long)r * cols);
+  if (r == k) return;
+  const size_t w = 2 * (size_t)n;
+  M[r * w + j] -= M[r * w + k] * M[k * w + j];
+}
+
+__global__ void k_gj_extract(int n, const double* __restrict__ M, double* __restrict__ inv) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)n * n) return;
+  const int r = (int)(t / n), j = (int)(t % n);
+  inv[t] = M[(size_t)r * 2 * n + n + j];
 }
 
 // Gauss-Jordan elimination with partial pivoting in one workgroup.
@@ -781,9 +941,18 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
     L.P.nnz = exclusive_scan(cnt.p, L.P.ptr.p, n + 1, s);
     L.P.col.ensure(L.P.nnz);
     L.P.val.ensure(L.P.nnz);
-    k_interp_fill<<<div_up(n, 128), 128, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p, L.state.p, L.comp.p,
-                                                 L.cidx.p, L.P.ptr.p, L.P.col.p, L.P.val.p);
-    HIP_LAUNCH_CHECK();
+    {
+      DevBuf<int> ovf;
+      ovf.zero(1, s);
+      k_interp_fill16<<<div_up((long)n * 16, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p,
+                                                                 L.state.p, L.comp.p, L.cidx.p, L.P.ptr.p, L.P.col.p,
+                                                                 L.P.val.p, ovf.p);
+      HIP_LAUNCH_CHECK();
+      int o = 0;
+      HIP_CHECK(hipMemcpyAsync(&o, ovf.p, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_CHECK(hipStreamSynchronize(s));
+      if (o) fail(HFSI_E_CAPACITY, "interpolation: a row has more than 64 strong C neighbours");
+    }
     if (l == 0 && prm.interp == 1) learned_correction(c, L);
     transpose(c, L.P, L.R);
     // Galerkin product
@@ -825,7 +994,14 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
   H.cwork.ensure(2 * (size_t)nc);
   k_dense_from_csr<<<div_up(nc, 256), 256, 0, s>>>(nc, Lc.A.ptr.p, Lc.A.col.p, Lc.A.val.p, M.p);
   HIP_LAUNCH_CHECK();
-  k_gauss_jordan<<<1, 1024, 0, s>>>(nc, M.p, H.coarse_inv.p, sing.p);
+  // Gauss-Jordan on [A | I]: per pivot, one block selects and normalises the
+  // pivot row, then the whole grid eliminates the pivot column elsewhere.
+  for (int k = 0; k < nc; ++k) {
+    k_gj_pivot<<<1, 256, 0, s>>>(nc, k, M.p, sing.p);
+    const long work = (long)nc * (2L * nc - k - 1);
+    if (work > 0) k_gj_elim<<<div_up(work, 256), 256, 0, s>>>(nc, k, M.p, sing.p);
+  }
+  k_gj_extract<<<div_up((long)nc * nc, 256), 256, 0, s>>>(nc, M.p, H.coarse_inv.p);
   HIP_LAUNCH_CHECK();
   HIP_CHECK(hipEventRecord(c->ev1, s));
   int sg = 0;
