@@ -377,7 +377,8 @@ __global__ void __launch_bounds__(64)
 k_spgemm(int n, const int* __restrict__ ap, const int* __restrict__ ac, const double* __restrict__ av,
          const int* __restrict__ bp, const int* __restrict__ bc, const double* __restrict__ bv,
          const int* __restrict__ sel, int sel_lo, int sel_hi, int* __restrict__ cnt, const int* __restrict__ cp,
-         int* __restrict__ cc, double* __restrict__ cv, int* __restrict__ overflow) {
+         int* __restrict__ cc, double* __restrict__ cv, int* __restrict__ overflow, const int* __restrict__ ubv,
+         int ub_min) {
   __shared__ int keys[TBL];
   __shared__ double vals[NUMERIC ? TBL : 1];
   __shared__ int ckeys[NUMERIC ? (TBL * 3) / 4 + 64 : 1];
@@ -385,7 +386,7 @@ k_spgemm(int n, const int* __restrict__ ap, const int* __restrict__ ac, const do
   const int lane = threadIdx.x;
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
     const int s = sel[i];
-    if (s < sel_lo || s > sel_hi) continue;
+    if (s < sel_lo || s > sel_hi || ubv[i] <= ub_min) continue;
     // table of T = pow2 >= 2 s slots (s = upper bound or exact count of the row)
     int T = 64;
     while (T < 2 * s && T < TBL) T <<= 1;
@@ -442,6 +443,164 @@ k_spgemm(int n, const int* __restrict__ ap, const int* __restrict__ ac, const do
     const int nk = ninsert;
     const int base = cp[i];
     if (nk != cp[i + 1] - base || nk > (TBL * 3) / 4 + 64) {
+      if (lane == 0) atomicOr(overflow, 2);
+      __syncthreads();
+      continue;
+    }
+    for (int t = lane; t < T; t += 64) {
+      const int key = keys[t];
+      if (key < 0) continue;
+      int r = 0;
+      for (int u = 0; u < nk; ++u) r += ckeys[u] < key ? 1 : 0;
+      cc[base + r] = key;
+      cv[base + r] = vals[t];
+    }
+    __syncthreads();
+  }
+}
+
+// Rows whose product list has ub <= SMAX entries: stage the list in LDS first
+// (lanes in parallel: compacted entries of A_i with non-empty B rows, their
+// offsets, then every (column, a_ik b_kj) pair), insert the columns into a
+// hash table, and accumulate the values entry by entry of A_i in ascending
+// order from LDS — the same summation order as the unstaged kernel.
+template <int SMAX, bool NUMERIC>
+__global__ void __launch_bounds__(64)
+k_spgemm_staged(int n, const int* __restrict__ ap, const int* __restrict__ ac, const double* __restrict__ av,
+                const int* __restrict__ bp, const int* __restrict__ bc, const double* __restrict__ bv,
+                const int* __restrict__ ub, int ub_lo, int* __restrict__ cnt, const int* __restrict__ cp,
+                int* __restrict__ cc, double* __restrict__ cv, int* __restrict__ overflow) {
+  __shared__ int e_k[SMAX], e_off[SMAX + 1];
+  __shared__ double e_a[NUMERIC ? SMAX : 1];
+  __shared__ int f_j[SMAX];
+  __shared__ double f_v[NUMERIC ? SMAX : 1];
+  __shared__ int keys[2 * SMAX];
+  __shared__ double vals[NUMERIC ? 2 * SMAX : 1];
+  __shared__ int ckeys[NUMERIC ? SMAX : 1];
+  __shared__ int ne_sh, nk_sh;
+  const int lane = threadIdx.x;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const int U = ub[i];
+    if (U < ub_lo || U > SMAX) continue;
+    if (U == 0) {
+      if (!NUMERIC && lane == 0) cnt[i] = 0;
+      continue;
+    }
+    // 1. compacted entries with their product offsets (wave prefix sums)
+    int run_off = 0, run_ne = 0;
+    for (int base = ap[i]; base < ap[i + 1]; base += 64) {
+      const int e = base + lane;
+      int k = 0, len = 0;
+      if (e < ap[i + 1]) {
+        k = ac[e];
+        len = bp[k + 1] - bp[k];
+      }
+      int inc = len;  // inclusive scan of len over the wave
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+      }
+      const unsigned long long fm = __ballot(len > 0);
+      const int pos = run_ne + __popcll(fm & ((1ull << lane) - 1ull));
+      if (len > 0) {
+        e_k[pos] = k;
+        e_off[pos] = run_off + inc - len;
+        if (NUMERIC) e_a[pos] = av[e];
+      }
+      run_off += __shfl(inc, 63, 64);
+      run_ne += __popcll(fm);
+    }
+    if (lane == 0) {
+      e_off[run_ne] = run_off;
+      ne_sh = run_ne;
+      nk_sh = 0;
+    }
+    int T = 64;
+    while (T < 2 * U) T <<= 1;
+    const int mask = T - 1;
+    for (int t = lane; t < T; t += 64) {
+      keys[t] = -1;
+      if (NUMERIC) vals[t] = 0.0;
+    }
+    __syncthreads();
+    const int ne = ne_sh;
+    // 2. the (column, value) pairs, lane-parallel over the whole list, four
+    //    independent pairs per lane and step so that their loads overlap
+    for (int t0 = lane; t0 < U; t0 += 256) {
+      int qq[4], ee[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int t = t0 + 64 * u;
+        qq[u] = -1;
+        if (t < U) {
+          int lo = 0, hi = ne - 1;  // last entry with e_off <= t
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (e_off[mid] <= t) lo = mid; else hi = mid - 1;
+          }
+          ee[u] = lo;
+          qq[u] = bp[e_k[lo]] + (t - e_off[lo]);
+        }
+      }
+      int jj[4];
+      double vv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (qq[u] >= 0) {
+          jj[u] = bc[qq[u]];
+          if (NUMERIC) vv[u] = bv[qq[u]];
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (qq[u] >= 0) {
+          f_j[t0 + 64 * u] = jj[u];
+          if (NUMERIC) f_v[t0 + 64 * u] = e_a[ee[u]] * vv[u];
+        }
+    }
+    __syncthreads();
+    // 3. hash insertion; f_j[t] becomes the slot of pair t
+    bool bad = false;
+    for (int t = lane; t < U; t += 64) {
+      const int j = f_j[t];
+      unsigned h = hslot(j, mask);
+      int probes = 0;
+      while (true) {
+        const int old = atomicCAS(&keys[h], -1, j);
+        if (old == -1) {
+          if (!NUMERIC) atomicAdd(&nk_sh, 1);
+          break;
+        }
+        if (old == j) break;
+        h = (h + 1) & mask;
+        if (++probes >= T) { bad = true; break; }
+      }
+      f_j[t] = (int)h;
+    }
+    if (bad) atomicOr(overflow, 1);
+    __syncthreads();
+    if (!NUMERIC) {
+      if (lane == 0) cnt[i] = nk_sh;
+      __syncthreads();
+      continue;
+    }
+    // 4. accumulate entry by entry (distinct columns within one entry)
+    for (int e = 0; e < ne; ++e) {
+      for (int t = e_off[e] + lane; t < e_off[e + 1]; t += 64) vals[f_j[t]] += f_v[t];
+      __syncthreads();
+    }
+    // 5. compact the keys and place every entry by its rank
+    for (int t = lane; t < T; t += 64) {
+      const int key = keys[t];
+      if (key >= 0) {
+        const int pos = atomicAdd(&nk_sh, 1);
+        if (pos < SMAX) ckeys[pos] = key;
+      }
+    }
+    __syncthreads();
+    const int nk = nk_sh;
+    const int base = cp[i];
+    if (nk != cp[i + 1] - base || nk > SMAX) {
       if (lane == 0) atomicOr(overflow, 2);
       __syncthreads();
       continue;
@@ -793,14 +952,16 @@ void spgemm(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>
   flag.zero(1, s);
   k_spgemm_ub<<<div_up(n, 256), 256, 0, s>>>(n, A.ptr.p, A.col.p, B.ptr.p, ub.p);
   HIP_LAUNCH_CHECK();
-  constexpr int TS = 2048, TL = 8192;
+  constexpr int TS = 2048, TL = 8192, S1 = 512, S2 = 1024;
   const int grid = std::min(n, 1 << 16);
-  // symbolic: rows with ub <= 3/4 TS use the small table, others the large one
-  k_spgemm<TS, false><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, nullptr, B.ptr.p, B.col.p, nullptr, ub.p, 0,
-                                          TS * 3 / 4, cnt.p, nullptr, nullptr, nullptr, flag.p);
-  HIP_LAUNCH_CHECK();
-  k_spgemm<TL, false><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, nullptr, B.ptr.p, B.col.p, nullptr, ub.p,
-                                          TS * 3 / 4 + 1, INT32_MAX, cnt.p, nullptr, nullptr, nullptr, flag.p);
+  // symbolic: staged kernels for product lists up to S2 entries, the
+  // unstaged large-table kernel for longer ones
+  k_spgemm_staged<S1, false><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, nullptr, B.ptr.p, B.col.p, nullptr, ub.p, 0,
+                                                 cnt.p, nullptr, nullptr, nullptr, flag.p);
+  k_spgemm_staged<S2, false><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, nullptr, B.ptr.p, B.col.p, nullptr, ub.p,
+                                                 S1 + 1, cnt.p, nullptr, nullptr, nullptr, flag.p);
+  k_spgemm<TL, false><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, nullptr, B.ptr.p, B.col.p, nullptr, ub.p, S2 + 1,
+                                          INT32_MAX, cnt.p, nullptr, nullptr, nullptr, flag.p, ub.p, S2);
   HIP_LAUNCH_CHECK();
   Cm.ptr.ensure(n + 1);
   int64_t nnz = exclusive_scan(cnt.p, Cm.ptr.p, n + 1, s);
@@ -812,12 +973,16 @@ void spgemm(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>
   Cm.nnz = nnz;
   Cm.col.ensure(nnz);
   Cm.val.ensure(nnz);
-  // numeric: dispatch on the exact row count
-  k_spgemm<TS, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 0,
-                                         TS * 3 / 4, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p);
-  HIP_LAUNCH_CHECK();
+  // numeric: the unstaged kernels by exact count (measured faster than the
+  // staged numeric variant, whose per-row latency chain is no shorter)
+  // (a 512-slot table for short rows keeps many more rows in flight per CU)
+  k_spgemm<512, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 0,
+                                          384, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p, ub.p, -1);
+  k_spgemm<TS, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 385,
+                                         TS * 3 / 4, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p, ub.p, -1);
   k_spgemm<TL, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p,
-                                         TS * 3 / 4 + 1, TL * 3 / 4, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p);
+                                         TS * 3 / 4 + 1, TL * 3 / 4, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p,
+                                         ub.p, -1);
   HIP_LAUNCH_CHECK();
   HIP_CHECK(hipMemcpyAsync(&fl, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipStreamSynchronize(s));
