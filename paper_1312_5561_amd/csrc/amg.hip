@@ -976,7 +976,9 @@ void spgemm(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>
   // numeric: the unstaged kernels by exact count (measured faster than the
   // staged numeric variant, whose per-row latency chain is no shorter)
   // (a 512-slot table for short rows keeps many more rows in flight per CU)
-  k_spgemm<512, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 0,
+  k_spgemm<256, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 0,
+                                          192, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p, ub.p, -1);
+  k_spgemm<512, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 193,
                                           384, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p, ub.p, -1);
   k_spgemm<TS, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 385,
                                          TS * 3 / 4, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p, ub.p, -1);
