@@ -191,9 +191,9 @@ def main():
     ms, nbytes = ctx.time_kernel(0, args.roofline_reps)
     achieved = nbytes / (ms * 1e-3) / 1e9
     sweep = "l1-Jacobi sweep (OP_JACOBI)" if args.smoother == 0 else "Chebyshev step (OP_CHEB)"
-    roof = {"kernel": f"level-0 {sweep}, fp32 CSR, k_csr<float,16,...>", "bound": "hbm",
+    roof = {"kernel": f"level-0 {sweep}, fp32 3x3 node blocks, k_b3<float,...>", "bound": "hbm",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic("k_csr<float,16,4>") if args.smoother == 1 else None,
+            "traffic": measured_traffic("k_b3<float,4>") if args.smoother == 1 else None,
             "avg_us": ms * 1e3, "bytes_per_launch": nbytes}
     extra = {}
     for kid, name in ((1, "level-0 residual fp32"), (2, "tangent SpMV fp64 4x4 blocks"), (3, "element assembly")):
