@@ -326,9 +326,16 @@ hfsi_status hfsi_amg_convergence_factor(hfsi_ctx* ctx, int32_t cycles, uint64_t 
  * *avg_ms and the algorithmic bytes one launch must move in *bytes (the
  * minimum traffic of its inputs and outputs).  kernel:
  *   0 = level-0 smoother sweep (hierarchy precision), 1 = level-0 residual,
+ *   100 + l = smoother sweep on level l, 200 + l = residual on level l
+ *   (HFSI_E_ARG if the hierarchy has no level l),
  *   2 = tangent SpMV y = K x (fp64 4x4 blocks), 3 = element assembly
  *   (all colours), 9 = plain device copy of `bytes_hint` bytes (counter
  *   calibration).  Needs the state the kernel reads (assembled K, hierarchy).
+ * For kernels 0, 1, 2, 100 + l and 200 + l with bytes_hint > 0, consecutive
+ * launches cycle through copies of the operator (temporary device memory)
+ * that together hold at least bytes_hint bytes (at most 16 copies): above the
+ * 256 MB last-level cache each launch then reads its operator from HBM.
+ * bytes_hint = 0 times repeated launches on the one operator.
  * Work buffers are context-owned; results are discarded, except that kernel
  * 3 leaves the zero-state tangent in the context (assemble again after it). */
 hfsi_status hfsi_time_kernel(hfsi_ctx* ctx, int32_t kernel, int32_t reps, int64_t bytes_hint, double* avg_ms,

@@ -419,6 +419,18 @@ void level_op(Level& L, const LevelView<T>& v, const T* x, const T* b, T* y, T* 
   }
 }
 
+// algorithmic bytes of one smoother step (resid = false) or residual on level
+// L: the operator once, plus per row the vectors the step reads and writes
+// (Chebyshev: x_i, b, D^-1, d read, d and y written; Jacobi: x_i, b, D^-1
+// read, y written; residual: b read, y written)
+double level_op_bytes(const hfsi_ctx* c, const Level& L, bool resid) {
+  const Hierarchy& H = c->H;
+  const double ts = H.precision == 1 ? 4.0 : 8.0;
+  const double per_row = resid ? 2.0 * ts : (H.smoother == 1 ? 6.0 * ts : 4.0 * ts);
+  if (L.bptr) return (double)c->nb * (9.0 * ts + 4.0) + (double)L.nbr * 4.0 + L.n * per_row;
+  return (double)L.A.nnz * (ts + 4.0) + L.n * (4.0 + per_row);
+}
+
 // smoothing sweeps on level L; x holds the current iterate (in buffer xa),
 // returns the buffer that holds the result (xa or xb).
 template <class T>
@@ -545,6 +557,10 @@ void precond_apply(hfsi_ctx* c, const double* r, double* z) {
   }
   HIP_LAUNCH_CHECK();
 }
+
+// algorithmic bytes of one tangent SpMV: the fp64 4x4 blocks and their column
+// indices, the row pointer, x and y
+double tangent_bytes(const hfsi_ctx* c) { return (double)c->nb * (128.0 + 4.0) + (double)c->n * (4.0 + 32.0 + 32.0); }
 
 void tangent_apply(hfsi_ctx* c, const double* x, double* y) {
   k_bsr4<OP_SPMV><<<div_up((long)c->n * 16, 256), 256, 0, c->stream>>>(c->n, c->nptr.p, c->ncol.p, c->Kval.p, x,
@@ -811,6 +827,39 @@ __global__ void k_copy4(long n4, const float4* __restrict__ x, float4* __restric
 }
 }  // namespace
 
+namespace hfsi {
+namespace {
+
+// one smoother step (Chebyshev or Jacobi, as the hierarchy) or residual on
+// level L with the operator arrays given explicitly (timing copies)
+template <class T>
+void time_level_op(hfsi_ctx* c, Level& L, bool blk, bool resid, const int* ptr, const int* col, const T* val) {
+  Hierarchy& H = c->H;
+  hipStream_t s = c->stream;
+  LevelView<T> v = view<T>(L, false);
+  T* x = v.x;
+  T* bb = v.b;
+  T* y = resid ? v.r : v.t;
+  T* d = resid ? nullptr : v.r;
+  const int op = resid ? OP_RESID : (H.smoother == 0 ? OP_JACOBI : OP_CHEB);
+  const T c1 = op == OP_CHEB ? (T)0.5 : (T)0, c2 = op == OP_CHEB ? (T)0.5 : (T)0;
+  if (blk) {
+    const int grid = div_up((long)L.nbr * 8, 256);
+    if (op == OP_RESID) k_b3<T, OP_RESID><<<grid, 256, 0, s>>>(L.nbr, ptr, col, val, x, bb, v.dinv, y, d, c1, c2);
+    else if (op == OP_JACOBI) k_b3<T, OP_JACOBI><<<grid, 256, 0, s>>>(L.nbr, ptr, col, val, x, bb, v.dinv, y, d, c1, c2);
+    else k_b3<T, OP_CHEB><<<grid, 256, 0, s>>>(L.nbr, ptr, col, val, x, bb, v.dinv, y, d, c1, c2);
+    HIP_LAUNCH_CHECK();
+  } else {
+    const int G = lanes_for(L.A.nnz, L.n);
+    if (op == OP_RESID) csr_launch<T, OP_RESID>(G, L.n, ptr, col, val, x, bb, v.dinv, y, d, c1, c2, s);
+    else if (op == OP_JACOBI) csr_launch<T, OP_JACOBI>(G, L.n, ptr, col, val, x, bb, v.dinv, y, d, c1, c2, s);
+    else csr_launch<T, OP_CHEB>(G, L.n, ptr, col, val, x, bb, v.dinv, y, d, c1, c2, s);
+  }
+}
+
+}  // namespace
+}  // namespace hfsi
+
 extern "C" hfsi_status hfsi_time_kernel(hfsi_ctx* c, int32_t kernel, int32_t reps, int64_t bytes_hint, double* avg_ms,
                                         double* bytes) {
   HFSI_ABI_BEGIN(c)
@@ -820,30 +869,49 @@ extern "C" hfsi_status hfsi_time_kernel(hfsi_ctx* c, int32_t kernel, int32_t rep
   std::function<void()> launch;
   double b = 0.0;
   hfsi::DevBuf<char> tmp;
-  if (kernel == 0 || kernel == 1) {
+  long rot = 0;
+  // With bytes_hint > 0 consecutive launches read different copies of the
+  // operator, together at least bytes_hint bytes (at most 16 copies): above
+  // the 256 MB last-level cache each launch reads its operator from HBM, as
+  // a kernel does inside a solve when other data streams between two of its
+  // launches.  bytes_hint = 0: one copy, launches reuse the cache.
+  if (kernel != 9 && bytes_hint < 0) fail(HFSI_E_ARG, "time_kernel: negative bytes_hint");
+  auto copies_for = [bytes_hint](double op_bytes) {
+    return std::max(1, std::min(16, (int)std::ceil((double)bytes_hint / std::max(op_bytes, 1.0))));
+  };
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const bool level_kernel = kernel == 0 || kernel == 1 || (kernel >= 100 && kernel < 300);
+  if (level_kernel) {
     if (!H.ready) fail(HFSI_E_ORDER, "time_kernel: no hierarchy");
-    hfsi::Level& L = H.L[0];
-    const int n = L.n;
-    const double ts = H.precision == 1 ? 4.0 : 8.0;
-    // per scalar row: Chebyshev reads x_i, b, D^-1, d and writes d, y; Jacobi
-    // reads x_i, b, D^-1 and writes y; the residual reads b and writes y
-    const double per_row = kernel == 1 ? 2.0 * ts : (H.smoother == 1 ? 6.0 * ts : 4.0 * ts);
-    if (L.bptr)  // 3x3 node blocks: 9 values + one column index per block, one pointer per node row
-      b = (double)c->nb * (9.0 * ts + 4.0) + (double)L.nbr * 4.0 + n * per_row;
-    else
-      b = (double)L.A.nnz * (ts + 4.0) + n * (4.0 + per_row);
-    launch = [&, kernel]() {
-      if (H.precision == 0) {
-        auto v = hfsi::view<double>(L, false);
-        if (kernel == 1) hfsi::level_op<double, OP_RESID>(L, v, L.x.p, L.b.p, L.r.p, nullptr, 0, 0, s);
-        else if (H.smoother == 0) hfsi::level_op<double, OP_JACOBI>(L, v, L.x.p, L.b.p, L.t.p, nullptr, 0, 0, s);
-        else hfsi::level_op<double, OP_CHEB>(L, v, L.x.p, L.b.p, L.t.p, L.r.p, 0.5, 0.5, s);
-      } else {
-        auto v = hfsi::view<float>(L, false);
-        if (kernel == 1) hfsi::level_op<float, OP_RESID>(L, v, L.xf.p, L.bf.p, L.rf.p, nullptr, 0, 0, s);
-        else if (H.smoother == 0) hfsi::level_op<float, OP_JACOBI>(L, v, L.xf.p, L.bf.p, L.tf.p, nullptr, 0, 0, s);
-        else hfsi::level_op<float, OP_CHEB>(L, v, L.xf.p, L.bf.p, L.tf.p, L.rf.p, 0.5f, 0.5f, s);
-      }
+    const bool resid = kernel == 1 || kernel >= 200;
+    const int lev = kernel < 100 ? 0 : kernel % 100;
+    if (lev >= (int)H.L.size()) fail(HFSI_E_ARG, "time_kernel: no such level");
+    hfsi::Level& L = H.L[lev];
+    b = hfsi::level_op_bytes(c, L, resid);
+    const bool f32 = H.precision == 1;
+    const size_t ts = f32 ? 4 : 8;
+    const bool blk = L.bptr != nullptr;
+    const size_t np = blk ? L.nbr + 1 : L.n + 1, nc = blk ? c->nb : L.A.nnz, nv = blk ? 9 * (size_t)c->nb : L.A.nnz;
+    const int* ptr0 = blk ? L.bptr : L.A.ptr.p;
+    const int* col0 = blk ? L.bcol : L.A.col.p;
+    const void* val0 = blk ? (f32 ? (const void*)L.b3f.p : (const void*)L.b3d.p)
+                           : (f32 ? (const void*)L.A32.p : (const void*)L.A.val.p);
+    const size_t stride = al(4 * np) + al(4 * nc) + al(ts * nv);
+    const int ncp = copies_for((double)stride);
+    tmp.ensure(stride * ncp);
+    for (int k = 0; k < ncp; ++k) {
+      char* base = tmp.p + stride * k;
+      HIP_CHECK(hipMemcpyAsync(base, ptr0, 4 * np, hipMemcpyDeviceToDevice, s));
+      HIP_CHECK(hipMemcpyAsync(base + al(4 * np), col0, 4 * nc, hipMemcpyDeviceToDevice, s));
+      HIP_CHECK(hipMemcpyAsync(base + al(4 * np) + al(4 * nc), val0, ts * nv, hipMemcpyDeviceToDevice, s));
+    }
+    launch = [&, resid, blk, f32, stride, ncp, np, nc]() {
+      char* base = tmp.p + stride * (rot++ % ncp);
+      const int* ptr = (const int*)base;
+      const int* col = (const int*)(base + al(4 * np));
+      const void* val = base + al(4 * np) + al(4 * nc);
+      if (f32) hfsi::time_level_op<float>(c, L, blk, resid, ptr, col, (const float*)val);
+      else hfsi::time_level_op<double>(c, L, blk, resid, ptr, col, (const double*)val);
     };
   } else if (kernel == 2) {
     require_stage(c, 4, "time_kernel");
@@ -851,8 +919,24 @@ extern "C" hfsi_status hfsi_time_kernel(hfsi_ctx* c, int32_t kernel, int32_t rep
     c->kw.ensure(N);
     c->kr.ensure(N);
     HIP_CHECK(hipMemsetAsync(c->kw.p, 0, sizeof(double) * N, s));
-    b = (double)c->nb * (128.0 + 4.0) + (double)c->n * (4.0 + 32.0 + 32.0);
-    launch = [&]() { tangent_apply(c, c->kw.p, c->kr.p); };
+    b = hfsi::tangent_bytes(c);
+    const size_t np = c->n + 1, nc = c->nb, nv = 16 * (size_t)c->nb;
+    const size_t stride = al(4 * np) + al(4 * nc) + al(8 * nv);
+    const int ncp = copies_for((double)stride);
+    tmp.ensure(stride * ncp);
+    for (int k = 0; k < ncp; ++k) {
+      char* base = tmp.p + stride * k;
+      HIP_CHECK(hipMemcpyAsync(base, c->nptr.p, 4 * np, hipMemcpyDeviceToDevice, s));
+      HIP_CHECK(hipMemcpyAsync(base + al(4 * np), c->ncol.p, 4 * nc, hipMemcpyDeviceToDevice, s));
+      HIP_CHECK(hipMemcpyAsync(base + al(4 * np) + al(4 * nc), c->Kval.p, 8 * nv, hipMemcpyDeviceToDevice, s));
+    }
+    launch = [&, stride, ncp, np, nc]() {
+      char* base = tmp.p + stride * (rot++ % ncp);
+      k_bsr4<OP_SPMV><<<div_up((long)c->n * 16, 256), 256, 0, s>>>(
+          c->n, (const int*)base, (const int*)(base + al(4 * np)), (const double*)(base + al(4 * np) + al(4 * nc)),
+          c->kw.p, nullptr, c->kr.p);
+      HIP_LAUNCH_CHECK();
+    };
   } else if (kernel == 3) {
     require_stage(c, 4, "time_kernel");
     b = hfsi::assembly_bytes(c);

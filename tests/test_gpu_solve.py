@@ -128,3 +128,24 @@ def test_newton_load_run_matches_oracle(lib):
     vg = v.cpu().numpy()
     assert np.linalg.norm(vg - vo) <= 1e-9 * np.linalg.norm(vo)
     assert all(3 <= k <= 6 for k in its), its
+
+
+def test_time_kernel_levels_and_errors(lib):
+    """Per-level timing ids: CSR levels report 8 B per entry plus 28 B per row
+    for an fp32 Chebyshev step (row pointer, x_i, b, D^-1, d read and written,
+    y) and 4 + 8 B per row for the residual; rotating operator copies leaves the
+    byte count unchanged; unknown levels and negative sizes are errors."""
+    prob = synth.cube_problem(6)
+    print("[time_kernel] cube6", flush=True)
+    ctx, R, info, oprm = _setup(lib, prob, np.zeros(prob.n_dofs), 1.0, smoother=1, precision=1, max_coarse=60)
+    assert info.levels >= 3
+    for lev in range(1, info.levels):
+        ms, b = ctx.time_kernel(100 + lev, 3)
+        assert ms > 0.0 and b == info.nnz[lev] * 8 + info.rows[lev] * 28
+        ms, b2 = ctx.time_kernel(200 + lev, 3, 1 << 20)
+        assert ms > 0.0 and b2 == info.nnz[lev] * 8 + info.rows[lev] * 12
+    assert ctx.time_kernel(0, 2)[1] == ctx.time_kernel(100, 2, 1 << 22)[1]
+    with pytest.raises(Exception):
+        ctx.time_kernel(100 + info.levels, 1)
+    with pytest.raises(Exception):
+        ctx.time_kernel(2, 1, -1)
