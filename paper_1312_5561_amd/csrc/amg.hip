@@ -12,6 +12,7 @@
 //  * l1-Jacobi diagonal or D^{-1} with a Lanczos estimate for Chebyshev
 //  * coarsest level: explicit inverse by Gauss-Jordan with partial pivoting
 #include <algorithm>
+#include <climits>
 #include <cmath>
 
 #include "common.hpp"
@@ -855,6 +856,45 @@ __global__ void k_tridiag_max(int k, const double* __restrict__ alpha, const dou
   out[0] = 0.5 * (lo + hi);
 }
 
+
+// ----------------------------------------------- padded CSR for the cycle
+// per row: number of 4-entry chunks, smallest column, and whether the row
+// spans more than 16 bits of columns
+__global__ void k_pack_count(int n, const int* __restrict__ ptr, const int* __restrict__ col, int* __restrict__ chunks,
+                             int* __restrict__ base, int* __restrict__ wide) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int a = ptr[r], e = ptr[r + 1];
+  int mn = INT_MAX, mx = INT_MIN;
+  for (int k = a; k < e; ++k) {
+    mn = min(mn, col[k]);
+    mx = max(mx, col[k]);
+  }
+  chunks[r] = (e - a + 3) / 4;
+  base[r] = e > a ? mn : 0;
+  if (e > a && mx - mn > 65535) atomicOr(wide, 1);
+}
+
+// one wavefront per row: copy values and columns into the padded layout
+template <class T>
+__global__ void k_pack_fill(int n, const int* __restrict__ ptr, const int* __restrict__ col, const T* __restrict__ val,
+                            const int* __restrict__ p4, const int* __restrict__ base, int wide,
+                            uint16_t* __restrict__ c16, int* __restrict__ c32, T* __restrict__ out) {
+  const int r = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (r >= n) return;
+  const int a = ptr[r], len = ptr[r + 1] - a;
+  const long o = 4L * p4[r];
+  const int padded = 4 * (p4[r + 1] - p4[r]);
+  const int b = base[r];
+  for (int k = lane; k < padded; k += 64) {
+    const bool real = k < len;
+    out[o + k] = real ? val[a + k] : (T)0;
+    const int cc = real ? col[a + k] : b;
+    if (wide) c32[o + k] = cc;
+    else c16[o + k] = (uint16_t)(cc - b);
+  }
+}
 }  // namespace
 
 namespace hfsi {
@@ -1010,6 +1050,49 @@ void alloc_vectors(Level& L) {
   L.xf.ensure(L.n); L.bf.ensure(L.n); L.rf.ensure(L.n); L.tf.ensure(L.n);
 }
 
+// padded copy of L.A in the cycle's precision (levels without node blocks)
+void pack_level(hfsi_ctx* c, Level& L, int precision) {
+  hipStream_t s = c->stream;
+  Packed4& K = L.pk;
+  const int n = L.n;
+  K.rows = n;
+  K.p4.ensure(n + 1);
+  K.base.ensure(n);
+  DevBuf<int> wide;
+  wide.zero(1, s);
+  k_pack_count<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, K.p4.p, K.base.p, wide.p);
+  HIP_LAUNCH_CHECK();
+  HIP_CHECK(hipMemsetAsync(K.p4.p + n, 0, sizeof(int), s));
+  K.chunks = exclusive_scan(K.p4.p, K.p4.p, n + 1, s);
+  int w = 0;
+  HIP_CHECK(hipMemcpyAsync(&w, wide.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  K.wide = w != 0;
+  const size_t m = 4 * (size_t)K.chunks;
+  // keep only the arrays of this layout and precision
+  if (K.wide) {
+    K.c32.ensure(m);
+    K.c16.release();
+  } else {
+    K.c16.ensure(m);
+    K.c32.release();
+  }
+  if (precision == 1) K.v64.release();
+  else K.v32.release();
+  const int grid = div_up((long)n * 64, 256);
+  if (precision == 1) {
+    K.v32.ensure(m);
+    k_pack_fill<float><<<grid, 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A32.p, K.p4.p, K.base.p, (int)K.wide, K.c16.p,
+                                            K.c32.p, K.v32.p);
+  } else {
+    K.v64.ensure(m);
+    k_pack_fill<double><<<grid, 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, K.p4.p, K.base.p, (int)K.wide,
+                                             K.c16.p, K.c32.p, K.v64.p);
+  }
+  HIP_LAUNCH_CHECK();
+  L.packed = true;
+}
+
 void copy_csr(hfsi_ctx* c, const Csr<double>& src, Csr<double>& dst) {
   dst.rows = src.rows;
   dst.cols = src.cols;
@@ -1148,6 +1231,11 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
       k_to_f32<<<div_up(L.A.nnz, 256), 256, 0, s>>>(L.A.nnz, L.A.val.p, L.A32.p);
       HIP_LAUNCH_CHECK();
     }
+  // padded operator copies for the smoother and residual
+  for (auto& L : H.L) {
+    L.packed = false;
+    if (!L.bptr) pack_level(c, L, prm.precision);
+  }
   // coarsest level: explicit inverse
   Level& Lc = H.L.back();
   const int nc = Lc.n;

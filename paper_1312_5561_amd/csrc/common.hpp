@@ -92,6 +92,23 @@ struct Csr {
   DevBuf<V> val;
 };
 
+// CSR copy for the smoother and residual of levels without node blocks: each
+// row padded to a multiple of 4 entries (zero values, column offset 0), so a
+// lane reads 4 values and 4 columns with one aligned load each.  Columns are
+// 16-bit offsets from the row's smallest column (`base`) unless some row spans
+// more than 65535 columns (`wide`: absolute int32 columns).
+struct Packed4 {
+  int rows = 0;
+  int64_t chunks = 0;          // padded entries / 4
+  bool wide = false;
+  DevBuf<int> p4;              // [rows+1] first chunk of each row
+  DevBuf<int> base;            // [rows] smallest column of each row
+  DevBuf<uint16_t> c16;        // [4*chunks] column - base
+  DevBuf<int> c32;             // [4*chunks] when wide
+  DevBuf<float> v32;           // [4*chunks] values of the fp32 cycle
+  DevBuf<double> v64;          // [4*chunks] values of the fp64 cycle
+};
+
 // ------------------------------------------------------------- AMG level
 struct Level {
   int n = 0;
@@ -113,6 +130,9 @@ struct Level {
   int nbr = 0;                // node rows
   DevBuf<double> b3d;         // [9 * blocks]
   DevBuf<float> b3f;
+  // other levels: padded copy of A in the cycle's precision
+  bool packed = false;
+  Packed4 pk;
   // V-cycle vectors (fp64 and fp32 variants used according to precision)
   DevBuf<double> x, b, r, t;
   DevBuf<float> xf, bf, rf, tf;

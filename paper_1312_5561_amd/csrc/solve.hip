@@ -65,6 +65,91 @@ void csr_launch(int G, int n, const int* ptr, const int* col, const T* val, cons
   HIP_LAUNCH_CHECK();
 }
 
+// Same operations on the padded CSR copy: G lanes per row, each lane whole
+// 4-entry chunks (one 16-byte value load for fp32, one 8-byte load of 16-bit
+// column offsets, or 16 bytes of int32 columns on wide levels).
+template <class T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  using type = float4;
+};
+template <>
+struct Vec4<double> {
+  using type = double4;
+};
+
+template <class T, int G, int OP, bool WIDE>
+__global__ void __launch_bounds__(256)
+k_csr4(int n, const int* __restrict__ p4, const int* __restrict__ base, const void* __restrict__ cols,
+       const T* __restrict__ val, const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ dinv,
+       T* __restrict__ y, T* __restrict__ d, T c1, T c2) {
+  using V4 = typename Vec4<T>::type;
+  const int gid = (blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  if (gid >= n) return;
+  const int hi = p4[gid + 1];
+  const T* xr = WIDE ? x : x + base[gid];
+  const V4* v4 = reinterpret_cast<const V4*>(val);
+  T s = 0;
+  for (int k = p4[gid] + lane; k < hi; k += G) {
+    const V4 a = v4[k];
+    if (WIDE) {
+      const int4 j = reinterpret_cast<const int4*>(cols)[k];
+      s += a.x * xr[j.x] + a.y * xr[j.y] + a.z * xr[j.z] + a.w * xr[j.w];
+    } else {
+      const ushort4 j = reinterpret_cast<const ushort4*>(cols)[k];
+      s += a.x * xr[j.x] + a.y * xr[j.y] + a.z * xr[j.z] + a.w * xr[j.w];
+    }
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+  if (lane != 0) return;
+  if (OP == OP_SPMV) y[gid] = s;
+  else if (OP == OP_RESID) y[gid] = b[gid] - s;
+  else if (OP == OP_JACOBI) y[gid] = x[gid] + dinv[gid] * (b[gid] - s);
+  else if (OP == OP_ADD) y[gid] += s;
+  else {
+    const T dn = c1 * d[gid] + c2 * dinv[gid] * (b[gid] - s);
+    d[gid] = dn;
+    y[gid] = x[gid] + dn;
+  }
+}
+
+// lanes per row for the padded layout: about 3 chunks per lane, more lanes on
+// small levels so that the launch still spreads over the whole chip
+inline int lanes_for4(int64_t chunks, int rows) {
+  const double avg = rows ? (double)chunks / rows : 1.0;
+  int G = 2;
+  while (G < 64 && 3.0 * G < avg) G *= 2;
+  while (G < 64 && (int64_t)rows * G < 65536) G *= 2;
+  return G;
+}
+
+template <class T, int OP, bool WIDE>
+void csr4_launch_w(int G, int n, const int* p4, const int* base, const void* cols, const T* val, const T* x,
+                   const T* b, const T* dinv, T* y, T* d, T c1, T c2, hipStream_t s) {
+  const int grid = div_up((long)n * G, 256);
+  switch (G) {
+    case 2: k_csr4<T, 2, OP, WIDE><<<grid, 256, 0, s>>>(n, p4, base, cols, val, x, b, dinv, y, d, c1, c2); break;
+    case 4: k_csr4<T, 4, OP, WIDE><<<grid, 256, 0, s>>>(n, p4, base, cols, val, x, b, dinv, y, d, c1, c2); break;
+    case 8: k_csr4<T, 8, OP, WIDE><<<grid, 256, 0, s>>>(n, p4, base, cols, val, x, b, dinv, y, d, c1, c2); break;
+    case 16: k_csr4<T, 16, OP, WIDE><<<grid, 256, 0, s>>>(n, p4, base, cols, val, x, b, dinv, y, d, c1, c2); break;
+    case 32: k_csr4<T, 32, OP, WIDE><<<grid, 256, 0, s>>>(n, p4, base, cols, val, x, b, dinv, y, d, c1, c2); break;
+    default: k_csr4<T, 64, OP, WIDE><<<grid, 256, 0, s>>>(n, p4, base, cols, val, x, b, dinv, y, d, c1, c2); break;
+  }
+  HIP_LAUNCH_CHECK();
+}
+
+template <class T, int OP>
+void csr4_launch(int n, int64_t chunks, bool wide, const int* p4, const int* base, const void* cols, const T* val,
+                 const T* x, const T* b, const T* dinv, T* y, T* d, T c1, T c2, hipStream_t s) {
+  if (n <= 0) return;
+  const int G = lanes_for4(chunks, n);
+  if (wide) csr4_launch_w<T, OP, true>(G, n, p4, base, cols, val, x, b, dinv, y, d, c1, c2, s);
+  else csr4_launch_w<T, OP, false>(G, n, p4, base, cols, val, x, b, dinv, y, d, c1, c2, s);
+}
+
 // Same operations on a 3x3 node-block matrix: 8 lanes per node row, each lane
 // a strided subset of the row's blocks (9 values + one column index), then a
 // shuffle reduction of the three row sums; lanes 0..2 finish rows 3i..3i+2.
@@ -391,6 +476,7 @@ struct LevelView {
   const T* dinv;
   T *x, *t, *b, *r;
   const T* B3;  // 3x3 node blocks of level 0 (or null)
+  const T* PK;  // padded CSR values (or null)
 };
 
 template <class T>
@@ -399,12 +485,12 @@ LevelView<T> view(Level& L, bool last);
 template <>
 LevelView<double> view<double>(Level& L, bool last) {
   return {L.A.val.p, last ? nullptr : L.P.val.p, last ? nullptr : L.R.val.p, L.dinv.p, L.x.p, L.t.p, L.b.p, L.r.p,
-          L.bptr ? L.b3d.p : nullptr};
+          L.bptr ? L.b3d.p : nullptr, L.packed ? L.pk.v64.p : nullptr};
 }
 template <>
 LevelView<float> view<float>(Level& L, bool last) {
   return {L.A32.p, last ? nullptr : L.P32.p, last ? nullptr : L.R32.p, L.dinv32.p, L.xf.p, L.tf.p, L.bf.p, L.rf.p,
-          L.bptr ? L.b3f.p : nullptr};
+          L.bptr ? L.b3f.p : nullptr, L.packed ? L.pk.v32.p : nullptr};
 }
 
 // y = f(A x) on level L with the node-block operator when the level has one
@@ -414,6 +500,10 @@ void level_op(Level& L, const LevelView<T>& v, const T* x, const T* b, T* y, T* 
     k_b3<T, OP><<<div_up((long)L.nbr * 8, 256), 256, 0, s>>>(L.nbr, L.bptr, L.bcol, v.B3, x, b, v.dinv, y, d, c1,
                                                               c2);
     HIP_LAUNCH_CHECK();
+  } else if (v.PK) {
+    const Packed4& K = L.pk;
+    csr4_launch<T, OP>(L.n, K.chunks, K.wide, K.p4.p, K.base.p, K.wide ? (const void*)K.c32.p : (const void*)K.c16.p,
+                       v.PK, x, b, v.dinv, y, d, c1, c2, s);
   } else {
     csr_launch<T, OP>(lanes_for(L.A.nnz, L.n), L.n, L.A.ptr.p, L.A.col.p, v.A, x, b, v.dinv, y, d, c1, c2, s);
   }
@@ -428,6 +518,9 @@ double level_op_bytes(const hfsi_ctx* c, const Level& L, bool resid) {
   const double ts = H.precision == 1 ? 4.0 : 8.0;
   const double per_row = resid ? 2.0 * ts : (H.smoother == 1 ? 6.0 * ts : 4.0 * ts);
   if (L.bptr) return (double)c->nb * (9.0 * ts + 4.0) + (double)L.nbr * 4.0 + L.n * per_row;
+  // padded CSR: values and 16-bit (or 32-bit) columns of every chunk, chunk
+  // pointer and column base per row
+  if (L.packed) return 4.0 * L.pk.chunks * (ts + (L.pk.wide ? 4.0 : 2.0)) + L.n * (8.0 + per_row);
   return (double)L.A.nnz * (ts + 4.0) + L.n * (4.0 + per_row);
 }
 
@@ -831,9 +924,10 @@ namespace hfsi {
 namespace {
 
 // one smoother step (Chebyshev or Jacobi, as the hierarchy) or residual on
-// level L with the operator arrays given explicitly (timing copies)
+// level L with the operator arrays given explicitly (timing copies): a[] are
+// the layout's arrays in the order listed by level_arrays
 template <class T>
-void time_level_op(hfsi_ctx* c, Level& L, bool blk, bool resid, const int* ptr, const int* col, const T* val) {
+void time_level_op(hfsi_ctx* c, Level& L, bool resid, void* const* a) {
   Hierarchy& H = c->H;
   hipStream_t s = c->stream;
   LevelView<T> v = view<T>(L, false);
@@ -843,18 +937,48 @@ void time_level_op(hfsi_ctx* c, Level& L, bool blk, bool resid, const int* ptr, 
   T* d = resid ? nullptr : v.r;
   const int op = resid ? OP_RESID : (H.smoother == 0 ? OP_JACOBI : OP_CHEB);
   const T c1 = op == OP_CHEB ? (T)0.5 : (T)0, c2 = op == OP_CHEB ? (T)0.5 : (T)0;
-  if (blk) {
+  const int* i0 = (const int*)a[0];
+  const int* i1 = (const int*)a[1];
+  if (L.bptr) {
+    const T* val = (const T*)a[2];
     const int grid = div_up((long)L.nbr * 8, 256);
-    if (op == OP_RESID) k_b3<T, OP_RESID><<<grid, 256, 0, s>>>(L.nbr, ptr, col, val, x, bb, v.dinv, y, d, c1, c2);
-    else if (op == OP_JACOBI) k_b3<T, OP_JACOBI><<<grid, 256, 0, s>>>(L.nbr, ptr, col, val, x, bb, v.dinv, y, d, c1, c2);
-    else k_b3<T, OP_CHEB><<<grid, 256, 0, s>>>(L.nbr, ptr, col, val, x, bb, v.dinv, y, d, c1, c2);
+    if (op == OP_RESID) k_b3<T, OP_RESID><<<grid, 256, 0, s>>>(L.nbr, i0, i1, val, x, bb, v.dinv, y, d, c1, c2);
+    else if (op == OP_JACOBI) k_b3<T, OP_JACOBI><<<grid, 256, 0, s>>>(L.nbr, i0, i1, val, x, bb, v.dinv, y, d, c1, c2);
+    else k_b3<T, OP_CHEB><<<grid, 256, 0, s>>>(L.nbr, i0, i1, val, x, bb, v.dinv, y, d, c1, c2);
     HIP_LAUNCH_CHECK();
+  } else if (L.packed) {
+    const Packed4& K = L.pk;
+    const T* val = (const T*)a[3];
+    if (op == OP_RESID) csr4_launch<T, OP_RESID>(L.n, K.chunks, K.wide, i0, i1, a[2], val, x, bb, v.dinv, y, d, c1, c2, s);
+    else if (op == OP_JACOBI) csr4_launch<T, OP_JACOBI>(L.n, K.chunks, K.wide, i0, i1, a[2], val, x, bb, v.dinv, y, d, c1, c2, s);
+    else csr4_launch<T, OP_CHEB>(L.n, K.chunks, K.wide, i0, i1, a[2], val, x, bb, v.dinv, y, d, c1, c2, s);
   } else {
+    const T* val = (const T*)a[2];
     const int G = lanes_for(L.A.nnz, L.n);
-    if (op == OP_RESID) csr_launch<T, OP_RESID>(G, L.n, ptr, col, val, x, bb, v.dinv, y, d, c1, c2, s);
-    else if (op == OP_JACOBI) csr_launch<T, OP_JACOBI>(G, L.n, ptr, col, val, x, bb, v.dinv, y, d, c1, c2, s);
-    else csr_launch<T, OP_CHEB>(G, L.n, ptr, col, val, x, bb, v.dinv, y, d, c1, c2, s);
+    if (op == OP_RESID) csr_launch<T, OP_RESID>(G, L.n, i0, i1, val, x, bb, v.dinv, y, d, c1, c2, s);
+    else if (op == OP_JACOBI) csr_launch<T, OP_JACOBI>(G, L.n, i0, i1, val, x, bb, v.dinv, y, d, c1, c2, s);
+    else csr_launch<T, OP_CHEB>(G, L.n, i0, i1, val, x, bb, v.dinv, y, d, c1, c2, s);
   }
+}
+
+// the operator arrays (pointer, bytes) the smoother of level L reads
+std::vector<std::pair<const void*, size_t>> level_arrays(const hfsi_ctx* c, const Level& L) {
+  const bool f32 = c->H.precision == 1;
+  const size_t ts = f32 ? 4 : 8;
+  if (L.bptr) {
+    const size_t nv = 9 * (size_t)c->nb;
+    return {{L.bptr, 4 * (size_t)(L.nbr + 1)}, {L.bcol, 4 * (size_t)c->nb},
+            {f32 ? (const void*)L.b3f.p : (const void*)L.b3d.p, ts * nv}};
+  }
+  if (L.packed) {
+    const Packed4& K = L.pk;
+    const size_t m = 4 * (size_t)K.chunks;
+    return {{K.p4.p, 4 * (size_t)(L.n + 1)}, {K.base.p, 4 * (size_t)L.n},
+            {K.wide ? (const void*)K.c32.p : (const void*)K.c16.p, (K.wide ? 4 : 2) * m},
+            {f32 ? (const void*)K.v32.p : (const void*)K.v64.p, ts * m}};
+  }
+  return {{L.A.ptr.p, 4 * (size_t)(L.n + 1)}, {L.A.col.p, 4 * (size_t)L.A.nnz},
+          {f32 ? (const void*)L.A32.p : (const void*)L.A.val.p, ts * (size_t)L.A.nnz}};
 }
 
 }  // namespace
@@ -889,29 +1013,27 @@ extern "C" hfsi_status hfsi_time_kernel(hfsi_ctx* c, int32_t kernel, int32_t rep
     hfsi::Level& L = H.L[lev];
     b = hfsi::level_op_bytes(c, L, resid);
     const bool f32 = H.precision == 1;
-    const size_t ts = f32 ? 4 : 8;
-    const bool blk = L.bptr != nullptr;
-    const size_t np = blk ? L.nbr + 1 : L.n + 1, nc = blk ? c->nb : L.A.nnz, nv = blk ? 9 * (size_t)c->nb : L.A.nnz;
-    const int* ptr0 = blk ? L.bptr : L.A.ptr.p;
-    const int* col0 = blk ? L.bcol : L.A.col.p;
-    const void* val0 = blk ? (f32 ? (const void*)L.b3f.p : (const void*)L.b3d.p)
-                           : (f32 ? (const void*)L.A32.p : (const void*)L.A.val.p);
-    const size_t stride = al(4 * np) + al(4 * nc) + al(ts * nv);
+    const auto arr = hfsi::level_arrays(c, L);
+    size_t stride = 0;
+    for (const auto& pa : arr) stride += al(pa.second);
     const int ncp = copies_for((double)stride);
     tmp.ensure(stride * ncp);
     for (int k = 0; k < ncp; ++k) {
-      char* base = tmp.p + stride * k;
-      HIP_CHECK(hipMemcpyAsync(base, ptr0, 4 * np, hipMemcpyDeviceToDevice, s));
-      HIP_CHECK(hipMemcpyAsync(base + al(4 * np), col0, 4 * nc, hipMemcpyDeviceToDevice, s));
-      HIP_CHECK(hipMemcpyAsync(base + al(4 * np) + al(4 * nc), val0, ts * nv, hipMemcpyDeviceToDevice, s));
+      size_t off = stride * k;
+      for (const auto& pa : arr) {
+        HIP_CHECK(hipMemcpyAsync(tmp.p + off, pa.first, pa.second, hipMemcpyDeviceToDevice, s));
+        off += al(pa.second);
+      }
     }
-    launch = [&, resid, blk, f32, stride, ncp, np, nc]() {
-      char* base = tmp.p + stride * (rot++ % ncp);
-      const int* ptr = (const int*)base;
-      const int* col = (const int*)(base + al(4 * np));
-      const void* val = base + al(4 * np) + al(4 * nc);
-      if (f32) hfsi::time_level_op<float>(c, L, blk, resid, ptr, col, (const float*)val);
-      else hfsi::time_level_op<double>(c, L, blk, resid, ptr, col, (const double*)val);
+    launch = [&, arr, resid, f32, stride, ncp]() {
+      void* a[4] = {nullptr, nullptr, nullptr, nullptr};
+      size_t off = stride * (rot++ % ncp);
+      for (size_t i = 0; i < arr.size(); ++i) {
+        a[i] = tmp.p + off;
+        off += al(arr[i].second);
+      }
+      if (f32) hfsi::time_level_op<float>(c, L, resid, a);
+      else hfsi::time_level_op<double>(c, L, resid, a);
     };
   } else if (kernel == 2) {
     require_stage(c, 4, "time_kernel");

@@ -131,19 +131,28 @@ def test_newton_load_run_matches_oracle(lib):
 
 
 def test_time_kernel_levels_and_errors(lib):
-    """Per-level timing ids: CSR levels report 8 B per entry plus 28 B per row
-    for an fp32 Chebyshev step (row pointer, x_i, b, D^-1, d read and written,
-    y) and 4 + 8 B per row for the residual; rotating operator copies leaves the
-    byte count unchanged; unknown levels and negative sizes are errors."""
+    """Per-level timing ids: levels >= 1 run on the padded CSR copy (rows
+    padded to 4 entries, fp32 values and 16-bit column offsets unless a row
+    spans more than 65535 columns), so an fp32 Chebyshev step moves
+    (4 + 2) B per padded entry plus 8 B (chunk pointer, column base) and
+    24 B of vectors per row, the residual 8 B of vectors per row; rotating
+    operator copies leaves the byte count unchanged; unknown levels and
+    negative sizes are errors."""
     prob = synth.cube_problem(6)
     print("[time_kernel] cube6", flush=True)
     ctx, R, info, oprm = _setup(lib, prob, np.zeros(prob.n_dofs), 1.0, smoother=1, precision=1, max_coarse=60)
     assert info.levels >= 3
+    H = gpu_hierarchy_to_oracle(ctx, info, oprm)
     for lev in range(1, info.levels):
+        A = H.levels[lev].A.tocsr()
+        lens = np.diff(A.indptr)
+        padded = int(np.sum(4 * ((lens + 3) // 4)))
+        spans = [A.indices[a:b].max() - A.indices[a:b].min() for a, b in zip(A.indptr[:-1], A.indptr[1:]) if b > a]
+        cb = 4 if max(spans) > 65535 else 2
         ms, b = ctx.time_kernel(100 + lev, 3)
-        assert ms > 0.0 and b == info.nnz[lev] * 8 + info.rows[lev] * 28
+        assert ms > 0.0 and b == padded * (4 + cb) + info.rows[lev] * (8 + 24)
         ms, b2 = ctx.time_kernel(200 + lev, 3, 1 << 20)
-        assert ms > 0.0 and b2 == info.nnz[lev] * 8 + info.rows[lev] * 12
+        assert ms > 0.0 and b2 == padded * (4 + cb) + info.rows[lev] * (8 + 8)
     assert ctx.time_kernel(0, 2)[1] == ctx.time_kernel(100, 2, 1 << 22)[1]
     with pytest.raises(Exception):
         ctx.time_kernel(100 + info.levels, 1)
