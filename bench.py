@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--N", type=int, default=48, help="hexahedra per cube edge")
     ap.add_argument("--kappa", type=float, default=1e4)
     ap.add_argument("--smoother", type=int, default=1, help="0 l1-Jacobi, 1 Chebyshev")
-    ap.add_argument("--restart", type=int, default=200)
+    ap.add_argument("--restart", type=int, default=256)
     ap.add_argument("--max-iter", type=int, default=3000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain fp64 comparison")

@@ -7,9 +7,10 @@
 //    z_p = Stilde^{-1} (B2 z_u - r_p) with Stilde = (1/theta + 1/kappa) diag(M_p)
 //    (eq. lpreschur); B2 is read from the pressure row of the 4x4 blocks of K.
 //  * right-preconditioned FGMRES(m): classical Gram-Schmidt with one
-//    re-orthogonalisation, Givens rotations on the device, one host
-//    synchronisation per iteration for the convergence test, true residual
-//    recomputed after every cycle.
+//    re-orthogonalisation in three passes over the basis (projection; update
+//    fused with the second projection; second update fused with the norm),
+//    Givens rotations on the device, one host synchronisation per iteration
+//    for the convergence test, true residual recomputed after every cycle.
 #include <algorithm>
 #include <cmath>
 #include <functional>
@@ -287,30 +288,6 @@ k_pl_combine(int n, const int* __restrict__ bptr, const int* __restrict__ bcol, 
 // ---- Krylov vector kernels
 constexpr int RED_BLOCKS = 512;
 
-// partial dot products of up to 8 basis vectors with w per block
-__global__ void __launch_bounds__(256)
-k_mdot(long N, int k, const double* __restrict__ V, long ldv, const double* __restrict__ w, double* __restrict__ part) {
-  __shared__ double sh[8][256];
-  const int i0 = blockIdx.y * 8;
-  const int kk = min(8, k - i0);
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long)gridDim.x * 256) {
-    const double we = w[e];
-#pragma unroll
-    for (int t = 0; t < 8; ++t)
-      if (t < kk) acc[t] += V[(i0 + t) * ldv + e] * we;
-  }
-#pragma unroll
-  for (int t = 0; t < 8; ++t) sh[t][threadIdx.x] = acc[t];
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o)
-#pragma unroll
-      for (int t = 0; t < 8; ++t) sh[t][threadIdx.x] += sh[t][threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x < kk) part[(long)(i0 + threadIdx.x) * gridDim.x + blockIdx.x] = sh[threadIdx.x][0];
-}
 
 // out[i] (+)= sum_b part[i*nb + b]
 __global__ void k_reduce_rows(int k, int nb, const double* __restrict__ part, double* __restrict__ out, int accumulate) {
@@ -401,42 +378,6 @@ __global__ void k_kinit(double* __restrict__ kh, int m, const double* __restrict
 // previous rotations, form rotation j, update g; report |g_{j+1}|.
 // (one block of 256 threads: the column and the rotations are staged in LDS,
 // the sequential sweep over the previous rotations runs on one thread)
-__global__ void __launch_bounds__(256) k_givens(double* __restrict__ kh, int m, int j, const double* __restrict__ hnorm,
-                                                double* __restrict__ report) {
-  __shared__ double sc[258], scs[257], ssn[257];
-  KState st{m};
-  double* cs = kh + st.cs();
-  double* sn = kh + st.sn();
-  double* g = kh + st.g();
-  double* col = kh + (long)j * (m + 1);
-  for (int t = threadIdx.x; t <= j; t += blockDim.x) sc[t] = col[t];
-  for (int t = threadIdx.x; t < j; t += blockDim.x) {
-    scs[t] = cs[t];
-    ssn[t] = sn[t];
-  }
-  if (threadIdx.x == 0) sc[j + 1] = hnorm[0];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < j; ++i) {
-      const double t = scs[i] * sc[i] + ssn[i] * sc[i + 1];
-      sc[i + 1] = -ssn[i] * sc[i] + scs[i] * sc[i + 1];
-      sc[i] = t;
-    }
-    const double d = hypot(sc[j], sc[j + 1]);
-    const double hj1 = sc[j + 1];
-    cs[j] = sc[j] / d;
-    sn[j] = hj1 / d;
-    sc[j] = d;
-    sc[j + 1] = 0.0;
-    const double gj = g[j];
-    g[j + 1] = -sn[j] * gj;
-    g[j] = cs[j] * gj;
-    report[0] = fabs(g[j + 1]);
-    report[1] = hj1;
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t <= j + 1; t += blockDim.x) col[t] = sc[t];
-}
 
 // back substitution H y = g on the first k columns, column by column:
 // y_i = s_i / H_ii, then s_t -= H_ti y_i for t < i (parallel over t)
@@ -457,10 +398,194 @@ __global__ void __launch_bounds__(256) k_backsolve(double* __restrict__ kh, int 
   }
 }
 
-__global__ void k_store_col(double* __restrict__ kh, int m, int j, const double* __restrict__ h) {
-  const int i = threadIdx.x;
-  if (i <= j) kh[(long)j * (m + 1) + i] = h[i];
+// ---- CGS2 in three passes over the basis
+// (A) partial dot products of 8 basis vectors per block (blockIdx.y picks
+// the group) with w, streamed; blocks of group 0 also accumulate w.w.
+// part[i * gridDim.x + block] (row k: w.w).
+constexpr int MDOT_G = 8;
+
+__global__ void __launch_bounds__(256)
+k_mdot8(long N, int k, const double* __restrict__ V, long ldv, const double* __restrict__ w,
+         double* __restrict__ part) {
+  __shared__ double sh[4][MDOT_G + 1];
+  const int i0 = blockIdx.y * MDOT_G;
+  const int kk = min(MDOT_G, k - i0);
+  const bool ww = blockIdx.y == 0;
+  double acc[MDOT_G + 1];
+#pragma unroll
+  for (int t = 0; t <= MDOT_G; ++t) acc[t] = 0.0;
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long)gridDim.x * 256) {
+    const double we = w[e];
+#pragma unroll
+    for (int t = 0; t < MDOT_G; ++t)
+      if (t < kk) acc[t] += V[(i0 + t) * ldv + e] * we;
+    if (ww) acc[MDOT_G] += we * we;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t <= MDOT_G; ++t) {
+    double a = acc[t];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if (lane == 0) sh[wv][t] = a;
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < kk) part[(long)(i0 + t) * gridDim.x + blockIdx.x] = sh[0][t] + sh[1][t] + sh[2][t] + sh[3][t];
+  if (ww && t == 0)
+    part[(long)k * gridDim.x + blockIdx.x] = sh[0][MDOT_G] + sh[1][MDOT_G] + sh[2][MDOT_G] + sh[3][MDOT_G];
 }
+
+// (B) w -= V h, then the partial dot products V^T w of the updated w, from
+// one read of V: tiles of ORTH_T elements of all k basis vectors are staged
+// in LDS (row stride ORTH_T + 1 against bank conflicts), the next tile is
+// loaded into registers while the current one is used.
+// part[i * gridDim.x + block].
+constexpr int ORTH_T = 16;
+constexpr int ORTH_BLOCKS = 2048;
+constexpr int ORTH_R = 256 * ORTH_T / 256;  // values per thread per tile (k <= 256)
+
+__global__ void __launch_bounds__(256)
+k_update_dot(long N, int k, const double* __restrict__ V, long ldv, const double* __restrict__ h,
+             double* __restrict__ w, double* __restrict__ part) {
+  constexpr int T = ORTH_T, LD = ORTH_T + 1;
+  extern __shared__ double sm[];
+  double* Vt = sm;                 // [k][LD]
+  double* wt = sm + (long)k * LD;  // [T]
+  double* hs = wt + T;             // [k]
+  const int tid = threadIdx.x;
+  for (int i = tid; i < k; i += 256) hs[i] = h[i];
+  const int tot = k * T;
+  const long ntiles = (N + T - 1) / T;
+  double r[ORTH_R];
+  double wr = 0.0;
+  auto fetch = [&](long tile) {
+    const long e0 = tile * T;
+    const int cnt = (int)min((long)T, N - e0);
+#pragma unroll
+    for (int u = 0; u < ORTH_R; ++u) {
+      const int q = tid + u * 256;
+      const int i = q / T, e = q % T;
+      r[u] = (q < tot && e < cnt) ? V[(long)i * ldv + e0 + e] : 0.0;
+    }
+    wr = tid < cnt ? w[e0 + tid] : 0.0;
+  };
+  double acc = 0.0;
+  long tile = blockIdx.x;
+  if (tile < ntiles) fetch(tile);
+  while (tile < ntiles) {
+    const long e0 = tile * T;
+    const int cnt = (int)min((long)T, N - e0);
+#pragma unroll
+    for (int u = 0; u < ORTH_R; ++u) {
+      const int q = tid + u * 256;
+      if (q < tot) Vt[(q / T) * LD + q % T] = r[u];
+    }
+    if (tid < T) wt[tid] = wr;
+    __syncthreads();
+    const long next = tile + gridDim.x;
+    if (next < ntiles) fetch(next);
+    // w_e -= sum_i V[i][e] h_i: 16 threads per element
+    const int e = tid >> 4, sub = tid & 15;
+    double sacc = 0.0;
+    for (int i = sub; i < k; i += 16) sacc += Vt[i * LD + e] * hs[i];
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, 16);
+    __syncthreads();
+    if (sub == 0) {
+      const double wn = wt[e] - sacc;
+      wt[e] = wn;
+      if (e < cnt) w[e0 + e] = wn;
+    }
+    __syncthreads();
+    if (tid < k) {
+      double a = 0.0;
+#pragma unroll
+      for (int j = 0; j < T; ++j) a += Vt[tid * LD + j] * wt[j];
+      acc += a;
+    }
+    __syncthreads();
+    tile = next;
+  }
+  if (tid < k) part[(long)tid * gridDim.x + blockIdx.x] = acc;
+}
+
+// w -= V h (k vectors) and the partial w.w of the updated w per block
+__global__ void __launch_bounds__(256)
+k_vupdate_norm(long N, int k, const double* __restrict__ V, long ldv, const double* __restrict__ h,
+               double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double hs[256];
+  __shared__ double red[4];
+  for (int t = threadIdx.x; t < k; t += 256) hs[t] = h[t];
+  __syncthreads();
+  double nacc = 0.0;
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long)gridDim.x * 256) {
+    double sacc = 0.0;
+    for (int i = 0; i < k; ++i) sacc += V[i * ldv + e] * hs[i];
+    const double wn = w[e] - sacc;
+    w[e] = wn;
+    nacc += wn * wn;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) nacc += __shfl_xor(nacc, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nacc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// End of one Arnoldi step: ||w|| from the pass-C partials, Hessenberg column
+// j = h1 + h2 (hA holds h1 and w0.w0 at index j+1), the Givens rotations of
+// the column, and the scalars the host reads: sc[2] = ||w_0||, sc[3] =
+// h_{j+1,j}, sc[4] = |g_{j+1}|, sc[5] = h_{j+1,j} before rotation.
+__global__ void __launch_bounds__(256)
+k_cgs_finish(double* __restrict__ kh, int m, int j, const double* __restrict__ hA, const double* __restrict__ hB,
+             int npart, const double* __restrict__ partC, double* __restrict__ sc_out) {
+  __shared__ double col[258], scs[257], ssn[257], red[256];
+  KState st{m};
+  double* cs = kh + st.cs();
+  double* sn = kh + st.sn();
+  double* g = kh + st.g();
+  double* hcol = kh + (long)j * (m + 1);
+  const int tid = threadIdx.x;
+  double a = 0.0;
+  for (int t = tid; t < npart; t += 256) a += partC[t];
+  red[tid] = a;
+  for (int t = tid; t <= j; t += 256) col[t] = hA[t] + hB[t];
+  for (int t = tid; t < j; t += 256) {
+    scs[t] = cs[t];
+    ssn[t] = sn[t];
+  }
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double hn = sqrt(red[0]);
+    col[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double t = scs[i] * col[i] + ssn[i] * col[i + 1];
+      col[i + 1] = -ssn[i] * col[i] + scs[i] * col[i + 1];
+      col[i] = t;
+    }
+    const double d = hypot(col[j], col[j + 1]);
+    const double hj1 = col[j + 1];
+    cs[j] = col[j] / d;
+    sn[j] = hj1 / d;
+    col[j] = d;
+    col[j + 1] = 0.0;
+    const double gj = g[j];
+    g[j + 1] = -sn[j] * gj;
+    g[j] = cs[j] * gj;
+    sc_out[2] = sqrt(hA[j + 1]);
+    sc_out[3] = hn;
+    sc_out[4] = fabs(g[j + 1]);
+    sc_out[5] = hj1;
+  }
+  __syncthreads();
+  for (int t = tid; t <= j + 1; t += 256) hcol[t] = col[t];
+}
+
 
 }  // namespace
 
@@ -683,31 +808,28 @@ double read_scalar(hfsi_ctx* c, const double* dev) {
   return c->pinned[0];
 }
 
-// h[0..k) = V[0..k)^T w  (device)
-void mdot(hfsi_ctx* c, long N, int k, const double* V, const double* w, double* h, int accumulate) {
-  dim3 grid(RED_BLOCKS, div_up(k, 8));
-  k_mdot<<<grid, 256, 0, c->stream>>>(N, k, V, N, w, c->kred.p + 2 * RED_BLOCKS);
-  HIP_LAUNCH_CHECK();
-  k_reduce_rows<<<k, 256, 0, c->stream>>>(k, RED_BLOCKS, c->kred.p + 2 * RED_BLOCKS, h, accumulate);
-  HIP_LAUNCH_CHECK();
-}
 
 }  // namespace
 
 void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_params& prm, hfsi_solve_info* info) {
   const long N = 4L * c->n;
+  const long ld = (N + 31) / 32 * 32;  // basis rows start on 256-byte boundaries
   const int m = prm.restart;
   hipStream_t s = c->stream;
-  c->kv.ensure((size_t)(m + 1) * N);
-  c->kz.ensure((size_t)m * N);
+  c->kv.ensure((size_t)(m + 1) * ld);
+  c->kz.ensure((size_t)m * ld);
   c->kw.ensure(N);
   c->kr.ensure(N);
   KState st{m};
-  c->kh.ensure(st.size() + 512);
-  c->kred.ensure(2 * RED_BLOCKS + (size_t)RED_BLOCKS * (m + 8));
+  const int gN = div_up(N, 256);
+  c->kh.ensure(st.size() + 1024);
+  c->kred.ensure(2 * RED_BLOCKS + (size_t)ORTH_BLOCKS * (m + 2) + gN);
   c->scal.ensure(16);
   double* sc = c->scal.p;  // 0 bnorm, 1 beta, 2 w0, 3 hnorm, 4-5 report
-  double* hbuf = c->kh.p + st.size();  // h and h2 (2 x 64)
+  double* hA = c->kh.p + st.size();  // h1 and w.w (up to 257 values)
+  double* hB = hA + 512;             // h2
+  double* partA = c->kred.p + 2 * RED_BLOCKS;                     // [(k+1) x ORTH_BLOCKS]
+  double* partC = partA + (size_t)ORTH_BLOCKS * (m + 2);          // [gN]
   HIP_CHECK(hipEventRecord(c->ev0, s));
   norm_dev(c, b, N, sc + 0);
   const double bnorm = read_scalar(c, sc + 0);
@@ -723,7 +845,6 @@ void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_para
     double beta = read_scalar(c, sc + 1);
     rel = beta / bnorm;
     converged = beta <= prm.tol * bnorm;
-    const int gN = div_up(N, 256);
     while (!converged && its < prm.max_iter) {
       double* V = c->kv.p;
       double* Z = c->kz.p;
@@ -733,24 +854,25 @@ void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_para
       HIP_LAUNCH_CHECK();
       int jend = 0;
       for (int j = 0; j < m; ++j) {
-        double* vj = V + (long)j * N;
-        double* zj = Z + (long)j * N;
+        double* vj = V + (long)j * ld;
+        double* zj = Z + (long)j * ld;
         precond_apply(c, vj, zj);
         tangent_apply(c, zj, c->kw.p);
-        norm_dev(c, c->kw.p, N, sc + 2);
-        // CGS2
-        mdot(c, N, j + 1, V, c->kw.p, hbuf, 0);
-        k_vupdate<<<gN, 256, 0, s>>>(N, j + 1, V, N, hbuf, -1.0, c->kw.p);
+        // CGS2: (A) h1 = V^T w and w.w; (B) w -= V h1, h2 = V^T w from the
+        // same staged tiles; (C) w -= V h2 and ||w||; then column j = h1 + h2
+        const int k = j + 1;
+        const size_t lds = sizeof(double) * ((size_t)k * (ORTH_T + 1) + ORTH_T + 256);
+        k_mdot8<<<dim3(RED_BLOCKS, div_up(k, MDOT_G)), 256, 0, s>>>(N, k, V, ld, c->kw.p, partA);
         HIP_LAUNCH_CHECK();
-        mdot(c, N, j + 1, V, c->kw.p, hbuf + 256, 0);
-        k_vupdate<<<gN, 256, 0, s>>>(N, j + 1, V, N, hbuf + 256, -1.0, c->kw.p);
+        k_reduce_rows<<<k + 1, 256, 0, s>>>(k + 1, RED_BLOCKS, partA, hA, 0);
         HIP_LAUNCH_CHECK();
-        k_reduce_rows<<<j + 1, 256, 0, s>>>(j + 1, 1, hbuf + 256, hbuf, 1);  // h += h2
+        k_update_dot<<<ORTH_BLOCKS, 256, lds, s>>>(N, k, V, ld, hA, c->kw.p, partA);
         HIP_LAUNCH_CHECK();
-        k_store_col<<<1, 256, 0, s>>>(c->kh.p, m, j, hbuf);
+        k_reduce_rows<<<k, 256, 0, s>>>(k, ORTH_BLOCKS, partA, hB, 0);
         HIP_LAUNCH_CHECK();
-        norm_dev(c, c->kw.p, N, sc + 3);
-        k_givens<<<1, 256, 0, s>>>(c->kh.p, m, j, sc + 3, sc + 4);
+        k_vupdate_norm<<<gN, 256, 0, s>>>(N, k, V, ld, hB, c->kw.p, partC);
+        HIP_LAUNCH_CHECK();
+        k_cgs_finish<<<1, 256, 0, s>>>(c->kh.p, m, j, hA, hB, gN, partC, sc);
         HIP_LAUNCH_CHECK();
         HIP_CHECK(hipMemcpyAsync(c->pinned, sc + 2, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
@@ -763,12 +885,12 @@ void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_para
           breakdown = true;
           break;
         }
-        k_div_scalar<<<gN, 256, 0, s>>>(N, c->kw.p, sc + 3, V + (long)(j + 1) * N);
+        k_div_scalar<<<gN, 256, 0, s>>>(N, c->kw.p, sc + 3, V + (long)(j + 1) * ld);
         HIP_LAUNCH_CHECK();
       }
       k_backsolve<<<1, 256, 0, s>>>(c->kh.p, m, jend);
       HIP_LAUNCH_CHECK();
-      k_vupdate<<<gN, 256, 0, s>>>(N, jend, Z, N, c->kh.p + st.y(), 1.0, x);
+      k_vupdate<<<gN, 256, 0, s>>>(N, jend, Z, ld, c->kh.p + st.y(), 1.0, x);
       HIP_LAUNCH_CHECK();
       residual(c, b, x, c->kr.p);
       norm_dev(c, c->kr.p, N, sc + 1);
