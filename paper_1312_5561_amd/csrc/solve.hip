@@ -117,12 +117,13 @@ k_csr4(int n, const int* __restrict__ p4, const int* __restrict__ base, const vo
   }
 }
 
-// lanes per row for the padded layout: about 3 chunks per lane, more lanes on
+// lanes per row for the padded layout: 3 to 6 chunks per lane (8 lanes for the
+// 25-35 chunks of the first coarse levels measured fastest), more lanes on
 // small levels so that the launch still spreads over the whole chip
 inline int lanes_for4(int64_t chunks, int rows) {
   const double avg = rows ? (double)chunks / rows : 1.0;
   int G = 2;
-  while (G < 64 && 3.0 * G < avg) G *= 2;
+  while (G < 64 && 6.0 * G <= avg) G *= 2;
   while (G < 64 && (int64_t)rows * G < 65536) G *= 2;
   return G;
 }
