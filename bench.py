@@ -15,6 +15,13 @@ corrected by the trained network (kept only when the V-cycle's measured
 convergence factor passes the judge, classical otherwise) and an fp32
 V-cycle inside fp64 FGMRES.  Classical fp32 and plain fp64 are timed the same
 way and reported beside it.
+
+--workload tube: the two-layer artery tube 64 x 8 x 128 (297,216 dofs,
+kappa=1e5), internal dead pressure ramped over 20 increments to 13.3 (plain
+Newton needs increments of 5% here); the timed step is the Newton step at
+full pressure from the converged 0.95 state,
+with classical interpolation (fp32 V-cycle against all-fp64) unless
+--interp learned is given.
 """
 from __future__ import annotations
 
@@ -38,18 +45,25 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=("cube", "tube"), default="cube")
     ap.add_argument("--N", type=int, default=48, help="hexahedra per cube edge")
-    ap.add_argument("--kappa", type=float, default=1e4)
+    ap.add_argument("--kappa", type=float, default=None, help="bulk modulus (cube 1e4, tube 1e5)")
     ap.add_argument("--smoother", type=int, default=1, help="0 l1-Jacobi, 1 Chebyshev")
     ap.add_argument("--restart", type=int, default=256)
     ap.add_argument("--max-iter", type=int, default=3000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain fp64 comparison")
     ap.add_argument("--roofline-reps", type=int, default=50)
-    ap.add_argument("--interp", choices=("learned", "classical"), default="learned")
+    ap.add_argument("--interp", choices=("learned", "classical"), default=None,
+                    help="level-0 interpolation of the headline path (cube: learned, tube: classical)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1312_5561_amd", "weights", "mlp_cube.npz"))
     ap.add_argument("--fallback-rho", type=float, default=0.5)
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.kappa is None:
+        args.kappa = 1e4 if args.workload == "cube" else 1e5
+    if args.interp is None:
+        args.interp = "learned" if args.workload == "cube" else "classical"
+    return args
 
 
 def measured_traffic(kernel_tag):
@@ -91,24 +105,33 @@ def summarize(infos):
     return out
 
 
-def cpu_baseline(N_sample=16, kappa=1e4):
-    """The oracle, untuned, on one Newton step of the same cube physics at
-    N_sample^3 hexahedra, single-threaded."""
+def cpu_baseline(workload="cube", kappa=1e4):
+    """The oracle, untuned, on one Newton step of the same physics at a
+    bounded size (cube: 16^3 hexahedra; tube: 16 x 4 x 32), single-threaded."""
     import synth
     from oracle import fe, newton
     try:
         from threadpoolctl import threadpool_limits
     except ImportError:  # pragma: no cover
         threadpool_limits = None
-    prob = synth.cube_problem(N_sample, kappa=kappa)
-    d = fe.Discretization(prob)
+    if workload == "cube":
+        prob = synth.cube_problem(16, kappa=kappa)
+        d = fe.Discretization(prob)
+        v = np.zeros(4 * prob.n_nodes)
+        v, _, _ = newton.solve_increment(d, v, 0.8, newton.NewtonParams(eps2=1e-6))
+        load, what = 1.0, "the same cube physics at 16^3 hexahedra, load 1.0 from the converged 0.8 state"
+    else:
+        # the oracle would need minutes to ramp the artery to full pressure:
+        # its sample is the first of the 20 pressure increments from rest
+        prob = synth.tube_problem(n_theta=16, n_media=2, n_adv=2, n_z=32, kappa=kappa)
+        d = fe.Discretization(prob)
+        v = np.zeros(4 * prob.n_nodes)
+        load, what = 0.05, "the same artery tube physics at 16 x 4 x 32 hexahedra, first pressure increment"
     prm = newton.NewtonParams()
-    v = np.zeros(4 * prob.n_nodes)
-    v, _, _ = newton.solve_increment(d, v, 0.8, newton.NewtonParams(eps2=1e-6))
 
     def one():
         t = time.perf_counter()
-        newton.newton_step(d, v, 1.0, prm)
+        newton.newton_step(d, v, load, prm)
         return time.perf_counter() - t
 
     if threadpool_limits is not None:
@@ -117,8 +140,8 @@ def cpu_baseline(N_sample=16, kappa=1e4):
     else:
         dt = one()
     return {"value": prob.n_dofs / dt, "unit": "dofs/s", "cores": 1, "kind": "oracle",
-            "sample": f"one full Newton step (assembly, AMG set-up, FGMRES to 1e-8) of the same cube physics at "
-                      f"{N_sample}^3 hexahedra ({prob.n_dofs} dofs), numpy/scipy fp64 single thread, {dt:.2f} s"}
+            "sample": f"one full Newton step (assembly, AMG set-up, FGMRES to 1e-8) of {what} "
+                      f"({prob.n_dofs} dofs), numpy/scipy fp64 single thread, {dt:.2f} s"}
 
 
 def main():
@@ -131,7 +154,16 @@ def main():
     import synth
     from paper_1312_5561_amd import hfsi
 
-    prob = synth.cube_problem(args.N, kappa=args.kappa)
+    if args.workload == "cube":
+        prob = synth.cube_problem(args.N, kappa=args.kappa)
+        increments = 5
+        wname = (f"cube{args.N} Mooney-Rivlin kappa={args.kappa:g}: one Newton step at load 1.0 from the "
+                 f"converged load-0.8 state, FGMRES to 1e-8")
+    else:
+        prob = synth.config_problem("tube", kappa=args.kappa)
+        increments = 20
+        wname = (f"artery tube 64x8x128 two-layer HGO kappa={args.kappa:g}: one Newton step at internal "
+                 f"pressure 13.3 from the converged 0.95 state, FGMRES to 1e-8")
     ndofs = prob.n_dofs
     ctx = hfsi.Context(0)
     ctx.set_problem(prob)
@@ -146,11 +178,11 @@ def main():
                                                     fallback_rho=args.fallback_rho), solve=sp)
     p_c32 = hfsi.newton_params(amg=hfsi.amg_params(precision=1, smoother=args.smoother), solve=sp)
     p64 = hfsi.newton_params(amg=hfsi.amg_params(precision=0, smoother=args.smoother), solve=sp)
-    # untimed: converge the load increments 0.2 .. 0.8
-    for k in range(1, int(round(0.8 * 5)) + 1):
+    # untimed: converge the load increments below 1.0
+    for k in range(1, increments):
         n0 = None
         for _ in range(25):
-            info, _ = ctx.newton_step(v, k / 5.0, p_c32)
+            info, _ = ctx.newton_step(v, k / increments, p_c32)
             n0 = info.dv_mass_norm if n0 is None else n0
             if info.dv_mass_norm <= 1e-10 * n0:
                 break
@@ -199,7 +231,8 @@ def main():
     sweep = "l1-Jacobi sweep (OP_JACOBI)" if args.smoother == 0 else "Chebyshev step (OP_CHEB)"
     roof = {"kernel": f"level-0 {sweep}, fp32 3x3 node blocks, k_b3<float,...>", "bound": "hbm",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic("k_b3<float,4>") if args.smoother == 1 else None,
+            "traffic": (measured_traffic("k_b3<float,4>")
+                        if args.smoother == 1 and args.workload == "cube" and args.N == 48 else None),
             "avg_us": ms * 1e3, "bytes_per_launch": nbytes, "avg_us_cache_cold": ms_cold * 1e3,
             "achieved_cache_cold": nbytes / (ms_cold * 1e-3) / 1e9}
     extra = {}
@@ -226,8 +259,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64 (fp32 V-cycle)",
         "data": "synthetic",
-        "config": {"workload": f"cube{args.N} Mooney-Rivlin kappa={args.kappa:g}: one Newton step at load 1.0 from "
-                               f"the converged load-0.8 state, FGMRES to 1e-8", "dofs": ndofs,
+        "config": {"workload": wname, "dofs": ndofs,
                    "interp": args.interp, "precision": "fp32 V-cycle in fp64 FGMRES", "restart": args.restart,
                    "smoother": "l1-Jacobi" if args.smoother == 0 else "Chebyshev"},
         "breakdown": summarize(inf_main),
@@ -237,7 +269,7 @@ def main():
         "kernels": extra,
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(kappa=args.kappa)
+        out["cpu_baseline"] = cpu_baseline(args.workload, kappa=args.kappa)
     print(json.dumps(out))
 
 

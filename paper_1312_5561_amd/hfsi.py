@@ -188,9 +188,13 @@ class Context:
         self.h = h
         self.n = 0
 
-    def _check(self, code, h=0):
+    _SELF = object()
+
+    def _check(self, code, h=_SELF):
+        """Raise HfsiError with the context's last error text (h: another
+        handle, None before the context exists) for a negative status."""
         if code < 0:
-            msg = self.lib.hfsi_last_error(h if h is not None else self.h)
+            msg = self.lib.hfsi_last_error(self.h if h is Context._SELF else h)
             raise HfsiError(code, msg.decode() if msg else "")
         return code
 

@@ -55,4 +55,39 @@ def amg_prm_pair(lib, smoother=0, precision=0, max_coarse=500, theta=0.5, seed=1
 
 
 __all__ = ["torch_dev", "context_for", "oracle_system", "export_level_matrix", "gpu_hierarchy_to_oracle",
-           "amg_prm_pair", "synth"]
+           "amg_prm_pair", "oracle_sampled_rows", "synth"]
+
+
+def oracle_sampled_rows(prob, v, load, nodes):
+    """Oracle residual entries and Dirichlet-eliminated tangent rows of the
+    given nodes, computed on the sub-mesh of the elements incident to them
+    (with the loaded boundary triangles that touch them): every contribution
+    to those rows comes from such an element or triangle, so the rows are
+    those of the full assembly.  Returns {node: (R[4], {global col dof: K row
+    values [4]})}."""
+    nodes = np.asarray(sorted(set(int(i) for i in nodes)))
+    sel = np.isin(prob.tets, nodes).any(axis=1)
+    tets = prob.tets[sel]
+    sub_nodes = np.unique(tets)
+    loc = -np.ones(prob.n_nodes, np.int64)
+    loc[sub_nodes] = np.arange(len(sub_nodes))
+    tsel = np.isin(prob.tris, nodes).any(axis=1) if len(prob.tris) else np.zeros(0, bool)
+    sub = synth.Problem(prob.X[sub_nodes], loc[tets].astype(np.int32), prob.mat_id[sel], prob.materials,
+                         prob.dir_mask[sub_nodes], loc[prob.tris[tsel]].astype(np.int32), prob.traction[tsel],
+                         prob.lattice[sub_nodes], None if prob.fibres is None else prob.fibres[sel], name="rows")
+    d = fe.Discretization(sub)
+    vs = np.asarray(v).reshape(prob.n_nodes, 4)[sub_nodes].ravel()
+    R, val = d.assemble(vs, load)
+    R, val = d.apply_dirichlet(R, val)
+    K = d.csr(val)
+    out = {}
+    for g in nodes:
+        li = loc[g]
+        rows = {}
+        for r in range(4):
+            i = 4 * li + r
+            for c, a in zip(K.indices[K.indptr[i]:K.indptr[i + 1]], K.data[K.indptr[i]:K.indptr[i + 1]]):
+                gc = 4 * sub_nodes[c // 4] + c % 4
+                rows.setdefault(int(gc), np.zeros(4))[r] = a
+        out[int(g)] = (R[4 * li:4 * li + 4].copy(), rows)
+    return out

@@ -88,6 +88,7 @@ def test_inverted_element_is_reported(lib):
     with pytest.raises(lib.HfsiError) as e:
         ctx.assemble_residual_tangent(vt, 0.0, R)
     assert e.value.code == -5
+    assert "has J <= 0" in str(e.value)   # the context's own error text
 
 
 def test_zero_state_zero_residual(lib):

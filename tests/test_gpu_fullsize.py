@@ -1,0 +1,131 @@
+"""GPU checks at the workloads' real sizes (48^3 and 96^3 cubes, the
+64 x 8 x 128 artery tube), where the oracle cannot run the whole path:
+
+* assembly: residual entries and tangent rows of sampled nodes against the
+  oracle on the sub-mesh of their elements (exact for those rows), 1e-12;
+* the artery tube with the fp32 V-cycle inside fp64 FGMRES and with the
+  all-fp64 cycle: both reach ||b - K x|| <= 1e-8 ||b||, checked on the host
+  with the exported tangent (independent of the GPU residual kernel); their
+  difference is printed;
+* the 96^3 cube: level-0 C/F splitting bit-exact with the oracle's PMIS on
+  the GPU's A; the learned interpolation is judged by the convergence factor
+  and both interpolations solve the Newton system to 1e-8.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from gpu_helpers import amg_prm_pair, context_for, export_level_matrix, oracle_sampled_rows, torch_dev
+from oracle import amg
+
+pytestmark = pytest.mark.gpu
+
+
+def _blocks_csr(out, n):
+    bp, bc, bv = out["block_ptr"], out["block_col"], out["block_val"]
+    rows = np.repeat(np.arange(n), np.diff(bp))
+    r = (4 * rows[:, None, None] + np.arange(4)[None, :, None]).repeat(4, axis=2)
+    c = (4 * bc[:, None, None] + np.arange(4)[None, None, :]).repeat(4, axis=1)
+    return sp.csr_matrix((bv.ravel(), (r.ravel(), c.ravel())), shape=(4 * n, 4 * n))
+
+
+def _assembled(lib, prob, v, load):
+    import torch
+    ctx = context_for(lib, prob)
+    vt = torch_dev(v.ravel())
+    R = torch.zeros_like(vt)
+    view, info = ctx.assemble_residual_tangent(vt, load, R)
+    return ctx, vt, R, view, info
+
+
+@pytest.mark.parametrize("case", ["cube48", "tube"])
+def test_sampled_assembly_rows_full_size(lib, case):
+    prob = synth.config_problem(case)
+    # nodal noise 0.1 * u_scale stays well below the 48^3 element size (0.021)
+    v = synth.random_state(prob, 31, u_scale=0.01, p_scale=0.1)
+    load = 0.5
+    print(f"[fullsize assembly] {case} n={prob.n_nodes} m={prob.n_tets}", flush=True)
+    ctx, vt, R, view, info = _assembled(lib, prob, v, load)
+    assert info.min_J > 0
+    out = ctx.export_tangent(view)
+    Rg = R.cpu().numpy()
+    bp, bc, bv = out["block_ptr"], out["block_col"], out["block_val"]
+    nodes = np.random.default_rng(5).choice(prob.n_nodes, 150, replace=False)
+    # include loaded and clamped nodes
+    nodes = np.concatenate([nodes, prob.tris[:10].ravel(), np.nonzero(prob.dir_mask[:, 0])[0][:10]])
+    rows = oracle_sampled_rows(prob, v, load, nodes)
+    rscale = np.abs(Rg).max()
+    kscale = np.abs(bv).max()
+    for g, (Ro, Ko) in rows.items():
+        assert np.abs(Rg[4 * g:4 * g + 4] - Ro).max() <= 1e-12 * rscale, g
+        cols = bc[bp[g]:bp[g + 1]]
+        assert sorted(set(c // 4 for c in Ko)) == cols.tolist(), g
+        for k, cb in enumerate(cols):
+            blk = bv[bp[g] + k]
+            ref = np.stack([Ko.get(4 * cb + cc, np.zeros(4)) for cc in range(4)], axis=1)
+            assert np.abs(blk - ref).max() <= 1e-12 * kscale, (g, cb)
+
+
+def test_tube_mixed_precision_solve(lib):
+    """Artery tube, first of the 20 pressure increments (0.665): fp32 V-cycle and fp64
+    cycle both solve K dv = -R to 1e-8, verified on the host."""
+    import torch
+    prob = synth.config_problem("tube")
+    n = prob.n_nodes
+    print(f"[fullsize tube] dofs={prob.n_dofs}", flush=True)
+    ctx, vt, R, view, info = _assembled(lib, prob, np.zeros((n, 4)), 0.05)
+    K = _blocks_csr(ctx.export_tangent(view), n)
+    b = -R
+    bh = b.cpu().numpy()
+    sol = {}
+    for prec in (1, 0):
+        gprm, _ = amg_prm_pair(lib, smoother=1, precision=prec)
+        ainfo = ctx.amg_setup(gprm)
+        x = torch.zeros_like(b)
+        si, code = ctx.krylov_amg_solve(b, x, lib.solve_params(tol=1e-8, restart=256, max_iter=3000))
+        assert code == 0 and si.converged
+        xh = x.cpu().numpy()
+        rel = np.linalg.norm(bh - K @ xh) / np.linalg.norm(bh)
+        print(f"[fullsize tube] precision={prec} levels={ainfo.levels} its={si.iterations} "
+              f"host residual={rel:.2e}", flush=True)
+        assert rel <= 1.05e-8
+        sol[prec] = xh
+    diff = np.linalg.norm(sol[1] - sol[0]) / np.linalg.norm(sol[0])
+    print(f"[fullsize tube] fp32-cycle vs fp64-cycle update: {diff:.2e} relative", flush=True)
+    assert diff < 1e-4
+
+
+@pytest.mark.timeout(900)
+def test_cube96_splitting_and_learned_judge(lib):
+    import torch
+    from paper_1312_5561_amd import train_mlp
+    prob = synth.config_problem("cube96")
+    n = prob.n_nodes
+    print(f"[fullsize cube96] dofs={prob.n_dofs}", flush=True)
+    ctx, vt, R, view, info = _assembled(lib, prob, np.zeros((n, 4)), 1.0)
+    gprm, oprm = amg_prm_pair(lib, smoother=1, precision=1)
+    cinfo = ctx.amg_setup(gprm)
+    A = export_level_matrix(ctx, 0, 0)
+    comp = ctx.amg_export(0, 4)
+    st = ctx.amg_export(0, 3)
+    print(f"[fullsize cube96] A rows={A.shape[0]} nnz={A.nnz}; oracle PMIS", flush=True)
+    S_ptr, S_idx = amg.strength(A, comp, oprm.theta)
+    assert np.array_equal(st, amg.pmis(S_ptr, S_idx, A.shape[0], oprm.seed, 0))
+    del A, S_ptr, S_idx
+    b = -R
+    x = torch.zeros_like(b)
+    sc, code = ctx.krylov_amg_solve(b, x, lib.solve_params(tol=1e-8, restart=256, max_iter=3000))
+    assert code == 0 and sc.converged
+    rho_c = ctx.amg_convergence_factor(10, 777)
+    w, _ = train_mlp.load(train_mlp.DEFAULT_WEIGHTS)
+    ctx.mlp_set_weights(w)
+    lprm = lib.amg_params(smoother=1, precision=1, interp=1, fallback_rho=0.5)
+    linfo = ctx.amg_setup(lprm)
+    x = torch.zeros_like(b)
+    sl, code = ctx.krylov_amg_solve(b, x, lib.solve_params(tol=1e-8, restart=256, max_iter=3000))
+    assert code == 0 and sl.converged
+    print(f"[fullsize cube96] classical: rho={rho_c:.3f} its={sc.iterations}; learned: rho={linfo.rho:.3f} "
+          f"kept={linfo.learned_used} its={sl.iterations}", flush=True)
+    assert 0 < linfo.rho < 1
+    assert linfo.learned_used == (linfo.rho <= 0.5)

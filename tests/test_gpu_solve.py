@@ -158,3 +158,23 @@ def test_time_kernel_levels_and_errors(lib):
         ctx.time_kernel(100 + info.levels, 1)
     with pytest.raises(Exception):
         ctx.time_kernel(2, 1, -1)
+
+
+def test_fp32_cycle_is_fp32(lib):
+    """The mixed-precision hierarchy really cycles in fp32: on the same
+    operator and vector its V-cycle differs from the fp64 cycle by fp32
+    rounding (well above fp64 rounding, well below the cycle's own size)."""
+    import torch
+    prob = synth.cube_problem(6)
+    print("[precision] cube6 fp32 vs fp64 V-cycle", flush=True)
+    ctx, R, info, oprm = _setup(lib, prob, np.zeros(prob.n_dofs), 1.0, smoother=1, precision=1, max_coarse=60)
+    r = torch_dev(np.random.default_rng(8).normal(size=3 * prob.n_nodes))
+    z32 = torch.zeros_like(r)
+    ctx.vcycle(r, z32)
+    gprm, _ = amg_prm_pair(lib, smoother=1, precision=0, max_coarse=60)
+    ctx.amg_setup(gprm)
+    z64 = torch.zeros_like(r)
+    ctx.vcycle(r, z64)
+    rel = float(torch.linalg.norm(z32 - z64) / torch.linalg.norm(z64))
+    print(f"[precision] relative difference {rel:.2e}", flush=True)
+    assert 1e-9 < rel < 1e-4

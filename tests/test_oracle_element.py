@@ -134,3 +134,28 @@ def test_sizes_of_the_cube_workload():
     assert len(p.tris) == 128 and p.dir_mask[:, 0:3].sum() == 3 * 81
     # total load equals traction times loaded area (unit face)
     assert np.allclose(d.f_ext.sum(axis=0), [0.0, 0.0, 0.05], atol=1e-15)
+
+
+@pytest.mark.parametrize("make", [lambda: synth.cube_problem(4, jitter=0.1, seed=5),
+                                  lambda: synth.tube_problem(n_theta=12, n_media=1, n_adv=1, n_z=4)])
+def test_sampled_rows_equal_full_assembly(make):
+    """The sub-mesh row helper used by the full-size GPU tests reproduces the
+    rows of the full assembly (residual and Dirichlet-eliminated tangent)."""
+    from gpu_helpers import oracle_sampled_rows
+    prob = make()
+    v = synth.random_state(prob, 4, u_scale=0.04, p_scale=0.1)
+    d = fe.Discretization(prob)
+    R, val = d.assemble(v.ravel(), 0.7)
+    R, val = d.apply_dirichlet(R, val)
+    K = d.csr(val)
+    nodes = np.random.default_rng(1).choice(prob.n_nodes, 12, replace=False)
+    rows = oracle_sampled_rows(prob, v, 0.7, nodes)
+    for g, (Rg, Kg) in rows.items():
+        assert np.allclose(Rg, R[4 * g:4 * g + 4], rtol=1e-12, atol=1e-14 * np.abs(R).max())
+        for r in range(4):
+            i = 4 * g + r
+            ref = dict(zip(K.indices[K.indptr[i]:K.indptr[i + 1]].tolist(), K.data[K.indptr[i]:K.indptr[i + 1]]))
+            got = {c: vals[r] for c, vals in Kg.items() if c in ref or vals[r] != 0.0}
+            assert set(got) == set(ref)
+            for c in ref:
+                assert abs(got[c] - ref[c]) <= 1e-12 * np.abs(K.data).max()
