@@ -57,6 +57,8 @@ void csr_launch(int G, int n, const int* ptr, const int* col, const T* val, cons
   const long threads = (long)n * G;
   const int grid = div_up(threads, 256);
   switch (G) {
+    case 1: k_csr<T, 1, OP><<<grid, 256, 0, s>>>(n, ptr, col, val, x, b, dinv, y, d, c1, c2); break;
+    case 2: k_csr<T, 2, OP><<<grid, 256, 0, s>>>(n, ptr, col, val, x, b, dinv, y, d, c1, c2); break;
     case 4: k_csr<T, 4, OP><<<grid, 256, 0, s>>>(n, ptr, col, val, x, b, dinv, y, d, c1, c2); break;
     case 8: k_csr<T, 8, OP><<<grid, 256, 0, s>>>(n, ptr, col, val, x, b, dinv, y, d, c1, c2); break;
     case 16: k_csr<T, 16, OP><<<grid, 256, 0, s>>>(n, ptr, col, val, x, b, dinv, y, d, c1, c2); break;
@@ -195,7 +197,9 @@ k_b3(int nn, const int* __restrict__ bptr, const int* __restrict__ bcol, const T
 
 inline int lanes_for(int64_t nnz, int rows) {
   const double avg = rows ? (double)nnz / rows : 1.0;
-  if (avg <= 8) return 4;
+  if (avg <= 3) return 1;   // interpolation rows (about 2 entries)
+  if (avg <= 6) return 2;
+  if (avg <= 12) return 4;
   if (avg <= 24) return 8;
   if (avg <= 64) return 16;
   if (avg <= 160) return 32;
@@ -216,6 +220,44 @@ __global__ void k_cheb_first(int n, const T* __restrict__ dinv, const T* __restr
   const T dn = c2 * dinv[i] * b[i];
   d[i] = dn;
   x[i] = dn;
+}
+
+// Restriction b_c = R r fused with the first smoothing step of the coarse
+// level from a zero guess: x_c = cf D^-1 b_c, and d_c = x_c for Chebyshev
+// (what k_cheb_first or k_scale_vec would compute from the stored b_c).
+template <class T, int G>
+__global__ void __launch_bounds__(256)
+k_restrict_first(int n, const int* __restrict__ ptr, const int* __restrict__ col, const T* __restrict__ val,
+                 const T* __restrict__ r, const T* __restrict__ dinv, T* __restrict__ bc, T* __restrict__ xc,
+                 T* __restrict__ dc, T cf) {
+  const int gid = (blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  if (gid >= n) return;
+  T s = 0;
+  const int hi = ptr[gid + 1];
+  for (int e = ptr[gid] + lane; e < hi; e += G) s += val[e] * r[col[e]];
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
+  if (lane != 0) return;
+  bc[gid] = s;
+  const T v = cf * dinv[gid] * s;
+  xc[gid] = v;
+  if (dc) dc[gid] = v;
+}
+
+// the same for level 0: r_u (node-interleaved fp64) -> right-hand side in T
+// and the first smoothing step
+template <class T>
+__global__ void k_split_u_first(int n, const double* __restrict__ r, const T* __restrict__ dinv, T* __restrict__ bu,
+                                T* __restrict__ xu, T* __restrict__ du, T cf) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * n) return;
+  const int i = t / 3, c = t - 3 * i;
+  const T bv = (T)r[4 * i + c];
+  bu[t] = bv;
+  const T v = cf * dinv[t] * bv;
+  xu[t] = v;
+  if (du) du[t] = v;
 }
 
 template <class Tin, class Tout>
@@ -246,7 +288,17 @@ k_bsr4(int n, const int* __restrict__ bptr, const int* __restrict__ bcol, const 
   if (gid >= n) return;
   const int c = lane & 3;
   double s = 0.0;
-  for (int q = bptr[gid]; q < bptr[gid + 1]; ++q) s += bval[16 * (size_t)q + lane] * x[4 * bcol[q] + c];
+  int q = bptr[gid];
+  const int qe = bptr[gid + 1];
+  // four blocks per step: their column indices, values and x entries are all
+  // requested before the first product is formed
+  for (; q + 3 < qe; q += 4) {
+    const int j0 = bcol[q], j1 = bcol[q + 1], j2 = bcol[q + 2], j3 = bcol[q + 3];
+    const double a0 = bval[16 * (size_t)q + lane], a1 = bval[16 * (size_t)(q + 1) + lane];
+    const double a2 = bval[16 * (size_t)(q + 2) + lane], a3 = bval[16 * (size_t)(q + 3) + lane];
+    s += a0 * x[4 * j0 + c] + a1 * x[4 * j1 + c] + a2 * x[4 * j2 + c] + a3 * x[4 * j3 + c];
+  }
+  for (; q < qe; ++q) s += bval[16 * (size_t)q + lane] * x[4 * bcol[q] + c];
   s += __shfl_xor(s, 1, 16);
   s += __shfl_xor(s, 2, 16);
   if (c == 0) {
@@ -650,18 +702,49 @@ double level_op_bytes(const hfsi_ctx* c, const Level& L, bool resid) {
   return (double)L.A.nnz * (ts + 4.0) + L.n * (4.0 + per_row);
 }
 
-// smoothing sweeps on level L; x holds the current iterate (in buffer xa),
-// returns the buffer that holds the result (xa or xb).
+// scale of the first smoothing step from a zero guess, x = cf D^-1 b: 1 for
+// Jacobi, 1/theta for Chebyshev on [lmax/30, 1.1 lmax]
+double first_step_coef(const Hierarchy& H, const Level& L) {
+  if (H.smoother == 0) return 1.0;
+  const double hi = 1.1 * L.lmax, lo = L.lmax / 30.0;
+  return 1.0 / (0.5 * (hi + lo));
+}
+
+// launch k_restrict_first with G lanes per coarse row
 template <class T>
-T* smooth(hfsi_ctx* c, Level& L, const LevelView<T>& v, const T* b, T* xa, T* xb, int nu, bool zero_start) {
+void restrict_first_launch(int G, int n, const int* ptr, const int* col, const T* val, const T* r, const T* dinv,
+                           T* bc, T* xc, T* dc, T cf, hipStream_t s) {
+  if (n <= 0) return;
+  const int grid = div_up((long)n * G, 256);
+  switch (G) {
+    case 1: k_restrict_first<T, 1><<<grid, 256, 0, s>>>(n, ptr, col, val, r, dinv, bc, xc, dc, cf); break;
+    case 2: k_restrict_first<T, 2><<<grid, 256, 0, s>>>(n, ptr, col, val, r, dinv, bc, xc, dc, cf); break;
+    case 4: k_restrict_first<T, 4><<<grid, 256, 0, s>>>(n, ptr, col, val, r, dinv, bc, xc, dc, cf); break;
+    case 8: k_restrict_first<T, 8><<<grid, 256, 0, s>>>(n, ptr, col, val, r, dinv, bc, xc, dc, cf); break;
+    case 16: k_restrict_first<T, 16><<<grid, 256, 0, s>>>(n, ptr, col, val, r, dinv, bc, xc, dc, cf); break;
+    case 32: k_restrict_first<T, 32><<<grid, 256, 0, s>>>(n, ptr, col, val, r, dinv, bc, xc, dc, cf); break;
+    default: k_restrict_first<T, 64><<<grid, 256, 0, s>>>(n, ptr, col, val, r, dinv, bc, xc, dc, cf); break;
+  }
+  HIP_LAUNCH_CHECK();
+}
+
+// smoothing sweeps on level L; x holds the current iterate (in buffer xa),
+// returns the buffer that holds the result (xa or xb).  first_done: the first
+// step from a zero guess (x = cf D^-1 b, and d = x for Chebyshev) was already
+// written by the kernel that produced b.
+template <class T>
+T* smooth(hfsi_ctx* c, Level& L, const LevelView<T>& v, const T* b, T* xa, T* xb, int nu, bool zero_start,
+          bool first_done = false) {
   hipStream_t s = c->stream;
   const int n = L.n;
   const Hierarchy& H = c->H;
   if (H.smoother == 0) {
     for (int k = 0; k < nu; ++k) {
       if (zero_start && k == 0) {
-        k_scale_vec<T><<<div_up(n, 256), 256, 0, s>>>(n, v.dinv, b, xa, (T)1);
-        HIP_LAUNCH_CHECK();
+        if (!first_done) {
+          k_scale_vec<T><<<div_up(n, 256), 256, 0, s>>>(n, v.dinv, b, xa, (T)1);
+          HIP_LAUNCH_CHECK();
+        }
         continue;
       }
       level_op<T, OP_JACOBI>(L, v, xa, b, xb, nullptr, 0, 0, s);
@@ -676,8 +759,10 @@ T* smooth(hfsi_ctx* c, Level& L, const LevelView<T>& v, const T* b, T* xa, T* xb
   T* d = v.r;  // direction vector (the residual buffer is free during smoothing)
   for (int k = 0; k < nu; ++k) {
     if (zero_start && k == 0) {
-      k_cheb_first<T><<<div_up(n, 256), 256, 0, s>>>(n, v.dinv, b, xa, d, (T)(1.0 / theta));
-      HIP_LAUNCH_CHECK();
+      if (!first_done) {
+        k_cheb_first<T><<<div_up(n, 256), 256, 0, s>>>(n, v.dinv, b, xa, d, (T)(1.0 / theta));
+        HIP_LAUNCH_CHECK();
+      }
     } else {
       level_op<T, OP_CHEB>(L, v, xa, b, xb, d, (T)0, (T)(1.0 / theta), s);
       std::swap(xa, xb);
@@ -689,8 +774,9 @@ T* smooth(hfsi_ctx* c, Level& L, const LevelView<T>& v, const T* b, T* xa, T* xb
 }
 
 // V-cycle on level l with right-hand side in L.b; returns the buffer holding x.
+// first_done: the first pre-smoothing step is already in L.x (and L.r).
 template <class T>
-T* vcycle_rec(hfsi_ctx* c, int l) {
+T* vcycle_rec(hfsi_ctx* c, int l, bool first_done) {
   Hierarchy& H = c->H;
   hipStream_t s = c->stream;
   Level& L = H.L[l];
@@ -716,17 +802,23 @@ T* vcycle_rec(hfsi_ctx* c, int l) {
   }
   T* x = v.x;
   if (H.nu_pre > 0) {
-    x = smooth<T>(c, L, v, v.b, v.x, v.t, H.nu_pre, true);
+    x = smooth<T>(c, L, v, v.b, v.x, v.t, H.nu_pre, true, first_done);
   } else {
     HIP_CHECK(hipMemsetAsync(v.x, 0, sizeof(T) * n, s));
   }
   T* other = x == v.x ? v.t : v.x;
   level_op<T, OP_RESID>(L, v, x, v.b, v.r, nullptr, 0, 0, s);
   Level& Lc = H.L[l + 1];
-  LevelView<T> vc = view<T>(Lc, l + 1 == (int)H.L.size() - 1);
-  csr_launch<T, OP_SPMV>(lanes_for(L.R.nnz, L.R.rows), L.R.rows, L.R.ptr.p, L.R.col.p, v.R, v.r, nullptr, nullptr,
-                         vc.b, nullptr, 0, 0, s);
-  T* xc = vcycle_rec<T>(c, l + 1);
+  const bool coarsest = l + 1 == (int)H.L.size() - 1;
+  LevelView<T> vc = view<T>(Lc, coarsest);
+  const bool fuse = !coarsest && H.nu_pre > 0;
+  if (fuse)
+    restrict_first_launch<T>(lanes_for(L.R.nnz, L.R.rows), L.R.rows, L.R.ptr.p, L.R.col.p, v.R, v.r, vc.dinv, vc.b,
+                             vc.x, H.smoother == 1 ? vc.r : nullptr, (T)first_step_coef(H, Lc), s);
+  else
+    csr_launch<T, OP_SPMV>(lanes_for(L.R.nnz, L.R.rows), L.R.rows, L.R.ptr.p, L.R.col.p, v.R, v.r, nullptr, nullptr,
+                           vc.b, nullptr, 0, 0, s);
+  T* xc = vcycle_rec<T>(c, l + 1, fuse);
   csr_launch<T, OP_ADD>(lanes_for(L.P.nnz, n), n, L.P.ptr.p, L.P.col.p, v.P, xc, nullptr, nullptr, x, nullptr, 0, 0,
                         s);
   if (H.nu_post > 0) x = smooth<T>(c, L, v, v.b, x, other, H.nu_post, false);
@@ -744,12 +836,12 @@ void vcycle_apply(hfsi_ctx* c, const double* r, double* z) {
   hipStream_t s = c->stream;
   if (H.precision == 0) {
     HIP_CHECK(hipMemcpyAsync(L0.b.p, r, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    double* x = vcycle_rec<double>(c, 0);
+    double* x = vcycle_rec<double>(c, 0, false);
     HIP_CHECK(hipMemcpyAsync(z, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   } else {
     k_cast<double, float><<<div_up(n, 256), 256, 0, s>>>(n, r, L0.bf.p);
     HIP_LAUNCH_CHECK();
-    float* x = vcycle_rec<float>(c, 0);
+    float* x = vcycle_rec<float>(c, 0, false);
     k_cast<float, double><<<div_up(n, 256), 256, 0, s>>>(n, x, z);
     HIP_LAUNCH_CHECK();
   }
@@ -763,15 +855,27 @@ void precond_apply(hfsi_ctx* c, const double* r, double* z) {
   if (L0.n != 3 * n) fail(HFSI_E_ORDER, "preconditioner: hierarchy was not built on the assembled A");
   hipStream_t s = c->stream;
   const int grid16 = div_up((long)n * 16, 256);
+  // level 0 takes its first pre-smoothing step in the kernel that splits r
+  const bool fuse = H.L.size() > 1 && H.nu_pre > 0;
+  const int g3 = div_up(3 * n, 256);
+  const double cf = first_step_coef(H, L0);
   if (H.precision == 0) {
-    k_split_u<double><<<div_up(3 * n, 256), 256, 0, s>>>(n, r, L0.b.p);
+    if (fuse)
+      k_split_u_first<double><<<g3, 256, 0, s>>>(n, r, L0.dinv.p, L0.b.p, L0.x.p, H.smoother == 1 ? L0.r.p : nullptr,
+                                                 cf);
+    else
+      k_split_u<double><<<g3, 256, 0, s>>>(n, r, L0.b.p);
     HIP_LAUNCH_CHECK();
-    double* zu = vcycle_rec<double>(c, 0);
+    double* zu = vcycle_rec<double>(c, 0, fuse);
     k_pl_combine<double><<<grid16, 256, 0, s>>>(n, c->nptr.p, c->ncol.p, c->b2.p, zu, r, c->schur.p, z);
   } else {
-    k_split_u<float><<<div_up(3 * n, 256), 256, 0, s>>>(n, r, L0.bf.p);
+    if (fuse)
+      k_split_u_first<float><<<g3, 256, 0, s>>>(n, r, L0.dinv32.p, L0.bf.p, L0.xf.p,
+                                                H.smoother == 1 ? L0.rf.p : nullptr, (float)cf);
+    else
+      k_split_u<float><<<g3, 256, 0, s>>>(n, r, L0.bf.p);
     HIP_LAUNCH_CHECK();
-    float* zu = vcycle_rec<float>(c, 0);
+    float* zu = vcycle_rec<float>(c, 0, fuse);
     k_pl_combine<float><<<grid16, 256, 0, s>>>(n, c->nptr.p, c->ncol.p, c->b2.p, zu, r, c->schur.p, z);
   }
   HIP_LAUNCH_CHECK();
