@@ -203,6 +203,7 @@ struct hfsi_ctx {
   hfsi::DevBuf<int> iscal;       // device integer scalars
   void* mlp_impl = nullptr;      // learned-interpolation state (mlp.hip)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t kev[2] = {nullptr, nullptr};  // FGMRES scalar read-back slots
 };
 
 namespace hfsi {

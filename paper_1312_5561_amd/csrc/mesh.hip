@@ -228,6 +228,19 @@ void colour_elements(int n, int m, const int32_t* tets, std::vector<int>& perm, 
 
 extern "C" int32_t hfsi_abi_version(void) { return 1; }
 
+namespace {
+// events and pinned host memory of a context (safe on partly created ones)
+void release_events(hfsi_ctx* c) {
+  for (hipEvent_t* e : {&c->ev0, &c->ev1, &c->kev[0], &c->kev[1]})
+    if (*e) {
+      (void)hipEventDestroy(*e);
+      *e = nullptr;
+    }
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  c->pinned = nullptr;
+}
+}  // namespace
+
 extern "C" hfsi_status hfsi_create(hfsi_ctx** out, int device, void* stream) {
   if (!out) return HFSI_E_ARG;
   *out = nullptr;
@@ -236,8 +249,13 @@ extern "C" hfsi_status hfsi_create(hfsi_ctx** out, int device, void* stream) {
   hfsi_ctx* c = new hfsi_ctx();
   c->device = device;
   c->stream = (hipStream_t)stream;
-  if (hipSetDevice(device) != hipSuccess || hipEventCreate(&c->ev0) != hipSuccess ||
-      hipEventCreate(&c->ev1) != hipSuccess || hipHostMalloc((void**)&c->pinned, 64 * sizeof(double)) != hipSuccess) {
+  const bool ok = hipSetDevice(device) == hipSuccess && hipEventCreate(&c->ev0) == hipSuccess &&
+                  hipEventCreate(&c->ev1) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->kev[0], hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->kev[1], hipEventDisableTiming) == hipSuccess &&
+                  hipHostMalloc((void**)&c->pinned, 64 * sizeof(double)) == hipSuccess;
+  if (!ok) {
+    release_events(c);
     delete c;
     return HFSI_E_HIP;
   }
@@ -249,9 +267,7 @@ extern "C" hfsi_status hfsi_destroy(hfsi_ctx* c) {
   if (!c) return HFSI_E_ARG;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  if (c->ev0) (void)hipEventDestroy(c->ev0);
-  if (c->ev1) (void)hipEventDestroy(c->ev1);
-  if (c->pinned) (void)hipHostFree(c->pinned);
+  release_events(c);
   hfsi::mlp_free(c);
   delete c;
   return HFSI_OK;

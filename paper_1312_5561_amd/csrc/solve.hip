@@ -957,8 +957,29 @@ void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_para
       HIP_LAUNCH_CHECK();
       k_kinit<<<64, 256, 0, s>>>(c->kh.p, m, sc + 1);
       HIP_LAUNCH_CHECK();
+      // The convergence test of iteration j is read one iteration late: the
+      // host enqueues iteration j + 1 before it waits for the scalars of j,
+      // so the GPU never idles at the read-back.  When j ends the cycle, the
+      // speculative iteration j + 1 is discarded: it only wrote Hessenberg
+      // column j + 1, its rotation, g[j+1..j+2] and basis vector j + 2,
+      // none of which the solution with j + 1 columns reads.
       int jend = 0;
-      for (int j = 0; j < m; ++j) {
+      bool stop = false;
+      auto evaluate = [&](int i) {
+        HIP_CHECK(hipEventSynchronize(c->kev[i & 1]));
+        const double* p = c->pinned + 4 * (i & 1);
+        const double w0 = p[0], gabs = p[2], hj1 = p[3];
+        ++its;
+        jend = i + 1;
+        if (!std::isfinite(gabs)) fail(HFSI_E_NAN, "FGMRES: non-finite residual estimate");
+        if (gabs <= prm.tol * bnorm || its >= prm.max_iter) {
+          stop = true;
+        } else if (hj1 <= 1e-14 * w0) {
+          breakdown = true;
+          stop = true;
+        }
+      };
+      for (int j = 0; j < m && !stop; ++j) {
         double* vj = V + (long)j * ld;
         double* zj = Z + (long)j * ld;
         precond_apply(c, vj, zj);
@@ -979,20 +1000,14 @@ void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_para
         HIP_LAUNCH_CHECK();
         k_cgs_finish<<<1, 256, 0, s>>>(c->kh.p, m, j, hA, hB, gN, partC, sc);
         HIP_LAUNCH_CHECK();
-        HIP_CHECK(hipMemcpyAsync(c->pinned, sc + 2, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipStreamSynchronize(s));
-        const double w0 = c->pinned[0], gabs = c->pinned[2], hj1 = c->pinned[3];
-        ++its;
-        jend = j + 1;
-        if (!std::isfinite(gabs)) fail(HFSI_E_NAN, "FGMRES: non-finite residual estimate");
-        if (gabs <= prm.tol * bnorm || its >= prm.max_iter) break;
-        if (hj1 <= 1e-14 * w0) {
-          breakdown = true;
-          break;
-        }
+        HIP_CHECK(hipMemcpyAsync(c->pinned + 4 * (j & 1), sc + 2, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipEventRecord(c->kev[j & 1], s));
+        // next basis vector (V has m + 1 rows)
         k_div_scalar<<<gN, 256, 0, s>>>(N, c->kw.p, sc + 3, V + (long)(j + 1) * ld);
         HIP_LAUNCH_CHECK();
+        if (j > 0) evaluate(j - 1);
       }
+      if (!stop) evaluate(m - 1);
       k_backsolve<<<1, 256, 0, s>>>(c->kh.p, m, jend);
       HIP_LAUNCH_CHECK();
       k_vupdate<<<gN, 256, 0, s>>>(N, jend, Z, ld, c->kh.p + st.y(), 1.0, x);
