@@ -66,19 +66,29 @@ def parse():
     return args
 
 
+def kernel_source_hash():
+    """sha256[:16] of the source the level-0 counters depend on: the k_b3
+    kernel and level_op, which launches it (solve.hip)."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_1312_5561_amd", "csrc", "solve.hip")).read()
+    parts = []
+    for start in ("k_b3(int nn,", "void level_op(Level& L,"):
+        a = src.index(start)
+        parts.append(src[a:src.index("\n}\n", a)])
+    return hashlib.sha256("\n".join(parts).encode()).hexdigest()[:16]
+
+
 def measured_traffic(kernel_tag):
     """Calibrated HBM bytes per launch from the committed PMC summary, or None
-    when the kernel source changed after the counters were taken."""
-    import hashlib
+    when the kernel or its launch changed after the counters were taken."""
     path = os.path.join(ROOT, "profiles", "cube48_level0_smoother_traffic.md")
-    src = os.path.join(ROOT, "paper_1312_5561_amd", "csrc", "solve.hip")
     if not os.path.exists(path):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    sha = kernel_source_hash()
     for line in open(path):
         if line.startswith("traffic ") and f"kernel={kernel_tag} " in line:
             kv = dict(t.split("=", 1) for t in line.split()[1:])
-            if kv.get("solve_hip_sha256_16") == sha:
+            if kv.get("kernel_src_sha256_16") == sha:
                 return float(kv["bytes_per_launch"])
     return None
 
