@@ -101,7 +101,7 @@ typedef struct {
  * measured convergence factor exceeds fallback_rho. */
 typedef struct {
   size_t struct_size;
-  double strength_theta; /* default 0.5                                    */
+  double strength_theta; /* default 0.15                                   */
   int32_t max_coarse;    /* default 500                                    */
   int32_t max_levels;    /* default 25                                     */
   uint64_t seed;         /* PMIS weight seed, default 12345                */

@@ -35,7 +35,7 @@ def _sgn(x):
     return np.where(x < 0, -1.0, 1.0)
 
 
-def strength(A: sp.csr_matrix, comp, theta=0.5):
+def strength(A: sp.csr_matrix, comp, theta=0.15):
     """Strong-dependence sets S_i as a boolean CSR pattern (indptr, indices)."""
     A = A.tocsr()
     n = A.shape[0]
@@ -234,7 +234,7 @@ class Level:
 
 @dataclasses.dataclass
 class AmgParams:
-    theta: float = 0.5
+    theta: float = 0.15
     max_coarse: int = 500
     max_levels: int = 25
     seed: int = 12345

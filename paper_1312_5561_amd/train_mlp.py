@@ -163,7 +163,8 @@ def main():
                                  log=lambda s: print(s, flush=True))
     print(f"[train] collected {total} samples ({failed} failed targets) in {time.time() - t0:.1f} s", flush=True)
     info = train(ctx, args.epochs, args.batch, args.lr, log=lambda s: print(s, flush=True))
-    meta = dict(setups=args.setups, N=args.N, epochs=args.epochs, batch=args.batch, lr=args.lr, samples=total,
+    meta = dict(setups=args.setups, N=args.N, strength_theta=hfsi.amg_params().strength_theta,
+                epochs=args.epochs, batch=args.batch, lr=args.lr, samples=total,
                 failed_targets=failed, loss_first=info.loss_first, loss_last=info.loss_last, steps=info.steps)
     save(args.out, ctx, meta)
     print(json.dumps(meta), flush=True)

@@ -46,7 +46,7 @@ def gpu_hierarchy_to_oracle(ctx, info, prm: amg.AmgParams):
     return amg.Hierarchy(levels, lu)
 
 
-def amg_prm_pair(lib, smoother=0, precision=0, max_coarse=500, theta=0.5, seed=12345, nu=2):
+def amg_prm_pair(lib, smoother=0, precision=0, max_coarse=500, theta=0.15, seed=12345, nu=2):
     g = lib.amg_params(theta=theta, max_coarse=max_coarse, seed=seed, smoother=smoother, nu_pre=nu, nu_post=nu,
                        precision=precision)
     o = amg.AmgParams(theta=theta, max_coarse=max_coarse, seed=seed,

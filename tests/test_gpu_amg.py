@@ -42,9 +42,10 @@ def _check_levels(ctx, info, theta, seed, rtol=1e-12):
         assert np.abs(Ac.data - Aco.data).max() <= rtol * np.abs(Aco.data).max()
 
 
-@pytest.mark.parametrize("case", ["cube8", "cube5_jitter_state", "tube_small", "laplacian3d"])
-def test_hierarchy_matches_oracle_level_by_level(lib, case):
-    print(f"[amg parity] case={case}", flush=True)
+@pytest.mark.parametrize("case,theta", [("cube8", 0.15), ("cube8", 0.5), ("cube5_jitter_state", 0.15),
+                                        ("tube_small", 0.15), ("laplacian3d", 0.15)])
+def test_hierarchy_matches_oracle_level_by_level(lib, case, theta):
+    print(f"[amg parity] case={case} theta={theta}", flush=True)
     if case == "laplacian3d":
         import test_oracle_amg as T
         A = T.laplacian(14, 13, 12)
@@ -61,7 +62,7 @@ def test_hierarchy_matches_oracle_level_by_level(lib, case):
             v = synth.random_state(prob, 6, u_scale=0.02, p_scale=0.5).ravel()
         _, K, b, A, B2, s = oracle_system(prob, v, 0.3)
         comp = np.tile(np.arange(3, dtype=np.int32), prob.n_nodes)
-    gprm, oprm = amg_prm_pair(lib, max_coarse=50)
+    gprm, oprm = amg_prm_pair(lib, max_coarse=50, theta=theta)
     ctx = lib.Context(0)
     info = ctx.amg_setup_csr(A.indptr, A.indices, A.data, comp, gprm)
     assert info.levels >= 2

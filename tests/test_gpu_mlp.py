@@ -98,7 +98,7 @@ def test_collect_matches_oracle(lib):
     comp = ctx.amg_export(0, 4)
     st = ctx.amg_export(0, 3)
     P = export_level_matrix(ctx, 0, 1)
-    S_ptr, S_idx = amg.strength(A, comp, 0.5)
+    S_ptr, S_idx = amg.strength(A, comp, lib.amg_params().strength_theta)
     rows, Xo, mo, wo = mlp.samples(A, comp, st, S_ptr, S_idx, P, prob.lattice, mlp.material_features(prob.materials))
     assert len(rows) == added
     assert np.array_equal(X.astype(np.float64), Xo.astype(np.float32).astype(np.float64))
