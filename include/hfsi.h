@@ -106,7 +106,8 @@ typedef struct {
   int32_t max_levels;    /* default 25                                     */
   uint64_t seed;         /* PMIS weight seed, default 12345                */
   int32_t smoother;
-  int32_t nu_pre, nu_post;
+  int32_t nu_pre, nu_post;  /* sweeps before / after the coarse correction,
+                               default 1 / 2 (smoother default 1)  */
   int32_t precision;
   int32_t interp;
   double fallback_rho;   /* default 0.5                                    */

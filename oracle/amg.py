@@ -238,8 +238,8 @@ class AmgParams:
     max_coarse: int = 500
     max_levels: int = 25
     seed: int = 12345
-    smoother: str = "l1jacobi"   # or "chebyshev"
-    nu_pre: int = 2
+    smoother: str = "chebyshev"   # or "l1jacobi"
+    nu_pre: int = 1
     nu_post: int = 2
     lanczos_steps: int = 10
     max_dense: int = 8192

@@ -95,7 +95,7 @@ def train_params(batch=1024, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     return TrainParams(C.sizeof(TrainParams), batch, lr, beta1, beta2, eps)
 
 
-def amg_params(theta=0.15, max_coarse=500, max_levels=25, seed=12345, smoother=0, nu_pre=2, nu_post=2,
+def amg_params(theta=0.15, max_coarse=500, max_levels=25, seed=12345, smoother=1, nu_pre=1, nu_post=2,
                precision=0, interp=0, fallback_rho=0.5):
     return AmgParams(C.sizeof(AmgParams), theta, max_coarse, max_levels, seed, smoother, nu_pre, nu_post,
                      precision, interp, fallback_rho)

@@ -140,7 +140,7 @@ def test_l1_jacobi_is_monotone_in_energy_norm():
     b = A @ x_true
     x = np.zeros_like(b)
     e_prev = np.inf
-    prm = amg.AmgParams()
+    prm = amg.AmgParams(smoother="l1jacobi")
     for _ in range(10):
         x = amg.smooth(L, b, x, 1, prm)
         e = x - x_true
