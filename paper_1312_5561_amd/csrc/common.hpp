@@ -35,33 +35,58 @@ struct Error : std::runtime_error {
 
 #define HIP_LAUNCH_CHECK() HIP_CHECK(hipGetLastError())
 
-// Device buffer owned by the context.  Allocation is synchronous and only
-// happens at set-up or when a buffer must grow.
+// Device memory comes from a per-process block cache.  A block released by a
+// DevBuf returns to the cache tagged with the stream of the library call that
+// released it (every kernel of a context runs on that context's stream) and
+// is handed out again only for work on the same stream, so stream order makes
+// the reuse safe; blocks released after a stream synchronisation (context
+// destruction) are free for any stream.  hipMalloc runs only when no cached
+// block of 1x..2x the request fits; no hipFree (which synchronises the
+// device) runs while a context is alive.
+extern thread_local hipStream_t tls_stream;  // stream of the current library call
+extern thread_local bool tls_idle;           // releases happen after a stream sync
+void* dev_alloc(size_t bytes, size_t* cap, int* dev);
+void dev_release(void* p, size_t cap, int dev);
+void dev_cache_trim();  // hipFree every idle cached block (no context alive)
+
+// Device buffer owned by the context or by one library call.
 template <class T>
 struct DevBuf {
   T* p = nullptr;
-  size_t n = 0;
+  size_t n = 0;    // elements the block holds
+  size_t cap = 0;  // bytes of the block
+  int dev = 0;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), cap(o.cap), dev(o.dev) {
+    o.p = nullptr;
+    o.n = o.cap = 0;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      cap = o.cap;
+      dev = o.dev;
+      o.p = nullptr;
+      o.n = o.cap = 0;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) dev_release(p, cap, dev);
     p = nullptr;
-    n = 0;
+    n = cap = 0;
   }
   // (re)allocate to at least cnt elements; contents are not preserved
   void ensure(size_t cnt) {
     if (cnt <= n && p) return;
     release();
-    size_t bytes = (cnt ? cnt : 1) * sizeof(T);
-    HIP_CHECK(hipMalloc(&p, bytes));
-    n = cnt;
+    p = (T*)dev_alloc((cnt ? cnt : 1) * sizeof(T), &cap, &dev);
+    n = cap / sizeof(T);
   }
   void upload(const T* h, size_t cnt, hipStream_t s) {
     ensure(cnt);
@@ -250,6 +275,8 @@ void assemble_kernels_only(hfsi_ctx* c);
 #define HFSI_ABI_BEGIN(ctx)                     \
   if (!(ctx)) return HFSI_E_ARG;                \
   try {                                         \
+    ::hfsi::tls_stream = (ctx)->stream;         \
+    ::hfsi::tls_idle = false;                   \
     HIP_CHECK(hipSetDevice((ctx)->device));
 
 #define HFSI_ABI_END(ctx)                       \

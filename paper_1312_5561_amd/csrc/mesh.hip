@@ -1,6 +1,7 @@
 // Context life cycle, mesh set-up (geometry, colouring, node-block sparsity
 // pattern), material table and boundary data.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 
 #include "common.hpp"
@@ -229,6 +230,8 @@ void colour_elements(int n, int m, const int32_t* tets, std::vector<int>& perm, 
 extern "C" int32_t hfsi_abi_version(void) { return 1; }
 
 namespace {
+std::atomic<int> g_live_contexts{0};  // the device block cache is trimmed when none is left
+
 // events and pinned host memory of a context (safe on partly created ones)
 void release_events(hfsi_ctx* c) {
   for (hipEvent_t* e : {&c->ev0, &c->ev1, &c->kev[0], &c->kev[1]})
@@ -260,6 +263,7 @@ extern "C" hfsi_status hfsi_create(hfsi_ctx** out, int device, void* stream) {
     return HFSI_E_HIP;
   }
   *out = c;
+  ++g_live_contexts;
   return HFSI_OK;
 }
 
@@ -267,9 +271,14 @@ extern "C" hfsi_status hfsi_destroy(hfsi_ctx* c) {
   if (!c) return HFSI_E_ARG;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  // the stream is idle: the context's device blocks become free for any stream
+  hfsi::tls_stream = c->stream;
+  hfsi::tls_idle = true;
   release_events(c);
   hfsi::mlp_free(c);
   delete c;
+  hfsi::tls_idle = false;
+  if (--g_live_contexts == 0) hfsi::dev_cache_trim();
   return HFSI_OK;
 }
 

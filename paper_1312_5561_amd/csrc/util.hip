@@ -1,7 +1,103 @@
-// Device utilities: exclusive scan and sums used across the library.
+// Device utilities: the device block cache, exclusive scan and sums used
+// across the library.
+#include <map>
+#include <mutex>
+
 #include "common.hpp"
 
 namespace hfsi {
+
+thread_local hipStream_t tls_stream = nullptr;
+thread_local bool tls_idle = false;
+
+namespace {
+
+struct Block {
+  void* p;
+  hipStream_t stream;  // stream of its last use
+  bool idle;           // released after that stream was synchronised
+};
+
+struct BlockCache {
+  std::mutex m;
+  std::map<int, std::multimap<size_t, Block>> free;  // device -> size -> block
+};
+
+BlockCache& cache() {
+  static BlockCache* c = new BlockCache();  // outlives every static destructor
+  return *c;
+}
+
+// take a cached block of [bytes, 2 bytes] that the current stream may use
+void* take(int dev, size_t bytes, size_t* cap) {
+  std::lock_guard<std::mutex> g(cache().m);
+  auto& mm = cache().free[dev];
+  for (auto it = mm.lower_bound(bytes); it != mm.end() && it->first <= 2 * bytes; ++it) {
+    if (it->second.idle || it->second.stream == tls_stream) {
+      void* p = it->second.p;
+      *cap = it->first;
+      mm.erase(it);
+      return p;
+    }
+  }
+  return nullptr;
+}
+
+// hipFree the idle blocks of one device (and, after synchronising it, the
+// current stream's own)
+void free_blocks(int dev, bool own_stream) {
+  if (own_stream) (void)hipStreamSynchronize(tls_stream);
+  std::lock_guard<std::mutex> g(cache().m);
+  auto& mm = cache().free[dev];
+  for (auto it = mm.begin(); it != mm.end();) {
+    if (it->second.idle || (own_stream && it->second.stream == tls_stream)) {
+      (void)hipFree(it->second.p);
+      it = mm.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+}  // namespace
+
+void* dev_alloc(size_t bytes, size_t* cap, int* dev) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  HIP_CHECK(hipGetDevice(dev));
+  if (void* p = take(*dev, bytes, cap)) return p;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    free_blocks(*dev, true);
+    e = hipMalloc(&p, bytes);
+  }
+  if (e != hipSuccess)
+    fail(e == hipErrorOutOfMemory ? HFSI_E_OOM : HFSI_E_HIP,
+         std::string("hipMalloc of ") + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+  *cap = bytes;
+  return p;
+}
+
+void dev_release(void* p, size_t cap, int dev) {
+  std::lock_guard<std::mutex> g(cache().m);
+  cache().free[dev].insert({cap, Block{p, tls_stream, tls_idle}});
+}
+
+void dev_cache_trim() {
+  std::lock_guard<std::mutex> g(cache().m);
+  for (auto& kv : cache().free) {
+    for (auto it = kv.second.begin(); it != kv.second.end();) {
+      if (it->second.idle) {
+        (void)hipSetDevice(kv.first);
+        (void)hipFree(it->second.p);
+        it = kv.second.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+}
 
 namespace {
 
