@@ -24,24 +24,31 @@ namespace {
 constexpr int8_t ST_U = 0, ST_C = 1, ST_F = -1;
 
 // ------------------------------------------------------------ strength
-__global__ void k_strength(int n, const int* __restrict__ ptr, const int* __restrict__ col,
-                           const double* __restrict__ val, const int* __restrict__ comp, double theta,
-                           uint8_t* __restrict__ strong) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+// 8 lanes per row; the diagonal (held by one lane) and the row maximum are
+// combined exactly, so the flags do not depend on the lane split
+__global__ void __launch_bounds__(256)
+k_strength(int n, const int* __restrict__ ptr, const int* __restrict__ col, const double* __restrict__ val,
+           const int* __restrict__ comp, double theta, uint8_t* __restrict__ strong) {
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const int lane = threadIdx.x & 7;
   if (i >= n) return;
   const int lo = ptr[i], hi = ptr[i + 1], ci = comp[i];
   double aii = 0.0;
-  for (int e = lo; e < hi; ++e)
+  for (int e = lo + lane; e < hi; e += 8)
     if (col[e] == i) aii = val[e];
+#pragma unroll
+  for (int o = 4; o > 0; o >>= 1) aii += __shfl_xor(aii, o, 8);
   const double sg = aii < 0.0 ? -1.0 : 1.0;
   double mi = -INFINITY;
-  for (int e = lo; e < hi; ++e) {
-    int j = col[e];
+  for (int e = lo + lane; e < hi; e += 8) {
+    const int j = col[e];
     if (j != i && comp[j] == ci) mi = fmax(mi, -val[e] * sg);
   }
+#pragma unroll
+  for (int o = 4; o > 0; o >>= 1) mi = fmax(mi, __shfl_xor(mi, o, 8));
   const double thr = theta * mi;
-  for (int e = lo; e < hi; ++e) {
-    int j = col[e];
+  for (int e = lo + lane; e < hi; e += 8) {
+    const int j = col[e];
     strong[e] = (j != i && comp[j] == ci && mi > 0.0 && -val[e] * sg >= thr) ? 1 : 0;
   }
 }
@@ -786,8 +793,9 @@ __global__ void k_lanczos_init(int n, uint64_t seed, int stream, double* __restr
 // 16 lanes per row; dm = |diag A|^{-1/2}
 __global__ void k_lanczos_apply(int n, const int* __restrict__ ptr, const int* __restrict__ col,
                                 const double* __restrict__ val, const double* __restrict__ dm,
-                                const double* __restrict__ q, const double* __restrict__ qp, double beta,
-                                double* __restrict__ w) {
+                                const double* __restrict__ q, const double* __restrict__ qp,
+                                const double* __restrict__ betap, double* __restrict__ w) {
+  const double beta = betap ? betap[0] : 0.0;
   const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
   const int lane = threadIdx.x & 15;
   if (i >= n) return;
@@ -820,20 +828,55 @@ __global__ void k_dot_partial(int n, const double* __restrict__ x, const double*
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-__global__ void k_axpy_inplace(int n, double a, const double* __restrict__ x, double* __restrict__ y) {
+// y += (-a[0]) x
+__global__ void k_axpy_neg_dev(int n, const double* __restrict__ a, const double* __restrict__ x,
+                               double* __restrict__ y) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] += a * x[i];
+  if (i < n) y[i] += (-a[0]) * x[i];
 }
 
-__global__ void k_scale_copy(int n, double a, const double* __restrict__ x, double* __restrict__ y) {
+// y = (1 / d[0]) x
+__global__ void k_scale_inv_dev(int n, const double* __restrict__ d, const double* __restrict__ x,
+                                double* __restrict__ y) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = a * x[i];
+  if (i < n) y[i] = (1.0 / d[0]) * x[i];
+}
+
+// Sum of the 256 block partials of k_dot_partial in one block, in the order
+// of the library's two-stage device sum (the same value bit for bit).
+// mode 0: out[0] = sum; mode 1: out[0] = sqrt(sum); mode 2 (Lanczos beta of
+// step it): b = sqrt(sum), alpha = ab[it]; while not stopped, count the step
+// in kst[0] and either stop (b <= 1e-14 |alpha|, kst[1] = 1) or keep
+// ab[32 + it] = b.
+__global__ void __launch_bounds__(256)
+k_dot_finish(const double* __restrict__ part, int mode, double* __restrict__ out, double* __restrict__ ab,
+             int* __restrict__ kst, int it) {
+  __shared__ double sh[256];
+  sh[threadIdx.x] = part[threadIdx.x];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  if (mode == 0) {
+    out[0] = sh[0];
+  } else if (mode == 1) {
+    out[0] = sqrt(sh[0]);
+  } else {
+    const double b = sqrt(sh[0]);
+    if (kst[1]) return;
+    kst[0] = it + 1;
+    if (b <= 1e-14 * fabs(ab[it])) kst[1] = 1;
+    else ab[32 + it] = b;
+  }
 }
 
 // largest eigenvalue of the symmetric tridiagonal (alpha, beta) by bisection
 // on Sturm sequence counts (single thread; k <= 32)
-__global__ void k_tridiag_max(int k, const double* __restrict__ alpha, const double* __restrict__ beta,
-                              double* __restrict__ out) {
+__global__ void k_tridiag_max(const int* __restrict__ kp, const double* __restrict__ alpha,
+                              const double* __restrict__ beta, double* __restrict__ out) {
+  const int k = kp[0];
   double lo = 1e300, hi = -1e300;
   for (int i = 0; i < k; ++i) {
     double r = (i > 0 ? fabs(beta[i - 1]) : 0.0) + (i < k - 1 ? fabs(beta[i]) : 0.0);
@@ -901,57 +944,49 @@ namespace hfsi {
 
 namespace {
 
-double dot_dev(hfsi_ctx* c, const double* x, const double* y, int n) {
-  const int nb = 256;
-  c->kred.ensure(2 * nb);
-  k_dot_partial<<<nb, 256, 0, c->stream>>>(n, x, y, c->kred.p + nb);
-  HIP_LAUNCH_CHECK();
-  return device_sum(c, c->kred.p + nb, nb);
-}
-
-// Largest Ritz value of `steps` Lanczos steps on D^{-1/2} A D^{-1/2}.
+// Largest Ritz value of `steps` Lanczos steps on D^{-1/2} A D^{-1/2}.  The
+// recurrence coefficients stay on the device (ab: alpha[32], beta[32], the
+// result, the start norm; kst: steps kept, stopped); the host reads only the
+// result.
 double lanczos_max(hfsi_ctx* c, Level& L, int steps, uint64_t seed, int level) {
   const int n = L.n;
   hipStream_t s = c->stream;
-  DevBuf<double> q, qp, w, ab;
+  const int nb = 256, g = div_up(n, 256);
+  DevBuf<double> q, qp, w, ab, part;
+  DevBuf<int> kst;
   q.ensure(n); qp.zero(n, s); w.ensure(n);
-  ab.ensure(80);
-  k_lanczos_init<<<div_up(n, 256), 256, 0, s>>>(n, seed, 1000 + level, q.p);
+  ab.zero(72, s);
+  kst.zero(2, s);
+  part.ensure(nb);
+  k_lanczos_init<<<g, 256, 0, s>>>(n, seed, 1000 + level, q.p);
   HIP_LAUNCH_CHECK();
-  double nq = std::sqrt(dot_dev(c, q.p, q.p, n));
-  k_scale_copy<<<div_up(n, 256), 256, 0, s>>>(n, 1.0 / nq, q.p, q.p);
+  k_dot_partial<<<nb, 256, 0, s>>>(n, q.p, q.p, part.p);
+  k_dot_finish<<<1, 256, 0, s>>>(part.p, 1, ab.p + 65, ab.p, kst.p, 0);
+  k_scale_inv_dev<<<g, 256, 0, s>>>(n, ab.p + 65, q.p, q.p);
   HIP_LAUNCH_CHECK();
-  std::vector<double> alpha, beta;
-  double b = 0.0;
-  // |diag|^{-1} for the scaling
+  // |diag|^{-1/2} for the scaling
   DevBuf<double> dabs;
   DevBuf<float> dummy;
   dabs.ensure(n); dummy.ensure(n);
-  k_inv_diag<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, dabs.p, dummy.p);
+  k_inv_diag<<<g, 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, dabs.p, dummy.p);
   HIP_LAUNCH_CHECK();
-  k_rsqrt_abs<<<div_up(n, 256), 256, 0, s>>>(n, dabs.p, dabs.p);  // dabs <- |diag|^{-1/2}
+  k_rsqrt_abs<<<g, 256, 0, s>>>(n, dabs.p, dabs.p);  // dabs <- |diag|^{-1/2}
   HIP_LAUNCH_CHECK();
-  for (int it = 0; it < std::min(steps, n); ++it) {
+  const int steps_run = std::min(steps, std::min(n, 32));
+  for (int it = 0; it < steps_run; ++it) {
     k_lanczos_apply<<<div_up((long)n * 16, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, dabs.p, q.p, qp.p,
-                                                               b, w.p);
+                                                               it ? ab.p + 32 + it - 1 : nullptr, w.p);
+    k_dot_partial<<<nb, 256, 0, s>>>(n, q.p, w.p, part.p);
+    k_dot_finish<<<1, 256, 0, s>>>(part.p, 0, ab.p + it, ab.p, kst.p, it);        // alpha
+    k_axpy_neg_dev<<<g, 256, 0, s>>>(n, ab.p + it, q.p, w.p);
+    k_dot_partial<<<nb, 256, 0, s>>>(n, w.p, w.p, part.p);
+    k_dot_finish<<<1, 256, 0, s>>>(part.p, 2, nullptr, ab.p, kst.p, it);         // beta, stop test
     HIP_LAUNCH_CHECK();
-    const double a = dot_dev(c, q.p, w.p, n);
-    k_axpy_inplace<<<div_up(n, 256), 256, 0, s>>>(n, -a, q.p, w.p);
-    HIP_LAUNCH_CHECK();
-    alpha.push_back(a);
-    b = std::sqrt(dot_dev(c, w.p, w.p, n));
-    if (b <= 1e-14 * std::fabs(a)) break;
-    beta.push_back(b);
-    std::swap(q.p, qp.p);  // qp <- q
-    k_scale_copy<<<div_up(n, 256), 256, 0, s>>>(n, 1.0 / b, w.p, q.p);
+    std::swap(q, qp);  // qp <- q (whole buffers: the blocks may differ in size)
+    k_scale_inv_dev<<<g, 256, 0, s>>>(n, ab.p + 32 + it, w.p, q.p);
     HIP_LAUNCH_CHECK();
   }
-  const int k = (int)alpha.size();
-  std::vector<double> buf(64, 0.0);
-  for (int i = 0; i < k; ++i) buf[i] = alpha[i];
-  for (int i = 0; i + 1 < k && i < (int)beta.size(); ++i) buf[32 + i] = beta[i];
-  ab.upload(buf.data(), 64, s);
-  k_tridiag_max<<<1, 1, 0, s>>>(k, ab.p, ab.p + 32, ab.p + 64);
+  k_tridiag_max<<<1, 1, 0, s>>>(kst.p, ab.p, ab.p + 32, ab.p + 64);
   HIP_LAUNCH_CHECK();
   double lmax = 0.0;
   HIP_CHECK(hipMemcpyAsync(&lmax, ab.p + 64, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1143,7 +1178,7 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
     if (n <= prm.max_coarse || l + 1 >= prm.max_levels || l + 1 >= 32) break;
     // strength and PMIS
     L.strong.ensure(L.A.nnz);
-    k_strength<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.comp.p, prm.strength_theta,
+    k_strength<<<div_up((long)n * 8, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.comp.p, prm.strength_theta,
                                               L.strong.p);
     HIP_LAUNCH_CHECK();
     lam.zero(n, s);
