@@ -145,84 +145,14 @@ __device__ __forceinline__ int find_in(const int* __restrict__ a, int lo, int hi
   return lo;
 }
 
-// w_ij = -(a_ij + sum_{k in F*} a_ik abar_kj / sum_{m in C_i} abar_km)
-//        / (a_ii + sum_{weak same comp} a_in + sum_{k in F \ F*} a_ik),
-// every sum in ascending column order of the rows involved.
-__global__ void k_interp_fill(int n, const int* __restrict__ ptr, const int* __restrict__ col,
-                              const double* __restrict__ val, const uint8_t* __restrict__ strong,
-                              const int8_t* __restrict__ state, const int* __restrict__ comp,
-                              const int* __restrict__ cidx, const int* __restrict__ pptr, int* __restrict__ pcol,
-                              double* __restrict__ pval) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int p0 = pptr[i], p1 = pptr[i + 1];
-  if (state[i] == ST_C) {
-    pcol[p0] = cidx[i];
-    pval[p0] = 1.0;
-    return;
-  }
-  if (p1 == p0) return;
-  const int lo = ptr[i], hi = ptr[i + 1], ci = comp[i];
-  int q = p0;
-  double aii = 0.0;
-  for (int e = lo; e < hi; ++e) {
-    const int j = col[e];
-    if (j == i) aii = val[e];
-    if (strong[e] && state[j] == ST_C) {
-      pcol[q] = j;  // fine index for now
-      pval[q] = 0.0;
-      ++q;
-    }
-  }
-  double den = aii;
-  for (int e = lo; e < hi; ++e) {
-    const int k = col[e];
-    if (k == i || comp[k] != ci) continue;
-    const double a = val[e];
-    if (strong[e] && state[k] == ST_C) {
-      pval[find_in(pcol, p0, p1, k)] += a;
-    } else if (strong[e]) {
-      // one merge of row k with the sorted C_i list: a_kk and the sums of the
-      // negative and the positive couplings to C_i (both in ascending order)
-      const int klo = ptr[k], khi = ptr[k + 1];
-      double akk = 0.0, s_neg = 0.0, s_pos = 0.0;
-      for (int f = klo, b = p0; f < khi; ++f) {
-        const int mm = col[f];
-        if (mm == k) akk = val[f];
-        while (b < p1 && pcol[b] < mm) ++b;
-        if (b < p1 && pcol[b] == mm) {
-          const double v = val[f];
-          if (v < 0.0) s_neg += v;
-          else if (v > 0.0) s_pos += v;
-        }
-      }
-      const double sk = akk < 0.0 ? -1.0 : 1.0;
-      const double s = sk > 0.0 ? s_neg : s_pos;  // abar keeps the sign opposite to a_kk
-      if (s != 0.0) {
-        for (int f = klo, b = p0; f < khi; ++f) {
-          const int mm = col[f];
-          while (b < p1 && pcol[b] < mm) ++b;
-          if (b < p1 && pcol[b] == mm) {
-            const double v = val[f];
-            if (v * sk < 0.0) pval[b] += a * v / s;
-          }
-        }
-      } else {
-        den += a;
-      }
-    } else {
-      den += a;
-    }
-  }
-  for (int t = p0; t < p1; ++t) {
-    pval[t] = -pval[t] / den;
-    pcol[t] = cidx[pcol[t]];
-  }
-}
-
-// The same weights with 16 lanes per row: the C_i list and the numerators
-// live in LDS, the rows of strong F neighbours are scanned lane-parallel
-// (their sums s are tree-reduced; every other sum keeps the row order).
+// Modified classical interpolation of an F row i:
+//   w_ij = -(a_ij + sum_{k in F*} a_ik abar_kj / sum_{m in C_i} abar_km)
+//          / (a_ii + sum_{weak same comp} a_in + sum_{k in F \ F*} a_ik)
+// (C_i the strong C neighbours, F* the strong F neighbours with a non-zero
+// denominator, abar_km = a_km where its sign differs from a_kk's, else 0).
+// 16 lanes per row: the C_i list and the numerators live in LDS, the rows of
+// strong F neighbours are scanned lane-parallel (their sums s are
+// tree-reduced; every other sum keeps the row order).
 constexpr int CI_MAX = 64;
 __global__ void __launch_bounds__(256)
 k_interp_fill16(int n, const int* __restrict__ ptr, const int* __restrict__ col, const double* __restrict__ val,
@@ -718,67 +648,6 @@ __global__ void k_gj_extract(int n, const double* __restrict__ M, double* __rest
   if (t >= (long)n * n) return;
   const int r = (int)(t / n), j = (int)(t % n);
   inv[t] = M[(size_t)r * 2 * n + n + j];
-}
-
-// Gauss-Jordan elimination with partial pivoting in one workgroup.
-__global__ void __launch_bounds__(1024) k_gauss_jordan(int n, double* __restrict__ M, double* __restrict__ inv,
-                                                        int* __restrict__ singular) {
-  __shared__ double red_v[1024];
-  __shared__ int red_i[1024];
-  __shared__ double prow[1];
-  const int t = threadIdx.x, nt = blockDim.x, w = 2 * n;
-  for (int k = 0; k < n; ++k) {
-    double best = -1.0;
-    int bi = k;
-    for (int r = k + t; r < n; r += nt) {
-      double a = fabs(M[(size_t)r * w + k]);
-      if (a > best || (a == best && r < bi)) { best = a; bi = r; }
-    }
-    red_v[t] = best;
-    red_i[t] = bi;
-    __syncthreads();
-    for (int o = nt / 2; o > 0; o >>= 1) {
-      if (t < o) {
-        double a = red_v[t + o];
-        int ai = red_i[t + o];
-        if (a > red_v[t] || (a == red_v[t] && ai < red_i[t])) { red_v[t] = a; red_i[t] = ai; }
-      }
-      __syncthreads();
-    }
-    const int p = red_i[0];
-    if (red_v[0] == 0.0) {
-      if (t == 0) *singular = 1;
-      return;
-    }
-    if (p != k)
-      for (int j = t; j < w; j += nt) {
-        double x = M[(size_t)k * w + j];
-        M[(size_t)k * w + j] = M[(size_t)p * w + j];
-        M[(size_t)p * w + j] = x;
-      }
-    __syncthreads();
-    if (t == 0) prow[0] = 1.0 / M[(size_t)k * w + k];
-    __syncthreads();
-    const double ip = prow[0];
-    for (int j = t; j < w; j += nt) M[(size_t)k * w + j] *= ip;
-    __syncthreads();
-    // eliminate column k from every other row
-    // (32 rows x 32 columns of threads; columns of row k are read coalesced)
-    for (int r = t >> 5; r < n; r += nt >> 5) {
-      if (r == k) continue;
-      const double f = M[(size_t)r * w + k];
-      if (f == 0.0) continue;
-      for (int j = k + 1 + (t & 31); j < w; j += 32) M[(size_t)r * w + j] -= f * M[(size_t)k * w + j];
-    }
-    __syncthreads();
-    for (int r = t; r < n; r += nt)
-      if (r != k) M[(size_t)r * w + k] = 0.0;
-    __syncthreads();
-  }
-  for (long q = t; q < (long)n * n; q += nt) {
-    const int r = (int)(q / n), j = (int)(q % n);
-    inv[q] = M[(size_t)r * w + n + j];
-  }
 }
 
 // ------------------------------------------------------------ Lanczos
