@@ -93,8 +93,9 @@ typedef struct {
   double min_J;         /* smallest element J = det F                      */
 } hfsi_assembly_info;
 
-/* AMG parameters.  smoother: 0 = l1-Jacobi, 1 = Chebyshev (degree 2 on
- * D^{-1}A over [lmax/30, 1.1 lmax], lmax from 10 Lanczos steps).
+/* AMG parameters.  smoother: 0 = l1-Jacobi, 1 = Chebyshev (degree
+ * cheb_degree on D^{-1}A over [lmax/cheb_ratio, 1.1 lmax], lmax from 10
+ * Lanczos steps).
  * precision: 0 = fp64 V-cycle, 1 = fp32 V-cycle (coarsest solve stays fp64).
  * interp: 0 = classical, 1 = learned correction on level 0 (needs MLP
  * weights and lattice coordinates), with classical fallback when the
@@ -111,6 +112,8 @@ typedef struct {
   int32_t precision;
   int32_t interp;
   double fallback_rho;   /* default 0.5                                    */
+  int32_t cheb_degree;   /* Chebyshev polynomial degree, 1..8, default 2   */
+  double cheb_ratio;     /* lmax / lower bound of the interval, > 1, default 30 */
 } hfsi_amg_params;
 
 typedef struct {

@@ -241,6 +241,8 @@ class AmgParams:
     smoother: str = "chebyshev"   # or "l1jacobi"
     nu_pre: int = 1
     nu_post: int = 2
+    cheb_degree: int = 2
+    cheb_ratio: float = 30.0
     lanczos_steps: int = 10
     max_dense: int = 8192
 
@@ -291,14 +293,14 @@ def smooth(L, b, x, nu, prm):
             x = x + L.dinv * (b - L.A @ x)
         return x
     for _ in range(nu):
-        x = chebyshev(L.A, L.dinv, L.lam, b, x)
+        x = chebyshev(L.A, L.dinv, L.lam, b, x, prm.cheb_degree, prm.cheb_ratio)
     return x
 
 
-def chebyshev(A, dinv, lam, b, x, degree=2):
-    """Degree-k Chebyshev smoothing of D^{-1}A on [lam/30, 1.1 lam]
+def chebyshev(A, dinv, lam, b, x, degree=2, ratio=30.0):
+    """Degree-k Chebyshev smoothing of D^{-1}A on [lam/ratio, 1.1 lam]
     (three-term recurrence for the residual polynomial)."""
-    hi, lo = 1.1 * lam, lam / 30.0
+    hi, lo = 1.1 * lam, lam / ratio
     theta = 0.5 * (hi + lo)
     delta = 0.5 * (hi - lo)
     sigma = theta / delta

@@ -1035,6 +1035,8 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
   H.smoother = prm.smoother;
   H.nu_pre = prm.nu_pre;
   H.nu_post = prm.nu_post;
+  H.cheb_degree = prm.cheb_degree;
+  H.cheb_ratio = prm.cheb_ratio;
   int rounds_total = 0;
   DevBuf<int> lam, notmax, flag, rem;
   DevBuf<uint64_t> key;
@@ -1231,6 +1233,8 @@ void check_amg_params(const hfsi_amg_params* p) {
   if (p->smoother < 0 || p->smoother > 1 || p->nu_pre < 0 || p->nu_post < 0 || p->nu_pre + p->nu_post < 1)
     fail(HFSI_E_ARG, "amg params: bad smoother");
   if (p->precision < 0 || p->precision > 1) fail(HFSI_E_ARG, "amg params: bad precision");
+  if (p->cheb_degree < 1 || p->cheb_degree > 8 || !(p->cheb_ratio > 1.0))
+    fail(HFSI_E_ARG, "amg params: Chebyshev degree in 1..8 and ratio > 1");
   if (p->interp < 0 || p->interp > 1) fail(HFSI_E_ARG, "amg params: interp must be 0 (classical) or 1 (learned)");
 }
 

@@ -171,6 +171,8 @@ struct Hierarchy {
   int precision = 0;
   int smoother = 0;
   int nu_pre = 2, nu_post = 2;
+  int cheb_degree = 2;     // Chebyshev degree and interval [lmax / ratio, 1.1 lmax]
+  double cheb_ratio = 30.0;
   bool ready = false;
 };
 

@@ -706,7 +706,7 @@ double level_op_bytes(const hfsi_ctx* c, const Level& L, bool resid) {
 // Jacobi, 1/theta for Chebyshev on [lmax/30, 1.1 lmax]
 double first_step_coef(const Hierarchy& H, const Level& L) {
   if (H.smoother == 0) return 1.0;
-  const double hi = 1.1 * L.lmax, lo = L.lmax / 30.0;
+  const double hi = 1.1 * L.lmax, lo = L.lmax / H.cheb_ratio;
   return 1.0 / (0.5 * (hi + lo));
 }
 
@@ -752,10 +752,13 @@ T* smooth(hfsi_ctx* c, Level& L, const LevelView<T>& v, const T* b, T* xa, T* xb
     }
     return xa;
   }
-  // Chebyshev of degree 2 on D^{-1} A over [lmax/30, 1.1 lmax], nu times
-  const double hi = 1.1 * L.lmax, lo = L.lmax / 30.0;
+  // Chebyshev of degree H.cheb_degree on D^{-1} A over [lmax/ratio, 1.1 lmax],
+  // nu times: d_0 = D^{-1} r / theta, then
+  // d_q = rho_q rho_{q-1} d_{q-1} + (2 rho_q / delta) D^{-1} r with
+  // rho_0 = 1/sigma, rho_q = 1 / (2 sigma - rho_{q-1}); x += d_q each step
+  const double hi = 1.1 * L.lmax, lo = L.lmax / H.cheb_ratio;
   const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
-  const double rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
+  const double rho0 = 1.0 / sigma;
   T* d = v.r;  // direction vector (the residual buffer is free during smoothing)
   for (int k = 0; k < nu; ++k) {
     if (zero_start && k == 0) {
@@ -767,8 +770,13 @@ T* smooth(hfsi_ctx* c, Level& L, const LevelView<T>& v, const T* b, T* xa, T* xb
       level_op<T, OP_CHEB>(L, v, xa, b, xb, d, (T)0, (T)(1.0 / theta), s);
       std::swap(xa, xb);
     }
-    level_op<T, OP_CHEB>(L, v, xa, b, xb, d, (T)(rho1 * rho0), (T)(2.0 * rho1 / delta), s);
-    std::swap(xa, xb);
+    double rho = rho0;
+    for (int q = 1; q < H.cheb_degree; ++q) {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      level_op<T, OP_CHEB>(L, v, xa, b, xb, d, (T)(rn * rho), (T)(2.0 * rn / delta), s);
+      std::swap(xa, xb);
+      rho = rn;
+    }
   }
   return xa;
 }
