@@ -593,54 +593,61 @@ __global__ void k_dense_from_csr(int n, const int* __restrict__ ptr, const int* 
   for (int e = ptr[i]; e < ptr[i + 1]; ++e) row[col[e]] = val[e];
 }
 
-// Pivot step k of Gauss-Jordan with partial pivoting on M = [A | I] (n x 2n):
-// select the row of largest |M_rk|, r >= k (smallest index on ties), swap it
-// into row k and divide the row by its pivot.
-__global__ void __launch_bounds__(256) k_gj_pivot(int n, int k, double* __restrict__ M, int* __restrict__ singular) {
-  __shared__ double rv[256];
-  __shared__ int ri[256];
+// One Gauss-Jordan step on [A | I] (n x 2n, row-major) with partial
+// pivoting, from Min into Mout: every block finds the pivot row p of column k
+// (largest |value| among rows >= k, ties to the smallest row) in its first
+// wavefront, then each thread forms one entry j > k of the step's result:
+// row k = Min[p] / Min[p][k]; row r != k = Min[s] - Min[s][k] * row k with
+// s = k for r = p (the rows swap), s = r otherwise.  Columns <= k are never
+// read again.  Two buffers remove the read-after-write race between the
+// pivot row and the rows that use it.
+__global__ void __launch_bounds__(256)
+k_gj_step(int n, int k, const double* __restrict__ Min, double* __restrict__ Mout, int* __restrict__ singular) {
+  __shared__ int s_p;
+  __shared__ double s_ip;
   if (*singular) return;
-  const int t = threadIdx.x, w = 2 * n;
-  double best = -1.0;
-  int bi = k;
-  for (int r = k + t; r < n; r += 256) {
-    const double a = fabs(M[(size_t)r * w + k]);
-    if (a > best) { best = a; bi = r; }
-  }
-  rv[t] = best;
-  ri[t] = bi;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (t < o && (rv[t + o] > rv[t] || (rv[t + o] == rv[t] && ri[t + o] < ri[t]))) {
-      rv[t] = rv[t + o];
-      ri[t] = ri[t + o];
+  const size_t w = 2 * (size_t)n;
+  if (threadIdx.x < 64) {
+    double best = -1.0;
+    int bi = k;
+    for (int r = k + (int)threadIdx.x; r < n; r += 64) {
+      const double a = fabs(Min[(size_t)r * w + k]);
+      if (a > best) {
+        best = a;
+        bi = r;
+      }
     }
-    __syncthreads();
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if (threadIdx.x == 0) {
+      s_p = bi;
+      s_ip = best > 0.0 ? 1.0 / Min[(size_t)bi * w + k] : 0.0;
+      if (!(best > 0.0)) *singular = 1;
+    }
   }
-  const int p = ri[0];
-  if (!(rv[0] > 0.0)) {
-    if (t == 0) *singular = 1;
-    return;
-  }
-  const double ip = 1.0 / M[(size_t)p * w + k];
   __syncthreads();
-  for (int j = k + t; j < w; j += 256) {
-    const double xk = M[(size_t)k * w + j], xp = M[(size_t)p * w + j];
-    M[(size_t)k * w + j] = xp * ip;
-    if (p != k) M[(size_t)p * w + j] = xk;
-  }
-}
-
-// M_rj -= M_rk M_kj for r != k, j > k (column k itself is never read again)
-__global__ void k_gj_elim(int n, int k, double* __restrict__ M, const int* __restrict__ singular) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s_ip == 0.0) return;
+  const int p = s_p;
+  const double ip = s_ip;
   const long cols = 2L * n - k - 1;
-  if (t >= (long)n * cols || *singular) return;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)n * cols) return;
   const int r = (int)(t / cols);
   const int j = k + 1 + (int)(t - (long)r * cols);
-  if (r == k) return;
-  const size_t w = 2 * (size_t)n;
-  M[r * w + j] -= M[r * w + k] * M[k * w + j];
+  const double pk = Min[(size_t)p * w + j] * ip;  // entry j of the normalised pivot row
+  if (r == k) {
+    Mout[(size_t)k * w + j] = pk;
+  } else {
+    const int src = r == p ? k : r;
+    Mout[(size_t)r * w + j] = Min[(size_t)src * w + j] - Min[(size_t)src * w + k] * pk;
+  }
 }
 
 __global__ void k_gj_extract(int n, const double* __restrict__ M, double* __restrict__ inv) {
@@ -1146,22 +1153,24 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
   const int nc = Lc.n;
   if (nc > 4096) fail(HFSI_E_CAPACITY, "coarsest level larger than 4096 rows (coarsening stalled)");
   H.nc = nc;
-  DevBuf<double> M;
+  DevBuf<double> M, M2;
   DevBuf<int> sing;
   M.ensure(2 * (size_t)nc * nc);
+  M2.ensure(2 * (size_t)nc * nc);
   sing.zero(1, s);
   H.coarse_inv.ensure((size_t)nc * nc);
   H.cwork.ensure(2 * (size_t)nc);
   k_dense_from_csr<<<div_up(nc, 256), 256, 0, s>>>(nc, Lc.A.ptr.p, Lc.A.col.p, Lc.A.val.p, M.p);
   HIP_LAUNCH_CHECK();
-  // Gauss-Jordan on [A | I]: per pivot, one block selects and normalises the
-  // pivot row, then the whole grid eliminates the pivot column elsewhere.
+  // Gauss-Jordan on [A | I]: one launch per pivot, alternating buffers
+  double* gin = M.p;
+  double* gout = M2.p;
   for (int k = 0; k < nc; ++k) {
-    k_gj_pivot<<<1, 256, 0, s>>>(nc, k, M.p, sing.p);
     const long work = (long)nc * (2L * nc - k - 1);
-    if (work > 0) k_gj_elim<<<div_up(work, 256), 256, 0, s>>>(nc, k, M.p, sing.p);
+    k_gj_step<<<div_up(work, 256), 256, 0, s>>>(nc, k, gin, gout, sing.p);
+    std::swap(gin, gout);
   }
-  k_gj_extract<<<div_up((long)nc * nc, 256), 256, 0, s>>>(nc, M.p, H.coarse_inv.p);
+  k_gj_extract<<<div_up((long)nc * nc, 256), 256, 0, s>>>(nc, gin, H.coarse_inv.p);
   HIP_LAUNCH_CHECK();
   int sg = 0;
   HIP_CHECK(hipMemcpyAsync(&sg, sing.p, sizeof(int), hipMemcpyDeviceToHost, s));
