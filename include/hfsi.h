@@ -114,6 +114,11 @@ typedef struct {
   double fallback_rho;   /* default 0.5                                    */
   int32_t cheb_degree;   /* Chebyshev polynomial degree, 1..8, default 2   */
   double cheb_ratio;     /* lmax / lower bound of the interval, > 1, default 30 */
+  int32_t interp_kind;   /* 0 = modified classical (distance one), 1 = extended+i
+                            (distance two, De Sterck et al. 2008); with
+                            interp = 1 level 0 stays distance one          */
+  int32_t p_max;         /* extended+i: entries kept per row (largest |w|,
+                            rescaled to the row sum), 0 = all, default 4   */
 } hfsi_amg_params;
 
 typedef struct {

@@ -143,8 +143,77 @@ def interp_row(A, S_set, state, comp, i):
     return {j: -num[j] / den for j in Ci}
 
 
-def interpolation(A, S_ptr, S_idx, state, comp):
-    """P (n x n_c) and the coarse component array."""
+def interp_row_extpi(A, S_ptr, S_idx, state, comp, i, p_max=0):
+    """Weights {j: w_ij} of one F row by extended+i interpolation (De Sterck,
+    Falgout, Nolting, Yang, "Distance-two interpolation for parallel
+    algebraic multigrid", 2008), on same-component couplings:
+
+    Chat_i = C_i united with the strong C neighbours of every strong F
+    neighbour k of i;
+    w_ij = -(a_ij + sum_{k in F_i} a_ik abar_kj / s_k) / atilde_ii,
+    atilde_ii = a_ii + sum_{weak n not in Chat_i} a_in
+                + sum_{k in F_i} a_ik abar_ki / s_k,
+    s_k = sum_{l in Chat_i + {i}} abar_kl (a strong F neighbour with s_k = 0
+    is lumped into the diagonal instead), abar_kl = a_kl where its sign
+    differs from that of a_kk, else 0.  With p_max > 0 a row with more
+    candidates keeps the p_max largest |w| (compared in float32, ties to the
+    smaller column) and is rescaled to its full row sum.  Every sum runs in
+    ascending column order.
+    """
+    lo, hi = A.indptr[i], A.indptr[i + 1]
+    cols, vals = A.indices[lo:hi], A.data[lo:hi]
+    S_i = set(S_idx[S_ptr[i]:S_ptr[i + 1]].tolist())
+    Fs = [int(k) for k in cols if k in S_i and state[k] == F_]
+    chat = {int(j) for j in cols if j in S_i and state[j] == C_}
+    for k in Fs:
+        S_k = set(S_idx[S_ptr[k]:S_ptr[k + 1]].tolist())
+        chat |= {int(m) for m in A.indices[A.indptr[k]:A.indptr[k + 1]] if m in S_k and state[m] == C_}
+    if not chat:
+        return {}
+    num = {j: 0.0 for j in chat}
+    den = vals[cols == i][0]
+    for j, a in zip(cols, vals):
+        j = int(j)
+        if j == i or comp[j] != comp[i]:
+            continue
+        if j in chat:
+            num[j] += a
+        elif not (j in S_i and state[j] == F_):
+            den += a  # weak neighbour outside Chat_i: lumped
+    for k in Fs:
+        a_ik = vals[cols == k][0]
+        kc = A.indices[A.indptr[k]:A.indptr[k + 1]]
+        kv = A.data[A.indptr[k]:A.indptr[k + 1]]
+        sk = -1.0 if kv[kc == k][0] < 0 else 1.0
+        abar = {int(m): (a if a * sk < 0 else 0.0) for m, a in zip(kc, kv)}
+        s = 0.0
+        for m in sorted(abar):
+            if m in chat or m == i:
+                s += abar[m]
+        if s == 0.0:
+            den += a_ik
+            continue
+        for m in sorted(abar):
+            if m in chat:
+                num[m] += a_ik * abar[m] / s
+        den += a_ik * abar.get(i, 0.0) / s
+    w = {j: -num[j] / den for j in chat}
+    if p_max and len(w) > p_max:
+        keep = sorted(w, key=lambda j: (-float(np.float32(abs(w[j]))), j))[:p_max]
+        tot = 0.0
+        for j in sorted(w):
+            tot += w[j]
+        kept = 0.0
+        for j in sorted(keep):
+            kept += w[j]
+        f = tot / kept if kept != 0.0 else 1.0
+        w = {j: w[j] * f for j in keep}
+    return w
+
+
+def interpolation(A, S_ptr, S_idx, state, comp, kind="classical", p_max=0):
+    """P (n x n_c) and the coarse component array; kind "classical"
+    (interp_row) or "ext+i" (interp_row_extpi with truncation p_max)."""
     A = A.tocsr()
     n = A.shape[0]
     cidx = np.cumsum(state == C_) - 1
@@ -154,8 +223,11 @@ def interpolation(A, S_ptr, S_idx, state, comp):
         if state[i] == C_:
             rows.append(i); cols.append(cidx[i]); vals.append(1.0)
             continue
-        S_set = set(S_idx[S_ptr[i]:S_ptr[i + 1]].tolist())
-        w = interp_row(A, S_set, state, comp, i)
+        if kind == "ext+i":
+            w = interp_row_extpi(A, S_ptr, S_idx, state, comp, i, p_max)
+        else:
+            S_set = set(S_idx[S_ptr[i]:S_ptr[i + 1]].tolist())
+            w = interp_row(A, S_set, state, comp, i)
         for j in sorted(w):
             rows.append(i); cols.append(cidx[j]); vals.append(w[j])
     P = sp.csr_matrix((np.array(vals), (np.array(rows, np.int64), np.array(cols, np.int64))), shape=(n, nc))
@@ -243,6 +315,8 @@ class AmgParams:
     nu_post: int = 2
     cheb_degree: int = 2
     cheb_ratio: float = 30.0
+    interp: str = "classical"      # or "ext+i"
+    p_max: int = 4                 # ext+i truncation (0: none)
     lanczos_steps: int = 10
     max_dense: int = 8192
 
@@ -268,7 +342,7 @@ def setup(A, comp, prm: AmgParams = AmgParams()):
         nc = int((st == C_).sum())
         if nc == 0 or nc > 0.9 * n:
             break
-        P, ccomp = interpolation(L.A, S[0], S[1], st, L.comp)
+        P, ccomp = interpolation(L.A, S[0], S[1], st, L.comp, prm.interp, prm.p_max)
         L.S, L.state, L.P, L.R = S, st, P, P.T.tocsr()
         levels.append(Level(galerkin(L.A, P), ccomp))
     last = levels[-1]

@@ -253,6 +253,260 @@ k_interp_fill16(int n, const int* __restrict__ ptr, const int* __restrict__ col,
   }
 }
 
+// Extended+i interpolation (De Sterck, Falgout, Nolting, Yang 2008) on
+// same-component couplings, 16 lanes per row.  For an F row i the candidate
+// set Chat_i (strong C neighbours of i and of its strong F neighbours) is
+// built in an LDS hash table and ranked by column; then
+//   w_ij = -(a_ij + sum_{k in F_i} a_ik abar_kj / s_k) / atilde_ii,
+//   atilde_ii = a_ii + sum_{weak n not in Chat_i} a_in + sum_k a_ik abar_ki / s_k,
+//   s_k = sum_{l in Chat_i + {i}} abar_kl (s_k = 0: a_ik lumped instead).
+// With p_max > 0 a longer row keeps its p_max largest |w| (float32 keys,
+// ties to the smaller column), rescaled to the full row sum.  FILL = false
+// writes the entry count of each row, FILL = true the entries (ascending
+// columns).  Sums over a row are lane-strided and tree-reduced.
+constexpr int XH = 128;    // hash slots per row
+constexpr int XMAX = 96;   // candidates per row
+constexpr int XQ = 4;      // entries of a neighbour row each lane keeps in registers (rows up to 64)
+__device__ __forceinline__ int xh_slot(int key) { return (int)(((unsigned)key * 2654435761u) >> 25); }
+
+template <bool FILL>
+__global__ void __launch_bounds__(256)
+k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const double* __restrict__ val,
+        const uint8_t* __restrict__ strong, const int8_t* __restrict__ state, const int* __restrict__ comp,
+        const int* __restrict__ cidx, int p_max, int* __restrict__ cnt, const int* __restrict__ pptr,
+        int* __restrict__ pcol, double* __restrict__ pval, int* __restrict__ overflow) {
+  __shared__ int h_key[16][XH];
+  __shared__ int h_rank[16][XH];
+  __shared__ int s_mem[16][XMAX];   // members in insertion order, then by rank
+  __shared__ int s_sorted[16][XMAX];
+  __shared__ double s_num[16][XMAX];
+  __shared__ int s_cnt[16];
+  const int g = threadIdx.x >> 4, lane = threadIdx.x & 15;
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const bool row = i < n && state[i] != ST_C;
+  for (int t = lane; t < XH; t += 16) h_key[g][t] = -1;
+  if (lane == 0) s_cnt[g] = 0;
+  __syncthreads();
+  // ---- candidates
+  if (row) {
+    auto insert = [&](int key) {
+      int h = xh_slot(key);
+      for (int probe = 0; probe < XH; ++probe) {
+        const int old = atomicCAS(&h_key[g][h], -1, key);
+        if (old == -1) {
+          const int at = atomicAdd(&s_cnt[g], 1);
+          if (at < XMAX) s_mem[g][at] = key;
+          return;
+        }
+        if (old == key) return;
+        h = (h + 1) & (XH - 1);
+      }
+    };
+    const int lo = ptr[i], hi = ptr[i + 1];
+    for (int e = lo + lane; e < hi; e += 16) {
+      const int j = col[e];
+      if (strong[e] && state[j] == ST_C) insert(j);
+    }
+    for (int e = lo; e < hi; ++e) {
+      const int k = col[e];
+      if (!strong[e] || state[k] == ST_C) continue;
+      for (int f = ptr[k] + lane; f < ptr[k + 1]; f += 16) {
+        const int m = col[f];
+        if (strong[f] && state[m] == ST_C) insert(m);
+      }
+    }
+  }
+  __syncthreads();
+  const int m = s_cnt[g];
+  if (row && m > XMAX && lane == 0) atomicOr(overflow, 1);
+  if (!FILL) {
+    if (i < n && lane == 0)
+      cnt[i] = state[i] == ST_C ? 1 : (m == 0 || m > XMAX ? 0 : (p_max > 0 && m > p_max ? p_max : m));
+    return;
+  }
+  const bool work = row && m > 0 && m <= XMAX;
+  // ---- rank by column
+  if (work) {
+    for (int t = lane; t < m; t += 16) {
+      const int key = s_mem[g][t];
+      int r = 0;
+      for (int u = 0; u < m; ++u) r += s_mem[g][u] < key;
+      s_sorted[g][r] = key;
+      s_num[g][r] = 0.0;
+      int h = xh_slot(key);
+      while (h_key[g][h] != key) h = (h + 1) & (XH - 1);
+      h_rank[g][h] = r;
+    }
+  }
+  __syncthreads();
+  auto rank_of = [&](int key) -> int {
+    int h = xh_slot(key);
+    for (int probe = 0; probe < XH; ++probe) {
+      const int kk = h_key[g][h];
+      if (kk == key) return h_rank[g][h];
+      if (kk == -1) return -1;
+      h = (h + 1) & (XH - 1);
+    }
+    return -1;
+  };
+  double den = 0.0;
+  if (work) {
+    const int lo = ptr[i], hi = ptr[i + 1], ci = comp[i];
+    // row i: direct couplings to Chat_i, weak ones lumped, the diagonal
+    double dpart = 0.0;
+    for (int e = lo + lane; e < hi; e += 16) {
+      const int j = col[e];
+      if (comp[j] != ci) continue;
+      const double a = val[e];
+      if (j == i) {
+        dpart += a;
+        continue;
+      }
+      const int r = rank_of(j);
+      if (r >= 0) s_num[g][r] += a;
+      else if (!(strong[e] && state[j] == ST_F)) dpart += a;
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) dpart += __shfl_xor(dpart, o, 16);
+    den = dpart;
+    // strong F neighbours, in row order
+    for (int e = lo; e < hi; ++e) {
+      const int k = col[e];
+      if (!strong[e] || state[k] != ST_F) continue;
+      const double a_ik = val[e];
+      const int klo = ptr[k], khi = ptr[k + 1];
+      double akk = 0.0, s_neg = 0.0, s_pos = 0.0, ki_neg = 0.0, ki_pos = 0.0;
+      int c_r[XQ];        // this lane's entries of row k: rank in Chat_i (or -1) and value
+      double c_v[XQ];
+#pragma unroll
+      for (int q = 0; q < XQ; ++q) {
+        c_r[q] = -1;
+        c_v[q] = 0.0;
+      }
+      int q = 0;
+      for (int f = klo + lane; f < khi; f += 16, ++q) {
+        const int mm = col[f];
+        const double v = val[f];
+        if (mm == k) akk = v;
+        const int r = mm == i ? -1 : rank_of(mm);
+        if (q < XQ) {
+          c_r[q] = r;
+          c_v[q] = v;
+        }
+        if (mm == i || r >= 0) {
+          if (v < 0.0) s_neg += v;
+          else if (v > 0.0) s_pos += v;
+        }
+        if (mm == i) {
+          if (v < 0.0) ki_neg = v;
+          else ki_pos = v;
+        }
+      }
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) {
+        akk += __shfl_xor(akk, o, 16);
+        s_neg += __shfl_xor(s_neg, o, 16);
+        s_pos += __shfl_xor(s_pos, o, 16);
+        ki_neg += __shfl_xor(ki_neg, o, 16);
+        ki_pos += __shfl_xor(ki_pos, o, 16);
+      }
+      const double sk = akk < 0.0 ? -1.0 : 1.0;
+      const double sden = sk > 0.0 ? s_neg : s_pos;
+      if (sden == 0.0) {
+        den += a_ik;
+        continue;
+      }
+      q = 0;
+      for (int f = klo + lane; f < khi; f += 16, ++q) {
+        int r = -1;
+        double v = 0.0;
+        if (q < XQ) {
+#pragma unroll
+          for (int u = 0; u < XQ; ++u)
+            if (u == q) {
+              r = c_r[u];
+              v = c_v[u];
+            }
+        } else {
+          const int mm = col[f];
+          r = mm == i ? -1 : rank_of(mm);
+          v = val[f];
+        }
+        if (r < 0) continue;
+        if (v * sk < 0.0) s_num[g][r] += a_ik * v / sden;  // distinct columns: one lane per slot
+      }
+      const double aki = sk > 0.0 ? ki_neg : ki_pos;
+      den += a_ik * aki / sden;
+    }
+  }
+  __syncthreads();
+  // ---- weights (in place), selection ranks, output in ascending columns
+  if (work)
+    for (int t = lane; t < m; t += 16) s_num[g][t] = -s_num[g][t] / den;
+  __syncthreads();
+  const bool trunc = work && p_max > 0 && m > p_max;
+  int* sel = s_mem[g];  // the insertion list is no longer needed
+  if (trunc)
+    for (int t = lane; t < m; t += 16) {
+      const float key = fabsf((float)s_num[g][t]);
+      int r = 0;
+      for (int u = 0; u < m; ++u) {
+        const float ku = fabsf((float)s_num[g][u]);
+        r += ku > key || (ku == key && u < t);
+      }
+      sel[t] = r;
+    }
+  __syncthreads();
+  if (work) {
+    double tot = 0.0, kept = 0.0;
+    for (int t = lane; t < m; t += 16) {
+      tot += s_num[g][t];
+      if (trunc && sel[t] < p_max) kept += s_num[g][t];
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+      tot += __shfl_xor(tot, o, 16);
+      kept += __shfl_xor(kept, o, 16);
+    }
+    const double scale = trunc && kept != 0.0 ? tot / kept : 1.0;
+    // pptr == nullptr: rows go to a fixed stride of p_max entries, counts to cnt
+    const long p0 = pptr ? (long)pptr[i] : (long)i * p_max;
+    if (!pptr && lane == 0) cnt[i] = trunc ? p_max : m;
+    for (int t = lane; t < m; t += 16) {
+      int pos = t;
+      if (trunc) {
+        if (sel[t] >= p_max) continue;
+        pos = 0;
+        for (int u = 0; u < t; ++u) pos += sel[u] < p_max;
+      }
+      pcol[p0 + pos] = cidx[s_sorted[g][t]];
+      pval[p0 + pos] = trunc ? s_num[g][t] * scale : s_num[g][t];
+    }
+  }
+  if (i < n && lane == 0) {
+    if (state[i] == ST_C) {
+      const long p0 = pptr ? (long)pptr[i] : (long)i * p_max;
+      pcol[p0] = cidx[i];
+      pval[p0] = 1.0;
+      if (!pptr) cnt[i] = 1;
+    } else if (!pptr && !work) {
+      cnt[i] = 0;
+    }
+  }
+}
+
+// copy rows written at a fixed stride into CSR order
+__global__ void k_compact_rows(int n, int stride, const int* __restrict__ ptr, const int* __restrict__ tcol,
+                               const double* __restrict__ tval, int* __restrict__ col, double* __restrict__ val) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const long src = (long)i * stride;
+  for (int q = ptr[i]; q < ptr[i + 1]; ++q) {
+    col[q] = tcol[src + q - ptr[i]];
+    val[q] = tval[src + q - ptr[i]];
+  }
+}
+
 // ------------------------------------------------------------ transpose
 __global__ void k_count_cols(int n, const int* __restrict__ ptr, const int* __restrict__ col, int* __restrict__ cnt) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1095,7 +1349,29 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
     DevBuf<int> cnt;
     cnt.ensure(n + 1);
     HIP_CHECK(hipMemsetAsync(cnt.p + n, 0, sizeof(int), s));
-    k_interp_count<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.strong.p, L.state.p, cnt.p);
+    // extended+i on every level, except level 0 of the learned interpolation
+    // (its network corrects the distance-one weights)
+    const bool extpi = prm.interp_kind == 1 && !(l == 0 && prm.interp == 1);
+    DevBuf<int> ovf;
+    ovf.zero(1, s);
+    // with truncation the rows have at most p_max entries: one pass writes
+    // counts and entries at a fixed stride, compacted after the scan
+    const bool strided = extpi && prm.p_max > 0;
+    DevBuf<int> tcol;
+    DevBuf<double> tval;
+    if (strided) {
+      tcol.ensure((size_t)n * prm.p_max);
+      tval.ensure((size_t)n * prm.p_max);
+      k_extpi<true><<<div_up((long)n * 16, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p,
+                                                               L.state.p, L.comp.p, L.cidx.p, prm.p_max, cnt.p,
+                                                               nullptr, tcol.p, tval.p, ovf.p);
+    } else if (extpi) {
+      k_extpi<false><<<div_up((long)n * 16, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p,
+                                                                L.state.p, L.comp.p, L.cidx.p, prm.p_max, cnt.p,
+                                                                nullptr, nullptr, nullptr, ovf.p);
+    } else {
+      k_interp_count<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.strong.p, L.state.p, cnt.p);
+    }
     HIP_LAUNCH_CHECK();
     L.P.rows = n;
     L.P.cols = nc;
@@ -1104,16 +1380,23 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
     L.P.col.ensure(L.P.nnz);
     L.P.val.ensure(L.P.nnz);
     {
-      DevBuf<int> ovf;
-      ovf.zero(1, s);
-      k_interp_fill16<<<div_up((long)n * 16, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p,
-                                                                 L.state.p, L.comp.p, L.cidx.p, L.P.ptr.p, L.P.col.p,
-                                                                 L.P.val.p, ovf.p);
+      if (strided)
+        k_compact_rows<<<div_up(n, 256), 256, 0, s>>>(n, prm.p_max, L.P.ptr.p, tcol.p, tval.p, L.P.col.p, L.P.val.p);
+      else if (extpi)
+        k_extpi<true><<<div_up((long)n * 16, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p,
+                                                                 L.state.p, L.comp.p, L.cidx.p, prm.p_max, nullptr,
+                                                                 L.P.ptr.p, L.P.col.p, L.P.val.p, ovf.p);
+      else
+        k_interp_fill16<<<div_up((long)n * 16, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p,
+                                                                   L.state.p, L.comp.p, L.cidx.p, L.P.ptr.p,
+                                                                   L.P.col.p, L.P.val.p, ovf.p);
       HIP_LAUNCH_CHECK();
       int o = 0;
       HIP_CHECK(hipMemcpyAsync(&o, ovf.p, sizeof(int), hipMemcpyDeviceToHost, s));
       HIP_CHECK(hipStreamSynchronize(s));
-      if (o) fail(HFSI_E_CAPACITY, "interpolation: a row has more than 64 strong C neighbours");
+      if (o)
+        fail(HFSI_E_CAPACITY, extpi ? "extended interpolation: a row has more than 96 candidate C points"
+                                    : "interpolation: a row has more than 64 strong C neighbours");
     }
     if (l == 0 && prm.interp == 1) learned_correction(c, L);
     transpose(c, L.P, L.R);
@@ -1244,6 +1527,8 @@ void check_amg_params(const hfsi_amg_params* p) {
   if (p->precision < 0 || p->precision > 1) fail(HFSI_E_ARG, "amg params: bad precision");
   if (p->cheb_degree < 1 || p->cheb_degree > 8 || !(p->cheb_ratio > 1.0))
     fail(HFSI_E_ARG, "amg params: Chebyshev degree in 1..8 and ratio > 1");
+  if (p->interp_kind < 0 || p->interp_kind > 1 || p->p_max < 0)
+    fail(HFSI_E_ARG, "amg params: interp_kind 0 or 1, p_max >= 0");
   if (p->interp < 0 || p->interp > 1) fail(HFSI_E_ARG, "amg params: interp must be 0 (classical) or 1 (learned)");
 }
 

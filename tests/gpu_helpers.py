@@ -47,14 +47,14 @@ def gpu_hierarchy_to_oracle(ctx, info, prm: amg.AmgParams):
 
 
 def amg_prm_pair(lib, smoother=0, precision=0, max_coarse=500, theta=0.15, seed=12345, nu=2, nu_post=None,
-                 cheb=(2, 30.0)):
+                 cheb=(2, 30.0), kind="classical", p_max=4):
     nu_pre, nu_post = nu, nu if nu_post is None else nu_post
     g = lib.amg_params(theta=theta, max_coarse=max_coarse, seed=seed, smoother=smoother, nu_pre=nu_pre, nu_post=nu_post,
-                       cheb_degree=cheb[0], cheb_ratio=cheb[1],
+                       cheb_degree=cheb[0], cheb_ratio=cheb[1], interp_kind=1 if kind == "ext+i" else 0, p_max=p_max,
                        precision=precision)
     o = amg.AmgParams(theta=theta, max_coarse=max_coarse, seed=seed,
                       smoother="l1jacobi" if smoother == 0 else "chebyshev", nu_pre=nu_pre, nu_post=nu_post,
-                      cheb_degree=cheb[0], cheb_ratio=cheb[1])
+                      cheb_degree=cheb[0], cheb_ratio=cheb[1], interp=kind, p_max=p_max)
     return g, o
 
 

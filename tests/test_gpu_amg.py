@@ -17,7 +17,7 @@ from oracle import amg
 pytestmark = pytest.mark.gpu
 
 
-def _check_levels(ctx, info, theta, seed, rtol=1e-12):
+def _check_levels(ctx, info, theta, seed, rtol=1e-12, kind="classical", p_max=4):
     for l in range(info.levels - 1):
         A = export_level_matrix(ctx, l, 0)
         comp = ctx.amg_export(l, 4)
@@ -33,7 +33,7 @@ def _check_levels(ctx, info, theta, seed, rtol=1e-12):
         o_st = amg.pmis(S_ptr, S_idx, A.shape[0], seed, l)
         assert np.array_equal(st, o_st), f"PMIS splitting differs on level {l}"
         P = export_level_matrix(ctx, l, 1)
-        Po, _ = amg.interpolation(A, S_ptr, S_idx, o_st, comp)
+        Po, _ = amg.interpolation(A, S_ptr, S_idx, o_st, comp, kind, p_max)
         assert np.array_equal(P.indptr, Po.indptr) and np.array_equal(P.indices, Po.indices), f"P pattern level {l}"
         assert np.abs(P.data - Po.data).max() <= rtol * max(1.0, np.abs(Po.data).max())
         Ac = export_level_matrix(ctx, l + 1, 0)
@@ -42,10 +42,13 @@ def _check_levels(ctx, info, theta, seed, rtol=1e-12):
         assert np.abs(Ac.data - Aco.data).max() <= rtol * np.abs(Aco.data).max()
 
 
-@pytest.mark.parametrize("case,theta", [("cube8", 0.15), ("cube8", 0.5), ("cube5_jitter_state", 0.15),
-                                        ("tube_small", 0.15), ("laplacian3d", 0.15)])
-def test_hierarchy_matches_oracle_level_by_level(lib, case, theta):
-    print(f"[amg parity] case={case} theta={theta}", flush=True)
+@pytest.mark.parametrize("case,theta,kind,p_max", [
+    ("cube8", 0.15, "classical", 4), ("cube8", 0.5, "classical", 4), ("cube5_jitter_state", 0.15, "classical", 4),
+    ("tube_small", 0.15, "classical", 4), ("laplacian3d", 0.15, "classical", 4),
+    ("cube8", 0.15, "ext+i", 4), ("cube8", 0.15, "ext+i", 0), ("cube5_jitter_state", 0.15, "ext+i", 4),
+    ("tube_small", 0.15, "ext+i", 4), ("laplacian3d", 0.15, "ext+i", 3), ("laplacian3d", 0.25, "ext+i", 0)])
+def test_hierarchy_matches_oracle_level_by_level(lib, case, theta, kind, p_max):
+    print(f"[amg parity] case={case} theta={theta} interp={kind} p_max={p_max}", flush=True)
     if case == "laplacian3d":
         import test_oracle_amg as T
         A = T.laplacian(14, 13, 12)
@@ -62,13 +65,13 @@ def test_hierarchy_matches_oracle_level_by_level(lib, case, theta):
             v = synth.random_state(prob, 6, u_scale=0.02, p_scale=0.5).ravel()
         _, K, b, A, B2, s = oracle_system(prob, v, 0.3)
         comp = np.tile(np.arange(3, dtype=np.int32), prob.n_nodes)
-    gprm, oprm = amg_prm_pair(lib, max_coarse=50, theta=theta)
+    gprm, oprm = amg_prm_pair(lib, max_coarse=50, theta=theta, kind=kind, p_max=p_max)
     ctx = lib.Context(0)
     info = ctx.amg_setup_csr(A.indptr, A.indices, A.data, comp, gprm)
     assert info.levels >= 2
     L0 = export_level_matrix(ctx, 0, 0)
     assert np.array_equal(L0.data, A.data)
-    _check_levels(ctx, info, oprm.theta, oprm.seed)
+    _check_levels(ctx, info, oprm.theta, oprm.seed, kind=kind, p_max=p_max)
 
 
 def test_full_size_cube48_splitting_and_sampled_rows(lib):

@@ -6,7 +6,10 @@
   symmetrised strength graph, every point decided, every F point with
   lambda > 0 strongly depends on a C point);
 * classical interpolation reproduces constants on zero-row-sum matrices
-  and is the identity on C rows;
+  and is the identity on C rows; so does extended+i, with and without
+  truncation (which rescales to the row sum); on the path C-F-F-C it gives
+  the linear interpolant (2/3, 1/3) through the distance-two C point, and a
+  truncated row keeps the largest weights;
 * the Galerkin product equals the dense P^T A P;
 * l1-Jacobi never increases the A-norm of the error for SPD A;
 * the Chebyshev smoother damps the extreme eigen-components by exactly
@@ -98,6 +101,60 @@ def test_interpolation_preserves_constants():
     for i in np.flatnonzero(st == amg.C_):
         row = P.getrow(i)
         assert row.nnz == 1 and row.indices[0] == cidx[i] and row.data[0] == 1.0
+
+
+@pytest.mark.parametrize("p_max", [0, 4, 2])
+def test_extpi_preserves_constants(p_max):
+    A = laplacian(10, 9, 4, neumann=True)  # zero row sums
+    comp = np.zeros(A.shape[0], np.int64)
+    ptr, idx = amg.strength(A, comp, 0.25)
+    st = amg.pmis(ptr, idx, A.shape[0], 7, 0)
+    P, _ = amg.interpolation(A, ptr, idx, st, comp, "ext+i", p_max)
+    Pc, _ = amg.interpolation(A, ptr, idx, st, comp)
+    lens = np.diff(P.indptr)
+    if p_max:
+        assert lens.max() <= p_max
+    else:  # distance-two points make the rows longer than classical ones
+        assert lens.sum() > np.diff(Pc.indptr).sum()
+    rs = np.asarray(P.sum(axis=1)).ravel()
+    assert np.allclose(rs[lens > 0], 1.0, atol=1e-13)
+    cidx = np.cumsum(st == amg.C_) - 1
+    for i in np.flatnonzero(st == amg.C_):
+        row = P.getrow(i)
+        assert row.nnz == 1 and row.indices[0] == cidx[i] and row.data[0] == 1.0
+
+
+def test_extpi_is_linear_on_a_path():
+    # 1D Laplacian on 0-1-2-3 (Dirichlet-free interior stencil), states C F F C:
+    # node 1 sees C point 0 directly and C point 3 through its strong F
+    # neighbour 2; the linear interpolant at 1 is 2/3 u_0 + 1/3 u_3
+    A = sp.csr_matrix(np.array([[1.0, -1, 0, 0], [-1, 2, -1, 0], [0, -1, 2, -1], [0, 0, -1, 1]]))
+    comp = np.zeros(4, np.int64)
+    ptr, idx = amg.strength(A, comp, 0.25)
+    st = np.array([amg.C_, amg.F_, amg.F_, amg.C_], np.int8)
+    w = amg.interp_row_extpi(A, ptr, idx, st, comp, 1)
+    assert set(w) == {0, 3}
+    assert abs(w[0] - 2.0 / 3.0) < 1e-15 and abs(w[3] - 1.0 / 3.0) < 1e-15
+    assert amg.interp_row(A, set(idx[ptr[1]:ptr[2]].tolist()), st, comp, 1) == pytest.approx({0: 1.0})
+
+
+def test_extpi_truncation_keeps_largest():
+    A = laplacian(9, 9, 5)
+    comp = np.zeros(A.shape[0], np.int64)
+    ptr, idx = amg.strength(A, comp, 0.25)
+    st = amg.pmis(ptr, idx, A.shape[0], 11, 0)
+    checked = 0
+    for i in np.flatnonzero(st == amg.F_):
+        full = amg.interp_row_extpi(A, ptr, idx, st, comp, int(i), 0)
+        if len(full) <= 3:
+            continue
+        tr = amg.interp_row_extpi(A, ptr, idx, st, comp, int(i), 3)
+        mags = sorted((abs(v) for v in full.values()), reverse=True)
+        assert len(tr) == 3 and min(abs(full[j]) for j in tr) >= mags[2] * (1 - 1e-6)
+        assert abs(sum(tr.values()) - sum(full.values())) <= 1e-13 * abs(sum(full.values()))
+        assert all(np.sign(tr[j]) == np.sign(full[j]) for j in tr)
+        checked += 1
+    assert checked > 10
 
 
 def test_interpolation_respects_components():
