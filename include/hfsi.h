@@ -115,8 +115,9 @@ typedef struct {
   int32_t cheb_degree;   /* Chebyshev polynomial degree, 1..8, default 2   */
   double cheb_ratio;     /* lmax / lower bound of the interval, > 1, default 30 */
   int32_t interp_kind;   /* 0 = modified classical (distance one), 1 = extended+i
-                            (distance two, De Sterck et al. 2008); with
-                            interp = 1 level 0 stays distance one          */
+                            (distance two, De Sterck et al. 2008); the learned
+                            correction (interp = 1) adjusts the level-0 row
+                            entries inside the 3x3x3 lattice box; default 1 */
   int32_t p_max;         /* extended+i: entries kept per row (largest |w|,
                             rescaled to the row sum), 0 = all, default 4   */
 } hfsi_amg_params;

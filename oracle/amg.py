@@ -315,7 +315,7 @@ class AmgParams:
     nu_post: int = 2
     cheb_degree: int = 2
     cheb_ratio: float = 30.0
-    interp: str = "classical"      # or "ext+i"
+    interp: str = "ext+i"          # or "classical"
     p_max: int = 4                 # ext+i truncation (0: none)
     lanczos_steps: int = 10
     max_dense: int = 8192

@@ -71,15 +71,17 @@ def material_features(materials):
 
 
 def samples(A, comp, state, S_ptr, S_idx, P, lattice, matfeat):
-    """Features X [M,64], mask [M,27], classical weights [M,27] and the row
-    indices of the samples, in ascending row order."""
+    """Features X [M,64], mask [M,27], base weights [M,27] and the row
+    indices of the samples, in ascending row order.  Features: the stencil
+    a_ij / a_ii of the same-component neighbours in the 3x3x3 lattice box;
+    mask and base weights: the entries of the row of P (classical or
+    extended+i) whose C point lies in the box."""
     n = A.shape[0]
     rows, X, mask, wcl = [], [], [], []
-    cidx = np.cumsum(state == 1) - 1
+    c2f = np.flatnonzero(state == 1)
     for i in range(n):
         if state[i] != -1 or P.indptr[i + 1] == P.indptr[i]:
             continue
-        S_set = set(S_idx[S_ptr[i]:S_ptr[i + 1]].tolist())
         node, c = i // 3, comp[i]
         lo, hi = A.indptr[i], A.indptr[i + 1]
         cols, vals = A.indices[lo:hi], A.data[lo:hi]
@@ -87,20 +89,21 @@ def samples(A, comp, state, S_ptr, S_idx, P, lattice, matfeat):
         x = np.zeros(NIN)
         mk = np.zeros(NOUT)
         w = np.zeros(NOUT)
-        pcols = P.indices[P.indptr[i]:P.indptr[i + 1]]
-        pvals = P.data[P.indptr[i]:P.indptr[i + 1]]
         for j, a in zip(cols, vals):
             if comp[j] != c:
                 continue
             off = lattice[j // 3] - lattice[node]
             if np.abs(off).max() > 1:
                 continue
+            x[slot_of(off)] = np.float32(a / aii)
+        for q in range(P.indptr[i], P.indptr[i + 1]):
+            off = lattice[c2f[P.indices[q]] // 3] - lattice[node]
+            if np.abs(off).max() > 1:
+                continue
             s = slot_of(off)
-            x[s] = np.float32(a / aii)
-            if j in S_set and state[j] == 1:
-                x[27 + s] = 1.0
-                mk[s] = 1.0
-                w[s] = pvals[np.flatnonzero(pcols == cidx[j])[0]]
+            x[27 + s] = 1.0
+            mk[s] = 1.0
+            w[s] = P.data[q]
         x[54:57] = np.float32(matfeat)
         x[57 + c] = 1.0
         rows.append(i)
@@ -110,31 +113,42 @@ def samples(A, comp, state, S_ptr, S_idx, P, lattice, matfeat):
     return np.array(rows, np.int64), np.array(X), np.array(mask), np.array(wcl)
 
 
-def ideal_target(A, comp, state, S_ptr, S_idx, lattice, i, classical_sum=None):
+def ideal_target(A, comp, state, S_ptr, S_idx, lattice, i, classical_sum=None, P=None):
     """w*_i on the 27 slots (zero outside C_i).
 
-    With classical_sum given, w*_i is rescaled to that row sum: the local
-    system drops every coupling outside F_loc, so its raw solution does not
-    reproduce constants; the classical weights do (for zero row sums), and
-    an interpolation that loses them slows the V-cycle down."""
+    C_i: the strong C neighbours of i, or, with P given, the C points of the
+    row of P (which may reach beyond the lattice box).  F_loc: i and the
+    same-component F points of row i.  w*_i solves A_FF X = -A_FC on F_loc x
+    C_i; only C points inside the box get a slot.  With classical_sum given,
+    the in-box part of w*_i is rescaled to that sum: the local system drops
+    every coupling outside F_loc, so its raw solution does not reproduce
+    constants; the base weights do (for zero row sums), and an
+    interpolation that loses them slows the V-cycle down."""
     lo, hi = A.indptr[i], A.indptr[i + 1]
     cols = A.indices[lo:hi]
-    S_set = set(S_idx[S_ptr[i]:S_ptr[i + 1]].tolist())
-    Ci = [int(j) for j in cols if j in S_set and state[j] == 1]
+    if P is None:
+        S_set = set(S_idx[S_ptr[i]:S_ptr[i + 1]].tolist())
+        Ci = [int(j) for j in cols if j in S_set and state[j] == 1]
+    else:
+        c2f = np.flatnonzero(state == 1)
+        Ci = [int(c2f[q]) for q in P.indices[P.indptr[i]:P.indptr[i + 1]]]
     Floc = [int(j) for j in cols if comp[j] == comp[i] and (j == i or state[j] == -1)]
     Ad = A[Floc][:, Floc].toarray()
     Ac = A[Floc][:, Ci].toarray()
     Xs = np.linalg.solve(Ad, -Ac)
     wi = Xs[Floc.index(i)]
+    inbox = [bool(np.abs(lattice[j // 3] - lattice[i // 3]).max() <= 1) for j in Ci]
     if classical_sum is not None:
         s = 0.0
-        for w in wi:
-            s += w
+        for w, ib in zip(wi, inbox):
+            if ib:
+                s += w
         if abs(s) > 1e-12:
             wi = wi * (classical_sum / s)
     out = np.zeros(NOUT)
-    for j, w in zip(Ci, wi):
-        out[slot_of(lattice[j // 3] - lattice[i // 3])] = w
+    for j, w, ib in zip(Ci, wi, inbox):
+        if ib:
+            out[slot_of(lattice[j // 3] - lattice[i // 3])] = w
     return out
 
 

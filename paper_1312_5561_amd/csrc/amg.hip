@@ -1349,9 +1349,7 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
     DevBuf<int> cnt;
     cnt.ensure(n + 1);
     HIP_CHECK(hipMemsetAsync(cnt.p + n, 0, sizeof(int), s));
-    // extended+i on every level, except level 0 of the learned interpolation
-    // (its network corrects the distance-one weights)
-    const bool extpi = prm.interp_kind == 1 && !(l == 0 && prm.interp == 1);
+    const bool extpi = prm.interp_kind == 1;
     DevBuf<int> ovf;
     ovf.zero(1, s);
     // with truncation the rows have at most p_max entries: one pass writes

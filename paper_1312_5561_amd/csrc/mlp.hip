@@ -52,13 +52,20 @@ __global__ void k_sample_rows(int n, const int* __restrict__ flag, const int* __
   if (i < n && flag[i]) rows[sidx[i]] = i;
 }
 
-// features, mask, classical weights in slot form, and the slot of every P entry
+__global__ void k_c2f(int n, const int8_t* __restrict__ state, const int* __restrict__ cidx, int* __restrict__ c2f) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && state[i] == 1) c2f[cidx[i]] = i;
+}
+
+// features, mask, base weights in slot form, and the slot of every P entry:
+// the stencil a_ij / a_ii of the same-component neighbours in the 3x3x3
+// lattice box, and the P row's entries whose C point lies in the box (the
+// mask and base weights; entries outside the box keep their weights)
 __global__ void k_features(int ns, const int* __restrict__ rows, const int* __restrict__ ap, const int* __restrict__ ac,
-                           const double* __restrict__ av, const int* __restrict__ comp, const int8_t* __restrict__ state,
-                           const uint8_t* __restrict__ strong, const int* __restrict__ cidx, const int* __restrict__ pptr,
-                           const int* __restrict__ pcol, const double* __restrict__ pval, const int* __restrict__ lat,
-                           float mf0, float mf1, float mf2, float* __restrict__ X, float* __restrict__ mask,
-                           float* __restrict__ wcl, int* __restrict__ pslot) {
+                           const double* __restrict__ av, const int* __restrict__ comp, const int* __restrict__ c2f,
+                           const int* __restrict__ pptr, const int* __restrict__ pcol, const double* __restrict__ pval,
+                           const int* __restrict__ lat, float mf0, float mf1, float mf2, float* __restrict__ X,
+                           float* __restrict__ mask, float* __restrict__ wcl, int* __restrict__ pslot) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= ns) return;
   const int i = rows[m], ni = i / 3, c = comp[i];
@@ -70,25 +77,19 @@ __global__ void k_features(int ns, const int* __restrict__ rows, const int* __re
   double aii = 0.0;
   for (int e = ap[i]; e < ap[i + 1]; ++e)
     if (ac[e] == i) aii = av[e];
-  int q = pptr[i];
   for (int e = ap[i]; e < ap[i + 1]; ++e) {
     const int j = ac[e];
     if (comp[j] != c) continue;
     const int s = slot_of(lat, ni, j / 3);
-    const bool isC = strong[e] && state[j] == 1;
+    if (s >= 0) x[s] = (float)(av[e] / aii);
+  }
+  for (int q = pptr[i]; q < pptr[i + 1]; ++q) {
+    const int s = slot_of(lat, ni, c2f[pcol[q]] / 3);
+    pslot[q] = s;
     if (s >= 0) {
-      x[s] = (float)(av[e] / aii);
-      if (isC) {
-        x[27 + s] = 1.f;
-        mk[s] = 1.f;
-      }
-    }
-    if (isC) {  // P row entries are the strong C columns in ascending order
-      while (q < pptr[i + 1] && pcol[q] < cidx[j]) ++q;
-      if (q < pptr[i + 1] && pcol[q] == cidx[j]) {
-        pslot[q] = s;
-        if (s >= 0) w[s] = (float)pval[q];
-      }
+      x[27 + s] = 1.f;
+      mk[s] = 1.f;
+      w[s] = (float)pval[q];
     }
   }
   x[54] = mf0;
@@ -102,8 +103,9 @@ constexpr int LMAX = 32, CMAX = 27;
 __global__ void __launch_bounds__(64)
 k_ideal_target(int ns, const int* __restrict__ rows, const int* __restrict__ ap, const int* __restrict__ ac,
                const double* __restrict__ av, const int* __restrict__ comp, const int8_t* __restrict__ state,
-               const uint8_t* __restrict__ strong, const int* __restrict__ lat, const float* __restrict__ wcl,
-               float* __restrict__ wstar, int* __restrict__ fail) {
+               const int* __restrict__ pptr, const int* __restrict__ pcol, const int* __restrict__ c2f,
+               const int* __restrict__ lat, const float* __restrict__ wcl, float* __restrict__ wstar,
+               int* __restrict__ fail) {
   __shared__ int Fl[LMAX], Cl[CMAX];
   __shared__ double Mx[LMAX][LMAX + CMAX];
   __shared__ int nF, nC, ipos, bad;
@@ -114,13 +116,14 @@ k_ideal_target(int ns, const int* __restrict__ rows, const int* __restrict__ ap,
     if (lane == 0) {
       int f = 0, cc = 0, ip = -1;
       bad = 0;
+      // C points: the columns of the P row
+      for (int q = pptr[i]; q < pptr[i + 1]; ++q) {
+        if (cc < CMAX) Cl[cc] = c2f[pcol[q]];
+        ++cc;
+      }
       for (int e = ap[i]; e < ap[i + 1]; ++e) {
         const int j = ac[e];
         if (comp[j] != ci) continue;
-        if (strong[e] && state[j] == 1) {
-          if (cc < CMAX) Cl[cc] = j;
-          ++cc;
-        }
         if (j == i || state[j] == -1) {
           if (j == i) ip = f;
           if (f < LMAX) Fl[f] = j;
@@ -185,8 +188,9 @@ k_ideal_target(int ns, const int* __restrict__ rows, const int* __restrict__ ap,
     // rescale to the classical row sum (constants are then reproduced as by
     // the classical weights; the local system alone drops outer couplings)
     if (lane == 0 && !bad) {
-      double si = 0.0, sc = 0.0;
-      for (int t = 0; t < NC; ++t) si += Mx[ipos][LMAX + t];
+      double si = 0.0, sc = 0.0;  // over the C points inside the lattice box
+      for (int t = 0; t < NC; ++t)
+        if (slot_of(lat, i / 3, Cl[t] / 3) >= 0) si += Mx[ipos][LMAX + t];
       for (int t = 0; t < NOUT; ++t) sc += (double)wcl[(size_t)m * NOUTP + t];
       scale = fabs(si) > 1e-12 ? sc / si : 1.0;
     }
@@ -420,7 +424,7 @@ static void refresh_bf16(hfsi_ctx* c, MlpState& S) {
 // weights and the slot of every P entry.
 struct Samples {
   int ns = 0;
-  DevBuf<int> rows, pslot;
+  DevBuf<int> rows, pslot, c2f;  // c2f: fine index of every coarse point
   DevBuf<float> X, mask, wcl;
 };
 
@@ -453,11 +457,13 @@ static void build_samples(hfsi_ctx* c, Level& L, Samples& S) {
   HIP_CHECK(hipMemsetAsync(S.pslot.p, 0xFF, sizeof(int) * std::max<int64_t>(L.P.nnz, 1), s));
   float mf[3];
   material_feats(c, mf);
+  S.c2f.ensure(std::max(L.P.cols, 1));
+  k_c2f<<<div_up(n, 256), 256, 0, s>>>(n, L.state.p, L.cidx.p, S.c2f.p);
+  HIP_LAUNCH_CHECK();
   if (S.ns > 0) {
-    k_features<<<div_up(S.ns, 128), 128, 0, s>>>(S.ns, S.rows.p, L.A.ptr.p, L.A.col.p, L.A.val.p, L.comp.p,
-                                                 L.state.p, L.strong.p, L.cidx.p, L.P.ptr.p, L.P.col.p, L.P.val.p,
-                                                 c->lattice.p, mf[0], mf[1], mf[2], S.X.p, S.mask.p, S.wcl.p,
-                                                 S.pslot.p);
+    k_features<<<div_up(S.ns, 128), 128, 0, s>>>(S.ns, S.rows.p, L.A.ptr.p, L.A.col.p, L.A.val.p, L.comp.p, S.c2f.p,
+                                                 L.P.ptr.p, L.P.col.p, L.P.val.p, c->lattice.p, mf[0], mf[1], mf[2],
+                                                 S.X.p, S.mask.p, S.wcl.p, S.pslot.p);
     HIP_LAUNCH_CHECK();
   }
 }
@@ -635,8 +641,9 @@ extern "C" hfsi_status hfsi_mlp_collect(hfsi_ctx* c, int32_t* n_added, int32_t* 
     HIP_CHECK(hipMemcpyAsync(S.mask.p + S.ns * NOUTP, smp.mask.p, sizeof(float) * ns * NOUTP, hipMemcpyDeviceToDevice, s));
     HIP_CHECK(hipMemcpyAsync(S.wcl.p + S.ns * NOUTP, smp.wcl.p, sizeof(float) * ns * NOUTP, hipMemcpyDeviceToDevice, s));
     k_ideal_target<<<(int)std::min<long>(ns, 65536), 64, 0, s>>>((int)ns, smp.rows.p, L.A.ptr.p, L.A.col.p, L.A.val.p,
-                                                                 L.comp.p, L.state.p, L.strong.p, c->lattice.p,
-                                                                 smp.wcl.p, S.wst.p + S.ns * NOUTP, fl.p);
+                                                                 L.comp.p, L.state.p, L.P.ptr.p, L.P.col.p,
+                                                                 smp.c2f.p, c->lattice.p, smp.wcl.p,
+                                                                 S.wst.p + S.ns * NOUTP, fl.p);
     HIP_LAUNCH_CHECK();
   }
   int nf = 0;

@@ -97,7 +97,7 @@ def train_params(batch=1024, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
 
 
 def amg_params(theta=0.15, max_coarse=500, max_levels=25, seed=12345, smoother=1, nu_pre=1, nu_post=2,
-               precision=0, interp=0, fallback_rho=0.5, cheb_degree=2, cheb_ratio=30.0, interp_kind=0, p_max=4):
+               precision=0, interp=0, fallback_rho=0.5, cheb_degree=2, cheb_ratio=30.0, interp_kind=1, p_max=4):
     return AmgParams(C.sizeof(AmgParams), theta, max_coarse, max_levels, seed, smoother, nu_pre, nu_post,
                      precision, interp, fallback_rho, cheb_degree, cheb_ratio, interp_kind, p_max)
 

@@ -76,7 +76,7 @@ def test_loss_gradient_matches_oracle(lib):
     assert np.abs(g[keep] - go[keep]).max() <= 1e-4 * np.abs(go[keep]).max()
 
 
-def _cube_setup(lib, N=6, seed=3, interp=0, weights=None, fallback=0.5):
+def _cube_setup(lib, N=6, seed=3, interp=0, weights=None, fallback=0.5, kind=1):
     import torch
     prob = synth.cube_problem(N, jitter=0.1, seed=seed)
     ctx = context_for(lib, prob)
@@ -85,12 +85,15 @@ def _cube_setup(lib, N=6, seed=3, interp=0, weights=None, fallback=0.5):
     v = torch.zeros(prob.n_dofs, dtype=torch.float64, device="cuda")
     R = torch.zeros_like(v)
     ctx.assemble_residual_tangent(v, 1.0, R)
-    info = ctx.amg_setup(lib.amg_params(max_coarse=60, interp=interp, fallback_rho=fallback, smoother=1))
+    info = ctx.amg_setup(lib.amg_params(max_coarse=60, interp=interp, fallback_rho=fallback, smoother=1,
+                                        interp_kind=kind))
     return prob, ctx, info
 
 
-def test_collect_matches_oracle(lib):
-    prob, ctx, info = _cube_setup(lib)
+@pytest.mark.parametrize("kind", [0, 1])
+def test_collect_matches_oracle(lib, kind):
+    """Samples of the classical (0) or extended+i (1) level-0 interpolation."""
+    prob, ctx, info = _cube_setup(lib, kind=kind)
     added, failed = ctx.mlp_collect()
     assert added > 0 and failed == 0
     X, mask, wcl, wst = ctx.mlp_samples()
@@ -108,7 +111,7 @@ def test_collect_matches_oracle(lib):
         csum = 0.0
         for s in range(27):
             csum += float(wcl[m, s])
-        t = mlp.ideal_target(A, comp, st, S_ptr, S_idx, prob.lattice, rows[m], classical_sum=csum)
+        t = mlp.ideal_target(A, comp, st, S_ptr, S_idx, prob.lattice, rows[m], classical_sum=csum, P=P)
         assert np.allclose(wst[m, :27], t, rtol=1e-5, atol=1e-6)
         assert abs(t.sum() - csum) <= 1e-9 * max(1.0, abs(csum))
 
