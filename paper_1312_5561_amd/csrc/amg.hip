@@ -254,7 +254,7 @@ k_interp_fill16(int n, const int* __restrict__ ptr, const int* __restrict__ col,
 }
 
 // Extended+i interpolation (De Sterck, Falgout, Nolting, Yang 2008) on
-// same-component couplings, 16 lanes per row.  For an F row i the candidate
+// same-component couplings, LN lanes per row.  For an F row i the candidate
 // set Chat_i (strong C neighbours of i and of its strong F neighbours) is
 // built in an LDS hash table and ranked by column; then
 //   w_ij = -(a_ij + sum_{k in F_i} a_ik abar_kj / s_k) / atilde_ii,
@@ -264,27 +264,29 @@ k_interp_fill16(int n, const int* __restrict__ ptr, const int* __restrict__ col,
 // ties to the smaller column), rescaled to the full row sum.  FILL = false
 // writes the entry count of each row, FILL = true the entries (ascending
 // columns).  Sums over a row are lane-strided and tree-reduced.
+constexpr int EXTPI_LANES = 64;  // lanes per row: one wavefront (measured fastest of 16/32/64)
 constexpr int XH = 128;    // hash slots per row
 constexpr int XMAX = 96;   // candidates per row
-constexpr int XQ = 4;      // entries of a neighbour row each lane keeps in registers (rows up to 64)
+constexpr int XQ = 4;      // entries of a neighbour row each lane keeps in registers
 __device__ __forceinline__ int xh_slot(int key) { return (int)(((unsigned)key * 2654435761u) >> 25); }
 
-template <bool FILL>
+template <bool FILL, int LN>
 __global__ void __launch_bounds__(256)
 k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const double* __restrict__ val,
         const uint8_t* __restrict__ strong, const int8_t* __restrict__ state, const int* __restrict__ comp,
         const int* __restrict__ cidx, int p_max, int* __restrict__ cnt, const int* __restrict__ pptr,
         int* __restrict__ pcol, double* __restrict__ pval, int* __restrict__ overflow) {
-  __shared__ int h_key[16][XH];
-  __shared__ int h_rank[16][XH];
-  __shared__ int s_mem[16][XMAX];   // members in insertion order, then by rank
-  __shared__ int s_sorted[16][XMAX];
-  __shared__ double s_num[16][XMAX];
-  __shared__ int s_cnt[16];
-  const int g = threadIdx.x >> 4, lane = threadIdx.x & 15;
-  const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  constexpr int RB = 256 / LN;  // rows per block
+  __shared__ int h_key[RB][XH];
+  __shared__ int h_rank[RB][XH];
+  __shared__ int s_mem[RB][XMAX];   // members in insertion order, then by rank
+  __shared__ int s_sorted[RB][XMAX];
+  __shared__ double s_num[RB][XMAX];
+  __shared__ int s_cnt[RB];
+  const int g = threadIdx.x / LN, lane = threadIdx.x % LN;
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) / LN;
   const bool row = i < n && state[i] != ST_C;
-  for (int t = lane; t < XH; t += 16) h_key[g][t] = -1;
+  for (int t = lane; t < XH; t += LN) h_key[g][t] = -1;
   if (lane == 0) s_cnt[g] = 0;
   __syncthreads();
   // ---- candidates
@@ -303,14 +305,14 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
       }
     };
     const int lo = ptr[i], hi = ptr[i + 1];
-    for (int e = lo + lane; e < hi; e += 16) {
+    for (int e = lo + lane; e < hi; e += LN) {
       const int j = col[e];
       if (strong[e] && state[j] == ST_C) insert(j);
     }
     for (int e = lo; e < hi; ++e) {
       const int k = col[e];
       if (!strong[e] || state[k] == ST_C) continue;
-      for (int f = ptr[k] + lane; f < ptr[k + 1]; f += 16) {
+      for (int f = ptr[k] + lane; f < ptr[k + 1]; f += LN) {
         const int m = col[f];
         if (strong[f] && state[m] == ST_C) insert(m);
       }
@@ -327,7 +329,7 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
   const bool work = row && m > 0 && m <= XMAX;
   // ---- rank by column
   if (work) {
-    for (int t = lane; t < m; t += 16) {
+    for (int t = lane; t < m; t += LN) {
       const int key = s_mem[g][t];
       int r = 0;
       for (int u = 0; u < m; ++u) r += s_mem[g][u] < key;
@@ -354,7 +356,7 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
     const int lo = ptr[i], hi = ptr[i + 1], ci = comp[i];
     // row i: direct couplings to Chat_i, weak ones lumped, the diagonal
     double dpart = 0.0;
-    for (int e = lo + lane; e < hi; e += 16) {
+    for (int e = lo + lane; e < hi; e += LN) {
       const int j = col[e];
       if (comp[j] != ci) continue;
       const double a = val[e];
@@ -367,7 +369,7 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
       else if (!(strong[e] && state[j] == ST_F)) dpart += a;
     }
 #pragma unroll
-    for (int o = 8; o > 0; o >>= 1) dpart += __shfl_xor(dpart, o, 16);
+    for (int o = LN / 2; o > 0; o >>= 1) dpart += __shfl_xor(dpart, o, LN);
     den = dpart;
     // strong F neighbours, in row order
     for (int e = lo; e < hi; ++e) {
@@ -384,7 +386,7 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
         c_v[q] = 0.0;
       }
       int q = 0;
-      for (int f = klo + lane; f < khi; f += 16, ++q) {
+      for (int f = klo + lane; f < khi; f += LN, ++q) {
         const int mm = col[f];
         const double v = val[f];
         if (mm == k) akk = v;
@@ -403,12 +405,12 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
         }
       }
 #pragma unroll
-      for (int o = 8; o > 0; o >>= 1) {
-        akk += __shfl_xor(akk, o, 16);
-        s_neg += __shfl_xor(s_neg, o, 16);
-        s_pos += __shfl_xor(s_pos, o, 16);
-        ki_neg += __shfl_xor(ki_neg, o, 16);
-        ki_pos += __shfl_xor(ki_pos, o, 16);
+      for (int o = LN / 2; o > 0; o >>= 1) {
+        akk += __shfl_xor(akk, o, LN);
+        s_neg += __shfl_xor(s_neg, o, LN);
+        s_pos += __shfl_xor(s_pos, o, LN);
+        ki_neg += __shfl_xor(ki_neg, o, LN);
+        ki_pos += __shfl_xor(ki_pos, o, LN);
       }
       const double sk = akk < 0.0 ? -1.0 : 1.0;
       const double sden = sk > 0.0 ? s_neg : s_pos;
@@ -417,7 +419,7 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
         continue;
       }
       q = 0;
-      for (int f = klo + lane; f < khi; f += 16, ++q) {
+      for (int f = klo + lane; f < khi; f += LN, ++q) {
         int r = -1;
         double v = 0.0;
         if (q < XQ) {
@@ -442,12 +444,12 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
   __syncthreads();
   // ---- weights (in place), selection ranks, output in ascending columns
   if (work)
-    for (int t = lane; t < m; t += 16) s_num[g][t] = -s_num[g][t] / den;
+    for (int t = lane; t < m; t += LN) s_num[g][t] = -s_num[g][t] / den;
   __syncthreads();
   const bool trunc = work && p_max > 0 && m > p_max;
   int* sel = s_mem[g];  // the insertion list is no longer needed
   if (trunc)
-    for (int t = lane; t < m; t += 16) {
+    for (int t = lane; t < m; t += LN) {
       const float key = fabsf((float)s_num[g][t]);
       int r = 0;
       for (int u = 0; u < m; ++u) {
@@ -459,20 +461,20 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
   __syncthreads();
   if (work) {
     double tot = 0.0, kept = 0.0;
-    for (int t = lane; t < m; t += 16) {
+    for (int t = lane; t < m; t += LN) {
       tot += s_num[g][t];
       if (trunc && sel[t] < p_max) kept += s_num[g][t];
     }
 #pragma unroll
-    for (int o = 8; o > 0; o >>= 1) {
-      tot += __shfl_xor(tot, o, 16);
-      kept += __shfl_xor(kept, o, 16);
+    for (int o = LN / 2; o > 0; o >>= 1) {
+      tot += __shfl_xor(tot, o, LN);
+      kept += __shfl_xor(kept, o, LN);
     }
     const double scale = trunc && kept != 0.0 ? tot / kept : 1.0;
     // pptr == nullptr: rows go to a fixed stride of p_max entries, counts to cnt
     const long p0 = pptr ? (long)pptr[i] : (long)i * p_max;
     if (!pptr && lane == 0) cnt[i] = trunc ? p_max : m;
-    for (int t = lane; t < m; t += 16) {
+    for (int t = lane; t < m; t += LN) {
       int pos = t;
       if (trunc) {
         if (sel[t] >= p_max) continue;
@@ -1360,11 +1362,11 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
     if (strided) {
       tcol.ensure((size_t)n * prm.p_max);
       tval.ensure((size_t)n * prm.p_max);
-      k_extpi<true><<<div_up((long)n * 16, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p,
+      k_extpi<true, EXTPI_LANES><<<div_up((long)n * EXTPI_LANES, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p,
                                                                L.state.p, L.comp.p, L.cidx.p, prm.p_max, cnt.p,
                                                                nullptr, tcol.p, tval.p, ovf.p);
     } else if (extpi) {
-      k_extpi<false><<<div_up((long)n * 16, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p,
+      k_extpi<false, EXTPI_LANES><<<div_up((long)n * EXTPI_LANES, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p,
                                                                 L.state.p, L.comp.p, L.cidx.p, prm.p_max, cnt.p,
                                                                 nullptr, nullptr, nullptr, ovf.p);
     } else {
@@ -1381,7 +1383,7 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
       if (strided)
         k_compact_rows<<<div_up(n, 256), 256, 0, s>>>(n, prm.p_max, L.P.ptr.p, tcol.p, tval.p, L.P.col.p, L.P.val.p);
       else if (extpi)
-        k_extpi<true><<<div_up((long)n * 16, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p,
+        k_extpi<true, EXTPI_LANES><<<div_up((long)n * EXTPI_LANES, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p,
                                                                  L.state.p, L.comp.p, L.cidx.p, prm.p_max, nullptr,
                                                                  L.P.ptr.p, L.P.col.p, L.P.val.p, ovf.p);
       else
