@@ -94,10 +94,12 @@ __global__ void k_pmis_select(int n, const int* __restrict__ ptr, const int* __r
   }
 }
 
-__global__ void k_pmis_mark_c(int n, const int* __restrict__ notmax, int8_t* __restrict__ state) {
+// also clears notmax for the next round
+__global__ void k_pmis_mark_c(int n, int* __restrict__ notmax, int8_t* __restrict__ state) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (state[i] == ST_U && !notmax[i]) state[i] = ST_C;
+  notmax[i] = 0;
 }
 
 __global__ void k_pmis_mark_f(int n, const int* __restrict__ ptr, const int* __restrict__ col,
@@ -822,15 +824,22 @@ __global__ void k_l1_diag(int n, const int* __restrict__ ptr, const double* __re
   d32[i] = (float)(1.0 / s);
 }
 
-__global__ void k_inv_diag(int n, const int* __restrict__ ptr, const int* __restrict__ col,
-                           const double* __restrict__ val, double* __restrict__ d, float* __restrict__ d32) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+// 1 / a_ii, 8 lanes per row (one lane holds the diagonal; the others add zeros)
+__global__ void __launch_bounds__(256)
+k_inv_diag(int n, const int* __restrict__ ptr, const int* __restrict__ col, const double* __restrict__ val,
+           double* __restrict__ d, float* __restrict__ d32) {
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const int lane = threadIdx.x & 7;
   if (i >= n) return;
   double a = 0.0;
-  for (int e = ptr[i]; e < ptr[i + 1]; ++e)
+  for (int e = ptr[i] + lane; e < ptr[i + 1]; e += 8)
     if (col[e] == i) a = val[e];
-  d[i] = 1.0 / a;
-  d32[i] = (float)(1.0 / a);
+#pragma unroll
+  for (int o = 4; o > 0; o >>= 1) a += __shfl_xor(a, o, 8);
+  if (lane == 0) {
+    d[i] = 1.0 / a;
+    d32[i] = (float)(1.0 / a);
+  }
 }
 
 __global__ void k_to_f32(long n, const double* __restrict__ x, float* __restrict__ y) {
@@ -1096,13 +1105,10 @@ double lanczos_max(hfsi_ctx* c, Level& L, int steps, uint64_t seed, int level) {
   k_dot_finish<<<1, 256, 0, s>>>(part.p, 1, ab.p + 65, ab.p, kst.p, 0);
   k_scale_inv_dev<<<g, 256, 0, s>>>(n, ab.p + 65, q.p, q.p);
   HIP_LAUNCH_CHECK();
-  // |diag|^{-1/2} for the scaling
+  // |diag|^{-1/2} for the scaling, from the smoother's D^{-1} (Chebyshev)
   DevBuf<double> dabs;
-  DevBuf<float> dummy;
-  dabs.ensure(n); dummy.ensure(n);
-  k_inv_diag<<<g, 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, dabs.p, dummy.p);
-  HIP_LAUNCH_CHECK();
-  k_rsqrt_abs<<<g, 256, 0, s>>>(n, dabs.p, dabs.p);  // dabs <- |diag|^{-1/2}
+  dabs.ensure(n);
+  k_rsqrt_abs<<<g, 256, 0, s>>>(n, L.dinv.p, dabs.p);
   HIP_LAUNCH_CHECK();
   const int steps_run = std::min(steps, std::min(n, 32));
   for (int it = 0; it < steps_run; ++it) {
@@ -1206,7 +1212,7 @@ void smoother_data(hfsi_ctx* c, Level& L, const hfsi_amg_params& prm, int level)
     k_l1_diag<<<div_up(L.n, 256), 256, 0, s>>>(L.n, L.A.ptr.p, L.A.val.p, L.dinv.p, L.dinv32.p);
     HIP_LAUNCH_CHECK();
   } else {
-    k_inv_diag<<<div_up(L.n, 256), 256, 0, s>>>(L.n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.dinv.p, L.dinv32.p);
+    k_inv_diag<<<div_up((long)L.n * 8, 256), 256, 0, s>>>(L.n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.dinv.p, L.dinv32.p);
     HIP_LAUNCH_CHECK();
     L.lmax = lanczos_max(c, L, 10, prm.seed, level);
   }
@@ -1289,6 +1295,8 @@ __global__ void k_comp_mod3(int n, int* __restrict__ comp) {
 
 }  // namespace
 
+constexpr int PMIS_BATCH = 3;
+
 // Build levels 1.. from level 0 (whose A and comp are already set).
 void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {
   hipStream_t s = c->stream;
@@ -1303,7 +1311,7 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
   int rounds_total = 0;
   DevBuf<int> lam, notmax, flag, rem;
   DevBuf<uint64_t> key;
-  rem.ensure(1);
+  rem.ensure(PMIS_BATCH);
   for (int l = 0;; ++l) {
     Level& L = H.L[l];
     const int n = L.n;
@@ -1322,22 +1330,30 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
     L.state.ensure(n);
     k_pmis_init<<<div_up(n, 256), 256, 0, s>>>(n, lam.p, prm.seed, l, key.p, L.state.p);
     HIP_LAUNCH_CHECK();
-    notmax.ensure(n);
-    for (int round = 0;; ++round) {
+    // PMIS rounds, PMIS_BATCH per host read of the undecided counts; rounds
+    // after the last undecided point is gone change nothing
+    notmax.zero(n, s);
+    for (int round = 0;; round += PMIS_BATCH) {
       if (round > n + 1) fail(HFSI_E_HIP, "PMIS did not terminate");
-      HIP_CHECK(hipMemsetAsync(notmax.p, 0, sizeof(int) * n, s));
-      HIP_CHECK(hipMemsetAsync(rem.p, 0, sizeof(int), s));
-      k_pmis_select<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.strong.p, key.p, L.state.p, notmax.p);
-      HIP_LAUNCH_CHECK();
-      k_pmis_mark_c<<<div_up(n, 256), 256, 0, s>>>(n, notmax.p, L.state.p);
-      HIP_LAUNCH_CHECK();
-      k_pmis_mark_f<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.strong.p, L.state.p, rem.p);
-      HIP_LAUNCH_CHECK();
-      int left = 0;
-      HIP_CHECK(hipMemcpyAsync(&left, rem.p, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_CHECK(hipMemsetAsync(rem.p, 0, sizeof(int) * PMIS_BATCH, s));
+      for (int k = 0; k < PMIS_BATCH; ++k) {
+        k_pmis_select<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.strong.p, key.p, L.state.p, notmax.p);
+        HIP_LAUNCH_CHECK();
+        k_pmis_mark_c<<<div_up(n, 256), 256, 0, s>>>(n, notmax.p, L.state.p);
+        HIP_LAUNCH_CHECK();
+        k_pmis_mark_f<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.strong.p, L.state.p, rem.p + k);
+        HIP_LAUNCH_CHECK();
+      }
+      int left[PMIS_BATCH];
+      HIP_CHECK(hipMemcpyAsync(left, rem.p, sizeof(left), hipMemcpyDeviceToHost, s));
       HIP_CHECK(hipStreamSynchronize(s));
-      ++rounds_total;
-      if (left == 0) break;
+      int k = 0;
+      while (k < PMIS_BATCH && left[k] != 0) ++k;
+      if (k < PMIS_BATCH) {
+        rounds_total += k + 1;
+        break;
+      }
+      rounds_total += PMIS_BATCH;
     }
     // coarse numbering
     flag.ensure(n + 1);
