@@ -531,22 +531,21 @@ __global__ void k_transpose_fill(int n, const int* __restrict__ ptr, const int* 
   }
 }
 
-// insertion sort of each row by column (rows of a transpose are short)
-__global__ void k_sort_rows(int n, const int* __restrict__ ptr, int* __restrict__ col, double* __restrict__ val) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Rows of a transpose into column order: one wavefront per row; the columns
+// of a row are distinct, so each entry's place is the number of smaller
+// columns in its row.
+__global__ void k_sort_rows(int n, const int* __restrict__ ptr, const int* __restrict__ col,
+                            const double* __restrict__ val, int* __restrict__ ocol, double* __restrict__ oval) {
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
   if (i >= n) return;
-  const int lo = ptr[i], hi = ptr[i + 1];
-  for (int a = lo + 1; a < hi; ++a) {
-    const int c = col[a];
-    const double v = val[a];
-    int b = a - 1;
-    while (b >= lo && col[b] > c) {
-      col[b + 1] = col[b];
-      val[b + 1] = val[b];
-      --b;
-    }
-    col[b + 1] = c;
-    val[b + 1] = v;
+  const int lo = ptr[i], len = ptr[i + 1] - lo;
+  for (int p = lane; p < len; p += 64) {
+    const int key = col[lo + p];
+    int r = 0;
+    for (int u = 0; u < len; ++u) r += col[lo + u] < key ? 1 : 0;
+    ocol[lo + r] = key;
+    oval[lo + r] = val[lo + p];
   }
 }
 
@@ -650,6 +649,136 @@ k_spgemm(int n, const int* __restrict__ ap, const int* __restrict__ ac, const do
       for (int u = 0; u < nk; ++u) r += ckeys[u] < key ? 1 : 0;
       cc[base + r] = key;
       cv[base + r] = vals[t];
+    }
+    __syncthreads();
+  }
+}
+
+// largest row length of B (wave maximum, one atomic per wavefront)
+__global__ void k_max_rowlen(int n, const int* __restrict__ ptr, int* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int len = i < n ? ptr[i + 1] - ptr[i] : 0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) len = max(len, __shfl_xor(len, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, len);
+}
+
+// Numeric rows of C = A B when no row of B has more than WB entries (B an
+// interpolation operator with truncated rows).  One wavefront per row: the
+// lanes fetch 64 entries of A_i and their rows of B at once and insert the
+// columns into the hash table in parallel, remembering each product's slot;
+// the values are then added entry by entry of A_i in ascending order from
+// LDS, the order and arithmetic of k_spgemm, without its chain of dependent
+// global loads per entry.  Rows whose exact count lies in [sel_lo, sel_hi].
+template <int TBL, int WB>
+__global__ void __launch_bounds__(64)
+k_spgemm_narrow(int n, const int* __restrict__ ap, const int* __restrict__ ac, const double* __restrict__ av,
+                const int* __restrict__ bp, const int* __restrict__ bc, const double* __restrict__ bv,
+                const int* __restrict__ cnt, int sel_lo, int sel_hi, const int* __restrict__ cp,
+                int* __restrict__ cc, double* __restrict__ cv, int* __restrict__ overflow) {
+  constexpr int CK = (TBL * 3) / 4 + 64;
+  __shared__ int keys[TBL];
+  __shared__ double vals[TBL];
+  __shared__ int f_s[64 * WB];
+  __shared__ double f_b[64 * WB];
+  __shared__ double f_a[64];
+  __shared__ int ckeys[CK];
+  __shared__ double cvals[CK];
+  __shared__ int ninsert;
+  const int lane = threadIdx.x;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const int s = cnt[i];
+    if (s < sel_lo || s > sel_hi) continue;
+    int T = 64;
+    while (T < 2 * s && T < TBL) T <<= 1;
+    const int mask = T - 1;
+    for (int t = lane; t < T; t += 64) {
+      keys[t] = -1;
+      vals[t] = 0.0;
+    }
+    if (lane == 0) ninsert = 0;
+    __syncthreads();
+    bool bad = false;
+    const int a0 = ap[i], a1 = ap[i + 1];
+    for (int base = a0; base < a1; base += 64) {
+      const int e = base + lane;
+      double a = 0.0;
+      int qb = 0, ql = 0;
+      if (e < a1) {
+        const int k = ac[e];
+        a = av[e];
+        qb = bp[k];
+        ql = bp[k + 1] - qb;
+      }
+      if (ql > WB) {
+        bad = true;
+        ql = WB;
+      }
+      int jj[WB];
+      double bb[WB];
+#pragma unroll
+      for (int q = 0; q < WB; ++q)
+        if (q < ql) {
+          jj[q] = bc[qb + q];
+          bb[q] = bv[qb + q];
+        }
+#pragma unroll
+      for (int q = 0; q < WB; ++q) {
+        int h = -1;
+        if (q < ql) {
+          h = (int)hslot(jj[q], mask);
+          int probes = 0;
+          while (true) {
+            const int old = atomicCAS(&keys[h], -1, jj[q]);
+            if (old == -1 || old == jj[q]) break;
+            h = (h + 1) & mask;
+            if (++probes >= T) {
+              bad = true;
+              h = -1;
+              break;
+            }
+          }
+          f_b[lane * WB + q] = bb[q];
+        }
+        f_s[lane * WB + q] = h;
+      }
+      f_a[lane] = a;
+      __syncthreads();
+      const int ne = min(64, a1 - base);
+      for (int e2 = 0; e2 < ne; ++e2) {
+        if (lane < WB) {
+          const int h = f_s[e2 * WB + lane];
+          if (h >= 0) vals[h] += f_a[e2] * f_b[e2 * WB + lane];
+        }
+        __syncthreads();
+      }
+    }
+    if (bad) atomicOr(overflow, 8);
+    // compact (key, value) pairs, then place every entry by its rank
+    for (int t = lane; t < T; t += 64) {
+      const int key = keys[t];
+      if (key >= 0) {
+        const int pos = atomicAdd(&ninsert, 1);
+        if (pos < CK) {
+          ckeys[pos] = key;
+          cvals[pos] = vals[t];
+        }
+      }
+    }
+    __syncthreads();
+    const int nk = ninsert;
+    const int base = cp[i];
+    if (nk != cp[i + 1] - base || nk > CK) {
+      if (lane == 0) atomicOr(overflow, 2);
+      __syncthreads();
+      continue;
+    }
+    for (int p = lane; p < nk; p += 64) {
+      const int key = ckeys[p];
+      int r = 0;
+      for (int u = 0; u < nk; ++u) r += ckeys[u] < key ? 1 : 0;
+      cc[base + r] = key;
+      cv[base + r] = cvals[p];
     }
     __syncthreads();
   }
@@ -1059,22 +1188,28 @@ __global__ void k_pack_count(int n, const int* __restrict__ ptr, const int* __re
   if (e > a && mx - mn > 65535) atomicOr(wide, 1);
 }
 
-// one wavefront per row: copy values and columns into the padded layout
+// one wavefront per row: copy values and columns into the padded layout,
+// interleaved for G lanes per row (lanes_for4)
 template <class T>
 __global__ void k_pack_fill(int n, const int* __restrict__ ptr, const int* __restrict__ col, const T* __restrict__ val,
-                            const int* __restrict__ p4, const int* __restrict__ base, int wide,
+                            const int* __restrict__ p4, const int* __restrict__ base, int wide, int G,
                             uint16_t* __restrict__ c16, int* __restrict__ c32, T* __restrict__ out) {
   const int r = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (r >= n) return;
   const int a = ptr[r], len = ptr[r + 1] - a;
   const long o = 4L * p4[r];
-  const int padded = 4 * (p4[r + 1] - p4[r]);
+  const int nch = p4[r + 1] - p4[r];
+  const int padded = 4 * nch;
   const int b = base[r];
   for (int k = lane; k < padded; k += 64) {
-    const bool real = k < len;
-    out[o + k] = real ? val[a + k] : (T)0;
-    const int cc = real ? col[a + k] : b;
+    const int ch = k >> 2, t = k & 3;
+    const int g0 = ch - ch % G;                // first chunk of the group
+    const int q = min(G, nch - g0);            // chunks in the group
+    const int src = 4 * g0 + (ch - g0) + q * t;
+    const bool real = src < len;
+    out[o + k] = real ? val[a + src] : (T)0;
+    const int cc = real ? col[a + src] : b;
     if (wide) c32[o + k] = cc;
     else c16[o + k] = (uint16_t)(cc - b);
   }
@@ -1137,19 +1272,22 @@ void transpose(hfsi_ctx* c, const Csr<double>& P, Csr<double>& R) {
   R.rows = P.cols;
   R.cols = P.rows;
   R.nnz = P.nnz;
-  DevBuf<int> cnt, cur;
+  DevBuf<int> cnt, cur, tcol;
+  DevBuf<double> tval;
   cnt.zero(R.rows + 1, s);
   k_count_cols<<<div_up(P.rows, 256), 256, 0, s>>>(P.rows, P.ptr.p, P.col.p, cnt.p);
   HIP_LAUNCH_CHECK();
   R.ptr.ensure(R.rows + 1);
   exclusive_scan_async(cnt.p, R.ptr.p, R.rows + 1, s);
   cur.zero(R.rows, s);
+  tcol.ensure(R.nnz);
+  tval.ensure(R.nnz);
+  k_transpose_fill<<<div_up(P.rows, 256), 256, 0, s>>>(P.rows, P.ptr.p, P.col.p, P.val.p, R.ptr.p, cur.p, tcol.p,
+                                                       tval.p);
+  HIP_LAUNCH_CHECK();
   R.col.ensure(R.nnz);
   R.val.ensure(R.nnz);
-  k_transpose_fill<<<div_up(P.rows, 256), 256, 0, s>>>(P.rows, P.ptr.p, P.col.p, P.val.p, R.ptr.p, cur.p, R.col.p,
-                                                       R.val.p);
-  HIP_LAUNCH_CHECK();
-  k_sort_rows<<<div_up(R.rows, 256), 256, 0, s>>>(R.rows, R.ptr.p, R.col.p, R.val.p);
+  k_sort_rows<<<div_up((long)R.rows * 64, 256), 256, 0, s>>>(R.rows, R.ptr.p, tcol.p, tval.p, R.col.p, R.val.p);
   HIP_LAUNCH_CHECK();
 }
 
@@ -1162,8 +1300,10 @@ void spgemm(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>
   DevBuf<int> ub, cnt, flag;
   ub.ensure(n);
   cnt.zero(n + 1, s);
-  flag.zero(1, s);
+  flag.zero(2, s);  // [0] overflow bits, [1] longest row of B
   k_spgemm_ub<<<div_up(n, 256), 256, 0, s>>>(n, A.ptr.p, A.col.p, B.ptr.p, ub.p);
+  HIP_LAUNCH_CHECK();
+  k_max_rowlen<<<div_up(B.rows, 256), 256, 0, s>>>(B.rows, B.ptr.p, flag.p + 1);
   HIP_LAUNCH_CHECK();
   constexpr int TS = 2048, TL = 8192, S1 = 512, S2 = 1024;
   const int grid = std::min(n, 1 << 16);
@@ -1178,10 +1318,12 @@ void spgemm(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>
   HIP_LAUNCH_CHECK();
   Cm.ptr.ensure(n + 1);
   int64_t nnz = exclusive_scan(cnt.p, Cm.ptr.p, n + 1, s);
-  int fl = 0;
-  HIP_CHECK(hipMemcpyAsync(&fl, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  int fl2[2] = {0, 0};
+  HIP_CHECK(hipMemcpyAsync(fl2, flag.p, sizeof(fl2), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipStreamSynchronize(s));
-  if (fl) fail(HFSI_E_CAPACITY, "sparse product: a row exceeds the hash table");
+  if (fl2[0]) fail(HFSI_E_CAPACITY, "sparse product: a row exceeds the hash table");
+  const int bmax = fl2[1];
+  int fl = 0;
   if (nnz > INT32_MAX) fail(HFSI_E_ARG, "sparse product exceeds int32 indexing");
   Cm.nnz = nnz;
   Cm.col.ensure(nnz);
@@ -1189,10 +1331,18 @@ void spgemm(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>
   // numeric: the unstaged kernels by exact count (measured faster than the
   // staged numeric variant, whose per-row latency chain is no shorter)
   // (a 512-slot table for short rows keeps many more rows in flight per CU)
-  k_spgemm<256, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 0,
-                                          192, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p, ub.p, -1);
-  k_spgemm<512, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 193,
-                                          384, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p, ub.p, -1);
+  if (bmax <= 4) {
+    // B with short rows (truncated interpolation): rows up to 384 entries
+    k_spgemm_narrow<256, 4><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 0,
+                                                192, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p);
+    k_spgemm_narrow<512, 4><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 193,
+                                                384, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p);
+  } else {
+    k_spgemm<256, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 0,
+                                            192, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p, ub.p, -1);
+    k_spgemm<512, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 193,
+                                            384, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p, ub.p, -1);
+  }
   k_spgemm<TS, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 385,
                                          TS * 3 / 4, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p, ub.p, -1);
   k_spgemm<TL, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p,
@@ -1201,7 +1351,7 @@ void spgemm(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>
   HIP_LAUNCH_CHECK();
   HIP_CHECK(hipMemcpyAsync(&fl, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipStreamSynchronize(s));
-  if (fl) fail(HFSI_E_CAPACITY, "sparse product: a row has more than 6144 entries");
+  if (fl) fail(HFSI_E_CAPACITY, "sparse product: a row has more than 6144 entries or overflowed its table");
 }
 
 void smoother_data(hfsi_ctx* c, Level& L, const hfsi_amg_params& prm, int level) {
@@ -1253,13 +1403,14 @@ void pack_level(hfsi_ctx* c, Level& L, int precision) {
   if (precision == 1) K.v64.release();
   else K.v32.release();
   const int grid = div_up((long)n * 64, 256);
+  const int G = lanes_for4(K.chunks, n);
   if (precision == 1) {
     K.v32.ensure(m);
-    k_pack_fill<float><<<grid, 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A32.p, K.p4.p, K.base.p, (int)K.wide, K.c16.p,
-                                            K.c32.p, K.v32.p);
+    k_pack_fill<float><<<grid, 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A32.p, K.p4.p, K.base.p, (int)K.wide, G,
+                                            K.c16.p, K.c32.p, K.v32.p);
   } else {
     K.v64.ensure(m);
-    k_pack_fill<double><<<grid, 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, K.p4.p, K.base.p, (int)K.wide,
+    k_pack_fill<double><<<grid, 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, K.p4.p, K.base.p, (int)K.wide, G,
                                              K.c16.p, K.c32.p, K.v64.p);
   }
   HIP_LAUNCH_CHECK();

@@ -108,6 +108,21 @@ struct DevBuf {
 
 inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 
+// Lanes per row of the padded CSR layout: 3 to 6 chunks per lane (8 lanes
+// for the 25-35 chunks of the first coarse levels measured fastest), more
+// lanes on small levels so that the launch still spreads over the whole chip.
+// Lane g of a row takes the row's chunks g, g+G, g+2G, ...; within a group of
+// q <= G consecutive chunks starting at entry e0, slot t of chunk g holds
+// entry e0 + g + q t, so that the G lanes' t-th gathers read G consecutive
+// (sorted) columns.
+inline int lanes_for4(int64_t chunks, int rows) {
+  const double avg = rows ? (double)chunks / rows : 1.0;
+  int G = 2;
+  while (G < 64 && 6.0 * G <= avg) G *= 2;
+  while (G < 64 && (int64_t)rows * G < 65536) G *= 2;
+  return G;
+}
+
 // --------------------------------------------------------------- CSR matrix
 template <class V>
 struct Csr {

@@ -70,7 +70,9 @@ void csr_launch(int G, int n, const int* ptr, const int* col, const T* val, cons
 
 // Same operations on the padded CSR copy: G lanes per row, each lane whole
 // 4-entry chunks (one 16-byte value load for fp32, one 8-byte load of 16-bit
-// column offsets, or 16 bytes of int32 columns on wide levels).
+// column offsets, or 16 bytes of int32 columns on wide levels).  The chunks
+// are interleaved so that the lanes' k-th gathers fall on neighbouring
+// columns of the row (see lanes_for4).
 template <class T>
 struct Vec4;
 template <>
@@ -117,17 +119,6 @@ k_csr4(int n, const int* __restrict__ p4, const int* __restrict__ base, const vo
     d[gid] = dn;
     y[gid] = x[gid] + dn;
   }
-}
-
-// lanes per row for the padded layout: 3 to 6 chunks per lane (8 lanes for the
-// 25-35 chunks of the first coarse levels measured fastest), more lanes on
-// small levels so that the launch still spreads over the whole chip
-inline int lanes_for4(int64_t chunks, int rows) {
-  const double avg = rows ? (double)chunks / rows : 1.0;
-  int G = 2;
-  while (G < 64 && 6.0 * G <= avg) G *= 2;
-  while (G < 64 && (int64_t)rows * G < 65536) G *= 2;
-  return G;
 }
 
 template <class T, int OP, bool WIDE>
