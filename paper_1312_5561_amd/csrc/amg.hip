@@ -53,11 +53,14 @@ k_strength(int n, const int* __restrict__ ptr, const int* __restrict__ col, cons
   }
 }
 
-__global__ void k_lambda(int n, const int* __restrict__ ptr, const int* __restrict__ col,
-                         const uint8_t* __restrict__ strong, int* __restrict__ lam) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+// PMIS kernels: 8 lanes per row
+__global__ void __launch_bounds__(256)
+k_lambda(int n, const int* __restrict__ ptr, const int* __restrict__ col, const uint8_t* __restrict__ strong,
+         int* __restrict__ lam) {
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const int lane = threadIdx.x & 7;
   if (i >= n) return;
-  for (int e = ptr[i]; e < ptr[i + 1]; ++e)
+  for (int e = ptr[i] + lane; e < ptr[i + 1]; e += 8)
     if (strong[e]) atomicAdd(&lam[col[e]], 1);
 }
 
@@ -78,13 +81,14 @@ __global__ void k_pmis_init(int n, const int* __restrict__ lam, uint64_t seed, i
 }
 
 // j beats i when (key_j, j) > (key_i, i)
-__global__ void k_pmis_select(int n, const int* __restrict__ ptr, const int* __restrict__ col,
-                              const uint8_t* __restrict__ strong, const uint64_t* __restrict__ key,
-                              const int8_t* __restrict__ state, int* __restrict__ notmax) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256)
+k_pmis_select(int n, const int* __restrict__ ptr, const int* __restrict__ col, const uint8_t* __restrict__ strong,
+              const uint64_t* __restrict__ key, const int8_t* __restrict__ state, int* __restrict__ notmax) {
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const int lane = threadIdx.x & 7;
   if (i >= n || state[i] != ST_U) return;
   const uint64_t ki = key[i];
-  for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
+  for (int e = ptr[i] + lane; e < ptr[i + 1]; e += 8) {
     if (!strong[e]) continue;
     const int j = col[e];
     if (state[j] != ST_U) continue;
@@ -102,17 +106,20 @@ __global__ void k_pmis_mark_c(int n, int* __restrict__ notmax, int8_t* __restric
   notmax[i] = 0;
 }
 
-__global__ void k_pmis_mark_f(int n, const int* __restrict__ ptr, const int* __restrict__ col,
-                              const uint8_t* __restrict__ strong, int8_t* __restrict__ state,
-                              int* __restrict__ remaining) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256)
+k_pmis_mark_f(int n, const int* __restrict__ ptr, const int* __restrict__ col, const uint8_t* __restrict__ strong,
+              int8_t* __restrict__ state, int* __restrict__ remaining) {
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const int lane = threadIdx.x & 7;
   if (i >= n || state[i] != ST_U) return;
-  for (int e = ptr[i]; e < ptr[i + 1]; ++e)
-    if (strong[e] && state[col[e]] == ST_C) {
-      state[i] = ST_F;
-      return;
-    }
-  atomicAdd(remaining, 1);
+  int found = 0;
+  for (int e = ptr[i] + lane; e < ptr[i + 1]; e += 8)
+    if (strong[e] && state[col[e]] == ST_C) found = 1;
+#pragma unroll
+  for (int o = 4; o > 0; o >>= 1) found |= __shfl_xor(found, o, 8);
+  if (lane != 0) return;
+  if (found) state[i] = ST_F;
+  else atomicAdd(remaining, 1);
 }
 
 __global__ void k_is_c(int n, const int8_t* __restrict__ state, int* __restrict__ flag) {
@@ -256,41 +263,93 @@ k_interp_fill16(int n, const int* __restrict__ ptr, const int* __restrict__ col,
 }
 
 // Extended+i interpolation (De Sterck, Falgout, Nolting, Yang 2008) on
-// same-component couplings, LN lanes per row.  For an F row i the candidate
-// set Chat_i (strong C neighbours of i and of its strong F neighbours) is
-// built in an LDS hash table and ranked by column; then
+// same-component couplings, one wavefront per row.  For an F row i the
+// candidate set Chat_i (strong C neighbours of i and of its strong F
+// neighbours) is built in an LDS hash table and ranked by column; then
 //   w_ij = -(a_ij + sum_{k in F_i} a_ik abar_kj / s_k) / atilde_ii,
 //   atilde_ii = a_ii + sum_{weak n not in Chat_i} a_in + sum_k a_ik abar_ki / s_k,
 //   s_k = sum_{l in Chat_i + {i}} abar_kl (s_k = 0: a_ik lumped instead).
-// With p_max > 0 a longer row keeps its p_max largest |w| (float32 keys,
-// ties to the smaller column), rescaled to the full row sum.  FILL = false
-// writes the entry count of each row, FILL = true the entries (ascending
-// columns).  Sums over a row are lane-strided and tree-reduced.
-constexpr int EXTPI_LANES = 64;  // lanes per row: one wavefront (measured fastest of 16/32/64)
+// The strong F neighbours are taken NG at a time, 64/NG lanes each: within a
+// window of 64 entries of row i, neighbour t goes to group t mod NG.  Every
+// group keeps its own partial sums, added in group order at the end, so the
+// result does not depend on scheduling.  With p_max > 0 a longer row keeps
+// its p_max largest |w| (float32 keys, ties to the smaller column), rescaled
+// to the full row sum.  FILL = false writes the entry count of each row,
+// FILL = true the entries (ascending columns).
 constexpr int XH = 128;    // hash slots per row
 constexpr int XMAX = 96;   // candidates per row
-constexpr int XQ = 4;      // entries of a neighbour row each lane keeps in registers
+constexpr int XNG = 1;     // strong F neighbours in flight per row (measured fastest of 1/2/4/8)
 __device__ __forceinline__ int xh_slot(int key) { return (int)(((unsigned)key * 2654435761u) >> 25); }
 
-template <bool FILL, int LN>
+// position of the t-th set bit (t < popcount) of a 64-bit mask
+__device__ __forceinline__ int nth_set(unsigned long long m, int t) {
+  int pos = 0;
+#pragma unroll
+  for (int w = 32; w > 0; w >>= 1) {
+    const int c = __popcll(m & ((1ull << w) - 1ull));
+    if (t >= c) {
+      t -= c;
+      m >>= w;
+      pos += w;
+    }
+  }
+  return pos;
+}
+
+template <bool FILL, int NG>
 __global__ void __launch_bounds__(256)
 k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const double* __restrict__ val,
         const uint8_t* __restrict__ strong, const int8_t* __restrict__ state, const int* __restrict__ comp,
         const int* __restrict__ cidx, int p_max, int* __restrict__ cnt, const int* __restrict__ pptr,
         int* __restrict__ pcol, double* __restrict__ pval, int* __restrict__ overflow) {
-  constexpr int RB = 256 / LN;  // rows per block
+  constexpr int RB = 4;         // rows per block, one wavefront each
+  constexpr int SUB = 64 / NG;  // lanes per neighbour
+  constexpr int XQ = 256 / SUB; // entries of a neighbour row each lane keeps in registers
   __shared__ int h_key[RB][XH];
   __shared__ int h_rank[RB][XH];
-  __shared__ int s_mem[RB][XMAX];   // members in insertion order, then by rank
+  __shared__ int s_mem[RB][XMAX];   // members in insertion order, then selection ranks
   __shared__ int s_sorted[RB][XMAX];
   __shared__ double s_num[RB][XMAX];
+  __shared__ double s_part[RB][NG][XMAX];
   __shared__ int s_cnt[RB];
-  const int g = threadIdx.x / LN, lane = threadIdx.x % LN;
-  const int i = (blockIdx.x * blockDim.x + threadIdx.x) / LN;
+  const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int grp = lane / SUB, sl = lane % SUB;
+  const int i = blockIdx.x * RB + g;
   const bool row = i < n && state[i] != ST_C;
-  for (int t = lane; t < XH; t += LN) h_key[g][t] = -1;
+  for (int t = lane; t < XH; t += 64) h_key[g][t] = -1;
   if (lane == 0) s_cnt[g] = 0;
   __syncthreads();
+  // the strong F neighbours of row i, NG at a time: fn(k, a_ik, row k's
+  // first entry, its end) runs on the SUB lanes of one group (called by the
+  // whole wavefront)
+  auto f_neighbours = [&](auto&& fn) {
+    const int lo = ptr[i], hi = ptr[i + 1];
+    for (int wb = lo; wb < hi; wb += 64) {
+      const int e = wb + lane;
+      int kk = 0, kb = 0, ke = 0;
+      double aa = 0.0;
+      bool isf = false;
+      if (e < hi) {
+        kk = col[e];
+        isf = strong[e] && state[kk] == ST_F;
+        aa = val[e];
+        if (isf) {
+          kb = ptr[kk];
+          ke = ptr[kk + 1];
+        }
+      }
+      const unsigned long long fm = __ballot(isf);
+      const int nf = __popcll(fm);
+      for (int t0 = 0; t0 < nf; t0 += NG) {
+        const int t = t0 + grp;
+        const int src = t < nf ? nth_set(fm, t) : 0;
+        const int k = __shfl(kk, src, 64);
+        const double a = __shfl(aa, src, 64);
+        const int k0 = __shfl(kb, src, 64), k1 = __shfl(ke, src, 64);
+        if (t < nf) fn(k, a, k0, k1);
+      }
+    }
+  };
   // ---- candidates
   if (row) {
     auto insert = [&](int key) {
@@ -307,18 +366,16 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
       }
     };
     const int lo = ptr[i], hi = ptr[i + 1];
-    for (int e = lo + lane; e < hi; e += LN) {
+    for (int e = lo + lane; e < hi; e += 64) {
       const int j = col[e];
       if (strong[e] && state[j] == ST_C) insert(j);
     }
-    for (int e = lo; e < hi; ++e) {
-      const int k = col[e];
-      if (!strong[e] || state[k] == ST_C) continue;
-      for (int f = ptr[k] + lane; f < ptr[k + 1]; f += LN) {
-        const int m = col[f];
-        if (strong[f] && state[m] == ST_C) insert(m);
+    f_neighbours([&](int, double, int klo, int khi) {
+      for (int f = klo + sl; f < khi; f += SUB) {
+        const int mm = col[f];
+        if (strong[f] && state[mm] == ST_C) insert(mm);
       }
-    }
+    });
   }
   __syncthreads();
   const int m = s_cnt[g];
@@ -331,12 +388,14 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
   const bool work = row && m > 0 && m <= XMAX;
   // ---- rank by column
   if (work) {
-    for (int t = lane; t < m; t += LN) {
+    for (int t = lane; t < m; t += 64) {
       const int key = s_mem[g][t];
       int r = 0;
       for (int u = 0; u < m; ++u) r += s_mem[g][u] < key;
       s_sorted[g][r] = key;
       s_num[g][r] = 0.0;
+#pragma unroll
+      for (int q = 0; q < NG; ++q) s_part[g][q][r] = 0.0;
       int h = xh_slot(key);
       while (h_key[g][h] != key) h = (h + 1) & (XH - 1);
       h_rank[g][h] = r;
@@ -358,7 +417,7 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
     const int lo = ptr[i], hi = ptr[i + 1], ci = comp[i];
     // row i: direct couplings to Chat_i, weak ones lumped, the diagonal
     double dpart = 0.0;
-    for (int e = lo + lane; e < hi; e += LN) {
+    for (int e = lo + lane; e < hi; e += 64) {
       const int j = col[e];
       if (comp[j] != ci) continue;
       const double a = val[e];
@@ -371,16 +430,14 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
       else if (!(strong[e] && state[j] == ST_F)) dpart += a;
     }
 #pragma unroll
-    for (int o = LN / 2; o > 0; o >>= 1) dpart += __shfl_xor(dpart, o, LN);
+    for (int o = 32; o > 0; o >>= 1) dpart += __shfl_xor(dpart, o, 64);
     den = dpart;
-    // strong F neighbours, in row order
-    for (int e = lo; e < hi; ++e) {
-      const int k = col[e];
-      if (!strong[e] || state[k] != ST_F) continue;
-      const double a_ik = val[e];
-      const int klo = ptr[k], khi = ptr[k + 1];
+    // strong F neighbours: this group's terms of atilde_ii and of the numerators
+    double den_g = 0.0;
+    double* part = s_part[g][grp];
+    f_neighbours([&](int k, double a_ik, int klo, int khi) {
       double akk = 0.0, s_neg = 0.0, s_pos = 0.0, ki_neg = 0.0, ki_pos = 0.0;
-      int c_r[XQ];        // this lane's entries of row k: rank in Chat_i (or -1) and value
+      int c_r[XQ];  // this lane's entries of row k: rank in Chat_i (or -1) and value
       double c_v[XQ];
 #pragma unroll
       for (int q = 0; q < XQ; ++q) {
@@ -388,15 +445,17 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
         c_v[q] = 0.0;
       }
       int q = 0;
-      for (int f = klo + lane; f < khi; f += LN, ++q) {
+      for (int f = klo + sl; f < khi; f += SUB, ++q) {
         const int mm = col[f];
         const double v = val[f];
         if (mm == k) akk = v;
         const int r = mm == i ? -1 : rank_of(mm);
-        if (q < XQ) {
-          c_r[q] = r;
-          c_v[q] = v;
-        }
+#pragma unroll
+        for (int u = 0; u < XQ; ++u)
+          if (u == q) {
+            c_r[u] = r;
+            c_v[u] = v;
+          }
         if (mm == i || r >= 0) {
           if (v < 0.0) s_neg += v;
           else if (v > 0.0) s_pos += v;
@@ -407,21 +466,21 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
         }
       }
 #pragma unroll
-      for (int o = LN / 2; o > 0; o >>= 1) {
-        akk += __shfl_xor(akk, o, LN);
-        s_neg += __shfl_xor(s_neg, o, LN);
-        s_pos += __shfl_xor(s_pos, o, LN);
-        ki_neg += __shfl_xor(ki_neg, o, LN);
-        ki_pos += __shfl_xor(ki_pos, o, LN);
+      for (int o = SUB / 2; o > 0; o >>= 1) {
+        akk += __shfl_xor(akk, o, SUB);
+        s_neg += __shfl_xor(s_neg, o, SUB);
+        s_pos += __shfl_xor(s_pos, o, SUB);
+        ki_neg += __shfl_xor(ki_neg, o, SUB);
+        ki_pos += __shfl_xor(ki_pos, o, SUB);
       }
       const double sk = akk < 0.0 ? -1.0 : 1.0;
       const double sden = sk > 0.0 ? s_neg : s_pos;
       if (sden == 0.0) {
-        den += a_ik;
-        continue;
+        den_g += a_ik;
+        return;
       }
       q = 0;
-      for (int f = klo + lane; f < khi; f += LN, ++q) {
+      for (int f = klo + sl; f < khi; f += SUB, ++q) {
         int r = -1;
         double v = 0.0;
         if (q < XQ) {
@@ -437,21 +496,28 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
           v = val[f];
         }
         if (r < 0) continue;
-        if (v * sk < 0.0) s_num[g][r] += a_ik * v / sden;  // distinct columns: one lane per slot
+        if (v * sk < 0.0) part[r] += a_ik * v / sden;  // distinct columns: one lane per slot
       }
       const double aki = sk > 0.0 ? ki_neg : ki_pos;
-      den += a_ik * aki / sden;
-    }
+      den_g += a_ik * aki / sden;
+    });
+#pragma unroll
+    for (int q = 0; q < NG; ++q) den += __shfl(den_g, q * SUB, 64);
   }
   __syncthreads();
   // ---- weights (in place), selection ranks, output in ascending columns
   if (work)
-    for (int t = lane; t < m; t += LN) s_num[g][t] = -s_num[g][t] / den;
+    for (int t = lane; t < m; t += 64) {
+      double v = s_num[g][t];
+#pragma unroll
+      for (int q = 0; q < NG; ++q) v += s_part[g][q][t];
+      s_num[g][t] = -v / den;
+    }
   __syncthreads();
   const bool trunc = work && p_max > 0 && m > p_max;
   int* sel = s_mem[g];  // the insertion list is no longer needed
   if (trunc)
-    for (int t = lane; t < m; t += LN) {
+    for (int t = lane; t < m; t += 64) {
       const float key = fabsf((float)s_num[g][t]);
       int r = 0;
       for (int u = 0; u < m; ++u) {
@@ -463,20 +529,20 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
   __syncthreads();
   if (work) {
     double tot = 0.0, kept = 0.0;
-    for (int t = lane; t < m; t += LN) {
+    for (int t = lane; t < m; t += 64) {
       tot += s_num[g][t];
       if (trunc && sel[t] < p_max) kept += s_num[g][t];
     }
 #pragma unroll
-    for (int o = LN / 2; o > 0; o >>= 1) {
-      tot += __shfl_xor(tot, o, LN);
-      kept += __shfl_xor(kept, o, LN);
+    for (int o = 32; o > 0; o >>= 1) {
+      tot += __shfl_xor(tot, o, 64);
+      kept += __shfl_xor(kept, o, 64);
     }
     const double scale = trunc && kept != 0.0 ? tot / kept : 1.0;
     // pptr == nullptr: rows go to a fixed stride of p_max entries, counts to cnt
     const long p0 = pptr ? (long)pptr[i] : (long)i * p_max;
     if (!pptr && lane == 0) cnt[i] = trunc ? p_max : m;
-    for (int t = lane; t < m; t += LN) {
+    for (int t = lane; t < m; t += 64) {
       int pos = t;
       if (trunc) {
         if (sel[t] >= p_max) continue;
@@ -1475,7 +1541,7 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
                                               L.strong.p);
     HIP_LAUNCH_CHECK();
     lam.zero(n, s);
-    k_lambda<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.strong.p, lam.p);
+    k_lambda<<<div_up((long)n * 8, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.strong.p, lam.p);
     HIP_LAUNCH_CHECK();
     key.ensure(n);
     L.state.ensure(n);
@@ -1488,11 +1554,11 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
       if (round > n + 1) fail(HFSI_E_HIP, "PMIS did not terminate");
       HIP_CHECK(hipMemsetAsync(rem.p, 0, sizeof(int) * PMIS_BATCH, s));
       for (int k = 0; k < PMIS_BATCH; ++k) {
-        k_pmis_select<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.strong.p, key.p, L.state.p, notmax.p);
+        k_pmis_select<<<div_up((long)n * 8, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.strong.p, key.p, L.state.p, notmax.p);
         HIP_LAUNCH_CHECK();
         k_pmis_mark_c<<<div_up(n, 256), 256, 0, s>>>(n, notmax.p, L.state.p);
         HIP_LAUNCH_CHECK();
-        k_pmis_mark_f<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.strong.p, L.state.p, rem.p + k);
+        k_pmis_mark_f<<<div_up((long)n * 8, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.strong.p, L.state.p, rem.p + k);
         HIP_LAUNCH_CHECK();
       }
       int left[PMIS_BATCH];
@@ -1529,11 +1595,11 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
     if (strided) {
       tcol.ensure((size_t)n * prm.p_max);
       tval.ensure((size_t)n * prm.p_max);
-      k_extpi<true, EXTPI_LANES><<<div_up((long)n * EXTPI_LANES, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p,
+      k_extpi<true, XNG><<<div_up(n, 4), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p,
                                                                L.state.p, L.comp.p, L.cidx.p, prm.p_max, cnt.p,
                                                                nullptr, tcol.p, tval.p, ovf.p);
     } else if (extpi) {
-      k_extpi<false, EXTPI_LANES><<<div_up((long)n * EXTPI_LANES, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p,
+      k_extpi<false, XNG><<<div_up(n, 4), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p,
                                                                 L.state.p, L.comp.p, L.cidx.p, prm.p_max, cnt.p,
                                                                 nullptr, nullptr, nullptr, ovf.p);
     } else {
@@ -1550,7 +1616,7 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
       if (strided)
         k_compact_rows<<<div_up(n, 256), 256, 0, s>>>(n, prm.p_max, L.P.ptr.p, tcol.p, tval.p, L.P.col.p, L.P.val.p);
       else if (extpi)
-        k_extpi<true, EXTPI_LANES><<<div_up((long)n * EXTPI_LANES, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p,
+        k_extpi<true, XNG><<<div_up(n, 4), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p,
                                                                  L.state.p, L.comp.p, L.cidx.p, prm.p_max, nullptr,
                                                                  L.P.ptr.p, L.P.col.p, L.P.val.p, ovf.p);
       else
