@@ -112,11 +112,14 @@ k_pmis_mark_f(int n, const int* __restrict__ ptr, const int* __restrict__ col, c
   const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
   const int lane = threadIdx.x & 7;
   if (i >= n || state[i] != ST_U) return;
+  const int hi = ptr[i + 1];
   int found = 0;
-  for (int e = ptr[i] + lane; e < ptr[i + 1]; e += 8)
-    if (strong[e] && state[col[e]] == ST_C) found = 1;
+  for (int b = ptr[i]; b < hi && !found; b += 8) {  // the 8 lanes leave together
+    const int e = b + lane;
+    found = e < hi && strong[e] && state[col[e]] == ST_C ? 1 : 0;
 #pragma unroll
-  for (int o = 4; o > 0; o >>= 1) found |= __shfl_xor(found, o, 8);
+    for (int o = 4; o > 0; o >>= 1) found |= __shfl_xor(found, o, 8);
+  }
   if (lane != 0) return;
   if (found) state[i] = ST_F;
   else atomicAdd(remaining, 1);
@@ -1290,9 +1293,13 @@ namespace {
 // recurrence coefficients stay on the device (ab: alpha[32], beta[32], the
 // result, the start norm; kst: steps kept, stopped); the host reads only the
 // result.
-double lanczos_max(hfsi_ctx* c, Level& L, int steps, uint64_t seed, int level) {
+void lanczos_enqueue(hfsi_ctx* c, Level& L, int steps, uint64_t seed, int level, double* out) {
   const int n = L.n;
-  hipStream_t s = c->stream;
+  // on the aux stream, after the level's operator and diagonal are ready
+  hipStream_t s = c->aux;
+  HIP_CHECK(hipEventRecord(c->aev[0], c->stream));
+  HIP_CHECK(hipStreamWaitEvent(s, c->aev[0], 0));
+  StreamTag tag(s);  // the temporaries below stay with the aux stream
   const int nb = 256, g = div_up(n, 256);
   DevBuf<double> q, qp, w, ab, part;
   DevBuf<int> kst;
@@ -1325,12 +1332,8 @@ double lanczos_max(hfsi_ctx* c, Level& L, int steps, uint64_t seed, int level) {
     k_scale_inv_dev<<<g, 256, 0, s>>>(n, ab.p + 32 + it, w.p, q.p);
     HIP_LAUNCH_CHECK();
   }
-  k_tridiag_max<<<1, 1, 0, s>>>(kst.p, ab.p, ab.p + 32, ab.p + 64);
+  k_tridiag_max<<<1, 1, 0, s>>>(kst.p, ab.p, ab.p + 32, out);
   HIP_LAUNCH_CHECK();
-  double lmax = 0.0;
-  HIP_CHECK(hipMemcpyAsync(&lmax, ab.p + 64, sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
-  return lmax;
 }
 
 void transpose(hfsi_ctx* c, const Csr<double>& P, Csr<double>& R) {
@@ -1430,7 +1433,7 @@ void smoother_data(hfsi_ctx* c, Level& L, const hfsi_amg_params& prm, int level)
   } else {
     k_inv_diag<<<div_up((long)L.n * 8, 256), 256, 0, s>>>(L.n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.dinv.p, L.dinv32.p);
     HIP_LAUNCH_CHECK();
-    L.lmax = lanczos_max(c, L, 10, prm.seed, level);
+    lanczos_enqueue(c, L, 10, prm.seed, level, c->H.lmax_dev.p + level);  // read when the hierarchy is done
   }
 }
 
@@ -1525,6 +1528,12 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
   H.nu_post = prm.nu_post;
   H.cheb_degree = prm.cheb_degree;
   H.cheb_ratio = prm.cheb_ratio;
+  // the Lanczos estimates run on the aux stream; joined below (and on unwind)
+  struct AuxJoin {
+    hfsi_ctx* c;
+    ~AuxJoin() { (void)hipStreamSynchronize(c->aux); }
+  } aux_join{c};
+  H.lmax_dev.ensure(32);
   int rounds_total = 0;
   DevBuf<int> lam, notmax, flag, rem;
   DevBuf<uint64_t> key;
@@ -1688,10 +1697,17 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
   }
   k_gj_extract<<<div_up((long)nc * nc, 256), 256, 0, s>>>(nc, gin, H.coarse_inv.p);
   HIP_LAUNCH_CHECK();
+  // join the aux stream, then read the singularity flag and the estimates
+  HIP_CHECK(hipEventRecord(c->aev[1], c->aux));
+  HIP_CHECK(hipStreamWaitEvent(s, c->aev[1], 0));
+  const int nl = (int)H.L.size();
+  double lm[32] = {0};
   int sg = 0;
   HIP_CHECK(hipMemcpyAsync(&sg, sing.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  if (prm.smoother == 1) HIP_CHECK(hipMemcpyAsync(lm, H.lmax_dev.p, sizeof(double) * nl, hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipStreamSynchronize(s));
   if (sg) fail(HFSI_E_BREAKDOWN, "coarsest AMG operator is singular");
+  for (int l = 0; l < nl; ++l) H.L[l].lmax = prm.smoother == 1 ? lm[l] : 0.0;
   H.ready = true;
   double rho = -1.0;
   if (prm.interp == 1) {

@@ -45,6 +45,16 @@ struct Error : std::runtime_error {
 // device) runs while a context is alive.
 extern thread_local hipStream_t tls_stream;  // stream of the current library call
 extern thread_local bool tls_idle;           // releases happen after a stream sync
+
+// Tags the device blocks released in its scope with another stream (declare
+// it before the buffers it covers).
+struct StreamTag {
+  hipStream_t saved;
+  explicit StreamTag(hipStream_t s) : saved(tls_stream) { tls_stream = s; }
+  ~StreamTag() { tls_stream = saved; }
+  StreamTag(const StreamTag&) = delete;
+  StreamTag& operator=(const StreamTag&) = delete;
+};
 void* dev_alloc(size_t bytes, size_t* cap, int* dev);
 void dev_release(void* p, size_t cap, int dev);
 void dev_cache_trim();  // hipFree every idle cached block (no context alive)
@@ -182,6 +192,7 @@ struct Hierarchy {
   std::vector<Level> L;
   int nc = 0;                 // coarsest size
   DevBuf<double> coarse_inv;  // explicit inverse of the coarsest operator
+  DevBuf<double> lmax_dev;    // per-level eigenvalue estimates (written on the aux stream)
   DevBuf<double> cwork;
   int precision = 0;
   int smoother = 0;
@@ -246,6 +257,8 @@ struct hfsi_ctx {
   void* mlp_impl = nullptr;      // learned-interpolation state (mlp.hip)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t kev[2] = {nullptr, nullptr};  // FGMRES scalar read-back slots
+  hipStream_t aux = nullptr;               // AMG set-up work off the critical path
+  hipEvent_t aev[2] = {nullptr, nullptr};  // aux fork and join
 };
 
 namespace hfsi {

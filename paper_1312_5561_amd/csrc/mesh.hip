@@ -234,11 +234,16 @@ std::atomic<int> g_live_contexts{0};  // the device block cache is trimmed when 
 
 // events and pinned host memory of a context (safe on partly created ones)
 void release_events(hfsi_ctx* c) {
-  for (hipEvent_t* e : {&c->ev0, &c->ev1, &c->kev[0], &c->kev[1]})
+  for (hipEvent_t* e : {&c->ev0, &c->ev1, &c->kev[0], &c->kev[1], &c->aev[0], &c->aev[1]})
     if (*e) {
       (void)hipEventDestroy(*e);
       *e = nullptr;
     }
+  if (c->aux) {
+    (void)hipStreamSynchronize(c->aux);
+    (void)hipStreamDestroy(c->aux);
+    c->aux = nullptr;
+  }
   if (c->pinned) (void)hipHostFree(c->pinned);
   c->pinned = nullptr;
 }
@@ -256,6 +261,9 @@ extern "C" hfsi_status hfsi_create(hfsi_ctx** out, int device, void* stream) {
                   hipEventCreate(&c->ev1) == hipSuccess &&
                   hipEventCreateWithFlags(&c->kev[0], hipEventDisableTiming) == hipSuccess &&
                   hipEventCreateWithFlags(&c->kev[1], hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->aev[0], hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->aev[1], hipEventDisableTiming) == hipSuccess &&
+                  hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) == hipSuccess &&
                   hipHostMalloc((void**)&c->pinned, 64 * sizeof(double)) == hipSuccess;
   if (!ok) {
     release_events(c);
@@ -271,7 +279,8 @@ extern "C" hfsi_status hfsi_destroy(hfsi_ctx* c) {
   if (!c) return HFSI_E_ARG;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  // the stream is idle: the context's device blocks become free for any stream
+  if (c->aux) (void)hipStreamSynchronize(c->aux);
+  // the streams are idle: the context's device blocks become free for any stream
   hfsi::tls_stream = c->stream;
   hfsi::tls_idle = true;
   release_events(c);
