@@ -1684,7 +1684,6 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
   M2.ensure(2 * (size_t)nc * nc);
   sing.zero(1, s);
   H.coarse_inv.ensure((size_t)nc * nc);
-  H.cwork.ensure(2 * (size_t)nc);
   k_dense_from_csr<<<div_up(nc, 256), 256, 0, s>>>(nc, Lc.A.ptr.p, Lc.A.col.p, Lc.A.val.p, M.p);
   HIP_LAUNCH_CHECK();
   // Gauss-Jordan on [A | I]: one launch per pivot, alternating buffers

@@ -193,7 +193,6 @@ struct Hierarchy {
   int nc = 0;                 // coarsest size
   DevBuf<double> coarse_inv;  // explicit inverse of the coarsest operator
   DevBuf<double> lmax_dev;    // per-level eigenvalue estimates (written on the aux stream)
-  DevBuf<double> cwork;
   int precision = 0;
   int smoother = 0;
   int nu_pre = 2, nu_post = 2;
@@ -285,7 +284,9 @@ void amg_setup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* in
 void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info);
 void check_amg_params(const hfsi_amg_params* p);
 void vcycle_apply(hfsi_ctx* c, const double* r, double* z);
-void precond_apply(hfsi_ctx* c, const double* r, double* z);
+// z = P_L^{-1} r; with scale, the vector preconditioned is r / *scale, also
+// written to rs
+void precond_apply(hfsi_ctx* c, const double* r, double* z, const double* scale = nullptr, double* rs = nullptr);
 void tangent_apply(hfsi_ctx* c, const double* x, double* y);
 void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_params& prm,
                   hfsi_solve_info* info);

@@ -239,16 +239,24 @@ k_restrict_first(int n, const int* __restrict__ ptr, const int* __restrict__ col
 // the same for level 0: r_u (node-interleaved fp64) -> right-hand side in T
 // and the first smoothing step
 template <class T>
-__global__ void k_split_u_first(int n, const double* __restrict__ r, const T* __restrict__ dinv, T* __restrict__ bu,
+__global__ void k_split_u_first(int n, const double* __restrict__ r, const double* __restrict__ scale,
+                                double* __restrict__ rs, const T* __restrict__ dinv, T* __restrict__ bu,
                                 T* __restrict__ xu, T* __restrict__ du, T cf) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 3 * n) return;
-  const int i = t / 3, c = t - 3 * i;
-  const T bv = (T)r[4 * i + c];
-  bu[t] = bv;
-  const T v = cf * dinv[t] * bv;
-  xu[t] = v;
-  if (du) du[t] = v;
+  if (t >= 4 * n) return;
+  const int i = t >> 2, c = t & 3;
+  double rv = r[t];
+  if (scale) {  // r / *scale is the vector preconditioned (and kept in rs)
+    rv = rv / scale[0];
+    rs[t] = rv;
+  }
+  if (c == 3) return;
+  const int u = 3 * i + c;
+  const T bv = (T)rv;
+  bu[u] = bv;
+  const T v = cf * dinv[u] * bv;
+  xu[u] = v;
+  if (du) du[u] = v;
 }
 
 template <class Tin, class Tout>
@@ -257,16 +265,18 @@ __global__ void k_cast(int n, const Tin* __restrict__ x, Tout* __restrict__ y) {
   if (i < n) y[i] = (Tout)x[i];
 }
 
-// coarse solve: y = Ainv b, one wavefront per row
-__global__ void k_dense_gemv(int n, const double* __restrict__ M, const double* __restrict__ x, double* __restrict__ y) {
+// coarse solve: y = Ainv b in fp64 (b and y in the cycle's type), one
+// wavefront per row
+template <class T>
+__global__ void k_dense_gemv(int n, const double* __restrict__ M, const T* __restrict__ x, T* __restrict__ y) {
   const int row = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
   const int lane = threadIdx.x % 64;
   if (row >= n) return;
   double s = 0.0;
-  for (int j = lane; j < n; j += 64) s += M[(size_t)row * n + j] * x[j];
+  for (int j = lane; j < n; j += 64) s += M[(size_t)row * n + j] * (double)x[j];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  if (lane == 0) y[row] = s;
+  if (lane == 0) y[row] = (T)s;
 }
 
 // ---- block matrix K (4x4 blocks), 16 lanes per node row
@@ -301,11 +311,17 @@ k_bsr4(int n, const int* __restrict__ bptr, const int* __restrict__ bcol, const 
 
 // r_u (node-interleaved fp64) -> level-0 right-hand side in T
 template <class T>
-__global__ void k_split_u(int n, const double* __restrict__ r, T* __restrict__ bu) {
+__global__ void k_split_u(int n, const double* __restrict__ r, const double* __restrict__ scale,
+                          double* __restrict__ rs, T* __restrict__ bu) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 3 * n) return;
-  const int i = t / 3, c = t - 3 * i;
-  bu[t] = (T)r[4 * i + c];
+  if (t >= 4 * n) return;
+  const int i = t >> 2, c = t & 3;
+  double rv = r[t];
+  if (scale) {
+    rv = rv / scale[0];
+    rs[t] = rv;
+  }
+  if (c < 3) bu[3 * i + c] = (T)rv;
 }
 
 // z_p = (B2 z_u - r_p) / s, z_u copied into the node-interleaved output
@@ -783,19 +799,7 @@ T* vcycle_rec(hfsi_ctx* c, int l, bool first_done) {
   LevelView<T> v = view<T>(L, last);
   const int n = L.n;
   if (last) {
-    double* bw = H.cwork.p;
-    double* xw = H.cwork.p + n;
-    const double* bd;
-    if (std::is_same<T, double>::value) {
-      bd = (const double*)v.b;
-    } else {
-      k_cast<T, double><<<div_up(n, 256), 256, 0, s>>>(n, v.b, bw);
-      HIP_LAUNCH_CHECK();
-      bd = bw;
-    }
-    k_dense_gemv<<<div_up((long)n * 64, 256), 256, 0, s>>>(n, H.coarse_inv.p, bd, xw);
-    HIP_LAUNCH_CHECK();
-    k_cast<double, T><<<div_up(n, 256), 256, 0, s>>>(n, xw, v.x);
+    k_dense_gemv<T><<<div_up((long)n * 64, 256), 256, 0, s>>>(n, H.coarse_inv.p, v.b, v.x);
     HIP_LAUNCH_CHECK();
     return v.x;
   }
@@ -846,7 +850,7 @@ void vcycle_apply(hfsi_ctx* c, const double* r, double* z) {
   }
 }
 
-void precond_apply(hfsi_ctx* c, const double* r, double* z) {
+void precond_apply(hfsi_ctx* c, const double* r, double* z, const double* scale, double* rs) {
   Hierarchy& H = c->H;
   if (!H.ready) fail(HFSI_E_ORDER, "preconditioner: no AMG hierarchy");
   Level& L0 = H.L[0];
@@ -856,26 +860,27 @@ void precond_apply(hfsi_ctx* c, const double* r, double* z) {
   const int grid16 = div_up((long)n * 16, 256);
   // level 0 takes its first pre-smoothing step in the kernel that splits r
   const bool fuse = H.L.size() > 1 && H.nu_pre > 0;
-  const int g3 = div_up(3 * n, 256);
+  const int g4 = div_up(4 * n, 256);
+  if (!scale) rs = nullptr;
   const double cf = first_step_coef(H, L0);
   if (H.precision == 0) {
     if (fuse)
-      k_split_u_first<double><<<g3, 256, 0, s>>>(n, r, L0.dinv.p, L0.b.p, L0.x.p, H.smoother == 1 ? L0.r.p : nullptr,
-                                                 cf);
+      k_split_u_first<double><<<g4, 256, 0, s>>>(n, r, scale, rs, L0.dinv.p, L0.b.p, L0.x.p,
+                                                 H.smoother == 1 ? L0.r.p : nullptr, cf);
     else
-      k_split_u<double><<<g3, 256, 0, s>>>(n, r, L0.b.p);
+      k_split_u<double><<<g4, 256, 0, s>>>(n, r, scale, rs, L0.b.p);
     HIP_LAUNCH_CHECK();
     double* zu = vcycle_rec<double>(c, 0, fuse);
-    k_pl_combine<double><<<grid16, 256, 0, s>>>(n, c->nptr.p, c->ncol.p, c->b2.p, zu, r, c->schur.p, z);
+    k_pl_combine<double><<<grid16, 256, 0, s>>>(n, c->nptr.p, c->ncol.p, c->b2.p, zu, scale ? rs : r, c->schur.p, z);
   } else {
     if (fuse)
-      k_split_u_first<float><<<g3, 256, 0, s>>>(n, r, L0.dinv32.p, L0.bf.p, L0.xf.p,
+      k_split_u_first<float><<<g4, 256, 0, s>>>(n, r, scale, rs, L0.dinv32.p, L0.bf.p, L0.xf.p,
                                                 H.smoother == 1 ? L0.rf.p : nullptr, (float)cf);
     else
-      k_split_u<float><<<g3, 256, 0, s>>>(n, r, L0.bf.p);
+      k_split_u<float><<<g4, 256, 0, s>>>(n, r, scale, rs, L0.bf.p);
     HIP_LAUNCH_CHECK();
     float* zu = vcycle_rec<float>(c, 0, fuse);
-    k_pl_combine<float><<<grid16, 256, 0, s>>>(n, c->nptr.p, c->ncol.p, c->b2.p, zu, r, c->schur.p, z);
+    k_pl_combine<float><<<grid16, 256, 0, s>>>(n, c->nptr.p, c->ncol.p, c->b2.p, zu, scale ? rs : r, c->schur.p, z);
   }
   HIP_LAUNCH_CHECK();
 }
@@ -981,7 +986,9 @@ void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_para
       for (int j = 0; j < m && !stop; ++j) {
         double* vj = V + (long)j * ld;
         double* zj = Z + (long)j * ld;
-        precond_apply(c, vj, zj);
+        // v_j = w / h_{j,j-1} is formed by the kernel that splits it for the cycle
+        if (j == 0) precond_apply(c, vj, zj);
+        else precond_apply(c, c->kw.p, zj, sc + 3, vj);
         tangent_apply(c, zj, c->kw.p);
         // CGS2: (A) h1 = V^T w and w.w; (B) w -= V h1, h2 = V^T w from the
         // same staged tiles; (C) w -= V h2 and ||w||; then column j = h1 + h2
@@ -1001,9 +1008,6 @@ void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_para
         HIP_LAUNCH_CHECK();
         HIP_CHECK(hipMemcpyAsync(c->pinned + 4 * (j & 1), sc + 2, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipEventRecord(c->kev[j & 1], s));
-        // next basis vector (V has m + 1 rows)
-        k_div_scalar<<<gN, 256, 0, s>>>(N, c->kw.p, sc + 3, V + (long)(j + 1) * ld);
-        HIP_LAUNCH_CHECK();
         if (j > 0) evaluate(j - 1);
       }
       if (!stop) evaluate(m - 1);
