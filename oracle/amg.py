@@ -311,10 +311,13 @@ class AmgParams:
     max_levels: int = 25
     seed: int = 12345
     smoother: str = "chebyshev"   # or "l1jacobi"
-    nu_pre: int = 1
-    nu_post: int = 2
-    cheb_degree: int = 2
+    nu_pre: int = 1                # sweeps before the coarse correction, every level
+    nu_post: int = 2               # sweeps after it on level 0
+    cheb_degree: int = 2           # their Chebyshev degree
     cheb_ratio: float = 30.0
+    cheb_degree_pre: int = 1       # pre-smoothing degree
+    nu_post_coarse: int = 1        # post-smoothing sweeps on levels >= 1
+    cheb_degree_coarse: int = 3    # their degree
     interp: str = "ext+i"          # or "classical"
     p_max: int = 4                 # ext+i truncation (0: none)
     lanczos_steps: int = 10
@@ -361,13 +364,13 @@ def _smoother_data(L, prm, lev):
         L.lam = lanczos_max(L.A, d, prm.lanczos_steps, prm.seed, lev)
 
 
-def smooth(L, b, x, nu, prm):
+def smooth(L, b, x, nu, prm, degree):
     if prm.smoother == "l1jacobi":
         for _ in range(nu):
             x = x + L.dinv * (b - L.A @ x)
         return x
     for _ in range(nu):
-        x = chebyshev(L.A, L.dinv, L.lam, b, x, prm.cheb_degree, prm.cheb_ratio)
+        x = chebyshev(L.A, L.dinv, L.lam, b, x, degree, prm.cheb_ratio)
     return x
 
 
@@ -392,15 +395,20 @@ def chebyshev(A, dinv, lam, b, x, degree=2, ratio=30.0):
 
 
 def vcycle(H: Hierarchy, b, prm: AmgParams = AmgParams(), lev=0):
-    """One V-cycle with zero initial guess on every level."""
+    """One V-cycle with zero initial guess on every level: nu_pre sweeps of
+    degree cheb_degree_pre, the coarse correction, then nu_post sweeps of
+    degree cheb_degree on level 0 (nu_post_coarse of cheb_degree_coarse on
+    the coarser levels)."""
     L = H.levels[lev]
     if lev == len(H.levels) - 1:
         return scipy.linalg.lu_solve(H.lu, b)
-    x = smooth(L, b, np.zeros_like(b), prm.nu_pre, prm)
+    x = smooth(L, b, np.zeros_like(b), prm.nu_pre, prm, prm.cheb_degree_pre)
     r = b - L.A @ x
     xc = vcycle(H, L.R @ r, prm, lev + 1)
     x = x + L.P @ xc
-    return smooth(L, b, x, prm.nu_post, prm)
+    if lev == 0:
+        return smooth(L, b, x, prm.nu_post, prm, prm.cheb_degree)
+    return smooth(L, b, x, prm.nu_post_coarse, prm, prm.cheb_degree_coarse)
 
 
 def convergence_factor(H, prm, cycles=10, seed=777):

@@ -1526,7 +1526,10 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
   H.smoother = prm.smoother;
   H.nu_pre = prm.nu_pre;
   H.nu_post = prm.nu_post;
+  H.nu_post_coarse = prm.nu_post_coarse;
   H.cheb_degree = prm.cheb_degree;
+  H.cheb_degree_pre = prm.cheb_degree_pre;
+  H.cheb_degree_coarse = prm.cheb_degree_coarse;
   H.cheb_ratio = prm.cheb_ratio;
   // the Lanczos estimates run on the aux stream; joined below (and on unwind)
   struct AuxJoin {
@@ -1770,11 +1773,13 @@ void check_amg_params(const hfsi_amg_params* p) {
   if (!p || p->struct_size != sizeof(hfsi_amg_params)) fail(HFSI_E_ARG, "amg params: struct_size mismatch");
   if (!(p->strength_theta > 0.0 && p->strength_theta <= 1.0)) fail(HFSI_E_ARG, "amg params: theta in (0,1]");
   if (p->max_coarse < 1 || p->max_levels < 1) fail(HFSI_E_ARG, "amg params: bad level limits");
-  if (p->smoother < 0 || p->smoother > 1 || p->nu_pre < 0 || p->nu_post < 0 || p->nu_pre + p->nu_post < 1)
-    fail(HFSI_E_ARG, "amg params: bad smoother");
+  if (p->smoother < 0 || p->smoother > 1 || p->nu_pre < 0 || p->nu_post < 0 || p->nu_post_coarse < 0 ||
+      p->nu_pre + p->nu_post < 1 || p->nu_pre + p->nu_post_coarse < 1)
+    fail(HFSI_E_ARG, "amg params: bad smoother or sweep counts");
   if (p->precision < 0 || p->precision > 1) fail(HFSI_E_ARG, "amg params: bad precision");
-  if (p->cheb_degree < 1 || p->cheb_degree > 8 || !(p->cheb_ratio > 1.0))
-    fail(HFSI_E_ARG, "amg params: Chebyshev degree in 1..8 and ratio > 1");
+  for (int d : {p->cheb_degree, p->cheb_degree_pre, p->cheb_degree_coarse})
+    if (d < 1 || d > 8) fail(HFSI_E_ARG, "amg params: Chebyshev degrees in 1..8");
+  if (!(p->cheb_ratio > 1.0)) fail(HFSI_E_ARG, "amg params: Chebyshev ratio > 1");
   if (p->interp_kind < 0 || p->interp_kind > 1 || p->p_max < 0)
     fail(HFSI_E_ARG, "amg params: interp_kind 0 or 1, p_max >= 0");
   if (p->interp < 0 || p->interp > 1) fail(HFSI_E_ARG, "amg params: interp must be 0 (classical) or 1 (learned)");

@@ -740,8 +740,8 @@ void restrict_first_launch(int G, int n, const int* ptr, const int* col, const T
 // step from a zero guess (x = cf D^-1 b, and d = x for Chebyshev) was already
 // written by the kernel that produced b.
 template <class T>
-T* smooth(hfsi_ctx* c, Level& L, const LevelView<T>& v, const T* b, T* xa, T* xb, int nu, bool zero_start,
-          bool first_done = false) {
+T* smooth(hfsi_ctx* c, Level& L, const LevelView<T>& v, const T* b, T* xa, T* xb, int nu, int degree,
+          bool zero_start, bool first_done = false) {
   hipStream_t s = c->stream;
   const int n = L.n;
   const Hierarchy& H = c->H;
@@ -759,7 +759,7 @@ T* smooth(hfsi_ctx* c, Level& L, const LevelView<T>& v, const T* b, T* xa, T* xb
     }
     return xa;
   }
-  // Chebyshev of degree H.cheb_degree on D^{-1} A over [lmax/ratio, 1.1 lmax],
+  // Chebyshev of the given degree on D^{-1} A over [lmax/ratio, 1.1 lmax],
   // nu times: d_0 = D^{-1} r / theta, then
   // d_q = rho_q rho_{q-1} d_{q-1} + (2 rho_q / delta) D^{-1} r with
   // rho_0 = 1/sigma, rho_q = 1 / (2 sigma - rho_{q-1}); x += d_q each step
@@ -778,7 +778,7 @@ T* smooth(hfsi_ctx* c, Level& L, const LevelView<T>& v, const T* b, T* xa, T* xb
       std::swap(xa, xb);
     }
     double rho = rho0;
-    for (int q = 1; q < H.cheb_degree; ++q) {
+    for (int q = 1; q < degree; ++q) {
       const double rn = 1.0 / (2.0 * sigma - rho);
       level_op<T, OP_CHEB>(L, v, xa, b, xb, d, (T)(rn * rho), (T)(2.0 * rn / delta), s);
       std::swap(xa, xb);
@@ -805,7 +805,7 @@ T* vcycle_rec(hfsi_ctx* c, int l, bool first_done) {
   }
   T* x = v.x;
   if (H.nu_pre > 0) {
-    x = smooth<T>(c, L, v, v.b, v.x, v.t, H.nu_pre, true, first_done);
+    x = smooth<T>(c, L, v, v.b, v.x, v.t, H.nu_pre, H.cheb_degree_pre, true, first_done);
   } else {
     HIP_CHECK(hipMemsetAsync(v.x, 0, sizeof(T) * n, s));
   }
@@ -824,7 +824,8 @@ T* vcycle_rec(hfsi_ctx* c, int l, bool first_done) {
   T* xc = vcycle_rec<T>(c, l + 1, fuse);
   csr_launch<T, OP_ADD>(lanes_for(L.P.nnz, n), n, L.P.ptr.p, L.P.col.p, v.P, xc, nullptr, nullptr, x, nullptr, 0, 0,
                         s);
-  if (H.nu_post > 0) x = smooth<T>(c, L, v, v.b, x, other, H.nu_post, false);
+  const int nu_post = l == 0 ? H.nu_post : H.nu_post_coarse;
+  if (nu_post > 0) x = smooth<T>(c, L, v, v.b, x, other, nu_post, l == 0 ? H.cheb_degree : H.cheb_degree_coarse, false);
   return x;
 }
 

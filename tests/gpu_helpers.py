@@ -47,14 +47,23 @@ def gpu_hierarchy_to_oracle(ctx, info, prm: amg.AmgParams):
 
 
 def amg_prm_pair(lib, smoother=0, precision=0, max_coarse=500, theta=0.15, seed=12345, nu=2, nu_post=None,
-                 cheb=(2, 30.0), kind="classical", p_max=4):
-    nu_pre, nu_post = nu, nu if nu_post is None else nu_post
-    g = lib.amg_params(theta=theta, max_coarse=max_coarse, seed=seed, smoother=smoother, nu_pre=nu_pre, nu_post=nu_post,
-                       cheb_degree=cheb[0], cheb_ratio=cheb[1], interp_kind=1 if kind == "ext+i" else 0, p_max=p_max,
-                       precision=precision)
+                 cheb=(2, 30.0), kind="classical", p_max=4, schedule=None):
+    """GPU and oracle AMG parameters with the same settings.  schedule=None:
+    the same sweeps (nu, nu_post) and Chebyshev degree cheb[0] on every level;
+    schedule="default": the library's default smoothing schedule."""
+    if schedule == "default":
+        d = lib.amg_params()
+        sm = dict(nu_pre=d.nu_pre, nu_post=d.nu_post, cheb_degree=d.cheb_degree, cheb_ratio=d.cheb_ratio,
+                  cheb_degree_pre=d.cheb_degree_pre, nu_post_coarse=d.nu_post_coarse,
+                  cheb_degree_coarse=d.cheb_degree_coarse)
+    else:
+        nu_post = nu if nu_post is None else nu_post
+        sm = dict(nu_pre=nu, nu_post=nu_post, cheb_degree=cheb[0], cheb_ratio=cheb[1], cheb_degree_pre=cheb[0],
+                  nu_post_coarse=nu_post, cheb_degree_coarse=cheb[0])
+    g = lib.amg_params(theta=theta, max_coarse=max_coarse, seed=seed, smoother=smoother,
+                       interp_kind=1 if kind == "ext+i" else 0, p_max=p_max, precision=precision, **sm)
     o = amg.AmgParams(theta=theta, max_coarse=max_coarse, seed=seed,
-                      smoother="l1jacobi" if smoother == 0 else "chebyshev", nu_pre=nu_pre, nu_post=nu_post,
-                      cheb_degree=cheb[0], cheb_ratio=cheb[1], interp=kind, p_max=p_max)
+                      smoother="l1jacobi" if smoother == 0 else "chebyshev", interp=kind, p_max=p_max, **sm)
     return g, o
 
 

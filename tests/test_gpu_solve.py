@@ -20,14 +20,14 @@ from oracle import amg, krylov, newton
 pytestmark = pytest.mark.gpu
 
 
-def _setup(lib, prob, v, load, smoother=0, precision=0, max_coarse=500, nu=(2, 2), cheb=(2, 30.0)):
+def _setup(lib, prob, v, load, smoother=0, precision=0, max_coarse=500, nu=(2, 2), cheb=(2, 30.0), schedule=None):
     import torch
     ctx = context_for(lib, prob)
     vt = torch_dev(v)
     R = torch.zeros_like(vt)
     ctx.assemble_residual_tangent(vt, load, R)
     gprm, oprm = amg_prm_pair(lib, smoother=smoother, precision=precision, max_coarse=max_coarse, nu=nu[0],
-                              nu_post=nu[1], cheb=cheb)
+                              nu_post=nu[1], cheb=cheb, schedule=schedule)
     info = ctx.amg_setup(gprm)
     return ctx, R, info, oprm
 
@@ -36,13 +36,20 @@ def _setup(lib, prob, v, load, smoother=0, precision=0, max_coarse=500, nu=(2, 2
                                                         (0, 1, (2, 2), (2, 30.0)), (1, 1, (2, 2), (2, 30.0)),
                                                         (1, 0, (1, 2), (2, 30.0)), (1, 1, (1, 2), (2, 30.0)),
                                                         (0, 0, (1, 2), (2, 30.0)), (1, 0, (1, 1), (3, 10.0)),
-                                                        (1, 1, (1, 2), (4, 20.0))])
+                                                        (1, 1, (1, 2), (4, 20.0)),
+                                                        (1, 0, None, None), (1, 1, None, None)])
 def test_vcycle_and_preconditioner_match_oracle(lib, smoother, precision, nu, cheb):
+    """nu = cheb = None: the default schedule (degree-1 pre-smoothing, two
+    degree-2 sweeps after the correction on level 0, one degree-3 sweep on
+    the coarser levels)."""
     import torch
     prob = synth.cube_problem(6, jitter=0.1, seed=2)
     v = synth.random_state(prob, 3, u_scale=0.03, p_scale=0.05).ravel()
     print(f"[vcycle parity] smoother={smoother} precision={precision} nu={nu} cheb={cheb}", flush=True)
-    ctx, R, info, oprm = _setup(lib, prob, v, 0.4, smoother, precision, max_coarse=60, nu=nu, cheb=cheb)
+    if nu is None:
+        ctx, R, info, oprm = _setup(lib, prob, v, 0.4, smoother, precision, max_coarse=60, schedule="default")
+    else:
+        ctx, R, info, oprm = _setup(lib, prob, v, 0.4, smoother, precision, max_coarse=60, nu=nu, cheb=cheb)
     H = gpu_hierarchy_to_oracle(ctx, info, oprm)
     rng = np.random.default_rng(1)
     n3 = H.levels[0].A.shape[0]

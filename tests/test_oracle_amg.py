@@ -199,7 +199,7 @@ def test_l1_jacobi_is_monotone_in_energy_norm():
     e_prev = np.inf
     prm = amg.AmgParams(smoother="l1jacobi")
     for _ in range(10):
-        x = amg.smooth(L, b, x, 1, prm)
+        x = amg.smooth(L, b, x, 1, prm, 1)
         e = x - x_true
         en = e @ (A @ e)
         assert en <= e_prev * (1 + 1e-14)
