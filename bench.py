@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--interp", choices=("learned", "classical"), default=None,
                     help="level-0 interpolation of the headline path (cube: learned, tube: classical)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1312_5561_amd", "weights", "mlp_cube.npz"))
-    ap.add_argument("--fallback-rho", type=float, default=0.5)
+    ap.add_argument("--fallback-rho", type=float, default=0.6)
     args = ap.parse_args()
     if args.kappa is None:
         args.kappa = 1e4 if args.workload == "cube" else 1e5

@@ -95,10 +95,12 @@ typedef struct {
 
 /* AMG parameters.  smoother: 0 = l1-Jacobi, 1 = Chebyshev (polynomial in
  * D^{-1}A over [lmax/cheb_ratio, 1.1 lmax], lmax from 10 Lanczos steps).
- * Smoothing schedule of the V-cycle: nu_pre sweeps of degree cheb_degree_pre
- * before the coarse correction on every level; after it nu_post sweeps of
- * degree cheb_degree on level 0 and nu_post_coarse sweeps of degree
- * cheb_degree_coarse on the coarser levels (degrees apply to Chebyshev only).
+ * Smoothing schedule of the V-cycle: on level 0, nu_pre sweeps of degree
+ * cheb_degree_pre before the coarse correction and nu_post sweeps of degree
+ * cheb_degree after it; on the coarser levels nu_pre_coarse sweeps of degree
+ * cheb_degree_pre before and nu_post_coarse sweeps of degree
+ * cheb_degree_coarse after (degrees apply to Chebyshev only; a level without
+ * pre-smoothing restricts its right-hand side directly).
  * precision: 0 = fp64 V-cycle, 1 = fp32 V-cycle (coarsest solve stays fp64).
  * interp: 0 = classical, 1 = learned correction on level 0 (needs MLP
  * weights and lattice coordinates), with classical fallback when the
@@ -110,11 +112,11 @@ typedef struct {
   int32_t max_levels;    /* default 25                                     */
   uint64_t seed;         /* PMIS weight seed, default 12345                */
   int32_t smoother;
-  int32_t nu_pre, nu_post;  /* sweeps before the coarse correction (every
-                               level) / after it (level 0), default 1 / 2 */
+  int32_t nu_pre, nu_post;  /* level 0: sweeps before / after the coarse
+                               correction, default 1 / 2                   */
   int32_t precision;
   int32_t interp;
-  double fallback_rho;   /* default 0.5                                    */
+  double fallback_rho;   /* default 0.6                                    */
   int32_t cheb_degree;   /* level-0 post-smoothing degree, 1..8, default 2 */
   double cheb_ratio;     /* lmax / lower bound of the interval, > 1, default 30 */
   int32_t interp_kind;   /* 0 = modified classical (distance one), 1 = extended+i
@@ -126,6 +128,7 @@ typedef struct {
   int32_t cheb_degree_pre;    /* pre-smoothing degree, 1..8, default 1     */
   int32_t nu_post_coarse;     /* post-smoothing sweeps on levels >= 1, default 1 */
   int32_t cheb_degree_coarse; /* their degree, 1..8, default 3             */
+  int32_t nu_pre_coarse;      /* pre-smoothing sweeps on levels >= 1, default 0 */
 } hfsi_amg_params;
 
 typedef struct {

@@ -311,13 +311,14 @@ class AmgParams:
     max_levels: int = 25
     seed: int = 12345
     smoother: str = "chebyshev"   # or "l1jacobi"
-    nu_pre: int = 1                # sweeps before the coarse correction, every level
-    nu_post: int = 2               # sweeps after it on level 0
+    nu_pre: int = 1                # level 0: sweeps before the coarse correction
+    nu_post: int = 2               # and after it
     cheb_degree: int = 2           # their Chebyshev degree
     cheb_ratio: float = 30.0
     cheb_degree_pre: int = 1       # pre-smoothing degree
     nu_post_coarse: int = 1        # post-smoothing sweeps on levels >= 1
     cheb_degree_coarse: int = 3    # their degree
+    nu_pre_coarse: int = 0         # pre-smoothing sweeps on levels >= 1 (degree cheb_degree_pre)
     interp: str = "ext+i"          # or "classical"
     p_max: int = 4                 # ext+i truncation (0: none)
     lanczos_steps: int = 10
@@ -395,14 +396,15 @@ def chebyshev(A, dinv, lam, b, x, degree=2, ratio=30.0):
 
 
 def vcycle(H: Hierarchy, b, prm: AmgParams = AmgParams(), lev=0):
-    """One V-cycle with zero initial guess on every level: nu_pre sweeps of
-    degree cheb_degree_pre, the coarse correction, then nu_post sweeps of
-    degree cheb_degree on level 0 (nu_post_coarse of cheb_degree_coarse on
-    the coarser levels)."""
+    """One V-cycle with zero initial guess on every level: pre-smoothing of
+    degree cheb_degree_pre (nu_pre sweeps on level 0, nu_pre_coarse on the
+    coarser levels), the coarse correction, then nu_post sweeps of degree
+    cheb_degree on level 0 (nu_post_coarse of cheb_degree_coarse on the
+    coarser levels)."""
     L = H.levels[lev]
     if lev == len(H.levels) - 1:
         return scipy.linalg.lu_solve(H.lu, b)
-    x = smooth(L, b, np.zeros_like(b), prm.nu_pre, prm, prm.cheb_degree_pre)
+    x = smooth(L, b, np.zeros_like(b), prm.nu_pre if lev == 0 else prm.nu_pre_coarse, prm, prm.cheb_degree_pre)
     r = b - L.A @ x
     xc = vcycle(H, L.R @ r, prm, lev + 1)
     x = x + L.P @ xc

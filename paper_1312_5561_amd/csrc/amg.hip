@@ -1526,6 +1526,7 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
   H.smoother = prm.smoother;
   H.nu_pre = prm.nu_pre;
   H.nu_post = prm.nu_post;
+  H.nu_pre_coarse = prm.nu_pre_coarse;
   H.nu_post_coarse = prm.nu_post_coarse;
   H.cheb_degree = prm.cheb_degree;
   H.cheb_degree_pre = prm.cheb_degree_pre;
@@ -1773,8 +1774,8 @@ void check_amg_params(const hfsi_amg_params* p) {
   if (!p || p->struct_size != sizeof(hfsi_amg_params)) fail(HFSI_E_ARG, "amg params: struct_size mismatch");
   if (!(p->strength_theta > 0.0 && p->strength_theta <= 1.0)) fail(HFSI_E_ARG, "amg params: theta in (0,1]");
   if (p->max_coarse < 1 || p->max_levels < 1) fail(HFSI_E_ARG, "amg params: bad level limits");
-  if (p->smoother < 0 || p->smoother > 1 || p->nu_pre < 0 || p->nu_post < 0 || p->nu_post_coarse < 0 ||
-      p->nu_pre + p->nu_post < 1 || p->nu_pre + p->nu_post_coarse < 1)
+  if (p->smoother < 0 || p->smoother > 1 || p->nu_pre < 0 || p->nu_post < 0 || p->nu_pre_coarse < 0 ||
+      p->nu_post_coarse < 0 || p->nu_pre + p->nu_post < 1 || p->nu_pre_coarse + p->nu_post_coarse < 1)
     fail(HFSI_E_ARG, "amg params: bad smoother or sweep counts");
   if (p->precision < 0 || p->precision > 1) fail(HFSI_E_ARG, "amg params: bad precision");
   for (int d : {p->cheb_degree, p->cheb_degree_pre, p->cheb_degree_coarse})

@@ -44,7 +44,7 @@ k_csr(int n, const int* __restrict__ ptr, const int* __restrict__ col, const T* 
   else if (OP == OP_JACOBI) y[gid] = x[gid] + dinv[gid] * (b[gid] - s);
   else if (OP == OP_ADD) y[gid] += s;
   else {  // Chebyshev step: d = c1 d + c2 D^{-1}(b - A x), y = x + d
-    const T dn = c1 * d[gid] + c2 * dinv[gid] * (b[gid] - s);
+    const T dn = (c1 != (T)0 ? c1 * d[gid] : (T)0) + c2 * dinv[gid] * (b[gid] - s);  // c1 = 0: d unread
     d[gid] = dn;
     y[gid] = x[gid] + dn;
   }
@@ -115,7 +115,7 @@ k_csr4(int n, const int* __restrict__ p4, const int* __restrict__ base, const vo
   else if (OP == OP_JACOBI) y[gid] = x[gid] + dinv[gid] * (b[gid] - s);
   else if (OP == OP_ADD) y[gid] += s;
   else {
-    const T dn = c1 * d[gid] + c2 * dinv[gid] * (b[gid] - s);
+    const T dn = (c1 != (T)0 ? c1 * d[gid] : (T)0) + c2 * dinv[gid] * (b[gid] - s);  // c1 = 0: d unread
     d[gid] = dn;
     y[gid] = x[gid] + dn;
   }
@@ -180,7 +180,7 @@ k_b3(int nn, const int* __restrict__ bptr, const int* __restrict__ bcol, const T
   else if (OP == OP_JACOBI) y[row] = x[row] + dinv[row] * (b[row] - s);
   else if (OP == OP_ADD) y[row] += s;
   else {
-    const T dn = c1 * d[row] + c2 * dinv[row] * (b[row] - s);
+    const T dn = (c1 != (T)0 ? c1 * d[row] : (T)0) + c2 * dinv[row] * (b[row] - s);  // c1 = 0: d unread
     d[row] = dn;
     y[row] = x[row] + dn;
   }
@@ -803,27 +803,33 @@ T* vcycle_rec(hfsi_ctx* c, int l, bool first_done) {
     HIP_LAUNCH_CHECK();
     return v.x;
   }
+  // pre-smoothing and its residual; without it x = 0 and the residual is b
+  const int nu_pre = l == 0 ? H.nu_pre : H.nu_pre_coarse;
   T* x = v.x;
-  if (H.nu_pre > 0) {
-    x = smooth<T>(c, L, v, v.b, v.x, v.t, H.nu_pre, H.cheb_degree_pre, true, first_done);
-  } else {
-    HIP_CHECK(hipMemsetAsync(v.x, 0, sizeof(T) * n, s));
+  const T* res = v.b;
+  if (nu_pre > 0) {
+    x = smooth<T>(c, L, v, v.b, v.x, v.t, nu_pre, H.cheb_degree_pre, true, first_done);
+    level_op<T, OP_RESID>(L, v, x, v.b, v.r, nullptr, 0, 0, s);
+    res = v.r;
   }
   T* other = x == v.x ? v.t : v.x;
-  level_op<T, OP_RESID>(L, v, x, v.b, v.r, nullptr, 0, 0, s);
   Level& Lc = H.L[l + 1];
   const bool coarsest = l + 1 == (int)H.L.size() - 1;
   LevelView<T> vc = view<T>(Lc, coarsest);
-  const bool fuse = !coarsest && H.nu_pre > 0;
+  const bool fuse = !coarsest && H.nu_pre_coarse > 0;
   if (fuse)
-    restrict_first_launch<T>(lanes_for(L.R.nnz, L.R.rows), L.R.rows, L.R.ptr.p, L.R.col.p, v.R, v.r, vc.dinv, vc.b,
+    restrict_first_launch<T>(lanes_for(L.R.nnz, L.R.rows), L.R.rows, L.R.ptr.p, L.R.col.p, v.R, res, vc.dinv, vc.b,
                              vc.x, H.smoother == 1 ? vc.r : nullptr, (T)first_step_coef(H, Lc), s);
   else
-    csr_launch<T, OP_SPMV>(lanes_for(L.R.nnz, L.R.rows), L.R.rows, L.R.ptr.p, L.R.col.p, v.R, v.r, nullptr, nullptr,
+    csr_launch<T, OP_SPMV>(lanes_for(L.R.nnz, L.R.rows), L.R.rows, L.R.ptr.p, L.R.col.p, v.R, res, nullptr, nullptr,
                            vc.b, nullptr, 0, 0, s);
   T* xc = vcycle_rec<T>(c, l + 1, fuse);
-  csr_launch<T, OP_ADD>(lanes_for(L.P.nnz, n), n, L.P.ptr.p, L.P.col.p, v.P, xc, nullptr, nullptr, x, nullptr, 0, 0,
-                        s);
+  if (nu_pre > 0)
+    csr_launch<T, OP_ADD>(lanes_for(L.P.nnz, n), n, L.P.ptr.p, L.P.col.p, v.P, xc, nullptr, nullptr, x, nullptr, 0, 0,
+                          s);
+  else
+    csr_launch<T, OP_SPMV>(lanes_for(L.P.nnz, n), n, L.P.ptr.p, L.P.col.p, v.P, xc, nullptr, nullptr, x, nullptr, 0, 0,
+                           s);
   const int nu_post = l == 0 ? H.nu_post : H.nu_post_coarse;
   if (nu_post > 0) x = smooth<T>(c, L, v, v.b, x, other, nu_post, l == 0 ? H.cheb_degree : H.cheb_degree_coarse, false);
   return x;

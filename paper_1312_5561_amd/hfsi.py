@@ -48,7 +48,7 @@ class AmgParams(C.Structure):
                 ("nu_post", C.c_int32), ("precision", C.c_int32), ("interp", C.c_int32),
                 ("fallback_rho", C.c_double), ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
                 ("interp_kind", C.c_int32), ("p_max", C.c_int32), ("cheb_degree_pre", C.c_int32),
-                ("nu_post_coarse", C.c_int32), ("cheb_degree_coarse", C.c_int32)]
+                ("nu_post_coarse", C.c_int32), ("cheb_degree_coarse", C.c_int32), ("nu_pre_coarse", C.c_int32)]
 
 
 class AmgInfo(C.Structure):
@@ -98,11 +98,11 @@ def train_params(batch=1024, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
 
 
 def amg_params(theta=0.15, max_coarse=500, max_levels=25, seed=12345, smoother=1, nu_pre=1, nu_post=2,
-               precision=0, interp=0, fallback_rho=0.5, cheb_degree=2, cheb_ratio=30.0, interp_kind=1, p_max=4,
-               cheb_degree_pre=1, nu_post_coarse=1, cheb_degree_coarse=3):
+               precision=0, interp=0, fallback_rho=0.6, cheb_degree=2, cheb_ratio=30.0, interp_kind=1, p_max=4,
+               cheb_degree_pre=1, nu_post_coarse=1, cheb_degree_coarse=3, nu_pre_coarse=0):
     return AmgParams(C.sizeof(AmgParams), theta, max_coarse, max_levels, seed, smoother, nu_pre, nu_post,
                      precision, interp, fallback_rho, cheb_degree, cheb_ratio, interp_kind, p_max, cheb_degree_pre,
-                     nu_post_coarse, cheb_degree_coarse)
+                     nu_post_coarse, cheb_degree_coarse, nu_pre_coarse)
 
 
 def solve_params(tol=1e-8, restart=50, max_iter=500):

@@ -55,11 +55,11 @@ def amg_prm_pair(lib, smoother=0, precision=0, max_coarse=500, theta=0.15, seed=
         d = lib.amg_params()
         sm = dict(nu_pre=d.nu_pre, nu_post=d.nu_post, cheb_degree=d.cheb_degree, cheb_ratio=d.cheb_ratio,
                   cheb_degree_pre=d.cheb_degree_pre, nu_post_coarse=d.nu_post_coarse,
-                  cheb_degree_coarse=d.cheb_degree_coarse)
+                  cheb_degree_coarse=d.cheb_degree_coarse, nu_pre_coarse=d.nu_pre_coarse)
     else:
         nu_post = nu if nu_post is None else nu_post
         sm = dict(nu_pre=nu, nu_post=nu_post, cheb_degree=cheb[0], cheb_ratio=cheb[1], cheb_degree_pre=cheb[0],
-                  nu_post_coarse=nu_post, cheb_degree_coarse=cheb[0])
+                  nu_post_coarse=nu_post, cheb_degree_coarse=cheb[0], nu_pre_coarse=nu)
     g = lib.amg_params(theta=theta, max_coarse=max_coarse, seed=seed, smoother=smoother,
                        interp_kind=1 if kind == "ext+i" else 0, p_max=p_max, precision=precision, **sm)
     o = amg.AmgParams(theta=theta, max_coarse=max_coarse, seed=seed,

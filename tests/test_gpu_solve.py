@@ -39,9 +39,9 @@ def _setup(lib, prob, v, load, smoother=0, precision=0, max_coarse=500, nu=(2, 2
                                                         (1, 1, (1, 2), (4, 20.0)),
                                                         (1, 0, None, None), (1, 1, None, None)])
 def test_vcycle_and_preconditioner_match_oracle(lib, smoother, precision, nu, cheb):
-    """nu = cheb = None: the default schedule (degree-1 pre-smoothing, two
-    degree-2 sweeps after the correction on level 0, one degree-3 sweep on
-    the coarser levels)."""
+    """nu = cheb = None: the default schedule (on level 0 one degree-1 sweep
+    before the correction and two degree-2 sweeps after it; on the coarser
+    levels no pre-smoothing and one degree-3 sweep after)."""
     import torch
     prob = synth.cube_problem(6, jitter=0.1, seed=2)
     v = synth.random_state(prob, 3, u_scale=0.03, p_scale=0.05).ravel()
@@ -102,6 +102,30 @@ def test_fgmres_solution(lib, precision):
     _, oinfo = krylov.fgmres(K, M, b, tol=1e-8)
     print(f"[fgmres] gpu its={sinfo.iterations} oracle its={oinfo.iterations} err={err:.2e}", flush=True)
     assert abs(sinfo.iterations - oinfo.iterations) <= (1 if precision == 0 else 3)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_vcycle_after_nonfinite_cycle(lib, precision):
+    """A cycle run after one on a non-finite vector equals the cycle before
+    it: no step reads a work vector it has not written in the same cycle
+    (levels without pre-smoothing start their post-smoothing with no
+    previous Chebyshev direction)."""
+    import torch
+    prob = synth.cube_problem(6, jitter=0.1, seed=2)
+    v = synth.random_state(prob, 3, u_scale=0.03, p_scale=0.05).ravel()
+    ctx, R, info, oprm = _setup(lib, prob, v, 0.4, 1, precision, max_coarse=60, schedule="default")
+    assert info.levels >= 3
+    n3 = 3 * prob.n_nodes
+    r = torch_dev(np.random.default_rng(4).normal(size=n3))
+    z1 = torch.zeros(n3, dtype=torch.float64, device="cuda")
+    ctx.vcycle(r, z1)
+    bad = torch.full_like(r, float("nan"))
+    zb = torch.zeros_like(z1)
+    ctx.vcycle(bad, zb)
+    assert not bool(torch.isfinite(zb).any())
+    z2 = torch.zeros_like(z1)
+    ctx.vcycle(r, z2)
+    assert torch.equal(z1, z2)
 
 
 def test_zero_rhs_and_not_converged(lib):
