@@ -1665,6 +1665,36 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
       HIP_LAUNCH_CHECK();
     }
   }
+  // coarsest level: explicit inverse, on the aux stream while this stream
+  // makes the operator copies of the cycle
+  Level& Lc = H.L.back();
+  const int nc = Lc.n;
+  if (nc > 4096) fail(HFSI_E_CAPACITY, "coarsest level larger than 4096 rows (coarsening stalled)");
+  H.nc = nc;
+  H.coarse_inv.ensure((size_t)nc * nc);
+  DevBuf<int> sing;
+  sing.zero(1, s);
+  HIP_CHECK(hipEventRecord(c->aev[0], s));
+  HIP_CHECK(hipStreamWaitEvent(c->aux, c->aev[0], 0));
+  {
+    hipStream_t a = c->aux;
+    StreamTag tag(a);
+    DevBuf<double> M, M2;
+    M.ensure(2 * (size_t)nc * nc);
+    M2.ensure(2 * (size_t)nc * nc);
+    k_dense_from_csr<<<div_up(nc, 256), 256, 0, a>>>(nc, Lc.A.ptr.p, Lc.A.col.p, Lc.A.val.p, M.p);
+    HIP_LAUNCH_CHECK();
+    // Gauss-Jordan on [A | I]: one launch per pivot, alternating buffers
+    double* gin = M.p;
+    double* gout = M2.p;
+    for (int k = 0; k < nc; ++k) {
+      const long work = (long)nc * (2L * nc - k - 1);
+      k_gj_step<<<div_up(work, 256), 256, 0, a>>>(nc, k, gin, gout, sing.p);
+      std::swap(gin, gout);
+    }
+    k_gj_extract<<<div_up((long)nc * nc, 256), 256, 0, a>>>(nc, gin, H.coarse_inv.p);
+    HIP_LAUNCH_CHECK();
+  }
   // fp32 operator copies
   if (prm.precision == 1)
     for (auto& L : H.L) {
@@ -1677,29 +1707,6 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
     L.packed = false;
     if (!L.bptr) pack_level(c, L, prm.precision);
   }
-  // coarsest level: explicit inverse
-  Level& Lc = H.L.back();
-  const int nc = Lc.n;
-  if (nc > 4096) fail(HFSI_E_CAPACITY, "coarsest level larger than 4096 rows (coarsening stalled)");
-  H.nc = nc;
-  DevBuf<double> M, M2;
-  DevBuf<int> sing;
-  M.ensure(2 * (size_t)nc * nc);
-  M2.ensure(2 * (size_t)nc * nc);
-  sing.zero(1, s);
-  H.coarse_inv.ensure((size_t)nc * nc);
-  k_dense_from_csr<<<div_up(nc, 256), 256, 0, s>>>(nc, Lc.A.ptr.p, Lc.A.col.p, Lc.A.val.p, M.p);
-  HIP_LAUNCH_CHECK();
-  // Gauss-Jordan on [A | I]: one launch per pivot, alternating buffers
-  double* gin = M.p;
-  double* gout = M2.p;
-  for (int k = 0; k < nc; ++k) {
-    const long work = (long)nc * (2L * nc - k - 1);
-    k_gj_step<<<div_up(work, 256), 256, 0, s>>>(nc, k, gin, gout, sing.p);
-    std::swap(gin, gout);
-  }
-  k_gj_extract<<<div_up((long)nc * nc, 256), 256, 0, s>>>(nc, gin, H.coarse_inv.p);
-  HIP_LAUNCH_CHECK();
   // join the aux stream, then read the singularity flag and the estimates
   HIP_CHECK(hipEventRecord(c->aev[1], c->aux));
   HIP_CHECK(hipStreamWaitEvent(s, c->aev[1], 0));

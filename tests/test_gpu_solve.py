@@ -104,6 +104,27 @@ def test_fgmres_solution(lib, precision):
     assert abs(sinfo.iterations - oinfo.iterations) <= (1 if precision == 0 else 3)
 
 
+def test_tangent_product_any_alignment(lib):
+    """K x with x 32-byte aligned (wide loads) and with x at an 8-byte offset
+    (the per-entry kernel) both equal the oracle tangent times x."""
+    import torch
+    prob = synth.cube_problem(5, jitter=0.1, seed=3)
+    v = synth.random_state(prob, 5, u_scale=0.03, p_scale=0.05).ravel()
+    ctx, R, info, oprm = _setup(lib, prob, v, 0.4, 1, 0, max_coarse=60)
+    d, K, b, A, B2, s = oracle_system(prob, v, 0.4)
+    n4 = 4 * prob.n_nodes
+    xr = np.random.default_rng(6).normal(size=n4)
+    ref = K @ xr
+    buf = torch.zeros(n4 + 1, dtype=torch.float64, device="cuda")
+    for off in (0, 1):
+        x = buf[off:off + n4]
+        x.copy_(torch_dev(xr))
+        assert (x.data_ptr() % 32 == 0) == (off == 0)
+        y = torch.zeros(n4, dtype=torch.float64, device="cuda")
+        ctx.apply_tangent(x, y)
+        assert np.linalg.norm(y.cpu().numpy() - ref) <= 1e-13 * np.linalg.norm(ref), off
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_vcycle_after_nonfinite_cycle(lib, precision):
     """A cycle run after one on a non-finite vector equals the cycle before
