@@ -111,18 +111,23 @@ k_pmis_mark_f(int n, const int* __restrict__ ptr, const int* __restrict__ col, c
               int8_t* __restrict__ state, int* __restrict__ remaining) {
   const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
   const int lane = threadIdx.x & 7;
-  if (i >= n || state[i] != ST_U) return;
-  const int hi = ptr[i + 1];
-  int found = 0;
-  for (int b = ptr[i]; b < hi && !found; b += 8) {  // the 8 lanes leave together
-    const int e = b + lane;
-    found = e < hi && strong[e] && state[col[e]] == ST_C ? 1 : 0;
+  bool left = false;  // row i stays undecided (counted once per wavefront)
+  if (i < n && state[i] == ST_U) {
+    const int hi = ptr[i + 1];
+    int found = 0;
+    for (int b = ptr[i]; b < hi && !found; b += 8) {  // the 8 lanes leave together
+      const int e = b + lane;
+      found = e < hi && strong[e] && state[col[e]] == ST_C ? 1 : 0;
 #pragma unroll
-    for (int o = 4; o > 0; o >>= 1) found |= __shfl_xor(found, o, 8);
+      for (int o = 4; o > 0; o >>= 1) found |= __shfl_xor(found, o, 8);
+    }
+    if (lane == 0) {
+      if (found) state[i] = ST_F;
+      else left = true;
+    }
   }
-  if (lane != 0) return;
-  if (found) state[i] = ST_F;
-  else atomicAdd(remaining, 1);
+  const unsigned long long lm = __ballot(left);
+  if ((threadIdx.x & 63) == 0 && lm) atomicAdd(remaining, __popcll(lm));
 }
 
 __global__ void k_is_c(int n, const int8_t* __restrict__ state, int* __restrict__ flag) {

@@ -1128,16 +1128,18 @@ double convergence_factor(hfsi_ctx* c, int cycles, uint64_t seed) {
   e.ensure(n); t.ensure(n); z.ensure(n); part.ensure(256);
   k_uniform_pm1<<<div_up(n, 256), 256, 0, s>>>(n, seed, e.p);
   HIP_LAUNCH_CHECK();
-  const int G = lanes_for(L.A.nnz, n);
+  // A e in fp64 (the 3x3 node blocks of level 0 when present)
+  const LevelView<double> v = view<double>(L, H.L.size() == 1);
+  auto apply_a = [&]() { level_op<double, OP_SPMV>(L, v, e.p, nullptr, t.p, nullptr, 0.0, 0.0, s); };
   auto anorm2 = [&]() {
-    csr_launch<double, OP_SPMV>(G, n, L.A.ptr.p, L.A.col.p, L.A.val.p, e.p, nullptr, nullptr, t.p, nullptr, 0, 0, s);
+    apply_a();
     k_dot_part<<<256, 256, 0, s>>>(n, e.p, t.p, part.p);
     HIP_LAUNCH_CHECK();
     return device_sum(c, part.p, 256);
   };
   const double n0 = anorm2();
   for (int k = 0; k < cycles; ++k) {
-    csr_launch<double, OP_SPMV>(G, n, L.A.ptr.p, L.A.col.p, L.A.val.p, e.p, nullptr, nullptr, t.p, nullptr, 0, 0, s);
+    apply_a();
     vcycle_apply(c, t.p, z.p);
     k_axpy<<<div_up(n, 256), 256, 0, s>>>(n, -1.0, z.p, e.p);
     HIP_LAUNCH_CHECK();
