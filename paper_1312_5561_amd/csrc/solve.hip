@@ -473,10 +473,6 @@ __global__ void k_kinit(double* __restrict__ kh, int m, const double* __restrict
     kh[t] = t == st.g() ? beta[0] : 0.0;
 }
 
-// Column j of H holds h (j+1 entries) and H[j+1][j] = hnorm.  Apply the
-// previous rotations, form rotation j, update g; report |g_{j+1}|.
-// (one block of 256 threads: the column and the rotations are staged in LDS,
-// the sequential sweep over the previous rotations runs on one thread)
 
 // back substitution H y = g on the first k columns, column by column:
 // y_i = s_i / H_ii, then s_t -= H_ti y_i for t < i (parallel over t)
@@ -497,131 +493,169 @@ __global__ void __launch_bounds__(256) k_backsolve(double* __restrict__ kh, int 
   }
 }
 
-// ---- CGS2 in three passes over the basis
-// (A) partial dot products of 8 basis vectors per block (blockIdx.y picks
-// the group) with w, streamed; blocks of group 0 also accumulate w.w.
-// part[i * gridDim.x + block] (row k: w.w).
-constexpr int MDOT_G = 8;
+// ---- Arnoldi step by classical Gram-Schmidt with delayed
+// reorthogonalisation (DCGS2: Bielich, Langou, Thomas, Swirydowicz,
+// Yamazaki, Boman 2022).  Step j finds the basis as q_0..q_{j-1} (final) and
+// u = v_j, the previous new vector after one projection pass, and w = K z_j.
+// One pass over the basis gives a = Q^T u, u.u, b = Q^T w, u.w and w.w; then
+// q_j = (u - Q a) / nu with nu^2 = u.u - a.a, the previous Hessenberg
+// column takes the correction h_{:,j-1} += a h_{j,j-1}, h_{j,j-1} *= nu (and
+// its Givens rotation), column j is (b, (u.w - a.b) / nu), and a second pass
+// forms q_j and w' = w - Q b - q_j h_jj with ||w'||; u_{j+1} = w' / ||w'||.
+// Two passes over the basis per step instead of the three of CGS2, with the
+// same orthogonality in practice.
 
+// (1) partial dot products of 8 basis vectors per block (blockIdx.y picks
+// the group) with u and with w, streamed; blocks of group 0 also accumulate
+// w.w.  part[i * gridDim.x + block]: rows 0..k-1 V_i.u, k..2k-1 V_i.w, 2k w.w.
+constexpr int MDOT_G = 8;
 __global__ void __launch_bounds__(256)
-k_mdot8(long N, int k, const double* __restrict__ V, long ldv, const double* __restrict__ w,
-         double* __restrict__ part) {
-  __shared__ double sh[4][MDOT_G + 1];
+k_mdot2(long N, int k, const double* __restrict__ V, long ldv, const double* __restrict__ u,
+        const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double sh[4][2 * MDOT_G + 1];
   const int i0 = blockIdx.y * MDOT_G;
   const int kk = min(MDOT_G, k - i0);
   const bool ww = blockIdx.y == 0;
-  double acc[MDOT_G + 1];
+  double au[MDOT_G], aw[MDOT_G], a2 = 0.0;
 #pragma unroll
-  for (int t = 0; t <= MDOT_G; ++t) acc[t] = 0.0;
+  for (int t = 0; t < MDOT_G; ++t) au[t] = aw[t] = 0.0;
   for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long)gridDim.x * 256) {
-    const double we = w[e];
+    const double ue = u[e], we = w[e];
 #pragma unroll
     for (int t = 0; t < MDOT_G; ++t)
-      if (t < kk) acc[t] += V[(i0 + t) * ldv + e] * we;
-    if (ww) acc[MDOT_G] += we * we;
+      if (t < kk) {
+        const double v = V[(i0 + t) * ldv + e];
+        au[t] += v * ue;
+        aw[t] += v * we;
+      }
+    if (ww) a2 += we * we;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int t = 0; t <= MDOT_G; ++t) {
-    double a = acc[t];
+  for (int t = 0; t <= 2 * MDOT_G; ++t) {
+    double a = t < MDOT_G ? au[t] : (t < 2 * MDOT_G ? aw[t - MDOT_G] : a2);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
     if (lane == 0) sh[wv][t] = a;
   }
   __syncthreads();
   const int t = threadIdx.x;
-  if (t < kk) part[(long)(i0 + t) * gridDim.x + blockIdx.x] = sh[0][t] + sh[1][t] + sh[2][t] + sh[3][t];
-  if (ww && t == 0)
-    part[(long)k * gridDim.x + blockIdx.x] = sh[0][MDOT_G] + sh[1][MDOT_G] + sh[2][MDOT_G] + sh[3][MDOT_G];
+  const long G = gridDim.x;
+  if (t < kk) part[(long)(i0 + t) * G + blockIdx.x] = sh[0][t] + sh[1][t] + sh[2][t] + sh[3][t];
+  else if (t >= MDOT_G && t - MDOT_G < kk)
+    part[(long)(k + i0 + t - MDOT_G) * G + blockIdx.x] = sh[0][t] + sh[1][t] + sh[2][t] + sh[3][t];
+  if (ww && t == 2 * MDOT_G)
+    part[(long)(2 * k) * G + blockIdx.x] = sh[0][t] + sh[1][t] + sh[2][t] + sh[3][t];
 }
 
-// (B) w -= V h, then the partial dot products V^T w of the updated w, from
-// one read of V: tiles of ORTH_T elements of all k basis vectors are staged
-// in LDS (row stride ORTH_T + 1 against bank conflicts), the next tile is
-// loaded into registers while the current one is used.
-// part[i * gridDim.x + block].
-constexpr int ORTH_T = 16;
-constexpr int ORTH_BLOCKS = 2048;
-constexpr int ORTH_R = 256 * ORTH_T / 256;  // values per thread per tile (k <= 256)
-
-__global__ void __launch_bounds__(256)
-k_update_dot(long N, int k, const double* __restrict__ V, long ldv, const double* __restrict__ h,
-             double* __restrict__ w, double* __restrict__ part) {
-  constexpr int T = ORTH_T, LD = ORTH_T + 1;
-  extern __shared__ double sm[];
-  double* Vt = sm;                 // [k][LD]
-  double* wt = sm + (long)k * LD;  // [T]
-  double* hs = wt + T;             // [k]
-  const int tid = threadIdx.x;
-  for (int i = tid; i < k; i += 256) hs[i] = h[i];
-  const int tot = k * T;
-  const long ntiles = (N + T - 1) / T;
-  double r[ORTH_R];
-  double wr = 0.0;
-  auto fetch = [&](long tile) {
-    const long e0 = tile * T;
-    const int cnt = (int)min((long)T, N - e0);
-#pragma unroll
-    for (int u = 0; u < ORTH_R; ++u) {
-      const int q = tid + u * 256;
-      const int i = q / T, e = q % T;
-      r[u] = (q < tot && e < cnt) ? V[(long)i * ldv + e0 + e] : 0.0;
-    }
-    wr = tid < cnt ? w[e0 + tid] : 0.0;
-  };
-  double acc = 0.0;
-  long tile = blockIdx.x;
-  if (tile < ntiles) fetch(tile);
-  while (tile < ntiles) {
-    const long e0 = tile * T;
-    const int cnt = (int)min((long)T, N - e0);
-#pragma unroll
-    for (int u = 0; u < ORTH_R; ++u) {
-      const int q = tid + u * 256;
-      if (q < tot) Vt[(q / T) * LD + q % T] = r[u];
-    }
-    if (tid < T) wt[tid] = wr;
-    __syncthreads();
-    const long next = tile + gridDim.x;
-    if (next < ntiles) fetch(next);
-    // w_e -= sum_i V[i][e] h_i: 16 threads per element
-    const int e = tid >> 4, sub = tid & 15;
-    double sacc = 0.0;
-    for (int i = sub; i < k; i += 16) sacc += Vt[i * LD + e] * hs[i];
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, 16);
-    __syncthreads();
-    if (sub == 0) {
-      const double wn = wt[e] - sacc;
-      wt[e] = wn;
-      if (e < cnt) w[e0 + e] = wn;
-    }
-    __syncthreads();
-    if (tid < k) {
-      double a = 0.0;
-#pragma unroll
-      for (int j = 0; j < T; ++j) a += Vt[tid * LD + j] * wt[j];
-      acc += a;
-    }
-    __syncthreads();
-    tile = next;
+// Givens rotations of one Hessenberg column (j+2 entries in col, rotations
+// 0..j-1 applied, rotation j formed, g updated); one thread.
+__device__ void givens_column(double* col, int j, double* cs, double* sn, double* g) {
+  for (int i = 0; i < j; ++i) {
+    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+    col[i] = t;
   }
-  if (tid < k) part[(long)tid * gridDim.x + blockIdx.x] = acc;
+  const double d = hypot(col[j], col[j + 1]);
+  const double hj1 = col[j + 1];
+  cs[j] = col[j] / d;
+  sn[j] = hj1 / d;
+  col[j] = d;
+  col[j + 1] = 0.0;
+  const double gj = g[j];
+  g[j + 1] = -sn[j] * gj;
+  g[j] = cs[j] * gj;
 }
 
-// w -= V h (k vectors) and the partial w.w of the updated w per block
+// (2) step j after the reduction of (1) into hA (P = V^T u at 0..j, Q = V^T w
+// at j+1..2j+1, w.w at 2j+2).  Scalars: sc[3] = ||w'|| of step j-1 (in),
+// sc[6] = nu, sc[7] = h_jj, sc[9] = ||w_j|| (out); the report of column j-1
+// (final now) goes to sc[10] = ||w_{j-1}||, sc[12] = |g_j|, sc[13] =
+// h_{j,j-1} before its rotation.
 __global__ void __launch_bounds__(256)
-k_vupdate_norm(long N, int k, const double* __restrict__ V, long ldv, const double* __restrict__ h,
-               double* __restrict__ w, double* __restrict__ part) {
-  __shared__ double hs[256];
-  __shared__ double red[4];
-  for (int t = threadIdx.x; t < k; t += 256) hs[t] = h[t];
+k_dcgs_fix(double* __restrict__ kh, int m, int j, const double* __restrict__ hA, double* __restrict__ sc) {
+  __shared__ double col[258], red1[256], red2[256];
+  __shared__ double nu_s;
+  KState st{m};
+  const int tid = threadIdx.x;
+  const int k = j + 1;
+  const double* P = hA;
+  const double* Q = hA + k;
+  double a1 = 0.0, a2 = 0.0;
+  for (int t = tid; t < j; t += 256) {
+    a1 += P[t] * P[t];
+    a2 += P[t] * Q[t];
+  }
+  red1[tid] = a1;
+  red2[tid] = a2;
   __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) {
+      red1[tid] += red1[tid + o];
+      red2[tid] += red2[tid + o];
+    }
+    __syncthreads();
+  }
+  // the first vector r / ||r|| is kept as it is
+  if (tid == 0) nu_s = j == 0 ? 1.0 : sqrt(fmax(P[j] - red1[0], 0.0));
+  __syncthreads();
+  const double nu = nu_s;
+  if (j > 0) {
+    // column j-1: correction by the reorthogonalisation of u, then its rotation
+    double* hc = kh + (long)(j - 1) * (m + 1);
+    const double hprev = sc[3];
+    // (an exact breakdown, hprev = 0, leaves a non-finite u: no correction)
+    for (int t = tid; t < j; t += 256) col[t] = hprev == 0.0 ? hc[t] : hc[t] + P[t] * hprev;
+    __syncthreads();
+    if (tid == 0) {
+      col[j] = hprev == 0.0 ? 0.0 : hprev * nu;
+      const double hj1 = col[j];
+      givens_column(col, j - 1, kh + st.cs(), kh + st.sn(), kh + st.g());
+      sc[10] = sc[9];
+      sc[12] = fabs(kh[st.g() + j]);
+      sc[13] = hj1;
+    }
+    __syncthreads();
+    for (int t = tid; t <= j; t += 256) hc[t] = col[t];
+  }
+  // column j: projections on the final basis
+  double* hj = kh + (long)j * (m + 1);
+  for (int t = tid; t < j; t += 256) hj[t] = Q[t];
+  if (tid == 0) {
+    const double hjj = (Q[j] - red2[0]) / nu;
+    hj[j] = hjj;
+    sc[6] = nu;
+    sc[7] = hjj;
+    sc[9] = sqrt(hA[2 * k]);
+  }
+}
+
+// (3) q_j = (u - Q a) / nu written over u (basis row j), w' = w - Q b - q_j
+// h_jj, and the partial w'.w' per block
+__global__ void __launch_bounds__(256)
+k_dcgs_update(long N, int j, double* __restrict__ V, long ldv, const double* __restrict__ hA,
+              const double* __restrict__ sc, double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double as[256], bs[256];
+  __shared__ double red[4];
+  const int k = j + 1;
+  for (int t = threadIdx.x; t < j; t += 256) {
+    as[t] = hA[t];
+    bs[t] = hA[k + t];
+  }
+  __syncthreads();
+  const double nu = sc[6], hjj = sc[7];
+  double* Vj = V + (long)j * ldv;
   double nacc = 0.0;
   for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long)gridDim.x * 256) {
-    double sacc = 0.0;
-    for (int i = 0; i < k; ++i) sacc += V[i * ldv + e] * hs[i];
-    const double wn = w[e] - sacc;
+    double sa = 0.0, sb = 0.0;
+    for (int i = 0; i < j; ++i) {
+      const double v = V[i * ldv + e];
+      sa += v * as[i];
+      sb += v * bs[i];
+    }
+    const double q = (Vj[e] - sa) / nu;
+    Vj[e] = q;
+    const double wn = w[e] - sb - hjj * q;
     w[e] = wn;
     nacc += wn * wn;
   }
@@ -632,59 +666,26 @@ k_vupdate_norm(long N, int k, const double* __restrict__ V, long ldv, const doub
   if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-// End of one Arnoldi step: ||w|| from the pass-C partials, Hessenberg column
-// j = h1 + h2 (hA holds h1 and w0.w0 at index j+1), the Givens rotations of
-// the column, and the scalars the host reads: sc[2] = ||w_0||, sc[3] =
-// h_{j+1,j}, sc[4] = |g_{j+1}|, sc[5] = h_{j+1,j} before rotation.
-__global__ void __launch_bounds__(256)
-k_cgs_finish(double* __restrict__ kh, int m, int j, const double* __restrict__ hA, const double* __restrict__ hB,
-             int npart, const double* __restrict__ partC, double* __restrict__ sc_out) {
-  __shared__ double col[258], scs[257], ssn[257], red[256];
+// (4) end of a cycle without convergence: column j (the last) is taken with
+// h_{j+1,j} = ||w'|| (its reorthogonalisation would be the next step's) and
+// rotated; report as in k_dcgs_fix.
+__global__ void k_dcgs_last(double* __restrict__ kh, int m, int j, double* __restrict__ sc) {
+  __shared__ double col[258];
   KState st{m};
-  double* cs = kh + st.cs();
-  double* sn = kh + st.sn();
-  double* g = kh + st.g();
-  double* hcol = kh + (long)j * (m + 1);
-  const int tid = threadIdx.x;
-  double a = 0.0;
-  for (int t = tid; t < npart; t += 256) a += partC[t];
-  red[tid] = a;
-  for (int t = tid; t <= j; t += 256) col[t] = hA[t] + hB[t];
-  for (int t = tid; t < j; t += 256) {
-    scs[t] = cs[t];
-    ssn[t] = sn[t];
-  }
+  double* hc = kh + (long)j * (m + 1);
+  for (int t = threadIdx.x; t <= j; t += blockDim.x) col[t] = hc[t];
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (tid < o) red[tid] += red[tid + o];
-    __syncthreads();
-  }
-  if (tid == 0) {
-    const double hn = sqrt(red[0]);
-    col[j + 1] = hn;
-    for (int i = 0; i < j; ++i) {
-      const double t = scs[i] * col[i] + ssn[i] * col[i + 1];
-      col[i + 1] = -ssn[i] * col[i] + scs[i] * col[i + 1];
-      col[i] = t;
-    }
-    const double d = hypot(col[j], col[j + 1]);
+  if (threadIdx.x == 0) {
+    col[j + 1] = sc[3];
     const double hj1 = col[j + 1];
-    cs[j] = col[j] / d;
-    sn[j] = hj1 / d;
-    col[j] = d;
-    col[j + 1] = 0.0;
-    const double gj = g[j];
-    g[j + 1] = -sn[j] * gj;
-    g[j] = cs[j] * gj;
-    sc_out[2] = sqrt(hA[j + 1]);
-    sc_out[3] = hn;
-    sc_out[4] = fabs(g[j + 1]);
-    sc_out[5] = hj1;
+    givens_column(col, j, kh + st.cs(), kh + st.sn(), kh + st.g());
+    sc[10] = sc[9];
+    sc[12] = fabs(kh[st.g() + j + 1]);
+    sc[13] = hj1;
   }
   __syncthreads();
-  for (int t = tid; t <= j + 1; t += 256) hcol[t] = col[t];
+  for (int t = threadIdx.x; t <= j + 1; t += blockDim.x) hc[t] = col[t];
 }
-
 
 }  // namespace
 
@@ -974,13 +975,12 @@ void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_para
   KState st{m};
   const int gN = div_up(N, 256);
   c->kh.ensure(st.size() + 1024);
-  c->kred.ensure(2 * RED_BLOCKS + (size_t)ORTH_BLOCKS * (m + 2) + gN);
+  c->kred.ensure(2 * RED_BLOCKS + (size_t)RED_BLOCKS * (2 * m + 1) + gN);
   c->scal.ensure(16);
-  double* sc = c->scal.p;  // 0 bnorm, 1 beta, 2 w0, 3 hnorm, 4-5 report
-  double* hA = c->kh.p + st.size();  // h1 and w.w (up to 257 values)
-  double* hB = hA + 512;             // h2
-  double* partA = c->kred.p + 2 * RED_BLOCKS;                     // [(k+1) x ORTH_BLOCKS]
-  double* partC = partA + (size_t)ORTH_BLOCKS * (m + 2);          // [gN]
+  double* sc = c->scal.p;  // 0 bnorm, 1 beta, 3 ||w'||, 6-7 nu and h_jj, 9 ||w||, 10-13 report
+  double* hA = c->kh.p + st.size();  // V^T u, V^T w and w.w (up to 2m + 1 values)
+  double* partA = c->kred.p + 2 * RED_BLOCKS;                     // [(2k+1) x RED_BLOCKS]
+  double* partC = partA + (size_t)RED_BLOCKS * (2 * m + 1);       // [gN]
   HIP_CHECK(hipEventRecord(c->ev0, s));
   norm_dev(c, b, N, sc + 0);
   const double bnorm = read_scalar(c, sc + 0);
@@ -1003,12 +1003,13 @@ void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_para
       HIP_LAUNCH_CHECK();
       k_kinit<<<64, 256, 0, s>>>(c->kh.p, m, sc + 1);
       HIP_LAUNCH_CHECK();
-      // The convergence test of iteration j is read one iteration late: the
-      // host enqueues iteration j + 1 before it waits for the scalars of j,
-      // so the GPU never idles at the read-back.  When j ends the cycle, the
-      // speculative iteration j + 1 is discarded: it only wrote Hessenberg
-      // column j + 1, its rotation, g[j+1..j+2] and basis vector j + 2,
-      // none of which the solution with j + 1 columns reads.
+      // Column j of the Hessenberg matrix is final after step j + 1 (the
+      // delayed reorthogonalisation), which reports its residual estimate;
+      // the host reads that report one step later still, so the GPU never
+      // idles at the read-back.  When column c ends the cycle, steps c + 1
+      // and c + 2 have been enqueued: c + 1 finalised column c, and neither
+      // touched a Hessenberg column, rotation or g entry that the solution
+      // with c + 1 columns reads.
       int jend = 0;
       bool stop = false;
       auto evaluate = [&](int i) {
@@ -1025,34 +1026,40 @@ void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_para
           stop = true;
         }
       };
+      auto report = [&](int i) {  // column i's scalars (sc[10..13]) to the host
+        HIP_CHECK(hipMemcpyAsync(c->pinned + 4 * (i & 1), sc + 10, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipEventRecord(c->kev[i & 1], s));
+      };
+      int last = -1;
       for (int j = 0; j < m && !stop; ++j) {
         double* vj = V + (long)j * ld;
         double* zj = Z + (long)j * ld;
-        // v_j = w / h_{j,j-1} is formed by the kernel that splits it for the cycle
+        // u_j = w' / ||w'|| is formed by the kernel that splits it for the cycle
         if (j == 0) precond_apply(c, vj, zj);
         else precond_apply(c, c->kw.p, zj, sc + 3, vj);
         tangent_apply(c, zj, c->kw.p);
-        // CGS2: (A) h1 = V^T w and w.w; (B) w -= V h1, h2 = V^T w from the
-        // same staged tiles; (C) w -= V h2 and ||w||; then column j = h1 + h2
         const int k = j + 1;
-        const size_t lds = sizeof(double) * ((size_t)k * (ORTH_T + 1) + ORTH_T + 256);
-        k_mdot8<<<dim3(RED_BLOCKS, div_up(k, MDOT_G)), 256, 0, s>>>(N, k, V, ld, c->kw.p, partA);
+        k_mdot2<<<dim3(RED_BLOCKS, div_up(k, MDOT_G)), 256, 0, s>>>(N, k, V, ld, vj, c->kw.p, partA);
         HIP_LAUNCH_CHECK();
-        k_reduce_rows<<<k + 1, 256, 0, s>>>(k + 1, RED_BLOCKS, partA, hA, 0);
+        k_reduce_rows<<<2 * k + 1, 256, 0, s>>>(2 * k + 1, RED_BLOCKS, partA, hA, 0);
         HIP_LAUNCH_CHECK();
-        k_update_dot<<<ORTH_BLOCKS, 256, lds, s>>>(N, k, V, ld, hA, c->kw.p, partA);
+        k_dcgs_fix<<<1, 256, 0, s>>>(c->kh.p, m, j, hA, sc);
         HIP_LAUNCH_CHECK();
-        k_reduce_rows<<<k, 256, 0, s>>>(k, ORTH_BLOCKS, partA, hB, 0);
+        if (j > 0) report(j - 1);
+        k_dcgs_update<<<gN, 256, 0, s>>>(N, j, V, ld, hA, sc, c->kw.p, partC);
         HIP_LAUNCH_CHECK();
-        k_vupdate_norm<<<gN, 256, 0, s>>>(N, k, V, ld, hB, c->kw.p, partC);
+        k_norm_final<<<1, 256, 0, s>>>(gN, partC, sc + 3);
         HIP_LAUNCH_CHECK();
-        k_cgs_finish<<<1, 256, 0, s>>>(c->kh.p, m, j, hA, hB, gN, partC, sc);
-        HIP_LAUNCH_CHECK();
-        HIP_CHECK(hipMemcpyAsync(c->pinned + 4 * (j & 1), sc + 2, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIP_CHECK(hipEventRecord(c->kev[j & 1], s));
-        if (j > 0) evaluate(j - 1);
+        last = j;
+        if (j >= 2) evaluate(j - 2);
       }
-      if (!stop) evaluate(m - 1);
+      if (!stop && last >= 1) evaluate(last - 1);
+      if (!stop) {
+        k_dcgs_last<<<1, 256, 0, s>>>(c->kh.p, m, last, sc);
+        HIP_LAUNCH_CHECK();
+        report(last);
+        evaluate(last);
+      }
       k_backsolve<<<1, 256, 0, s>>>(c->kh.p, m, jend);
       HIP_LAUNCH_CHECK();
       k_vupdate<<<gN, 256, 0, s>>>(N, jend, Z, ld, c->kh.p + st.y(), 1.0, x);
