@@ -625,13 +625,18 @@ __global__ void k_sort_rows(int n, const int* __restrict__ ptr, const int* __res
 
 // ------------------------------------------------------------ SpGEMM C = A B
 // upper bound of row i of C: sum over k in A_i of nnz(B_k)
-__global__ void k_spgemm_ub(int n, const int* __restrict__ ap, const int* __restrict__ ac, const int* __restrict__ bp,
-                            int* __restrict__ ub) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+// (8 lanes per row)
+__global__ void __launch_bounds__(256)
+k_spgemm_ub(int n, const int* __restrict__ ap, const int* __restrict__ ac, const int* __restrict__ bp,
+            int* __restrict__ ub) {
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const int lane = threadIdx.x & 7;
   if (i >= n) return;
   long s = 0;
-  for (int e = ap[i]; e < ap[i + 1]; ++e) s += bp[ac[e] + 1] - bp[ac[e]];
-  ub[i] = (int)min(s, (long)INT32_MAX);
+  for (int e = ap[i] + lane; e < ap[i + 1]; e += 8) s += bp[ac[e] + 1] - bp[ac[e]];
+#pragma unroll
+  for (int o = 4; o > 0; o >>= 1) s += __shfl_xor(s, o, 8);
+  if (lane == 0) ub[i] = (int)min(s, (long)INT32_MAX);
 }
 
 __device__ __forceinline__ unsigned hslot(int key, int mask) { return ((unsigned)key * 2654435761u) & (unsigned)mask; }
@@ -1375,7 +1380,7 @@ void spgemm(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>
   ub.ensure(n);
   cnt.zero(n + 1, s);
   flag.zero(2, s);  // [0] overflow bits, [1] longest row of B
-  k_spgemm_ub<<<div_up(n, 256), 256, 0, s>>>(n, A.ptr.p, A.col.p, B.ptr.p, ub.p);
+  k_spgemm_ub<<<div_up((long)n * 8, 256), 256, 0, s>>>(n, A.ptr.p, A.col.p, B.ptr.p, ub.p);
   HIP_LAUNCH_CHECK();
   k_max_rowlen<<<div_up(B.rows, 256), 256, 0, s>>>(B.rows, B.ptr.p, flag.p + 1);
   HIP_LAUNCH_CHECK();
