@@ -658,78 +658,100 @@ k_spgemm(int n, const int* __restrict__ ap, const int* __restrict__ ac, const do
   __shared__ int ckeys[NUMERIC ? (TBL * 3) / 4 + 64 : 1];
   __shared__ int ninsert;
   const int lane = threadIdx.x;
-  for (int i = blockIdx.x; i < n; i += gridDim.x) {
-    const int s = sel[i];
-    if (s < sel_lo || s > sel_hi || ubv[i] <= ub_min) continue;
-    // table of T = pow2 >= 2 s slots (s = upper bound or exact count of the row)
-    int T = 64;
-    while (T < 2 * s && T < TBL) T <<= 1;
-    const int mask = T - 1;
-    for (int t = lane; t < T; t += 64) {
-      keys[t] = -1;
-      if (NUMERIC) vals[t] = 0.0;
-    }
-    if (lane == 0) ninsert = 0;
-    __syncthreads();
-    bool bad = false;
-    for (int e = ap[i]; e < ap[i + 1]; ++e) {
-      const int k = ac[e];
-      const double a = NUMERIC ? av[e] : 0.0;
-      for (int q = bp[k] + lane; q < bp[k + 1]; q += 64) {
-        const int j = bc[q];
-        unsigned h = hslot(j, mask);
-        int probes = 0;
-        while (true) {
-          const int old = atomicCAS(&keys[h], -1, j);
-          if (old == -1) {
-            if (!NUMERIC) atomicAdd(&ninsert, 1);
-            break;
-          }
-          if (old == j) break;
-          h = (h + 1) & mask;
-          if (++probes >= T) { bad = true; break; }
+  // block b serves rows b, b + G, b + 2G, ... (G = gridDim.x), testing 64 of
+  // them at once; `continue` below moves on to the next selected row
+  const long G = gridDim.x;
+  for (long c0 = 0; blockIdx.x + c0 * G < n; c0 += 64) {
+    const long r = blockIdx.x + (c0 + lane) * G;
+    unsigned long long pick = __ballot(r < n && sel[r] >= sel_lo && sel[r] <= sel_hi && ubv[r] > ub_min);
+    while (pick) {
+      const int i = (int)(blockIdx.x + (c0 + __ffsll(pick) - 1) * G);
+      pick &= pick - 1;
+      const int s = sel[i];
+      // table of T = pow2 >= 2 s slots (s = upper bound or exact count of the row)
+      int T = 64;
+      while (T < 2 * s && T < TBL) T <<= 1;
+      const int mask = T - 1;
+      for (int t = lane; t < T; t += 64) {
+        keys[t] = -1;
+        if (NUMERIC) vals[t] = 0.0;
+      }
+      if (lane == 0) ninsert = 0;
+      __syncthreads();
+      bool bad = false;
+      // the row bounds of B for 64 entries of A_i are fetched at once, then
+      // the entries are taken in order
+      const int a0 = ap[i], a1 = ap[i + 1];
+      for (int base = a0; base < a1; base += 64) {
+        int kq0 = 0, kq1 = 0;
+        double ka = 0.0;
+        if (base + lane < a1) {
+          const int kk = ac[base + lane];
+          kq0 = bp[kk];
+          kq1 = bp[kk + 1];
+          if (NUMERIC) ka = av[base + lane];
         }
-        if (NUMERIC && !bad) vals[h] += a * bv[q];
+        const int ne = min(64, a1 - base);
+        for (int te = 0; te < ne; ++te) {
+          const int q0 = __shfl(kq0, te, 64), q1 = __shfl(kq1, te, 64);
+          const double a = NUMERIC ? __shfl(ka, te, 64) : 0.0;
+          for (int q = q0 + lane; q < q1; q += 64) {
+            const int j = bc[q];
+            unsigned h = hslot(j, mask);
+            int probes = 0;
+            while (true) {
+              const int old = atomicCAS(&keys[h], -1, j);
+              if (old == -1) {
+                if (!NUMERIC) atomicAdd(&ninsert, 1);
+                break;
+              }
+              if (old == j) break;
+              h = (h + 1) & mask;
+              if (++probes >= T) { bad = true; break; }
+            }
+            if (NUMERIC && !bad) vals[h] += a * bv[q];
+          }
+          __syncthreads();
+        }
+      }
+      if (bad) atomicOr(overflow, 1);
+      if (!NUMERIC) {
+        __syncthreads();
+        if (lane == 0) {
+          cnt[i] = ninsert;
+          if (ninsert > (TBL * 3) / 4) atomicOr(overflow, 4);  // the numeric pass could not hold it
+        }
+        __syncthreads();
+        continue;
+      }
+      // compact the keys, then place every entry by its rank
+      if (lane == 0) ninsert = 0;
+      __syncthreads();
+      for (int t = lane; t < T; t += 64) {
+        const int key = keys[t];
+        if (key >= 0) {
+          const int pos = atomicAdd(&ninsert, 1);
+          if (pos < (TBL * 3) / 4 + 64) ckeys[pos] = key;
+        }
+      }
+      __syncthreads();
+      const int nk = ninsert;
+      const int base = cp[i];
+      if (nk != cp[i + 1] - base || nk > (TBL * 3) / 4 + 64) {
+        if (lane == 0) atomicOr(overflow, 2);
+        __syncthreads();
+        continue;
+      }
+      for (int t = lane; t < T; t += 64) {
+        const int key = keys[t];
+        if (key < 0) continue;
+        int r = 0;
+        for (int u = 0; u < nk; ++u) r += ckeys[u] < key ? 1 : 0;
+        cc[base + r] = key;
+        cv[base + r] = vals[t];
       }
       __syncthreads();
     }
-    if (bad) atomicOr(overflow, 1);
-    if (!NUMERIC) {
-      __syncthreads();
-      if (lane == 0) {
-        cnt[i] = ninsert;
-        if (ninsert > (TBL * 3) / 4) atomicOr(overflow, 4);  // the numeric pass could not hold it
-      }
-      __syncthreads();
-      continue;
-    }
-    // compact the keys, then place every entry by its rank
-    if (lane == 0) ninsert = 0;
-    __syncthreads();
-    for (int t = lane; t < T; t += 64) {
-      const int key = keys[t];
-      if (key >= 0) {
-        const int pos = atomicAdd(&ninsert, 1);
-        if (pos < (TBL * 3) / 4 + 64) ckeys[pos] = key;
-      }
-    }
-    __syncthreads();
-    const int nk = ninsert;
-    const int base = cp[i];
-    if (nk != cp[i + 1] - base || nk > (TBL * 3) / 4 + 64) {
-      if (lane == 0) atomicOr(overflow, 2);
-      __syncthreads();
-      continue;
-    }
-    for (int t = lane; t < T; t += 64) {
-      const int key = keys[t];
-      if (key < 0) continue;
-      int r = 0;
-      for (int u = 0; u < nk; ++u) r += ckeys[u] < key ? 1 : 0;
-      cc[base + r] = key;
-      cv[base + r] = vals[t];
-    }
-    __syncthreads();
   }
 }
 
@@ -765,101 +787,108 @@ k_spgemm_narrow(int n, const int* __restrict__ ap, const int* __restrict__ ac, c
   __shared__ double cvals[CK];
   __shared__ int ninsert;
   const int lane = threadIdx.x;
-  for (int i = blockIdx.x; i < n; i += gridDim.x) {
-    const int s = cnt[i];
-    if (s < sel_lo || s > sel_hi) continue;
-    int T = 64;
-    while (T < 2 * s && T < TBL) T <<= 1;
-    const int mask = T - 1;
-    for (int t = lane; t < T; t += 64) {
-      keys[t] = -1;
-      vals[t] = 0.0;
-    }
-    if (lane == 0) ninsert = 0;
-    __syncthreads();
-    bool bad = false;
-    const int a0 = ap[i], a1 = ap[i + 1];
-    for (int base = a0; base < a1; base += 64) {
-      const int e = base + lane;
-      double a = 0.0;
-      int qb = 0, ql = 0;
-      if (e < a1) {
-        const int k = ac[e];
-        a = av[e];
-        qb = bp[k];
-        ql = bp[k + 1] - qb;
+  // rows selected 64 at a time as in k_spgemm
+  const long G = gridDim.x;
+  for (long c0 = 0; blockIdx.x + c0 * G < n; c0 += 64) {
+    const long r = blockIdx.x + (c0 + lane) * G;
+    unsigned long long pick = __ballot(r < n && cnt[r] >= sel_lo && cnt[r] <= sel_hi);
+    while (pick) {
+      const int i = (int)(blockIdx.x + (c0 + __ffsll(pick) - 1) * G);
+      pick &= pick - 1;
+      const int s = cnt[i];
+      int T = 64;
+      while (T < 2 * s && T < TBL) T <<= 1;
+      const int mask = T - 1;
+      for (int t = lane; t < T; t += 64) {
+        keys[t] = -1;
+        vals[t] = 0.0;
       }
-      if (ql > WB) {
-        bad = true;
-        ql = WB;
-      }
-      int jj[WB];
-      double bb[WB];
-#pragma unroll
-      for (int q = 0; q < WB; ++q)
-        if (q < ql) {
-          jj[q] = bc[qb + q];
-          bb[q] = bv[qb + q];
+      if (lane == 0) ninsert = 0;
+      __syncthreads();
+      bool bad = false;
+      const int a0 = ap[i], a1 = ap[i + 1];
+      for (int base = a0; base < a1; base += 64) {
+        const int e = base + lane;
+        double a = 0.0;
+        int qb = 0, ql = 0;
+        if (e < a1) {
+          const int k = ac[e];
+          a = av[e];
+          qb = bp[k];
+          ql = bp[k + 1] - qb;
         }
-#pragma unroll
-      for (int q = 0; q < WB; ++q) {
-        int h = -1;
-        if (q < ql) {
-          h = (int)hslot(jj[q], mask);
-          int probes = 0;
-          while (true) {
-            const int old = atomicCAS(&keys[h], -1, jj[q]);
-            if (old == -1 || old == jj[q]) break;
-            h = (h + 1) & mask;
-            if (++probes >= T) {
-              bad = true;
-              h = -1;
-              break;
-            }
+        if (ql > WB) {
+          bad = true;
+          ql = WB;
+        }
+        int jj[WB];
+        double bb[WB];
+  #pragma unroll
+        for (int q = 0; q < WB; ++q)
+          if (q < ql) {
+            jj[q] = bc[qb + q];
+            bb[q] = bv[qb + q];
           }
-          f_b[lane * WB + q] = bb[q];
+  #pragma unroll
+        for (int q = 0; q < WB; ++q) {
+          int h = -1;
+          if (q < ql) {
+            h = (int)hslot(jj[q], mask);
+            int probes = 0;
+            while (true) {
+              const int old = atomicCAS(&keys[h], -1, jj[q]);
+              if (old == -1 || old == jj[q]) break;
+              h = (h + 1) & mask;
+              if (++probes >= T) {
+                bad = true;
+                h = -1;
+                break;
+              }
+            }
+            f_b[lane * WB + q] = bb[q];
+          }
+          f_s[lane * WB + q] = h;
         }
-        f_s[lane * WB + q] = h;
-      }
-      f_a[lane] = a;
-      __syncthreads();
-      const int ne = min(64, a1 - base);
-      for (int e2 = 0; e2 < ne; ++e2) {
-        if (lane < WB) {
-          const int h = f_s[e2 * WB + lane];
-          if (h >= 0) vals[h] += f_a[e2] * f_b[e2 * WB + lane];
-        }
+        f_a[lane] = a;
         __syncthreads();
-      }
-    }
-    if (bad) atomicOr(overflow, 8);
-    // compact (key, value) pairs, then place every entry by its rank
-    for (int t = lane; t < T; t += 64) {
-      const int key = keys[t];
-      if (key >= 0) {
-        const int pos = atomicAdd(&ninsert, 1);
-        if (pos < CK) {
-          ckeys[pos] = key;
-          cvals[pos] = vals[t];
+        const int ne = min(64, a1 - base);
+        for (int e2 = 0; e2 < ne; ++e2) {
+          if (lane < WB) {
+            const int h = f_s[e2 * WB + lane];
+            if (h >= 0) vals[h] += f_a[e2] * f_b[e2 * WB + lane];
+          }
+          __syncthreads();
         }
       }
-    }
-    __syncthreads();
-    const int nk = ninsert;
-    const int base = cp[i];
-    if (nk != cp[i + 1] - base || nk > CK) {
-      if (lane == 0) atomicOr(overflow, 2);
+      if (bad) atomicOr(overflow, 8);
+      // compact (key, value) pairs, then place every entry by its rank
+      for (int t = lane; t < T; t += 64) {
+        const int key = keys[t];
+        if (key >= 0) {
+          const int pos = atomicAdd(&ninsert, 1);
+          if (pos < CK) {
+            ckeys[pos] = key;
+            cvals[pos] = vals[t];
+          }
+        }
+      }
       __syncthreads();
-      continue;
+      const int nk = ninsert;
+      const int base = cp[i];
+      if (nk != cp[i + 1] - base || nk > CK) {
+        if (lane == 0) atomicOr(overflow, 2);
+        __syncthreads();
+        continue;
+      }
+      for (int p = lane; p < nk; p += 64) {
+        const int key = ckeys[p];
+        int r = 0;
+        for (int u = 0; u < nk; ++u) r += ckeys[u] < key ? 1 : 0;
+        cc[base + r] = key;
+        cv[base + r] = cvals[p];
+      }
+      __syncthreads();
     }
-    for (int p = lane; p < nk; p += 64) {
-      const int key = ckeys[p];
-      int r = 0;
-      for (int u = 0; u < nk; ++u) r += ckeys[u] < key ? 1 : 0;
-      cc[base + r] = key;
-      cv[base + r] = cvals[p];
-    }
-    __syncthreads();
   }
 }
 
@@ -883,141 +912,148 @@ k_spgemm_staged(int n, const int* __restrict__ ap, const int* __restrict__ ac, c
   __shared__ int ckeys[NUMERIC ? SMAX : 1];
   __shared__ int ne_sh, nk_sh;
   const int lane = threadIdx.x;
-  for (int i = blockIdx.x; i < n; i += gridDim.x) {
-    const int U = ub[i];
-    if (U < ub_lo || U > SMAX) continue;
-    if (U == 0) {
-      if (!NUMERIC && lane == 0) cnt[i] = 0;
-      continue;
-    }
-    // 1. compacted entries with their product offsets (wave prefix sums)
-    int run_off = 0, run_ne = 0;
-    for (int base = ap[i]; base < ap[i + 1]; base += 64) {
-      const int e = base + lane;
-      int k = 0, len = 0;
-      if (e < ap[i + 1]) {
-        k = ac[e];
-        len = bp[k + 1] - bp[k];
+  // rows selected 64 at a time as in k_spgemm
+  const long G = gridDim.x;
+  for (long c0 = 0; blockIdx.x + c0 * G < n; c0 += 64) {
+    const long r = blockIdx.x + (c0 + lane) * G;
+    unsigned long long pick = __ballot(r < n && ub[r] >= ub_lo && ub[r] <= SMAX);
+    while (pick) {
+      const int i = (int)(blockIdx.x + (c0 + __ffsll(pick) - 1) * G);
+      pick &= pick - 1;
+      const int U = ub[i];
+      if (U == 0) {
+        if (!NUMERIC && lane == 0) cnt[i] = 0;
+        continue;
       }
-      int inc = len;  // inclusive scan of len over the wave
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(inc, o, 64);
-        if (lane >= o) inc += y;
+      // 1. compacted entries with their product offsets (wave prefix sums)
+      int run_off = 0, run_ne = 0;
+      for (int base = ap[i]; base < ap[i + 1]; base += 64) {
+        const int e = base + lane;
+        int k = 0, len = 0;
+        if (e < ap[i + 1]) {
+          k = ac[e];
+          len = bp[k + 1] - bp[k];
+        }
+        int inc = len;  // inclusive scan of len over the wave
+  #pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const int y = __shfl_up(inc, o, 64);
+          if (lane >= o) inc += y;
+        }
+        const unsigned long long fm = __ballot(len > 0);
+        const int pos = run_ne + __popcll(fm & ((1ull << lane) - 1ull));
+        if (len > 0) {
+          e_k[pos] = k;
+          e_off[pos] = run_off + inc - len;
+          if (NUMERIC) e_a[pos] = av[e];
+        }
+        run_off += __shfl(inc, 63, 64);
+        run_ne += __popcll(fm);
       }
-      const unsigned long long fm = __ballot(len > 0);
-      const int pos = run_ne + __popcll(fm & ((1ull << lane) - 1ull));
-      if (len > 0) {
-        e_k[pos] = k;
-        e_off[pos] = run_off + inc - len;
-        if (NUMERIC) e_a[pos] = av[e];
+      if (lane == 0) {
+        e_off[run_ne] = run_off;
+        ne_sh = run_ne;
+        nk_sh = 0;
       }
-      run_off += __shfl(inc, 63, 64);
-      run_ne += __popcll(fm);
-    }
-    if (lane == 0) {
-      e_off[run_ne] = run_off;
-      ne_sh = run_ne;
-      nk_sh = 0;
-    }
-    int T = 64;
-    while (T < 2 * U) T <<= 1;
-    const int mask = T - 1;
-    for (int t = lane; t < T; t += 64) {
-      keys[t] = -1;
-      if (NUMERIC) vals[t] = 0.0;
-    }
-    __syncthreads();
-    const int ne = ne_sh;
-    // 2. the (column, value) pairs, lane-parallel over the whole list, four
-    //    independent pairs per lane and step so that their loads overlap
-    for (int t0 = lane; t0 < U; t0 += 256) {
-      int qq[4], ee[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int t = t0 + 64 * u;
-        qq[u] = -1;
-        if (t < U) {
-          int lo = 0, hi = ne - 1;  // last entry with e_off <= t
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (e_off[mid] <= t) lo = mid; else hi = mid - 1;
+      int T = 64;
+      while (T < 2 * U) T <<= 1;
+      const int mask = T - 1;
+      for (int t = lane; t < T; t += 64) {
+        keys[t] = -1;
+        if (NUMERIC) vals[t] = 0.0;
+      }
+      __syncthreads();
+      const int ne = ne_sh;
+      // 2. the (column, value) pairs, lane-parallel over the whole list, four
+      //    independent pairs per lane and step so that their loads overlap
+      for (int t0 = lane; t0 < U; t0 += 256) {
+        int qq[4], ee[4];
+  #pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int t = t0 + 64 * u;
+          qq[u] = -1;
+          if (t < U) {
+            int lo = 0, hi = ne - 1;  // last entry with e_off <= t
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (e_off[mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            ee[u] = lo;
+            qq[u] = bp[e_k[lo]] + (t - e_off[lo]);
           }
-          ee[u] = lo;
-          qq[u] = bp[e_k[lo]] + (t - e_off[lo]);
+        }
+        int jj[4];
+        double vv[4];
+  #pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (qq[u] >= 0) {
+            jj[u] = bc[qq[u]];
+            if (NUMERIC) vv[u] = bv[qq[u]];
+          }
+  #pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (qq[u] >= 0) {
+            f_j[t0 + 64 * u] = jj[u];
+            if (NUMERIC) f_v[t0 + 64 * u] = e_a[ee[u]] * vv[u];
+          }
+      }
+      __syncthreads();
+      // 3. hash insertion; f_j[t] becomes the slot of pair t
+      bool bad = false;
+      for (int t = lane; t < U; t += 64) {
+        const int j = f_j[t];
+        unsigned h = hslot(j, mask);
+        int probes = 0;
+        while (true) {
+          const int old = atomicCAS(&keys[h], -1, j);
+          if (old == -1) {
+            if (!NUMERIC) atomicAdd(&nk_sh, 1);
+            break;
+          }
+          if (old == j) break;
+          h = (h + 1) & mask;
+          if (++probes >= T) { bad = true; break; }
+        }
+        f_j[t] = (int)h;
+      }
+      if (bad) atomicOr(overflow, 1);
+      __syncthreads();
+      if (!NUMERIC) {
+        if (lane == 0) cnt[i] = nk_sh;
+        __syncthreads();
+        continue;
+      }
+      // 4. accumulate entry by entry (distinct columns within one entry)
+      for (int e = 0; e < ne; ++e) {
+        for (int t = e_off[e] + lane; t < e_off[e + 1]; t += 64) vals[f_j[t]] += f_v[t];
+        __syncthreads();
+      }
+      // 5. compact the keys and place every entry by its rank
+      for (int t = lane; t < T; t += 64) {
+        const int key = keys[t];
+        if (key >= 0) {
+          const int pos = atomicAdd(&nk_sh, 1);
+          if (pos < SMAX) ckeys[pos] = key;
         }
       }
-      int jj[4];
-      double vv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (qq[u] >= 0) {
-          jj[u] = bc[qq[u]];
-          if (NUMERIC) vv[u] = bv[qq[u]];
-        }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (qq[u] >= 0) {
-          f_j[t0 + 64 * u] = jj[u];
-          if (NUMERIC) f_v[t0 + 64 * u] = e_a[ee[u]] * vv[u];
-        }
-    }
-    __syncthreads();
-    // 3. hash insertion; f_j[t] becomes the slot of pair t
-    bool bad = false;
-    for (int t = lane; t < U; t += 64) {
-      const int j = f_j[t];
-      unsigned h = hslot(j, mask);
-      int probes = 0;
-      while (true) {
-        const int old = atomicCAS(&keys[h], -1, j);
-        if (old == -1) {
-          if (!NUMERIC) atomicAdd(&nk_sh, 1);
-          break;
-        }
-        if (old == j) break;
-        h = (h + 1) & mask;
-        if (++probes >= T) { bad = true; break; }
+      __syncthreads();
+      const int nk = nk_sh;
+      const int base = cp[i];
+      if (nk != cp[i + 1] - base || nk > SMAX) {
+        if (lane == 0) atomicOr(overflow, 2);
+        __syncthreads();
+        continue;
       }
-      f_j[t] = (int)h;
-    }
-    if (bad) atomicOr(overflow, 1);
-    __syncthreads();
-    if (!NUMERIC) {
-      if (lane == 0) cnt[i] = nk_sh;
-      __syncthreads();
-      continue;
-    }
-    // 4. accumulate entry by entry (distinct columns within one entry)
-    for (int e = 0; e < ne; ++e) {
-      for (int t = e_off[e] + lane; t < e_off[e + 1]; t += 64) vals[f_j[t]] += f_v[t];
-      __syncthreads();
-    }
-    // 5. compact the keys and place every entry by its rank
-    for (int t = lane; t < T; t += 64) {
-      const int key = keys[t];
-      if (key >= 0) {
-        const int pos = atomicAdd(&nk_sh, 1);
-        if (pos < SMAX) ckeys[pos] = key;
+      for (int t = lane; t < T; t += 64) {
+        const int key = keys[t];
+        if (key < 0) continue;
+        int r = 0;
+        for (int u = 0; u < nk; ++u) r += ckeys[u] < key ? 1 : 0;
+        cc[base + r] = key;
+        cv[base + r] = vals[t];
       }
-    }
-    __syncthreads();
-    const int nk = nk_sh;
-    const int base = cp[i];
-    if (nk != cp[i + 1] - base || nk > SMAX) {
-      if (lane == 0) atomicOr(overflow, 2);
       __syncthreads();
-      continue;
     }
-    for (int t = lane; t < T; t += 64) {
-      const int key = keys[t];
-      if (key < 0) continue;
-      int r = 0;
-      for (int u = 0; u < nk; ++u) r += ckeys[u] < key ? 1 : 0;
-      cc[base + r] = key;
-      cv[base + r] = vals[t];
-    }
-    __syncthreads();
   }
 }
 
@@ -1386,13 +1422,16 @@ void spgemm(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>
   HIP_LAUNCH_CHECK();
   constexpr int TS = 2048, TL = 8192, S1 = 512, S2 = 1024;
   const int grid = std::min(n, 1 << 16);
+  // kernels with large LDS tables fit few blocks per CU and serve few rows:
+  // fewer blocks, each testing its rows 64 at a time
+  const int gridL = std::min(n, 2048);
   // symbolic: staged kernels for product lists up to S2 entries, the
   // unstaged large-table kernel for longer ones
   k_spgemm_staged<S1, false><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, nullptr, B.ptr.p, B.col.p, nullptr, ub.p, 0,
                                                  cnt.p, nullptr, nullptr, nullptr, flag.p);
-  k_spgemm_staged<S2, false><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, nullptr, B.ptr.p, B.col.p, nullptr, ub.p,
+  k_spgemm_staged<S2, false><<<gridL, 64, 0, s>>>(n, A.ptr.p, A.col.p, nullptr, B.ptr.p, B.col.p, nullptr, ub.p,
                                                  S1 + 1, cnt.p, nullptr, nullptr, nullptr, flag.p);
-  k_spgemm<TL, false><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, nullptr, B.ptr.p, B.col.p, nullptr, ub.p, S2 + 1,
+  k_spgemm<TL, false><<<gridL, 64, 0, s>>>(n, A.ptr.p, A.col.p, nullptr, B.ptr.p, B.col.p, nullptr, ub.p, S2 + 1,
                                           INT32_MAX, cnt.p, nullptr, nullptr, nullptr, flag.p, ub.p, S2);
   HIP_LAUNCH_CHECK();
   Cm.ptr.ensure(n + 1);
@@ -1422,9 +1461,9 @@ void spgemm(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>
     k_spgemm<512, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 193,
                                             384, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p, ub.p, -1);
   }
-  k_spgemm<TS, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 385,
+  k_spgemm<TS, true><<<gridL, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 385,
                                          TS * 3 / 4, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p, ub.p, -1);
-  k_spgemm<TL, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p,
+  k_spgemm<TL, true><<<gridL, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p,
                                          TS * 3 / 4 + 1, TL * 3 / 4, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p,
                                          ub.p, -1);
   HIP_LAUNCH_CHECK();
