@@ -372,15 +372,11 @@ k_pl_combine(int n, const int* __restrict__ bptr, const int* __restrict__ bcol, 
   const int gid = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
   const int lane = threadIdx.x & 15;
   if (gid >= n) return;
-  // the row's 3 x (blocks) coefficients are contiguous: the 16 lanes read
-  // them in order (coalesced), entry t belonging to block t / 3, column t % 3
   double s = 0.0;
-  const int q0 = bptr[gid];
-  const int len = 3 * (bptr[gid + 1] - q0);
-  const double* row = b2 + 3 * (size_t)q0;
-  for (int t = lane; t < len; t += 16) {
-    const int blk = t / 3;
-    s += row[t] * (double)zu[3 * bcol[q0 + blk] + (t - 3 * blk)];
+  for (int q = bptr[gid] + lane; q < bptr[gid + 1]; q += 16) {
+    const int j = bcol[q];
+    const double* blk = b2 + 3 * (size_t)q;
+    s += blk[0] * (double)zu[3 * j] + blk[1] * (double)zu[3 * j + 1] + blk[2] * (double)zu[3 * j + 2];
   }
 #pragma unroll
   for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
