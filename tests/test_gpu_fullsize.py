@@ -7,16 +7,17 @@
   all-fp64 cycle: both reach ||b - K x|| <= 1e-8 ||b||, checked on the host
   with the exported tangent (independent of the GPU residual kernel); their
   difference is printed;
-* the 96^3 cube: level-0 C/F splitting bit-exact with the oracle's PMIS on
-  the GPU's A; the learned interpolation is judged by the convergence factor
-  and both interpolations solve the Newton system to 1e-8.
+* the 96^3 cube with the default hierarchy: level-0 C/F splitting bit-exact
+  with the oracle's PMIS on the GPU's A; the learned interpolation is judged
+  by the convergence factor and both interpolations solve the Newton system
+  to 1e-8.
 """
 import numpy as np
 import pytest
 import scipy.sparse as sp
 
 import synth
-from gpu_helpers import amg_prm_pair, context_for, export_level_matrix, oracle_sampled_rows, torch_dev
+from gpu_helpers import context_for, export_level_matrix, oracle_sampled_rows, torch_dev
 from oracle import amg
 
 pytestmark = pytest.mark.gpu
@@ -80,7 +81,7 @@ def test_tube_mixed_precision_solve(lib):
     bh = b.cpu().numpy()
     sol = {}
     for prec in (1, 0):
-        gprm, _ = amg_prm_pair(lib, smoother=1, precision=prec)
+        gprm = lib.amg_params(smoother=1, precision=prec)
         ainfo = ctx.amg_setup(gprm)
         x = torch.zeros_like(b)
         si, code = ctx.krylov_amg_solve(b, x, lib.solve_params(tol=1e-8, restart=256, max_iter=3000))
@@ -104,14 +105,15 @@ def test_cube96_splitting_and_learned_judge(lib):
     n = prob.n_nodes
     print(f"[fullsize cube96] dofs={prob.n_dofs}", flush=True)
     ctx, vt, R, view, info = _assembled(lib, prob, np.zeros((n, 4)), 1.0)
-    gprm, oprm = amg_prm_pair(lib, smoother=1, precision=1)
+    # the library's default hierarchy (extended+i, default cycle), fp32 cycle
+    gprm = lib.amg_params(smoother=1, precision=1)
     cinfo = ctx.amg_setup(gprm)
     A = export_level_matrix(ctx, 0, 0)
     comp = ctx.amg_export(0, 4)
     st = ctx.amg_export(0, 3)
     print(f"[fullsize cube96] A rows={A.shape[0]} nnz={A.nnz}; oracle PMIS", flush=True)
-    S_ptr, S_idx = amg.strength(A, comp, oprm.theta)
-    assert np.array_equal(st, amg.pmis(S_ptr, S_idx, A.shape[0], oprm.seed, 0))
+    S_ptr, S_idx = amg.strength(A, comp, gprm.strength_theta)
+    assert np.array_equal(st, amg.pmis(S_ptr, S_idx, A.shape[0], gprm.seed, 0))
     del A, S_ptr, S_idx
     b = -R
     x = torch.zeros_like(b)
@@ -120,7 +122,7 @@ def test_cube96_splitting_and_learned_judge(lib):
     rho_c = ctx.amg_convergence_factor(10, 777)
     w, _ = train_mlp.load(train_mlp.DEFAULT_WEIGHTS)
     ctx.mlp_set_weights(w)
-    lprm = lib.amg_params(smoother=1, precision=1, interp=1, fallback_rho=0.5)
+    lprm = lib.amg_params(smoother=1, precision=1, interp=1)
     linfo = ctx.amg_setup(lprm)
     x = torch.zeros_like(b)
     sl, code = ctx.krylov_amg_solve(b, x, lib.solve_params(tol=1e-8, restart=256, max_iter=3000))
@@ -128,4 +130,4 @@ def test_cube96_splitting_and_learned_judge(lib):
     print(f"[fullsize cube96] classical: rho={rho_c:.3f} its={sc.iterations}; learned: rho={linfo.rho:.3f} "
           f"kept={linfo.learned_used} its={sl.iterations}", flush=True)
     assert 0 < linfo.rho < 1
-    assert linfo.learned_used == (linfo.rho <= 0.5)
+    assert linfo.learned_used == (linfo.rho <= lprm.fallback_rho)
