@@ -113,11 +113,11 @@ typedef struct {
   uint64_t seed;         /* PMIS weight seed, default 12345                */
   int32_t smoother;
   int32_t nu_pre, nu_post;  /* level 0: sweeps before / after the coarse
-                               correction, default 1 / 2                   */
+                               correction, default 1 / 1                   */
   int32_t precision;
   int32_t interp;
   double fallback_rho;   /* default 0.6                                    */
-  int32_t cheb_degree;   /* level-0 post-smoothing degree, 1..8, default 2 */
+  int32_t cheb_degree;   /* level-0 post-smoothing degree, 1..8, default 3 */
   double cheb_ratio;     /* lmax / lower bound of the interval, > 1, default 30 */
   int32_t interp_kind;   /* 0 = modified classical (distance one), 1 = extended+i
                             (distance two, De Sterck et al. 2008); the learned

@@ -312,8 +312,8 @@ class AmgParams:
     seed: int = 12345
     smoother: str = "chebyshev"   # or "l1jacobi"
     nu_pre: int = 1                # level 0: sweeps before the coarse correction
-    nu_post: int = 2               # and after it
-    cheb_degree: int = 2           # their Chebyshev degree
+    nu_post: int = 1               # and after it
+    cheb_degree: int = 3           # their Chebyshev degree
     cheb_ratio: float = 30.0
     cheb_degree_pre: int = 1       # pre-smoothing degree
     nu_post_coarse: int = 1        # post-smoothing sweeps on levels >= 1

@@ -195,9 +195,9 @@ struct Hierarchy {
   DevBuf<double> lmax_dev;    // per-level eigenvalue estimates (written on the aux stream)
   int precision = 0;
   int smoother = 0;
-  int nu_pre = 1, nu_post = 2;  // level 0: sweeps before / after the correction
+  int nu_pre = 1, nu_post = 1;  // level 0: sweeps before / after the correction
   int nu_pre_coarse = 0, nu_post_coarse = 1;  // the same on levels >= 1
-  int cheb_degree = 2;          // Chebyshev degrees: level-0 post, pre, coarse post
+  int cheb_degree = 3;          // Chebyshev degrees: level-0 post, pre, coarse post
   int cheb_degree_pre = 1, cheb_degree_coarse = 3;
   double cheb_ratio = 30.0;     // interval [lmax / ratio, 1.1 lmax]
   bool ready = false;

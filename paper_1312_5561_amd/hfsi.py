@@ -97,8 +97,8 @@ def train_params(batch=1024, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     return TrainParams(C.sizeof(TrainParams), batch, lr, beta1, beta2, eps)
 
 
-def amg_params(theta=0.15, max_coarse=500, max_levels=25, seed=12345, smoother=1, nu_pre=1, nu_post=2,
-               precision=0, interp=0, fallback_rho=0.6, cheb_degree=2, cheb_ratio=30.0, interp_kind=1, p_max=4,
+def amg_params(theta=0.15, max_coarse=500, max_levels=25, seed=12345, smoother=1, nu_pre=1, nu_post=1,
+               precision=0, interp=0, fallback_rho=0.6, cheb_degree=3, cheb_ratio=30.0, interp_kind=1, p_max=4,
                cheb_degree_pre=1, nu_post_coarse=1, cheb_degree_coarse=3, nu_pre_coarse=0):
     return AmgParams(C.sizeof(AmgParams), theta, max_coarse, max_levels, seed, smoother, nu_pre, nu_post,
                      precision, interp, fallback_rho, cheb_degree, cheb_ratio, interp_kind, p_max, cheb_degree_pre,

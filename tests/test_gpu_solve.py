@@ -40,7 +40,7 @@ def _setup(lib, prob, v, load, smoother=0, precision=0, max_coarse=500, nu=(2, 2
                                                         (1, 0, None, None), (1, 1, None, None)])
 def test_vcycle_and_preconditioner_match_oracle(lib, smoother, precision, nu, cheb):
     """nu = cheb = None: the default schedule (on level 0 one degree-1 sweep
-    before the correction and two degree-2 sweeps after it; on the coarser
+    before the correction and one degree-3 sweep after it; on the coarser
     levels no pre-smoothing and one degree-3 sweep after)."""
     import torch
     prob = synth.cube_problem(6, jitter=0.1, seed=2)
