@@ -1435,10 +1435,8 @@ void spgemm(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>
                                           INT32_MAX, cnt.p, nullptr, nullptr, nullptr, flag.p, ub.p, S2);
   HIP_LAUNCH_CHECK();
   Cm.ptr.ensure(n + 1);
-  int64_t nnz = exclusive_scan(cnt.p, Cm.ptr.p, n + 1, s);
-  int fl2[2] = {0, 0};
-  HIP_CHECK(hipMemcpyAsync(fl2, flag.p, sizeof(fl2), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
+  int fl2[2] = {0, 0};  // read in the scan's wait
+  int64_t nnz = exclusive_scan(cnt.p, Cm.ptr.p, n + 1, s, flag.p, 2, fl2);
   if (fl2[0]) fail(HFSI_E_CAPACITY, "sparse product: a row exceeds the hash table");
   const int bmax = fl2[1];
   int fl = 0;
@@ -1504,10 +1502,8 @@ void pack_level(hfsi_ctx* c, Level& L, int precision) {
   k_pack_count<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, K.p4.p, K.base.p, wide.p);
   HIP_LAUNCH_CHECK();
   HIP_CHECK(hipMemsetAsync(K.p4.p + n, 0, sizeof(int), s));
-  K.chunks = exclusive_scan(K.p4.p, K.p4.p, n + 1, s);
-  int w = 0;
-  HIP_CHECK(hipMemcpyAsync(&w, wide.p, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
+  int w = 0;  // read in the scan's wait
+  K.chunks = exclusive_scan(K.p4.p, K.p4.p, n + 1, s, wide.p, 1, &w);
   K.wide = w != 0;
   const size_t m = 4 * (size_t)K.chunks;
   // keep only the arrays of this layout and precision
@@ -1671,13 +1667,17 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
     L.P.rows = n;
     L.P.cols = nc;
     L.P.ptr.ensure(n + 1);
-    L.P.nnz = exclusive_scan(cnt.p, L.P.ptr.p, n + 1, s);
+    int o = 0;  // overflow of the single strided pass, read in the scan's wait
+    L.P.nnz = strided ? exclusive_scan(cnt.p, L.P.ptr.p, n + 1, s, ovf.p, 1, &o)
+                      : exclusive_scan(cnt.p, L.P.ptr.p, n + 1, s);
+    if (o) fail(HFSI_E_CAPACITY, "extended interpolation: a row has more than 96 candidate C points");
     L.P.col.ensure(L.P.nnz);
     L.P.val.ensure(L.P.nnz);
-    {
-      if (strided)
-        k_compact_rows<<<div_up(n, 256), 256, 0, s>>>(n, prm.p_max, L.P.ptr.p, tcol.p, tval.p, L.P.col.p, L.P.val.p);
-      else if (extpi)
+    if (strided) {
+      k_compact_rows<<<div_up(n, 256), 256, 0, s>>>(n, prm.p_max, L.P.ptr.p, tcol.p, tval.p, L.P.col.p, L.P.val.p);
+      HIP_LAUNCH_CHECK();
+    } else {
+      if (extpi)
         k_extpi<true, XNG><<<div_up(n, 4), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, L.strong.p,
                                                                  L.state.p, L.comp.p, L.cidx.p, prm.p_max, nullptr,
                                                                  L.P.ptr.p, L.P.col.p, L.P.val.p, ovf.p);
@@ -1686,7 +1686,6 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
                                                                    L.state.p, L.comp.p, L.cidx.p, L.P.ptr.p,
                                                                    L.P.col.p, L.P.val.p, ovf.p);
       HIP_LAUNCH_CHECK();
-      int o = 0;
       HIP_CHECK(hipMemcpyAsync(&o, ovf.p, sizeof(int), hipMemcpyDeviceToHost, s));
       HIP_CHECK(hipStreamSynchronize(s));
       if (o)

@@ -266,8 +266,10 @@ namespace hfsi {
 
 // ------------------------------------------------------------------ scans
 // Exclusive prefix sum of `n` int32 values; out may alias in.  Returns the
-// total (synchronises the stream).
-int64_t exclusive_scan(const int* in, int* out, int n, hipStream_t s);
+// total (one wait on the stream); `n_extra` (at most 8) device ints from
+// `extra` are copied to `extra_host` in the same wait.
+int64_t exclusive_scan(const int* in, int* out, int n, hipStream_t s, const int* extra = nullptr, int n_extra = 0,
+                       int* extra_host = nullptr);
 // Same without reading back the total.
 void exclusive_scan_async(const int* in, int* out, int n, hipStream_t s);
 

@@ -194,15 +194,28 @@ __global__ void k_sum_final(const double* __restrict__ part, int n, double* __re
 
 void exclusive_scan_async(const int* in, int* out, int n, hipStream_t s) { scan_rec(in, out, n, s); }
 
-int64_t exclusive_scan(const int* in, int* out, int n, hipStream_t s) {
-  if (n <= 0) return 0;
-  int last_in = 0, last_out = 0;
-  HIP_CHECK(hipMemcpyAsync(&last_in, in + n - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+namespace {
+constexpr int SCAN_EXTRA_MAX = 8;
+thread_local int* g_scan_pinned = nullptr;  // [2 + SCAN_EXTRA_MAX], held until the process ends
+}  // namespace
+
+int64_t exclusive_scan(const int* in, int* out, int n, hipStream_t s, const int* extra, int n_extra,
+                       int* extra_host) {
+  if (n_extra < 0 || n_extra > SCAN_EXTRA_MAX) fail(HFSI_E_ARG, "exclusive_scan: too many extra values");
+  if (!g_scan_pinned) HIP_CHECK(hipHostMalloc((void**)&g_scan_pinned, sizeof(int) * (2 + SCAN_EXTRA_MAX)));
+  int* p = g_scan_pinned;
+  p[0] = p[1] = 0;
+  // the last input is read before an in-place scan overwrites it; the extra
+  // values and the last output come back in the same wait
+  if (n > 0) HIP_CHECK(hipMemcpyAsync(p, in + n - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  if (n_extra > 0) HIP_CHECK(hipMemcpyAsync(p + 2, extra, sizeof(int) * n_extra, hipMemcpyDeviceToHost, s));
+  if (n > 0) {
+    scan_rec(in, out, n, s);
+    HIP_CHECK(hipMemcpyAsync(p + 1, out + n - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  }
   HIP_CHECK(hipStreamSynchronize(s));
-  scan_rec(in, out, n, s);
-  HIP_CHECK(hipMemcpyAsync(&last_out, out + n - 1, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
-  return (int64_t)last_out + last_in;
+  for (int k = 0; k < n_extra; ++k) extra_host[k] = p[2 + k];
+  return n > 0 ? (int64_t)p[1] + p[0] : 0;
 }
 
 double device_sum(hfsi_ctx* c, const double* x, int n) {
