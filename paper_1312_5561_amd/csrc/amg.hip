@@ -738,7 +738,14 @@ k_spgemm(int n, const int* __restrict__ ap, const int* __restrict__ ac, const do
       const int nk = ninsert;
       const int base = cp[i];
       if (nk != cp[i + 1] - base || nk > (TBL * 3) / 4 + 64) {
+        // a row that cannot be placed gets column 0 / value 0 entries, so
+        // that nothing downstream reads an unset column before the flag is
+        // checked
         if (lane == 0) atomicOr(overflow, 2);
+        for (int t = base + lane; t < cp[i + 1]; t += 64) {
+          cc[t] = 0;
+          if (cv) cv[t] = 0.0;
+        }
         __syncthreads();
         continue;
       }
@@ -876,7 +883,14 @@ k_spgemm_narrow(int n, const int* __restrict__ ap, const int* __restrict__ ac, c
       const int nk = ninsert;
       const int base = cp[i];
       if (nk != cp[i + 1] - base || nk > CK) {
+        // a row that cannot be placed gets column 0 / value 0 entries, so
+        // that nothing downstream reads an unset column before the flag is
+        // checked
         if (lane == 0) atomicOr(overflow, 2);
+        for (int t = base + lane; t < cp[i + 1]; t += 64) {
+          cc[t] = 0;
+          if (cv) cv[t] = 0.0;
+        }
         __syncthreads();
         continue;
       }
@@ -1040,7 +1054,14 @@ k_spgemm_staged(int n, const int* __restrict__ ap, const int* __restrict__ ac, c
       const int nk = nk_sh;
       const int base = cp[i];
       if (nk != cp[i + 1] - base || nk > SMAX) {
+        // a row that cannot be placed gets column 0 / value 0 entries, so
+        // that nothing downstream reads an unset column before the flag is
+        // checked
         if (lane == 0) atomicOr(overflow, 2);
+        for (int t = base + lane; t < cp[i + 1]; t += 64) {
+          cc[t] = 0;
+          if (cv) cv[t] = 0.0;
+        }
         __syncthreads();
         continue;
       }
@@ -1407,7 +1428,9 @@ void transpose(hfsi_ctx* c, const Csr<double>& P, Csr<double>& R) {
 }
 
 // C = A B with the structural pattern (no numerical dropping).
-void spgemm(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>& Cm) {
+// The numeric pass reports overflow into *deferred (checked by the caller
+// later: an overflowing row is written with column 0 entries).
+void spgemm(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>& Cm, int* deferred) {
   hipStream_t s = c->stream;
   const int n = A.rows;
   Cm.rows = n;
@@ -1439,7 +1462,6 @@ void spgemm(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>
   int64_t nnz = exclusive_scan(cnt.p, Cm.ptr.p, n + 1, s, flag.p, 2, fl2);
   if (fl2[0]) fail(HFSI_E_CAPACITY, "sparse product: a row exceeds the hash table");
   const int bmax = fl2[1];
-  int fl = 0;
   if (nnz > INT32_MAX) fail(HFSI_E_ARG, "sparse product exceeds int32 indexing");
   Cm.nnz = nnz;
   Cm.col.ensure(nnz);
@@ -1450,24 +1472,21 @@ void spgemm(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>
   if (bmax <= 4) {
     // B with short rows (truncated interpolation): rows up to 384 entries
     k_spgemm_narrow<256, 4><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 0,
-                                                192, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p);
+                                                192, Cm.ptr.p, Cm.col.p, Cm.val.p, deferred);
     k_spgemm_narrow<512, 4><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 193,
-                                                384, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p);
+                                                384, Cm.ptr.p, Cm.col.p, Cm.val.p, deferred);
   } else {
     k_spgemm<256, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 0,
-                                            192, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p, ub.p, -1);
+                                            192, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, deferred, ub.p, -1);
     k_spgemm<512, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 193,
-                                            384, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p, ub.p, -1);
+                                            384, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, deferred, ub.p, -1);
   }
   k_spgemm<TS, true><<<gridL, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p, 385,
-                                         TS * 3 / 4, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p, ub.p, -1);
+                                         TS * 3 / 4, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, deferred, ub.p, -1);
   k_spgemm<TL, true><<<gridL, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p, cnt.p,
-                                         TS * 3 / 4 + 1, TL * 3 / 4, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, flag.p,
+                                         TS * 3 / 4 + 1, TL * 3 / 4, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, deferred,
                                          ub.p, -1);
   HIP_LAUNCH_CHECK();
-  HIP_CHECK(hipMemcpyAsync(&fl, flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
-  if (fl) fail(HFSI_E_CAPACITY, "sparse product: a row has more than 6144 entries or overflowed its table");
 }
 
 void smoother_data(hfsi_ctx* c, Level& L, const hfsi_amg_params& prm, int level) {
@@ -1583,6 +1602,7 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
     ~AuxJoin() { (void)hipStreamSynchronize(c->aux); }
   } aux_join{c};
   H.lmax_dev.ensure(32);
+  H.setup_flags.zero(1, s);
   int rounds_total = 0;
   DevBuf<int> lam, notmax, flag, rem;
   DevBuf<uint64_t> key;
@@ -1696,11 +1716,11 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
     transpose(c, L.P, L.R);
     // Galerkin product
     Csr<double> AP;
-    spgemm(c, L.A, L.P, AP);
+    spgemm(c, L.A, L.P, AP, H.setup_flags.p);
     H.L.emplace_back();
     Level& Lc = H.L.back();
     Level& Lf = H.L[l];  // reference may move with emplace_back
-    spgemm(c, Lf.R, AP, Lc.A);
+    spgemm(c, Lf.R, AP, Lc.A, H.setup_flags.p);
     Lc.n = nc;
     Lc.comp.ensure(nc);
     k_coarse_comp<<<div_up(n, 256), 256, 0, s>>>(n, Lf.state.p, Lf.cidx.p, Lf.comp.p, Lc.comp.p);
@@ -1760,10 +1780,12 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
   HIP_CHECK(hipStreamWaitEvent(s, c->aev[1], 0));
   const int nl = (int)H.L.size();
   double lm[32] = {0};
-  int sg = 0;
+  int sg = 0, sf = 0;
   HIP_CHECK(hipMemcpyAsync(&sg, sing.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(&sf, H.setup_flags.p, sizeof(int), hipMemcpyDeviceToHost, s));
   if (prm.smoother == 1) HIP_CHECK(hipMemcpyAsync(lm, H.lmax_dev.p, sizeof(double) * nl, hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipStreamSynchronize(s));
+  if (sf) fail(HFSI_E_CAPACITY, "sparse product: a row has more than 6144 entries or overflowed its table");
   if (sg) fail(HFSI_E_BREAKDOWN, "coarsest AMG operator is singular");
   for (int l = 0; l < nl; ++l) H.L[l].lmax = prm.smoother == 1 ? lm[l] : 0.0;
   H.ready = true;

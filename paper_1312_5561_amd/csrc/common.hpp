@@ -193,6 +193,7 @@ struct Hierarchy {
   int nc = 0;                 // coarsest size
   DevBuf<double> coarse_inv;  // explicit inverse of the coarsest operator
   DevBuf<double> lmax_dev;    // per-level eigenvalue estimates (written on the aux stream)
+  DevBuf<int> setup_flags;    // numeric sparse-product overflow, read with the estimates
   int precision = 0;
   int smoother = 0;
   int nu_pre = 1, nu_post = 1;  // level 0: sweeps before / after the correction
