@@ -444,7 +444,8 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
     double den_g = 0.0;
     double* part = s_part[g][grp];
     f_neighbours([&](int k, double a_ik, int klo, int khi) {
-      double akk = 0.0, s_neg = 0.0, s_pos = 0.0, ki_neg = 0.0, ki_pos = 0.0;
+      double akk = 0.0, s_neg = 0.0, s_pos = 0.0, aki = 0.0;
+      bool has_kk = false, has_ki = false;
       int c_r[XQ];  // this lane's entries of row k: rank in Chat_i (or -1) and value
       double c_v[XQ];
 #pragma unroll
@@ -456,7 +457,10 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
       for (int f = klo + sl; f < khi; f += SUB, ++q) {
         const int mm = col[f];
         const double v = val[f];
-        if (mm == k) akk = v;
+        if (mm == k) {
+          akk = v;
+          has_kk = true;
+        }
         const int r = mm == i ? -1 : rank_of(mm);
 #pragma unroll
         for (int u = 0; u < XQ; ++u)
@@ -469,17 +473,21 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
           else if (v > 0.0) s_pos += v;
         }
         if (mm == i) {
-          if (v < 0.0) ki_neg = v;
-          else ki_pos = v;
+          aki = v;
+          has_ki = true;
         }
       }
+      // a_kk and a_ki sit in one lane each of the group: broadcast them; the
+      // two signed sums are reduced
+      unsigned long long gmask = ~0ull;
+      if constexpr (SUB < 64) gmask = ((1ull << SUB) - 1ull) << (grp * SUB);
+      const unsigned long long mkk = __ballot(has_kk) & gmask, mki = __ballot(has_ki) & gmask;
+      akk = mkk ? __shfl(akk, __ffsll(mkk) - 1, 64) : 0.0;
+      aki = mki ? __shfl(aki, __ffsll(mki) - 1, 64) : 0.0;
 #pragma unroll
       for (int o = SUB / 2; o > 0; o >>= 1) {
-        akk += __shfl_xor(akk, o, SUB);
         s_neg += __shfl_xor(s_neg, o, SUB);
         s_pos += __shfl_xor(s_pos, o, SUB);
-        ki_neg += __shfl_xor(ki_neg, o, SUB);
-        ki_pos += __shfl_xor(ki_pos, o, SUB);
       }
       const double sk = akk < 0.0 ? -1.0 : 1.0;
       const double sden = sk > 0.0 ? s_neg : s_pos;
@@ -506,8 +514,9 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
         if (r < 0) continue;
         if (v * sk < 0.0) part[r] += a_ik * v / sden;  // distinct columns: one lane per slot
       }
-      const double aki = sk > 0.0 ? ki_neg : ki_pos;
-      den_g += a_ik * aki / sden;
+      // the coupling back to i counts when its sign is opposite to a_kk's
+      const double aki_bar = aki * sk < 0.0 ? aki : 0.0;
+      den_g += a_ik * aki_bar / sden;
     });
 #pragma unroll
     for (int q = 0; q < NG; ++q) den += __shfl(den_g, q * SUB, 64);
