@@ -839,13 +839,13 @@ k_spgemm_narrow(int n, const int* __restrict__ ap, const int* __restrict__ ac, c
         }
         int jj[WB];
         double bb[WB];
-  #pragma unroll
+#pragma unroll
         for (int q = 0; q < WB; ++q)
           if (q < ql) {
             jj[q] = bc[qb + q];
             bb[q] = bv[qb + q];
           }
-  #pragma unroll
+#pragma unroll
         for (int q = 0; q < WB; ++q) {
           int h = -1;
           if (q < ql) {
@@ -958,7 +958,7 @@ k_spgemm_staged(int n, const int* __restrict__ ap, const int* __restrict__ ac, c
           len = bp[k + 1] - bp[k];
         }
         int inc = len;  // inclusive scan of len over the wave
-  #pragma unroll
+#pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
           const int y = __shfl_up(inc, o, 64);
           if (lane >= o) inc += y;
@@ -991,7 +991,7 @@ k_spgemm_staged(int n, const int* __restrict__ ap, const int* __restrict__ ac, c
       //    independent pairs per lane and step so that their loads overlap
       for (int t0 = lane; t0 < U; t0 += 256) {
         int qq[4], ee[4];
-  #pragma unroll
+#pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int t = t0 + 64 * u;
           qq[u] = -1;
@@ -1007,13 +1007,13 @@ k_spgemm_staged(int n, const int* __restrict__ ap, const int* __restrict__ ac, c
         }
         int jj[4];
         double vv[4];
-  #pragma unroll
+#pragma unroll
         for (int u = 0; u < 4; ++u)
           if (qq[u] >= 0) {
             jj[u] = bc[qq[u]];
             if (NUMERIC) vv[u] = bv[qq[u]];
           }
-  #pragma unroll
+#pragma unroll
         for (int u = 0; u < 4; ++u)
           if (qq[u] >= 0) {
             f_j[t0 + 64 * u] = jj[u];
