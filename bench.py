@@ -157,8 +157,8 @@ def cpu_baseline(workload="cube", kappa=1e4):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the multi-GPU "
-              f"partitioning is a design in DESIGN.md, not built)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the node-slab "
+              f"partitioning across GPUs is designed, not built)", file=sys.stderr)
         sys.exit(2)
     import torch
     import synth
