@@ -226,7 +226,11 @@ hfsi_status hfsi_amg_setup(hfsi_ctx* ctx, const hfsi_amg_params* prm, hfsi_amg_i
 /* Solve K x = b (device b, device x [N]; x is the initial guess on entry)
  * with FGMRES(m) right-preconditioned by P_L^{-1} = [Atilde^{-1} 0;
  * Stilde^{-1} B2 Atilde^{-1}  -Stilde^{-1}] (eq. lpre, eq. lpreschur), Atilde^{-1}
- * one V-cycle of the hierarchy.  HFSI_NOT_CONVERGED if max_iter is reached. */
+ * one V-cycle of the hierarchy; the Arnoldi basis is orthogonalised by
+ * classical Gram-Schmidt with delayed reorthogonalisation (two passes over
+ * the basis per step), all fp64; stop at ||b - K x||_2 <= tol ||b||_2 (the
+ * true residual decides after every restart cycle).  HFSI_NOT_CONVERGED if
+ * max_iter is reached. */
 hfsi_status hfsi_krylov_amg_solve(hfsi_ctx* ctx, const double* b, double* x, const hfsi_solve_params* prm,
                                   hfsi_solve_info* info);
 
