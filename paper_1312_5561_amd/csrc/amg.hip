@@ -1318,16 +1318,25 @@ __global__ void k_tridiag_max(const int* __restrict__ kp, const double* __restri
 // ----------------------------------------------- padded CSR for the cycle
 // per row: number of 4-entry chunks, smallest column, and whether the row
 // spans more than 16 bits of columns
-__global__ void k_pack_count(int n, const int* __restrict__ ptr, const int* __restrict__ col, int* __restrict__ chunks,
-                             int* __restrict__ base, int* __restrict__ wide) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+// (8 lanes per row)
+__global__ void __launch_bounds__(256)
+k_pack_count(int n, const int* __restrict__ ptr, const int* __restrict__ col, int* __restrict__ chunks,
+             int* __restrict__ base, int* __restrict__ wide) {
+  const int r = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const int lane = threadIdx.x & 7;
   if (r >= n) return;
   const int a = ptr[r], e = ptr[r + 1];
   int mn = INT_MAX, mx = INT_MIN;
-  for (int k = a; k < e; ++k) {
+  for (int k = a + lane; k < e; k += 8) {
     mn = min(mn, col[k]);
     mx = max(mx, col[k]);
   }
+#pragma unroll
+  for (int o = 4; o > 0; o >>= 1) {
+    mn = min(mn, __shfl_xor(mn, o, 8));
+    mx = max(mx, __shfl_xor(mx, o, 8));
+  }
+  if (lane != 0) return;
   chunks[r] = (e - a + 3) / 4;
   base[r] = e > a ? mn : 0;
   if (e > a && mx - mn > 65535) atomicOr(wide, 1);
@@ -1527,7 +1536,7 @@ void pack_level(hfsi_ctx* c, Level& L, int precision) {
   K.base.ensure(n);
   DevBuf<int> wide;
   wide.zero(1, s);
-  k_pack_count<<<div_up(n, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, K.p4.p, K.base.p, wide.p);
+  k_pack_count<<<div_up((long)n * 8, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, K.p4.p, K.base.p, wide.p);
   HIP_LAUNCH_CHECK();
   HIP_CHECK(hipMemsetAsync(K.p4.p + n, 0, sizeof(int), s));
   int w = 0;  // read in the scan's wait
