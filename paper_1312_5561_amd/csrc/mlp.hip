@@ -69,11 +69,10 @@ __global__ void k_features(int ns, const int* __restrict__ rows, const int* __re
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= ns) return;
   const int i = rows[m], ni = i / 3, c = comp[i];
+  // X, mask and wcl arrive zeroed: only the non-zero entries are written
   float* x = X + (size_t)m * NIN;
   float* mk = mask + (size_t)m * NOUTP;
   float* w = wcl + (size_t)m * NOUTP;
-  for (int t = 0; t < NIN; ++t) x[t] = 0.f;
-  for (int t = 0; t < NOUTP; ++t) { mk[t] = 0.f; w[t] = 0.f; }
   double aii = 0.0;
   for (int e = ap[i]; e < ap[i + 1]; ++e)
     if (ac[e] == i) aii = av[e];
@@ -461,6 +460,9 @@ static void build_samples(hfsi_ctx* c, Level& L, Samples& S) {
   k_c2f<<<div_up(n, 256), 256, 0, s>>>(n, L.state.p, L.cidx.p, S.c2f.p);
   HIP_LAUNCH_CHECK();
   if (S.ns > 0) {
+    HIP_CHECK(hipMemsetAsync(S.X.p, 0, sizeof(float) * (size_t)S.ns * NIN, s));
+    HIP_CHECK(hipMemsetAsync(S.mask.p, 0, sizeof(float) * (size_t)S.ns * NOUTP, s));
+    HIP_CHECK(hipMemsetAsync(S.wcl.p, 0, sizeof(float) * (size_t)S.ns * NOUTP, s));
     k_features<<<div_up(S.ns, 128), 128, 0, s>>>(S.ns, S.rows.p, L.A.ptr.p, L.A.col.p, L.A.val.p, L.comp.p, S.c2f.p,
                                                  L.P.ptr.p, L.P.col.p, L.P.val.p, c->lattice.p, mf[0], mf[1], mf[2],
                                                  S.X.p, S.mask.p, S.wcl.p, S.pslot.p);
