@@ -109,13 +109,19 @@ __global__ void k_pmis_mark_c(int n, int* __restrict__ notmax, int8_t* __restric
 __global__ void __launch_bounds__(256)
 k_pmis_mark_f(int n, const int* __restrict__ ptr, const int* __restrict__ col, const uint8_t* __restrict__ strong,
               int8_t* __restrict__ state, int* __restrict__ remaining) {
-  const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  // rows grid-strided; *remaining becomes non-zero if some row stays
+  // undecided (one atomic per block: many atomics on one address serialise)
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
   const int lane = threadIdx.x & 7;
-  bool left = false;  // row i stays undecided (counted once per wavefront)
-  if (i < n && state[i] == ST_U) {
+  const long groups = ((long)gridDim.x * blockDim.x) >> 3;
+  bool left = false;
+  for (long i = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 3; i < n; i += groups) {
+    if (state[i] != ST_U) continue;  // the 8 lanes of a row move together
     const int hi = ptr[i + 1];
     int found = 0;
-    for (int b = ptr[i]; b < hi && !found; b += 8) {  // the 8 lanes leave together
+    for (int b = ptr[i]; b < hi && !found; b += 8) {
       const int e = b + lane;
       found = e < hi && strong[e] && state[col[e]] == ST_C ? 1 : 0;
 #pragma unroll
@@ -126,8 +132,9 @@ k_pmis_mark_f(int n, const int* __restrict__ ptr, const int* __restrict__ col, c
       else left = true;
     }
   }
-  const unsigned long long lm = __ballot(left);
-  if ((threadIdx.x & 63) == 0 && lm) atomicAdd(remaining, __popcll(lm));
+  if (left) any = 1;
+  __syncthreads();
+  if (threadIdx.x == 0 && any) atomicOr(remaining, 1);
 }
 
 __global__ void k_is_c(int n, const int8_t* __restrict__ state, int* __restrict__ flag) {
@@ -772,12 +779,17 @@ k_spgemm(int n, const int* __restrict__ ap, const int* __restrict__ ac, const do
 }
 
 // largest row length of B (wave maximum, one atomic per wavefront)
-__global__ void k_max_rowlen(int n, const int* __restrict__ ptr, int* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int len = i < n ? ptr[i + 1] - ptr[i] : 0;
+// (rows grid-strided, one atomic per block)
+__global__ void __launch_bounds__(256) k_max_rowlen(int n, const int* __restrict__ ptr, int* __restrict__ out) {
+  __shared__ int red[4];
+  int len = 0;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256)
+    len = max(len, ptr[i + 1] - ptr[i]);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) len = max(len, __shfl_xor(len, o, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(out, len);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = len;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(out, max(max(red[0], red[1]), max(red[2], red[3])));
 }
 
 // Numeric rows of C = A B when no row of B has more than WB entries (B an
@@ -1459,7 +1471,7 @@ void spgemm(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>
   flag.zero(2, s);  // [0] overflow bits, [1] longest row of B
   k_spgemm_ub<<<div_up((long)n * 8, 256), 256, 0, s>>>(n, A.ptr.p, A.col.p, B.ptr.p, ub.p);
   HIP_LAUNCH_CHECK();
-  k_max_rowlen<<<div_up(B.rows, 256), 256, 0, s>>>(B.rows, B.ptr.p, flag.p + 1);
+  k_max_rowlen<<<std::min(div_up(B.rows, 256), 1024), 256, 0, s>>>(B.rows, B.ptr.p, flag.p + 1);
   HIP_LAUNCH_CHECK();
   constexpr int TS = 2048, TL = 8192, S1 = 512, S2 = 1024;
   const int grid = std::min(n, 1 << 16);
@@ -1643,7 +1655,7 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
     L.state.ensure(n);
     k_pmis_init<<<div_up(n, 256), 256, 0, s>>>(n, lam.p, prm.seed, l, key.p, L.state.p);
     HIP_LAUNCH_CHECK();
-    // PMIS rounds, PMIS_BATCH per host read of the undecided counts; rounds
+    // PMIS rounds, PMIS_BATCH per host read of the undecided flags; rounds
     // after the last undecided point is gone change nothing
     notmax.zero(n, s);
     for (int round = 0;; round += PMIS_BATCH) {
@@ -1654,7 +1666,8 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
         HIP_LAUNCH_CHECK();
         k_pmis_mark_c<<<div_up(n, 256), 256, 0, s>>>(n, notmax.p, L.state.p);
         HIP_LAUNCH_CHECK();
-        k_pmis_mark_f<<<div_up((long)n * 8, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.strong.p, L.state.p, rem.p + k);
+        k_pmis_mark_f<<<std::min(div_up((long)n * 8, 256), 2048), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.strong.p,
+                                                                               L.state.p, rem.p + k);
         HIP_LAUNCH_CHECK();
       }
       int left[PMIS_BATCH];

@@ -192,7 +192,10 @@ k_element(int e0, int e1, int m, const int* __restrict__ T, const int* __restric
     atomicMin(inverted, e);
     return;
   }
-  atomicMin(minJ, (unsigned long long)__double_as_longlong(Jd));
+  // smallest J: the atomic only when J is below the value already recorded
+  // (many atomics on one address serialise)
+  const unsigned long long jbits = (unsigned long long)__double_as_longlong(Jd);
+  if (jbits < __hip_atomic_load(minJ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(minJ, jbits);
   const double iJ = 1.0 / Jd;
   double Fi[3][3];
   Fi[0][0] = c00 * iJ;
