@@ -123,3 +123,24 @@ def test_capacity_and_order_errors(lib):
     assert e.value.code == -4
     with pytest.raises(lib.HfsiError):
         ctx.amg_setup_csr(np.array([0, 1]), np.array([5]), np.array([1.0]), np.array([0]))
+
+
+def test_failed_setup_then_valid_setup(lib):
+    """A set-up that fails after work was queued on the second stream (the
+    coarsest level exceeds 4096 rows with max_levels = 1) leaves the context
+    usable: the next set-up and solve on it succeed."""
+    import torch
+    prob = synth.cube_problem(12)
+    ctx = context_for(lib, prob)
+    v = torch.zeros(prob.n_dofs, dtype=torch.float64, device="cuda")
+    R = torch.zeros_like(v)
+    ctx.assemble_residual_tangent(v, 1.0, R)
+    with pytest.raises(lib.HfsiError) as e:
+        ctx.amg_setup(lib.amg_params(smoother=1, precision=1, max_levels=1))
+    assert e.value.code == -8 and "4096" in str(e.value)
+    info = ctx.amg_setup(lib.amg_params(smoother=1, precision=1))
+    assert info.levels >= 2
+    x = torch.zeros_like(R)
+    si, code = ctx.krylov_amg_solve(-R, x, lib.solve_params(tol=1e-8, restart=100, max_iter=500))
+    assert code == 0 and si.converged
+
