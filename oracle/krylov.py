@@ -1,4 +1,4 @@
-"""Block-triangular preconditioner and FGMRES (oracle).
+"""Block-triangular preconditioner, FGMRES and BiCGStab (oracle).
 
 The preconditioner is the paper's P_L (eq. lpre): with K = [A B1^T; B2 -C],
     P_L^{-1} [r_u; r_p] = [z_u; z_p],  z_u = Atilde^{-1} r_u,
@@ -136,3 +136,72 @@ def fgmres(K, precond, b, x0=None, m=50, maxit=500, tol=1e-8):
             break
         info.restarts += 1
     return x, info
+
+
+def bicgstab(K, precond, b, x0=None, maxit=500, tol=1e-8):
+    """Solve K x = b with right-preconditioned BiCGStab, the Krylov method of
+    the paper's structure sub-problem (section "A preconditioner for the
+    structure sub-problem"; van der Vorst's BiCGStab), preconditioner M^{-1}.
+
+    Shadow residual r^ = r_0.  One iteration: rho = r^.r;
+    p = r + (rho / rho_old)(alpha / omega)(p - omega v) (p = r at the
+    start); p^ = M^{-1} p, v = K p^, alpha = rho / r^.v; s = r - alpha v;
+    s^ = M^{-1} s, t = K s^, omega = t.s / t.t (0 when t = 0); x += alpha p^ +
+    omega s^, r = s - omega t.  The updated residual ends the iteration loop
+    at ||r|| <= tol ||b||; the true residual then decides, and the method
+    starts again from it (new shadow) if it is still above the tolerance.
+    Breakdown when r^.r or r^.v vanishes, or omega = 0 before convergence.
+    """
+    n = b.shape[0]
+    x = np.zeros(n) if x0 is None else x0.copy()
+    info = SolveInfo()
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        x[:] = 0.0
+        info.rel_residual, info.converged = 0.0, True
+        return x, info
+    r = b - K @ x
+    info.rel_residual = np.linalg.norm(r) / bnorm
+    while info.rel_residual > tol and info.iterations < maxit and not info.breakdown:
+        rhat = r.copy()
+        rho_old = alpha = omega = 1.0
+        p = np.zeros(n)
+        v = np.zeros(n)
+        first = True
+        while info.iterations < maxit:
+            rho = rhat @ r
+            if rho == 0.0:
+                info.breakdown = True
+                break
+            p = r.copy() if first else r + (rho / rho_old) * (alpha / omega) * (p - omega * v)
+            first = False
+            ph = precond(p)
+            v = K @ ph
+            rv = rhat @ v
+            if rv == 0.0:
+                info.breakdown = True
+                break
+            alpha = rho / rv
+            s = r - alpha * v
+            sh = precond(s)
+            t = K @ sh
+            tt = t @ t
+            omega = (t @ s) / tt if tt > 0.0 else 0.0
+            x = x + alpha * ph + omega * sh
+            r = s - omega * t
+            rho_old = rho
+            info.iterations += 1
+            rel = np.linalg.norm(r) / bnorm
+            info.history.append(rel)
+            if rel <= tol:
+                break
+            if omega == 0.0:
+                info.breakdown = True
+                break
+        r = b - K @ x
+        info.rel_residual = np.linalg.norm(r) / bnorm
+        if info.rel_residual > tol and not info.breakdown and info.iterations < maxit:
+            info.restarts += 1
+    info.converged = info.rel_residual <= tol
+    return x, info
+

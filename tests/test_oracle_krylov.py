@@ -6,7 +6,12 @@
   preconditioner of eq. lpre makes P_L^{-1} K block upper triangular with
   identity diagonal blocks, so FGMRES converges in two iterations;
 * the AMG-preconditioned solve reaches the requested true relative
-  residual and agrees with the direct solution.
+  residual and agrees with the direct solution;
+* BiCGStab: with the identity preconditioner it reproduces the dense solve;
+  on a matrix with two distinct eigenvalues (and with the exact block
+  preconditioner, whose preconditioned operator has minimal polynomial
+  (z - 1)^2) it converges in at most two iterations; AMG-preconditioned it
+  reaches the requested true residual.
 """
 import numpy as np
 import pytest
@@ -74,3 +79,56 @@ def test_arnoldi_relation_holds():
     x, info = krylov.fgmres(K, prec, b, m=8, maxit=8, tol=1e-30)
     assert info.iterations == 8
     assert info.history == sorted(info.history, reverse=True)   # residual never grows
+
+
+@pytest.mark.parametrize("N", [1, 2])
+def test_bicgstab_identity_matches_dense_solve(N):
+    d, K, b, *_ = _system(N)
+    x_ref = np.linalg.solve(K.toarray(), b)
+    x, info = krylov.bicgstab(K, lambda r: r.copy(), b, maxit=5000, tol=1e-12)
+    assert info.converged
+    assert np.linalg.norm(x - x_ref) <= 1e-8 * np.linalg.norm(x_ref)
+
+
+def test_bicgstab_two_eigenvalues_two_iterations():
+    import scipy.sparse as sp
+    rng = np.random.default_rng(3)
+    diag = np.where(rng.uniform(size=40) < 0.5, 2.0, 7.0)
+    K = sp.diags(diag).tocsr()
+    b = rng.normal(size=40)
+    x, info = krylov.bicgstab(K, lambda r: r.copy(), b, tol=1e-12)
+    assert info.converged and info.iterations <= 2
+    assert np.allclose(x, b / diag, rtol=1e-12)
+
+
+def test_bicgstab_exact_block_preconditioner_two_iterations():
+    d, K, b, A, B2, s = _system(2)
+    n = d.n
+    Kd = K.toarray()
+    u = np.array([4 * i + c for i in range(n) for c in range(3)])
+    pp = 4 * np.arange(n) + 3
+    Ad = Kd[np.ix_(u, u)]
+    B1T = Kd[np.ix_(u, pp)]
+    B2d = Kd[np.ix_(pp, u)]
+    Cd = -Kd[np.ix_(pp, pp)]
+    Sd = B2d @ np.linalg.solve(Ad, B1T) + Cd
+
+    def prec(r):
+        ru, rp = krylov.split(r, n)
+        zu = np.linalg.solve(Ad, ru)
+        zp = np.linalg.solve(Sd, B2d @ zu - rp)
+        return krylov.join(zu, zp, n)
+
+    x, info = krylov.bicgstab(K, prec, b, tol=1e-10)
+    assert info.converged and info.iterations <= 2
+
+
+def test_bicgstab_amg_preconditioned_solve():
+    d, K, b, A, B2, s = _system(4)
+    M, H = krylov.amg_preconditioner(A, B2, s, d.n, amg.AmgParams(max_coarse=60))
+    x, info = krylov.bicgstab(K, M, b, tol=1e-10)
+    assert info.converged
+    assert np.linalg.norm(b - K @ x) <= 1e-10 * np.linalg.norm(b)
+    x_ref = np.linalg.solve(K.toarray(), b)
+    assert np.linalg.norm(x - x_ref) <= 1e-6 * np.linalg.norm(x_ref)
+
