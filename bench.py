@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--kappa", type=float, default=None, help="bulk modulus (cube 1e4, tube 1e5)")
     ap.add_argument("--smoother", type=int, default=1, help="0 l1-Jacobi, 1 Chebyshev")
     ap.add_argument("--restart", type=int, default=256)
+    ap.add_argument("--krylov", choices=("fgmres", "bicgstab"), default="fgmres",
+                    help="Krylov method (BiCGStab: the paper's, two V-cycles per iteration)")
     ap.add_argument("--max-iter", type=int, default=3000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain fp64 comparison")
@@ -178,7 +180,8 @@ def main():
     ctx = hfsi.Context(0)
     ctx.set_problem(prob)
     v = torch.zeros(ndofs, dtype=torch.float64, device="cuda")
-    sp = hfsi.solve_params(tol=1e-8, restart=args.restart, max_iter=args.max_iter)
+    sp = hfsi.solve_params(tol=1e-8, restart=args.restart, max_iter=args.max_iter,
+                           method=1 if args.krylov == "bicgstab" else 0)
     learned = args.interp == "learned"
     if learned:
         from paper_1312_5561_amd import train_mlp
@@ -270,7 +273,9 @@ def main():
         "dtype": "f64 (fp32 V-cycle)",
         "data": "synthetic",
         "config": {"workload": wname, "dofs": ndofs,
-                   "interp": args.interp, "precision": "fp32 V-cycle in fp64 FGMRES", "restart": args.restart,
+                   "interp": args.interp, "krylov": args.krylov,
+                   "precision": f"fp32 V-cycle in fp64 {'FGMRES' if args.krylov == 'fgmres' else 'BiCGStab'}",
+                   "restart": args.restart,
                    "smoother": "l1-Jacobi" if args.smoother == 0 else "Chebyshev"},
         "breakdown": summarize(inf_main),
         **({"judge": judge} if judge else {}),

@@ -147,8 +147,12 @@ typedef struct {
 typedef struct {
   size_t struct_size;
   double tol;           /* relative residual ||b-Kx||/||b||, default 1e-8   */
-  int32_t restart;      /* m, default 50                                   */
+  int32_t restart;      /* m, default 50 (FGMRES)                          */
   int32_t max_iter;     /* default 500                                     */
+  int32_t method;       /* 0 = FGMRES(m) (default), 1 = BiCGStab, the
+                           paper's Krylov method for the structure
+                           sub-problem (right preconditioning; restart
+                           unused)                                         */
 } hfsi_solve_params;
 
 typedef struct {

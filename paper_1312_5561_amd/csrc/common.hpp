@@ -295,6 +295,9 @@ void precond_apply(hfsi_ctx* c, const double* r, double* z, const double* scale 
 void tangent_apply(hfsi_ctx* c, const double* x, double* y);
 void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_params& prm,
                   hfsi_solve_info* info);
+// BiCGStab with the same preconditioner; krylov_solve picks by prm.method
+void bicgstab_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_params& prm, hfsi_solve_info* info);
+void krylov_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_params& prm, hfsi_solve_info* info);
 double mass_norm(hfsi_ctx* c, const double* dv);
 // learned interpolation: correct level-0 P in place; free the state
 void learned_correction(hfsi_ctx* c, Level& L);

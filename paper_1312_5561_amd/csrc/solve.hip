@@ -1089,6 +1089,212 @@ void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_para
   if (breakdown && !converged) fail(HFSI_E_BREAKDOWN, "FGMRES breakdown before convergence");
 }
 
+namespace {
+// ---- BiCGStab (right preconditioning).  Device scalars bs[]: 0 rho,
+// 1 alpha, 2 omega, 3 beta, 4 r^.v, 5 t.s, 6 t.t, 7 r.r, 8 r^.r (new rho).
+
+// partial sums of x1.y1 and x2.y2 (x2 may be null) per block
+__global__ void __launch_bounds__(256)
+k_dot2_part(long N, const double* __restrict__ x1, const double* __restrict__ y1, const double* __restrict__ x2,
+            const double* __restrict__ y2, double* __restrict__ part) {
+  __shared__ double sh[2][4];
+  double a = 0.0, c = 0.0;
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long)gridDim.x * 256) {
+    a += x1[e] * y1[e];
+    if (x2) c += x2[e] * y2[e];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    c += __shfl_xor(c, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = a;
+    sh[1][threadIdx.x >> 6] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+    part[gridDim.x + blockIdx.x] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+  }
+}
+
+// reduce the two partial rows into bs[i1], bs[i2] (i2 < 0: one row), then
+// step: 0 alpha = rho / r^.v; 1 omega = t.s / t.t (0 if t = 0); 2 beta for
+// the next direction, rho <- r^.r; 3 nothing
+__global__ void __launch_bounds__(256)
+k_bicg_scalars(int nb, const double* __restrict__ part, double* __restrict__ bs, int i1, int i2, int step) {
+  __shared__ double r1[256], r2[256];
+  double a = 0.0, c = 0.0;
+  for (int t = threadIdx.x; t < nb; t += 256) {
+    a += part[t];
+    c += part[nb + t];
+  }
+  r1[threadIdx.x] = a;
+  r2[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      r1[threadIdx.x] += r1[threadIdx.x + o];
+      r2[threadIdx.x] += r2[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  bs[i1] = r1[0];
+  if (i2 >= 0) bs[i2] = r2[0];
+  if (step == 0) bs[1] = bs[0] / bs[4];
+  else if (step == 1) bs[2] = bs[6] > 0.0 ? bs[5] / bs[6] : 0.0;
+  else if (step == 2) {
+    bs[3] = (bs[8] / bs[0]) * (bs[1] / bs[2]);
+    bs[0] = bs[8];
+  }
+}
+
+// p = r + beta (p - omega v), or p = r on the first step
+__global__ void k_bicg_dir(long N, const double* __restrict__ r, const double* __restrict__ v,
+                           const double* __restrict__ bs, int first, double* __restrict__ p) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= N) return;
+  p[e] = first ? r[e] : r[e] + bs[3] * (p[e] - bs[2] * v[e]);
+}
+
+// s = r - alpha v
+__global__ void k_bicg_s(long N, const double* __restrict__ r, const double* __restrict__ v,
+                         const double* __restrict__ bs, double* __restrict__ s) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e < N) s[e] = r[e] - bs[1] * v[e];
+}
+
+// x += alpha p^ + omega s^, r = s - omega t, with the partial r^.r and r.r
+__global__ void __launch_bounds__(256)
+k_bicg_update(long N, const double* __restrict__ ph, const double* __restrict__ sh, const double* __restrict__ s,
+              const double* __restrict__ t, const double* __restrict__ rhat, const double* __restrict__ bs,
+              double* __restrict__ x, double* __restrict__ r, double* __restrict__ part) {
+  __shared__ double red[2][4];
+  const double alpha = bs[1], omega = bs[2];
+  double a = 0.0, c = 0.0;
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long)gridDim.x * 256) {
+    x[e] += alpha * ph[e] + omega * sh[e];
+    const double rn = s[e] - omega * t[e];
+    r[e] = rn;
+    a += rhat[e] * rn;
+    c += rn * rn;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    c += __shfl_xor(c, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = a;
+    red[1][threadIdx.x >> 6] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    part[gridDim.x + blockIdx.x] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+}  // namespace
+
+// BiCGStab with P_L^{-1} as right preconditioner (section "A preconditioner
+// for the structure sub-problem"): two preconditioner applications and two
+// tangent products per iteration; the updated residual norm is read back
+// after every iteration; the true residual decides convergence, and the
+// method starts again from it (new shadow residual) while it is above the
+// tolerance.
+void bicgstab_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_params& prm, hfsi_solve_info* info) {
+  const long N = 4L * c->n;
+  const long ld = (N + 31) / 32 * 32;
+  hipStream_t s = c->stream;
+  c->kv.ensure((size_t)8 * ld);
+  c->kr.ensure(N);
+  c->kred.ensure(2 * RED_BLOCKS);
+  c->scal.ensure(16);
+  double* W = c->kv.p;
+  double *r = W, *rhat = W + ld, *p = W + 2 * ld, *v = W + 3 * ld, *sv = W + 4 * ld, *t = W + 5 * ld,
+         *ph = W + 6 * ld, *sh = W + 7 * ld;
+  c->kh.ensure(16);
+  double* bs = c->kh.p;
+  double* part = c->kred.p;
+  const int gN = div_up(N, 256);
+  double* sc = c->scal.p;
+  HIP_CHECK(hipEventRecord(c->ev0, s));
+  norm_dev(c, b, N, sc + 0);
+  const double bnorm = read_scalar(c, sc + 0);
+  int its = 0, restarts = 0;
+  bool converged = false, breakdown = false;
+  double rel = 0.0;
+  if (bnorm == 0.0) {
+    HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * N, s));
+    converged = true;
+  } else {
+    residual(c, b, x, r);
+    norm_dev(c, r, N, sc + 1);
+    rel = read_scalar(c, sc + 1) / bnorm;
+    converged = rel <= prm.tol;
+    while (!converged && !breakdown && its < prm.max_iter) {
+      // a fresh start: shadow r^ = r, rho = r^.r
+      HIP_CHECK(hipMemcpyAsync(rhat, r, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+      k_dot2_part<<<RED_BLOCKS, 256, 0, s>>>(N, rhat, r, nullptr, nullptr, part);
+      k_bicg_scalars<<<1, 256, 0, s>>>(RED_BLOCKS, part, bs, 0, -1, 3);
+      HIP_LAUNCH_CHECK();
+      bool first = true;
+      while (its < prm.max_iter) {
+        k_bicg_dir<<<gN, 256, 0, s>>>(N, r, v, bs, first ? 1 : 0, p);
+        HIP_LAUNCH_CHECK();
+        first = false;
+        precond_apply(c, p, ph);
+        tangent_apply(c, ph, v);
+        k_dot2_part<<<RED_BLOCKS, 256, 0, s>>>(N, rhat, v, nullptr, nullptr, part);
+        k_bicg_scalars<<<1, 256, 0, s>>>(RED_BLOCKS, part, bs, 4, -1, 0);  // alpha
+        k_bicg_s<<<gN, 256, 0, s>>>(N, r, v, bs, sv);
+        HIP_LAUNCH_CHECK();
+        precond_apply(c, sv, sh);
+        tangent_apply(c, sh, t);
+        k_dot2_part<<<RED_BLOCKS, 256, 0, s>>>(N, t, sv, t, t, part);
+        k_bicg_scalars<<<1, 256, 0, s>>>(RED_BLOCKS, part, bs, 5, 6, 1);  // omega
+        k_bicg_update<<<RED_BLOCKS, 256, 0, s>>>(N, ph, sh, sv, t, rhat, bs, x, r, part);
+        k_bicg_scalars<<<1, 256, 0, s>>>(RED_BLOCKS, part, bs, 8, 7, 2);  // beta, rho
+        HIP_LAUNCH_CHECK();
+        HIP_CHECK(hipMemcpyAsync(c->pinned, bs, 9 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        ++its;
+        const double* q = c->pinned;
+        const double rr = q[7], rv = q[4], omega = q[2], rho = q[0];
+        if (!std::isfinite(rr)) fail(HFSI_E_NAN, "BiCGStab: non-finite residual");
+        if (std::sqrt(rr) <= prm.tol * bnorm) break;
+        if (rv == 0.0 || omega == 0.0 || rho == 0.0) {
+          breakdown = true;
+          break;
+        }
+      }
+      residual(c, b, x, r);
+      norm_dev(c, r, N, sc + 1);
+      rel = read_scalar(c, sc + 1) / bnorm;
+      if (!std::isfinite(rel)) fail(HFSI_E_NAN, "BiCGStab: non-finite residual");
+      converged = rel <= prm.tol;
+      if (!converged && !breakdown && its < prm.max_iter) ++restarts;
+    }
+  }
+  HIP_CHECK(hipEventRecord(c->ev1, s));
+  if (info) {
+    info->iterations = its;
+    info->restarts = restarts;
+    info->rel_residual = rel;
+    info->converged = converged ? 1 : 0;
+    info->breakdown = breakdown ? 1 : 0;
+    info->seconds = elapsed_ms(c) * 1e-3;
+  }
+  if (breakdown && !converged) fail(HFSI_E_BREAKDOWN, "BiCGStab breakdown before convergence");
+}
+
+void krylov_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_params& prm, hfsi_solve_info* info) {
+  if (prm.method == 1) bicgstab_solve(c, b, x, prm, info);
+  else fgmres_solve(c, b, x, prm, info);
+}
+
 }  // namespace hfsi
 
 namespace {
@@ -1096,6 +1302,7 @@ void check_solve_params(const hfsi_solve_params* p) {
   if (!p || p->struct_size != sizeof(hfsi_solve_params)) fail(HFSI_E_ARG, "solve params: struct_size mismatch");
   if (!(p->tol > 0) || p->restart < 1 || p->restart > 256 || p->max_iter < 1)
     fail(HFSI_E_ARG, "solve params: need tol > 0, 1 <= restart <= 256, max_iter >= 1");
+  if (p->method < 0 || p->method > 1) fail(HFSI_E_ARG, "solve params: method 0 (FGMRES) or 1 (BiCGStab)");
 }
 }  // namespace
 
@@ -1198,7 +1405,7 @@ extern "C" hfsi_status hfsi_krylov_amg_solve(hfsi_ctx* c, const double* b, doubl
   if (info && info->struct_size != sizeof(hfsi_solve_info)) fail(HFSI_E_ARG, "solve info: struct_size mismatch");
   hfsi_solve_info tmp{sizeof(hfsi_solve_info)};
   hfsi_solve_info* inf = info ? info : &tmp;
-  hfsi::fgmres_solve(c, b, x, *prm, inf);
+  hfsi::krylov_solve(c, b, x, *prm, inf);
   if (!inf->converged) return HFSI_NOT_CONVERGED;
   HFSI_ABI_END(c)
 }
@@ -1411,7 +1618,7 @@ extern "C" hfsi_status hfsi_newton_step(hfsi_ctx* c, double* v, double load, con
   HIP_LAUNCH_CHECK();
   HIP_CHECK(hipMemsetAsync(c->kdv.p, 0, sizeof(double) * N, s));
   hfsi_solve_info si{sizeof(hfsi_solve_info)};
-  hfsi::fgmres_solve(c, c->ktmp.p, c->kdv.p, prm->solve, &si);
+  hfsi::krylov_solve(c, c->ktmp.p, c->kdv.p, prm->solve, &si);
   k_axpy<<<div_up(N, 256), 256, 0, s>>>(N, 1.0, c->kdv.p, v);
   HIP_LAUNCH_CHECK();
   const double dvm = hfsi::mass_norm(c, c->kdv.p);

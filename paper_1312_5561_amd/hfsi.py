@@ -60,7 +60,7 @@ class AmgInfo(C.Structure):
 
 class SolveParams(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("tol", C.c_double), ("restart", C.c_int32),
-                ("max_iter", C.c_int32)]
+                ("max_iter", C.c_int32), ("method", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -105,8 +105,9 @@ def amg_params(theta=0.15, max_coarse=500, max_levels=25, seed=12345, smoother=1
                      nu_post_coarse, cheb_degree_coarse, nu_pre_coarse)
 
 
-def solve_params(tol=1e-8, restart=50, max_iter=500):
-    return SolveParams(C.sizeof(SolveParams), tol, restart, max_iter)
+def solve_params(tol=1e-8, restart=50, max_iter=500, method=0):
+    """method: 0 FGMRES(restart), 1 BiCGStab."""
+    return SolveParams(C.sizeof(SolveParams), tol, restart, max_iter, method)
 
 
 def newton_params(amg=None, solve=None):

@@ -104,6 +104,39 @@ def test_fgmres_solution(lib, precision):
     assert abs(sinfo.iterations - oinfo.iterations) <= (1 if precision == 0 else 3)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_bicgstab_solution(lib, precision):
+    """BiCGStab (method 1) with the same P_L: the direct solution to 1e-9 at
+    a 1e-12 tolerance, the true residual at 1e-8, and about as many
+    iterations as the oracle's BiCGStab with the GPU's hierarchy."""
+    import torch
+    prob = synth.cube_problem(8)
+    v = synth.random_state(prob, 8, u_scale=0.02, p_scale=0.02).ravel()
+    print(f"[bicgstab parity] precision={precision}", flush=True)
+    ctx, R, info, oprm = _setup(lib, prob, v, 0.6, smoother=1, precision=precision, schedule="default")
+    d, K, b, A, B2, s = oracle_system(prob, v, 0.6)
+    x_ref = spl.spsolve(K.tocsc(), b)
+    bt = -R
+    x = torch.zeros_like(bt)
+    sinfo, code = ctx.krylov_amg_solve(bt, x, lib.solve_params(tol=1e-12, max_iter=2000, method=1))
+    assert code == 0 and sinfo.converged
+    err = np.linalg.norm(x.cpu().numpy() - x_ref) / np.linalg.norm(x_ref)
+    assert err <= 1e-9
+    x.zero_()
+    sinfo, code = ctx.krylov_amg_solve(bt, x, lib.solve_params(tol=1e-8, method=1))
+    true_res = np.linalg.norm(b - K @ x.cpu().numpy()) / np.linalg.norm(b)
+    assert sinfo.converged and true_res <= 1e-8
+    assert abs(sinfo.rel_residual - true_res) <= 1e-10
+    H = gpu_hierarchy_to_oracle(ctx, info, oprm)
+    M = krylov.BlockPreconditioner(lambda r: amg.vcycle(H, r, oprm), B2, s, prob.n_nodes)
+    _, oinfo = krylov.bicgstab(K, M, b, tol=1e-8)
+    print(f"[bicgstab] gpu its={sinfo.iterations} oracle its={oinfo.iterations} err={err:.2e}", flush=True)
+    assert oinfo.converged
+    assert abs(sinfo.iterations - oinfo.iterations) <= (1 if precision == 0 else 3)
+    with pytest.raises(lib.HfsiError):
+        ctx.krylov_amg_solve(bt, x, lib.solve_params(method=2))
+
+
 def test_tangent_product_any_alignment(lib):
     """K x with x 32-byte aligned (wide loads) and with x at an 8-byte offset
     (the per-entry kernel) both equal the oracle tangent times x."""
