@@ -356,6 +356,28 @@ def setup(A, comp, prm: AmgParams = AmgParams()):
     return Hierarchy(levels, lu)
 
 
+def resetup(A, H: Hierarchy, prm: AmgParams = AmgParams()):
+    """Hierarchy of a new operator A (same size and component map as the
+    level-0 operator of H) on the coarse grids of H: the C/F splittings and
+    interpolations P (R = P^T) of H are kept, every coarse operator is the
+    Galerkin product of the new level above it, and the smoother data and the
+    coarsest LU are recomputed.  With A equal to H's own level-0 operator this
+    is H again."""
+    old = H.levels
+    if A.shape != old[0].A.shape:
+        raise ValueError("resetup: operator size differs from the hierarchy's")
+    levels = [Level(A.tocsr(), old[0].comp)]
+    for lev, o in enumerate(old):
+        L = levels[-1]
+        _smoother_data(L, prm, lev)
+        if o.P is None:
+            break
+        L.S, L.state, L.P, L.R = o.S, o.state, o.P, o.R
+        levels.append(Level(galerkin(L.A, o.P), old[lev + 1].comp))
+    lu = scipy.linalg.lu_factor(levels[-1].A.toarray())
+    return Hierarchy(levels, lu)
+
+
 def _smoother_data(L, prm, lev):
     if prm.smoother == "l1jacobi":
         L.dinv = 1.0 / l1_diag(L.A)

@@ -14,12 +14,17 @@
 * l1-Jacobi never increases the A-norm of the error for SPD A;
 * the Chebyshev smoother damps the extreme eigen-components by exactly
   1/T_2((b+a)/(b-a));
-* the Lanczos estimate converges to the largest eigenvalue.
+* the Lanczos estimate converges to the largest eigenvalue;
+* re-set-up on kept coarse grids: with the original operator it rebuilds
+  the hierarchy, it is covariant under scaling of the operator, and on two
+  levels its coarse correction for a new operator is the energy projection
+  onto the kept interpolation's range (which a stale coarse operator fails).
 """
 import os
 
 import numpy as np
 import pytest
+import scipy.linalg
 import scipy.sparse as sp
 
 from oracle import amg, rng
@@ -228,3 +233,70 @@ def test_lanczos_largest_eigenvalue():
     assert abs(est - true) <= 1e-10 * true
     short = amg.lanczos_max(A, d, 10, 1, 0)
     assert 0.8 * true <= short <= true * (1 + 1e-12)
+
+
+def _reuse_problem(seed=3):
+    r = np.random.default_rng(seed)
+    A = (laplacian(10, 9, 8) + sp.diags(r.uniform(0.0, 0.5, 720))).tocsr()
+    A.sort_indices()
+    # a different operator on the same pattern: positive reweighting of the
+    # off-diagonal couplings with the diagonal kept dominant
+    B = A.copy()
+    off = B.indices != np.repeat(np.arange(720), np.diff(B.indptr))
+    B.data[off] *= r.uniform(0.5, 1.5, off.sum())
+    B = B + sp.diags(r.uniform(0.0, 0.5, 720) + np.asarray(abs(B).sum(axis=1)).ravel() - 2 * B.diagonal())
+    B = B.tocsr()
+    B.sort_indices()
+    return A, B
+
+
+@pytest.mark.parametrize("smoother", ["l1jacobi", "chebyshev"])
+def test_resetup_of_the_same_operator_is_the_setup(smoother):
+    """Re-set-up with the operator the hierarchy was built from rebuilds it."""
+    A, _ = _reuse_problem()
+    prm = amg.AmgParams(max_coarse=40, smoother=smoother, nu_pre=1, nu_post=1)
+    H = amg.setup(A, np.zeros(720, np.int64), prm)
+    H2 = amg.resetup(A, H, prm)
+    assert len(H.levels) >= 3 and len(H2.levels) == len(H.levels)
+    for a, b in zip(H.levels, H2.levels):
+        assert (a.A != b.A).nnz == 0 and np.array_equal(a.dinv, b.dinv) and a.lam == b.lam
+    b = np.random.default_rng(0).standard_normal(720)
+    assert np.array_equal(amg.vcycle(H, b, prm), amg.vcycle(H2, b, prm))
+
+
+@pytest.mark.parametrize("smoother", ["l1jacobi", "chebyshev"])
+def test_resetup_is_scale_covariant(smoother):
+    """For A' = 4A every coarse operator scales by 4 and the V-cycle of A' on
+    4b equals that of A on b (both smoothers are invariant under scaling)."""
+    A, _ = _reuse_problem()
+    prm = amg.AmgParams(max_coarse=40, smoother=smoother)
+    H = amg.setup(A, np.zeros(720, np.int64), prm)
+    H4 = amg.resetup((4.0 * A).tocsr(), H, prm)
+    for a, b in zip(H.levels, H4.levels):
+        assert np.abs((b.A - 4.0 * a.A).data).max(initial=0.0) <= 1e-13 * np.abs(b.A.data).max()
+    b = np.random.default_rng(1).standard_normal(720)
+    y, y4 = amg.vcycle(H, b, prm), amg.vcycle(H4, 4.0 * b, prm)
+    assert np.abs(y4 - y).max() <= 1e-11 * np.abs(y).max()
+
+
+def test_resetup_coarse_correction_is_an_energy_projection():
+    """On two levels the exact coarse correction for the new operator B
+    leaves an error B-orthogonal to the kept interpolation's range, and the
+    reused hierarchy still preconditions B well."""
+    A, B = _reuse_problem()
+    prm = amg.AmgParams(max_coarse=400, max_levels=2)
+    H = amg.setup(A, np.zeros(720, np.int64), prm)
+    HB = amg.resetup(B, H, prm)
+    assert len(HB.levels) == 2
+    P = HB.levels[0].P
+    e = np.random.default_rng(2).standard_normal(720)
+    ec = scipy.linalg.lu_solve(HB.lu, P.T @ (B @ e))
+    e_new = e - P @ ec
+    g = P.T @ (B @ e_new)
+    assert np.abs(g).max() <= 1e-10 * np.abs(P.T @ (B @ e)).max()
+    # and the same correction with the stale coarse operator is not
+    ec_old = scipy.linalg.lu_solve(H.lu, P.T @ (B @ e))
+    assert np.abs(P.T @ (B @ (e - P @ ec_old))).max() > 1e-3 * np.abs(P.T @ (B @ e)).max()
+    prm3 = amg.AmgParams(max_coarse=40)
+    H3 = amg.resetup(B, amg.setup(A, np.zeros(720, np.int64), prm3), prm3)
+    assert amg.convergence_factor(H3, prm3) < 0.5
