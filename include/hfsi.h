@@ -169,6 +169,10 @@ typedef struct {
   size_t struct_size;
   hfsi_amg_params amg;
   hfsi_solve_params solve;
+  int32_t amg_reuse;    /* 0 = full AMG set-up every step (default); 1 =
+                           re-set-up on the coarse grids of the previous
+                           set-up of this mesh when there is one (see
+                           hfsi_amg_resetup), else a full set-up           */
 } hfsi_newton_params;
 
 typedef struct {
@@ -179,6 +183,7 @@ typedef struct {
   double rel_residual;
   double t_assemble, t_setup, t_solve, t_total;
   int32_t amg_levels;
+  int32_t amg_reused;   /* 1 if this step re-used the previous coarse grids */
 } hfsi_newton_info;
 
 /* ---------------------------------------------------------------- context */
@@ -227,6 +232,21 @@ hfsi_status hfsi_assemble_residual_tangent(hfsi_ctx* ctx, const double* v, doubl
  * mixed problems"). */
 hfsi_status hfsi_amg_setup(hfsi_ctx* ctx, const hfsi_amg_params* prm, hfsi_amg_info* info);
 
+/* Re-set-up of the hierarchy for the displacement block of the last
+ * assembly, keeping the coarse grids of the last hfsi_amg_setup (or Newton
+ * step set-up) on this mesh: its C/F splittings and interpolations P (R =
+ * P^T, the learned level-0 rows included) are kept, and only the Galerkin
+ * coarse operators R A P (as in "AMG methods for the mixed problems"), the
+ * smoother data and the coarsest inverse are recomputed.  The smoothing
+ * settings and precision come from *prm; its coarsening settings (theta,
+ * seed, interp, interp_kind, p_max, level limits) are those of the kept
+ * grids and are ignored.  No judge runs (info->rho = -1).  For a sequence of
+ * nearby tangents (Newton or time steps) this trades a slower V-cycle for a
+ * cheaper set-up.  HFSI_E_ORDER if no set-up of this mesh's tangent is
+ * available (a new mesh or boundary data, a set-up from a caller CSR, or a
+ * failed set-up discard it). */
+hfsi_status hfsi_amg_resetup(hfsi_ctx* ctx, const hfsi_amg_params* prm, hfsi_amg_info* info);
+
 /* Solve K x = b (device b, device x [N]; x is the initial guess on entry)
  * with FGMRES(m) right-preconditioned by P_L^{-1} = [Atilde^{-1} 0;
  * Stilde^{-1} B2 Atilde^{-1}  -Stilde^{-1}] (eq. lpre, eq. lpreschur), Atilde^{-1}
@@ -239,7 +259,8 @@ hfsi_status hfsi_krylov_amg_solve(hfsi_ctx* ctx, const double* b, double* x, con
                                   hfsi_solve_info* info);
 
 /* One Newton iteration at load factor `load` (Section "Newton's Method"):
- * assemble, set up AMG, solve K dv = -R, v += dv in place (device v [N]),
+ * assemble, set up AMG (or re-set it up, prm->amg_reuse), solve K dv = -R,
+ * v += dv in place (device v [N]),
  * report ||dv||_M for the stopping rule eq. newstop. */
 hfsi_status hfsi_newton_step(hfsi_ctx* ctx, double* v, double load, const hfsi_newton_params* prm,
                              hfsi_newton_info* info);

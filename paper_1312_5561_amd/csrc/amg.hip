@@ -1611,11 +1611,9 @@ __global__ void k_comp_mod3(int n, int* __restrict__ comp) {
 
 constexpr int PMIS_BATCH = 3;
 
-// Build levels 1.. from level 0 (whose A and comp are already set).
-void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {
-  hipStream_t s = c->stream;
-  Hierarchy& H = c->H;
-  H.ready = false;
+namespace {
+
+void set_schedule(Hierarchy& H, const hfsi_amg_params& prm) {
   H.precision = prm.precision;
   H.smoother = prm.smoother;
   H.nu_pre = prm.nu_pre;
@@ -1626,11 +1624,114 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
   H.cheb_degree_pre = prm.cheb_degree_pre;
   H.cheb_degree_coarse = prm.cheb_degree_coarse;
   H.cheb_ratio = prm.cheb_ratio;
-  // the Lanczos estimates run on the aux stream; joined below (and on unwind)
-  struct AuxJoin {
-    hfsi_ctx* c;
-    ~AuxJoin() { (void)hipStreamSynchronize(c->aux); }
-  } aux_join{c};
+}
+
+// The Lanczos estimates and the coarsest inverse run on the aux stream: a
+// set-up joins it before returning, also when it unwinds with an error.
+struct AuxJoin {
+  hfsi_ctx* c;
+  ~AuxJoin() { (void)hipStreamSynchronize(c->aux); }
+};
+
+void to_f32_transfer(hfsi_ctx* c, Level& L) {
+  hipStream_t s = c->stream;
+  L.P32.ensure(L.P.nnz);
+  L.R32.ensure(L.R.nnz);
+  k_to_f32<<<div_up(L.P.nnz, 256), 256, 0, s>>>(L.P.nnz, L.P.val.p, L.P32.p);
+  k_to_f32<<<div_up(L.R.nnz, 256), 256, 0, s>>>(L.R.nnz, L.R.val.p, L.R32.p);
+  HIP_LAUNCH_CHECK();
+}
+
+// With every level operator final: the coarsest level's explicit inverse (on
+// the aux stream while this stream makes the operator copies of the cycle),
+// the fp32 and padded copies, then one read of the deferred checks and the
+// eigenvalue estimates.  Marks the hierarchy ready.
+void finish_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm) {
+  hipStream_t s = c->stream;
+  Hierarchy& H = c->H;
+  Level& Lc = H.L.back();
+  const int nc = Lc.n;
+  if (nc > 4096) fail(HFSI_E_CAPACITY, "coarsest level larger than 4096 rows (coarsening stalled)");
+  H.nc = nc;
+  H.coarse_inv.ensure((size_t)nc * nc);
+  DevBuf<int> sing;
+  sing.zero(1, s);
+  HIP_CHECK(hipEventRecord(c->aev[0], s));
+  HIP_CHECK(hipStreamWaitEvent(c->aux, c->aev[0], 0));
+  {
+    hipStream_t a = c->aux;
+    StreamTag tag(a);
+    DevBuf<double> M, M2;
+    M.ensure(2 * (size_t)nc * nc);
+    M2.ensure(2 * (size_t)nc * nc);
+    k_dense_from_csr<<<div_up(nc, 256), 256, 0, a>>>(nc, Lc.A.ptr.p, Lc.A.col.p, Lc.A.val.p, M.p);
+    HIP_LAUNCH_CHECK();
+    // Gauss-Jordan on [A | I]: one launch per pivot, alternating buffers
+    double* gin = M.p;
+    double* gout = M2.p;
+    for (int k = 0; k < nc; ++k) {
+      const long work = (long)nc * (2L * nc - k - 1);
+      k_gj_step<<<div_up(work, 256), 256, 0, a>>>(nc, k, gin, gout, sing.p);
+      std::swap(gin, gout);
+    }
+    k_gj_extract<<<div_up((long)nc * nc, 256), 256, 0, a>>>(nc, gin, H.coarse_inv.p);
+    HIP_LAUNCH_CHECK();
+  }
+  // fp32 operator copies
+  if (prm.precision == 1)
+    for (auto& L : H.L) {
+      L.A32.ensure(L.A.nnz);
+      k_to_f32<<<div_up(L.A.nnz, 256), 256, 0, s>>>(L.A.nnz, L.A.val.p, L.A32.p);
+      HIP_LAUNCH_CHECK();
+    }
+  // padded operator copies for the smoother and residual
+  for (auto& L : H.L) {
+    L.packed = false;
+    if (!L.bptr) pack_level(c, L, prm.precision);
+  }
+  // join the aux stream, then read the singularity flag and the estimates
+  HIP_CHECK(hipEventRecord(c->aev[1], c->aux));
+  HIP_CHECK(hipStreamWaitEvent(s, c->aev[1], 0));
+  const int nl = (int)H.L.size();
+  double lm[32] = {0};
+  int sg = 0, sf = 0;
+  HIP_CHECK(hipMemcpyAsync(&sg, sing.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(&sf, H.setup_flags.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  if (prm.smoother == 1) HIP_CHECK(hipMemcpyAsync(lm, H.lmax_dev.p, sizeof(double) * nl, hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  if (sf) fail(HFSI_E_CAPACITY, "sparse product: a row has more than 6144 entries or overflowed its table");
+  if (sg) fail(HFSI_E_BREAKDOWN, "coarsest AMG operator is singular");
+  for (int l = 0; l < nl; ++l) H.L[l].lmax = prm.smoother == 1 ? lm[l] : 0.0;
+  H.ready = true;
+}
+
+void fill_info(const Hierarchy& H, hfsi_amg_info* info, int rounds, double rho) {
+  if (!info) return;
+  info->levels = (int)H.L.size();
+  double nnz0 = (double)H.L[0].A.nnz, rows0 = (double)H.L[0].n, sn = 0, sr = 0;
+  for (size_t l = 0; l < H.L.size() && l < 32; ++l) {
+    info->rows[l] = H.L[l].n;
+    info->nnz[l] = H.L[l].A.nnz;
+    sn += (double)H.L[l].A.nnz;
+    sr += H.L[l].n;
+  }
+  info->op_complexity = sn / nnz0;
+  info->grid_complexity = sr / rows0;
+  info->pmis_rounds = rounds;
+  info->rho = rho;
+  info->learned_used = H.learned;
+}
+
+}  // namespace
+
+// Build levels 1.. from level 0 (whose A and comp are already set).
+void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {
+  hipStream_t s = c->stream;
+  Hierarchy& H = c->H;
+  H.ready = false;
+  H.reusable = false;
+  set_schedule(H, prm);
+  AuxJoin aux_join{c};
   H.lmax_dev.ensure(32);
   H.setup_flags.zero(1, s);
   int rounds_total = 0;
@@ -1756,70 +1857,10 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
     Lc.comp.ensure(nc);
     k_coarse_comp<<<div_up(n, 256), 256, 0, s>>>(n, Lf.state.p, Lf.cidx.p, Lf.comp.p, Lc.comp.p);
     HIP_LAUNCH_CHECK();
-    if (prm.precision == 1) {
-      Lf.P32.ensure(Lf.P.nnz);
-      Lf.R32.ensure(Lf.R.nnz);
-      k_to_f32<<<div_up(Lf.P.nnz, 256), 256, 0, s>>>(Lf.P.nnz, Lf.P.val.p, Lf.P32.p);
-      k_to_f32<<<div_up(Lf.R.nnz, 256), 256, 0, s>>>(Lf.R.nnz, Lf.R.val.p, Lf.R32.p);
-      HIP_LAUNCH_CHECK();
-    }
+    if (prm.precision == 1) to_f32_transfer(c, Lf);
   }
-  // coarsest level: explicit inverse, on the aux stream while this stream
-  // makes the operator copies of the cycle
-  Level& Lc = H.L.back();
-  const int nc = Lc.n;
-  if (nc > 4096) fail(HFSI_E_CAPACITY, "coarsest level larger than 4096 rows (coarsening stalled)");
-  H.nc = nc;
-  H.coarse_inv.ensure((size_t)nc * nc);
-  DevBuf<int> sing;
-  sing.zero(1, s);
-  HIP_CHECK(hipEventRecord(c->aev[0], s));
-  HIP_CHECK(hipStreamWaitEvent(c->aux, c->aev[0], 0));
-  {
-    hipStream_t a = c->aux;
-    StreamTag tag(a);
-    DevBuf<double> M, M2;
-    M.ensure(2 * (size_t)nc * nc);
-    M2.ensure(2 * (size_t)nc * nc);
-    k_dense_from_csr<<<div_up(nc, 256), 256, 0, a>>>(nc, Lc.A.ptr.p, Lc.A.col.p, Lc.A.val.p, M.p);
-    HIP_LAUNCH_CHECK();
-    // Gauss-Jordan on [A | I]: one launch per pivot, alternating buffers
-    double* gin = M.p;
-    double* gout = M2.p;
-    for (int k = 0; k < nc; ++k) {
-      const long work = (long)nc * (2L * nc - k - 1);
-      k_gj_step<<<div_up(work, 256), 256, 0, a>>>(nc, k, gin, gout, sing.p);
-      std::swap(gin, gout);
-    }
-    k_gj_extract<<<div_up((long)nc * nc, 256), 256, 0, a>>>(nc, gin, H.coarse_inv.p);
-    HIP_LAUNCH_CHECK();
-  }
-  // fp32 operator copies
-  if (prm.precision == 1)
-    for (auto& L : H.L) {
-      L.A32.ensure(L.A.nnz);
-      k_to_f32<<<div_up(L.A.nnz, 256), 256, 0, s>>>(L.A.nnz, L.A.val.p, L.A32.p);
-      HIP_LAUNCH_CHECK();
-    }
-  // padded operator copies for the smoother and residual
-  for (auto& L : H.L) {
-    L.packed = false;
-    if (!L.bptr) pack_level(c, L, prm.precision);
-  }
-  // join the aux stream, then read the singularity flag and the estimates
-  HIP_CHECK(hipEventRecord(c->aev[1], c->aux));
-  HIP_CHECK(hipStreamWaitEvent(s, c->aev[1], 0));
-  const int nl = (int)H.L.size();
-  double lm[32] = {0};
-  int sg = 0, sf = 0;
-  HIP_CHECK(hipMemcpyAsync(&sg, sing.p, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipMemcpyAsync(&sf, H.setup_flags.p, sizeof(int), hipMemcpyDeviceToHost, s));
-  if (prm.smoother == 1) HIP_CHECK(hipMemcpyAsync(lm, H.lmax_dev.p, sizeof(double) * nl, hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
-  if (sf) fail(HFSI_E_CAPACITY, "sparse product: a row has more than 6144 entries or overflowed its table");
-  if (sg) fail(HFSI_E_BREAKDOWN, "coarsest AMG operator is singular");
-  for (int l = 0; l < nl; ++l) H.L[l].lmax = prm.smoother == 1 ? lm[l] : 0.0;
-  H.ready = true;
+  H.learned = prm.interp == 1 ? 1 : 0;
+  finish_hierarchy(c, prm);
   double rho = -1.0;
   if (prm.interp == 1) {
     // judge: keep the learned interpolation only if the V-cycle converges fast
@@ -1836,21 +1877,7 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
       return;
     }
   }
-  if (info) {
-    info->levels = (int)H.L.size();
-    double nnz0 = (double)H.L[0].A.nnz, rows0 = (double)H.L[0].n, sn = 0, sr = 0;
-    for (size_t l = 0; l < H.L.size() && l < 32; ++l) {
-      info->rows[l] = H.L[l].n;
-      info->nnz[l] = H.L[l].A.nnz;
-      sn += (double)H.L[l].A.nnz;
-      sr += H.L[l].n;
-    }
-    info->op_complexity = sn / nnz0;
-    info->grid_complexity = sr / rows0;
-    info->pmis_rounds = rounds_total;
-    info->rho = rho;
-    info->learned_used = prm.interp == 1 ? 1 : 0;
-  }
+  fill_info(H, info, rounds_total, rho);
 }
 
 void amg_setup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {
@@ -1874,7 +1901,46 @@ void amg_setup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* in
   k_block3<<<div_up(9L * c->nb, 256), 256, 0, c->stream>>>(c->nb, c->Kval.p, L0.b3d.p, L0.b3f.p);
   HIP_LAUNCH_CHECK();
   build_hierarchy(c, prm, info);
+  H.reusable = true;
   HIP_CHECK(hipEventRecord(c->ev1, c->stream));
+  if (info) info->seconds = elapsed_ms(c) * 1e-3;
+}
+
+// Re-set-up on the coarse grids of the last set-up of this mesh's tangent:
+// the splittings, P and R (and the learned level-0 rows, if kept) stay; level
+// 0 takes the displacement block of the last assembly, every coarser operator
+// is again the Galerkin product R A P, and the smoother data, coarsest inverse
+// and cycle copies are rebuilt.  No strength, PMIS, interpolation or judge.
+void amg_resetup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {
+  Hierarchy& H = c->H;
+  hipStream_t s = c->stream;
+  if (!H.reusable || H.L.empty() || H.L[0].n != c->A.rows || H.L[0].A.nnz != c->A.nnz)
+    fail(HFSI_E_ORDER, "amg_resetup: no hierarchy of this mesh's tangent to reuse");
+  HIP_CHECK(hipEventRecord(c->ev0, s));
+  H.ready = false;
+  H.reusable = false;
+  set_schedule(H, prm);
+  AuxJoin aux_join{c};
+  H.lmax_dev.ensure(32);
+  H.setup_flags.zero(1, s);
+  Level& L0 = H.L[0];
+  HIP_CHECK(hipMemcpyAsync(L0.A.val.p, c->A.val.p, sizeof(double) * c->A.nnz, hipMemcpyDeviceToDevice, s));
+  k_block3<<<div_up(9L * c->nb, 256), 256, 0, s>>>(c->nb, c->Kval.p, L0.b3d.p, L0.b3f.p);
+  HIP_LAUNCH_CHECK();
+  const int nl = (int)H.L.size();
+  for (int l = 0; l < nl; ++l) {
+    smoother_data(c, H.L[l], prm, l);
+    if (l + 1 == nl) break;
+    Level& Lf = H.L[l];
+    Csr<double> AP;
+    spgemm(c, Lf.A, Lf.P, AP, H.setup_flags.p);
+    spgemm(c, Lf.R, AP, H.L[l + 1].A, H.setup_flags.p);
+    if (prm.precision == 1) to_f32_transfer(c, Lf);
+  }
+  finish_hierarchy(c, prm);
+  H.reusable = true;
+  fill_info(H, info, 0, -1.0);
+  HIP_CHECK(hipEventRecord(c->ev1, s));
   if (info) info->seconds = elapsed_ms(c) * 1e-3;
 }
 
@@ -1902,6 +1968,15 @@ extern "C" hfsi_status hfsi_amg_setup(hfsi_ctx* c, const hfsi_amg_params* prm, h
   hfsi::check_amg_params(prm);
   if (info && info->struct_size != sizeof(hfsi_amg_info)) fail(HFSI_E_ARG, "amg info: struct_size mismatch");
   hfsi::amg_setup_level0(c, *prm, info);
+  HFSI_ABI_END(c)
+}
+
+extern "C" hfsi_status hfsi_amg_resetup(hfsi_ctx* c, const hfsi_amg_params* prm, hfsi_amg_info* info) {
+  HFSI_ABI_BEGIN(c)
+  require_stage(c, 4, "amg_resetup");
+  hfsi::check_amg_params(prm);
+  if (info && info->struct_size != sizeof(hfsi_amg_info)) fail(HFSI_E_ARG, "amg info: struct_size mismatch");
+  hfsi::amg_resetup_level0(c, *prm, info);
   HFSI_ABI_END(c)
 }
 

@@ -202,6 +202,9 @@ struct Hierarchy {
   int cheb_degree_pre = 1, cheb_degree_coarse = 3;
   double cheb_ratio = 30.0;     // interval [lmax / ratio, 1.1 lmax]
   bool ready = false;
+  int learned = 0;        // 1 if level 0 carries the learned interpolation
+  bool reusable = false;  // built from this mesh's assembled tangent: its
+                          // coarse grids may be kept by a re-set-up
 };
 
 }  // namespace hfsi
@@ -286,6 +289,7 @@ void require_stage(hfsi_ctx* c, int st, const char* what);
 void assemble(hfsi_ctx* c, const double* v, double load, double* R, hfsi_assembly_info* info);
 void build_a_pattern(hfsi_ctx* c);
 void amg_setup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info);
+void amg_resetup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info);
 void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info);
 void check_amg_params(const hfsi_amg_params* p);
 void vcycle_apply(hfsi_ctx* c, const double* r, double* z);

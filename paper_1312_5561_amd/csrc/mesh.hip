@@ -312,6 +312,7 @@ extern "C" hfsi_status hfsi_set_mesh(hfsi_ctx* c, int64_t n_nodes, const double*
   c->m = m;
   c->stage = 0;
   c->H.ready = false;
+  c->H.reusable = false;
   colour_elements(n, m, tets, c->perm, c->colour_ptr);
 
   // element arrays in colour order, structure of arrays
@@ -461,5 +462,6 @@ extern "C" hfsi_status hfsi_set_bc(hfsi_ctx* c, const uint8_t* dir_mask, int64_t
   HIP_CHECK(hipStreamSynchronize(c->stream));
   c->stage = 3;
   c->H.ready = false;
+  c->H.reusable = false;
   HFSI_ABI_END(c)
 }

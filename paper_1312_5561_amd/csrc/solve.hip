@@ -1612,7 +1612,9 @@ extern "C" hfsi_status hfsi_newton_step(hfsi_ctx* c, double* v, double load, con
   const double rnorm = hfsi::read_scalar(c, c->scal.p + 6);
   if (!std::isfinite(rnorm)) fail(HFSI_E_NAN, "newton_step: non-finite residual");
   hfsi_amg_info mi{sizeof(hfsi_amg_info)};
-  hfsi::amg_setup_level0(c, prm->amg, &mi);
+  const bool reuse = prm->amg_reuse != 0 && c->H.reusable;
+  if (reuse) hfsi::amg_resetup_level0(c, prm->amg, &mi);
+  else hfsi::amg_setup_level0(c, prm->amg, &mi);
   // b = -R, dv = 0
   k_negate<<<div_up(N, 256), 256, 0, s>>>(N, c->ktmp.p, c->ktmp.p);
   HIP_LAUNCH_CHECK();
@@ -1639,6 +1641,7 @@ extern "C" hfsi_status hfsi_newton_step(hfsi_ctx* c, double* v, double load, con
     info->t_solve = si.seconds;
     info->t_total = ms * 1e-3;
     info->amg_levels = mi.levels;
+    info->amg_reused = reuse ? 1 : 0;
   }
   if (!si.converged) return HFSI_NOT_CONVERGED;
   HFSI_ABI_END(c)

@@ -70,14 +70,15 @@ class SolveInfo(C.Structure):
 
 
 class NewtonParams(C.Structure):
-    _fields_ = [("struct_size", C.c_size_t), ("amg", AmgParams), ("solve", SolveParams)]
+    _fields_ = [("struct_size", C.c_size_t), ("amg", AmgParams), ("solve", SolveParams),
+                ("amg_reuse", C.c_int32)]
 
 
 class NewtonInfo(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("dv_mass_norm", C.c_double), ("residual_norm", C.c_double),
                 ("krylov_iterations", C.c_int32), ("rel_residual", C.c_double), ("t_assemble", C.c_double),
                 ("t_setup", C.c_double), ("t_solve", C.c_double), ("t_total", C.c_double),
-                ("amg_levels", C.c_int32)]
+                ("amg_levels", C.c_int32), ("amg_reused", C.c_int32)]
 
 
 class TrainParams(C.Structure):
@@ -110,8 +111,9 @@ def solve_params(tol=1e-8, restart=50, max_iter=500, method=0):
     return SolveParams(C.sizeof(SolveParams), tol, restart, max_iter, method)
 
 
-def newton_params(amg=None, solve=None):
-    return NewtonParams(C.sizeof(NewtonParams), amg or amg_params(), solve or solve_params())
+def newton_params(amg=None, solve=None, amg_reuse=0):
+    """amg_reuse=1: re-set-up on the previous coarse grids when available."""
+    return NewtonParams(C.sizeof(NewtonParams), amg or amg_params(), solve or solve_params(), amg_reuse)
 
 
 _lib = None
@@ -134,6 +136,7 @@ def load():
         "hfsi_set_bc": [vp, vp, i64, vp, vp],
         "hfsi_assemble_residual_tangent": [vp, vp, dbl, vp, C.POINTER(CsrView), C.POINTER(AssemblyInfo)],
         "hfsi_amg_setup": [vp, C.POINTER(AmgParams), C.POINTER(AmgInfo)],
+        "hfsi_amg_resetup": [vp, C.POINTER(AmgParams), C.POINTER(AmgInfo)],
         "hfsi_krylov_amg_solve": [vp, vp, vp, C.POINTER(SolveParams), C.POINTER(SolveInfo)],
         "hfsi_newton_step": [vp, vp, dbl, C.POINTER(NewtonParams), C.POINTER(NewtonInfo)],
         "hfsi_amg_setup_csr": [vp, i32, vp, vp, vp, vp, C.POINTER(AmgParams), C.POINTER(AmgInfo)],
@@ -257,6 +260,13 @@ class Context:
         prm = prm or amg_params()
         info = AmgInfo(C.sizeof(AmgInfo))
         self._check(self.lib.hfsi_amg_setup(self.h, C.byref(prm), C.byref(info)))
+        return info
+
+    def amg_resetup(self, prm=None):
+        """Keep the coarse grids of the last set-up; new Galerkin operators."""
+        prm = prm or amg_params()
+        info = AmgInfo(C.sizeof(AmgInfo))
+        self._check(self.lib.hfsi_amg_resetup(self.h, C.byref(prm), C.byref(info)))
         return info
 
     def amg_setup_csr(self, ptr, col, val, comp, prm=None):

@@ -1,0 +1,144 @@
+"""GPU parity of the AMG re-set-up on kept coarse grids.
+
+After a set-up at one state and an assembly at another, the re-set-up keeps
+the splittings and P of the first set-up and rebuilds the Galerkin operators
+of the new tangent: level by level they equal the oracle's Galerkin product
+of the GPU's own level operator and kept P (pattern exact, values 1e-12
+relative), end to end the oracle's re-set-up of the new tangent on the first
+hierarchy, and the V-cycle on the rebuilt hierarchy matches the oracle's.
+A Newton load run that re-uses the coarse grids converges to the oracle's
+states.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import amg_prm_pair, context_for, export_level_matrix, gpu_hierarchy_to_oracle, oracle_system
+from gpu_helpers import torch_dev
+from oracle import amg, fe, newton
+
+pytestmark = pytest.mark.gpu
+
+
+def _assemble(ctx, v, load):
+    import torch
+    vt = torch_dev(v)
+    R = torch.zeros_like(vt)
+    ctx.assemble_residual_tangent(vt, load, R)
+    return R
+
+
+@pytest.mark.parametrize("smoother,precision", [(0, 0), (1, 0), (1, 1)])
+def test_resetup_matches_oracle(lib, smoother, precision):
+    import torch
+    print(f"[reuse parity] smoother={smoother} precision={precision}", flush=True)
+    prob = synth.cube_problem(6, jitter=0.1, seed=2)
+    v0 = synth.random_state(prob, 3, u_scale=0.03, p_scale=0.05).ravel()
+    v1 = synth.random_state(prob, 7, u_scale=0.06, p_scale=0.2).ravel()
+    gprm, oprm = amg_prm_pair(lib, smoother=smoother, precision=precision, max_coarse=60, schedule="default")
+    ctx = context_for(lib, prob)
+    _assemble(ctx, v0, 0.4)
+    info0 = ctx.amg_setup(gprm)
+    assert info0.levels >= 3
+    H0 = gpu_hierarchy_to_oracle(ctx, info0, oprm)
+    _assemble(ctx, v1, 0.7)
+    info1 = ctx.amg_resetup(gprm)
+    assert info1.levels == info0.levels and info1.pmis_rounds == 0 and info1.rho == -1.0
+    assert [info1.rows[l] for l in range(info1.levels)] == [info0.rows[l] for l in range(info0.levels)]
+    _, K1, b1, A1, B2, s = oracle_system(prob, v1, 0.7)
+    A1 = A1.tocsr()
+    A1.sort_indices()
+    G0 = export_level_matrix(ctx, 0, 0)
+    assert np.array_equal(G0.indptr, A1.indptr) and np.array_equal(G0.indices, A1.indices)
+    assert np.abs(G0.data - A1.data).max() <= 1e-12 * np.abs(A1.data).max()
+    Ho = amg.resetup(A1, H0, oprm)
+    for l in range(info1.levels - 1):
+        P = export_level_matrix(ctx, l, 1)
+        Pk = H0.levels[l].P
+        assert np.array_equal(P.indptr, Pk.indptr) and np.array_equal(P.indices, Pk.indices)
+        assert np.array_equal(P.data, Pk.data), f"P changed on level {l}"
+        A = export_level_matrix(ctx, l, 0)
+        Ac = export_level_matrix(ctx, l + 1, 0)
+        Aco = amg.galerkin(A, P)
+        assert np.array_equal(Ac.indptr, Aco.indptr) and np.array_equal(Ac.indices, Aco.indices)
+        assert np.abs(Ac.data - Aco.data).max() <= 1e-12 * np.abs(Aco.data).max(), f"RAP level {l}"
+        Ae = Ho.levels[l + 1].A
+        assert np.abs(Ac.data - Ae.data).max() <= 1e-10 * np.abs(Ae.data).max(), f"end-to-end level {l + 1}"
+    # the V-cycle on the rebuilt hierarchy
+    H1 = gpu_hierarchy_to_oracle(ctx, info1, oprm)
+    n3 = 3 * prob.n_nodes
+    r = np.random.default_rng(5).normal(size=n3)
+    z = torch.zeros(n3, dtype=torch.float64, device="cuda")
+    ctx.vcycle(torch_dev(r), z)
+    zo = amg.vcycle(H1, r, oprm)
+    tol = 1e-12 if precision == 0 else 2e-5
+    assert np.linalg.norm(z.cpu().numpy() - zo) <= tol * np.linalg.norm(zo)
+    # a second re-set-up at the first state restores the first hierarchy's operators
+    _assemble(ctx, v0, 0.4)
+    ctx.amg_resetup(gprm)
+    for l in range(info0.levels):
+        A = export_level_matrix(ctx, l, 0)
+        assert np.abs(A.data - H0.levels[l].A.data).max() <= 1e-12 * np.abs(H0.levels[l].A.data).max()
+
+
+def test_resetup_order_errors(lib):
+    """No hierarchy, one from a caller CSR, a new mesh or a failed set-up:
+    nothing to reuse."""
+    prob = synth.cube_problem(5)
+    ctx = context_for(lib, prob)
+    _assemble(ctx, np.zeros(prob.n_dofs), 0.5)
+    with pytest.raises(lib.HfsiError) as e:
+        ctx.amg_resetup(lib.amg_params())
+    assert e.value.code == -4
+    ctx.amg_setup(lib.amg_params(max_coarse=40))
+    ctx.amg_resetup(lib.amg_params(max_coarse=40))
+    ctx.set_problem(prob)
+    _assemble(ctx, np.zeros(prob.n_dofs), 0.5)
+    with pytest.raises(lib.HfsiError) as e:
+        ctx.amg_resetup(lib.amg_params())
+    assert e.value.code == -4
+    # a set-up that fails (a single level of 6591 rows is over the dense limit)
+    big = synth.cube_problem(12)
+    ctx12 = context_for(lib, big)
+    _assemble(ctx12, np.zeros(big.n_dofs), 0.5)
+    ctx12.amg_setup(lib.amg_params())
+    with pytest.raises(lib.HfsiError) as e:
+        ctx12.amg_setup(lib.amg_params(max_levels=1))
+    assert e.value.code == -8
+    with pytest.raises(lib.HfsiError) as e:
+        ctx12.amg_resetup(lib.amg_params())
+    assert e.value.code == -4
+    ctx.amg_setup(lib.amg_params(max_coarse=40))
+    K_ptr = np.array([0, 1, 2], np.int32)
+    ctx.amg_setup_csr(K_ptr, np.array([0, 1], np.int32), np.array([2.0, 3.0]), np.zeros(2, np.int32),
+                      lib.amg_params())
+    with pytest.raises(lib.HfsiError) as e:
+        ctx.amg_resetup(lib.amg_params())
+    assert e.value.code == -4
+
+
+def test_newton_run_with_reused_coarse_grids(lib):
+    """The 8^3 cube load run (5 increments, Newton to 1e-10) with the coarse
+    grids of each increment's first step kept for its later steps reaches the
+    oracle's converged states."""
+    import torch
+    prob = synth.cube_problem(8)
+    print("[newton reuse] cube8 5 increments", flush=True)
+    ctx = context_for(lib, prob)
+    v = torch.zeros(4 * prob.n_nodes, dtype=torch.float64, device="cuda")
+    fresh = lib.newton_params()
+    reuse = lib.newton_params(amg_reuse=1)
+    reused = []
+    for k in range(1, 6):
+        n0 = None
+        for it in range(25):
+            info, code = ctx.newton_step(v, k / 5.0, fresh if it == 0 else reuse)
+            assert code == 0
+            reused.append(info.amg_reused)
+            n0 = info.dv_mass_norm if n0 is None else n0
+            if info.dv_mass_norm <= 1e-10 * n0:
+                break
+    assert reused[0] == 0 and sum(reused) >= 10
+    disc = fe.Discretization(prob)
+    vo = newton.load_run(disc, 5, newton.NewtonParams())
+    assert np.linalg.norm(v.cpu().numpy() - vo) <= 1e-9 * np.linalg.norm(vo)
