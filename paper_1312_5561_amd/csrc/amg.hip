@@ -1460,7 +1460,143 @@ void transpose(hfsi_ctx* c, const Csr<double>& P, Csr<double>& R) {
 // C = A B with the structural pattern (no numerical dropping).
 // The numeric pass reports overflow into *deferred (checked by the caller
 // later: an overflowing row is written with column 0 entries).
-void spgemm(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>& Cm, int* deferred) {
+// Slot of column j in the sorted window w[0, wl), or -1.
+__device__ __forceinline__ int window_slot(const int* w, int wl, int j) {
+  int lo = 0, hi = wl - 1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int v = w[mid];
+    if (v < j) lo = mid + 1;
+    else if (v > j) hi = mid - 1;
+    else return mid;
+  }
+  return -1;
+}
+
+// Values of C = A B on the pattern of an earlier product of the same two
+// patterns (C's row pointer and sorted columns given).  One wavefront per row
+// of C; the row's columns are held in LDS windows of W entries (one window
+// unless the row is longer).  For every entry a_ik of A_i, in ascending
+// order, the products a_ik b_kj are added into the slots of their columns,
+// found by binary search: per entry of C the additions are those of the full
+// product in the same order and form, so the values are bitwise equal to it.
+// NARROW (rows of B with at most WB entries): the lanes take 64 entries of
+// A_i and their rows of B at once to find the slots, then add entry by entry
+// with WB lanes.  Otherwise the lanes fetch the row bounds of B for 64
+// entries of A_i at once and take the entries in order, the lanes over the
+// row of B.  A column of B_k inside the window's range but missing from it
+// (a pattern that does not belong to these operands) sets bit 16 of *flag.
+template <int W, int WB, bool NARROW>
+__global__ void __launch_bounds__(64)
+k_spgemm_values(int n, const int* __restrict__ ap, const int* __restrict__ ac, const double* __restrict__ av,
+                const int* __restrict__ bp, const int* __restrict__ bc, const double* __restrict__ bv,
+                const int* __restrict__ cp, const int* __restrict__ cc, double* __restrict__ cv,
+                int* __restrict__ flag) {
+  __shared__ int wcol[W];
+  __shared__ double wval[W];
+  __shared__ int f_s[NARROW ? 64 * WB : 1];
+  __shared__ double f_b[NARROW ? 64 * WB : 1];
+  __shared__ double f_a[NARROW ? 64 : 1];
+  const int lane = threadIdx.x;
+  bool bad = false;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const int c0 = cp[i], c1 = cp[i + 1];
+    const int a0 = ap[i], a1 = ap[i + 1];
+    for (int w0 = c0; w0 < c1; w0 += W) {
+      const int wl = min(W, c1 - w0);
+      for (int t = lane; t < wl; t += 64) {
+        wcol[t] = cc[w0 + t];
+        wval[t] = 0.0;
+      }
+      __syncthreads();
+      const int jlo = wcol[0], jhi = wcol[wl - 1];
+      for (int base = a0; base < a1; base += 64) {
+        const int ne = min(64, a1 - base);
+        if (NARROW) {
+          const int e = base + lane;
+          double a = 0.0;
+          int qb = 0, ql = 0;
+          if (lane < ne) {
+            const int k = ac[e];
+            a = av[e];
+            qb = bp[k];
+            ql = bp[k + 1] - qb;
+          }
+          if (ql > WB) {
+            bad = true;
+            ql = WB;
+          }
+#pragma unroll
+          for (int q = 0; q < WB; ++q) {
+            int h = -1;
+            if (q < ql) {
+              const int j = bc[qb + q];
+              if (j >= jlo && j <= jhi) {
+                h = window_slot(wcol, wl, j);
+                if (h < 0) bad = true;
+              }
+              f_b[lane * WB + q] = bv[qb + q];
+            }
+            f_s[lane * WB + q] = h;
+          }
+          f_a[lane] = a;
+          __syncthreads();
+          for (int e2 = 0; e2 < ne; ++e2) {
+            if (lane < WB) {
+              const int h = f_s[e2 * WB + lane];
+              if (h >= 0) wval[h] += f_a[e2] * f_b[e2 * WB + lane];
+            }
+            __syncthreads();
+          }
+        } else {
+          int kq0 = 0, kq1 = 0;
+          double ka = 0.0;
+          if (lane < ne) {
+            const int kk = ac[base + lane];
+            kq0 = bp[kk];
+            kq1 = bp[kk + 1];
+            ka = av[base + lane];
+          }
+          for (int te = 0; te < ne; ++te) {
+            const int q0 = __shfl(kq0, te, 64), q1 = __shfl(kq1, te, 64);
+            const double a = __shfl(ka, te, 64);
+            for (int q = q0 + lane; q < q1; q += 64) {
+              const int j = bc[q];
+              if (j >= jlo && j <= jhi) {
+                const int h = window_slot(wcol, wl, j);
+                if (h >= 0) wval[h] += a * bv[q];
+                else bad = true;
+              }
+            }
+            __syncthreads();
+          }
+        }
+      }
+      for (int t = lane; t < wl; t += 64) cv[w0 + t] = wval[t];
+      __syncthreads();
+    }
+  }
+  if (__any(bad) && lane == 0) atomicOr(flag, 16);
+}
+
+// C = A B into the existing pattern of Cm (an earlier product of the same
+// patterns); bmax = the longest row of B, as returned by spgemm.
+void spgemm_values(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>& Cm, int bmax,
+                   int* deferred) {
+  hipStream_t s = c->stream;
+  const int n = A.rows;
+  if (Cm.rows != n || Cm.cols != B.cols) fail(HFSI_E_ARG, "sparse product values: pattern of other operands");
+  const int grid = std::max(1, std::min(n, 1 << 16));
+  if (bmax <= 4)
+    k_spgemm_values<512, 4, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p,
+                                                      Cm.ptr.p, Cm.col.p, Cm.val.p, deferred);
+  else
+    k_spgemm_values<512, 1, false><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p,
+                                                       Cm.ptr.p, Cm.col.p, Cm.val.p, deferred);
+  HIP_LAUNCH_CHECK();
+}
+
+int spgemm(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>& Cm, int* deferred) {
   hipStream_t s = c->stream;
   const int n = A.rows;
   Cm.rows = n;
@@ -1517,6 +1653,7 @@ void spgemm(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>
                                          TS * 3 / 4 + 1, TL * 3 / 4, nullptr, Cm.ptr.p, Cm.col.p, Cm.val.p, deferred,
                                          ub.p, -1);
   HIP_LAUNCH_CHECK();
+  return bmax;
 }
 
 void smoother_data(hfsi_ctx* c, Level& L, const hfsi_amg_params& prm, int level) {
@@ -1699,6 +1836,7 @@ void finish_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm) {
   HIP_CHECK(hipMemcpyAsync(&sf, H.setup_flags.p, sizeof(int), hipMemcpyDeviceToHost, s));
   if (prm.smoother == 1) HIP_CHECK(hipMemcpyAsync(lm, H.lmax_dev.p, sizeof(double) * nl, hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipStreamSynchronize(s));
+  if (sf & 16) fail(HFSI_E_HIP, "sparse product values: a product column is missing from the kept pattern");
   if (sf) fail(HFSI_E_CAPACITY, "sparse product: a row has more than 6144 entries or overflowed its table");
   if (sg) fail(HFSI_E_BREAKDOWN, "coarsest AMG operator is singular");
   for (int l = 0; l < nl; ++l) H.L[l].lmax = prm.smoother == 1 ? lm[l] : 0.0;
@@ -1847,12 +1985,11 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
     if (l == 0 && prm.interp == 1) learned_correction(c, L);
     transpose(c, L.P, L.R);
     // Galerkin product
-    Csr<double> AP;
-    spgemm(c, L.A, L.P, AP, H.setup_flags.p);
+    L.p_rowmax = spgemm(c, L.A, L.P, L.AP, H.setup_flags.p);
     H.L.emplace_back();
     Level& Lc = H.L.back();
     Level& Lf = H.L[l];  // reference may move with emplace_back
-    spgemm(c, Lf.R, AP, Lc.A, H.setup_flags.p);
+    Lf.ap_rowmax = spgemm(c, Lf.R, Lf.AP, Lc.A, H.setup_flags.p);
     Lc.n = nc;
     Lc.comp.ensure(nc);
     k_coarse_comp<<<div_up(n, 256), 256, 0, s>>>(n, Lf.state.p, Lf.cidx.p, Lf.comp.p, Lc.comp.p);
@@ -1932,9 +2069,8 @@ void amg_resetup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* 
     smoother_data(c, H.L[l], prm, l);
     if (l + 1 == nl) break;
     Level& Lf = H.L[l];
-    Csr<double> AP;
-    spgemm(c, Lf.A, Lf.P, AP, H.setup_flags.p);
-    spgemm(c, Lf.R, AP, H.L[l + 1].A, H.setup_flags.p);
+    spgemm_values(c, Lf.A, Lf.P, Lf.AP, Lf.p_rowmax, H.setup_flags.p);
+    spgemm_values(c, Lf.R, Lf.AP, H.L[l + 1].A, Lf.ap_rowmax, H.setup_flags.p);
     if (prm.precision == 1) to_f32_transfer(c, Lf);
   }
   finish_hierarchy(c, prm);

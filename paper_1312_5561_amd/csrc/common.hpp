@@ -170,6 +170,9 @@ struct Level {
   DevBuf<int> cidx;        // coarse index of C points (exclusive scan)
   Csr<double> P, R;        // interpolation and restriction (R = P^T)
   DevBuf<float> P32, R32;
+  Csr<double> AP;          // A P, kept for a re-set-up on the same pattern
+  int p_rowmax = 0;        // longest row of P, and of AP
+  int ap_rowmax = 0;
   DevBuf<double> dinv;     // smoother diagonal (l1 or plain), fp64
   DevBuf<float> dinv32;
   double lmax = 0.0;       // Chebyshev upper eigenvalue estimate

@@ -28,14 +28,18 @@ def _assemble(ctx, v, load):
     return R
 
 
-@pytest.mark.parametrize("smoother,precision", [(0, 0), (1, 0), (1, 1)])
-def test_resetup_matches_oracle(lib, smoother, precision):
+@pytest.mark.parametrize("smoother,precision,kind", [(0, 0, "ext+i"), (1, 0, "ext+i"), (1, 1, "ext+i"),
+                                                     (1, 0, "classical")])
+def test_resetup_matches_oracle(lib, smoother, precision, kind):
+    """ext+i with p_max = 4 takes the narrow value-only product for A P;
+    classical interpolation (longer rows of P) the general one."""
     import torch
-    print(f"[reuse parity] smoother={smoother} precision={precision}", flush=True)
+    print(f"[reuse parity] smoother={smoother} precision={precision} interp={kind}", flush=True)
     prob = synth.cube_problem(6, jitter=0.1, seed=2)
     v0 = synth.random_state(prob, 3, u_scale=0.03, p_scale=0.05).ravel()
     v1 = synth.random_state(prob, 7, u_scale=0.06, p_scale=0.2).ravel()
-    gprm, oprm = amg_prm_pair(lib, smoother=smoother, precision=precision, max_coarse=60, schedule="default")
+    gprm, oprm = amg_prm_pair(lib, smoother=smoother, precision=precision, max_coarse=60, schedule="default",
+                              kind=kind)
     ctx = context_for(lib, prob)
     _assemble(ctx, v0, 0.4)
     info0 = ctx.amg_setup(gprm)
@@ -73,12 +77,15 @@ def test_resetup_matches_oracle(lib, smoother, precision):
     zo = amg.vcycle(H1, r, oprm)
     tol = 1e-12 if precision == 0 else 2e-5
     assert np.linalg.norm(z.cpu().numpy() - zo) <= tol * np.linalg.norm(zo)
-    # a second re-set-up at the first state restores the first hierarchy's operators
+    # a second re-set-up at the first state restores the first hierarchy's
+    # operators bit for bit (the value-only products add in the order of the
+    # full products)
     _assemble(ctx, v0, 0.4)
     ctx.amg_resetup(gprm)
     for l in range(info0.levels):
         A = export_level_matrix(ctx, l, 0)
-        assert np.abs(A.data - H0.levels[l].A.data).max() <= 1e-12 * np.abs(H0.levels[l].A.data).max()
+        assert np.array_equal(A.indptr, H0.levels[l].A.indptr) and np.array_equal(A.indices, H0.levels[l].A.indices)
+        assert np.array_equal(A.data, H0.levels[l].A.data), f"level {l} differs from the full set-up"
 
 
 def test_resetup_order_errors(lib):
