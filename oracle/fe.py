@@ -187,17 +187,20 @@ def stress_tangent(C, mat, fib=None):
 # ---------------------------------------------------------------------------
 
 
-def element_kernel(G, V, h, mat, ue, pe, fib=None, want_tangent=True, theta=None):
+def element_kernel(G, V, h, mat, ue, pe, fib=None, want_tangent=True, theta=None, cm=0.0, re=None):
     """Residual R_e [m,4,4] and tangent K_e [m,16,16] of a batch of tetrahedra.
 
     Dof order inside an element is node-interleaved: 4a + c, c = 0,1,2 the
     displacement components and c = 3 the pressure.
 
-    Residual (eq. weakelas with rho_s = 0 and r_s = 0, plus the PSPG term of
-    eq. stelas):
-        R^u_a = V (F S' G_a - pbar J F^{-T} G_a)
+    Residual (eq. weakelas plus the stabilisation term of eq. stelas):
+        R^u_a = V (F S' G_a - pbar J F^{-T} G_a) + sum_b M_ab (cm d_b - r_b)
         R^p_a = -V/4 (J-1) - 1/kappa sum_b M_ab p_b - tau V J (F^{-T}G_a).(F^{-T} grad p)
-    with M_ab = V (1 + delta_ab)/20 the exact P1 mass and pbar the mean of p.
+                + tau (F^{-T}G_a) . int_T (r_s - cm d)
+    with M_ab = V (1 + delta_ab)/20 the exact P1 mass, pbar the mean of p,
+    cm = rho_s/(beta dt^2) the Newmark-beta inertia coefficient and r_b the
+    nodal values of the P1 field r_s (re [m,4,3]); cm = 0 and r_s = 0 give
+    the quasi-static problem.  int_T (r_s - cm d) = V/4 sum_b (r_b - cm d_b).
     The tangent is the exact derivative of this residual (block structure of
     eq. globsys: K = [A B1^T; B2 -C]).  External loads are added globally.
     """
@@ -223,6 +226,13 @@ def element_kernel(G, V, h, mat, ue, pe, fib=None, want_tangent=True, theta=None
     R[:, :, 3] = (-(V / 4.0 * (J - 1.0))[:, None]
                   - np.einsum("mab,mb->ma", Mab, pe) / kappa[:, None]
                   - (tau * V * J)[:, None] * gdot)
+    dynamic = cm != 0.0 or re is not None
+    if dynamic:
+        r_nodal = np.zeros((m, 4, 3)) if re is None else re
+        Mu = (1.0 + np.eye(4)) / 20.0
+        R[:, :, 0:3] += V[:, None, None] * np.einsum("ab,mbi->mai", Mu, cm * ue - r_nodal)
+        mvec = 0.25 * (r_nodal - cm * ue).sum(axis=1)      # mean of r_s - cm d on T
+        R[:, :, 3] += (tau * V)[:, None] * np.einsum("mai,mi->ma", g, mvec)
     if not want_tangent:
         return R, None
 
@@ -248,6 +258,14 @@ def element_kernel(G, V, h, mat, ue, pe, fib=None, want_tangent=True, theta=None
     K[:, :, 3, :, 0:3] = B2
     # -C: dR^p_a / dp_b
     K[:, :, 3, :, 3] = -(Mab / kappa[:, None, None] + (tau * V * J)[:, None, None] * gg)
+    if dynamic:
+        # inertia: cm M_ab I, and the derivative of tau g_a . int_T (r_s - cm d)
+        # through the mean (-cm/4) and through g_a (d g_a = -g_b (g_a . du_b))
+        K[:, :, 0:3, :, 0:3] += (cm * V[:, None, None, None, None] * Mu[None, :, None, :, None]
+                                 * I3x3[None, None, :, None, :])
+        gm = np.einsum("mbi,mi->mb", g, mvec)
+        K[:, :, 3, :, 0:3] += ((tau * V)[:, None, None, None] * (-(cm / 4.0) - gm[:, None, :, None])
+                               * g[:, :, None, :])
     return R, K.reshape(m, 16, 16)
 
 
@@ -308,6 +326,15 @@ class Discretization:
                 np.add.at(f, p.tris[:, a], contrib)
         self.f_ext = f
 
+    def set_inertia(self, cm, rs):
+        """Newmark-beta inertia: coefficient cm = rho_s/(beta dt^2) and the
+        nodal history field r_s [n,3] (cm = 0, rs = None: quasi-static)."""
+        self.cm = float(cm)
+        self.rs = None if rs is None else np.asarray(rs, np.float64).reshape(self.n, 3)
+
+    cm = 0.0
+    rs = None
+
     def element_batches(self, v):
         v = np.asarray(v).reshape(self.n, 4)
         for s in range(0, self.m, CHUNK):
@@ -318,12 +345,17 @@ class Discretization:
             fib = None if self.fib is None else self.fib[e]
             yield e, ve, mat, fib
 
+    def _inertia(self, e):
+        if self.cm == 0.0 and self.rs is None:
+            return {}
+        return dict(cm=self.cm, re=None if self.rs is None else self.rs[self.prob.tets[e]])
+
     def residual(self, v, load):
         """Global residual R (4n, node-interleaved) before Dirichlet handling."""
         R = np.zeros((self.n, 4))
         for e, ve, mat, fib in self.element_batches(v):
             Re, _ = element_kernel(self.G[e], self.V[e], self.h[e], mat, ve[:, :, 0:3], ve[:, :, 3],
-                                   fib, want_tangent=False)
+                                   fib, want_tangent=False, **self._inertia(e))
             for a in range(4):
                 np.add.at(R, self.prob.tets[e, a], Re[:, a])
         R[:, 0:3] -= load * self.f_ext
@@ -334,7 +366,8 @@ class Discretization:
         R = np.zeros((self.n, 4))
         val = np.zeros(len(self.K_indices))
         for e, ve, mat, fib in self.element_batches(v):
-            Re, Ke = element_kernel(self.G[e], self.V[e], self.h[e], mat, ve[:, :, 0:3], ve[:, :, 3], fib)
+            Re, Ke = element_kernel(self.G[e], self.V[e], self.h[e], mat, ve[:, :, 0:3], ve[:, :, 3], fib,
+                                    **self._inertia(e))
             for a in range(4):
                 np.add.at(R, self.prob.tets[e, a], Re[:, a])
             np.add.at(val, self.elem_pos[e].ravel(), Ke.ravel())

@@ -159,3 +159,59 @@ def test_sampled_rows_equal_full_assembly(make):
             assert set(got) == set(ref)
             for c in ref:
                 assert abs(got[c] - ref[c]) <= 1e-12 * np.abs(K.data).max()
+
+
+# ---------------------------------------------------------------- inertia
+
+
+def _with_inertia(d, seed, cm=37.0):
+    r = np.random.default_rng(seed)
+    d.set_inertia(cm, r.normal(scale=2.0, size=(d.n, 3)))
+    return d
+
+
+@pytest.mark.parametrize("law", ["mr", "artery"])
+def test_inertia_tangent_matches_finite_differences(law):
+    """With the Newmark-beta inertia terms (mass and history in R^u, the
+    history in the stabilisation of R^p) the tangent is still the derivative
+    of the residual."""
+    p = _problem(law)
+    d = _with_inertia(fe.Discretization(p), 5)
+    v = synth.random_state(p, 12, u_scale=0.1, p_scale=0.3)
+    R, val = d.assemble(v, 0.5)
+    K = d.csr(val).toarray()
+    Kfd = _fd_jacobian(d, v, 0.5)
+    assert np.abs(K - Kfd).max() <= 1e-6 * np.abs(K).max()
+    d0 = fe.Discretization(p)
+    R0, val0 = d0.assemble(v, 0.5)
+    assert np.abs(K - d0.csr(val0).toarray()).max() > 1e-3 * np.abs(K).max()
+
+
+def test_inertia_of_a_rigid_translation():
+    """A uniform displacement t with p = 0 and a uniform history r0 leaves
+    only inertia: the displacement rows sum to |Omega| (cm t - r0) (the
+    consistent mass integrates to the volume) and the pressure rows of every
+    element sum to zero (sum_a G_a = 0)."""
+    p = _problem("mr")
+    d = fe.Discretization(p)
+    t, r0, cm = np.array([0.3, -0.2, 0.5]), np.array([1.5, 0.7, -2.0]), 11.0
+    d.set_inertia(cm, np.tile(r0, (d.n, 1)))
+    v = np.zeros((d.n, 4))
+    v[:, 0:3] = t
+    R = d.residual(v.ravel(), 0.0).reshape(d.n, 4)
+    vol = d.V.sum()
+    assert np.allclose(R[:, 0:3].sum(axis=0), vol * (cm * t - r0), rtol=1e-12, atol=1e-12)
+    assert abs(R[:, 3].sum()) <= 1e-12 * np.abs(R[:, 3]).max()
+    assert np.abs(R[:, 3]).max() > 1e-6
+
+
+def test_inertia_history_matching_the_state_cancels():
+    """r_s = cm d at the current (non-uniform) d: the inertia forces cancel
+    node by node and the residual is the quasi-static one."""
+    p = _problem("artery")
+    d = fe.Discretization(p)
+    v = synth.random_state(p, 13, u_scale=0.1, p_scale=0.3)
+    R0 = d.residual(v.ravel(), 0.4)
+    d.set_inertia(25.0, 25.0 * v.reshape(d.n, 4)[:, 0:3])
+    R1 = d.residual(v.ravel(), 0.4)
+    assert np.abs(R1 - R0).max() <= 1e-12 * np.abs(R0).max()
