@@ -216,6 +216,32 @@ hfsi_status hfsi_set_materials(hfsi_ctx* ctx, int32_t n_mat, const hfsi_material
 hfsi_status hfsi_set_bc(hfsi_ctx* ctx, const uint8_t* dir_mask, int64_t n_tris, const int32_t* tris,
                         const double* traction);
 
+/* Newmark-beta inertia of the structure (sections "Temporal discretization
+ * for the structure sub-problem" and "The time semi-discretized structure
+ * weak formulation", and the stabilisation term eq. stelas).  rho = density
+ * rho_s (0 turns inertia off: quasi-static, the default and the state after
+ * hfsi_set_mesh); beta in (0, 1], gamma in [0, 1], dt > 0 (the paper takes
+ * beta = 0.625, gamma = 1).  With inertia on, every assembly adds
+ * rho_s/(beta dt^2) (d, v) - (r_s, v) to the displacement rows and
+ * tau (r_s - rho_s/(beta dt^2) d, F^{-T} grad q) to the pressure rows, with
+ * their exact derivatives, r_s being the P1 history field of the current
+ * time step (zero after this call: a body at rest at d = 0).
+ * HFSI_E_ARG on bad values. */
+hfsi_status hfsi_set_newmark(hfsi_ctx* ctx, double rho, double beta, double gamma, double dt);
+
+/* Start a time step from device state v_prev [N] (its displacement entries
+ * are d^{n-1}) and device nodal velocity vel and acceleration acc [n][3]:
+ * r_s = rho_s/(beta dt^2) d^{n-1} + rho_s/(beta dt) vel + rho_s (1-2 beta)/(2 beta) acc.
+ * HFSI_E_ORDER when inertia is off. */
+hfsi_status hfsi_newmark_history(hfsi_ctx* ctx, const double* v_prev, const double* vel, const double* acc);
+
+/* End a time step: with d^n from device v_new [N] and d^{n-1} from v_prev,
+ * overwrite device acc [n][3] with (d^n - d^{n-1})/(beta dt^2) - vel/(beta dt)
+ * - (1-2 beta)/(2 beta) acc and device vel [n][3] with vel + gamma dt acc^n +
+ * (1-gamma) dt acc^{n-1}.  HFSI_E_ORDER when inertia is off. */
+hfsi_status hfsi_newmark_update(hfsi_ctx* ctx, const double* v_new, const double* v_prev, double* vel,
+                                double* acc);
+
 /* --------------------------------------------------------------- hot path */
 
 /* Residual and consistent tangent at device state v [N] for load factor

@@ -6,8 +6,13 @@
 //   R^u_a = V (F S' G_a - pbar J g_a),                      g_a = F^{-T} G_a
 //   R^p_a = -V/4 (J-1) - 1/kappa sum_b M_ab p_b - tau V J g_a . ghat,
 //           ghat = F^{-T} grad p,  M_ab = V (1+delta_ab)/20,  tau = h^2/(4 mu^l)
-// (weak residuals of the structure with the PSPG term of eq. stelas,
-// quasi-static), and the exact derivative K = [A B1^T; B2 -C] (eq. globsys):
+// (weak residuals of the structure with the PSPG term of eq. stelas), with
+// the Newmark-beta inertia when it is on (cm = rho_s/(beta dt^2), r_b the
+// nodal history field r_s, m = V/4 sum_b (r_b - cm d_b) / V the element mean
+// of r_s - cm d):
+//   R^u_a += sum_b M_ab (cm d_b - r_b),   R^p_a += tau V g_a . m,
+//   A_ab  += cm M_ab I,                   B2_ab += tau V (-cm/4 - g_b . m) g_a^T,
+// and the exact derivative K = [A B1^T; B2 -C] (eq. globsys):
 //   A_ab  = V [ (G_a.S'G_b) I + B_a^T D B_b ] - pbar V J (g_a g_b^T - g_b g_a^T)
 //   B1^T_ab = -V/4 J g_a
 //   B2_ab = -V/4 J g_b^T - tau V J [ (g_a.ghat) g_b^T - (g_b.ghat) g_a^T - (g_a.g_b) ghat^T ]
@@ -148,7 +153,8 @@ k_element(int e0, int e1, int m, const int* __restrict__ T, const int* __restric
           const double* __restrict__ mtab, const double* __restrict__ Gs, const double* __restrict__ Vs,
           const double* __restrict__ Hs, const double* __restrict__ fib, const int* __restrict__ slot,
           const double* __restrict__ v, double* __restrict__ R, double* __restrict__ Kval, int want_K,
-          unsigned long long* __restrict__ minJ, int* __restrict__ inverted) {
+          unsigned long long* __restrict__ minJ, int* __restrict__ inverted, double cm,
+          const double* __restrict__ rs) {
   const int e = e0 + blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= e1) return;
   int nd[4];
@@ -233,6 +239,21 @@ k_element(int e0, int e1, int m, const int* __restrict__ T, const int* __restric
   double gdot[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) gdot[a] = g[a][0] * gh[0] + g[a][1] * gh[1] + g[a][2] * gh[2];
+  // inertia: ru_b = cm d_b - r_b, mv = mean of r_s - cm d, gm_a = g_a . mv
+  const bool dyn = rs != nullptr;
+  double ru[4][3], gm[4] = {0.0, 0.0, 0.0, 0.0};
+  if (dyn) {
+    double mv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        ru[a][i] = cm * u[a][i] - rs[3 * nd[a] + i];
+        mv[i] -= 0.25 * ru[a][i];
+      }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) gm[a] = g[a][0] * mv[0] + g[a][1] * mv[1] + g[a][2] * mv[2];
+  }
   const double VJ_ = V * Jd;
   const double tVJ = tau * V * Jd;
   double FS[3][3];
@@ -253,6 +274,16 @@ k_element(int e0, int e1, int m, const int* __restrict__ T, const int* __restric
     for (int b = 0; b < 4; ++b) Mp += (a == b ? 2.0 : 1.0) * p[b];
     Mp *= V / 20.0;
     Ra[3] += -0.25 * V * (Jd - 1.0) - Mp / kappa - tVJ * gdot[a];
+    if (dyn) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        double Mr = 0.0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) Mr += (a == b ? 2.0 : 1.0) * ru[b][i];
+        Ra[i] += V / 20.0 * Mr;
+      }
+      Ra[3] += tau * V * gm[a];
+    }
   }
   if (!want_K) return;
 
@@ -285,6 +316,7 @@ k_element(int e0, int e1, int m, const int* __restrict__ T, const int* __restric
                       DB[i][5] * bb[5];
           double val = V * mm - pbar * VJ_ * (g[a][i] * g[b][k] - g[b][i] * g[a][k]);
           if (i == k) val += geo;
+          if (dyn && i == k) val += cm * (a == b ? 2.0 : 1.0) * V / 20.0;
           blk[i * 4 + k] = val;
         }
       }
@@ -294,6 +326,9 @@ k_element(int e0, int e1, int m, const int* __restrict__ T, const int* __restric
 #pragma unroll
       for (int k = 0; k < 3; ++k)
         blk[12 + k] = -0.25 * VJ_ * g[b][k] - tVJ * (gdot[a] * g[b][k] - gdot[b] * g[a][k] - gab * gh[k]);
+      if (dyn)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) blk[12 + k] += tau * V * (-0.25 * cm - gm[b]) * g[a][k];
       blk[15] = -((a == b ? 2.0 : 1.0) * V / 20.0 / kappa + tVJ * gab);
       double* dst = Kval + 16 * (size_t)slot[(a * 4 + b) * m + e];
 #pragma unroll
@@ -446,7 +481,8 @@ void assemble(hfsi_ctx* c, const double* v, double load, double* R, hfsi_assembl
     int e0 = c->colour_ptr[q], e1 = c->colour_ptr[q + 1];
     k_element<<<div_up(e1 - e0, 128), 128, 0, s>>>(e0, e1, m, c->tets.p, c->mat.p, c->mtab.p, c->G.p, c->V.p, c->h.p,
                                                    c->has_fib ? c->fib.p : nullptr, c->slot.p, v, R, c->Kval.p, 1,
-                                                   (unsigned long long*)c->scal.p, c->iscal.p);
+                                                   (unsigned long long*)c->scal.p, c->iscal.p, c->cm,
+                                                   c->cm > 0.0 ? c->rs.p : nullptr);
     HIP_LAUNCH_CHECK();
   }
   k_residual_bc<<<div_up(n, 256), 256, 0, s>>>(n, load, c->fext.p, c->dir.p, R);
@@ -475,11 +511,11 @@ void assemble(hfsi_ctx* c, const double* v, double load, double* R, hfsi_assembl
 
 // Per element: gradients (96 B), volume and size (16 B), connectivity (16 B),
 // material id (4 B), fibres (48 B, anisotropic meshes); per node the state
-// (32 B); the tangent values (8 B per scalar entry) and the residual (8 B per
+// (32 B) and, with inertia, the history field (24 B); the tangent values (8 B per scalar entry) and the residual (8 B per
 // dof) written once.
 double assembly_bytes(hfsi_ctx* c) {
   const double per_elem = 96.0 + 16.0 + 16.0 + 4.0 + (c->has_fib ? 48.0 : 0.0);
-  return c->m * per_elem + c->n * 32.0 + 16.0 * c->nb * 8.0 + 4.0 * c->n * 8.0;
+  return c->m * per_elem + c->n * (32.0 + (c->cm > 0.0 ? 24.0 : 0.0)) + 16.0 * c->nb * 8.0 + 4.0 * c->n * 8.0;
 }
 
 // The colour launches of one assembly at the zero state (timing only).
@@ -498,7 +534,7 @@ void assemble_kernels_only(hfsi_ctx* c) {
     k_element<<<div_up(e1 - e0, 128), 128, 0, s>>>(e0, e1, c->m, c->tets.p, c->mat.p, c->mtab.p, c->G.p, c->V.p,
                                                    c->h.p, c->has_fib ? c->fib.p : nullptr, c->slot.p, c->kdv.p,
                                                    c->ktmp.p, c->Kval.p, 1, (unsigned long long*)c->scal.p,
-                                                   c->iscal.p);
+                                                   c->iscal.p, c->cm, c->cm > 0.0 ? c->rs.p : nullptr);
     HIP_LAUNCH_CHECK();
   }
 }
@@ -564,5 +600,86 @@ extern "C" hfsi_status hfsi_export_tangent(hfsi_ctx* c, int32_t* block_ptr, int3
   cp(a_val, c->A.val.p, sizeof(double) * c->A.nnz);
   cp(schur, c->schur.p, sizeof(double) * c->n);
   HIP_CHECK(hipStreamSynchronize(s));
+  HFSI_ABI_END(c)
+}
+
+namespace {
+
+// r_s = c0 d + c1 vel + c2 acc per displacement dof (d from the node-
+// interleaved state).
+__global__ void k_newmark_history(int n, double c0, double c1, double c2, const double* __restrict__ v,
+                                  const double* __restrict__ vel, const double* __restrict__ acc,
+                                  double* __restrict__ rs) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3L * n) return;
+  const long node = t / 3;
+  const int i = (int)(t - 3 * node);
+  rs[t] = c0 * v[4 * node + i] + c1 * vel[t] + c2 * acc[t];
+}
+
+// a_new = (d_new - d_prev) / (beta dt^2) - vel / (beta dt) - (1-2beta)/(2beta) acc,
+// vel += gamma dt a_new + (1-gamma) dt acc, in place.
+__global__ void k_newmark_update(int n, double beta, double gamma, double dt, const double* __restrict__ vn,
+                                 const double* __restrict__ vp, double* __restrict__ vel, double* __restrict__ acc) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3L * n) return;
+  const long node = t / 3;
+  const int i = (int)(t - 3 * node);
+  const double a0 = acc[t], v0 = vel[t];
+  const double a1 = (vn[4 * node + i] - vp[4 * node + i]) / (beta * dt * dt) - v0 / (beta * dt) -
+                    (1.0 - 2.0 * beta) / (2.0 * beta) * a0;
+  vel[t] = v0 + gamma * dt * a1 + (1.0 - gamma) * dt * a0;
+  acc[t] = a1;
+}
+
+void require_newmark(hfsi_ctx* c, const char* what) {
+  if (!(c->cm > 0.0)) fail(HFSI_E_ORDER, std::string(what) + ": Newmark inertia is off (hfsi_set_newmark)");
+}
+
+}  // namespace
+
+extern "C" hfsi_status hfsi_set_newmark(hfsi_ctx* c, double rho, double beta, double gamma, double dt) {
+  HFSI_ABI_BEGIN(c)
+  require_stage(c, 1, "set_newmark");
+  if (!(rho >= 0.0) || !std::isfinite(rho)) fail(HFSI_E_ARG, "set_newmark: rho must be finite and >= 0");
+  if (rho == 0.0) {
+    c->nm_rho = 0.0;
+    c->cm = 0.0;
+    c->rs.release();
+  } else {
+    if (!(beta > 0.0 && beta <= 1.0) || !(gamma >= 0.0 && gamma <= 1.0) || !(dt > 0.0) || !std::isfinite(dt))
+      fail(HFSI_E_ARG, "set_newmark: need 0 < beta <= 1, 0 <= gamma <= 1, dt > 0");
+    const double cm = rho / (beta * dt * dt);
+    if (!std::isfinite(cm)) fail(HFSI_E_ARG, "set_newmark: rho / (beta dt^2) overflows");
+    c->nm_rho = rho;
+    c->nm_beta = beta;
+    c->nm_gamma = gamma;
+    c->nm_dt = dt;
+    c->cm = cm;
+    c->rs.zero(3 * (size_t)c->n, c->stream);
+  }
+  HFSI_ABI_END(c)
+}
+
+extern "C" hfsi_status hfsi_newmark_history(hfsi_ctx* c, const double* v_prev, const double* vel,
+                                            const double* acc) {
+  HFSI_ABI_BEGIN(c)
+  require_newmark(c, "newmark_history");
+  if (!v_prev || !vel || !acc) fail(HFSI_E_ARG, "newmark_history: null vector");
+  const double b = c->nm_beta, dt = c->nm_dt, rho = c->nm_rho;
+  k_newmark_history<<<div_up(3L * c->n, 256), 256, 0, c->stream>>>(
+      c->n, rho / (b * dt * dt), rho / (b * dt), rho * (1.0 - 2.0 * b) / (2.0 * b), v_prev, vel, acc, c->rs.p);
+  HIP_LAUNCH_CHECK();
+  HFSI_ABI_END(c)
+}
+
+extern "C" hfsi_status hfsi_newmark_update(hfsi_ctx* c, const double* v_new, const double* v_prev, double* vel,
+                                           double* acc) {
+  HFSI_ABI_BEGIN(c)
+  require_newmark(c, "newmark_update");
+  if (!v_new || !v_prev || !vel || !acc) fail(HFSI_E_ARG, "newmark_update: null vector");
+  k_newmark_update<<<div_up(3L * c->n, 256), 256, 0, c->stream>>>(c->n, c->nm_beta, c->nm_gamma, c->nm_dt, v_new,
+                                                                  v_prev, vel, acc);
+  HIP_LAUNCH_CHECK();
   HFSI_ABI_END(c)
 }

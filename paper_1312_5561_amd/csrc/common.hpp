@@ -247,6 +247,10 @@ struct hfsi_ctx {
   // boundary
   hfsi::DevBuf<uint8_t> dir;     // [4n]
   hfsi::DevBuf<double> fext;     // [3n] nodal load at load factor 1
+  // Newmark-beta inertia: cm = rho_s / (beta dt^2) (0 = quasi-static) and
+  // the history field r_s [3n] of the current time step
+  double nm_rho = 0.0, nm_beta = 0.625, nm_gamma = 1.0, nm_dt = 0.0, cm = 0.0;
+  hfsi::DevBuf<double> rs;
   hfsi::DevBuf<double> schur;    // [n]
   // A block (scalar CSR over 3n dofs) and its source positions in Kval
   hfsi::Csr<double> A;

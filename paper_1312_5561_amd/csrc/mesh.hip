@@ -313,6 +313,9 @@ extern "C" hfsi_status hfsi_set_mesh(hfsi_ctx* c, int64_t n_nodes, const double*
   c->stage = 0;
   c->H.ready = false;
   c->H.reusable = false;
+  c->nm_rho = 0.0;  // a new mesh starts quasi-static
+  c->cm = 0.0;
+  c->rs.release();
   colour_elements(n, m, tets, c->perm, c->colour_ptr);
 
   // element arrays in colour order, structure of arrays

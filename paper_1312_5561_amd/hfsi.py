@@ -135,6 +135,9 @@ def load():
         "hfsi_set_materials": [vp, i32, vp],
         "hfsi_set_bc": [vp, vp, i64, vp, vp],
         "hfsi_assemble_residual_tangent": [vp, vp, dbl, vp, C.POINTER(CsrView), C.POINTER(AssemblyInfo)],
+        "hfsi_set_newmark": [vp, dbl, dbl, dbl, dbl],
+        "hfsi_newmark_history": [vp, vp, vp, vp],
+        "hfsi_newmark_update": [vp, vp, vp, vp, vp],
         "hfsi_amg_setup": [vp, C.POINTER(AmgParams), C.POINTER(AmgInfo)],
         "hfsi_amg_resetup": [vp, C.POINTER(AmgParams), C.POINTER(AmgInfo)],
         "hfsi_krylov_amg_solve": [vp, vp, vp, C.POINTER(SolveParams), C.POINTER(SolveInfo)],
@@ -247,6 +250,16 @@ class Context:
         mats = [dict(m, theta=theta or 0.0) for m in prob.materials]
         self.set_materials(mats)
         self.set_bc(prob.dir_mask, prob.tris, prob.traction)
+
+    def set_newmark(self, rho, dt=1.0, beta=0.625, gamma=1.0):
+        """Newmark-beta inertia (rho = 0: quasi-static); history starts at rest."""
+        self._check(self.lib.hfsi_set_newmark(self.h, rho, beta, gamma, dt))
+
+    def newmark_history(self, v_prev, vel, acc):
+        self._check(self.lib.hfsi_newmark_history(self.h, _ptr(v_prev), _ptr(vel), _ptr(acc)))
+
+    def newmark_update(self, v_new, v_prev, vel, acc):
+        self._check(self.lib.hfsi_newmark_update(self.h, _ptr(v_new), _ptr(v_prev), _ptr(vel), _ptr(acc)))
 
     # ---- hot path
     def assemble_residual_tangent(self, v, load, R):
