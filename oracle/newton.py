@@ -5,6 +5,13 @@ relative residual eps_1, update v_{k+1} = v_k + dv and stop when
 ||dv_k||_M <= eps_2 ||dv_0||_M (eq. newstop in the mass-matrix form with
 M = diag(M1, M2)).  Loads are applied in increments lambda = k / n_inc,
 each starting from the previous converged state.
+
+Adaptive inner tolerance (the inexact-Newton analysis of the same section):
+the inner reduction of step k is the square of the outer reduction reached
+at step k-1, eps_1,k = eps_2,k-1^2, read here with the relative outer
+reduction eps_2,k-1 = ||dv_{k-1}||_M / ||dv_0||_M of the stopping rule;
+the first step (no reduction yet) and very small values are clamped to
+[eps1_min, eps1_max].
 """
 from __future__ import annotations
 
@@ -23,6 +30,18 @@ class NewtonParams:
     restart: int = 50
     lin_maxit: int = 500
     amg: amg.AmgParams = dataclasses.field(default_factory=amg.AmgParams)
+    adaptive: bool = False   # eps_1,k = eps_2,k-1^2 instead of lin_tol
+    eps1_max: float = 1e-2
+    eps1_min: float = 1e-12
+
+
+def inner_tolerance(prm: NewtonParams, k, dv_prev=None, dv_first=None):
+    """Relative residual reduction asked of the linear solve of step k."""
+    if not prm.adaptive:
+        return prm.lin_tol
+    if k == 0 or not dv_first:
+        return prm.eps1_max
+    return min(prm.eps1_max, max(prm.eps1_min, (dv_prev / dv_first) ** 2))
 
 
 def linear_system(disc: fe.Discretization, v, load):
@@ -34,22 +53,24 @@ def linear_system(disc: fe.Discretization, v, load):
     return K, -R, A, B2, s
 
 
-def newton_step(disc, v, load, prm: NewtonParams):
+def newton_step(disc, v, load, prm: NewtonParams, tol=None):
     """One Newton update; returns (v_new, ||dv||_M, solve info)."""
     K, b, A, B2, s = linear_system(disc, v.ravel(), load)
     M, _ = krylov.amg_preconditioner(A, B2, s, disc.n, prm.amg)
-    dv, info = krylov.fgmres(K, M, b, m=prm.restart, maxit=prm.lin_maxit, tol=prm.lin_tol)
+    dv, info = krylov.fgmres(K, M, b, m=prm.restart, maxit=prm.lin_maxit, tol=prm.lin_tol if tol is None else tol)
     return v.ravel() + dv, disc.mass_norm(dv), info
 
 
 def solve_increment(disc, v, load, prm: NewtonParams, log=None):
     v = v.ravel().copy()
     n0 = None
+    nrm = None
     for k in range(prm.max_iter):
-        v, nrm, info = newton_step(disc, v, load, prm)
+        tol = inner_tolerance(prm, k, nrm, n0)
+        v, nrm, info = newton_step(disc, v, load, prm, tol)
         if log is not None:
             log.append(dict(load=load, it=k, dv_M=nrm, krylov=info.iterations,
-                            rel_res=info.rel_residual))
+                            rel_res=info.rel_residual, eps1=tol))
         if n0 is None:
             n0 = nrm
         if nrm <= prm.eps2 * n0 or n0 == 0.0:

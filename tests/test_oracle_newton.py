@@ -94,3 +94,30 @@ def test_newton_converges_quadratically():
     # log(e_{k+1}) / log(e_k) relative to the first step approaches 2
     ratios = [np.log(r[k + 1] / r[0]) / np.log(r[k] / r[0]) for k in range(1, len(r) - 1) if r[k + 1] > 1e-14 * r[0]]
     assert ratios and min(ratios) > 1.7
+
+
+def test_adaptive_inner_tolerance_keeps_quadratic_convergence():
+    """With eps_1,k = eps_2,k-1^2 the inexact Newton iteration keeps the
+    quadratic rate of the exact one (the point of the rule): it reaches the
+    same state in at most one more step, every step after the first asks the
+    square of the previous relative increment, and it spends fewer Krylov
+    iterations than solving every step to 1e-8."""
+    prob = synth.cube_problem(4)
+    d = fe.Discretization(prob)
+    exact, adapt = [], []
+    v_exact, ok1, k1 = newton.solve_increment(d, np.zeros(4 * d.n), 1.0, newton.NewtonParams(lin_tol=1e-12), exact)
+    prm = newton.NewtonParams(adaptive=True)
+    v_adapt, ok2, k2 = newton.solve_increment(d, np.zeros(4 * d.n), 1.0, prm, adapt)
+    assert ok1 and ok2 and k2 <= k1 + 1
+    assert np.linalg.norm(v_adapt - v_exact) <= 1e-9 * np.linalg.norm(v_exact)
+    dv = [e["dv_M"] for e in adapt]
+    assert adapt[0]["eps1"] == prm.eps1_max
+    for k in range(1, len(adapt)):
+        want = min(prm.eps1_max, max(prm.eps1_min, (dv[k - 1] / dv[0]) ** 2))
+        assert adapt[k]["eps1"] == want and adapt[k]["rel_res"] <= want
+    fixed = []
+    newton.solve_increment(d, np.zeros(4 * d.n), 1.0, newton.NewtonParams(), fixed)
+    assert sum(e["krylov"] for e in adapt) < sum(e["krylov"] for e in fixed)
+    ratios = [np.log(dv[k + 1] / dv[0]) / np.log(dv[k] / dv[0]) for k in range(1, len(dv) - 1)
+              if dv[k + 1] > 1e-14 * dv[0]]
+    assert ratios and min(ratios) > 1.6
