@@ -186,6 +186,36 @@ typedef struct {
   int32_t amg_reused;   /* 1 if this step re-used the previous coarse grids */
 } hfsi_newton_info;
 
+typedef struct {
+  size_t struct_size;
+  hfsi_newton_params step;  /* AMG and Krylov settings of every iteration;
+                               step.solve.tol is the inner tolerance when
+                               adaptive = 0; step.amg_reuse = 1 keeps the
+                               first iteration's coarse grids for the later
+                               ones                                        */
+  double eps2;              /* stop at ||dv_k||_M <= eps2 ||dv_0||_M (eq.
+                               newstop, relative form), default 1e-10       */
+  int32_t max_newton;       /* default 25                                   */
+  int32_t adaptive;         /* 1: inner tolerance eps_1,k = eps_2,k-1^2 with
+                               eps_2,k-1 = ||dv_k-1||_M / ||dv_0||_M (the
+                               inexact-Newton rule of Section "Newton's
+                               Method"), clamped to [eps1_min, eps1_max];
+                               eps1_max for the first iteration             */
+  double eps1_max;          /* default 1e-2                                 */
+  double eps1_min;          /* default 1e-12                                */
+} hfsi_newton_solve_params;
+
+typedef struct {
+  size_t struct_size;
+  int32_t newton_iterations;
+  int32_t krylov_iterations;  /* summed over the iterations                 */
+  int32_t converged;
+  double dv_mass_norm[32];    /* ||dv_k||_M of the first 32 iterations      */
+  double eps1[32];            /* their inner tolerances                     */
+  int32_t krylov[32];         /* their Krylov iterations                    */
+  double seconds;             /* wall time of the call                      */
+} hfsi_newton_solve_info;
+
 /* ---------------------------------------------------------------- context */
 
 /* Create a context on HIP device `device`; `stream` is a hipStream_t (NULL =
@@ -290,6 +320,16 @@ hfsi_status hfsi_krylov_amg_solve(hfsi_ctx* ctx, const double* b, double* x, con
  * report ||dv||_M for the stopping rule eq. newstop. */
 hfsi_status hfsi_newton_step(hfsi_ctx* ctx, double* v, double load, const hfsi_newton_params* prm,
                              hfsi_newton_info* info);
+
+/* Newton's method at load factor `load` from device state v [N] (updated in
+ * place): iterations of hfsi_newton_step until eq. newstop holds in the
+ * relative form ||dv_k||_M <= eps2 ||dv_0||_M, with a fixed or an adaptive
+ * inner tolerance (Section "Newton's Method"; see
+ * hfsi_newton_solve_params).  An iteration whose linear solve stops at
+ * step.solve.max_iter is kept (inexact Newton).  HFSI_NOT_CONVERGED when
+ * max_newton iterations do not meet the criterion. */
+hfsi_status hfsi_newton_solve(hfsi_ctx* ctx, double* v, double load, const hfsi_newton_solve_params* prm,
+                              hfsi_newton_solve_info* info);
 
 /* ------------------------------------------------ inspection and testing */
 

@@ -12,6 +12,7 @@
 //    Givens rotations on the device, one host synchronisation per iteration
 //    for the convergence test, true residual recomputed after every cycle.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <functional>
 #include <type_traits>
@@ -1586,23 +1587,38 @@ extern "C" hfsi_status hfsi_time_kernel(hfsi_ctx* c, int32_t kernel, int32_t rep
   HFSI_ABI_END(c)
 }
 
-extern "C" hfsi_status hfsi_newton_step(hfsi_ctx* c, double* v, double load, const hfsi_newton_params* prm,
-                                        hfsi_newton_info* info) {
-  HFSI_ABI_BEGIN(c)
-  require_stage(c, 3, "newton_step");
-  if (!v) fail(HFSI_E_ARG, "newton_step: null state");
+namespace {
+
+struct EventPair {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  EventPair() {
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+  }
+  ~EventPair() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+};
+
+void check_newton_params(const hfsi_newton_params* prm) {
   if (!prm || prm->struct_size != sizeof(hfsi_newton_params)) fail(HFSI_E_ARG, "newton params: struct_size mismatch");
-  if (info && info->struct_size != sizeof(hfsi_newton_info)) fail(HFSI_E_ARG, "newton info: struct_size mismatch");
   hfsi::check_amg_params(&prm->amg);
   check_solve_params(&prm->solve);
+}
+
+// One Newton iteration (Section "Newton's Method"): assemble R and K at v,
+// set up the hierarchy (or re-set it up on the kept coarse grids when
+// `reuse` and one is available), solve K dv = -R to sp.tol, v += dv.
+// Returns whether the linear solve converged.
+bool newton_iteration(hfsi_ctx* c, double* v, double load, const hfsi_amg_params& amg, const hfsi_solve_params& sp,
+                      bool reuse, hfsi_newton_info* info) {
   const long N = 4L * c->n;
   hipStream_t s = c->stream;
   c->kdv.ensure(N);
   c->ktmp.ensure(N);
-  hipEvent_t t0, t1;
-  HIP_CHECK(hipEventCreate(&t0));
-  HIP_CHECK(hipEventCreate(&t1));
-  HIP_CHECK(hipEventRecord(t0, s));
+  EventPair ev;
+  HIP_CHECK(hipEventRecord(ev.e0, s));
   hfsi_assembly_info ai{sizeof(hfsi_assembly_info)};
   hfsi::assemble(c, v, load, c->ktmp.p, &ai);
   c->stage = 4;
@@ -1612,24 +1628,22 @@ extern "C" hfsi_status hfsi_newton_step(hfsi_ctx* c, double* v, double load, con
   const double rnorm = hfsi::read_scalar(c, c->scal.p + 6);
   if (!std::isfinite(rnorm)) fail(HFSI_E_NAN, "newton_step: non-finite residual");
   hfsi_amg_info mi{sizeof(hfsi_amg_info)};
-  const bool reuse = prm->amg_reuse != 0 && c->H.reusable;
-  if (reuse) hfsi::amg_resetup_level0(c, prm->amg, &mi);
-  else hfsi::amg_setup_level0(c, prm->amg, &mi);
+  reuse = reuse && c->H.reusable;
+  if (reuse) hfsi::amg_resetup_level0(c, amg, &mi);
+  else hfsi::amg_setup_level0(c, amg, &mi);
   // b = -R, dv = 0
   k_negate<<<div_up(N, 256), 256, 0, s>>>(N, c->ktmp.p, c->ktmp.p);
   HIP_LAUNCH_CHECK();
   HIP_CHECK(hipMemsetAsync(c->kdv.p, 0, sizeof(double) * N, s));
   hfsi_solve_info si{sizeof(hfsi_solve_info)};
-  hfsi::krylov_solve(c, c->ktmp.p, c->kdv.p, prm->solve, &si);
+  hfsi::krylov_solve(c, c->ktmp.p, c->kdv.p, sp, &si);
   k_axpy<<<div_up(N, 256), 256, 0, s>>>(N, 1.0, c->kdv.p, v);
   HIP_LAUNCH_CHECK();
   const double dvm = hfsi::mass_norm(c, c->kdv.p);
-  HIP_CHECK(hipEventRecord(t1, s));
-  HIP_CHECK(hipEventSynchronize(t1));
+  HIP_CHECK(hipEventRecord(ev.e1, s));
+  HIP_CHECK(hipEventSynchronize(ev.e1));
   float ms = 0.f;
-  HIP_CHECK(hipEventElapsedTime(&ms, t0, t1));
-  HIP_CHECK(hipEventDestroy(t0));
-  HIP_CHECK(hipEventDestroy(t1));
+  HIP_CHECK(hipEventElapsedTime(&ms, ev.e0, ev.e1));
   if (!std::isfinite(dvm)) fail(HFSI_E_NAN, "newton_step: non-finite update");
   if (info) {
     info->dv_mass_norm = dvm;
@@ -1643,6 +1657,71 @@ extern "C" hfsi_status hfsi_newton_step(hfsi_ctx* c, double* v, double load, con
     info->amg_levels = mi.levels;
     info->amg_reused = reuse ? 1 : 0;
   }
-  if (!si.converged) return HFSI_NOT_CONVERGED;
+  return si.converged != 0;
+}
+
+}  // namespace
+
+extern "C" hfsi_status hfsi_newton_step(hfsi_ctx* c, double* v, double load, const hfsi_newton_params* prm,
+                                        hfsi_newton_info* info) {
+  HFSI_ABI_BEGIN(c)
+  require_stage(c, 3, "newton_step");
+  if (!v) fail(HFSI_E_ARG, "newton_step: null state");
+  check_newton_params(prm);
+  if (info && info->struct_size != sizeof(hfsi_newton_info)) fail(HFSI_E_ARG, "newton info: struct_size mismatch");
+  if (!newton_iteration(c, v, load, prm->amg, prm->solve, prm->amg_reuse != 0, info)) return HFSI_NOT_CONVERGED;
+  HFSI_ABI_END(c)
+}
+
+extern "C" hfsi_status hfsi_newton_solve(hfsi_ctx* c, double* v, double load, const hfsi_newton_solve_params* prm,
+                                         hfsi_newton_solve_info* info) {
+  HFSI_ABI_BEGIN(c)
+  require_stage(c, 3, "newton_solve");
+  if (!v) fail(HFSI_E_ARG, "newton_solve: null state");
+  if (!prm || prm->struct_size != sizeof(hfsi_newton_solve_params))
+    fail(HFSI_E_ARG, "newton solve params: struct_size mismatch");
+  check_newton_params(&prm->step);
+  if (!(prm->eps2 > 0.0) || prm->max_newton < 1 || prm->adaptive < 0 || prm->adaptive > 1 ||
+      !(prm->eps1_min > 0.0) || !(prm->eps1_max >= prm->eps1_min) || !(prm->eps1_max < 1.0))
+    fail(HFSI_E_ARG, "newton solve params: need eps2 > 0, max_newton >= 1, 0 < eps1_min <= eps1_max < 1");
+  if (info && info->struct_size != sizeof(hfsi_newton_solve_info))
+    fail(HFSI_E_ARG, "newton solve info: struct_size mismatch");
+  auto t_start = std::chrono::steady_clock::now();
+  hfsi_solve_params sp = prm->step.solve;
+  double dv0 = 0.0, dv_prev = 0.0;
+  int its = 0, kry = 0;
+  bool done = false;
+  if (info) {
+    info->newton_iterations = 0;
+    info->krylov_iterations = 0;
+    info->converged = 0;
+  }
+  for (int k = 0; k < prm->max_newton && !done; ++k) {
+    // inner tolerance: eps_1,k = eps_2,k-1^2 with the relative increment
+    // eps_2,k-1 = ||dv_k-1||_M / ||dv_0||_M of the stopping rule, clamped
+    if (prm->adaptive) {
+      if (k == 0 || dv0 == 0.0) sp.tol = prm->eps1_max;
+      else sp.tol = std::min(prm->eps1_max, std::max(prm->eps1_min, (dv_prev / dv0) * (dv_prev / dv0)));
+    }
+    hfsi_newton_info ni{sizeof(hfsi_newton_info)};
+    newton_iteration(c, v, load, prm->step.amg, sp, k > 0 && prm->step.amg_reuse != 0, &ni);
+    ++its;
+    kry += ni.krylov_iterations;
+    if (k == 0) dv0 = ni.dv_mass_norm;
+    dv_prev = ni.dv_mass_norm;
+    if (info && k < 32) {
+      info->dv_mass_norm[k] = ni.dv_mass_norm;
+      info->eps1[k] = sp.tol;
+      info->krylov[k] = ni.krylov_iterations;
+    }
+    done = dv0 == 0.0 || ni.dv_mass_norm <= prm->eps2 * dv0;
+  }
+  if (info) {
+    info->newton_iterations = its;
+    info->krylov_iterations = kry;
+    info->converged = done ? 1 : 0;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  }
+  if (!done) return HFSI_NOT_CONVERGED;
   HFSI_ABI_END(c)
 }

@@ -81,6 +81,18 @@ class NewtonInfo(C.Structure):
                 ("amg_levels", C.c_int32), ("amg_reused", C.c_int32)]
 
 
+class NewtonSolveParams(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("step", NewtonParams), ("eps2", C.c_double),
+                ("max_newton", C.c_int32), ("adaptive", C.c_int32), ("eps1_max", C.c_double),
+                ("eps1_min", C.c_double)]
+
+
+class NewtonSolveInfo(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("newton_iterations", C.c_int32), ("krylov_iterations", C.c_int32),
+                ("converged", C.c_int32), ("dv_mass_norm", C.c_double * 32), ("eps1", C.c_double * 32),
+                ("krylov", C.c_int32 * 32), ("seconds", C.c_double)]
+
+
 class TrainParams(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("batch", C.c_int32), ("lr", C.c_double), ("beta1", C.c_double),
                 ("beta2", C.c_double), ("eps", C.c_double)]
@@ -116,6 +128,12 @@ def newton_params(amg=None, solve=None, amg_reuse=0):
     return NewtonParams(C.sizeof(NewtonParams), amg or amg_params(), solve or solve_params(), amg_reuse)
 
 
+def newton_solve_params(step=None, eps2=1e-10, max_newton=25, adaptive=0, eps1_max=1e-2, eps1_min=1e-12):
+    """adaptive=1: inner tolerance eps_1,k = (||dv_k-1||_M / ||dv_0||_M)^2."""
+    return NewtonSolveParams(C.sizeof(NewtonSolveParams), step or newton_params(), eps2, max_newton, adaptive,
+                             eps1_max, eps1_min)
+
+
 _lib = None
 
 
@@ -142,6 +160,7 @@ def load():
         "hfsi_amg_resetup": [vp, C.POINTER(AmgParams), C.POINTER(AmgInfo)],
         "hfsi_krylov_amg_solve": [vp, vp, vp, C.POINTER(SolveParams), C.POINTER(SolveInfo)],
         "hfsi_newton_step": [vp, vp, dbl, C.POINTER(NewtonParams), C.POINTER(NewtonInfo)],
+        "hfsi_newton_solve": [vp, vp, dbl, C.POINTER(NewtonSolveParams), C.POINTER(NewtonSolveInfo)],
         "hfsi_amg_setup_csr": [vp, i32, vp, vp, vp, vp, C.POINTER(AmgParams), C.POINTER(AmgInfo)],
         "hfsi_amg_export": [vp, i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64), vp, vp, vp, vp],
         "hfsi_vcycle": [vp, vp, vp],
@@ -303,6 +322,12 @@ class Context:
         prm = prm or newton_params()
         info = NewtonInfo(C.sizeof(NewtonInfo))
         code = self._check(self.lib.hfsi_newton_step(self.h, _ptr(v), load, C.byref(prm), C.byref(info)))
+        return info, code
+
+    def newton_solve(self, v, load, prm=None):
+        prm = prm or newton_solve_params()
+        info = NewtonSolveInfo(C.sizeof(NewtonSolveInfo))
+        code = self._check(self.lib.hfsi_newton_solve(self.h, _ptr(v), load, C.byref(prm), C.byref(info)))
         return info, code
 
     # ---- inspection

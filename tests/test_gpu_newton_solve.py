@@ -1,0 +1,69 @@
+"""GPU Newton solve (hfsi_newton_solve) with fixed and adaptive inner
+tolerances against the oracle.
+
+The 8^3 cube load run (5 increments, eps2 = 1e-10): the adaptive run's inner
+tolerances follow eps_1,k = (||dv_k-1||_M / ||dv_0||_M)^2 clamped to
+[1e-12, 1e-2], its states equal the oracle's adaptive run to 1e-9 with
+Newton counts within one per increment, and it needs fewer Krylov
+iterations than the run at the fixed 1e-8 tolerance, which reaches the same
+states.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import fe, newton
+
+pytestmark = pytest.mark.gpu
+
+
+def test_newton_solve_fixed_and_adaptive(lib):
+    import torch
+    print("[newton solve] cube8 5 increments fixed / adaptive", flush=True)
+    prob = synth.cube_problem(8)
+    runs = {}
+    for adaptive in (0, 1):
+        ctx = lib.Context(0)
+        ctx.set_problem(prob)
+        v = torch.zeros(4 * prob.n_nodes, dtype=torch.float64, device="cuda")
+        prm = lib.newton_solve_params(adaptive=adaptive)
+        infos = []
+        for k in range(1, 6):
+            info, code = ctx.newton_solve(v, k / 5.0, prm)
+            assert code == 0 and info.converged
+            infos.append(info)
+        runs[adaptive] = (v.cpu().numpy(), infos)
+    v_fixed, inf_fixed = runs[0]
+    v_adapt, inf_adapt = runs[1]
+    for info in inf_adapt:
+        dv = [info.dv_mass_norm[k] for k in range(info.newton_iterations)]
+        assert info.eps1[0] == 1e-2
+        for k in range(1, info.newton_iterations):
+            r = dv[k - 1] / dv[0]
+            assert abs(info.eps1[k] - min(1e-2, max(1e-12, r * r))) <= 1e-15 * info.eps1[k]
+    for info in inf_fixed:
+        assert all(info.eps1[k] == 1e-8 for k in range(info.newton_iterations))
+    assert sum(i.krylov_iterations for i in inf_adapt) < sum(i.krylov_iterations for i in inf_fixed)
+    assert np.linalg.norm(v_adapt - v_fixed) <= 1e-9 * np.linalg.norm(v_fixed)
+    disc = fe.Discretization(prob)
+    vo = np.zeros(4 * prob.n_nodes)
+    prm_o = newton.NewtonParams(adaptive=True)
+    for k in range(1, 6):
+        vo, ok, its = newton.solve_increment(disc, vo, k / 5.0, prm_o)
+        assert ok and abs(its - inf_adapt[k - 1].newton_iterations) <= 1
+    assert np.linalg.norm(v_adapt - vo) <= 1e-9 * np.linalg.norm(vo)
+    print(f"[newton solve] krylov fixed {[i.krylov_iterations for i in inf_fixed]} "
+          f"adaptive {[i.krylov_iterations for i in inf_adapt]}", flush=True)
+
+
+def test_newton_solve_errors(lib):
+    prob = synth.cube_problem(3)
+    ctx = lib.Context(0)
+    ctx.set_problem(prob)
+    import torch
+    v = torch.zeros(4 * prob.n_nodes, dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.HfsiError) as e:
+        ctx.newton_solve(v, 1.0, lib.newton_solve_params(eps1_min=0.0, adaptive=1))
+    assert e.value.code == -1
+    info, code = ctx.newton_solve(v, 1.0, lib.newton_solve_params(max_newton=1))
+    assert code == 1 and not info.converged and info.newton_iterations == 1
