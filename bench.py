@@ -227,6 +227,26 @@ def main():
         print(f"[bench] second Newton step, {label}: {dt_r / args.steps * 1e3:.1f} ms/step", file=sys.stderr,
               flush=True)
     res["second_newton_step"] = reuse
+    # the whole last increment (Newton to ||dv_k||_M <= 1e-10 ||dv_0||_M) from
+    # the converged state of the one before: fixed 1e-8 inner solves with a
+    # full set-up per iteration, and the adaptive inner tolerance with the
+    # first iteration's coarse grids kept
+    inc = {}
+    for label, sprm in (("fixed_1e-8_full_setups", hfsi.newton_solve_params(step=p_main)),
+                        ("adaptive_reused_grids",
+                         hfsi.newton_solve_params(step=hfsi.newton_params(amg=p_main.amg, solve=sp, amg_reuse=1),
+                                                  adaptive=1))):
+        v.copy_(v0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ninfo, code = ctx.newton_solve(v, 1.0, sprm)
+        torch.cuda.synchronize()
+        inc[label] = {"ms": (time.perf_counter() - t0) * 1e3, "newton_iterations": ninfo.newton_iterations,
+                      "krylov_iterations": ninfo.krylov_iterations, "converged": bool(ninfo.converged),
+                      "krylov_per_iteration": [ninfo.krylov[k] for k in range(min(ninfo.newton_iterations, 32))]}
+        print(f"[bench] last increment, {label}: {inc[label]['ms']:.0f} ms, {ninfo.newton_iterations} Newton, "
+              f"{ninfo.krylov_iterations} Krylov", file=sys.stderr, flush=True)
+    res["last_increment_newton_solve"] = inc
     judge = {}
     if learned:
         info = ctx.amg_setup(p_main.amg)
