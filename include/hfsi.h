@@ -192,7 +192,9 @@ typedef struct {
                                step.solve.tol is the inner tolerance when
                                adaptive = 0; step.amg_reuse = 1 keeps the
                                first iteration's coarse grids for the later
-                               ones                                        */
+                               ones, 2 also starts from the coarse grids of
+                               an earlier call on this mesh when there are
+                               some (time steps)                            */
   double eps2;              /* stop at ||dv_k||_M <= eps2 ||dv_0||_M (eq.
                                newstop, relative form), default 1e-10       */
   int32_t max_newton;       /* default 25                                   */
@@ -330,6 +332,16 @@ hfsi_status hfsi_newton_step(hfsi_ctx* ctx, double* v, double load, const hfsi_n
  * max_newton iterations do not meet the criterion. */
 hfsi_status hfsi_newton_solve(hfsi_ctx* ctx, double* v, double load, const hfsi_newton_solve_params* prm,
                               hfsi_newton_solve_info* info);
+
+/* One Newmark-beta time step (inertia on, hfsi_set_newmark): from device
+ * state v [N], velocity vel and acceleration acc [n][3] at t^{n-1}, form the
+ * history r_s, solve the step's nonlinear problem at load factor `load` with
+ * hfsi_newton_solve (prm->step.amg_reuse = 2 keeps the coarse grids of the
+ * previous step) and update v, vel and acc in place to t^n.  When Newton
+ * does not converge, v, vel and acc are left as they were and
+ * HFSI_NOT_CONVERGED is returned.  HFSI_E_ORDER when inertia is off. */
+hfsi_status hfsi_time_step(hfsi_ctx* ctx, double* v, double* vel, double* acc, double load,
+                           const hfsi_newton_solve_params* prm, hfsi_newton_solve_info* info);
 
 /* ------------------------------------------------ inspection and testing */
 

@@ -1681,6 +1681,7 @@ extern "C" hfsi_status hfsi_newton_solve(hfsi_ctx* c, double* v, double load, co
   if (!prm || prm->struct_size != sizeof(hfsi_newton_solve_params))
     fail(HFSI_E_ARG, "newton solve params: struct_size mismatch");
   check_newton_params(&prm->step);
+  if (prm->step.amg_reuse < 0 || prm->step.amg_reuse > 2) fail(HFSI_E_ARG, "newton solve params: amg_reuse 0, 1 or 2");
   if (!(prm->eps2 > 0.0) || prm->max_newton < 1 || prm->adaptive < 0 || prm->adaptive > 1 ||
       !(prm->eps1_min > 0.0) || !(prm->eps1_max >= prm->eps1_min) || !(prm->eps1_max < 1.0))
     fail(HFSI_E_ARG, "newton solve params: need eps2 > 0, max_newton >= 1, 0 < eps1_min <= eps1_max < 1");
@@ -1704,7 +1705,10 @@ extern "C" hfsi_status hfsi_newton_solve(hfsi_ctx* c, double* v, double load, co
       else sp.tol = std::min(prm->eps1_max, std::max(prm->eps1_min, (dv_prev / dv0) * (dv_prev / dv0)));
     }
     hfsi_newton_info ni{sizeof(hfsi_newton_info)};
-    newton_iteration(c, v, load, prm->step.amg, sp, k > 0 && prm->step.amg_reuse != 0, &ni);
+    // amg_reuse: 1 keeps the first iteration's coarse grids, 2 also those of
+    // an earlier call on this mesh (e.g. the previous time step)
+    const bool reuse = prm->step.amg_reuse == 2 || (k > 0 && prm->step.amg_reuse == 1);
+    newton_iteration(c, v, load, prm->step.amg, sp, reuse, &ni);
     ++its;
     kry += ni.krylov_iterations;
     if (k == 0) dv0 = ni.dv_mass_norm;
@@ -1723,5 +1727,31 @@ extern "C" hfsi_status hfsi_newton_solve(hfsi_ctx* c, double* v, double load, co
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   }
   if (!done) return HFSI_NOT_CONVERGED;
+  HFSI_ABI_END(c)
+}
+
+extern "C" hfsi_status hfsi_time_step(hfsi_ctx* c, double* v, double* vel, double* acc, double load,
+                                      const hfsi_newton_solve_params* prm, hfsi_newton_solve_info* info) {
+  HFSI_ABI_BEGIN(c)
+  require_stage(c, 3, "time_step");
+  if (!v || !vel || !acc) fail(HFSI_E_ARG, "time_step: null vector");
+  if (!(c->cm > 0.0)) fail(HFSI_E_ORDER, "time_step: Newmark inertia is off (hfsi_set_newmark)");
+  const long N = 4L * c->n;
+  hipStream_t s = c->stream;
+  c->kvprev.ensure(N);
+  HIP_CHECK(hipMemcpyAsync(c->kvprev.p, v, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  hfsi_status st = hfsi_newmark_history(c, c->kvprev.p, vel, acc);
+  if (st < 0) return st;
+  st = hfsi_newton_solve(c, v, load, prm, info);
+  if (st < 0) return st;
+  if (st == HFSI_NOT_CONVERGED) {
+    // leave the step undone: the caller may retry it (a smaller dt)
+    HIP_CHECK(hipMemcpyAsync(v, c->kvprev.p, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    c->err = "time_step: Newton did not converge; state, velocity and acceleration unchanged";
+    return HFSI_NOT_CONVERGED;
+  }
+  st = hfsi_newmark_update(c, v, c->kvprev.p, vel, acc);
+  if (st < 0) return st;
   HFSI_ABI_END(c)
 }

@@ -161,6 +161,7 @@ def load():
         "hfsi_krylov_amg_solve": [vp, vp, vp, C.POINTER(SolveParams), C.POINTER(SolveInfo)],
         "hfsi_newton_step": [vp, vp, dbl, C.POINTER(NewtonParams), C.POINTER(NewtonInfo)],
         "hfsi_newton_solve": [vp, vp, dbl, C.POINTER(NewtonSolveParams), C.POINTER(NewtonSolveInfo)],
+        "hfsi_time_step": [vp, vp, vp, vp, dbl, C.POINTER(NewtonSolveParams), C.POINTER(NewtonSolveInfo)],
         "hfsi_amg_setup_csr": [vp, i32, vp, vp, vp, vp, C.POINTER(AmgParams), C.POINTER(AmgInfo)],
         "hfsi_amg_export": [vp, i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64), vp, vp, vp, vp],
         "hfsi_vcycle": [vp, vp, vp],
@@ -328,6 +329,13 @@ class Context:
         prm = prm or newton_solve_params()
         info = NewtonSolveInfo(C.sizeof(NewtonSolveInfo))
         code = self._check(self.lib.hfsi_newton_solve(self.h, _ptr(v), load, C.byref(prm), C.byref(info)))
+        return info, code
+
+    def time_step(self, v, vel, acc, load, prm=None):
+        prm = prm or newton_solve_params()
+        info = NewtonSolveInfo(C.sizeof(NewtonSolveInfo))
+        code = self._check(self.lib.hfsi_time_step(self.h, _ptr(v), _ptr(vel), _ptr(acc), load, C.byref(prm),
+                                                   C.byref(info)))
         return info, code
 
     # ---- inspection

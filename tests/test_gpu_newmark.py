@@ -114,3 +114,33 @@ def test_time_steps_match_oracle(lib):
         assert np.linalg.norm(vel.cpu().numpy().reshape(n, 3) - velo) <= 1e-7 * np.linalg.norm(velo)
         assert np.linalg.norm(acc.cpu().numpy().reshape(n, 3) - acco) <= 1e-7 * np.linalg.norm(acco)
     assert np.linalg.norm(acco) > 0
+
+
+def test_time_step_entry_with_reuse_matches_oracle(lib):
+    """hfsi_time_step (history, Newton solve, update in one call) with the
+    adaptive inner tolerance and the coarse grids kept from step to step
+    reaches the oracle's time steps (a new hierarchy per Newton iteration,
+    fixed inner tolerance) to the Newton tolerance; with inertia off it is
+    an order error."""
+    import torch
+    print("[newmark time_step] cube4 3 steps, adaptive, reused grids", flush=True)
+    prob = synth.cube_problem(4)
+    n = prob.n_nodes
+    ctx = _context(lib, prob)
+    v = torch.zeros(4 * n, dtype=torch.float64, device="cuda")
+    vel = torch.zeros(3 * n, dtype=torch.float64, device="cuda")
+    acc = torch.zeros_like(vel)
+    prm = lib.newton_solve_params(step=lib.newton_params(amg_reuse=2), adaptive=1)
+    disc = fe.Discretization(prob)
+    vo, velo, acco = np.zeros(4 * n), np.zeros((n, 3)), np.zeros((n, 3))
+    for step in range(3):
+        info, code = ctx.time_step(v, vel, acc, 1.0, prm)
+        assert code == 0 and info.converged
+        vo, velo, acco, _ = newmark.time_step(disc, vo, 1.0, PRM, newton.NewtonParams(), velo, acco)
+        assert np.linalg.norm(v.cpu().numpy() - vo) <= 1e-8 * np.linalg.norm(vo)
+        assert np.linalg.norm(vel.cpu().numpy().reshape(n, 3) - velo) <= 1e-7 * np.linalg.norm(velo)
+        assert np.linalg.norm(acc.cpu().numpy().reshape(n, 3) - acco) <= 1e-7 * np.linalg.norm(acco)
+    ctx.set_newmark(0.0)
+    with pytest.raises(lib.HfsiError) as e:
+        ctx.time_step(v, vel, acc, 1.0, prm)
+    assert e.value.code == -4
