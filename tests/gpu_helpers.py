@@ -71,13 +71,14 @@ __all__ = ["torch_dev", "context_for", "oracle_system", "export_level_matrix", "
            "amg_prm_pair", "oracle_sampled_rows", "synth"]
 
 
-def oracle_sampled_rows(prob, v, load, nodes):
+def oracle_sampled_rows(prob, v, load, nodes, inertia=None):
     """Oracle residual entries and Dirichlet-eliminated tangent rows of the
     given nodes, computed on the sub-mesh of the elements incident to them
     (with the loaded boundary triangles that touch them): every contribution
     to those rows comes from such an element or triangle, so the rows are
-    those of the full assembly.  Returns {node: (R[4], {global col dof: K row
-    values [4]})}."""
+    those of the full assembly.  inertia = (cm, r_s [n,3]) adds the
+    Newmark-beta terms.  Returns {node: (R[4], {global col dof: K row values
+    [4]})}."""
     nodes = np.asarray(sorted(set(int(i) for i in nodes)))
     sel = np.isin(prob.tets, nodes).any(axis=1)
     tets = prob.tets[sel]
@@ -89,6 +90,8 @@ def oracle_sampled_rows(prob, v, load, nodes):
                          prob.dir_mask[sub_nodes], loc[prob.tris[tsel]].astype(np.int32), prob.traction[tsel],
                          prob.lattice[sub_nodes], None if prob.fibres is None else prob.fibres[sel], name="rows")
     d = fe.Discretization(sub)
+    if inertia is not None:
+        d.set_inertia(inertia[0], np.asarray(inertia[1]).reshape(prob.n_nodes, 3)[sub_nodes])
     vs = np.asarray(v).reshape(prob.n_nodes, 4)[sub_nodes].ravel()
     R, val = d.assemble(vs, load)
     R, val = d.apply_dirichlet(R, val)

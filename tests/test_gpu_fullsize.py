@@ -2,7 +2,8 @@
 64 x 8 x 128 artery tube), where the oracle cannot run the whole path:
 
 * assembly: residual entries and tangent rows of sampled nodes against the
-  oracle on the sub-mesh of their elements (exact for those rows), 1e-12;
+  oracle on the sub-mesh of their elements (exact for those rows), 1e-12,
+  quasi-static and with the Newmark-beta inertia;
 * the artery tube with the fp32 V-cycle inside fp64 FGMRES and with the
   all-fp64 cycle: both reach ||b - K x|| <= 1e-8 ||b||, checked on the host
   with the exported tangent (independent of the GPU residual kernel); their
@@ -31,23 +32,40 @@ def _blocks_csr(out, n):
     return sp.csr_matrix((bv.ravel(), (r.ravel(), c.ravel())), shape=(4 * n, 4 * n))
 
 
-def _assembled(lib, prob, v, load):
+def _assembled(lib, prob, v, load, inertia=None):
+    """inertia = (NewmarkParams, v_prev, vel, acc): Newmark-beta terms on."""
     import torch
     ctx = context_for(lib, prob)
+    if inertia is not None:
+        nm, v_prev, vel, acc = inertia
+        ctx.set_newmark(nm.rho, dt=nm.dt, beta=nm.beta, gamma=nm.gamma)
+        ctx.newmark_history(torch_dev(v_prev.ravel()), torch_dev(vel), torch_dev(acc))
     vt = torch_dev(v.ravel())
     R = torch.zeros_like(vt)
     view, info = ctx.assemble_residual_tangent(vt, load, R)
     return ctx, vt, R, view, info
 
 
-@pytest.mark.parametrize("case", ["cube48", "tube"])
+@pytest.mark.parametrize("case", ["cube48", "tube", "cube48_inertia"])
 def test_sampled_assembly_rows_full_size(lib, case):
-    prob = synth.config_problem(case)
+    """cube48_inertia: with the Newmark-beta terms (rho_s = 1, dt = 0.05),
+    the history from a second random state and random nodal velocities and
+    accelerations."""
+    prob = synth.config_problem(case.replace("_inertia", ""))
     # nodal noise 0.1 * u_scale stays well below the 48^3 element size (0.021)
     v = synth.random_state(prob, 31, u_scale=0.01, p_scale=0.1)
     load = 0.5
     print(f"[fullsize assembly] {case} n={prob.n_nodes} m={prob.n_tets}", flush=True)
-    ctx, vt, R, view, info = _assembled(lib, prob, v, load)
+    inertia = oinertia = None
+    if case.endswith("_inertia"):
+        from oracle import newmark
+        nm = newmark.NewmarkParams(rho=1.0, dt=0.05)
+        v_prev = synth.random_state(prob, 32, u_scale=0.01, p_scale=0.1)
+        r = np.random.default_rng(6)
+        vel, acc = r.normal(scale=0.1, size=(prob.n_nodes, 3)), r.normal(scale=1.0, size=(prob.n_nodes, 3))
+        inertia = (nm, v_prev, vel, acc)
+        oinertia = (newmark.coefficient(nm), newmark.history(nm, v_prev.reshape(-1, 4)[:, 0:3], vel, acc))
+    ctx, vt, R, view, info = _assembled(lib, prob, v, load, inertia)
     assert info.min_J > 0
     out = ctx.export_tangent(view)
     Rg = R.cpu().numpy()
@@ -55,7 +73,7 @@ def test_sampled_assembly_rows_full_size(lib, case):
     nodes = np.random.default_rng(5).choice(prob.n_nodes, 150, replace=False)
     # include loaded and clamped nodes
     nodes = np.concatenate([nodes, prob.tris[:10].ravel(), np.nonzero(prob.dir_mask[:, 0])[0][:10]])
-    rows = oracle_sampled_rows(prob, v, load, nodes)
+    rows = oracle_sampled_rows(prob, v, load, nodes, oinertia)
     rscale = np.abs(Rg).max()
     kscale = np.abs(bv).max()
     for g, (Ro, Ko) in rows.items():

@@ -6,7 +6,8 @@
 * the update kernel against the oracle's formulas;
 * time steps of a cube under a suddenly applied traction (Newton per step,
   then the Newmark update) reproduce the oracle's states, velocities and
-  accelerations.
+  accelerations, also through the one-call hfsi_time_step with the adaptive
+  inner tolerance and coarse grids kept across steps.
 """
 import numpy as np
 import pytest
