@@ -48,9 +48,28 @@ def build(verbose: bool = True) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")
     os.replace(tmp, LIB)
+    build_driver()
     if verbose:
-        print(f"built {LIB} from {len(srcs)} sources")
+        print(f"built {LIB} from {len(srcs)} sources, and {DRIVER}")
     return LIB
+
+
+DRIVER = os.path.join(HERE, "examples", "newton_driver")
+
+
+def build_driver() -> str:
+    """The C example that drives the library through its C ABI alone (host
+    code: gcc against the HIP runtime and libhfsi.so)."""
+    src = DRIVER + ".c"
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(rocm, "include"), "-I", os.path.join(ROOT, "include"), src,
+           "-L", HERE, "-lhfsi", "-L", os.path.join(rocm, "lib"), "-lamdhip64",
+           f"-Wl,-rpath,$ORIGIN/..:{os.path.join(rocm, 'lib')}", "-o", DRIVER]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0 or r.stderr.strip():
+        raise RuntimeError(f"gcc failed for {src}:\n{r.stderr[-4000:]}")
+    return DRIVER
 
 
 if __name__ == "__main__":
