@@ -339,7 +339,8 @@ hfsi_status hfsi_newton_solve(hfsi_ctx* ctx, double* v, double load, const hfsi_
  * hfsi_newton_solve (prm->step.amg_reuse = 2 keeps the coarse grids of the
  * previous step) and update v, vel and acc in place to t^n.  When Newton
  * does not converge, v, vel and acc are left as they were and
- * HFSI_NOT_CONVERGED is returned.  HFSI_E_ORDER when inertia is off. */
+ * HFSI_NOT_CONVERGED is returned; after an error (negative status) v may
+ * hold a partial Newton iterate.  HFSI_E_ORDER when inertia is off. */
 hfsi_status hfsi_time_step(hfsi_ctx* ctx, double* v, double* vel, double* acc, double load,
                            const hfsi_newton_solve_params* prm, hfsi_newton_solve_info* info);
 
