@@ -1675,22 +1675,26 @@ void alloc_vectors(Level& L) {
   L.xf.ensure(L.n); L.bf.ensure(L.n); L.rf.ensure(L.n); L.tf.ensure(L.n);
 }
 
-// padded copy of L.A in the cycle's precision (levels without node blocks)
-void pack_level(hfsi_ctx* c, Level& L, int precision) {
+// padded copy of L.A in the cycle's precision (levels without node blocks);
+// same_pattern: L.A has the pattern of the last packing of this level, whose
+// chunk layout is kept (values and columns are written again)
+void pack_level(hfsi_ctx* c, Level& L, int precision, bool same_pattern = false) {
   hipStream_t s = c->stream;
   Packed4& K = L.pk;
   const int n = L.n;
-  K.rows = n;
-  K.p4.ensure(n + 1);
-  K.base.ensure(n);
-  DevBuf<int> wide;
-  wide.zero(1, s);
-  k_pack_count<<<div_up((long)n * 8, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, K.p4.p, K.base.p, wide.p);
-  HIP_LAUNCH_CHECK();
-  HIP_CHECK(hipMemsetAsync(K.p4.p + n, 0, sizeof(int), s));
-  int w = 0;  // read in the scan's wait
-  K.chunks = exclusive_scan(K.p4.p, K.p4.p, n + 1, s, wide.p, 1, &w);
-  K.wide = w != 0;
+  if (!same_pattern || K.rows != n) {
+    K.rows = n;
+    K.p4.ensure(n + 1);
+    K.base.ensure(n);
+    DevBuf<int> wide;
+    wide.zero(1, s);
+    k_pack_count<<<div_up((long)n * 8, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, K.p4.p, K.base.p, wide.p);
+    HIP_LAUNCH_CHECK();
+    HIP_CHECK(hipMemsetAsync(K.p4.p + n, 0, sizeof(int), s));
+    int w = 0;  // read in the scan's wait
+    K.chunks = exclusive_scan(K.p4.p, K.p4.p, n + 1, s, wide.p, 1, &w);
+    K.wide = w != 0;
+  }
   const size_t m = 4 * (size_t)K.chunks;
   // keep only the arrays of this layout and precision
   if (K.wide) {
@@ -1783,7 +1787,7 @@ void to_f32_transfer(hfsi_ctx* c, Level& L) {
 // the aux stream while this stream makes the operator copies of the cycle),
 // the fp32 and padded copies, then one read of the deferred checks and the
 // eigenvalue estimates.  Marks the hierarchy ready.
-void finish_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm) {
+void finish_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, bool same_patterns = false) {
   hipStream_t s = c->stream;
   Hierarchy& H = c->H;
   Level& Lc = H.L.back();
@@ -1824,7 +1828,7 @@ void finish_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm) {
   // padded operator copies for the smoother and residual
   for (auto& L : H.L) {
     L.packed = false;
-    if (!L.bptr) pack_level(c, L, prm.precision);
+    if (!L.bptr) pack_level(c, L, prm.precision, same_patterns);
   }
   // join the aux stream, then read the singularity flag and the estimates
   HIP_CHECK(hipEventRecord(c->aev[1], c->aux));
@@ -2054,6 +2058,7 @@ void amg_resetup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* 
   if (!H.reusable || H.L.empty() || H.L[0].n != c->A.rows || H.L[0].A.nnz != c->A.nnz)
     fail(HFSI_E_ORDER, "amg_resetup: no hierarchy of this mesh's tangent to reuse");
   HIP_CHECK(hipEventRecord(c->ev0, s));
+  const int prev_precision = H.precision;
   H.ready = false;
   H.reusable = false;
   set_schedule(H, prm);
@@ -2071,9 +2076,9 @@ void amg_resetup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* 
     Level& Lf = H.L[l];
     spgemm_values(c, Lf.A, Lf.P, Lf.AP, Lf.p_rowmax, H.setup_flags.p);
     spgemm_values(c, Lf.R, Lf.AP, H.L[l + 1].A, Lf.ap_rowmax, H.setup_flags.p);
-    if (prm.precision == 1) to_f32_transfer(c, Lf);
+    if (prm.precision == 1 && prev_precision != 1) to_f32_transfer(c, Lf);  // P, R unchanged
   }
-  finish_hierarchy(c, prm);
+  finish_hierarchy(c, prm, true);
   H.reusable = true;
   fill_info(H, info, 0, -1.0);
   HIP_CHECK(hipEventRecord(c->ev1, s));

@@ -149,3 +149,38 @@ def test_newton_run_with_reused_coarse_grids(lib):
     disc = fe.Discretization(prob)
     vo = newton.load_run(disc, 5, newton.NewtonParams())
     assert np.linalg.norm(v.cpu().numpy() - vo) <= 1e-9 * np.linalg.norm(vo)
+
+
+@pytest.mark.parametrize("p_setup,p_resetup", [(0, 1), (1, 0)])
+def test_resetup_changes_cycle_precision(lib, p_setup, p_resetup):
+    """A re-set-up may switch the cycle between fp64 and fp32 (the fp32
+    copies of P and R are made when the kept grids have none): its V-cycle
+    matches the oracle's on the rebuilt operators to the new precision's
+    accuracy, and switching back reproduces the first cycle."""
+    import torch
+    print(f"[reuse precision] {p_setup} -> {p_resetup}", flush=True)
+    prob = synth.cube_problem(6, jitter=0.1, seed=2)
+    v0 = synth.random_state(prob, 3, u_scale=0.03, p_scale=0.05).ravel()
+    v1 = synth.random_state(prob, 7, u_scale=0.06, p_scale=0.2).ravel()
+    g0, oprm = amg_prm_pair(lib, smoother=1, precision=p_setup, max_coarse=60, schedule="default")
+    g1, _ = amg_prm_pair(lib, smoother=1, precision=p_resetup, max_coarse=60, schedule="default")
+    ctx = context_for(lib, prob)
+    _assemble(ctx, v0, 0.4)
+    ctx.amg_setup(g0)
+    n3 = 3 * prob.n_nodes
+    r = torch_dev(np.random.default_rng(8).normal(size=n3))
+    z0 = torch.zeros(n3, dtype=torch.float64, device="cuda")
+    ctx.vcycle(r, z0)
+    _assemble(ctx, v1, 0.7)
+    info1 = ctx.amg_resetup(g1)
+    H1 = gpu_hierarchy_to_oracle(ctx, info1, oprm)
+    z = torch.zeros_like(z0)
+    ctx.vcycle(r, z)
+    zo = amg.vcycle(H1, r.cpu().numpy(), oprm)
+    tol = 1e-12 if p_resetup == 0 else 2e-5
+    assert np.linalg.norm(z.cpu().numpy() - zo) <= tol * np.linalg.norm(zo)
+    _assemble(ctx, v0, 0.4)
+    ctx.amg_resetup(g0)
+    z2 = torch.zeros_like(z0)
+    ctx.vcycle(r, z2)
+    assert torch.equal(z0, z2)
