@@ -261,7 +261,9 @@ def main():
         torch.cuda.synchronize()
         inc[label] = {"ms": (time.perf_counter() - t0) * 1e3, "newton_iterations": ninfo.newton_iterations,
                       "krylov_iterations": ninfo.krylov_iterations, "converged": bool(ninfo.converged),
-                      "krylov_per_iteration": [ninfo.krylov[k] for k in range(min(ninfo.newton_iterations, 32))]}
+                      "krylov_per_iteration": [ninfo.krylov[k] for k in range(min(ninfo.newton_iterations, 32))],
+                      "dv_mass_norm": [ninfo.dv_mass_norm[k] for k in range(min(ninfo.newton_iterations, 32))],
+                      "eps1": [ninfo.eps1[k] for k in range(min(ninfo.newton_iterations, 32))]}
         print(f"[bench] last increment, {label}: {inc[label]['ms']:.0f} ms, {ninfo.newton_iterations} Newton, "
               f"{ninfo.krylov_iterations} Krylov", file=sys.stderr, flush=True)
     res["last_increment_newton_solve"] = inc
