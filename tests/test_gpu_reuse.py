@@ -7,7 +7,8 @@ of the GPU's own level operator and kept P (pattern exact, values 1e-12
 relative), end to end the oracle's re-set-up of the new tangent on the first
 hierarchy, and the V-cycle on the rebuilt hierarchy matches the oracle's.
 A Newton load run that re-uses the coarse grids converges to the oracle's
-states.
+states.  A re-set-up may switch the cycle's precision, and keeps learned
+level-0 rows bit for bit.
 """
 import numpy as np
 import pytest
@@ -184,3 +185,41 @@ def test_resetup_changes_cycle_precision(lib, p_setup, p_resetup):
     z2 = torch.zeros_like(z0)
     ctx.vcycle(r, z2)
     assert torch.equal(z0, z2)
+
+
+def test_resetup_keeps_learned_interpolation(lib):
+    """With the trained network the level-0 interpolation carries the learned
+    rows; a re-set-up at another state keeps them bit for bit (and reports
+    them as kept), and rebuilds the coarse operator as their Galerkin
+    product."""
+    import os
+
+    from paper_1312_5561_amd import train_mlp
+    print("[reuse learned] cube6", flush=True)
+    w, _ = train_mlp.load(os.path.join(os.path.dirname(lib.__file__), "weights", "mlp_cube.npz"))
+    prob = synth.cube_problem(6, jitter=0.1, seed=3)
+    v1 = synth.random_state(prob, 9, u_scale=0.04, p_scale=0.1).ravel()
+    prm_c = lib.amg_params(max_coarse=60)
+    prm_l = lib.amg_params(max_coarse=60, interp=1, fallback_rho=1.0)
+    ctx_c = context_for(lib, prob)
+    _assemble(ctx_c, np.zeros(prob.n_dofs), 1.0)
+    ctx_c.amg_setup(prm_c)
+    P_classical = export_level_matrix(ctx_c, 0, 1)
+    ctx = context_for(lib, prob)
+    ctx.mlp_set_weights(w)
+    _assemble(ctx, np.zeros(prob.n_dofs), 1.0)
+    info0 = ctx.amg_setup(prm_l)
+    assert info0.learned_used == 1
+    P0 = export_level_matrix(ctx, 0, 1)
+    assert (P0 != P_classical).nnz > 0
+    _assemble(ctx, v1, 0.8)
+    info1 = ctx.amg_resetup(prm_l)
+    assert info1.learned_used == 1 and info1.rho == -1.0
+    P1 = export_level_matrix(ctx, 0, 1)
+    assert np.array_equal(P1.indptr, P0.indptr) and np.array_equal(P1.indices, P0.indices)
+    assert np.array_equal(P1.data, P0.data)
+    A = export_level_matrix(ctx, 0, 0)
+    Ac = export_level_matrix(ctx, 1, 0)
+    Aco = amg.galerkin(A, P1)
+    assert np.array_equal(Ac.indptr, Aco.indptr) and np.array_equal(Ac.indices, Aco.indices)
+    assert np.abs(Ac.data - Aco.data).max() <= 1e-12 * np.abs(Aco.data).max()
