@@ -9,7 +9,9 @@ Readings taken where the paper is silent or garbled:
 * the anisotropic stress carries the factor 2 k1 that S = 2 dPsi/dC gives
   (the printed stress formula drops it);
 * a fibre contributes stress and tangent only while its invariant J_i > 1;
-* quasi-static loading (no inertia, r_s = 0), dead nominal traction;
+* quasi-static loading (no inertia, r_s = 0) unless the Newmark-beta
+  inertia is set (set_inertia: one density, the exact P1 mass, r_s in P1
+  from its nodal values), dead nominal traction;
 * one centroid quadrature point per tetrahedron (exact for every term of the
   P1-P1 form except the pressure mass, which uses the exact P1 mass matrix);
 * h_T is the longest edge of T in the reference configuration, and the
