@@ -109,11 +109,18 @@ def run_steps(ctx, v0, v, prm, steps, torch):
     return time.perf_counter() - t0, infos
 
 
-def summarize(infos):
+def summarize(infos, ndofs=None):
+    """Medians over the timed steps, with min and max of the solve and step
+    times; ndofs given: also dofs per second of the Krylov solve alone."""
     keys = ("krylov_iterations", "t_assemble", "t_setup", "t_solve", "t_total", "rel_residual", "amg_levels")
     out = {k: float(np.median([getattr(i, k) for i in infos])) for k in keys}
     out["krylov_iterations"] = int(out["krylov_iterations"])
     out["amg_levels"] = int(out["amg_levels"])
+    for k in ("t_solve", "t_total"):
+        vals = [getattr(i, k) for i in infos]
+        out[k + "_min"], out[k + "_max"] = float(min(vals)), float(max(vals))
+    if ndofs:
+        out["dofs_per_s_solve"] = ndofs / out["t_solve"]
     return out
 
 
@@ -220,12 +227,12 @@ def main():
         judge["rho_classical"] = ctx.amg_convergence_factor(10, 777)
         dt_c32, inf_c32, d_c32 = timed(p_c32, "classical fp32")
         res["classical_fp32"] = {"value": ndofs * args.steps / dt_c32, "unit": "dofs/s",
-                                 "ms_per_step": dt_c32 / args.steps * 1e3, **summarize(inf_c32)}
+                                 "ms_per_step": dt_c32 / args.steps * 1e3, **summarize(inf_c32, ndofs)}
     if not args.no_fp64:
         dt64, inf64, d64 = timed(p64, "plain fp64")
         err = float(torch.linalg.norm(d_main - d64) / torch.linalg.norm(d64))
         res["fp64_plain"] = {"value": ndofs * args.steps / dt64, "unit": "dofs/s",
-                             "ms_per_step": dt64 / args.steps * 1e3, **summarize(inf64)}
+                             "ms_per_step": dt64 / args.steps * 1e3, **summarize(inf64, ndofs)}
         res["update_rel_err_vs_fp64"] = err
         res["speedup_vs_fp64_plain"] = dt64 / dt_main
     # (these legs follow the judge, whose set-ups use the last assembly: the
@@ -267,6 +274,30 @@ def main():
         print(f"[bench] last increment, {label}: {inc[label]['ms']:.0f} ms, {ninfo.newton_iterations} Newton, "
               f"{ninfo.krylov_iterations} Krylov", file=sys.stderr, flush=True)
     res["last_increment_newton_solve"] = inc
+    # the whole load run from the unloaded state (every increment solved by
+    # Newton to 1e-10), fixed 1e-8 inner solves with full set-ups against
+    # the adaptive inner tolerance with the coarse grids kept per increment
+    run = {}
+    for label, sprm in (("fixed_1e-8_full_setups", hfsi.newton_solve_params(step=p_main)),
+                        ("adaptive_reused_grids",
+                         hfsi.newton_solve_params(step=hfsi.newton_params(amg=p_main.amg, solve=sp, amg_reuse=1),
+                                                  adaptive=1))):
+        v.zero_()
+        newton_its = krylov_its = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(1, increments + 1):
+            ninfo, code = ctx.newton_solve(v, k / increments, sprm)
+            if code != 0:
+                raise RuntimeError(f"increment {k} did not converge")
+            newton_its += ninfo.newton_iterations
+            krylov_its += ninfo.krylov_iterations
+        torch.cuda.synchronize()
+        run[label] = {"seconds": time.perf_counter() - t0, "increments": increments, "newton_iterations": newton_its,
+                      "krylov_iterations": krylov_its}
+        print(f"[bench] load run ({increments} increments), {label}: {run[label]['seconds']:.2f} s, {newton_its} "
+              f"Newton, {krylov_its} Krylov", file=sys.stderr, flush=True)
+    res["load_run"] = run
     # dynamics (cube): Newmark-beta (rho_s = 1, dt = 0.05, beta = 0.625,
     # gamma = 1) from rest under the full load, five time steps, with fixed
     # 1e-8 inner solves and a new hierarchy per Newton iteration, and with the
@@ -387,7 +418,7 @@ def main():
                    "precision": f"fp32 V-cycle in fp64 {'FGMRES' if args.krylov == 'fgmres' else 'BiCGStab'}",
                    "restart": args.restart,
                    "smoother": "l1-Jacobi" if args.smoother == 0 else "Chebyshev"},
-        "breakdown": summarize(inf_main),
+        "breakdown": summarize(inf_main, ndofs),
         **({"judge": judge} if judge else {}),
         **res,
         "roofline": roof,
