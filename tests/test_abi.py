@@ -35,3 +35,24 @@ def test_binding_has_no_cpu_fallback():
     src = open(os.path.join(ROOT, "paper_1312_5561_amd", "hfsi.py")).read()
     assert "oracle" not in src.replace("no fallback", "")
     assert "scipy" not in src
+
+
+def test_c_example_links_and_checks_its_arguments():
+    """The C example is built against the library and the HIP runtime; run
+    without arguments it prints its usage and exits with status 2 before any
+    GPU call."""
+    import subprocess
+
+    from paper_1312_5561_amd import build as b
+    if not os.path.exists(b.DRIVER):
+        pytest.fail(f"{b.DRIVER} is not built (run __graft_entry__.build())")
+    r = subprocess.run([b.DRIVER], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2 and "usage" in r.stderr
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode != 0 and "one GPU only" in (r.stdout + r.stderr)
