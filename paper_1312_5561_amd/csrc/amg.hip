@@ -288,7 +288,7 @@ k_interp_fill16(int n, const int* __restrict__ ptr, const int* __restrict__ col,
 // window of 64 entries of row i, neighbour t goes to group t mod NG.  Every
 // group keeps its own partial sums, added in group order at the end, so the
 // result does not depend on scheduling.  With p_max > 0 a longer row keeps
-// its p_max largest |w| (float32 keys, ties to the smaller column), rescaled
+// its p_max largest |w| (fp64 keys, ties to the smaller column), rescaled
 // to the full row sum.  FILL = false writes the entry count of each row,
 // FILL = true the entries (ascending columns).
 constexpr int XH = 128;    // hash slots per row
@@ -544,10 +544,10 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
   int* sel = s_mem[g];  // the insertion list is no longer needed
   if (trunc)
     for (int t = lane; t < m; t += 64) {
-      const float key = fabsf((float)s_num[g][t]);
+      const double key = fabs(s_num[g][t]);
       int r = 0;
       for (int u = 0; u < m; ++u) {
-        const float ku = fabsf((float)s_num[g][u]);
+        const double ku = fabs(s_num[g][u]);
         r += ku > key || (ku == key && u < t);
       }
       sel[t] = r;

@@ -145,9 +145,15 @@ def tube_mesh(n_theta=64, n_media=5, n_adv=3, n_z=128, r_in=0.71, media=0.26,
 def boundary_faces(tets):
     """Triangles (sorted node triples) that belong to exactly one tetrahedron."""
     f = np.concatenate([tets[:, [1, 2, 3]], tets[:, [0, 2, 3]], tets[:, [0, 1, 3]], tets[:, [0, 1, 2]]])
-    f = np.sort(f, axis=1)
-    uniq, cnt = np.unique(f, axis=0, return_counts=True)
-    return uniq[cnt == 1].astype(np.int32)
+    f = np.sort(f, axis=1).astype(np.int64)
+    # one int64 key per sorted triple (lexicographic order = key order) makes
+    # the duplicate count a 1-D unique, much faster than unique over rows
+    n = int(f.max()) + 1
+    assert n < (1 << 21)
+    key = (f[:, 0] * n + f[:, 1]) * n + f[:, 2]
+    uk, cnt = np.unique(key, return_counts=True)
+    uk = uk[cnt == 1]
+    return np.stack([uk // (n * n), (uk // n) % n, uk % n], axis=1).astype(np.int32)
 
 
 @dataclasses.dataclass

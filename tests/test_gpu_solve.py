@@ -101,7 +101,7 @@ def test_fgmres_solution(lib, precision):
     M = krylov.BlockPreconditioner(lambda r: amg.vcycle(H, r, oprm), B2, s, prob.n_nodes)
     _, oinfo = krylov.fgmres(K, M, b, tol=1e-8)
     print(f"[fgmres] gpu its={sinfo.iterations} oracle its={oinfo.iterations} err={err:.2e}", flush=True)
-    assert abs(sinfo.iterations - oinfo.iterations) <= (1 if precision == 0 else max(3, oinfo.iterations // 10))
+    assert abs(sinfo.iterations - oinfo.iterations) <= (1 if precision == 0 else 3)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -109,9 +109,8 @@ def test_bicgstab_solution(lib, precision):
     """BiCGStab (method 1) with the same P_L: the direct solution to 1e-9 at
     a 1e-12 tolerance, the true residual at 1e-8, and about as many
     iterations as the oracle's BiCGStab with the GPU's hierarchy: within one
-    with the fp64 cycle; with the fp32 cycle within 10% (at least 3), since
-    BiCGStab is not flexible and the fp32 cycle's rounding (relative 1e-7 per
-    application, not in the oracle) shifts its count by a few iterations."""
+    with the fp64 cycle, within three with the fp32 cycle (its rounding,
+    relative 1e-7 per application, is not in the oracle)."""
     import torch
     prob = synth.cube_problem(8)
     v = synth.random_state(prob, 8, u_scale=0.02, p_scale=0.02).ravel()
