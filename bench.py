@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark: dofs solved per second by one Newton step of the solid problem.
 
-Workload (default): the 48^3 Kuhn cube (117,649 nodes, 470,596 dofs),
+Workload (default): the 96^3 Kuhn cube (912,673 nodes, 3,650,692 dofs),
 Mooney-Rivlin c10=0.5 c01=0.1 kappa=1e4, clamped at x=0, dead traction
 (0,0,0.05) on x=1.  The state is first driven through load increments
 0.2..0.8 (untimed); every timed step then performs one full Newton step at
@@ -11,10 +11,11 @@ mass norm.  All arithmetic runs in the HIP library; inputs are resident in
 device memory before the timed region.
 
 value = dofs * steps / elapsed for the learned path: level-0 interpolation
-corrected by the trained network (kept only when the V-cycle's measured
-convergence factor passes the judge, classical otherwise) and an fp32
-V-cycle inside fp64 FGMRES.  Classical fp32 and plain fp64 are timed the same
-way and reported beside it.
+corrected by the trained network under its judge (kept only when its V-cycle
+converges at least as fast as the classical one and at rate <= 0.5, the
+verdict taken on the first set-up of the problem), fp32 V-cycle inside fp64
+FGMRES.  The network forced on (no judge), classical fp32 and plain fp64 are
+timed the same way and reported beside it.
 
 --workload tube: the two-layer artery tube 64 x 8 x 128 (297,216 dofs,
 kappa=1e5), internal dead pressure ramped over 20 increments to 13.3 (plain
@@ -46,7 +47,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", choices=("cube", "tube"), default="cube")
-    ap.add_argument("--N", type=int, default=48, help="hexahedra per cube edge")
+    ap.add_argument("--N", type=int, default=96, help="hexahedra per cube edge")
     ap.add_argument("--kappa", type=float, default=None, help="bulk modulus (cube 1e4, tube 1e5)")
     ap.add_argument("--smoother", type=int, default=1, help="0 l1-Jacobi, 1 Chebyshev")
     ap.add_argument("--restart", type=int, default=256)
@@ -59,7 +60,12 @@ def parse():
     ap.add_argument("--interp", choices=("learned", "classical"), default=None,
                     help="level-0 interpolation of the headline path (cube: learned, tube: classical)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1312_5561_amd", "weights", "mlp_cube.npz"))
-    ap.add_argument("--fallback-rho", type=float, default=0.6)
+    ap.add_argument("--fallback-rho", type=float, default=0.5)
+    ap.add_argument("--judge", type=int, default=2,
+                    help="learned interpolation judge: 0 threshold only, 1 vs classical every set-up, "
+                         "2 vs classical once per problem")
+    ap.add_argument("--quick", action="store_true",
+                    help="headline legs only (no reuse, load-run, dynamics or sequence legs)")
     args = ap.parse_args()
     if args.kappa is None:
         args.kappa = 1e4 if args.workload == "cube" else 1e5
@@ -68,25 +74,31 @@ def parse():
     return args
 
 
-def kernel_source_hash():
-    """sha256[:16] of the source the level-0 counters depend on: the k_b3
-    kernel and level_op, which launches it (solve.hip)."""
+def kernel_source_hash(starts):
+    """sha256[:16] of the source the counters of a kernel depend on: the
+    functions of solve.hip that begin with the given strings (the kernel and
+    the host code that launches it)."""
     import hashlib
     src = open(os.path.join(ROOT, "paper_1312_5561_amd", "csrc", "solve.hip")).read()
     parts = []
-    for start in ("k_b3(int nn,", "void level_op(Level& L,"):
+    for start in starts:
         a = src.index(start)
         parts.append(src[a:src.index("\n}\n", a)])
     return hashlib.sha256("\n".join(parts).encode()).hexdigest()[:16]
 
 
-def measured_traffic(kernel_tag):
+# the dominant kernel of the 96^3 Newton step (the level-1 Chebyshev step on
+# the padded CSR copy) and the source its counters depend on
+ROOF_KERNEL_SRC = ("k_csr4(int n,", "void csr4_launch(", "void level_op(Level& L,")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cube96_level1_smoother_traffic.md")
+
+
+def measured_traffic(kernel_tag, path=TRAFFIC_FILE, starts=ROOF_KERNEL_SRC):
     """Calibrated HBM bytes per launch from the committed PMC summary, or None
     when the kernel or its launch changed after the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "cube48_level0_smoother_traffic.md")
     if not os.path.exists(path):
         return None
-    sha = kernel_source_hash()
+    sha = kernel_source_hash(starts)
     for line in open(path):
         if line.startswith("traffic ") and f"kernel={kernel_tag} " in line:
             kv = dict(t.split("=", 1) for t in line.split()[1:])
@@ -124,15 +136,33 @@ def summarize(infos, ndofs=None):
     return out
 
 
-def cpu_baseline(workload="cube", kappa=1e4):
-    """The oracle, untuned, on one Newton step of the same physics at a
-    bounded size (cube: 16^3 hexahedra; tube: 16 x 4 x 32), single-threaded."""
-    import synth
-    from oracle import fe, newton
+def host_cpu():
+    """(threads this process may run on, CPU model name) of the host."""
     try:
-        from threadpoolctl import threadpool_limits
-    except ImportError:  # pragma: no cover
-        threadpool_limits = None
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:  # pragma: no cover
+        pass
+    return n, model
+
+
+def cpu_baseline(workload="cube", kappa=1e4, reps=3):
+    """The oracle, untuned, on one Newton step of the same physics at a
+    bounded size (cube: 16^3 hexahedra from the converged load-0.8 state;
+    tube: 16 x 4 x 32, first pressure increment), timed per phase (assembly
+    with Dirichlet elimination and blocks, AMG set-up, FGMRES) with the BLAS
+    pool at all host threads and at one, median of `reps`."""
+    import synth
+    from oracle import fe, krylov, newton
+    from threadpoolctl import threadpool_limits
+    threads, model = host_cpu()
     if workload == "cube":
         prob = synth.cube_problem(16, kappa=kappa)
         d = fe.Discretization(prob)
@@ -149,18 +179,32 @@ def cpu_baseline(workload="cube", kappa=1e4):
     prm = newton.NewtonParams()
 
     def one():
-        t = time.perf_counter()
-        newton.newton_step(d, v, load, prm)
-        return time.perf_counter() - t
+        t0 = time.perf_counter()
+        K, b, A, B2, s = newton.linear_system(d, v, load)
+        t1 = time.perf_counter()
+        M, _ = krylov.amg_preconditioner(A, B2, s, d.n, prm.amg)
+        t2 = time.perf_counter()
+        dv, info = krylov.fgmres(K, M, b, m=prm.restart, maxit=prm.lin_maxit, tol=prm.lin_tol)
+        t3 = time.perf_counter()
+        d.mass_norm(dv)
+        t4 = time.perf_counter()
+        return dict(assembly=t1 - t0, setup=t2 - t1, solve=t3 - t2, step=t4 - t0, its=info.iterations)
 
-    if threadpool_limits is not None:
-        with threadpool_limits(limits=1):
-            dt = one()
-    else:
-        dt = one()
-    return {"value": prob.n_dofs / dt, "unit": "dofs/s", "cores": 1, "kind": "oracle",
+    runs = {}
+    for label, limit in (("all_threads", threads), ("one_thread", 1)):
+        with threadpool_limits(limits=limit):
+            rs = [one() for _ in range(reps)]
+        med = {k: float(np.median([r[k] for r in rs])) for k in ("assembly", "setup", "solve", "step")}
+        runs[label] = dict(threads=limit, dofs_per_s=prob.n_dofs / med["step"], seconds_median=med,
+                           seconds_step_min=min(r["step"] for r in rs), seconds_step_max=max(r["step"] for r in rs),
+                           fgmres_iterations=rs[0]["its"])
+    best = runs["all_threads"]
+    return {"value": best["dofs_per_s"], "unit": "dofs/s", "cores": threads, "kind": "oracle",
             "sample": f"one full Newton step (assembly, AMG set-up, FGMRES to 1e-8) of {what} "
-                      f"({prob.n_dofs} dofs), numpy/scipy fp64 single thread, {dt:.2f} s"}
+                      f"({prob.n_dofs} dofs), numpy/scipy fp64; median of {reps}; BLAS pool at {threads} threads "
+                      f"(the scipy sparse products, the element kernels and the set-up loops run on one thread); "
+                      f"host: {threads} threads, {model}",
+            "host_threads": threads, "host_cpu_model": model, "runs": runs}
 
 
 def main():
@@ -195,7 +239,11 @@ def main():
         w, wmeta = train_mlp.load(args.weights)
         ctx.mlp_set_weights(w)
     p_main = hfsi.newton_params(amg=hfsi.amg_params(precision=1, smoother=args.smoother, interp=1 if learned else 0,
-                                                    fallback_rho=args.fallback_rho), solve=sp)
+                                                    fallback_rho=args.fallback_rho, judge_classical=args.judge),
+                                solve=sp)
+    # the network forced on: no judge
+    p_forced = hfsi.newton_params(amg=hfsi.amg_params(precision=1, smoother=args.smoother, interp=1,
+                                                      fallback_rho=1.0, judge_classical=0), solve=sp)
     p_c32 = hfsi.newton_params(amg=hfsi.amg_params(precision=1, smoother=args.smoother), solve=sp)
     p64 = hfsi.newton_params(amg=hfsi.amg_params(precision=0, smoother=args.smoother), solve=sp)
     # untimed: converge the load increments below 1.0
@@ -217,188 +265,210 @@ def main():
         print(f"[bench] {label}: {dt / args.steps * 1e3:.1f} ms/step", file=sys.stderr, flush=True)
         return dt, inf, (v - v0).clone()
 
-    # headline: learned interpolation (or classical with --interp classical), fp32 V-cycle
-    dt_main, inf_main, d_main = timed(p_main, "learned fp32" if learned else "classical fp32")
+    # headline: learned interpolation under its judge (or classical with
+    # --interp classical), fp32 V-cycle; the first warm-up step takes the
+    # judge's verdict, the timed steps keep it
+    dt_main, inf_main, d_main = timed(p_main, "learned fp32 (judged)" if learned else "classical fp32")
+    legs = {}
     judge = {}
     if learned:
         info = ctx.amg_setup(p_main.amg)
-        judge = {"rho_learned": info.rho, "learned_used": bool(info.learned_used), "fallback_rho": args.fallback_rho}
-        info_c = ctx.amg_setup(p_c32.amg)
-        judge["rho_classical"] = ctx.amg_convergence_factor(10, 777)
+        judge = {"rho_learned": info.rho, "rho_classical": info.rho_classical,
+                 "learned_used": bool(info.learned_used), "fallback_rho": args.fallback_rho,
+                 "judge_classical": args.judge}
+        dt_f, inf_f, d_f = timed(p_forced, "learned fp32 forced on (no judge)")
+        legs["learned_forced_fp32"] = (dt_f, inf_f, d_f)
         dt_c32, inf_c32, d_c32 = timed(p_c32, "classical fp32")
-        res["classical_fp32"] = {"value": ndofs * args.steps / dt_c32, "unit": "dofs/s",
-                                 "ms_per_step": dt_c32 / args.steps * 1e3, **summarize(inf_c32, ndofs)}
+        legs["classical_fp32"] = (dt_c32, inf_c32, d_c32)
     if not args.no_fp64:
         dt64, inf64, d64 = timed(p64, "plain fp64")
-        err = float(torch.linalg.norm(d_main - d64) / torch.linalg.norm(d64))
-        res["fp64_plain"] = {"value": ndofs * args.steps / dt64, "unit": "dofs/s",
-                             "ms_per_step": dt64 / args.steps * 1e3, **summarize(inf64, ndofs)}
-        res["update_rel_err_vs_fp64"] = err
+        legs["fp64_plain"] = (dt64, inf64, d64)
+    for label, (dt_l, inf_l, d_l) in legs.items():
+        res[label] = {"value": ndofs * args.steps / dt_l, "unit": "dofs/s", "ms_per_step": dt_l / args.steps * 1e3,
+                      **summarize(inf_l, ndofs)}
+        if "fp64_plain" in legs and label != "fp64_plain":
+            res[label]["update_rel_diff_vs_fp64"] = float(torch.linalg.norm(d_l - d64) / torch.linalg.norm(d64))
+    if "fp64_plain" in legs:
+        res["update_rel_err_vs_fp64"] = float(torch.linalg.norm(d_main - d64) / torch.linalg.norm(d64))
         res["speedup_vs_fp64_plain"] = dt64 / dt_main
-    # (these legs follow the judge, whose set-ups use the last assembly: the
-    # headline state)
-    # coarse-grid reuse: the increment's second Newton step (from v1 = v0 +
-    # dv) re-set up on the first step's coarse grids, beside the same step
-    # with a full set-up
-    v.copy_(v0)
-    ctx.newton_step(v, 1.0, p_main)
-    v1 = v.clone()
-    p_reuse = hfsi.newton_params(amg=p_main.amg, solve=sp, amg_reuse=1)
-    reuse = {}
-    for label, prm in (("reused_coarse_grids", p_reuse), ("full_setup", p_main)):
-        run_steps(ctx, v1, v, prm, args.warmup, torch)
-        dt_r, inf_r = run_steps(ctx, v1, v, prm, args.steps, torch)
-        reuse[label] = {"ms_per_step": dt_r / args.steps * 1e3, **summarize(inf_r)}
-        print(f"[bench] second Newton step, {label}: {dt_r / args.steps * 1e3:.1f} ms/step", file=sys.stderr,
-              flush=True)
-    res["second_newton_step"] = reuse
-    # the whole last increment (Newton to ||dv_k||_M <= 1e-10 ||dv_0||_M) from
-    # the converged state of the one before: fixed 1e-8 inner solves with a
-    # full set-up per iteration, and the adaptive inner tolerance with the
-    # first iteration's coarse grids kept
-    inc = {}
-    for label, sprm in (("fixed_1e-8_full_setups", hfsi.newton_solve_params(step=p_main)),
-                        ("adaptive_reused_grids",
-                         hfsi.newton_solve_params(step=hfsi.newton_params(amg=p_main.amg, solve=sp, amg_reuse=1),
-                                                  adaptive=1))):
+    if not args.quick:
+        # (these legs follow the judge, whose set-ups use the last assembly: the
+        # headline state)
+        # coarse-grid reuse: the increment's second Newton step (from v1 = v0 +
+        # dv) re-set up on the first step's coarse grids, beside the same step
+        # with a full set-up
         v.copy_(v0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ninfo, code = ctx.newton_solve(v, 1.0, sprm)
-        torch.cuda.synchronize()
-        inc[label] = {"ms": (time.perf_counter() - t0) * 1e3, "newton_iterations": ninfo.newton_iterations,
-                      "krylov_iterations": ninfo.krylov_iterations, "converged": bool(ninfo.converged),
-                      "krylov_per_iteration": [ninfo.krylov[k] for k in range(min(ninfo.newton_iterations, 32))],
-                      "dv_mass_norm": [ninfo.dv_mass_norm[k] for k in range(min(ninfo.newton_iterations, 32))],
-                      "eps1": [ninfo.eps1[k] for k in range(min(ninfo.newton_iterations, 32))]}
-        print(f"[bench] last increment, {label}: {inc[label]['ms']:.0f} ms, {ninfo.newton_iterations} Newton, "
-              f"{ninfo.krylov_iterations} Krylov", file=sys.stderr, flush=True)
-    res["last_increment_newton_solve"] = inc
-    # the whole load run from the unloaded state (every increment solved by
-    # Newton to 1e-10), fixed 1e-8 inner solves with full set-ups against
-    # the adaptive inner tolerance with the coarse grids kept per increment
-    run = {}
-    for label, sprm in (("fixed_1e-8_full_setups", hfsi.newton_solve_params(step=p_main)),
-                        ("adaptive_reused_grids",
-                         hfsi.newton_solve_params(step=hfsi.newton_params(amg=p_main.amg, solve=sp, amg_reuse=1),
-                                                  adaptive=1))):
-        v.zero_()
-        newton_its = krylov_its = 0
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(1, increments + 1):
-            ninfo, code = ctx.newton_solve(v, k / increments, sprm)
-            if code != 0:
-                raise RuntimeError(f"increment {k} did not converge")
-            newton_its += ninfo.newton_iterations
-            krylov_its += ninfo.krylov_iterations
-        torch.cuda.synchronize()
-        run[label] = {"seconds": time.perf_counter() - t0, "increments": increments, "newton_iterations": newton_its,
-                      "krylov_iterations": krylov_its}
-        print(f"[bench] load run ({increments} increments), {label}: {run[label]['seconds']:.2f} s, {newton_its} "
-              f"Newton, {krylov_its} Krylov", file=sys.stderr, flush=True)
-    res["load_run"] = run
-    # dynamics (cube): Newmark-beta (rho_s = 1, dt = 0.05, beta = 0.625,
-    # gamma = 1) from rest under the full load, five time steps, with fixed
-    # 1e-8 inner solves and a new hierarchy per Newton iteration, and with the
-    # adaptive inner tolerance and the coarse grids kept across iterations and
-    # steps (the artery under its full pressure from rest needs smaller steps)
-    dyn = {}
-    dyn_runs = [("fixed_1e-8_full_setups", hfsi.newton_solve_params(step=p_main)),
-                ("adaptive_grids_kept_across_steps",
-                 hfsi.newton_solve_params(step=hfsi.newton_params(amg=p_main.amg, solve=sp, amg_reuse=2), adaptive=1))]
-    for label, sprm in dyn_runs if args.workload == "cube" else []:
-        ctx.set_newmark(1.0, dt=0.05)
-        v.zero_()
-        vel = torch.zeros(3 * (ndofs // 4), dtype=torch.float64, device="cuda")
-        acc = torch.zeros_like(vel)
-        newton_its = krylov_its = 0
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(5):
-            tinfo, code = ctx.time_step(v, vel, acc, 1.0, sprm)
-            if code != 0:
-                raise RuntimeError("a time step did not converge")
-            newton_its += tinfo.newton_iterations
-            krylov_its += tinfo.krylov_iterations
-        torch.cuda.synchronize()
-        dyn[label] = {"ms_per_time_step": (time.perf_counter() - t0) / 5 * 1e3, "newton_iterations": newton_its,
-                      "krylov_iterations": krylov_its}
-        print(f"[bench] 5 time steps, {label}: {dyn[label]['ms_per_time_step']:.0f} ms per step, "
-              f"{newton_its} Newton, {krylov_its} Krylov", file=sys.stderr, flush=True)
-    ctx.set_newmark(0.0)
-    if dyn:
-        res["newmark_time_steps"] = dyn
-    if args.workload == "tube":
-        # the solid side of the partitioned FSI sequence: 20 Newmark-beta steps
-        # of dt = 1e-3 (beta = 0.625, gamma = 1, wall density 1200 kg/m^3 =
-        # 1.2e-6 in the mm / kPa / s units of the model) from the converged
-        # state of the previous pressure increment under the full pressure;
-        # fp32 cycle with the coarse grids kept across steps and the adaptive
-        # inner tolerance, against plain fp64 AMG set up afresh per Newton
-        # iteration with fixed 1e-8 inner solves
-        # (Newton stops at the paper's eps2 = 1e-8 relative to the step's first
-        # increment)
-        seq = {}
-        for label, sprm in (("fp32_grids_kept_adaptive",
-                             hfsi.newton_solve_params(step=hfsi.newton_params(amg=p_main.amg, solve=sp, amg_reuse=2),
-                                                      adaptive=1, eps2=1e-8)),
-                            ("fp64_fresh_setups_fixed", hfsi.newton_solve_params(step=p64, eps2=1e-8))):
-            ctx.set_newmark(1.2e-6, dt=1e-3)
+        ctx.newton_step(v, 1.0, p_main)
+        v1 = v.clone()
+        p_reuse = hfsi.newton_params(amg=p_main.amg, solve=sp, amg_reuse=1)
+        reuse = {}
+        for label, prm in (("reused_coarse_grids", p_reuse), ("full_setup", p_main)):
+            run_steps(ctx, v1, v, prm, args.warmup, torch)
+            dt_r, inf_r = run_steps(ctx, v1, v, prm, args.steps, torch)
+            reuse[label] = {"ms_per_step": dt_r / args.steps * 1e3, **summarize(inf_r)}
+            print(f"[bench] second Newton step, {label}: {dt_r / args.steps * 1e3:.1f} ms/step", file=sys.stderr,
+                  flush=True)
+        res["second_newton_step"] = reuse
+        # the whole last increment (Newton to ||dv_k||_M <= 1e-10 ||dv_0||_M) from
+        # the converged state of the one before: fixed 1e-8 inner solves with a
+        # full set-up per iteration, and the adaptive inner tolerance with the
+        # first iteration's coarse grids kept
+        inc = {}
+        for label, sprm in (("fixed_1e-8_full_setups", hfsi.newton_solve_params(step=p_main)),
+                            ("adaptive_reused_grids",
+                             hfsi.newton_solve_params(step=hfsi.newton_params(amg=p_main.amg, solve=sp, amg_reuse=1),
+                                                      adaptive=1))):
             v.copy_(v0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ninfo, code = ctx.newton_solve(v, 1.0, sprm)
+            torch.cuda.synchronize()
+            inc[label] = {"ms": (time.perf_counter() - t0) * 1e3, "newton_iterations": ninfo.newton_iterations,
+                          "krylov_iterations": ninfo.krylov_iterations, "converged": bool(ninfo.converged),
+                          "krylov_per_iteration": [ninfo.krylov[k] for k in range(min(ninfo.newton_iterations, 32))],
+                          "dv_mass_norm": [ninfo.dv_mass_norm[k] for k in range(min(ninfo.newton_iterations, 32))],
+                          "eps1": [ninfo.eps1[k] for k in range(min(ninfo.newton_iterations, 32))]}
+            print(f"[bench] last increment, {label}: {inc[label]['ms']:.0f} ms, {ninfo.newton_iterations} Newton, "
+                  f"{ninfo.krylov_iterations} Krylov", file=sys.stderr, flush=True)
+        res["last_increment_newton_solve"] = inc
+        # the whole load run from the unloaded state (every increment solved by
+        # Newton to 1e-10), fixed 1e-8 inner solves with full set-ups against
+        # the adaptive inner tolerance with the coarse grids kept per increment
+        run = {}
+        for label, sprm in (("fixed_1e-8_full_setups", hfsi.newton_solve_params(step=p_main)),
+                            ("adaptive_reused_grids",
+                             hfsi.newton_solve_params(step=hfsi.newton_params(amg=p_main.amg, solve=sp, amg_reuse=1),
+                                                      adaptive=1))):
+            v.zero_()
+            newton_its = krylov_its = 0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(1, increments + 1):
+                ninfo, code = ctx.newton_solve(v, k / increments, sprm)
+                if code != 0:
+                    raise RuntimeError(f"increment {k} did not converge")
+                newton_its += ninfo.newton_iterations
+                krylov_its += ninfo.krylov_iterations
+            torch.cuda.synchronize()
+            run[label] = {"seconds": time.perf_counter() - t0, "increments": increments, "newton_iterations": newton_its,
+                          "krylov_iterations": krylov_its}
+            print(f"[bench] load run ({increments} increments), {label}: {run[label]['seconds']:.2f} s, {newton_its} "
+                  f"Newton, {krylov_its} Krylov", file=sys.stderr, flush=True)
+        res["load_run"] = run
+        # dynamics (cube): Newmark-beta (rho_s = 1, dt = 0.05, beta = 0.625,
+        # gamma = 1) from rest under the full load, five time steps, with fixed
+        # 1e-8 inner solves and a new hierarchy per Newton iteration, and with the
+        # adaptive inner tolerance and the coarse grids kept across iterations and
+        # steps (the artery under its full pressure from rest needs smaller steps)
+        dyn = {}
+        dyn_runs = [("fixed_1e-8_full_setups", hfsi.newton_solve_params(step=p_main)),
+                    ("adaptive_grids_kept_across_steps",
+                     hfsi.newton_solve_params(step=hfsi.newton_params(amg=p_main.amg, solve=sp, amg_reuse=2), adaptive=1))]
+        for label, sprm in dyn_runs if args.workload == "cube" else []:
+            ctx.set_newmark(1.0, dt=0.05)
+            v.zero_()
             vel = torch.zeros(3 * (ndofs // 4), dtype=torch.float64, device="cuda")
             acc = torch.zeros_like(vel)
             newton_its = krylov_its = 0
-            failed = None
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            for step in range(20):
+            for _ in range(5):
                 tinfo, code = ctx.time_step(v, vel, acc, 1.0, sprm)
+                if code != 0:
+                    raise RuntimeError("a time step did not converge")
                 newton_its += tinfo.newton_iterations
                 krylov_its += tinfo.krylov_iterations
-                if code != 0:
-                    failed = {"step": step, "dv_mass_norm": [tinfo.dv_mass_norm[k] for k in
-                                                             range(min(tinfo.newton_iterations, 32))]}
-                    break
             torch.cuda.synchronize()
-            seq[label] = {"seconds": time.perf_counter() - t0, "newton_iterations": newton_its,
-                          "krylov_iterations": krylov_its, "steps_done": 20 if failed is None else failed["step"],
-                          **({"failed": failed} if failed else {})}
-            print(f"[bench] FSI solid sequence (20 steps), {label}: {seq[label]['seconds']:.2f} s, {newton_its} Newton, "
-                  f"{krylov_its} Krylov{'' if failed is None else ', Newton failed at step %d' % failed['step']}",
-                  file=sys.stderr, flush=True)
+            dyn[label] = {"ms_per_time_step": (time.perf_counter() - t0) / 5 * 1e3, "newton_iterations": newton_its,
+                          "krylov_iterations": krylov_its}
+            print(f"[bench] 5 time steps, {label}: {dyn[label]['ms_per_time_step']:.0f} ms per step, "
+                  f"{newton_its} Newton, {krylov_its} Krylov", file=sys.stderr, flush=True)
         ctx.set_newmark(0.0)
-        res["fsi_solid_sequence"] = seq
-    # leave an fp32 classical hierarchy in place for the roofline timing
+        if dyn:
+            res["newmark_time_steps"] = dyn
+        if args.workload == "tube":
+            # the solid side of the partitioned FSI sequence: 20 Newmark-beta steps
+            # of dt = 1e-3 (beta = 0.625, gamma = 1, wall density 1200 kg/m^3 =
+            # 1.2e-6 in the mm / kPa / s units of the model) from the converged
+            # state of the previous pressure increment under the full pressure;
+            # fp32 cycle with the coarse grids kept across steps and the adaptive
+            # inner tolerance, against plain fp64 AMG set up afresh per Newton
+            # iteration with fixed 1e-8 inner solves
+            # (Newton stops at the paper's eps2 = 1e-8 relative to the step's first
+            # increment)
+            seq = {}
+            for label, sprm in (("fp32_grids_kept_adaptive",
+                                 hfsi.newton_solve_params(step=hfsi.newton_params(amg=p_main.amg, solve=sp, amg_reuse=2),
+                                                          adaptive=1, eps2=1e-8)),
+                                ("fp64_fresh_setups_fixed", hfsi.newton_solve_params(step=p64, eps2=1e-8))):
+                ctx.set_newmark(1.2e-6, dt=1e-3)
+                v.copy_(v0)
+                vel = torch.zeros(3 * (ndofs // 4), dtype=torch.float64, device="cuda")
+                acc = torch.zeros_like(vel)
+                newton_its = krylov_its = 0
+                failed = None
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for step in range(20):
+                    tinfo, code = ctx.time_step(v, vel, acc, 1.0, sprm)
+                    newton_its += tinfo.newton_iterations
+                    krylov_its += tinfo.krylov_iterations
+                    if code != 0:
+                        failed = {"step": step, "dv_mass_norm": [tinfo.dv_mass_norm[k] for k in
+                                                                 range(min(tinfo.newton_iterations, 32))]}
+                        break
+                torch.cuda.synchronize()
+                seq[label] = {"seconds": time.perf_counter() - t0, "newton_iterations": newton_its,
+                              "krylov_iterations": krylov_its, "steps_done": 20 if failed is None else failed["step"],
+                              **({"failed": failed} if failed else {})}
+                print(f"[bench] FSI solid sequence (20 steps), {label}: {seq[label]['seconds']:.2f} s, {newton_its} Newton, "
+                      f"{krylov_its} Krylov{'' if failed is None else ', Newton failed at step %d' % failed['step']}",
+                      file=sys.stderr, flush=True)
+            ctx.set_newmark(0.0)
+            res["fsi_solid_sequence"] = seq
+    # the headline state's tangent for the roofline timing
     v.copy_(v0)
-    info_last, _ = ctx.newton_step(v, 1.0, p_c32)
+    R0 = torch.zeros_like(v)
+    ctx.assemble_residual_tangent(v, 1.0, R0)
 
-    # roofline of the dominant kernel: the level-0 smoother step (fp32); HIP
-    # events around back-to-back launches on the library stream.  Inside a
-    # V-cycle the level-0 steps also run back to back and the data touched
-    # between two visits of level 0 fits the 256 MB last-level cache, so the
-    # operator is timed as reused; the cold figure (copies rotated through
-    # 512 MB) is reported beside it.
-    ms, nbytes = ctx.time_kernel(0, args.roofline_reps)
-    ms_cold, _ = ctx.time_kernel(0, args.roofline_reps, 512 << 20)
-    achieved = nbytes / (ms * 1e-3) / 1e9
-    sweep = "l1-Jacobi sweep (OP_JACOBI)" if args.smoother == 0 else "Chebyshev step (OP_CHEB)"
-    roof = {"kernel": f"level-0 {sweep}, fp32 3x3 node blocks, k_b3<float,...>", "bound": "hbm",
+    # roofline of the dominant kernel: the level-1 smoother step (fp32, padded
+    # CSR copy of A_1; at 96^3 its three launches per V-cycle take more time
+    # than any other kernel of the Newton step).  HIP events around
+    # back-to-back launches on the library stream; consecutive launches read
+    # different copies of the operator (together at least 1 GiB, above the
+    # 256 MB last-level cache), so every launch reads A_1 from HBM as it does
+    # inside the cycle.  Algorithmic bytes per launch (CSR with int32 columns
+    # and row pointers, fp32 values and vectors): 8 B per stored entry plus,
+    # per row, the row pointer and the vectors the step reads and writes
+    # (Chebyshev: x, b, D^-1 and the direction read, the direction and the
+    # new iterate written, 28 B; l1-Jacobi: x, b, D1^-1 read, x written, 20 B).
+    a1 = ctx.amg_setup(p_c32.amg)
+    rows1, nnz1 = a1.rows[1], a1.nnz[1]
+    per_row = 28.0 if args.smoother == 1 else 20.0
+    alg_bytes = 8.0 * nnz1 + per_row * rows1
+    ms_cold, lay_bytes = ctx.time_kernel(101, args.roofline_reps, 1 << 30)
+    ms_warm, _ = ctx.time_kernel(101, args.roofline_reps)
+    achieved = alg_bytes / (ms_cold * 1e-3) / 1e9
+    sweep = "l1-Jacobi sweep" if args.smoother == 0 else "Chebyshev step"
+    traffic = None
+    if args.smoother == 1 and args.workload == "cube" and args.N == 96:
+        traffic = measured_traffic("level1_cheb_fp32")
+    roof = {"kernel": f"level-1 {sweep}, fp32 padded CSR (k_csr4<float,G,4>)", "bound": "hbm",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": (measured_traffic("k_b3<float,4>")
-                        if args.smoother == 1 and args.workload == "cube" and args.N == 48 else None),
-            "avg_us": ms * 1e3, "bytes_per_launch": nbytes, "avg_us_cache_cold": ms_cold * 1e3,
-            "achieved_cache_cold": nbytes / (ms_cold * 1e-3) / 1e9}
+            "traffic": traffic, "avg_us": ms_cold * 1e3, "avg_us_operator_reused": ms_warm * 1e3,
+            "algorithmic_bytes_per_launch": alg_bytes, "level1_rows": rows1, "level1_nnz": nnz1,
+            "layout_bytes_per_launch": lay_bytes}
     extra = {}
-    for kid, name in ((1, "level-0 residual fp32"), (2, "tangent SpMV fp64 4x4 blocks"), (3, "element assembly")):
-        # the tangent product follows the V-cycle and the Krylov basis: cold
-        kms, kb = ctx.time_kernel(kid, 20 if kid != 3 else 3, 512 << 20 if kid == 2 else 0)
-        extra[name] = {"avg_us": kms * 1e3, "GB/s": kb / (kms * 1e-3) / 1e9}
-    for lev in range(1, info_last.amg_levels - 1):
+    for kid, name in ((0, "level-0 Chebyshev step fp32 3x3 blocks"), (1, "level-0 residual fp32"),
+                      (2, "tangent SpMV fp64 4x4 blocks"), (3, "element assembly")):
+        kms, kb = ctx.time_kernel(kid, 20 if kid != 3 else 3, (1 << 30) if kid in (0, 1, 2) else 0)
+        extra[name] = {"avg_us": kms * 1e3, "GB/s": kb / (kms * 1e-3) / 1e9, "bytes": kb}
+    for lev in range(2, a1.levels - 1):
         kms, kb = ctx.time_kernel(100 + lev, 20)
-        extra[f"level-{lev} smoother step fp32 CSR"] = {"avg_us": kms * 1e3, "GB/s": kb / (kms * 1e-3) / 1e9}
-    cms, cb = ctx.time_kernel(9, 20, 256 << 20)
-    extra["copy 256 MiB"] = {"avg_us": cms * 1e3, "GB/s": cb / (cms * 1e-3) / 1e9}
+        extra[f"level-{lev} smoother step fp32 CSR"] = {"avg_us": kms * 1e3, "GB/s": kb / (kms * 1e-3) / 1e9,
+                                                       "bytes": kb}
+    cms, cb = ctx.time_kernel(9, 20, 1 << 30)
+    extra["copy 1 GiB"] = {"avg_us": cms * 1e3, "GB/s": cb / (cms * 1e-3) / 1e9}
 
     out = {
         "metric": METRIC,

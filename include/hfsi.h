@@ -103,8 +103,11 @@ typedef struct {
  * pre-smoothing restricts its right-hand side directly).
  * precision: 0 = fp64 V-cycle, 1 = fp32 V-cycle (coarsest solve stays fp64).
  * interp: 0 = classical, 1 = learned correction on level 0 (needs MLP
- * weights and lattice coordinates), with classical fallback when the
- * measured convergence factor exceeds fallback_rho. */
+ * weights and lattice coordinates), judged by the convergence factor rho of
+ * its V-cycle (10 stationary cycles from the SplitMix64 vector of seed 777):
+ * the learned rows are kept only if rho <= fallback_rho and, with
+ * judge_classical > 0, rho <= the factor of the classical hierarchy on the
+ * same tangent; otherwise the classical hierarchy is built (the fallback). */
 typedef struct {
   size_t struct_size;
   double strength_theta; /* default 0.15                                   */
@@ -116,7 +119,7 @@ typedef struct {
                                correction, default 1 / 1                   */
   int32_t precision;
   int32_t interp;
-  double fallback_rho;   /* default 0.6                                    */
+  double fallback_rho;   /* default 0.5                                    */
   int32_t cheb_degree;   /* level-0 post-smoothing degree, 1..8, default 3 */
   double cheb_ratio;     /* lmax / lower bound of the interval, > 1, default 30 */
   int32_t interp_kind;   /* 0 = modified classical (distance one), 1 = extended+i
@@ -129,6 +132,14 @@ typedef struct {
   int32_t nu_post_coarse;     /* post-smoothing sweeps on levels >= 1, default 1 */
   int32_t cheb_degree_coarse; /* their degree, 1..8, default 3             */
   int32_t nu_pre_coarse;      /* pre-smoothing sweeps on levels >= 1, default 0 */
+  int32_t judge_classical;    /* learned interpolation only: 0 = threshold
+                                 fallback_rho alone; 1 = also compare with the
+                                 classical hierarchy's factor on every full
+                                 set-up (up to three hierarchy builds); 2 =
+                                 compare on the first full set-up of a mesh,
+                                 boundary set, material table, weight set and
+                                 parameter set, and keep that verdict for the
+                                 later set-ups (default)                   */
 } hfsi_amg_params;
 
 typedef struct {
@@ -142,6 +153,9 @@ typedef struct {
   double rho;            /* convergence factor measured by the judge (or -1) */
   int32_t learned_used;  /* 1 if the learned level-0 interpolation is kept */
   int32_t pmis_rounds;   /* PMIS rounds summed over levels                 */
+  double rho_classical;  /* the classical hierarchy's factor the judge
+                            compared with (measured now or kept from the
+                            first set-up), -1 if none                      */
 } hfsi_amg_info;
 
 typedef struct {
@@ -410,6 +424,19 @@ typedef struct {
 } hfsi_train_info;
 
 hfsi_status hfsi_mlp_set_weights(hfsi_ctx* ctx, const float* w /* host [HFSI_MLP_NPARAM] */);
+
+/* Weights from / to a raw checkpoint file (little endian): the 8 bytes
+ * "HFSIMLP" plus a zero byte, int32 version (1), int32 parameter count
+ * (HFSI_MLP_NPARAM), the fp32 parameters in the layout above, and the uint64
+ * FNV-1a hash of those parameter bytes.  Load replaces the weights as
+ * hfsi_mlp_set_weights does (Adam moments reset); HFSI_E_ARG when the file
+ * cannot be read or its magic, version, count or hash is wrong (the
+ * weights are then unchanged).  Save writes the current weights;
+ * HFSI_E_ORDER before any weights are set, HFSI_E_ARG when the file cannot
+ * be written. */
+#define HFSI_MLP_FILE_VERSION 1
+hfsi_status hfsi_mlp_load(hfsi_ctx* ctx, const char* path);
+hfsi_status hfsi_mlp_save(hfsi_ctx* ctx, const char* path);
 hfsi_status hfsi_mlp_get_weights(hfsi_ctx* ctx, float* w /* host [HFSI_MLP_NPARAM] */);
 /* host m [HFSI_MLP_NPARAM] and v: Adam moments; *step: Adam steps taken */
 hfsi_status hfsi_mlp_adam_state(hfsi_ctx* ctx, float* m, float* v, int64_t* step);

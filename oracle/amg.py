@@ -156,9 +156,11 @@ def interp_row_extpi(A, S_ptr, S_idx, state, comp, i, p_max=0):
     s_k = sum_{l in Chat_i + {i}} abar_kl (a strong F neighbour with s_k = 0
     is lumped into the diagonal instead), abar_kl = a_kl where its sign
     differs from that of a_kk, else 0.  With p_max > 0 a row with more
-    candidates keeps the p_max largest |w| (ties to the smaller column) and
-    is rescaled to its full row sum.  Every sum runs in ascending column
-    order.
+    candidates keeps the p_max largest |w| and is rescaled to its full row
+    sum; |w| is compared in float32, so that weights equal in exact
+    arithmetic (the symmetric stencils of a structured mesh give many) tie
+    whatever order their fp64 sums ran in, and ties go to the smaller
+    column.  Every sum runs in ascending column order.
     """
     lo, hi = A.indptr[i], A.indptr[i + 1]
     cols, vals = A.indices[lo:hi], A.data[lo:hi]
@@ -199,7 +201,7 @@ def interp_row_extpi(A, S_ptr, S_idx, state, comp, i, p_max=0):
         den += a_ik * abar.get(i, 0.0) / s
     w = {j: -num[j] / den for j in chat}
     if p_max and len(w) > p_max:
-        keep = sorted(w, key=lambda j: (-abs(w[j]), j))[:p_max]
+        keep = sorted(w, key=lambda j: (-float(np.float32(abs(w[j]))), j))[:p_max]
         tot = 0.0
         for j in sorted(w):
             tot += w[j]

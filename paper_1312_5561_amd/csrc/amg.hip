@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstring>
 
 #include "common.hpp"
 
@@ -288,8 +289,10 @@ k_interp_fill16(int n, const int* __restrict__ ptr, const int* __restrict__ col,
 // window of 64 entries of row i, neighbour t goes to group t mod NG.  Every
 // group keeps its own partial sums, added in group order at the end, so the
 // result does not depend on scheduling.  With p_max > 0 a longer row keeps
-// its p_max largest |w| (fp64 keys, ties to the smaller column), rescaled
-// to the full row sum.  FILL = false writes the entry count of each row,
+// its p_max largest |w| (compared in float32: weights equal in exact
+// arithmetic stay ties whatever order their fp64 sums ran in; ties to the
+// smaller column), rescaled to the full row sum.  FILL = false writes the
+// entry count of each row,
 // FILL = true the entries (ascending columns).
 constexpr int XH = 128;    // hash slots per row
 constexpr int XMAX = 96;   // candidates per row
@@ -544,10 +547,10 @@ k_extpi(int n, const int* __restrict__ ptr, const int* __restrict__ col, const d
   int* sel = s_mem[g];  // the insertion list is no longer needed
   if (trunc)
     for (int t = lane; t < m; t += 64) {
-      const double key = fabs(s_num[g][t]);
+      const float key = fabsf((float)s_num[g][t]);
       int r = 0;
       for (int u = 0; u < m; ++u) {
-        const double ku = fabs(s_num[g][u]);
+        const float ku = fabsf((float)s_num[g][u]);
         r += ku > key || (ku == key && u < t);
       }
       sel[t] = r;
@@ -1863,13 +1866,15 @@ void fill_info(const Hierarchy& H, hfsi_amg_info* info, int rounds, double rho) 
   info->grid_complexity = sr / rows0;
   info->pmis_rounds = rounds;
   info->rho = rho;
+  info->rho_classical = -1.0;
   info->learned_used = H.learned;
 }
 
 }  // namespace
 
-// Build levels 1.. from level 0 (whose A and comp are already set).
-void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {
+// Build levels 1.. from level 0 (whose A and comp are already set), with no
+// judge: the learned level-0 correction is applied when prm.interp == 1.
+void build_levels(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {
   hipStream_t s = c->stream;
   Hierarchy& H = c->H;
   H.ready = false;
@@ -2004,23 +2009,67 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
   }
   H.learned = prm.interp == 1 ? 1 : 0;
   finish_hierarchy(c, prm);
-  double rho = -1.0;
-  if (prm.interp == 1) {
-    // judge: keep the learned interpolation only if the V-cycle converges fast
-    rho = convergence_factor(c, 10, 777);
-    if (!(rho <= prm.fallback_rho)) {
-      hfsi_amg_params cl = prm;
-      cl.interp = 0;
-      H.L.resize(1);
-      build_hierarchy(c, cl, info);
-      if (info) {
-        info->rho = rho;
-        info->learned_used = 0;
-      }
-      return;
-    }
+  fill_info(H, info, rounds_total, -1.0);
+}
+
+// The hierarchy with the judge of the learned interpolation: the learned
+// level-0 rows are kept only if the convergence factor rho of the V-cycle
+// (10 stationary cycles from the SplitMix64 vector of seed 777) is at most
+// fallback_rho and, with judge_classical > 0, at most the factor of the
+// classical hierarchy on the same tangent; otherwise the classical hierarchy
+// is built.  judge_classical = 2 compares on the first set-up of a mesh,
+// boundary set, material table, weight set and parameter set and keeps the
+// verdict for the later set-ups (the learned rows follow the local stencils,
+// which the tangents of one problem share); 1 compares on every set-up.
+void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {
+  Hierarchy& H = c->H;
+  if (prm.interp != 1) {
+    build_levels(c, prm, info);
+    return;
   }
-  fill_info(H, info, rounds_total, rho);
+  hfsi_amg_params cl = prm;
+  cl.interp = 0;
+  auto& J = c->judge;
+  const bool cached = prm.judge_classical == 2 && J.valid && std::memcmp(&J.prm, &prm, sizeof(prm)) == 0;
+  if (cached && !J.learned_wins) {
+    H.L.resize(1);
+    build_levels(c, cl, info);
+    if (info) {
+      info->rho = J.rho_learned;
+      info->rho_classical = J.rho_classical;
+      info->learned_used = 0;
+    }
+    return;
+  }
+  build_levels(c, prm, info);
+  const double rho = convergence_factor(c, 10, 777);
+  double rho_c = cached ? J.rho_classical : -1.0;
+  bool keep = rho <= prm.fallback_rho;  // false for NaN
+  if (keep && prm.judge_classical > 0 && !cached) {
+    H.L.resize(1);
+    build_levels(c, cl, info);
+    rho_c = convergence_factor(c, 10, 777);
+    keep = rho <= rho_c;
+    if (keep) {
+      H.L.resize(1);
+      build_levels(c, prm, info);
+    }
+    if (prm.judge_classical == 2) {
+      J.valid = true;
+      J.prm = prm;
+      J.learned_wins = keep;
+      J.rho_learned = rho;
+      J.rho_classical = rho_c;
+    }
+  } else if (!keep) {
+    H.L.resize(1);
+    build_levels(c, cl, info);
+  }
+  if (info) {
+    info->rho = rho;
+    info->rho_classical = rho_c;
+    info->learned_used = keep ? 1 : 0;
+  }
 }
 
 void amg_setup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {
@@ -2101,6 +2150,7 @@ void check_amg_params(const hfsi_amg_params* p) {
   if (p->interp_kind < 0 || p->interp_kind > 1 || p->p_max < 0)
     fail(HFSI_E_ARG, "amg params: interp_kind 0 or 1, p_max >= 0");
   if (p->interp < 0 || p->interp > 1) fail(HFSI_E_ARG, "amg params: interp must be 0 (classical) or 1 (learned)");
+  if (p->judge_classical < 0 || p->judge_classical > 2) fail(HFSI_E_ARG, "amg params: judge_classical in 0..2");
 }
 
 }  // namespace hfsi

@@ -257,6 +257,15 @@ struct hfsi_ctx {
   hfsi::DevBuf<int> a_src;
   // hierarchy
   hfsi::Hierarchy H;
+  // verdict of the classical judge of the learned interpolation, kept for
+  // the later set-ups of the same problem, weights and parameters (reset by
+  // set_mesh, set_materials, set_bc and any change of the weights)
+  struct {
+    bool valid = false;
+    bool learned_wins = false;
+    double rho_learned = -1.0, rho_classical = -1.0;
+    hfsi_amg_params prm{};
+  } judge;
   // Krylov workspace
   hfsi::DevBuf<double> kv;       // basis V [(m+1) * N]
   hfsi::DevBuf<double> kz;       // Z [m * N]

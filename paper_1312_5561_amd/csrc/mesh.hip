@@ -227,7 +227,7 @@ void colour_elements(int n, int m, const int32_t* tets, std::vector<int>& perm, 
 
 // ================================================================== ABI
 
-extern "C" int32_t hfsi_abi_version(void) { return 1; }
+extern "C" int32_t hfsi_abi_version(void) { return 2; }
 
 namespace {
 std::atomic<int> g_live_contexts{0};  // the device block cache is trimmed when none is left
@@ -394,6 +394,7 @@ extern "C" hfsi_status hfsi_set_mesh(hfsi_ctx* c, int64_t n_nodes, const double*
   if (f[0]) fail(HFSI_E_ARG, "set_mesh: an element has non-positive volume (check orientation)");
   if (f[1]) fail(HFSI_E_CAPACITY, "set_mesh: a node has more than 127 neighbours");
   c->stage = 1;
+  c->judge.valid = false;
   HFSI_ABI_END(c)
 }
 
@@ -428,6 +429,7 @@ extern "C" hfsi_status hfsi_set_materials(hfsi_ctx* c, int32_t n_mat, const hfsi
   }
   HIP_CHECK(hipStreamSynchronize(c->stream));
   c->stage = 2;
+  c->judge.valid = false;
   HFSI_ABI_END(c)
 }
 
@@ -464,6 +466,7 @@ extern "C" hfsi_status hfsi_set_bc(hfsi_ctx* c, const uint8_t* dir_mask, int64_t
   build_a_pattern(c);
   HIP_CHECK(hipStreamSynchronize(c->stream));
   c->stage = 3;
+  c->judge.valid = false;
   c->H.ready = false;
   c->H.reusable = false;
   HFSI_ABI_END(c)

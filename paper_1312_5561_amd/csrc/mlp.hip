@@ -12,6 +12,10 @@
 // among the columns of row i, A[F_loc,F_loc] X = -A[F_loc,C_i], w*_i = row i.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
 
 #include "common.hpp"
 
@@ -507,6 +511,73 @@ extern "C" hfsi_status hfsi_mlp_set_weights(hfsi_ctx* c, const float* w) {
   hfsi::refresh_bf16(c, S);
   HIP_CHECK(hipStreamSynchronize(c->stream));
   S.ready = true;
+  c->judge.valid = false;
+  HFSI_ABI_END(c)
+}
+
+namespace {
+// 64-bit FNV-1a over a byte string (Fowler, Noll, Vo): offset basis
+// 14695981039346656037, prime 1099511628211
+uint64_t fnv1a64(const unsigned char* p, size_t n) {
+  uint64_t h = 14695981039346656037ull;
+  for (size_t k = 0; k < n; ++k) {
+    h ^= p[k];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+const char kMlpMagic[8] = {'H', 'F', 'S', 'I', 'M', 'L', 'P', '\0'};
+}  // namespace
+
+extern "C" hfsi_status hfsi_mlp_load(hfsi_ctx* c, const char* path) {
+  HFSI_ABI_BEGIN(c)
+  if (!path) fail(HFSI_E_ARG, "mlp_load: null path");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) fail(HFSI_E_ARG, std::string("mlp_load: cannot open ") + path);
+  char magic[8];
+  int32_t version = 0, count = 0;
+  uint64_t hash = 0;
+  std::vector<float> w(NPARAM);
+  const bool ok = std::fread(magic, 1, 8, f) == 8 && std::fread(&version, 4, 1, f) == 1 &&
+                  std::fread(&count, 4, 1, f) == 1 && count == NPARAM &&
+                  std::fread(w.data(), sizeof(float), NPARAM, f) == (size_t)NPARAM && std::fread(&hash, 8, 1, f) == 1;
+  const bool trailing = ok && std::fgetc(f) != EOF;
+  std::fclose(f);
+  if (!ok || std::memcmp(magic, kMlpMagic, 8) != 0)
+    fail(HFSI_E_ARG, std::string("mlp_load: ") + path + " is not a weight file of this network");
+  if (version != HFSI_MLP_FILE_VERSION) fail(HFSI_E_ARG, "mlp_load: unsupported file version");
+  if (trailing) fail(HFSI_E_ARG, "mlp_load: trailing bytes after the hash");
+  if (fnv1a64(reinterpret_cast<const unsigned char*>(w.data()), sizeof(float) * NPARAM) != hash)
+    fail(HFSI_E_ARG, "mlp_load: parameter hash mismatch (corrupt file)");
+  hfsi::MlpState& S = hfsi::mlp_state(c);
+  S.master.upload(w.data(), NPARAM, c->stream);
+  S.m.zero(NPARAM, c->stream);
+  S.v.zero(NPARAM, c->stream);
+  S.step = 0;
+  hfsi::refresh_bf16(c, S);
+  HIP_CHECK(hipStreamSynchronize(c->stream));
+  S.ready = true;
+  c->judge.valid = false;
+  HFSI_ABI_END(c)
+}
+
+extern "C" hfsi_status hfsi_mlp_save(hfsi_ctx* c, const char* path) {
+  HFSI_ABI_BEGIN(c)
+  if (!path) fail(HFSI_E_ARG, "mlp_save: null path");
+  hfsi::MlpState& S = hfsi::mlp_state(c);
+  if (!S.ready) fail(HFSI_E_ORDER, "mlp_save: no weights are set");
+  std::vector<float> w(NPARAM);
+  HIP_CHECK(hipMemcpyAsync(w.data(), S.master.p, sizeof(float) * NPARAM, hipMemcpyDeviceToHost, c->stream));
+  HIP_CHECK(hipStreamSynchronize(c->stream));
+  const int32_t version = HFSI_MLP_FILE_VERSION, count = NPARAM;
+  const uint64_t hash = fnv1a64(reinterpret_cast<const unsigned char*>(w.data()), sizeof(float) * NPARAM);
+  FILE* f = std::fopen(path, "wb");
+  if (!f) fail(HFSI_E_ARG, std::string("mlp_save: cannot open ") + path);
+  bool ok = std::fwrite(kMlpMagic, 1, 8, f) == 8 && std::fwrite(&version, 4, 1, f) == 1 &&
+            std::fwrite(&count, 4, 1, f) == 1 && std::fwrite(w.data(), sizeof(float), NPARAM, f) == (size_t)NPARAM &&
+            std::fwrite(&hash, 8, 1, f) == 1;
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) fail(HFSI_E_ARG, std::string("mlp_save: cannot write ") + path);
   HFSI_ABI_END(c)
 }
 
@@ -698,6 +769,7 @@ extern "C" hfsi_status hfsi_mlp_train(hfsi_ctx* c, const hfsi_train_params* prm,
   hfsi::DevBuf<int> dorder;
   dorder.upload(order, n_order, s);
   hfsi::DevBuf<float> ws;
+  c->judge.valid = false;
   HIP_CHECK(hipEventRecord(c->ev0, s));
   double first = -1, last = 0;
   int steps = 0;

@@ -1121,8 +1121,11 @@ k_dot2_part(long N, const double* __restrict__ x1, const double* __restrict__ y1
 }
 
 // reduce the two partial rows into bs[i1], bs[i2] (i2 < 0: one row), then
-// step: 0 alpha = rho / r^.v; 1 omega = t.s / t.t (0 if t = 0); 2 beta for
-// the next direction, rho <- r^.r; 3 nothing
+// step: 0 alpha = rho / r^.v (0 if r^.v = 0: the update below is then a
+// minimal-residual step along P_L^{-1} r, so x and r stay finite and
+// consistent, and the host restarts or reports the breakdown); 1 omega =
+// t.s / t.t (0 if t = 0); 2 beta for the next direction (0 if the old rho or
+// omega is 0; the host never uses it then), rho <- r^.r; 3 nothing
 __global__ void __launch_bounds__(256)
 k_bicg_scalars(int nb, const double* __restrict__ part, double* __restrict__ bs, int i1, int i2, int step) {
   __shared__ double r1[256], r2[256];
@@ -1144,10 +1147,10 @@ k_bicg_scalars(int nb, const double* __restrict__ part, double* __restrict__ bs,
   if (threadIdx.x != 0) return;
   bs[i1] = r1[0];
   if (i2 >= 0) bs[i2] = r2[0];
-  if (step == 0) bs[1] = bs[0] / bs[4];
+  if (step == 0) bs[1] = bs[4] != 0.0 ? bs[0] / bs[4] : 0.0;
   else if (step == 1) bs[2] = bs[6] > 0.0 ? bs[5] / bs[6] : 0.0;
   else if (step == 2) {
-    bs[3] = (bs[8] / bs[0]) * (bs[1] / bs[2]);
+    bs[3] = bs[0] != 0.0 && bs[2] != 0.0 ? (bs[8] / bs[0]) * (bs[1] / bs[2]) : 0.0;
     bs[0] = bs[8];
   }
 }
@@ -1242,6 +1245,8 @@ void bicgstab_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_pa
       k_bicg_scalars<<<1, 256, 0, s>>>(RED_BLOCKS, part, bs, 0, -1, 3);
       HIP_LAUNCH_CHECK();
       bool first = true;
+      int cycle_its = 0;
+      bool stalled = false;
       while (its < prm.max_iter) {
         k_bicg_dir<<<gN, 256, 0, s>>>(N, r, v, bs, first ? 1 : 0, p);
         HIP_LAUNCH_CHECK();
@@ -1262,15 +1267,20 @@ void bicgstab_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_pa
         HIP_CHECK(hipMemcpyAsync(c->pinned, bs, 9 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
         ++its;
+        ++cycle_its;
         const double* q = c->pinned;
         const double rr = q[7], rv = q[4], omega = q[2], rho = q[0];
         if (!std::isfinite(rr)) fail(HFSI_E_NAN, "BiCGStab: non-finite residual");
         if (std::sqrt(rr) <= prm.tol * bnorm) break;
         if (rv == 0.0 || omega == 0.0 || rho == 0.0) {
-          breakdown = true;
+          // the recurrence cannot continue: start again from the true
+          // residual with a new shadow vector, unless the fresh start itself
+          // broke down
+          stalled = true;
           break;
         }
       }
+      if (stalled && cycle_its == 1) breakdown = true;
       residual(c, b, x, r);
       norm_dev(c, r, N, sc + 1);
       rel = read_scalar(c, sc + 1) / bnorm;

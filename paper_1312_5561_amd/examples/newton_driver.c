@@ -3,13 +3,17 @@
  * load in increments with Newton's method (hfsi_newton_solve, Section
  * "Newton's Method") and writes the final state.
  *
- *   newton_driver <problem file> <increments> <state out> [adaptive 0/1]
+ *   newton_driver <problem file> <increments> <state out> [adaptive 0/1] [weights]
  *
  * Problem file, little endian: int64 n, m, k; double X[n][3]; int32
  * tets[m][4]; int32 mat_id[m]; uint8 dir_mask[n][4]; int32 tris[k][3];
  * double traction[k][3]; int32 n_mat; per material int32 model and double
- * c10, c01, kappa, k1, k2.  State out: double v[n][4].  Exit status 0 when
- * every increment converged. */
+ * c10, c01, kappa, k1, k2; optionally int32 has_lattice and, if it is 1,
+ * int32 lattice[n][3] (the integer lattice coordinates the learned
+ * interpolation needs).  With a weight file (hfsi_mlp_load format) the
+ * level-0 interpolation is the learned one under the classical judge and the
+ * V-cycle runs in fp32; otherwise classical interpolation and an fp64 cycle.
+ * State out: double v[n][4].  Exit status 0 when every increment converged. */
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -29,7 +33,7 @@ static void* take(size_t bytes) {
 }
 
 /* defaults documented in hfsi.h */
-static hfsi_newton_solve_params default_params(int adaptive) {
+static hfsi_newton_solve_params default_params(int adaptive, int learned) {
   hfsi_newton_solve_params p;
   hfsi_amg_params* a = &p.step.amg;
   hfsi_solve_params* s = &p.step.solve;
@@ -44,9 +48,9 @@ static hfsi_newton_solve_params default_params(int adaptive) {
   a->smoother = 1;
   a->nu_pre = 1;
   a->nu_post = 1;
-  a->precision = 0;
-  a->interp = 0;
-  a->fallback_rho = 0.6;
+  a->precision = learned ? 1 : 0;
+  a->interp = learned ? 1 : 0;
+  a->fallback_rho = 0.5;
   a->cheb_degree = 3;
   a->cheb_ratio = 30.0;
   a->interp_kind = 1;
@@ -55,6 +59,7 @@ static hfsi_newton_solve_params default_params(int adaptive) {
   a->nu_post_coarse = 1;
   a->cheb_degree_coarse = 3;
   a->nu_pre_coarse = 0;
+  a->judge_classical = 2;
   s->struct_size = sizeof *s;
   s->tol = 1e-8;
   s->restart = 50;
@@ -79,11 +84,12 @@ static hfsi_newton_solve_params default_params(int adaptive) {
 
 int main(int argc, char** argv) {
   if (argc < 4) {
-    fprintf(stderr, "usage: %s <problem file> <increments> <state out> [adaptive]\n", argv[0]);
+    fprintf(stderr, "usage: %s <problem file> <increments> <state out> [adaptive] [weights]\n", argv[0]);
     return 2;
   }
   const int increments = atoi(argv[2]);
   const int adaptive = argc > 4 ? atoi(argv[4]) : 0;
+  const char* weights = argc > 5 ? argv[5] : NULL;
   FILE* f = fopen(argv[1], "rb");
   if (!f || increments < 1) {
     fprintf(stderr, "cannot read %s or bad increment count\n", argv[1]);
@@ -124,14 +130,27 @@ int main(int argc, char** argv) {
     mats[i].k2 = c[4];
     mats[i].theta = 0.0;
   }
+  int32_t has_lattice = 0;
+  int32_t* lattice = NULL;
+  if (read_all(f, &has_lattice, 4, 1) && has_lattice == 1) {
+    lattice = take(sizeof(int32_t) * 3 * n);
+    if (!read_all(f, lattice, 4, 3 * n)) {
+      fprintf(stderr, "truncated lattice coordinates\n");
+      return 2;
+    }
+  }
   fclose(f);
+  if (weights && !lattice) {
+    fprintf(stderr, "the learned interpolation needs lattice coordinates in the problem file\n");
+    return 2;
+  }
 
   hfsi_ctx* ctx = NULL;
   if (hfsi_create(&ctx, 0, NULL) != HFSI_OK) {
     fprintf(stderr, "hfsi_create failed\n");
     return 1;
   }
-  CHECK(hfsi_set_mesh(ctx, n, X, m, tets, mat, NULL, NULL));
+  CHECK(hfsi_set_mesh(ctx, n, X, m, tets, mat, lattice, NULL));
   CHECK(hfsi_set_materials(ctx, n_mat, mats));
   CHECK(hfsi_set_bc(ctx, dir, k, tris, trac));
   double* v = NULL;
@@ -139,7 +158,8 @@ int main(int argc, char** argv) {
     fprintf(stderr, "device allocation failed\n");
     return 1;
   }
-  const hfsi_newton_solve_params prm = default_params(adaptive);
+  if (weights) CHECK(hfsi_mlp_load(ctx, weights));
+  const hfsi_newton_solve_params prm = default_params(adaptive, weights != NULL);
   int all = 1;
   for (int inc = 1; inc <= increments; ++inc) {
     hfsi_newton_solve_info info;
@@ -166,6 +186,6 @@ int main(int argc, char** argv) {
   fclose(o);
   (void)hipFree(v);
   (void)hfsi_destroy(ctx);
-  free(X); free(tets); free(mat); free(dir); free(tris); free(trac); free(mats); free(h);
+  free(X); free(tets); free(mat); free(dir); free(tris); free(trac); free(mats); free(h); free(lattice);
   return all ? 0 : 3;
 }

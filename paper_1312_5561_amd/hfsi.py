@@ -48,14 +48,15 @@ class AmgParams(C.Structure):
                 ("nu_post", C.c_int32), ("precision", C.c_int32), ("interp", C.c_int32),
                 ("fallback_rho", C.c_double), ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
                 ("interp_kind", C.c_int32), ("p_max", C.c_int32), ("cheb_degree_pre", C.c_int32),
-                ("nu_post_coarse", C.c_int32), ("cheb_degree_coarse", C.c_int32), ("nu_pre_coarse", C.c_int32)]
+                ("nu_post_coarse", C.c_int32), ("cheb_degree_coarse", C.c_int32), ("nu_pre_coarse", C.c_int32),
+                ("judge_classical", C.c_int32)]
 
 
 class AmgInfo(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("levels", C.c_int32), ("rows", C.c_int32 * 32),
                 ("nnz", C.c_int64 * 32), ("op_complexity", C.c_double), ("grid_complexity", C.c_double),
                 ("seconds", C.c_double), ("rho", C.c_double), ("learned_used", C.c_int32),
-                ("pmis_rounds", C.c_int32)]
+                ("pmis_rounds", C.c_int32), ("rho_classical", C.c_double)]
 
 
 class SolveParams(C.Structure):
@@ -111,11 +112,14 @@ def train_params(batch=1024, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
 
 
 def amg_params(theta=0.15, max_coarse=500, max_levels=25, seed=12345, smoother=1, nu_pre=1, nu_post=1,
-               precision=0, interp=0, fallback_rho=0.6, cheb_degree=3, cheb_ratio=30.0, interp_kind=1, p_max=4,
-               cheb_degree_pre=1, nu_post_coarse=1, cheb_degree_coarse=3, nu_pre_coarse=0):
+               precision=0, interp=0, fallback_rho=0.5, cheb_degree=3, cheb_ratio=30.0, interp_kind=1, p_max=4,
+               cheb_degree_pre=1, nu_post_coarse=1, cheb_degree_coarse=3, nu_pre_coarse=0, judge_classical=2):
+    """judge_classical (learned interpolation): 0 threshold only, 1 compare
+    with the classical factor on every set-up, 2 on the first set-up of a
+    problem and weight set (verdict kept)."""
     return AmgParams(C.sizeof(AmgParams), theta, max_coarse, max_levels, seed, smoother, nu_pre, nu_post,
                      precision, interp, fallback_rho, cheb_degree, cheb_ratio, interp_kind, p_max, cheb_degree_pre,
-                     nu_post_coarse, cheb_degree_coarse, nu_pre_coarse)
+                     nu_post_coarse, cheb_degree_coarse, nu_pre_coarse, judge_classical)
 
 
 def solve_params(tol=1e-8, restart=50, max_iter=500, method=0):
@@ -171,6 +175,8 @@ def load():
         "hfsi_export_tangent": [vp, vp, vp, vp, vp, vp, vp, vp],
         "hfsi_time_kernel": [vp, i32, i32, i64, C.POINTER(dbl), C.POINTER(dbl)],
         "hfsi_mlp_set_weights": [vp, vp],
+        "hfsi_mlp_load": [vp, C.c_char_p],
+        "hfsi_mlp_save": [vp, C.c_char_p],
         "hfsi_mlp_get_weights": [vp, vp],
         "hfsi_mlp_adam_state": [vp, vp, vp, C.POINTER(i64)],
         "hfsi_mlp_forward": [vp, i32, vp, vp, vp, vp, vp],
@@ -383,6 +389,13 @@ class Context:
         w = np.ascontiguousarray(w, np.float32)
         assert w.size == MLP_NPARAM
         self._check(self.lib.hfsi_mlp_set_weights(self.h, _ptr(w)))
+
+    def mlp_load(self, path):
+        """Weights from a raw checkpoint file (see hfsi_mlp_load)."""
+        self._check(self.lib.hfsi_mlp_load(self.h, os.fsencode(path)))
+
+    def mlp_save(self, path):
+        self._check(self.lib.hfsi_mlp_save(self.h, os.fsencode(path)))
 
     def mlp_get_weights(self):
         w = np.zeros(MLP_NPARAM, np.float32)

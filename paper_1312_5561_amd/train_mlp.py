@@ -26,6 +26,29 @@ if ROOT not in sys.path:
 
 FORMAT_VERSION = 1
 DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "mlp_cube.npz")
+# the same weights as the raw file hfsi_mlp_load reads (C callers)
+DEFAULT_RAW_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "mlp_cube.hfsimlp")
+RAW_MAGIC = b"HFSIMLP\0"
+RAW_VERSION = 1
+
+
+def _fnv1a64(data: bytes) -> int:
+    h = 14695981039346656037
+    for byte in data:
+        h = ((h ^ byte) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def write_raw(path, w):
+    """The raw weight file of hfsi_mlp_load: magic, int32 version, int32
+    count, fp32 parameters, uint64 FNV-1a hash of the parameter bytes."""
+    w = np.ascontiguousarray(w, "<f4")
+    payload = w.tobytes()
+    with open(path, "wb") as f:
+        f.write(RAW_MAGIC)
+        f.write(np.array([RAW_VERSION, w.size], "<i4").tobytes())
+        f.write(payload)
+        f.write(np.array([_fnv1a64(payload)], "<u8").tobytes())
 
 
 def init_weights(seed=0):
@@ -92,6 +115,7 @@ def save(path, ctx, meta):
     os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
     np.savez(path, weights=w, adam_m=m, adam_v=v, step=np.int64(step), version=np.int64(FORMAT_VERSION),
              meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
+    write_raw(os.path.splitext(path)[0] + ".hfsimlp", w)
 
 
 def load(path):
@@ -128,7 +152,8 @@ def evaluate(path, cases=((8, 9001), (8, 9002), (16, 9003), (24, 9004), (48, 900
         b = -R
         res = {}
         for interp in (0, 1):
-            info = ctx.amg_setup(hfsi.amg_params(smoother=1, precision=1, interp=interp, fallback_rho=1.0))
+            info = ctx.amg_setup(hfsi.amg_params(smoother=1, precision=1, interp=interp, fallback_rho=1.0,
+                                                    judge_classical=0))
             rho = ctx.amg_convergence_factor(10, 777)
             x = torch.zeros_like(b)
             torch.cuda.synchronize()

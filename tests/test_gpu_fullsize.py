@@ -11,7 +11,7 @@
 * the 96^3 cube with the default hierarchy: level-0 C/F splitting bit-exact
   with the oracle's PMIS on the GPU's A; the learned interpolation is judged
   by the convergence factor and both interpolations solve the Newton system
-  to 1e-8.
+  to 1e-8, checked on the host with the exported tangent.
 """
 import numpy as np
 import pytest
@@ -30,6 +30,11 @@ def _blocks_csr(out, n):
     r = (4 * rows[:, None, None] + np.arange(4)[None, :, None]).repeat(4, axis=2)
     c = (4 * bc[:, None, None] + np.arange(4)[None, None, :]).repeat(4, axis=1)
     return sp.csr_matrix((bv.ravel(), (r.ravel(), c.ravel())), shape=(4 * n, 4 * n))
+
+
+def _blocks_bsr(out, n):
+    """The exported block tangent as a scipy BSR matrix (no index expansion)."""
+    return sp.bsr_matrix((out["block_val"], out["block_col"], out["block_ptr"]), shape=(4 * n, 4 * n))
 
 
 def _assembled(lib, prob, v, load, inertia=None):
@@ -134,9 +139,15 @@ def test_cube96_splitting_and_learned_judge(lib):
     assert np.array_equal(st, amg.pmis(S_ptr, S_idx, A.shape[0], gprm.seed, 0))
     del A, S_ptr, S_idx
     b = -R
+    bh = b.cpu().numpy()
+    K = _blocks_bsr(ctx.export_tangent(view), n)
     x = torch.zeros_like(b)
     sc, code = ctx.krylov_amg_solve(b, x, lib.solve_params(tol=1e-8, restart=256, max_iter=3000))
     assert code == 0 and sc.converged
+    xc = x.cpu().numpy()
+    rel_c = np.linalg.norm(bh - K @ xc) / np.linalg.norm(bh)
+    print(f"[fullsize cube96] classical fp32 cycle: host residual {rel_c:.2e}", flush=True)
+    assert rel_c <= 1.05e-8
     rho_c = ctx.amg_convergence_factor(10, 777)
     w, _ = train_mlp.load(train_mlp.DEFAULT_WEIGHTS)
     ctx.mlp_set_weights(w)
@@ -145,6 +156,11 @@ def test_cube96_splitting_and_learned_judge(lib):
     x = torch.zeros_like(b)
     sl, code = ctx.krylov_amg_solve(b, x, lib.solve_params(tol=1e-8, restart=256, max_iter=3000))
     assert code == 0 and sl.converged
+    xl = x.cpu().numpy()
+    rel_l = np.linalg.norm(bh - K @ xl) / np.linalg.norm(bh)
+    print(f"[fullsize cube96] learned fp32 cycle: host residual {rel_l:.2e}; update vs classical "
+          f"{np.linalg.norm(xl - xc) / np.linalg.norm(xc):.2e}", flush=True)
+    assert rel_l <= 1.05e-8
     print(f"[fullsize cube96] classical: rho={rho_c:.3f} its={sc.iterations}; learned: rho={linfo.rho:.3f} "
           f"kept={linfo.learned_used} its={sl.iterations}", flush=True)
     assert 0 < linfo.rho < 1

@@ -76,7 +76,7 @@ def test_loss_gradient_matches_oracle(lib):
     assert np.abs(g[keep] - go[keep]).max() <= 1e-4 * np.abs(go[keep]).max()
 
 
-def _cube_setup(lib, N=6, seed=3, interp=0, weights=None, fallback=0.5, kind=1):
+def _cube_setup(lib, N=6, seed=3, interp=0, weights=None, fallback=0.5, kind=1, judge=0):
     import torch
     prob = synth.cube_problem(N, jitter=0.1, seed=seed)
     ctx = context_for(lib, prob)
@@ -86,7 +86,7 @@ def _cube_setup(lib, N=6, seed=3, interp=0, weights=None, fallback=0.5, kind=1):
     R = torch.zeros_like(v)
     ctx.assemble_residual_tangent(v, 1.0, R)
     info = ctx.amg_setup(lib.amg_params(max_coarse=60, interp=interp, fallback_rho=fallback, smoother=1,
-                                        interp_kind=kind))
+                                        interp_kind=kind, judge_classical=judge))
     return prob, ctx, info
 
 
@@ -164,3 +164,104 @@ def test_training_reduces_loss_and_adam_matches(lib):
     loss_before, _ = ctx.mlp_loss_grad(X, mask, wcl, wst)
     print(f"[mlp training] full-set loss {loss_before:.3e} -> {loss_after:.3e} ({info.steps} steps)", flush=True)
     assert loss_after < 0.9 * loss_before
+
+
+def _same_hierarchy(ctx_a, ctx_b, levels):
+    for l in range(levels):
+        a = export_level_matrix(ctx_a, l, 0)
+        b = export_level_matrix(ctx_b, l, 0)
+        if not (np.array_equal(a.indptr, b.indptr) and np.array_equal(a.indices, b.indices)
+                and np.array_equal(a.data, b.data)):
+            return False
+    return True
+
+
+def test_judge_against_classical(lib):
+    """judge_classical = 1: the classical factor on the same tangent is
+    measured (equal to a separate classical set-up's), and the learned rows
+    are kept iff rho_learned <= min(fallback_rho, rho_classical); a network
+    that spoils the rows loses to classical even under a permissive
+    threshold, and the hierarchy is then the classical one bit for bit; the
+    zero-last-layer network ties with classical and is kept."""
+    import torch
+    from paper_1312_5561_amd import train_mlp
+    print("[judge] cube6 classical reference", flush=True)
+    prob, ctx_c, info_c = _cube_setup(lib)
+    rho_c = ctx_c.amg_convergence_factor(10, 777)
+    w, _ = train_mlp.load(train_mlp.DEFAULT_WEIGHTS)
+    _, ctx, info = _cube_setup(lib, interp=1, weights=w, judge=1)
+    assert abs(info.rho_classical - rho_c) <= 1e-12 * rho_c
+    assert info.learned_used == (info.rho <= min(0.5, info.rho_classical))
+    print(f"[judge] trained: rho_learned={info.rho:.4f} rho_classical={info.rho_classical:.4f} "
+          f"kept={info.learned_used}", flush=True)
+    if not info.learned_used:
+        assert _same_hierarchy(ctx, ctx_c, info_c.levels)
+    bad = mlp.init_weights(11)
+    bad[-32 - 2048:-32] = 0.05
+    _, ctx_b, info_b = _cube_setup(lib, interp=1, weights=bad, fallback=1.0, judge=1)
+    assert info_b.rho > rho_c and info_b.learned_used == 0
+    assert abs(info_b.rho_classical - rho_c) <= 1e-12 * rho_c
+    assert _same_hierarchy(ctx_b, ctx_c, info_c.levels)
+    _, ctx_z, info_z = _cube_setup(lib, interp=1, weights=mlp.init_weights(11), fallback=1.0, judge=1)
+    assert info_z.learned_used == 1 and info_z.rho == info_z.rho_classical
+    # threshold only: the spoiled network is kept under fallback_rho = 1
+    _, ctx_t, info_t = _cube_setup(lib, interp=1, weights=bad, fallback=1.0, judge=0)
+    assert info_t.learned_used == 1 and info_t.rho_classical == -1.0
+
+
+def test_judge_verdict_is_kept_per_problem(lib):
+    """judge_classical = 2: the first set-up measures both factors; a later
+    set-up on another tangent of the same problem reuses that verdict (the
+    same rho_classical, no new measurement); new weights reset it."""
+    import torch
+    bad = mlp.init_weights(11)
+    bad[-32 - 2048:-32] = 0.05
+    prob, ctx, info1 = _cube_setup(lib, interp=1, weights=bad, fallback=1.0, judge=2)
+    assert info1.learned_used == 0 and info1.rho_classical > 0
+    v = torch_dev(synth.random_state(prob, 9, u_scale=0.04, p_scale=0.1).ravel())
+    R = torch.zeros_like(v)
+    ctx.assemble_residual_tangent(v, 0.8, R)
+    prm = lib.amg_params(max_coarse=60, interp=1, fallback_rho=1.0, smoother=1, judge_classical=2)
+    info2 = ctx.amg_setup(prm)
+    assert info2.learned_used == 0
+    assert info2.rho_classical == info1.rho_classical and info2.rho == info1.rho
+    # a fresh classical factor on the new tangent differs from the kept one
+    rho_new = ctx.amg_convergence_factor(10, 777)
+    assert rho_new != info1.rho_classical
+    ctx.mlp_set_weights(bad)
+    info3 = ctx.amg_setup(prm)
+    assert abs(info3.rho_classical - rho_new) <= 1e-12 * rho_new
+
+
+def test_weight_file_round_trip(lib, tmp_path):
+    """hfsi_mlp_save / hfsi_mlp_load: the raw file restores the weights bit
+    for bit; a corrupted byte, a wrong count or a missing file is an
+    argument error that leaves the weights unchanged; the committed raw file
+    holds the committed checkpoint's weights."""
+    import os
+    from paper_1312_5561_amd import train_mlp
+    ctx = lib.Context(0)
+    w = mlp.init_weights(5)
+    w[-32 - 2048:-32] = np.linspace(-1, 1, 2048, dtype=np.float32)
+    ctx.mlp_set_weights(w)
+    path = str(tmp_path / "w.hfsimlp")
+    ctx.mlp_save(path)
+    raw = open(path, "rb").read()
+    assert len(raw) == 8 + 4 + 4 + 4 * lib.MLP_NPARAM + 8 and raw[:8] == b"HFSIMLP\0"
+    ctx2 = lib.Context(0)
+    ctx2.mlp_load(path)
+    assert np.array_equal(ctx2.mlp_get_weights(), w)
+    bad = bytearray(raw)
+    bad[100] ^= 1
+    open(path, "wb").write(bytes(bad))
+    with pytest.raises(lib.HfsiError):
+        ctx2.mlp_load(path)
+    assert np.array_equal(ctx2.mlp_get_weights(), w)
+    with pytest.raises(lib.HfsiError):
+        ctx2.mlp_load(str(tmp_path / "missing.hfsimlp"))
+    open(path, "wb").write(raw[:-8])
+    with pytest.raises(lib.HfsiError):
+        ctx2.mlp_load(path)
+    wc, _ = train_mlp.load(train_mlp.DEFAULT_WEIGHTS)
+    ctx2.mlp_load(train_mlp.DEFAULT_RAW_WEIGHTS)
+    assert np.array_equal(ctx2.mlp_get_weights(), wc)

@@ -200,7 +200,7 @@ def test_resetup_keeps_learned_interpolation(lib):
     prob = synth.cube_problem(6, jitter=0.1, seed=3)
     v1 = synth.random_state(prob, 9, u_scale=0.04, p_scale=0.1).ravel()
     prm_c = lib.amg_params(max_coarse=60)
-    prm_l = lib.amg_params(max_coarse=60, interp=1, fallback_rho=1.0)
+    prm_l = lib.amg_params(max_coarse=60, interp=1, fallback_rho=1.0, judge_classical=0)
     ctx_c = context_for(lib, prob)
     _assemble(ctx_c, np.zeros(prob.n_dofs), 1.0)
     ctx_c.amg_setup(prm_c)

@@ -75,6 +75,66 @@ def test_vcycle_and_preconditioner_match_oracle(lib, smoother, precision, nu, ch
     assert np.linalg.norm(ky.cpu().numpy() - ko) <= 1e-13 * np.linalg.norm(ko)
 
 
+def _lanes_per_row(A):
+    """Lanes per row the library's padded-CSR smoother picks for a coarse
+    level (3 to 6 four-entry chunks per lane, more lanes on small levels):
+    the test asserts which kernel variants a case exercises."""
+    chunks = int(np.sum((np.diff(A.indptr) + 3) // 4))
+    rows = A.shape[0]
+    avg = chunks / rows if rows else 1.0
+    G = 2
+    while G < 64 and 6.0 * G <= avg:
+        G *= 2
+    while G < 64 and rows * G < 65536:
+        G *= 2
+    return G
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("N,precision", [(24, 0), (24, 1), (48, 0), (48, 1)])
+def test_vcycle_and_preconditioner_entrywise_on_large_levels(lib, N, precision):
+    """The default cycle and hierarchy at 24^3 and 48^3, where level 1 has
+    more than 8192 rows and its smoother runs with 8 lanes per row (16 on
+    level 2 at 48^3), the variants the benchmark sizes use: V-cycle, P_L and
+    K x against the oracle applying the same operators, entry by entry
+    (|z_i - zo_i| <= tol max|zo|)."""
+    import torch
+    prob = synth.cube_problem(N, jitter=0.1, seed=2)
+    v = synth.random_state(prob, 3, u_scale=0.01, p_scale=0.05).ravel()
+    print(f"[vcycle entrywise] N={N} precision={precision}", flush=True)
+    ctx, R, info, oprm = _setup(lib, prob, v, 0.4, 1, precision, schedule="default")
+    H = gpu_hierarchy_to_oracle(ctx, info, oprm)
+    lanes = [_lanes_per_row(L.A) for L in H.levels[1:-1]]
+    print(f"[vcycle entrywise] rows={[L.A.shape[0] for L in H.levels]} lanes={lanes}", flush=True)
+    assert H.levels[1].A.shape[0] >= 8192 and lanes[0] == 8
+    if N == 48:
+        assert 16 in lanes
+    rng = np.random.default_rng(1)
+    n3 = H.levels[0].A.shape[0]
+    r = rng.normal(size=n3)
+    z = torch.zeros(n3, dtype=torch.float64, device="cuda")
+    ctx.vcycle(torch_dev(r), z)
+    zo = amg.vcycle(H, r, oprm)
+    tol = 1e-12 if precision == 0 else 2e-5
+    dz = np.abs(z.cpu().numpy() - zo)
+    print(f"[vcycle entrywise] max |z - zo| / max |zo| = {dz.max() / np.abs(zo).max():.2e}", flush=True)
+    assert dz.max() <= tol * np.abs(zo).max()
+    d, K, b, A, B2, s = oracle_system(prob, v, 0.4)
+    M = krylov.BlockPreconditioner(lambda x: amg.vcycle(H, x, oprm), B2, s, prob.n_nodes)
+    rr = rng.normal(size=4 * prob.n_nodes)
+    rr[prob.dir_mask.ravel().astype(bool)] = 0.0
+    y = torch.zeros(4 * prob.n_nodes, dtype=torch.float64, device="cuda")
+    ctx.apply_preconditioner(torch_dev(rr), y)
+    yo = M(rr)
+    dy = np.abs(y.cpu().numpy() - yo)
+    print(f"[vcycle entrywise] P_L: max |y - yo| / max |yo| = {dy.max() / np.abs(yo).max():.2e}", flush=True)
+    assert dy.max() <= tol * np.abs(yo).max()
+    ky = torch.zeros_like(y)
+    ctx.apply_tangent(torch_dev(rr), ky)
+    ko = K @ rr
+    assert np.abs(ky.cpu().numpy() - ko).max() <= 1e-13 * np.abs(ko).max()
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_fgmres_solution(lib, precision):
     import torch
