@@ -140,6 +140,12 @@ typedef struct {
                                  boundary set, material table, weight set and
                                  parameter set, and keep that verdict for the
                                  later set-ups (default)                   */
+  double drop_tol;            /* coarse operators: off-diagonal entries with
+                                 |a_ij| < drop_tol sqrt(|a_ii a_jj|) of each
+                                 Galerkin product are dropped (compared in
+                                 float32), in [0, 1), 0 = exact Galerkin
+                                 (default); a re-set-up keeps the
+                                 set-up's sparsified patterns              */
 } hfsi_amg_params;
 
 typedef struct {
@@ -311,8 +317,9 @@ hfsi_status hfsi_amg_setup(hfsi_ctx* ctx, const hfsi_amg_params* prm, hfsi_amg_i
  * coarse operators R A P (as in "AMG methods for the mixed problems"), the
  * smoother data and the coarsest inverse are recomputed.  The smoothing
  * settings and precision come from *prm; its coarsening settings (theta,
- * seed, interp, interp_kind, p_max, level limits) are those of the kept
- * grids and are ignored.  No judge runs (info->rho = -1).  For a sequence of
+ * seed, interp, interp_kind, p_max, drop_tol, level limits) are those of the
+ * kept grids and are ignored (the coarse operators keep the set-up's
+ * sparsified patterns).  No judge runs (info->rho = -1).  For a sequence of
  * nearby tangents (Newton or time steps) this trades a slower V-cycle for a
  * cheaper set-up.  HFSI_E_ORDER if no set-up of this mesh's tangent is
  * available (a new mesh or boundary data, a set-up from a caller CSR, or a

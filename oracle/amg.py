@@ -14,7 +14,9 @@ used here.  The readings followed are:
   De Sterck et al. 2008) restricted to same-component strong couplings, no
   truncation, C rows the identity;
 * Galerkin coarse operators A_c = P^T A P with the structural product
-  pattern (no dropping of numerically zero entries);
+  pattern, then sparsified: off-diagonal entries with
+  |a_ij| < drop_tol sqrt(|a_ii a_jj|) are removed (no lumping; drop_tol = 0
+  keeps the exact Galerkin operator);
 * l1-Jacobi smoothing (Baker, Falgout, Kolev & Yang 2011) or degree-2
   Chebyshev on D^{-1}A, and a dense LU solve on the coarsest level.
 """
@@ -259,6 +261,42 @@ def galerkin(A, P):
     return sp.csr_matrix((data, pat.indices.copy(), pat.indptr.copy()), shape=pat.shape)
 
 
+def drop_small(Ac, eps):
+    """Sparsified coarse operator: every off-diagonal entry with
+    |a_ij| < eps sqrt(|a_ii a_jj|) is removed, nothing is lumped.  Both
+    sides of the comparison are rounded to float32 (the product, square root
+    and scaling in fp64 first), so an entry that sits on the threshold in
+    exact arithmetic is decided the same way whatever order the sums of the
+    Galerkin product ran in.  eps <= 0 returns Ac unchanged."""
+    if eps <= 0:
+        return Ac
+    Ac = Ac.tocsr()
+    n = Ac.shape[0]
+    rows = np.repeat(np.arange(n), np.diff(Ac.indptr))
+    cols = Ac.indices
+    d = np.abs(Ac.diagonal())
+    thr = (eps * np.sqrt(d[rows] * d[cols])).astype(np.float32)
+    keep = (rows == cols) | ~(np.abs(Ac.data).astype(np.float32) < thr)
+    indptr = np.zeros(n + 1, np.int64)
+    np.add.at(indptr, rows[keep] + 1, 1)
+    return sp.csr_matrix((Ac.data[keep], cols[keep], np.cumsum(indptr)), shape=Ac.shape)
+
+
+def coarse_operator(A, P, drop_tol=0.0):
+    """A_c = drop_small(P^T A P, drop_tol)."""
+    return drop_small(galerkin(A, P), drop_tol)
+
+
+def on_pattern(M, pattern):
+    """The entries of M at the stored positions of `pattern` (a subset of
+    M's pattern), in pattern's layout."""
+    M = M.tocsr()
+    pattern = pattern.tocsr()
+    rr = np.repeat(np.arange(pattern.shape[0]), np.diff(pattern.indptr))
+    data = np.asarray(M[rr, pattern.indices]).ravel() if pattern.nnz else np.zeros(0)
+    return sp.csr_matrix((data, pattern.indices.copy(), pattern.indptr.copy()), shape=pattern.shape)
+
+
 # ---------------------------------------------------------------------------
 # smoothers
 # ---------------------------------------------------------------------------
@@ -323,6 +361,7 @@ class AmgParams:
     nu_pre_coarse: int = 0         # pre-smoothing sweeps on levels >= 1 (degree cheb_degree_pre)
     interp: str = "ext+i"          # or "classical"
     p_max: int = 4                 # ext+i truncation (0: none)
+    drop_tol: float = 0.0          # coarse-operator sparsification (0: exact Galerkin)
     lanczos_steps: int = 10
     max_dense: int = 8192
 
@@ -350,7 +389,7 @@ def setup(A, comp, prm: AmgParams = AmgParams()):
             break
         P, ccomp = interpolation(L.A, S[0], S[1], st, L.comp, prm.interp, prm.p_max)
         L.S, L.state, L.P, L.R = S, st, P, P.T.tocsr()
-        levels.append(Level(galerkin(L.A, P), ccomp))
+        levels.append(Level(coarse_operator(L.A, P, prm.drop_tol), ccomp))
     last = levels[-1]
     if last.A.shape[0] > prm.max_dense:
         raise RuntimeError("coarsest level too large for the dense solve")
@@ -362,9 +401,10 @@ def resetup(A, H: Hierarchy, prm: AmgParams = AmgParams()):
     """Hierarchy of a new operator A (same size and component map as the
     level-0 operator of H) on the coarse grids of H: the C/F splittings and
     interpolations P (R = P^T) of H are kept, every coarse operator is the
-    Galerkin product of the new level above it, and the smoother data and the
-    coarsest LU are recomputed.  With A equal to H's own level-0 operator this
-    is H again."""
+    Galerkin product of the new level above it restricted to the stored
+    pattern of H's operator on that level (the set-up's sparsified pattern),
+    and the smoother data and the coarsest LU are recomputed.  With A equal
+    to H's own level-0 operator this is H again."""
     old = H.levels
     if A.shape != old[0].A.shape:
         raise ValueError("resetup: operator size differs from the hierarchy's")
@@ -375,7 +415,7 @@ def resetup(A, H: Hierarchy, prm: AmgParams = AmgParams()):
         if o.P is None:
             break
         L.S, L.state, L.P, L.R = o.S, o.state, o.P, o.R
-        levels.append(Level(galerkin(L.A, o.P), old[lev + 1].comp))
+        levels.append(Level(on_pattern(galerkin(L.A, o.P), old[lev + 1].A), old[lev + 1].comp))
     lu = scipy.linalg.lu_factor(levels[-1].A.toarray())
     return Hierarchy(levels, lu)
 

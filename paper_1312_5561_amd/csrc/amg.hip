@@ -1496,7 +1496,7 @@ __global__ void __launch_bounds__(64)
 k_spgemm_values(int n, const int* __restrict__ ap, const int* __restrict__ ac, const double* __restrict__ av,
                 const int* __restrict__ bp, const int* __restrict__ bc, const double* __restrict__ bv,
                 const int* __restrict__ cp, const int* __restrict__ cc, double* __restrict__ cv,
-                int* __restrict__ flag) {
+                int* __restrict__ flag, int strict) {
   __shared__ int wcol[W];
   __shared__ double wval[W];
   __shared__ int f_s[NARROW ? 64 * WB : 1];
@@ -1538,7 +1538,7 @@ k_spgemm_values(int n, const int* __restrict__ ap, const int* __restrict__ ac, c
               const int j = bc[qb + q];
               if (j >= jlo && j <= jhi) {
                 h = window_slot(wcol, wl, j);
-                if (h < 0) bad = true;
+                if (h < 0 && strict) bad = true;
               }
               f_b[lane * WB + q] = bv[qb + q];
             }
@@ -1570,7 +1570,7 @@ k_spgemm_values(int n, const int* __restrict__ ap, const int* __restrict__ ac, c
               if (j >= jlo && j <= jhi) {
                 const int h = window_slot(wcol, wl, j);
                 if (h >= 0) wval[h] += a * bv[q];
-                else bad = true;
+                else if (strict) bad = true;
               }
             }
             __syncthreads();
@@ -1584,20 +1584,110 @@ k_spgemm_values(int n, const int* __restrict__ ap, const int* __restrict__ ac, c
   if (__any(bad) && lane == 0) atomicOr(flag, 16);
 }
 
+// diagonal entry of every row (0 if the row has none); columns ascending
+__global__ void k_diag_of(int n, const int* __restrict__ ptr, const int* __restrict__ col,
+                          const double* __restrict__ val, double* __restrict__ dg) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int lo = ptr[i], hi = ptr[i + 1] - 1;
+  double d = 0.0;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int j = col[mid];
+    if (j < i) lo = mid + 1;
+    else if (j > i) hi = mid - 1;
+    else {
+      d = val[mid];
+      break;
+    }
+  }
+  dg[i] = d;
+}
+
+// Coarse-operator sparsification: an off-diagonal entry is dropped when
+// (float)|a_ij| < (float)(eps sqrt(|a_ii| |a_jj|)) (both sides rounded to
+// float32 after the fp64 product, square root and scaling, so that entries
+// on the threshold in exact arithmetic decide alike whatever the summation
+// order of the product); nothing is lumped.  One wavefront per row, 64
+// entries per ballot.  FILL = false writes the kept count of row i to cnt[i],
+// FILL = true writes the kept entries in order from optr[i].
+template <bool FILL>
+__global__ void __launch_bounds__(256)
+k_drop_small(int n, const int* __restrict__ ptr, const int* __restrict__ col, const double* __restrict__ val,
+             const double* __restrict__ dg, double eps, int* __restrict__ cnt, const int* __restrict__ optr,
+             int* __restrict__ ocol, double* __restrict__ oval) {
+  const int i = (int)(((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;  // uniform per wavefront
+  const double di = fabs(dg[i]);
+  const int hi = ptr[i + 1];
+  int off = FILL ? optr[i] : 0;
+  for (int b = ptr[i]; b < hi; b += 64) {
+    const int e = b + lane;
+    bool keep = false;
+    int j = 0;
+    double a = 0.0;
+    if (e < hi) {
+      j = col[e];
+      a = val[e];
+      keep = j == i || !((float)fabs(a) < (float)(eps * sqrt(di * fabs(dg[j]))));
+    }
+    const unsigned long long m = __ballot(keep);
+    if (FILL && keep) {
+      const int pos = off + __popcll(m & ((1ull << lane) - 1ull));
+      ocol[pos] = j;
+      oval[pos] = a;
+    }
+    off += __popcll(m);
+  }
+  if (!FILL && lane == 0) cnt[i] = off;
+}
+
+// A <- A without its small off-diagonal entries (k_drop_small), in place of
+// the Galerkin product on a coarse level
+void drop_small(hfsi_ctx* c, Csr<double>& A, double eps) {
+  hipStream_t s = c->stream;
+  const int n = A.rows;
+  if (n <= 0 || !(eps > 0.0)) return;
+  DevBuf<double> dg;
+  dg.ensure(n);
+  k_diag_of<<<div_up(n, 256), 256, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, dg.p);
+  HIP_LAUNCH_CHECK();
+  DevBuf<int> cnt;
+  cnt.zero(n + 1, s);
+  const int grid = div_up((long)n * 64, 256);
+  k_drop_small<false><<<grid, 256, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, dg.p, eps, cnt.p, nullptr, nullptr,
+                                           nullptr);
+  HIP_LAUNCH_CHECK();
+  Csr<double> B;
+  B.rows = n;
+  B.cols = A.cols;
+  B.ptr.ensure(n + 1);
+  B.nnz = exclusive_scan(cnt.p, B.ptr.p, n + 1, s);
+  B.col.ensure(std::max<int64_t>(B.nnz, 1));
+  B.val.ensure(std::max<int64_t>(B.nnz, 1));
+  k_drop_small<true><<<grid, 256, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, dg.p, eps, nullptr, B.ptr.p, B.col.p,
+                                          B.val.p);
+  HIP_LAUNCH_CHECK();
+  A = std::move(B);
+}
+
 // C = A B into the existing pattern of Cm (an earlier product of the same
-// patterns); bmax = the longest row of B, as returned by spgemm.
+// patterns, or a sparsified one: strict = false skips the products whose
+// column the pattern does not hold); bmax = the longest row of B, as
+// returned by spgemm.
 void spgemm_values(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>& Cm, int bmax,
-                   int* deferred) {
+                   int* deferred, bool strict = true) {
   hipStream_t s = c->stream;
   const int n = A.rows;
   if (Cm.rows != n || Cm.cols != B.cols) fail(HFSI_E_ARG, "sparse product values: pattern of other operands");
   const int grid = std::max(1, std::min(n, 1 << 16));
   if (bmax <= 4)
     k_spgemm_values<512, 4, true><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p,
-                                                      Cm.ptr.p, Cm.col.p, Cm.val.p, deferred);
+                                                      Cm.ptr.p, Cm.col.p, Cm.val.p, deferred, strict ? 1 : 0);
   else
     k_spgemm_values<512, 1, false><<<grid, 64, 0, s>>>(n, A.ptr.p, A.col.p, A.val.p, B.ptr.p, B.col.p, B.val.p,
-                                                       Cm.ptr.p, Cm.col.p, Cm.val.p, deferred);
+                                                       Cm.ptr.p, Cm.col.p, Cm.val.p, deferred, strict ? 1 : 0);
   HIP_LAUNCH_CHECK();
 }
 
@@ -2001,6 +2091,7 @@ void build_levels(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) 
     Level& Lc = H.L.back();
     Level& Lf = H.L[l];  // reference may move with emplace_back
     Lf.ap_rowmax = spgemm(c, Lf.R, Lf.AP, Lc.A, H.setup_flags.p);
+    drop_small(c, Lc.A, prm.drop_tol);
     Lc.n = nc;
     Lc.comp.ensure(nc);
     k_coarse_comp<<<div_up(n, 256), 256, 0, s>>>(n, Lf.state.p, Lf.cidx.p, Lf.comp.p, Lc.comp.p);
@@ -2008,6 +2099,7 @@ void build_levels(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) 
     if (prm.precision == 1) to_f32_transfer(c, Lf);
   }
   H.learned = prm.interp == 1 ? 1 : 0;
+  H.drop_tol = prm.drop_tol;
   finish_hierarchy(c, prm);
   fill_info(H, info, rounds_total, -1.0);
 }
@@ -2126,7 +2218,7 @@ void amg_resetup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* 
     if (l + 1 == nl) break;
     Level& Lf = H.L[l];
     spgemm_values(c, Lf.A, Lf.P, Lf.AP, Lf.p_rowmax, H.setup_flags.p);
-    spgemm_values(c, Lf.R, Lf.AP, H.L[l + 1].A, Lf.ap_rowmax, H.setup_flags.p);
+    spgemm_values(c, Lf.R, Lf.AP, H.L[l + 1].A, Lf.ap_rowmax, H.setup_flags.p, !(H.drop_tol > 0.0));
     if (prm.precision == 1 && prev_precision != 1) to_f32_transfer(c, Lf);  // P, R unchanged
   }
   finish_hierarchy(c, prm, true);
@@ -2151,6 +2243,7 @@ void check_amg_params(const hfsi_amg_params* p) {
     fail(HFSI_E_ARG, "amg params: interp_kind 0 or 1, p_max >= 0");
   if (p->interp < 0 || p->interp > 1) fail(HFSI_E_ARG, "amg params: interp must be 0 (classical) or 1 (learned)");
   if (p->judge_classical < 0 || p->judge_classical > 2) fail(HFSI_E_ARG, "amg params: judge_classical in 0..2");
+  if (!(p->drop_tol >= 0.0 && p->drop_tol < 1.0)) fail(HFSI_E_ARG, "amg params: drop_tol in [0, 1)");
 }
 
 }  // namespace hfsi

@@ -206,6 +206,8 @@ struct Hierarchy {
   double cheb_ratio = 30.0;     // interval [lmax / ratio, 1.1 lmax]
   bool ready = false;
   int learned = 0;        // 1 if level 0 carries the learned interpolation
+  double drop_tol = 0.0;  // coarse-operator sparsification of the set-up (a
+                          // re-set-up keeps the sparsified patterns)
   bool reusable = false;  // built from this mesh's assembled tangent: its
                           // coarse grids may be kept by a re-set-up
 };

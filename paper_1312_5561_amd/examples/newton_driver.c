@@ -60,6 +60,7 @@ static hfsi_newton_solve_params default_params(int adaptive, int learned) {
   a->cheb_degree_coarse = 3;
   a->nu_pre_coarse = 0;
   a->judge_classical = 2;
+  a->drop_tol = 0.0;
   s->struct_size = sizeof *s;
   s->tol = 1e-8;
   s->restart = 50;

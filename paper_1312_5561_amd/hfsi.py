@@ -49,7 +49,7 @@ class AmgParams(C.Structure):
                 ("fallback_rho", C.c_double), ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
                 ("interp_kind", C.c_int32), ("p_max", C.c_int32), ("cheb_degree_pre", C.c_int32),
                 ("nu_post_coarse", C.c_int32), ("cheb_degree_coarse", C.c_int32), ("nu_pre_coarse", C.c_int32),
-                ("judge_classical", C.c_int32)]
+                ("judge_classical", C.c_int32), ("drop_tol", C.c_double)]
 
 
 class AmgInfo(C.Structure):
@@ -113,13 +113,16 @@ def train_params(batch=1024, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
 
 def amg_params(theta=0.15, max_coarse=500, max_levels=25, seed=12345, smoother=1, nu_pre=1, nu_post=1,
                precision=0, interp=0, fallback_rho=0.5, cheb_degree=3, cheb_ratio=30.0, interp_kind=1, p_max=4,
-               cheb_degree_pre=1, nu_post_coarse=1, cheb_degree_coarse=3, nu_pre_coarse=0, judge_classical=2):
+               cheb_degree_pre=1, nu_post_coarse=1, cheb_degree_coarse=3, nu_pre_coarse=0, judge_classical=2,
+               drop_tol=0.0):
     """judge_classical (learned interpolation): 0 threshold only, 1 compare
     with the classical factor on every set-up, 2 on the first set-up of a
-    problem and weight set (verdict kept)."""
+    problem and weight set (verdict kept).  drop_tol: coarse operators lose
+    their off-diagonal entries below drop_tol sqrt(|a_ii a_jj|) (0: exact
+    Galerkin)."""
     return AmgParams(C.sizeof(AmgParams), theta, max_coarse, max_levels, seed, smoother, nu_pre, nu_post,
                      precision, interp, fallback_rho, cheb_degree, cheb_ratio, interp_kind, p_max, cheb_degree_pre,
-                     nu_post_coarse, cheb_degree_coarse, nu_pre_coarse, judge_classical)
+                     nu_post_coarse, cheb_degree_coarse, nu_pre_coarse, judge_classical, drop_tol)
 
 
 def solve_params(tol=1e-8, restart=50, max_iter=500, method=0):

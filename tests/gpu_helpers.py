@@ -47,7 +47,7 @@ def gpu_hierarchy_to_oracle(ctx, info, prm: amg.AmgParams):
 
 
 def amg_prm_pair(lib, smoother=0, precision=0, max_coarse=500, theta=0.15, seed=12345, nu=2, nu_post=None,
-                 cheb=(2, 30.0), kind="classical", p_max=4, schedule=None):
+                 cheb=(2, 30.0), kind="classical", p_max=4, schedule=None, drop_tol=None):
     """GPU and oracle AMG parameters with the same settings.  schedule=None:
     the same sweeps (nu, nu_post) and Chebyshev degree cheb[0] on every level;
     schedule="default": the library's default smoothing schedule."""
@@ -60,10 +60,14 @@ def amg_prm_pair(lib, smoother=0, precision=0, max_coarse=500, theta=0.15, seed=
         nu_post = nu if nu_post is None else nu_post
         sm = dict(nu_pre=nu, nu_post=nu_post, cheb_degree=cheb[0], cheb_ratio=cheb[1], cheb_degree_pre=cheb[0],
                   nu_post_coarse=nu_post, cheb_degree_coarse=cheb[0], nu_pre_coarse=nu)
+    if drop_tol is None:
+        drop_tol = lib.amg_params().drop_tol
     g = lib.amg_params(theta=theta, max_coarse=max_coarse, seed=seed, smoother=smoother,
-                       interp_kind=1 if kind == "ext+i" else 0, p_max=p_max, precision=precision, **sm)
+                       interp_kind=1 if kind == "ext+i" else 0, p_max=p_max, precision=precision,
+                       drop_tol=drop_tol, **sm)
     o = amg.AmgParams(theta=theta, max_coarse=max_coarse, seed=seed,
-                      smoother="l1jacobi" if smoother == 0 else "chebyshev", interp=kind, p_max=p_max, **sm)
+                      smoother="l1jacobi" if smoother == 0 else "chebyshev", interp=kind, p_max=p_max,
+                      drop_tol=drop_tol, **sm)
     return g, o
 
 

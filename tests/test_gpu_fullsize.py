@@ -164,4 +164,5 @@ def test_cube96_splitting_and_learned_judge(lib):
     print(f"[fullsize cube96] classical: rho={rho_c:.3f} its={sc.iterations}; learned: rho={linfo.rho:.3f} "
           f"kept={linfo.learned_used} its={sl.iterations}", flush=True)
     assert 0 < linfo.rho < 1
-    assert linfo.learned_used == (linfo.rho <= lprm.fallback_rho)
+    assert abs(linfo.rho_classical - rho_c) <= 1e-9 * rho_c
+    assert linfo.learned_used == (linfo.rho <= min(lprm.fallback_rho, linfo.rho_classical))

@@ -29,18 +29,20 @@ def _assemble(ctx, v, load):
     return R
 
 
-@pytest.mark.parametrize("smoother,precision,kind", [(0, 0, "ext+i"), (1, 0, "ext+i"), (1, 1, "ext+i"),
-                                                     (1, 0, "classical")])
-def test_resetup_matches_oracle(lib, smoother, precision, kind):
+@pytest.mark.parametrize("smoother,precision,kind,drop", [(0, 0, "ext+i", 0.0), (1, 0, "ext+i", 0.0),
+                                                          (1, 1, "ext+i", 0.0), (1, 0, "classical", 0.0),
+                                                          (1, 0, "ext+i", 2e-3)])
+def test_resetup_matches_oracle(lib, smoother, precision, kind, drop):
     """ext+i with p_max = 4 takes the narrow value-only product for A P;
-    classical interpolation (longer rows of P) the general one."""
+    classical interpolation (longer rows of P) the general one; drop > 0:
+    sparsified coarse operators, whose patterns the re-set-up keeps."""
     import torch
-    print(f"[reuse parity] smoother={smoother} precision={precision} interp={kind}", flush=True)
+    print(f"[reuse parity] smoother={smoother} precision={precision} interp={kind} drop={drop}", flush=True)
     prob = synth.cube_problem(6, jitter=0.1, seed=2)
     v0 = synth.random_state(prob, 3, u_scale=0.03, p_scale=0.05).ravel()
     v1 = synth.random_state(prob, 7, u_scale=0.06, p_scale=0.2).ravel()
     gprm, oprm = amg_prm_pair(lib, smoother=smoother, precision=precision, max_coarse=60, schedule="default",
-                              kind=kind)
+                              kind=kind, drop_tol=drop)
     ctx = context_for(lib, prob)
     _assemble(ctx, v0, 0.4)
     info0 = ctx.amg_setup(gprm)
@@ -64,7 +66,8 @@ def test_resetup_matches_oracle(lib, smoother, precision, kind):
         assert np.array_equal(P.data, Pk.data), f"P changed on level {l}"
         A = export_level_matrix(ctx, l, 0)
         Ac = export_level_matrix(ctx, l + 1, 0)
-        Aco = amg.galerkin(A, P)
+        # the Galerkin product on the set-up's (sparsified) pattern
+        Aco = amg.on_pattern(amg.galerkin(A, P), H0.levels[l + 1].A)
         assert np.array_equal(Ac.indptr, Aco.indptr) and np.array_equal(Ac.indices, Aco.indices)
         assert np.abs(Ac.data - Aco.data).max() <= 1e-12 * np.abs(Aco.data).max(), f"RAP level {l}"
         Ae = Ho.levels[l + 1].A
@@ -211,6 +214,7 @@ def test_resetup_keeps_learned_interpolation(lib):
     info0 = ctx.amg_setup(prm_l)
     assert info0.learned_used == 1
     P0 = export_level_matrix(ctx, 0, 1)
+    Ac0 = export_level_matrix(ctx, 1, 0)
     assert (P0 != P_classical).nnz > 0
     _assemble(ctx, v1, 0.8)
     info1 = ctx.amg_resetup(prm_l)
@@ -220,6 +224,6 @@ def test_resetup_keeps_learned_interpolation(lib):
     assert np.array_equal(P1.data, P0.data)
     A = export_level_matrix(ctx, 0, 0)
     Ac = export_level_matrix(ctx, 1, 0)
-    Aco = amg.galerkin(A, P1)
+    Aco = amg.on_pattern(amg.galerkin(A, P1), Ac0)
     assert np.array_equal(Ac.indptr, Aco.indptr) and np.array_equal(Ac.indices, Aco.indices)
     assert np.abs(Ac.data - Aco.data).max() <= 1e-12 * np.abs(Aco.data).max()

@@ -284,7 +284,7 @@ def test_resetup_coarse_correction_is_an_energy_projection():
     leaves an error B-orthogonal to the kept interpolation's range, and the
     reused hierarchy still preconditions B well."""
     A, B = _reuse_problem()
-    prm = amg.AmgParams(max_coarse=400, max_levels=2)
+    prm = amg.AmgParams(max_coarse=400, max_levels=2, drop_tol=0.0)
     H = amg.setup(A, np.zeros(720, np.int64), prm)
     HB = amg.resetup(B, H, prm)
     assert len(HB.levels) == 2

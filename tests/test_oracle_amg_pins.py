@@ -18,6 +18,10 @@ hand-worked case rather than against the oracle itself.
   with positive off-diagonal couplings and negative diagonals (the sign
   rules: sgn(a_ii) in the strength test, abar_kl = a_kl only where its sign
   differs from a_kk's); negating the matrix changes neither S nor P.
+* Coarse-operator sparsification on a hand-worked matrix (the symmetric
+  threshold eps sqrt(|a_ii a_jj|), explicit zeros dropped, diagonal kept),
+  and a sparsified hierarchy: coarse values equal the Galerkin product at the
+  kept positions, a re-set-up keeps the set-up's pattern.
 """
 import math
 
@@ -59,7 +63,9 @@ def test_chebyshev_equioscillates_at_degree(k):
 
 
 def _zero_smoothing(**kw):
-    return amg.AmgParams(smoother="l1jacobi", nu_pre=0, nu_post=0, nu_pre_coarse=0, nu_post_coarse=0, **kw)
+    """No smoothing and the exact Galerkin coarse operators."""
+    return amg.AmgParams(smoother="l1jacobi", nu_pre=0, nu_post=0, nu_pre_coarse=0, nu_post_coarse=0,
+                         drop_tol=0.0, **kw)
 
 
 @pytest.mark.parametrize("levels", [2, 3])
@@ -190,3 +196,63 @@ def test_negated_operator_gives_the_same_hierarchy():
             assert np.array_equal(L1.state, L2.state)
             assert (L1.P != L2.P).nnz == 0
             assert np.abs((L1.A + L2.A).data).max(initial=0.0) == 0.0
+
+
+def test_drop_small_by_hand():
+    """eps = 1e-3 on a hand-made symmetric matrix with diagonal (4, 1, 9, 0.25):
+    threshold of (i, j) = 1e-3 sqrt(a_ii a_jj):
+      (0,1): 2e-3,  |0.0015| < 2e-3  -> dropped (both sides of the pair);
+      (0,2): 6e-3,  |-1|             -> kept;
+      (1,2): 3e-3,  |0.0031|         -> kept;
+      (2,3): 1.5e-3, |-0.0014|       -> dropped;
+      (1,3): 5e-4,  |0.0006|         -> kept (a row-scaled test by a_11 = 1
+             would drop it, one scaled by a_33 would keep (3,1) too);
+      (0,3): explicit zero           -> dropped.
+    The diagonal always stays; eps = 0 changes nothing."""
+    A = np.array([[4.0, 0.0015, -1.0, 0.0],
+                  [0.0015, 1.0, 0.0031, 0.0006],
+                  [-1.0, 0.0031, 9.0, -0.0014],
+                  [0.0, 0.0006, -0.0014, 0.25]])
+    # every position stored, the zeros of (0,3) and (3,0) explicitly
+    rows = [0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 2, 2, 3, 3, 3, 3]
+    cols = [0, 1, 2, 3] * 4
+    M = sp.csr_matrix((A[rows, cols], (rows, cols)), shape=(4, 4))
+    M.sort_indices()
+    assert M.nnz == 16
+    D = amg.drop_small(M, 1e-3)
+    keep = {(0, 0), (0, 2), (1, 1), (1, 2), (1, 3), (2, 0), (2, 1), (2, 2), (3, 1), (3, 3)}
+    got = set(zip(np.repeat(np.arange(4), np.diff(D.indptr)).tolist(), D.indices.tolist()))
+    assert got == keep
+    assert np.array_equal(D.toarray(), np.where([[(i, j) in keep for j in range(4)] for i in range(4)], A, 0.0))
+    assert amg.drop_small(M, 0.0) is M
+
+
+def test_sparsified_hierarchy_and_its_resetup():
+    """With drop_tol > 0 every coarse operator is the Galerkin product minus
+    the small entries (values equal at the kept positions), symmetric for a
+    symmetric A; a re-set-up with a new operator keeps the set-up's pattern
+    and takes the new Galerkin values there."""
+    r = np.random.default_rng(5)
+    A = _lap3(8).tolil()
+    for _ in range(60):
+        i, j = r.integers(0, A.shape[0], 2)
+        if i != j and A[i, j] == 0:
+            A[i, j] = A[j, i] = -1e-4 * r.uniform(0.5, 1.5)
+    A = A.tocsr()
+    A.sort_indices()
+    prm = amg.AmgParams(max_coarse=30, drop_tol=2e-3)
+    H = amg.setup(A, np.zeros(A.shape[0], np.int64), prm)
+    H0 = amg.setup(A, np.zeros(A.shape[0], np.int64), amg.AmgParams(max_coarse=30, drop_tol=0.0))
+    assert len(H.levels) >= 3
+    assert np.array_equal(H.levels[0].state, H0.levels[0].state)
+    G = amg.galerkin(H.levels[0].A, H.levels[0].P)
+    Ac = H.levels[1].A
+    assert Ac.nnz < G.nnz
+    assert np.abs(amg.on_pattern(G, Ac).toarray() - Ac.toarray()).max() == 0.0
+    assert np.abs((Ac - Ac.T).toarray()).max() <= 1e-14 * np.abs(Ac.data).max()
+    B = (A * 1.5).tocsr()
+    HB = amg.resetup(B, H, prm)
+    for a, b in zip(H.levels, HB.levels):
+        assert np.array_equal(a.A.indptr, b.A.indptr) and np.array_equal(a.A.indices, b.A.indices)
+    GB = amg.galerkin(HB.levels[0].A, H.levels[0].P)
+    assert np.abs(amg.on_pattern(GB, Ac).toarray() - HB.levels[1].A.toarray()).max() <= 1e-13 * np.abs(GB.data).max()
