@@ -399,6 +399,18 @@ hfsi_status hfsi_export_tangent(hfsi_ctx* ctx, int32_t* block_ptr, int32_t* bloc
 /* ||dv||_M for a device vector dv [N]. */
 hfsi_status hfsi_mass_norm(hfsi_ctx* ctx, const double* dv, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * ||dv||_M as hfsi_mass_norm, written to the device scalar `out` (fp64, [1],
+ * caller-owned) with neither an allocation nor a host wait.  The block
+ * partial sums live in a fixed file-scope device array of 256 doubles (2 KiB
+ * per GPU, held until the process ends, independent of the mesh size, so no
+ * input exceeds it); every call on one GPU shares that array, and calls that
+ * overlap on one GPU (several streams or threads at once) race on it.  The
+ * result is ready when the context's stream reaches the call.  HFSI_E_ORDER
+ * before hfsi_set_mesh, HFSI_E_ARG for a null pointer. */
+hfsi_status hfsi_mass_norm_noalloc(hfsi_ctx* ctx, const double* dv, double* out);
+
 /* ------------------------------------------------ learned interpolation */
 
 /* The learned level-0 interpolation (no counterpart in the paper, whose AMG

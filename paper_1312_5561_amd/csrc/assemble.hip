@@ -22,6 +22,8 @@
 // (Mooney-Rivlin) and eq. arpkt/arpktmix (artery; the fibre stress carries
 // the 2 k1 factor of S = 2 dPsi/dC, fibres act only while J_i > 1).
 #include <cmath>
+#include <mutex>
+#include <string>
 
 #include "common.hpp"
 
@@ -422,6 +424,20 @@ __global__ void k_extract_b2(int nb, const double* __restrict__ Kval, double* __
   b2[t] = Kval[16 * (size_t)q + 12 + c];
 }
 
+// ||dv||_M from the partials of k_massnorm: one block of kNoallocParts
+// threads folds them in the order k_sum_partial + k_sum_final fold the same
+// values (slot t to thread t, then the halving tree) and writes the root
+__global__ void __launch_bounds__(256) k_massnorm_final(const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[256];
+  sh[threadIdx.x] = part[threadIdx.x];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sqrt(sh[0] > 0.0 ? sh[0] : 0.0);
+}
+
 // mass norm partials: sum over blocks (i,j) of M_ij sum_c dv_ic dv_jc
 __global__ void k_massnorm(int nb, const int* __restrict__ brow, const int* __restrict__ bcol,
                            const double* __restrict__ M, const double* __restrict__ dv, double* __restrict__ part) {
@@ -539,6 +555,38 @@ void assemble_kernels_only(hfsi_ctx* c) {
   }
 }
 
+// ------------------------------------------- allocation-free mass norm
+// The block partial sums of k_massnorm for hfsi_mass_norm_noalloc live in a
+// file-scope device array: one copy per GPU, held until the process ends,
+// shared by every call on that GPU (calls that overlap on one GPU race on
+// it).  k_massnorm writes every slot before the final kernel reads it, so
+// nothing needs clearing between calls.  Host code uses the address that
+// hipGetSymbolAddress returns for the device, never the array's name.
+constexpr int kNoallocParts = 256;
+static __device__ __align__(256) double scratch[kNoallocParts];
+
+constexpr int kMaxDevices = 64;
+static double* g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// Resolve the scratch address of `device` (current device at the call).
+void noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) fail(HFSI_E_ARG, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) fail(HFSI_E_HIP, std::string("scratch address: ") + hipGetErrorString(e));
+  g_scratch_ptr[device] = static_cast<double*>(p);
+}
+
+static double* noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  double* p = device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
+  if (!p) fail(HFSI_E_ORDER, "mass_norm_noalloc: scratch of this device not resolved (hfsi_create)");
+  return p;
+}
+
 double mass_norm(hfsi_ctx* c, const double* dv) {
   const int nb = 256;
   c->kred.ensure(2 * nb);
@@ -581,6 +629,20 @@ extern "C" hfsi_status hfsi_mass_norm(hfsi_ctx* c, const double* dv, double* out
   require_stage(c, 1, "mass_norm");
   if (!dv || !out) fail(HFSI_E_ARG, "mass_norm: null pointer");
   *out = hfsi::mass_norm(c, dv);
+  HFSI_ABI_END(c)
+}
+
+extern "C" hfsi_status hfsi_mass_norm_noalloc(hfsi_ctx* c, const double* dv, double* out) {
+  HFSI_ABI_BEGIN(c)
+  require_stage(c, 1, "mass_norm_noalloc");
+  if (!dv || !out) fail(HFSI_E_ARG, "mass_norm_noalloc: null pointer");
+  static_assert(kNoallocParts == 256, "k_massnorm_final folds 256 partials with 256 threads");
+  double* part = noalloc_scratch(c->device);
+  // the grid is the partial count: never more slots than the scratch holds
+  k_massnorm<<<kNoallocParts, 256, 0, c->stream>>>(c->nb, c->brow.p, c->ncol.p, c->Mval.p, dv, part);
+  HIP_LAUNCH_CHECK();
+  k_massnorm_final<<<1, kNoallocParts, 0, c->stream>>>(part, out);
+  HIP_LAUNCH_CHECK();
   HFSI_ABI_END(c)
 }
 

@@ -322,6 +322,9 @@ void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_para
 void bicgstab_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_params& prm, hfsi_solve_info* info);
 void krylov_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_params& prm, hfsi_solve_info* info);
 double mass_norm(hfsi_ctx* c, const double* dv);
+// resolve the allocation-free entry point's scratch address on `device`
+// (the current device); called once per context creation
+void noalloc_scratch_init(int device);
 // learned interpolation: correct level-0 P in place; free the state
 void learned_correction(hfsi_ctx* c, Level& L);
 void mlp_free(hfsi_ctx* c);

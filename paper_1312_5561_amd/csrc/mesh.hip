@@ -270,6 +270,13 @@ extern "C" hfsi_status hfsi_create(hfsi_ctx** out, int device, void* stream) {
     delete c;
     return HFSI_E_HIP;
   }
+  try {
+    hfsi::noalloc_scratch_init(device);
+  } catch (const hfsi::Error&) {
+    release_events(c);
+    delete c;
+    return HFSI_E_HIP;
+  }
   *out = c;
   ++g_live_contexts;
   return HFSI_OK;

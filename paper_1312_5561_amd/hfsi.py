@@ -175,6 +175,7 @@ def load():
         "hfsi_apply_preconditioner": [vp, vp, vp],
         "hfsi_apply_tangent": [vp, vp, vp],
         "hfsi_mass_norm": [vp, vp, C.POINTER(dbl)],
+        "hfsi_mass_norm_noalloc": [vp, vp, vp],
         "hfsi_export_tangent": [vp, vp, vp, vp, vp, vp, vp, vp],
         "hfsi_time_kernel": [vp, i32, i32, i64, C.POINTER(dbl), C.POINTER(dbl)],
         "hfsi_mlp_set_weights": [vp, vp],
@@ -386,6 +387,11 @@ class Context:
         out = C.c_double()
         self._check(self.lib.hfsi_mass_norm(self.h, _ptr(dv), C.byref(out)))
         return out.value
+
+    def mass_norm_noalloc(self, dv, out):
+        """||dv||_M written to the device scalar `out` (a one-element fp64
+        tensor) without allocating or synchronising."""
+        self._check(self.lib.hfsi_mass_norm_noalloc(self.h, _ptr(dv), _ptr(out)))
 
     # ---- learned interpolation
     def mlp_set_weights(self, w):
