@@ -225,6 +225,14 @@ typedef struct {
                                eps1_max for the first iteration             */
   double eps1_max;          /* default 1e-2                                 */
   double eps1_min;          /* default 1e-12                                */
+  int32_t line_search;      /* 1: damped Newton: v += a dv with the largest
+                               a in {1, 1/2, ..., 1/1024} for which every
+                               element keeps J > 0 and the residual decreases,
+                               ||R(v + a dv)||_2 <= (1 - 1e-4 a) ||R(v)||_2;
+                               the stopping rule needs a full step (a = 1);
+                               no admissible a ends the call with
+                               HFSI_NOT_CONVERGED and v at the last accepted
+                               state.  0: full steps (default)              */
 } hfsi_newton_solve_params;
 
 typedef struct {
@@ -236,6 +244,8 @@ typedef struct {
   double eps1[32];            /* their inner tolerances                     */
   int32_t krylov[32];         /* their Krylov iterations                    */
   double seconds;             /* wall time of the call                      */
+  double step_length[32];     /* their step lengths a (1 without damping; 0:
+                                 no admissible step, the call failed there) */
 } hfsi_newton_solve_info;
 
 /* ---------------------------------------------------------------- context */

@@ -273,6 +273,7 @@ struct hfsi_ctx {
   hfsi::DevBuf<double> kz;       // Z [m * N]
   hfsi::DevBuf<double> kw, kr, ktmp, kdv;
   hfsi::DevBuf<double> kvprev;  // state at the start of a time step
+  hfsi::DevBuf<double> ktrial, ktres;  // damped Newton: trial state and its residual
   hfsi::DevBuf<double> kred;     // reduction partials
   hfsi::DevBuf<double> kh;       // Hessenberg / Givens state on device
   double* pinned = nullptr;      // host-pinned scalars

@@ -1422,6 +1422,13 @@ extern "C" hfsi_status hfsi_krylov_amg_solve(hfsi_ctx* c, const double* b, doubl
 }
 
 namespace {
+// y = x + a d
+__global__ void k_trial(long N, double a, const double* __restrict__ x, const double* __restrict__ d,
+                        double* __restrict__ y) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e < N) y[e] = x[e] + a * d[e];
+}
+
 __global__ void k_negate(long N, const double* __restrict__ x, double* __restrict__ y) {
   long i = (long)blockIdx.x * 256 + threadIdx.x;
   if (i < N) y[i] = -x[i];
@@ -1617,12 +1624,21 @@ void check_newton_params(const hfsi_newton_params* prm) {
   check_solve_params(&prm->solve);
 }
 
+// Damped Newton: the constants of the backtracking (Armijo factor on the
+// residual norm and the smallest step length tried)
+constexpr double kArmijo = 1e-4;
+constexpr double kAlphaMin = 1.0 / 1024.0;
+
 // One Newton iteration (Section "Newton's Method"): assemble R and K at v,
 // set up the hierarchy (or re-set it up on the kept coarse grids when
 // `reuse` and one is available), solve K dv = -R to sp.tol, v += dv.
-// Returns whether the linear solve converged.
+// With `alpha` (damped Newton) the update is v += a dv with the largest a in
+// {1, 1/2, ..., 1/1024} for which every element keeps J > 0 and
+// ||R(v + a dv)||_2 <= (1 - 1e-4 a) ||R(v)||_2 (the context's tangent is then
+// the one of the accepted state); *alpha receives a, or 0 (v unchanged) when
+// no step length qualifies.  Returns whether the linear solve converged.
 bool newton_iteration(hfsi_ctx* c, double* v, double load, const hfsi_amg_params& amg, const hfsi_solve_params& sp,
-                      bool reuse, hfsi_newton_info* info) {
+                      bool reuse, hfsi_newton_info* info, double* alpha = nullptr) {
   const long N = 4L * c->n;
   hipStream_t s = c->stream;
   c->kdv.ensure(N);
@@ -1647,8 +1663,36 @@ bool newton_iteration(hfsi_ctx* c, double* v, double load, const hfsi_amg_params
   HIP_CHECK(hipMemsetAsync(c->kdv.p, 0, sizeof(double) * N, s));
   hfsi_solve_info si{sizeof(hfsi_solve_info)};
   hfsi::krylov_solve(c, c->ktmp.p, c->kdv.p, sp, &si);
-  k_axpy<<<div_up(N, 256), 256, 0, s>>>(N, 1.0, c->kdv.p, v);
-  HIP_LAUNCH_CHECK();
+  if (alpha) {
+    c->ktrial.ensure(N);
+    c->ktres.ensure(N);
+    double a = 1.0;
+    bool ok = false;
+    for (; a >= kAlphaMin; a *= 0.5) {
+      k_trial<<<div_up(N, 256), 256, 0, s>>>(N, a, v, c->kdv.p, c->ktrial.p);
+      HIP_LAUNCH_CHECK();
+      hfsi_assembly_info ti{sizeof(hfsi_assembly_info)};
+      bool inverted = false;
+      try {
+        hfsi::assemble(c, c->ktrial.p, load, c->ktres.p, &ti);
+      } catch (const hfsi::Error& e) {
+        if (e.code != HFSI_E_INVERTED) throw;
+        inverted = true;
+      }
+      if (inverted) continue;
+      hfsi::norm_dev(c, c->ktres.p, N, c->scal.p + 7);
+      const double rt = hfsi::read_scalar(c, c->scal.p + 7);
+      if (std::isfinite(rt) && rt <= (1.0 - kArmijo * a) * rnorm) {
+        ok = true;
+        break;
+      }
+    }
+    *alpha = ok ? a : 0.0;
+    if (ok) HIP_CHECK(hipMemcpyAsync(v, c->ktrial.p, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  } else {
+    k_axpy<<<div_up(N, 256), 256, 0, s>>>(N, 1.0, c->kdv.p, v);
+    HIP_LAUNCH_CHECK();
+  }
   const double dvm = hfsi::mass_norm(c, c->kdv.p);
   HIP_CHECK(hipEventRecord(ev.e1, s));
   HIP_CHECK(hipEventSynchronize(ev.e1));
@@ -1695,6 +1739,7 @@ extern "C" hfsi_status hfsi_newton_solve(hfsi_ctx* c, double* v, double load, co
   if (!(prm->eps2 > 0.0) || prm->max_newton < 1 || prm->adaptive < 0 || prm->adaptive > 1 ||
       !(prm->eps1_min > 0.0) || !(prm->eps1_max >= prm->eps1_min) || !(prm->eps1_max < 1.0))
     fail(HFSI_E_ARG, "newton solve params: need eps2 > 0, max_newton >= 1, 0 < eps1_min <= eps1_max < 1");
+  if (prm->line_search < 0 || prm->line_search > 1) fail(HFSI_E_ARG, "newton solve params: line_search 0 or 1");
   if (info && info->struct_size != sizeof(hfsi_newton_solve_info))
     fail(HFSI_E_ARG, "newton solve info: struct_size mismatch");
   auto t_start = std::chrono::steady_clock::now();
@@ -1718,7 +1763,8 @@ extern "C" hfsi_status hfsi_newton_solve(hfsi_ctx* c, double* v, double load, co
     // amg_reuse: 1 keeps the first iteration's coarse grids, 2 also those of
     // an earlier call on this mesh (e.g. the previous time step)
     const bool reuse = prm->step.amg_reuse == 2 || (k > 0 && prm->step.amg_reuse == 1);
-    newton_iteration(c, v, load, prm->step.amg, sp, reuse, &ni);
+    double alpha = 1.0;
+    newton_iteration(c, v, load, prm->step.amg, sp, reuse, &ni, prm->line_search ? &alpha : nullptr);
     ++its;
     kry += ni.krylov_iterations;
     if (k == 0) dv0 = ni.dv_mass_norm;
@@ -1727,8 +1773,10 @@ extern "C" hfsi_status hfsi_newton_solve(hfsi_ctx* c, double* v, double load, co
       info->dv_mass_norm[k] = ni.dv_mass_norm;
       info->eps1[k] = sp.tol;
       info->krylov[k] = ni.krylov_iterations;
+      info->step_length[k] = alpha;
     }
-    done = dv0 == 0.0 || ni.dv_mass_norm <= prm->eps2 * dv0;
+    if (alpha == 0.0) break;  // no admissible step length: the increment fails
+    done = (dv0 == 0.0 || ni.dv_mass_norm <= prm->eps2 * dv0) && alpha == 1.0;
   }
   if (info) {
     info->newton_iterations = its;

@@ -71,6 +71,7 @@ static hfsi_newton_solve_params default_params(int adaptive, int learned) {
   p.adaptive = adaptive;
   p.eps1_max = 1e-2;
   p.eps1_min = 1e-12;
+  p.line_search = 0;
   return p;
 }
 

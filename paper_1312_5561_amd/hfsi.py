@@ -85,13 +85,13 @@ class NewtonInfo(C.Structure):
 class NewtonSolveParams(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("step", NewtonParams), ("eps2", C.c_double),
                 ("max_newton", C.c_int32), ("adaptive", C.c_int32), ("eps1_max", C.c_double),
-                ("eps1_min", C.c_double)]
+                ("eps1_min", C.c_double), ("line_search", C.c_int32)]
 
 
 class NewtonSolveInfo(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("newton_iterations", C.c_int32), ("krylov_iterations", C.c_int32),
                 ("converged", C.c_int32), ("dv_mass_norm", C.c_double * 32), ("eps1", C.c_double * 32),
-                ("krylov", C.c_int32 * 32), ("seconds", C.c_double)]
+                ("krylov", C.c_int32 * 32), ("seconds", C.c_double), ("step_length", C.c_double * 32)]
 
 
 class TrainParams(C.Structure):
@@ -135,10 +135,12 @@ def newton_params(amg=None, solve=None, amg_reuse=0):
     return NewtonParams(C.sizeof(NewtonParams), amg or amg_params(), solve or solve_params(), amg_reuse)
 
 
-def newton_solve_params(step=None, eps2=1e-10, max_newton=25, adaptive=0, eps1_max=1e-2, eps1_min=1e-12):
-    """adaptive=1: inner tolerance eps_1,k = (||dv_k-1||_M / ||dv_0||_M)^2."""
+def newton_solve_params(step=None, eps2=1e-10, max_newton=25, adaptive=0, eps1_max=1e-2, eps1_min=1e-12,
+                        line_search=0):
+    """adaptive=1: inner tolerance eps_1,k = (||dv_k-1||_M / ||dv_0||_M)^2;
+    line_search=1: damped Newton (backtracking on ||R||_2)."""
     return NewtonSolveParams(C.sizeof(NewtonSolveParams), step or newton_params(), eps2, max_newton, adaptive,
-                             eps1_max, eps1_min)
+                             eps1_max, eps1_min, line_search)
 
 
 _lib = None

@@ -67,3 +67,43 @@ def test_newton_solve_errors(lib):
     assert e.value.code == -1
     info, code = ctx.newton_solve(v, 1.0, lib.newton_solve_params(max_newton=1))
     assert code == 1 and not info.converged and info.newton_iterations == 1
+
+
+def test_damped_newton_tube_ramp_matches_oracle(lib):
+    """The artery tube 8 x 2 x 8 under its full internal pressure in 10
+    increments (full steps leave the admissible states in the first
+    increment): damped Newton (line_search = 1) on the GPU takes the oracle's
+    step lengths and reaches its states to 1e-9 in every increment."""
+    import torch
+    prob = synth.tube_problem(n_theta=8, n_media=1, n_adv=1, n_z=8)
+    print("[damped newton] tube 8x2x8, 10 increments", flush=True)
+    ctx = lib.Context(0)
+    ctx.set_problem(prob)
+    v = torch.zeros(prob.n_dofs, dtype=torch.float64, device="cuda")
+    prm = lib.newton_solve_params(line_search=1, max_newton=40)
+    disc = fe.Discretization(prob)
+    vo = np.zeros(prob.n_dofs)
+    prm_o = newton.NewtonParams(line_search=True, max_iter=40)
+    for k in range(1, 11):
+        info, code = ctx.newton_solve(v, k / 10.0, prm)
+        log = []
+        vo, ok, its = newton.solve_increment(disc, vo, k / 10.0, prm_o, log)
+        a_gpu = [info.step_length[q] for q in range(min(info.newton_iterations, 32))]
+        a_orc = [e["alpha"] for e in log]
+        print(f"[damped newton] increment {k}: gpu {info.newton_iterations} its steps {a_gpu}; "
+              f"oracle {its} its steps {a_orc}", flush=True)
+        assert code == 0 and info.converged and ok
+        assert a_gpu == a_orc
+        err = np.linalg.norm(v.cpu().numpy() - vo) / np.linalg.norm(vo)
+        assert err <= 1e-9, (k, err)
+    # without damping the first increment fails (non-finite values or no
+    # convergence)
+    ctx2 = lib.Context(0)
+    ctx2.set_problem(prob)
+    v2 = torch.zeros(prob.n_dofs, dtype=torch.float64, device="cuda")
+    try:
+        info2, code2 = ctx2.newton_solve(v2, 0.1, lib.newton_solve_params(max_newton=40))
+        failed = code2 != 0 or not info2.converged
+    except lib.HfsiError:
+        failed = True
+    assert failed

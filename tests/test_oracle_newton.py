@@ -121,3 +121,68 @@ def test_adaptive_inner_tolerance_keeps_quadratic_convergence():
     ratios = [np.log(dv[k + 1] / dv[0]) / np.log(dv[k] / dv[0]) for k in range(1, len(dv) - 1)
               if dv[k + 1] > 1e-14 * dv[0]]
     assert ratios and min(ratios) > 1.6
+
+
+def _tiny_tube():
+    return synth.tube_problem(n_theta=8, n_media=1, n_adv=1, n_z=8)
+
+
+def test_damped_newton_reaches_the_undamped_equilibrium():
+    """The artery tube under its full internal pressure in 10 increments:
+    plain Newton leaves the admissible states in the first increment (the
+    fibres are off in the first tangent), the damped method converges with
+    alpha < 1 in its first steps, every accepted step meets the Armijo
+    decrease, and its final state is the equilibrium that undamped Newton
+    reaches with 40 increments (same state to 1e-8, residual near zero)."""
+    prob = _tiny_tube()
+    d = fe.Discretization(prob)
+    plain = newton.NewtonParams(eps2=1e-10)
+    v = np.zeros(prob.n_dofs)
+    failed = False
+    with np.errstate(all="ignore"):
+        try:
+            v1, ok, _ = newton.solve_increment(d, v, 0.1, plain)
+            failed = not ok or not _converged(d, v1, 0.1)
+        except np.linalg.LinAlgError:
+            failed = True   # the set-up met non-finite values
+    assert failed
+    damped = newton.NewtonParams(eps2=1e-10, line_search=True)
+    log = []
+    v = np.zeros(prob.n_dofs)
+    for k in range(1, 11):
+        v, ok, _ = newton.solve_increment(d, v, k / 10, damped, log)
+        assert ok, k
+    alphas = [e["alpha"] for e in log]
+    assert min(alphas) < 1.0 and alphas[-1] == 1.0
+    ref = np.zeros(prob.n_dofs)
+    for k in range(1, 41):
+        ref, ok, _ = newton.solve_increment(d, ref, k / 40, plain)
+        assert ok, k
+    assert np.linalg.norm(v - ref) <= 1e-8 * np.linalg.norm(ref)
+    assert newton.residual_norm(d, v, 1.0) <= 1e-9 * newton.residual_norm(d, np.zeros(prob.n_dofs), 1.0)
+
+
+def _converged(d, v, load):
+    r = newton.residual_norm(d, v, load)
+    return np.isfinite(r) and r <= 1e-8 * newton.residual_norm(d, np.zeros_like(v), load)
+
+
+def test_damped_newton_takes_full_steps_where_newton_converges():
+    """On the cube (where full steps already decrease the residual) the damped
+    method takes alpha = 1 every time and repeats the undamped iterates."""
+    prob = synth.cube_problem(3, jitter=0.1, seed=2)
+    d = fe.Discretization(prob)
+    log_a, log_b = [], []
+    va, _, _ = newton.solve_increment(d, np.zeros(prob.n_dofs), 1.0, newton.NewtonParams(), log_a)
+    vb, _, _ = newton.solve_increment(d, np.zeros(prob.n_dofs), 1.0, newton.NewtonParams(line_search=True), log_b)
+    assert all(e["alpha"] == 1.0 for e in log_b)
+    assert np.array_equal(va, vb) and len(log_a) == len(log_b)
+
+
+def test_residual_norm_rejects_inverted_states():
+    prob = synth.cube_problem(2)
+    d = fe.Discretization(prob)
+    v = np.zeros((prob.n_nodes, 4))
+    v[:, 0] = -2.0 * prob.X[:, 0]          # x -> -x: every element inverted
+    assert newton.residual_norm(d, v.ravel(), 0.0) == np.inf
+    assert np.isfinite(newton.residual_norm(d, np.zeros(prob.n_dofs), 1.0))
