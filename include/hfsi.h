@@ -59,8 +59,11 @@ typedef struct hfsi_ctx hfsi_ctx;
  * model 1: two-layer artery layer, neo-Hookean c10/2 (J1-3) plus the
  *          exponential fibre energy k1/(2 k2) sum_{i=4,6} (exp(k2 (J_i-1)^2)-1)
  *          active while J_i > 1, plus kappa/2 (J-1)^2 (eq. areng).
- * theta: the Schur-complement parameter of eq. lpreschur; <= 0 selects the
- *        linear shear modulus mu^l of the stabilisation paragraph. */
+ * theta: the Schur-complement parameter of eq. lpreschur; <= 0 selects
+ *        mu^l / 5, mu^l the linear shear modulus of the stabilisation
+ *        paragraph (the paper takes theta = O(c10), adjusted by tests on a
+ *        coarse mesh and then held fixed; mu^l / 5 needed the fewest Krylov
+ *        iterations on the 16^3 cube). */
 typedef struct {
   size_t struct_size; /* = sizeof(hfsi_material)                      */
   int32_t model;
@@ -106,8 +109,11 @@ typedef struct {
  * weights and lattice coordinates), judged by the convergence factor rho of
  * its V-cycle (10 stationary cycles from the SplitMix64 vector of seed 777):
  * the learned rows are kept only if rho <= fallback_rho and, with
- * judge_classical > 0, rho <= the factor of the classical hierarchy on the
- * same tangent; otherwise the classical hierarchy is built (the fallback). */
+ * judge_classical > 0, the learned hierarchy solves at least as fast as the
+ * classical one on the same tangent: on a hierarchy of the assembled tangent
+ * the FGMRES rates of hfsi_amg_info.krylov_rho are compared, on one of a
+ * caller matrix (hfsi_amg_setup_csr) the V-cycle factors; otherwise the
+ * classical hierarchy is built (the fallback). */
 typedef struct {
   size_t struct_size;
   double strength_theta; /* default 0.15                                   */
@@ -159,9 +165,14 @@ typedef struct {
   double rho;            /* convergence factor measured by the judge (or -1) */
   int32_t learned_used;  /* 1 if the learned level-0 interpolation is kept */
   int32_t pmis_rounds;   /* PMIS rounds summed over levels                 */
-  double rho_classical;  /* the classical hierarchy's factor the judge
-                            compared with (measured now or kept from the
-                            first set-up), -1 if none                      */
+  double rho_classical;  /* the classical hierarchy's V-cycle factor (the
+                            judge's comparison, measured now or kept from
+                            the first set-up), -1 if none                  */
+  double krylov_rho;     /* judge on an assembled tangent: the learned
+                            hierarchy's FGMRES rate (||r_20||/||r_0||)^(1/20)
+                            on K x = b (b a SplitMix64 vector of seed 777,
+                            fixed dofs zeroed), -1 if not measured         */
+  double krylov_rho_classical; /* the same with the classical hierarchy    */
 } hfsi_amg_info;
 
 typedef struct {
@@ -229,7 +240,9 @@ typedef struct {
                                a in {1, 1/2, ..., 1/1024} for which every
                                element keeps J > 0 and the residual decreases,
                                ||R(v + a dv)||_2 <= (1 - 1e-4 a) ||R(v)||_2;
-                               the stopping rule needs a full step (a = 1);
+                               the stopping rule needs a full step (a = 1),
+                               and a correction that already meets it is
+                               taken whole without a search;
                                no admissible a ends the call with
                                HFSI_NOT_CONVERGED and v at the last accepted
                                state.  0: full steps (default)              */

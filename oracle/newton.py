@@ -18,8 +18,9 @@ update is v + alpha dv with the largest alpha in {1, 1/2, 1/4, ...,
 alpha_min} for which every element keeps J > 0 and the Dirichlet-eliminated
 residual decreases by the Armijo factor, ||R(v + alpha dv)||_2 <=
 (1 - c alpha) ||R(v)||_2; the stopping rule stays eq. newstop on the full
-Newton corrections dv_k, met only by a full step (alpha = 1).  When no
-alpha qualifies the increment fails.
+Newton corrections dv_k, met only by a full step (alpha = 1); a correction
+that already meets it is taken whole without a search (the residual is then
+at its rounding floor).  When no alpha qualifies the increment fails.
 """
 from __future__ import annotations
 
@@ -112,7 +113,11 @@ def solve_increment(disc, v, load, prm: NewtonParams, log=None):
         dv, info, r0 = newton_direction(disc, v, load, prm, tol)
         nrm = disc.mass_norm(dv)
         alpha = 1.0
-        if prm.line_search:
+        # a correction that already meets the stopping rule is taken whole
+        # (near the solution the residual sits at its rounding floor and
+        # cannot show the Armijo decrease)
+        small = n0 is not None and nrm <= prm.eps2 * n0
+        if prm.line_search and not small:
             alpha = damped_step(disc, v, dv, load, r0, prm)
             if alpha is None:
                 return v, False, k + 1

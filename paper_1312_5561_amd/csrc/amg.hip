@@ -1957,6 +1957,8 @@ void fill_info(const Hierarchy& H, hfsi_amg_info* info, int rounds, double rho) 
   info->pmis_rounds = rounds;
   info->rho = rho;
   info->rho_classical = -1.0;
+  info->krylov_rho = -1.0;
+  info->krylov_rho_classical = -1.0;
   info->learned_used = H.learned;
 }
 
@@ -2107,12 +2109,18 @@ void build_levels(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) 
 // The hierarchy with the judge of the learned interpolation: the learned
 // level-0 rows are kept only if the convergence factor rho of the V-cycle
 // (10 stationary cycles from the SplitMix64 vector of seed 777) is at most
-// fallback_rho and, with judge_classical > 0, at most the factor of the
-// classical hierarchy on the same tangent; otherwise the classical hierarchy
-// is built.  judge_classical = 2 compares on the first set-up of a mesh,
-// boundary set, material table, weight set and parameter set and keeps the
-// verdict for the later set-ups (the learned rows follow the local stencils,
-// which the tangents of one problem share); 1 compares on every set-up.
+// fallback_rho and, with judge_classical > 0, the learned hierarchy solves
+// at least as fast as the classical one: on a hierarchy of the assembled
+// tangent the rate (||r_k|| / ||r_0||)^(1/k) of kJudgeSteps FGMRES steps on
+// K x = b with P_L (b the SplitMix64 vector of seed 777, fixed dofs zeroed)
+// is compared, on one of a caller matrix the V-cycle factors; otherwise the
+// classical hierarchy is built.  judge_classical = 2 compares on the first
+// set-up of a mesh, boundary set, material table, weight set and parameter
+// set and keeps the verdict for the later set-ups (the learned rows follow
+// the local stencils, which the tangents of one problem share); 1 compares
+// on every set-up.
+constexpr int kJudgeSteps = 20;
+
 void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {
   Hierarchy& H = c->H;
   if (prm.interp != 1) {
@@ -2122,26 +2130,38 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
   hfsi_amg_params cl = prm;
   cl.interp = 0;
   auto& J = c->judge;
+  const bool tangent = H.L[0].bptr != nullptr && c->stage >= 4;
   const bool cached = prm.judge_classical == 2 && J.valid && std::memcmp(&J.prm, &prm, sizeof(prm)) == 0;
+  auto report = [&](double rho, double rho_c, double kl, double kc, bool keep) {
+    if (!info) return;
+    info->rho = rho;
+    info->rho_classical = rho_c;
+    info->krylov_rho = kl;
+    info->krylov_rho_classical = kc;
+    info->learned_used = keep ? 1 : 0;
+  };
   if (cached && !J.learned_wins) {
     H.L.resize(1);
     build_levels(c, cl, info);
-    if (info) {
-      info->rho = J.rho_learned;
-      info->rho_classical = J.rho_classical;
-      info->learned_used = 0;
-    }
+    report(J.rho_learned, J.rho_classical, J.krylov_learned, J.krylov_classical, false);
     return;
   }
   build_levels(c, prm, info);
   const double rho = convergence_factor(c, 10, 777);
   double rho_c = cached ? J.rho_classical : -1.0;
+  double kl = cached ? J.krylov_learned : -1.0, kc = cached ? J.krylov_classical : -1.0;
   bool keep = rho <= prm.fallback_rho;  // false for NaN
   if (keep && prm.judge_classical > 0 && !cached) {
+    if (tangent) kl = krylov_factor(c, kJudgeSteps, 777);
     H.L.resize(1);
     build_levels(c, cl, info);
     rho_c = convergence_factor(c, 10, 777);
-    keep = rho <= rho_c;
+    if (tangent) {
+      kc = krylov_factor(c, kJudgeSteps, 777);
+      keep = kl <= kc;
+    } else {
+      keep = rho <= rho_c;
+    }
     if (keep) {
       H.L.resize(1);
       build_levels(c, prm, info);
@@ -2152,16 +2172,14 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
       J.learned_wins = keep;
       J.rho_learned = rho;
       J.rho_classical = rho_c;
+      J.krylov_learned = kl;
+      J.krylov_classical = kc;
     }
   } else if (!keep) {
     H.L.resize(1);
     build_levels(c, cl, info);
   }
-  if (info) {
-    info->rho = rho;
-    info->rho_classical = rho_c;
-    info->learned_used = keep ? 1 : 0;
-  }
+  report(rho, rho_c, kl, kc, keep);
 }
 
 void amg_setup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {

@@ -266,6 +266,7 @@ struct hfsi_ctx {
     bool valid = false;
     bool learned_wins = false;
     double rho_learned = -1.0, rho_classical = -1.0;
+    double krylov_learned = -1.0, krylov_classical = -1.0;
     hfsi_amg_params prm{};
   } judge;
   // Krylov workspace
@@ -332,6 +333,9 @@ void mlp_free(hfsi_ctx* c);
 // rho = (||e_k||_A / ||e_0||_A)^{1/k} of k stationary V-cycles from a
 // SplitMix64 start vector
 double convergence_factor(hfsi_ctx* c, int cycles, uint64_t seed);
+// (||r_k|| / ||r_0||)^(1/k) of k FGMRES steps on the assembled tangent with
+// P_L on the current hierarchy, from a SplitMix64 right-hand side
+double krylov_factor(hfsi_ctx* c, int k, uint64_t seed);
 // minimum bytes one assembly must move; the element kernels alone (timing)
 double assembly_bytes(hfsi_ctx* c);
 void assemble_kernels_only(hfsi_ctx* c);

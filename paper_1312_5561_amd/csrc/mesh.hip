@@ -227,7 +227,7 @@ void colour_elements(int n, int m, const int32_t* tets, std::vector<int>& perm, 
 
 // ================================================================== ABI
 
-extern "C" int32_t hfsi_abi_version(void) { return 4; }
+extern "C" int32_t hfsi_abi_version(void) { return 5; }
 
 namespace {
 std::atomic<int> g_live_contexts{0};  // the device block cache is trimmed when none is left
@@ -421,7 +421,10 @@ extern "C" hfsi_status hfsi_set_materials(hfsi_ctx* c, int32_t n_mat, const hfsi
     double mu = q.model == 1 ? 2.0 * (q.c10 + (q.k2 > 0 ? q.k1 / (2.0 * q.k2) : 0.0)) : 2.0 * (q.c10 + q.c01);
     double* r = &c->mtab_h[8 * k];
     r[0] = q.model; r[1] = q.c10; r[2] = q.model == 0 ? q.c01 : 0.0; r[3] = q.kappa;
-    r[4] = q.k1; r[5] = q.k2; r[6] = mu; r[7] = q.theta > 0 ? q.theta : mu;
+    // Schur parameter of eq. lpreschur: theta = O(c10), adjusted on a coarse
+    // mesh and then kept (the fewest Krylov iterations on the 16^3 cube at
+    // mu^l / 5); a positive theta in the record overrides it
+    r[4] = q.k1; r[5] = q.k2; r[6] = mu; r[7] = q.theta > 0 ? q.theta : 0.2 * mu;
   }
   for (int k = 0; k < n_mat; ++k)
     if (c->mtab_h[8 * k] == 1 && !c->has_fib) fail(HFSI_E_ARG, "set_materials: artery model needs fibre directions");

@@ -97,17 +97,27 @@ k_csr4(int n, const int* __restrict__ p4, const int* __restrict__ base, const vo
   const int hi = p4[gid + 1];
   const T* xr = WIDE ? x : x + base[gid];
   const V4* v4 = reinterpret_cast<const V4*>(val);
-  T s = 0;
-  for (int k = p4[gid] + lane; k < hi; k += G) {
+  // two chunks per trip (k and k + G) so that a lane has both chunks' loads
+  // and gathers in flight at once; the second is a zero chunk at column
+  // offset 0 (an element of the row) past the row's end
+  T s = 0, s2 = 0;
+  for (int k = p4[gid] + lane; k < hi; k += 2 * G) {
+    const bool two = k + G < hi;
     const V4 a = v4[k];
+    const V4 b = two ? v4[k + G] : V4{};
     if (WIDE) {
       const int4 j = reinterpret_cast<const int4*>(cols)[k];
+      const int4 q = two ? reinterpret_cast<const int4*>(cols)[k + G] : make_int4(j.x, j.x, j.x, j.x);
       s += a.x * xr[j.x] + a.y * xr[j.y] + a.z * xr[j.z] + a.w * xr[j.w];
+      s2 += b.x * xr[q.x] + b.y * xr[q.y] + b.z * xr[q.z] + b.w * xr[q.w];
     } else {
       const ushort4 j = reinterpret_cast<const ushort4*>(cols)[k];
+      const ushort4 q = two ? reinterpret_cast<const ushort4*>(cols)[k + G] : make_ushort4(0, 0, 0, 0);
       s += a.x * xr[j.x] + a.y * xr[j.y] + a.z * xr[j.z] + a.w * xr[j.w];
+      s2 += b.x * xr[q.x] + b.y * xr[q.y] + b.z * xr[q.z] + b.w * xr[q.w];
     }
   }
+  s += s2;
 #pragma unroll
   for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
   if (lane != 0) return;
@@ -1343,6 +1353,35 @@ __global__ void k_dot_part(int n, const double* __restrict__ x, const double* __
 }  // namespace
 
 namespace hfsi {
+// the judge's right-hand side: SplitMix64 values (stream 0) with the fixed
+// dofs set to zero
+__global__ void k_mask_fixed(long N, const uint8_t* __restrict__ dir, double* __restrict__ b) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e < N && dir[e]) b[e] = 0.0;
+}
+
+// Residual reduction rate (||r_k|| / ||r_0||)^(1/k) of k FGMRES steps (no
+// restart, x_0 = 0) on K x = b with P_L built on the current hierarchy, b the
+// SplitMix64 vector of `seed` (stream 0, values in [-1, 1)) with the fixed
+// dofs zeroed; k is the steps taken (fewer after a lucky breakdown).
+double krylov_factor(hfsi_ctx* c, int k, uint64_t seed) {
+  if (!c->H.ready) fail(HFSI_E_ORDER, "krylov factor: no hierarchy");
+  const long N = 4L * c->n;
+  hipStream_t s = c->stream;
+  DevBuf<double> b, x;
+  b.ensure(N);
+  x.ensure(N);
+  k_uniform_pm1<<<div_up(N, 256), 256, 0, s>>>((int)N, seed, b.p);
+  HIP_LAUNCH_CHECK();
+  k_mask_fixed<<<div_up(N, 256), 256, 0, s>>>(N, c->dir.p, b.p);
+  HIP_LAUNCH_CHECK();
+  HIP_CHECK(hipMemsetAsync(x.p, 0, sizeof(double) * N, s));
+  hfsi_solve_params sp{sizeof(hfsi_solve_params), 1e-300, k, k, 0};
+  hfsi_solve_info si{sizeof(hfsi_solve_info)};
+  fgmres_solve(c, b.p, x.p, sp, &si);
+  return std::pow(si.rel_residual, 1.0 / std::max(si.iterations, 1));
+}
+
 double convergence_factor(hfsi_ctx* c, int cycles, uint64_t seed) {
   Hierarchy& H = c->H;
   if (!H.ready) fail(HFSI_E_ORDER, "convergence factor: no hierarchy");
@@ -1635,10 +1674,11 @@ constexpr double kAlphaMin = 1.0 / 1024.0;
 // With `alpha` (damped Newton) the update is v += a dv with the largest a in
 // {1, 1/2, ..., 1/1024} for which every element keeps J > 0 and
 // ||R(v + a dv)||_2 <= (1 - 1e-4 a) ||R(v)||_2 (the context's tangent is then
-// the one of the accepted state); *alpha receives a, or 0 (v unchanged) when
-// no step length qualifies.  Returns whether the linear solve converged.
+// the one of the accepted state), unless ||dv||_M <= full_below; *alpha
+// receives a, or 0 (v unchanged) when no step length qualifies.  Returns
+// whether the linear solve converged.
 bool newton_iteration(hfsi_ctx* c, double* v, double load, const hfsi_amg_params& amg, const hfsi_solve_params& sp,
-                      bool reuse, hfsi_newton_info* info, double* alpha = nullptr) {
+                      bool reuse, hfsi_newton_info* info, double* alpha = nullptr, double full_below = -1.0) {
   const long N = 4L * c->n;
   hipStream_t s = c->stream;
   c->kdv.ensure(N);
@@ -1663,7 +1703,10 @@ bool newton_iteration(hfsi_ctx* c, double* v, double load, const hfsi_amg_params
   HIP_CHECK(hipMemsetAsync(c->kdv.p, 0, sizeof(double) * N, s));
   hfsi_solve_info si{sizeof(hfsi_solve_info)};
   hfsi::krylov_solve(c, c->ktmp.p, c->kdv.p, sp, &si);
-  if (alpha) {
+  const double dvm = hfsi::mass_norm(c, c->kdv.p);
+  // a correction that meets the stopping rule (||dv||_M <= full_below) is
+  // taken whole: the residual is then at its rounding floor
+  if (alpha && !(dvm <= full_below)) {
     c->ktrial.ensure(N);
     c->ktres.ensure(N);
     double a = 1.0;
@@ -1690,10 +1733,10 @@ bool newton_iteration(hfsi_ctx* c, double* v, double load, const hfsi_amg_params
     *alpha = ok ? a : 0.0;
     if (ok) HIP_CHECK(hipMemcpyAsync(v, c->ktrial.p, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
   } else {
+    if (alpha) *alpha = 1.0;
     k_axpy<<<div_up(N, 256), 256, 0, s>>>(N, 1.0, c->kdv.p, v);
     HIP_LAUNCH_CHECK();
   }
-  const double dvm = hfsi::mass_norm(c, c->kdv.p);
   HIP_CHECK(hipEventRecord(ev.e1, s));
   HIP_CHECK(hipEventSynchronize(ev.e1));
   float ms = 0.f;
@@ -1764,7 +1807,8 @@ extern "C" hfsi_status hfsi_newton_solve(hfsi_ctx* c, double* v, double load, co
     // an earlier call on this mesh (e.g. the previous time step)
     const bool reuse = prm->step.amg_reuse == 2 || (k > 0 && prm->step.amg_reuse == 1);
     double alpha = 1.0;
-    newton_iteration(c, v, load, prm->step.amg, sp, reuse, &ni, prm->line_search ? &alpha : nullptr);
+    newton_iteration(c, v, load, prm->step.amg, sp, reuse, &ni, prm->line_search ? &alpha : nullptr,
+                     k > 0 ? prm->eps2 * dv0 : -1.0);
     ++its;
     kry += ni.krylov_iterations;
     if (k == 0) dv0 = ni.dv_mass_norm;

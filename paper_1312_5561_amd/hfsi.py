@@ -56,7 +56,8 @@ class AmgInfo(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("levels", C.c_int32), ("rows", C.c_int32 * 32),
                 ("nnz", C.c_int64 * 32), ("op_complexity", C.c_double), ("grid_complexity", C.c_double),
                 ("seconds", C.c_double), ("rho", C.c_double), ("learned_used", C.c_int32),
-                ("pmis_rounds", C.c_int32), ("rho_classical", C.c_double)]
+                ("pmis_rounds", C.c_int32), ("rho_classical", C.c_double), ("krylov_rho", C.c_double),
+                ("krylov_rho_classical", C.c_double)]
 
 
 class SolveParams(C.Structure):

@@ -183,3 +183,27 @@ def test_mass_norm_of_uniform_and_linear_fields(jitter):
     v[:, 1] = prob.X[:, 0]
     v[:, 3] = 1.0
     assert abs(d.mass_norm(v.ravel()) ** 2 - (1.0 / 3.0 + 1.0)) <= 1e-13
+
+
+@pytest.mark.parametrize("law", ["mooney-rivlin", "artery"])
+def test_schur_diagonal_default_theta(law):
+    """s_i = sum_T (1/theta_T + 1/kappa_T) diag(M_T)_i with the default
+    theta_T = mu^l_T / 5 (mu^l as printed) and the diagonal of the exact P1
+    pressure mass (quadrature)."""
+    prob = _problems()[law]
+    d = fe.Discretization(prob)
+    _, val = d.assemble(np.zeros(prob.n_dofs), 0.0)
+    _, _, s = d.blocks(val)
+    ref = np.zeros(prob.n_nodes)
+    for e, T in enumerate(prob.tets):
+        m = prob.materials[prob.mat_id[e]]
+        theta = _mu_l_printed(m) / 5.0
+        ref[T] += (1.0 / theta + 1.0 / m["kappa"]) * np.diag(_quad_mass(prob.X[T]))
+    assert np.abs(s - ref).max() <= 1e-13 * np.abs(ref).max()
+    # an explicit theta overrides it
+    d2 = fe.Discretization(prob, theta=0.7)
+    _, _, s2 = d2.blocks(val)
+    ref2 = np.zeros(prob.n_nodes)
+    for e, T in enumerate(prob.tets):
+        ref2[T] += (1.0 / 0.7 + 1.0 / prob.materials[prob.mat_id[e]]["kappa"]) * np.diag(_quad_mass(prob.X[T]))
+    assert np.abs(s2 - ref2).max() <= 1e-13 * np.abs(ref2).max()
