@@ -194,7 +194,8 @@ def stress_tangent(C, mat, fib=None):
 # ---------------------------------------------------------------------------
 
 
-def element_kernel(G, V, h, mat, ue, pe, fib=None, want_tangent=True, theta=None, cm=0.0, re=None):
+def element_kernel(G, V, h, mat, ue, pe, fib=None, want_tangent=True, theta=None, cm=0.0, re=None,
+                   pressure_geometric=True):
     """Residual R_e [m,4,4] and tangent K_e [m,16,16] of a batch of tetrahedra.
 
     Dof order inside an element is node-interleaved: 4a + c, c = 0,1,2 the
@@ -210,6 +211,9 @@ def element_kernel(G, V, h, mat, ue, pe, fib=None, want_tangent=True, theta=None
     the quasi-static problem.  int_T (r_s - cm d) = V/4 sum_b (r_b - cm d_b).
     The tangent is the exact derivative of this residual (block structure of
     eq. globsys: K = [A B1^T; B2 -C]).  External loads are added globally.
+    pressure_geometric=False leaves the pressure-geometric part
+    -pbar V J (g_a g_b^T - g_b g_a^T) out of A (the operator A_plus), and
+    the residual unchanged.
     """
     m = len(V)
     F = np.broadcast_to(I3x3, (m, 3, 3)) + np.einsum("mai,maj->mij", ue, G)
@@ -249,8 +253,9 @@ def element_kernel(G, V, h, mat, ue, pe, fib=None, want_tangent=True, theta=None
     # F_iM G_aJ C'_MJNL F_kN G_bL
     mat_part = np.einsum("zip,zaj,zpjnl,zkn,zbl->zaibk", F, G, CC, F, G, optimize=True)
     pg = np.einsum("mai,mbk->maibk", g, g)
-    A = (V[:, None, None, None, None] * mat_part
-         - (pbar * V * J)[:, None, None, None, None] * (pg - pg.transpose(0, 3, 2, 1, 4)))
+    A = V[:, None, None, None, None] * mat_part
+    if pressure_geometric:
+        A = A - (pbar * V * J)[:, None, None, None, None] * (pg - pg.transpose(0, 3, 2, 1, 4))
     A = A + (V[:, None, None] * geo)[:, :, None, :, None] * I3x3[None, None, :, None, :]
     K[:, :, 0:3, :, 0:3] = A
     # B1^T: dR^u_a / dp_b = -V/4 J g_a
@@ -368,13 +373,14 @@ class Discretization:
         R[:, 0:3] -= load * self.f_ext
         return R.ravel()
 
-    def assemble(self, v, load):
-        """Residual and consistent tangent (CSR values on the fixed pattern)."""
+    def assemble(self, v, load, pressure_geometric=True):
+        """Residual and consistent tangent (CSR values on the fixed pattern);
+        pressure_geometric=False: the tangent with A_plus in place of A."""
         R = np.zeros((self.n, 4))
         val = np.zeros(len(self.K_indices))
         for e, ve, mat, fib in self.element_batches(v):
             Re, Ke = element_kernel(self.G[e], self.V[e], self.h[e], mat, ve[:, :, 0:3], ve[:, :, 3], fib,
-                                    **self._inertia(e))
+                                    pressure_geometric=pressure_geometric, **self._inertia(e))
             for a in range(4):
                 np.add.at(R, self.prob.tets[e, a], Re[:, a])
             np.add.at(val, self.elem_pos[e].ravel(), Ke.ravel())

@@ -1334,11 +1334,11 @@ __global__ void k_tridiag_max(const int* __restrict__ kp, const double* __restri
 
 // ----------------------------------------------- padded CSR for the cycle
 // per row: number of 4-entry chunks, smallest column, and whether the row
-// spans more than 16 bits of columns
+// spans more than 16 bits of columns (1 in wide[r]; its chunks in wc[r])
 // (8 lanes per row)
 __global__ void __launch_bounds__(256)
 k_pack_count(int n, const int* __restrict__ ptr, const int* __restrict__ col, int* __restrict__ chunks,
-             int* __restrict__ base, int* __restrict__ wide) {
+             int* __restrict__ base, int* __restrict__ wide, int* __restrict__ wc) {
   const int r = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
   const int lane = threadIdx.x & 7;
   if (r >= n) return;
@@ -1354,17 +1354,31 @@ k_pack_count(int n, const int* __restrict__ ptr, const int* __restrict__ col, in
     mx = max(mx, __shfl_xor(mx, o, 8));
   }
   if (lane != 0) return;
-  chunks[r] = (e - a + 3) / 4;
+  const int nch = (e - a + 3) / 4;
+  const bool w = e > a && mx - mn > 65535;
+  chunks[r] = nch;
   base[r] = e > a ? mn : 0;
-  if (e > a && mx - mn > 65535) atomicOr(wide, 1);
+  wide[r] = w ? 1 : 0;
+  wc[r] = w ? nch : 0;
+}
+
+// wide rows: base = -1 - (index among wide rows), wch = first chunk in c32w
+// minus the row's first chunk (widx, wofs: exclusive scans of wide, wc)
+__global__ void k_pack_wide(int n, const int* __restrict__ p4, const int* __restrict__ wide,
+                            const int* __restrict__ widx, const int* __restrict__ wofs, int* __restrict__ base,
+                            int* __restrict__ wch) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n || !wide[r]) return;
+  base[r] = -1 - widx[r];
+  wch[widx[r]] = wofs[r] - p4[r];
 }
 
 // one wavefront per row: copy values and columns into the padded layout,
 // interleaved for G lanes per row (lanes_for4)
 template <class T>
 __global__ void k_pack_fill(int n, const int* __restrict__ ptr, const int* __restrict__ col, const T* __restrict__ val,
-                            const int* __restrict__ p4, const int* __restrict__ base, int wide, int G,
-                            uint16_t* __restrict__ c16, int* __restrict__ c32, T* __restrict__ out) {
+                            const int* __restrict__ p4, const int* __restrict__ base, const int* __restrict__ wch, int G,
+                            uint16_t* __restrict__ c16, int* __restrict__ c32w, T* __restrict__ out) {
   const int r = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (r >= n) return;
@@ -1373,6 +1387,8 @@ __global__ void k_pack_fill(int n, const int* __restrict__ ptr, const int* __res
   const int nch = p4[r + 1] - p4[r];
   const int padded = 4 * nch;
   const int b = base[r];
+  const bool wide = b < 0;
+  const long ow = wide ? 4L * (p4[r] + wch[-1 - b]) : 0;
   for (int k = lane; k < padded; k += 64) {
     const int ch = k >> 2, t = k & 3;
     const int g0 = ch - ch % G;                // first chunk of the group
@@ -1380,9 +1396,13 @@ __global__ void k_pack_fill(int n, const int* __restrict__ ptr, const int* __res
     const int src = 4 * g0 + (ch - g0) + q * t;
     const bool real = src < len;
     out[o + k] = real ? val[a + src] : (T)0;
-    const int cc = real ? col[a + src] : b;
-    if (wide) c32[o + k] = cc;
-    else c16[o + k] = (uint16_t)(cc - b);
+    if (wide) {
+      c32w[ow + k] = real ? col[a + src] : col[a];
+      c16[o + k] = 0;
+    } else {
+      const int cc = real ? col[a + src] : b;
+      c16[o + k] = (uint16_t)(cc - b);
+    }
   }
 }
 }  // namespace
@@ -1781,36 +1801,44 @@ void pack_level(hfsi_ctx* c, Level& L, int precision, bool same_pattern = false)
     K.rows = n;
     K.p4.ensure(n + 1);
     K.base.ensure(n);
-    DevBuf<int> wide;
-    wide.zero(1, s);
-    k_pack_count<<<div_up((long)n * 8, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, K.p4.p, K.base.p, wide.p);
+    DevBuf<int> wide, wc, widx;
+    wide.ensure(n + 1);
+    wc.ensure(n + 1);
+    widx.ensure(n + 1);
+    k_pack_count<<<div_up((long)n * 8, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, K.p4.p, K.base.p, wide.p, wc.p);
     HIP_LAUNCH_CHECK();
     HIP_CHECK(hipMemsetAsync(K.p4.p + n, 0, sizeof(int), s));
-    int w = 0;  // read in the scan's wait
-    K.chunks = exclusive_scan(K.p4.p, K.p4.p, n + 1, s, wide.p, 1, &w);
-    K.wide = w != 0;
+    HIP_CHECK(hipMemsetAsync(wide.p + n, 0, sizeof(int), s));
+    HIP_CHECK(hipMemsetAsync(wc.p + n, 0, sizeof(int), s));
+    K.chunks = exclusive_scan(K.p4.p, K.p4.p, n + 1, s);
+    K.nwide = (int)exclusive_scan(wide.p, widx.p, n + 1, s);
+    K.wchunks = 0;
+    if (K.nwide > 0) {
+      K.wchunks = exclusive_scan(wc.p, wc.p, n + 1, s);
+      K.wch.ensure(K.nwide);
+      k_pack_wide<<<div_up(n, 256), 256, 0, s>>>(n, K.p4.p, wide.p, widx.p, wc.p, K.base.p, K.wch.p);
+      HIP_LAUNCH_CHECK();
+      K.c32w.ensure(4 * (size_t)K.wchunks);
+    } else {
+      K.c32w.release();
+      K.wch.release();
+    }
   }
   const size_t m = 4 * (size_t)K.chunks;
-  // keep only the arrays of this layout and precision
-  if (K.wide) {
-    K.c32.ensure(m);
-    K.c16.release();
-  } else {
-    K.c16.ensure(m);
-    K.c32.release();
-  }
+  // keep only the arrays of this precision
+  K.c16.ensure(m);
   if (precision == 1) K.v64.release();
   else K.v32.release();
   const int grid = div_up((long)n * 64, 256);
   const int G = lanes_for4(K.chunks, n);
   if (precision == 1) {
     K.v32.ensure(m);
-    k_pack_fill<float><<<grid, 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A32.p, K.p4.p, K.base.p, (int)K.wide, G,
-                                            K.c16.p, K.c32.p, K.v32.p);
+    k_pack_fill<float><<<grid, 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A32.p, K.p4.p, K.base.p, K.wch.p, G, K.c16.p,
+                                            K.c32w.p, K.v32.p);
   } else {
     K.v64.ensure(m);
-    k_pack_fill<double><<<grid, 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, K.p4.p, K.base.p, (int)K.wide, G,
-                                             K.c16.p, K.c32.p, K.v64.p);
+    k_pack_fill<double><<<grid, 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, K.p4.p, K.base.p, K.wch.p, G,
+                                             K.c16.p, K.c32w.p, K.v64.p);
   }
   HIP_LAUNCH_CHECK();
   L.packed = true;

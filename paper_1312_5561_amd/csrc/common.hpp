@@ -145,16 +145,20 @@ struct Csr {
 // CSR copy for the smoother and residual of levels without node blocks: each
 // row padded to a multiple of 4 entries (zero values, column offset 0), so a
 // lane reads 4 values and 4 columns with one aligned load each.  Columns are
-// 16-bit offsets from the row's smallest column (`base`) unless some row spans
-// more than 65535 columns (`wide`: absolute int32 columns).
+// 16-bit offsets from the row's smallest column (`base`); a row that spans
+// more than 65535 columns (a few rows of the large coarse levels) keeps
+// absolute int32 columns in a side array instead: its base is -1 - w, w its
+// index among those rows, and its chunk k sits at chunk k + wch[w] of c32w.
 struct Packed4 {
   int rows = 0;
   int64_t chunks = 0;          // padded entries / 4
-  bool wide = false;
+  int nwide = 0;               // rows with int32 columns
+  int64_t wchunks = 0;         // their chunks
   DevBuf<int> p4;              // [rows+1] first chunk of each row
-  DevBuf<int> base;            // [rows] smallest column of each row
-  DevBuf<uint16_t> c16;        // [4*chunks] column - base
-  DevBuf<int> c32;             // [4*chunks] when wide
+  DevBuf<int> base;            // [rows] smallest column, or -1 - w
+  DevBuf<uint16_t> c16;        // [4*chunks] column - base (narrow rows)
+  DevBuf<int> c32w;            // [4*wchunks] columns of the wide rows
+  DevBuf<int> wch;             // [nwide] chunk shift of each wide row
   DevBuf<float> v32;           // [4*chunks] values of the fp32 cycle
   DevBuf<double> v64;          // [4*chunks] values of the fp64 cycle
 };

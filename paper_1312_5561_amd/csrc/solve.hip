@@ -85,36 +85,47 @@ struct Vec4<double> {
   using type = double4;
 };
 
-template <class T, int G, int OP, bool WIDE>
+template <class T, int G, int OP, bool MIXED>
 __global__ void __launch_bounds__(256)
-k_csr4(int n, const int* __restrict__ p4, const int* __restrict__ base, const void* __restrict__ cols,
-       const T* __restrict__ val, const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ dinv,
-       T* __restrict__ y, T* __restrict__ d, T c1, T c2) {
+k_csr4(int n, const int* __restrict__ p4, const int* __restrict__ base, const uint16_t* __restrict__ c16,
+       const int* __restrict__ c32w, const int* __restrict__ wch, const T* __restrict__ val,
+       const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ dinv, T* __restrict__ y,
+       T* __restrict__ d, T c1, T c2) {
   using V4 = typename Vec4<T>::type;
   const int gid = (blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int lane = threadIdx.x % G;
   if (gid >= n) return;
   const int hi = p4[gid + 1];
-  const T* xr = WIDE ? x : x + base[gid];
+  const int bs = base[gid];
   const V4* v4 = reinterpret_cast<const V4*>(val);
   // two chunks per trip (k and k + G) so that a lane has both chunks' loads
-  // and gathers in flight at once; the second is a zero chunk at column
-  // offset 0 (an element of the row) past the row's end
+  // and gathers in flight at once; the second is a zero chunk at a column of
+  // the row past the row's end
   T s = 0, s2 = 0;
-  for (int k = p4[gid] + lane; k < hi; k += 2 * G) {
-    const bool two = k + G < hi;
-    const V4 a = v4[k];
-    const V4 b = two ? v4[k + G] : V4{};
-    if (WIDE) {
-      const int4 j = reinterpret_cast<const int4*>(cols)[k];
-      const int4 q = two ? reinterpret_cast<const int4*>(cols)[k + G] : make_int4(j.x, j.x, j.x, j.x);
+  if (!MIXED || bs >= 0) {
+    const T* xr = x + bs;
+    const ushort4* cc = reinterpret_cast<const ushort4*>(c16);
+    for (int k = p4[gid] + lane; k < hi; k += 2 * G) {
+      const bool two = k + G < hi;
+      const V4 a = v4[k];
+      const V4 e = two ? v4[k + G] : V4{};
+      const ushort4 j = cc[k];
+      const ushort4 q = two ? cc[k + G] : make_ushort4(0, 0, 0, 0);
       s += a.x * xr[j.x] + a.y * xr[j.y] + a.z * xr[j.z] + a.w * xr[j.w];
-      s2 += b.x * xr[q.x] + b.y * xr[q.y] + b.z * xr[q.z] + b.w * xr[q.w];
-    } else {
-      const ushort4 j = reinterpret_cast<const ushort4*>(cols)[k];
-      const ushort4 q = two ? reinterpret_cast<const ushort4*>(cols)[k + G] : make_ushort4(0, 0, 0, 0);
-      s += a.x * xr[j.x] + a.y * xr[j.y] + a.z * xr[j.z] + a.w * xr[j.w];
-      s2 += b.x * xr[q.x] + b.y * xr[q.y] + b.z * xr[q.z] + b.w * xr[q.w];
+      s2 += e.x * xr[q.x] + e.y * xr[q.y] + e.z * xr[q.z] + e.w * xr[q.w];
+    }
+  } else {
+    // a row spanning more than 65535 columns: absolute columns
+    const int4* cw = reinterpret_cast<const int4*>(c32w);
+    const int sh = wch[-1 - bs];
+    for (int k = p4[gid] + lane; k < hi; k += 2 * G) {
+      const bool two = k + G < hi;
+      const V4 a = v4[k];
+      const V4 e = two ? v4[k + G] : V4{};
+      const int4 j = cw[k + sh];
+      const int4 q = two ? cw[k + G + sh] : make_int4(j.x, j.x, j.x, j.x);
+      s += a.x * x[j.x] + a.y * x[j.y] + a.z * x[j.z] + a.w * x[j.w];
+      s2 += e.x * x[q.x] + e.y * x[q.y] + e.z * x[q.z] + e.w * x[q.w];
     }
   }
   s += s2;
@@ -132,28 +143,34 @@ k_csr4(int n, const int* __restrict__ p4, const int* __restrict__ base, const vo
   }
 }
 
-template <class T, int OP, bool WIDE>
-void csr4_launch_w(int G, int n, const int* p4, const int* base, const void* cols, const T* val, const T* x,
-                   const T* b, const T* dinv, T* y, T* d, T c1, T c2, hipStream_t s) {
+template <class T, int OP, bool MIXED>
+void csr4_launch_w(int G, int n, const int* p4, const int* base, const uint16_t* c16, const int* c32w,
+                   const int* wch, const T* val, const T* x, const T* b, const T* dinv, T* y, T* d, T c1, T c2,
+                   hipStream_t s) {
   const int grid = div_up((long)n * G, 256);
+#define HFSI_CSR4(GG)                                                                                      \
+  k_csr4<T, GG, OP, MIXED><<<grid, 256, 0, s>>>(n, p4, base, c16, c32w, wch, val, x, b, dinv, y, d, c1, c2)
   switch (G) {
-    case 2: k_csr4<T, 2, OP, WIDE><<<grid, 256, 0, s>>>(n, p4, base, cols, val, x, b, dinv, y, d, c1, c2); break;
-    case 4: k_csr4<T, 4, OP, WIDE><<<grid, 256, 0, s>>>(n, p4, base, cols, val, x, b, dinv, y, d, c1, c2); break;
-    case 8: k_csr4<T, 8, OP, WIDE><<<grid, 256, 0, s>>>(n, p4, base, cols, val, x, b, dinv, y, d, c1, c2); break;
-    case 16: k_csr4<T, 16, OP, WIDE><<<grid, 256, 0, s>>>(n, p4, base, cols, val, x, b, dinv, y, d, c1, c2); break;
-    case 32: k_csr4<T, 32, OP, WIDE><<<grid, 256, 0, s>>>(n, p4, base, cols, val, x, b, dinv, y, d, c1, c2); break;
-    default: k_csr4<T, 64, OP, WIDE><<<grid, 256, 0, s>>>(n, p4, base, cols, val, x, b, dinv, y, d, c1, c2); break;
+    case 2: HFSI_CSR4(2); break;
+    case 4: HFSI_CSR4(4); break;
+    case 8: HFSI_CSR4(8); break;
+    case 16: HFSI_CSR4(16); break;
+    case 32: HFSI_CSR4(32); break;
+    default: HFSI_CSR4(64); break;
   }
+#undef HFSI_CSR4
   HIP_LAUNCH_CHECK();
 }
 
+// nwide > 0: the level has rows with int32 columns (Packed4)
 template <class T, int OP>
-void csr4_launch(int n, int64_t chunks, bool wide, const int* p4, const int* base, const void* cols, const T* val,
-                 const T* x, const T* b, const T* dinv, T* y, T* d, T c1, T c2, hipStream_t s) {
+void csr4_launch(int n, int64_t chunks, int nwide, const int* p4, const int* base, const uint16_t* c16,
+                 const int* c32w, const int* wch, const T* val, const T* x, const T* b, const T* dinv, T* y, T* d,
+                 T c1, T c2, hipStream_t s) {
   if (n <= 0) return;
   const int G = lanes_for4(chunks, n);
-  if (wide) csr4_launch_w<T, OP, true>(G, n, p4, base, cols, val, x, b, dinv, y, d, c1, c2, s);
-  else csr4_launch_w<T, OP, false>(G, n, p4, base, cols, val, x, b, dinv, y, d, c1, c2, s);
+  if (nwide > 0) csr4_launch_w<T, OP, true>(G, n, p4, base, c16, c32w, wch, val, x, b, dinv, y, d, c1, c2, s);
+  else csr4_launch_w<T, OP, false>(G, n, p4, base, c16, c32w, wch, val, x, b, dinv, y, d, c1, c2, s);
 }
 
 // Same operations on a 3x3 node-block matrix: 8 lanes per node row, each lane
@@ -738,8 +755,8 @@ void level_op(Level& L, const LevelView<T>& v, const T* x, const T* b, T* y, T* 
     HIP_LAUNCH_CHECK();
   } else if (v.PK) {
     const Packed4& K = L.pk;
-    csr4_launch<T, OP>(L.n, K.chunks, K.wide, K.p4.p, K.base.p, K.wide ? (const void*)K.c32.p : (const void*)K.c16.p,
-                       v.PK, x, b, v.dinv, y, d, c1, c2, s);
+    csr4_launch<T, OP>(L.n, K.chunks, K.nwide, K.p4.p, K.base.p, K.c16.p, K.c32w.p, K.wch.p, v.PK, x, b, v.dinv, y,
+                       d, c1, c2, s);
   } else {
     csr_launch<T, OP>(lanes_for(L.A.nnz, L.n), L.n, L.A.ptr.p, L.A.col.p, v.A, x, b, v.dinv, y, d, c1, c2, s);
   }
@@ -754,9 +771,10 @@ double level_op_bytes(const hfsi_ctx* c, const Level& L, bool resid) {
   const double ts = H.precision == 1 ? 4.0 : 8.0;
   const double per_row = resid ? 2.0 * ts : (H.smoother == 1 ? 6.0 * ts : 4.0 * ts);
   if (L.bptr) return (double)c->nb * (9.0 * ts + 4.0) + (double)L.nbr * 4.0 + L.n * per_row;
-  // padded CSR: values and 16-bit (or 32-bit) columns of every chunk, chunk
-  // pointer and column base per row
-  if (L.packed) return 4.0 * L.pk.chunks * (ts + (L.pk.wide ? 4.0 : 2.0)) + L.n * (8.0 + per_row);
+  // padded CSR: values and 16-bit columns of every chunk (int32 columns on
+  // the wide rows), chunk pointer and column base per row
+  if (L.packed)
+    return 4.0 * L.pk.chunks * (ts + 2.0) + 4.0 * L.pk.wchunks * 2.0 + L.n * (8.0 + per_row);
   return (double)L.A.nnz * (ts + 4.0) + L.n * (4.0 + per_row);
 }
 
@@ -1509,9 +1527,15 @@ void time_level_op(hfsi_ctx* c, Level& L, bool resid, void* const* a) {
   } else if (L.packed) {
     const Packed4& K = L.pk;
     const T* val = (const T*)a[3];
-    if (op == OP_RESID) csr4_launch<T, OP_RESID>(L.n, K.chunks, K.wide, i0, i1, a[2], val, x, bb, v.dinv, y, d, c1, c2, s);
-    else if (op == OP_JACOBI) csr4_launch<T, OP_JACOBI>(L.n, K.chunks, K.wide, i0, i1, a[2], val, x, bb, v.dinv, y, d, c1, c2, s);
-    else csr4_launch<T, OP_CHEB>(L.n, K.chunks, K.wide, i0, i1, a[2], val, x, bb, v.dinv, y, d, c1, c2, s);
+    const uint16_t* c16 = (const uint16_t*)a[2];
+    const int* cw = K.nwide > 0 ? (const int*)a[4] : nullptr;
+    const int* wch = K.nwide > 0 ? (const int*)a[5] : nullptr;
+    if (op == OP_RESID)
+      csr4_launch<T, OP_RESID>(L.n, K.chunks, K.nwide, i0, i1, c16, cw, wch, val, x, bb, v.dinv, y, d, c1, c2, s);
+    else if (op == OP_JACOBI)
+      csr4_launch<T, OP_JACOBI>(L.n, K.chunks, K.nwide, i0, i1, c16, cw, wch, val, x, bb, v.dinv, y, d, c1, c2, s);
+    else
+      csr4_launch<T, OP_CHEB>(L.n, K.chunks, K.nwide, i0, i1, c16, cw, wch, val, x, bb, v.dinv, y, d, c1, c2, s);
   } else {
     const T* val = (const T*)a[2];
     const int G = lanes_for(L.A.nnz, L.n);
@@ -1533,9 +1557,14 @@ std::vector<std::pair<const void*, size_t>> level_arrays(const hfsi_ctx* c, cons
   if (L.packed) {
     const Packed4& K = L.pk;
     const size_t m = 4 * (size_t)K.chunks;
-    return {{K.p4.p, 4 * (size_t)(L.n + 1)}, {K.base.p, 4 * (size_t)L.n},
-            {K.wide ? (const void*)K.c32.p : (const void*)K.c16.p, (K.wide ? 4 : 2) * m},
-            {f32 ? (const void*)K.v32.p : (const void*)K.v64.p, ts * m}};
+    std::vector<std::pair<const void*, size_t>> out = {
+        {K.p4.p, 4 * (size_t)(L.n + 1)}, {K.base.p, 4 * (size_t)L.n}, {K.c16.p, 2 * m},
+        {f32 ? (const void*)K.v32.p : (const void*)K.v64.p, ts * m}};
+    if (K.nwide > 0) {
+      out.push_back({K.c32w.p, 16 * (size_t)K.wchunks});
+      out.push_back({K.wch.p, 4 * (size_t)K.nwide});
+    }
+    return out;
   }
   return {{L.A.ptr.p, 4 * (size_t)(L.n + 1)}, {L.A.col.p, 4 * (size_t)L.A.nnz},
           {f32 ? (const void*)L.A32.p : (const void*)L.A.val.p, ts * (size_t)L.A.nnz}};
@@ -1586,7 +1615,7 @@ extern "C" hfsi_status hfsi_time_kernel(hfsi_ctx* c, int32_t kernel, int32_t rep
       }
     }
     launch = [&, arr, resid, f32, stride, ncp]() {
-      void* a[4] = {nullptr, nullptr, nullptr, nullptr};
+      void* a[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
       size_t off = stride * (rot++ % ncp);
       for (size_t i = 0; i < arr.size(); ++i) {
         a[i] = tmp.p + off;

@@ -328,3 +328,41 @@ def test_fp32_cycle_is_fp32(lib):
     rel = float(torch.linalg.norm(z32 - z64) / torch.linalg.norm(z64))
     print(f"[precision] relative difference {rel:.2e}", flush=True)
     assert 1e-9 < rel < 1e-4
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_vcycle_with_rows_spanning_more_than_16_bits(lib, precision):
+    """A caller matrix (hfsi_amg_setup_csr) whose rows partly span more than
+    65535 columns: the padded smoother keeps int32 columns for those rows
+    and 16-bit offsets for the others; the V-cycle matches the oracle on the
+    exported hierarchy entry by entry."""
+    import torch
+    import scipy.sparse as sp
+    import test_oracle_amg as T
+    A = T.laplacian(48, 48, 48).tolil()
+    n = A.shape[0]
+    rng = np.random.default_rng(11)
+    for i in rng.choice(n - 70000, 400, replace=False):
+        j = int(i) + 70000
+        A[i, j] = A[j, i] = -0.05
+        A[i, i] += 0.05
+        A[j, j] += 0.05
+    A = A.tocsr()
+    A.sort_indices()
+    comp = np.zeros(n, np.int32)
+    rows = np.repeat(np.arange(n), np.diff(A.indptr))
+    span = np.maximum.reduceat(A.indices, A.indptr[:-1]) - np.minimum.reduceat(A.indices, A.indptr[:-1])
+    assert (span > 65535).sum() >= 400
+    gprm, oprm = amg_prm_pair(lib, smoother=1, precision=precision, max_coarse=200, schedule="default")
+    ctx = lib.Context(0)
+    print(f"[vcycle wide rows] n={n} precision={precision}", flush=True)
+    info = ctx.amg_setup_csr(A.indptr, A.indices, A.data, comp, gprm)
+    H = gpu_hierarchy_to_oracle(ctx, info, oprm)
+    r = rng.normal(size=n)
+    z = torch.zeros(n, dtype=torch.float64, device="cuda")
+    ctx.vcycle(torch_dev(r), z)
+    zo = amg.vcycle(H, r, oprm)
+    tol = 1e-12 if precision == 0 else 2e-5
+    dz = np.abs(z.cpu().numpy() - zo)
+    print(f"[vcycle wide rows] max |z - zo| / max |zo| = {dz.max() / np.abs(zo).max():.2e}", flush=True)
+    assert dz.max() <= tol * np.abs(zo).max()

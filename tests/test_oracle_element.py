@@ -215,3 +215,43 @@ def test_inertia_history_matching_the_state_cancels():
     d.set_inertia(25.0, 25.0 * v.reshape(d.n, 4)[:, 0:3])
     R1 = d.residual(v.ravel(), 0.4)
     assert np.abs(R1 - R0).max() <= 1e-12 * np.abs(R0).max()
+
+
+@pytest.mark.parametrize("law", ["mr", "artery"])
+def test_pressure_geometric_part_is_the_derivative_of_the_pressure_force(law):
+    """A - A_plus is the derivative with respect to u of the pressure part
+    of the displacement residual, -V pbar J F^{-T} G_a, at fixed p: central
+    differences of that force alone (written from F with numpy here)."""
+    p = _problem(law)
+    d = fe.Discretization(p)
+    v = synth.random_state(p, 13, u_scale=0.1, p_scale=0.5)
+    _, val = d.assemble(v, 0.5)
+    _, valp = d.assemble(v, 0.5, pressure_geometric=False)
+    D = (d.csr(val) - d.csr(valp)).toarray()
+    Duu = D.reshape(p.n_nodes, 4, p.n_nodes, 4)[:, 0:3, :, 0:3].reshape(3 * p.n_nodes, 3 * p.n_nodes)
+    # nothing else changes
+    mask = np.ones((p.n_nodes, 4, p.n_nodes, 4), bool)
+    mask[:, 0:3, :, 0:3] = False
+    assert np.abs(D.reshape(p.n_nodes, 4, p.n_nodes, 4)[mask]).max() == 0.0
+
+    def pforce(u):
+        T = p.tets
+        F = np.eye(3)[None] + np.einsum("mai,maj->mij", u[T], d.G)
+        J = np.linalg.det(F)
+        g = np.einsum("mji,maj->mai", np.linalg.inv(F), d.G)
+        pbar = v[:, 3][T].mean(axis=1)
+        f = np.zeros((p.n_nodes, 3))
+        fe_ = -(d.V * pbar * J)[:, None, None] * g
+        for a in range(4):
+            np.add.at(f, T[:, a], fe_[:, a])
+        return f.ravel()
+
+    u0 = v[:, 0:3].copy()
+    h = 1e-6
+    Dfd = np.zeros_like(Duu)
+    for j in range(3 * p.n_nodes):
+        up = u0.copy().ravel(); up[j] += h
+        um = u0.copy().ravel(); um[j] -= h
+        Dfd[:, j] = (pforce(up.reshape(-1, 3)) - pforce(um.reshape(-1, 3))) / (2 * h)
+    assert np.abs(Duu - Dfd).max() <= 1e-7 * max(1.0, np.abs(Duu).max())
+    assert np.abs(Duu).max() > 0
