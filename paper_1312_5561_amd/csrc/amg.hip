@@ -1241,6 +1241,38 @@ __global__ void k_lanczos_apply(int n, const int* __restrict__ ptr, const int* _
   if (lane == 0) w[i] = dm[i] * s - beta * qp[i];
 }
 
+// the same step on level 0's 3x3 node blocks (8 lanes per node row, three
+// rows each): one column index per nine values instead of one per value
+__global__ void k_lanczos_apply_b3(int nn, const int* __restrict__ bptr, const int* __restrict__ bcol,
+                                   const double* __restrict__ B, const double* __restrict__ dm,
+                                   const double* __restrict__ q, const double* __restrict__ qp,
+                                   const double* __restrict__ betap, double* __restrict__ w) {
+  const double beta = betap ? betap[0] : 0.0;
+  const int node = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  const int lane = threadIdx.x & 7;
+  if (node >= nn) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int e = bptr[node] + lane; e < bptr[node + 1]; e += 8) {
+    const int j = 3 * bcol[e];
+    const double* v = B + 9 * (size_t)e;
+    const double x0 = dm[j] * q[j], x1 = dm[j + 1] * q[j + 1], x2 = dm[j + 2] * q[j + 2];
+    s0 += v[0] * x0 + v[1] * x1 + v[2] * x2;
+    s1 += v[3] * x0 + v[4] * x1 + v[5] * x2;
+    s2 += v[6] * x0 + v[7] * x1 + v[8] * x2;
+  }
+#pragma unroll
+  for (int o = 4; o > 0; o >>= 1) {
+    s0 += __shfl_xor(s0, o, 8);
+    s1 += __shfl_xor(s1, o, 8);
+    s2 += __shfl_xor(s2, o, 8);
+  }
+  if (lane < 3) {
+    const int i = 3 * node + lane;
+    const double sv = lane == 0 ? s0 : (lane == 1 ? s1 : s2);
+    w[i] = dm[i] * sv - beta * qp[i];
+  }
+}
+
 __global__ void k_rsqrt_abs(int n, const double* __restrict__ dinv, double* __restrict__ dm) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dm[i] = sqrt(fabs(dinv[i]));
@@ -1442,8 +1474,12 @@ void lanczos_enqueue(hfsi_ctx* c, Level& L, int steps, uint64_t seed, int level,
   HIP_LAUNCH_CHECK();
   const int steps_run = std::min(steps, std::min(n, 32));
   for (int it = 0; it < steps_run; ++it) {
-    k_lanczos_apply<<<div_up((long)n * 16, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, dabs.p, q.p, qp.p,
-                                                               it ? ab.p + 32 + it - 1 : nullptr, w.p);
+    if (L.bptr)
+      k_lanczos_apply_b3<<<div_up((long)L.nbr * 8, 256), 256, 0, s>>>(L.nbr, L.bptr, L.bcol, L.b3d.p, dabs.p, q.p,
+                                                                       qp.p, it ? ab.p + 32 + it - 1 : nullptr, w.p);
+    else
+      k_lanczos_apply<<<div_up((long)n * 16, 256), 256, 0, s>>>(n, L.A.ptr.p, L.A.col.p, L.A.val.p, dabs.p, q.p,
+                                                                 qp.p, it ? ab.p + 32 + it - 1 : nullptr, w.p);
     k_dot_partial<<<nb, 256, 0, s>>>(n, q.p, w.p, part.p);
     k_dot_finish<<<1, 256, 0, s>>>(part.p, 0, ab.p + it, ab.p, kst.p, it);        // alpha
     k_axpy_neg_dev<<<g, 256, 0, s>>>(n, ab.p + it, q.p, w.p);

@@ -28,7 +28,8 @@ constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NIN * NH, OFF_W2 = OFF_B1 + NH, OFF_
               OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NH * NOUTP, NPARAM = OFF_B3 + NOUTP;
 constexpr int NWB = NIN * NH + NH * NH + NH * NOUTP;  // bf16 weights (W1|W2|W3)
 
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -210,8 +211,9 @@ k_ideal_target(int ns, const int* __restrict__ rows, const int* __restrict__ ap,
 }
 
 // ------------------------------------------------------------ network
-// 4 wavefronts per block, 16 samples per wavefront, v_mfma_f32_16x16x16_bf16:
-// lane l holds A[l%16][4(l/16)+v], B[4(l/16)+v][l%16], D[4(l/16)+v][l%16].
+// 4 wavefronts per block, 16 samples per wavefront, gfx950's
+// v_mfma_f32_16x16x32_bf16: lane l holds A[l%16][8(l/16)+v] and
+// B[8(l/16)+v][l%16] (v = 0..7), D[4(l/16)+v][l%16] (v = 0..3).
 template <int NJ, bool RELU>
 __device__ __forceinline__ void dense_layer(const uint16_t (*in)[NIN + 8], const uint16_t* __restrict__ Wl,
                                             const float* __restrict__ bias, uint16_t (*outb)[NIN + 8],
@@ -221,14 +223,15 @@ __device__ __forceinline__ void dense_layer(const uint16_t (*in)[NIN + 8], const
   for (int jb = 0; jb < NJ / 16; ++jb) {
     v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kb = 0; kb < NIN / 16; ++kb) {
-      v4s a, b;
+    for (int kb = 0; kb < NIN / 32; ++kb) {
+      v8s a, b;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        a[v] = (short)in[lr][16 * kb + 4 * lg + v];
-        b[v] = (short)Wl[(16 * kb + 4 * lg + v) * NJ + 16 * jb + lr];
+      for (int v = 0; v < 8; ++v) {
+        a[v] = (short)in[lr][32 * kb + 8 * lg + v];
+        b[v] = (short)Wl[(32 * kb + 8 * lg + v) * NJ + 16 * jb + lr];
       }
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), acc, 0,
+                                                     0, 0);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
