@@ -1,0 +1,248 @@
+"""Pins of the coupled-AMG / multiplicative Vanka oracle (section "The
+multiplicative Vanka smoother", eq. locsys and eq. vankasmooth).
+
+* the four blocks put back together are the assembled tangent (a wrong
+  sign of -C, a transposed B block or a missing Dirichlet zero fails);
+* on disjoint patches one sweep is block SOR, written as the textbook
+  splitting (D/omega + L) x1 = b - (U + (1 - 1/omega) D) x0 and solved
+  densely (a local system from the wrong rows, a residual without the
+  earlier updates, or omega applied to the residual instead of the
+  correction fails);
+* a single patch holding every unknown gives x0 + omega K^-1 (b - K x0);
+* the greedy colours are first-fit and valid: no two patches of a colour
+  share an unknown or a stored coupling, checked by brute force on the
+  dense pattern; a sweep that treats each colour at once (all its local
+  residuals from the same iterate) equals the sequential sweep;
+* the coarse coupled system is P^T K P with P = diag(P_u, P_p) formed
+  densely, and the two-level cycle without smoothing is P K_c^-1 P^T b;
+* on the 6^3 Mooney-Rivlin cube the AMG method converges (the paper's
+  observation for the solid).
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.sparse as sp
+
+import synth
+from oracle import amg, fe, krylov, vanka
+
+
+def _cube_system(N=6, load=1.0, seed_state=None):
+    prob = synth.cube_problem(N)
+    d = fe.Discretization(prob)
+    v = np.zeros(prob.n_dofs) if seed_state is None else synth.random_state(prob, seed_state, 0.05, 0.1).ravel()
+    R, val = d.assemble(v, load)
+    R, val = d.apply_dirichlet(R, val)
+    return prob, d, d.csr(val), -R, val
+
+
+def _small_prm(steps=2, omega=0.78, max_coarse=150):
+    return vanka.VankaParams(omega=omega, steps=steps,
+                             amg=amg.AmgParams(smoother="l1jacobi", interp="ext+i", max_coarse=max_coarse))
+
+
+@pytest.fixture(scope="module")
+def cube6():
+    prob, d, K, b, val = _cube_system(6, seed_state=3)
+    blocks = vanka.tangent_blocks(d, val)
+    CH = vanka.setup(*blocks, _small_prm())
+    return prob, d, K, b, blocks, CH
+
+
+def test_blocks_are_the_tangent(cube6):
+    prob, d, K, b, blocks, CH = cube6
+    n = prob.n_nodes
+    Kuu, Kup, Kpu, Kpp = blocks
+    perm = np.concatenate([np.arange(4 * n).reshape(n, 4)[:, :3].ravel(), 4 * np.arange(n) + 3])
+    Kd = K.toarray()[np.ix_(perm, perm)]
+    Kb = sp.bmat([[Kuu, Kup], [Kpu, Kpp]]).toarray()
+    assert np.array_equal(Kb, Kd)
+    # -C is negative definite on the pressure block
+    assert np.linalg.eigvalsh(0.5 * (Kpp + Kpp.T).toarray()).max() < 0
+    # vector reordering round trip
+    x = np.random.default_rng(0).normal(size=4 * n)
+    assert np.array_equal(vanka.to_interleaved(vanka.to_blocked(x, n), n), x)
+    assert np.array_equal(vanka.to_blocked(x, n), x[perm])
+
+
+def _disjoint_system(rng, npr=5, per=3):
+    """Saddle system whose patches partition the unknowns: pressure i is
+    coupled through B2 to displacement unknowns per*i .. per*i+per-1 only."""
+    nu = npr * per
+    M = rng.normal(size=(nu, nu))
+    Kuu = M @ M.T + nu * np.eye(nu)
+    Kpu = np.zeros((npr, nu))
+    for i in range(npr):
+        Kpu[i, per * i:per * (i + 1)] = rng.normal(size=per)
+    Kup = Kpu.T + 0.1 * (Kpu.T != 0) * rng.normal(size=Kpu.T.shape)
+    Kpp = -np.diag(rng.uniform(0.5, 1.5, npr))
+    Kpp[0, 1] = Kpp[1, 0] = 0.1
+    return [sp.csr_matrix(B) for B in (Kuu, Kup, Kpu, Kpp)], nu, npr
+
+
+def _level_of(blocks):
+    L = vanka.CoupledLevel(*[B.tocsr() for B in blocks])
+    vanka._vanka_data(L)
+    return L
+
+
+@pytest.mark.parametrize("omega", [1.0, 0.78, 0.5])
+def test_disjoint_patches_give_block_sor(omega):
+    rng = np.random.default_rng(4)
+    blocks, nu, npr = _disjoint_system(rng)
+    L = _level_of(blocks)
+    K = L.K().toarray()
+    b = rng.normal(size=nu + npr)
+    x0 = rng.normal(size=nu + npr)
+    x1 = vanka.vanka_sweep(L, b, x0, omega)
+    # the patch order, then D, L, U of the block splitting in that order
+    order = np.concatenate([np.concatenate([L.patches[i], [nu + i]]) for i in L.order])
+    assert sorted(order) == list(range(nu + npr))   # a partition
+    Kp = K[np.ix_(order, order)]
+    sizes = [len(L.patches[i]) + 1 for i in L.order]
+    edges = np.concatenate([[0], np.cumsum(sizes)])
+    D = np.zeros_like(Kp)
+    for a, e in zip(edges[:-1], edges[1:]):
+        D[a:e, a:e] = Kp[a:e, a:e]
+    blk = np.zeros(len(order), int)
+    for k, (a, e) in enumerate(zip(edges[:-1], edges[1:])):
+        blk[a:e] = k
+    lower = (blk[:, None] > blk[None, :]) * Kp
+    upper = (blk[:, None] < blk[None, :]) * Kp
+    y0 = x0[order]
+    y1 = np.linalg.solve(D / omega + lower, b[order] - (upper + (1.0 - 1.0 / omega) * D) @ y0)
+    assert np.abs(x1[order] - y1).max() <= 1e-12 * np.abs(y1).max()
+
+
+def test_single_patch_is_the_relaxed_solve():
+    rng = np.random.default_rng(5)
+    nu = 7
+    M = rng.normal(size=(nu, nu))
+    Kuu = sp.csr_matrix(M @ M.T + nu * np.eye(nu))
+    Kpu = sp.csr_matrix(rng.normal(size=(1, nu)))
+    Kup = sp.csr_matrix(rng.normal(size=(nu, 1)))
+    Kpp = sp.csr_matrix([[-0.7]])
+    L = _level_of([Kuu, Kup, Kpu, Kpp])
+    K = L.K().toarray()
+    b, x0 = rng.normal(size=nu + 1), rng.normal(size=nu + 1)
+    x1 = vanka.vanka_sweep(L, b, x0, 0.6)
+    ref = x0 + 0.6 * np.linalg.solve(K, b - K @ x0)
+    assert np.abs(x1 - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def _dense_pattern(L):
+    K = L.K()
+    P = K.copy()
+    P.data = np.ones_like(P.data)
+    return P.toarray() != 0
+
+
+def test_colours_are_first_fit_and_valid(cube6):
+    *_, CH = cube6
+    assert len(CH.levels) >= 3
+    for L in CH.levels[:-1]:
+        pat = _dense_pattern(L)
+        sets = [np.concatenate([L.patches[i], [L.nu + i]]) for i in range(L.np_)]
+        col = L.colour
+        for c in range(col.max() + 1):
+            members = np.flatnonzero(col == c)
+            for x in range(len(members)):
+                for y in range(x + 1, len(members)):
+                    a, b = sets[members[x]], sets[members[y]]
+                    assert not np.intersect1d(a, b).size
+                    assert not pat[np.ix_(a, b)].any() and not pat[np.ix_(b, a)].any()
+        # first fit: a patch of colour c meets every colour below c among
+        # the earlier patches it conflicts with
+        for i in range(L.np_):
+            if col[i] == 0:
+                continue
+            earlier = [k for k in range(i) if pat[np.ix_(sets[i], sets[k])].any() or pat[np.ix_(sets[k], sets[i])].any()]
+            assert set(range(col[i])) <= set(col[earlier].tolist())
+
+
+def test_colour_at_once_equals_sequential(cube6):
+    prob, d, K, b, blocks, CH = cube6
+    L = CH.levels[0]
+    Kl = L.K()
+    rng = np.random.default_rng(6)
+    bb, x0 = rng.normal(size=Kl.shape[0]), rng.normal(size=Kl.shape[0])
+    seq = vanka.vanka_sweep(L, bb, x0, 0.78, Kl)
+    x = x0.copy()
+    for c in range(L.colour.max() + 1):
+        members = np.flatnonzero(L.colour == c)
+        upd = []
+        for i in members:
+            idx = np.concatenate([L.patches[i], [L.nu + i]])
+            r = bb[idx] - Kl[idx] @ x
+            upd.append((idx, 0.78 * scipy.linalg.lu_solve(L.lu[i], r)))
+        for idx, dx in upd:
+            x[idx] += dx
+    assert np.abs(x - seq).max() <= 1e-12 * np.abs(seq).max()
+
+
+def test_coarse_system_and_two_level_cycle(cube6):
+    *_, CH = cube6
+    L0, L1 = CH.levels[0], CH.levels[1]
+    assert L0.Pu is not None and L0.Pp is not None
+    P = sp.block_diag([L0.Pu, L0.Pp]).toarray()
+    K0 = L0.K().toarray()
+    Kc = P.T @ K0 @ P
+    K1 = L1.K().toarray()
+    assert np.abs(K1 - Kc).max() <= 1e-12 * np.abs(Kc).max()
+    # every nonzero of the dense product is stored
+    assert not ((Kc != 0) & ~_dense_pattern(L1)).any()
+    # two-level cycle without smoothing
+    two = vanka.CoupledHierarchy([L0, vanka.CoupledLevel(L1.Kuu, L1.Kup, L1.Kpu, L1.Kpp)],
+                                 scipy.linalg.lu_factor(K1), None, None)
+    b = np.random.default_rng(7).normal(size=K0.shape[0])
+    z = vanka.vcycle(two, b, vanka.VankaParams(steps=0))
+    ref = P @ np.linalg.solve(K1, P.T @ b)
+    assert np.abs(z - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_identity_transfer_below_the_shorter_hierarchy(cube6):
+    *_, CH = cube6
+    nl = len(CH.levels)
+    lu, lp = len(CH.Hu.levels), len(CH.Hp.levels)
+    assert nl == max(lu, lp)
+    for lev in range(nl - 1):
+        L, Lc = CH.levels[lev], CH.levels[lev + 1]
+        assert (L.Pu is None) == (lev >= lu - 1)
+        assert (L.Pp is None) == (lev >= lp - 1)
+        if L.Pu is None:
+            assert Lc.nu == L.nu and abs(Lc.Kuu - L.Kuu).max() == 0
+        if L.Pp is None:
+            assert Lc.np_ == L.np_ and abs(Lc.Kpp - L.Kpp).max() == 0
+
+
+def test_coupled_amg_solves_the_solid(cube6):
+    prob, d, K, b, blocks, CH = cube6
+    prm = _small_prm()
+    x, hist = vanka.amg_iteration(CH, K, b, prob.n_nodes, prm, tol=1e-8, maxit=40)
+    assert hist[-1] <= 1e-8
+    rate = hist[-1] ** (1.0 / (len(hist) - 1))
+    assert rate < 0.35, hist
+    x2, info = krylov.fgmres(K, vanka.preconditioner(CH, prob.n_nodes, prm), b, m=50, tol=1e-8)
+    assert info.converged and info.iterations <= 12
+    assert np.linalg.norm(b - K @ x2) <= 1e-8 * np.linalg.norm(b)
+
+
+def test_colours_hand_case():
+    """Five patches, each with its own three displacement unknowns and no
+    displacement coupling between patches; only C couples pressures 0-1 and
+    3-4.  Conflicts: {0,1} and {3,4} alone, so first fit gives colours
+    0,1,0,0,1 and a sweep visits patches 0,2,3 then 1,4."""
+    rng = np.random.default_rng(8)
+    npr, per = 5, 3
+    nu = npr * per
+    Kuu = np.zeros((nu, nu))
+    Kpu = np.zeros((npr, nu))
+    for i in range(npr):
+        M = rng.normal(size=(per, per))
+        Kuu[per * i:per * (i + 1), per * i:per * (i + 1)] = M @ M.T + per * np.eye(per)
+        Kpu[i, per * i:per * (i + 1)] = rng.normal(size=per)
+    Kpp = -np.eye(npr)
+    Kpp[0, 1] = Kpp[1, 0] = Kpp[3, 4] = Kpp[4, 3] = 0.2
+    L = _level_of([sp.csr_matrix(B) for B in (Kuu, Kpu.T, Kpu, Kpp)])
+    assert L.colour.tolist() == [0, 1, 0, 0, 1]
+    assert L.order.tolist() == [0, 2, 3, 1, 4]
