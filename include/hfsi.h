@@ -152,6 +152,33 @@ typedef struct {
                                  float32), in [0, 1), 0 = exact Galerkin
                                  (default); a re-set-up keeps the
                                  set-up's sparsified patterns              */
+  int32_t coupled;            /* 0 = AMG on the displacement block inside the
+                                 block preconditioner P_L (eq. lpre, default);
+                                 1 = the paper's own solid AMG (section "AMG
+                                 methods for the mixed problems"): one V-cycle
+                                 on the whole tangent K (eq. globsys) replaces
+                                 P_L.  Transfer P = diag(P_u, P_p), P_u from
+                                 the displacement hierarchy on A, P_p from a
+                                 hierarchy built by the same rules on the
+                                 pressure block C (the shorter one continues
+                                 with the identity), coarse systems P^T K P,
+                                 the coarsest inverted densely (at most 4096
+                                 unknowns); smoother: the multiplicative Vanka
+                                 sweep (eq. locsys, eq. vankasmooth), one patch
+                                 per pressure unknown with the displacement
+                                 unknowns of its B2 row (at most 2048 per
+                                 patch), local LU with partial pivoting, the
+                                 patches visited by first-fit colours (in
+                                 increasing index on the pattern of K between
+                                 patches) and by index within a colour.  Uses
+                                 strength_theta, max_coarse, max_levels, seed,
+                                 interp_kind and p_max for both hierarchies;
+                                 needs interp = 0 and drop_tol = 0; every
+                                 set-up and re-set-up builds it anew (fp64)  */
+  double vanka_omega;         /* relaxation omega of eq. vankasmooth, in (0, 2)
+                                 (the paper: 0.78 Mooney-Rivlin, 0.86 artery) */
+  int32_t vanka_steps;        /* sweeps before and after the coarse correction
+                                 on every level, 0..64 (the paper: 6 or 12)  */
 } hfsi_amg_params;
 
 typedef struct {
@@ -183,7 +210,11 @@ typedef struct {
   int32_t method;       /* 0 = FGMRES(m) (default), 1 = BiCGStab, the
                            paper's Krylov method for the structure
                            sub-problem (right preconditioning; restart
-                           unused)                                         */
+                           unused), 2 = the AMG method as the solver:
+                           x <- x + M^{-1}(b - K x) with the preconditioner
+                           of the last set-up (one V-cycle, normally the
+                           coupled one) until the tolerance; iterations =
+                           V-cycles                                        */
 } hfsi_solve_params;
 
 typedef struct {
@@ -400,8 +431,12 @@ hfsi_status hfsi_amg_setup_csr(hfsi_ctx* ctx, int32_t n, const int32_t* ptr, con
 /* Copy level `level` of the current hierarchy to host buffers.  which: 0 = A
  * (ptr [rows+1], col, val), 1 = P, 2 = strength flags (u8 per A entry, in
  * val_u8), 3 = C/F state (int8 per row in val_u8: +1 C, -1 F), 4 = component
- * per row (int32 in col).  Pass NULL buffers to query sizes in *rows, *cols,
- * *nnz. */
+ * per row (int32 in col).  Of the coupled hierarchy (coupled = 1): 10 = Kuu
+ * (the displacement block A of the level), 11 = Kup (B1^T), 12 = Kpu (B2),
+ * 13 = Kpp (-C), each as CSR; 14 = the Vanka colour of every patch (int32
+ * per pressure unknown in col, the colour count in *cols); 15 = P_u, 16 =
+ * P_p (HFSI_E_ARG where the transfer is the identity or on the coarsest
+ * level).  Pass NULL buffers to query sizes in *rows, *cols, *nnz. */
 hfsi_status hfsi_amg_export(hfsi_ctx* ctx, int32_t level, int32_t which, int32_t* rows, int32_t* cols,
                             int64_t* nnz, int32_t* ptr, int32_t* col, double* val, uint8_t* val_u8);
 
@@ -409,7 +444,9 @@ hfsi_status hfsi_amg_export(hfsi_ctx* ctx, int32_t level, int32_t which, int32_t
  * in the hierarchy's precision (inputs and outputs fp64). */
 hfsi_status hfsi_vcycle(hfsi_ctx* ctx, const double* r, double* z);
 
-/* y = P_L^{-1} r (device [N]) and y = K x (device [N]). */
+/* y = M^{-1} r with the preconditioner of the last set-up (P_L^{-1} of
+ * eq. lpre, or one V-cycle of the coupled hierarchy when it was set up with
+ * coupled = 1) and y = K x (device [N]). */
 hfsi_status hfsi_apply_preconditioner(hfsi_ctx* ctx, const double* r, double* y);
 hfsi_status hfsi_apply_tangent(hfsi_ctx* ctx, const double* x, double* y);
 

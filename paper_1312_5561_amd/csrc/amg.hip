@@ -2028,6 +2028,11 @@ void fill_info(const Hierarchy& H, hfsi_amg_info* info, int rounds, double rho) 
 
 }  // namespace
 
+// C = A B on the structural product pattern (overflow bits into *deferred)
+int sparse_product(hfsi_ctx* c, const Csr<double>& A, const Csr<double>& B, Csr<double>& Cm, int* deferred) {
+  return spgemm(c, A, B, Cm, deferred);
+}
+
 // Build levels 1.. from level 0 (whose A and comp are already set), with no
 // judge: the learned level-0 correction is applied when prm.interp == 1.
 void build_levels(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {
@@ -2247,6 +2252,11 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
 }
 
 void amg_setup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {
+  if (prm.coupled) {
+    vanka_setup(c, prm, info);
+    return;
+  }
+  c->precond_kind = 0;
   Hierarchy& H = c->H;
   HIP_CHECK(hipEventRecord(c->ev0, c->stream));  // set-up time includes the judge
   H.L.clear();
@@ -2278,6 +2288,11 @@ void amg_setup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* in
 // is again the Galerkin product R A P, and the smoother data, coarsest inverse
 // and cycle copies are rebuilt.  No strength, PMIS, interpolation or judge.
 void amg_resetup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {
+  if (prm.coupled) {  // the coupled hierarchy is always built anew
+    vanka_setup(c, prm, info);
+    return;
+  }
+  c->precond_kind = 0;
   Hierarchy& H = c->H;
   hipStream_t s = c->stream;
   if (!H.reusable || H.L.empty() || H.L[0].n != c->A.rows || H.L[0].A.nnz != c->A.nnz)
@@ -2326,6 +2341,13 @@ void check_amg_params(const hfsi_amg_params* p) {
   if (p->interp < 0 || p->interp > 1) fail(HFSI_E_ARG, "amg params: interp must be 0 (classical) or 1 (learned)");
   if (p->judge_classical < 0 || p->judge_classical > 2) fail(HFSI_E_ARG, "amg params: judge_classical in 0..2");
   if (!(p->drop_tol >= 0.0 && p->drop_tol < 1.0)) fail(HFSI_E_ARG, "amg params: drop_tol in [0, 1)");
+  if (p->coupled < 0 || p->coupled > 1) fail(HFSI_E_ARG, "amg params: coupled 0 or 1");
+  if (p->coupled) {
+    if (!(p->vanka_omega > 0.0 && p->vanka_omega < 2.0) || p->vanka_steps < 0 || p->vanka_steps > 64)
+      fail(HFSI_E_ARG, "amg params: vanka_omega in (0, 2), vanka_steps in 0..64");
+    if (p->interp != 0 || p->drop_tol != 0.0)
+      fail(HFSI_E_ARG, "amg params: the coupled hierarchy takes interp 0 and drop_tol 0");
+  }
 }
 
 }  // namespace hfsi
@@ -2354,6 +2376,7 @@ extern "C" hfsi_status hfsi_amg_setup_csr(hfsi_ctx* c, int32_t n, const int32_t*
   HFSI_ABI_BEGIN(c)
   hfsi::check_amg_params(prm);
   if (n <= 0 || !ptr || !col || !val || !comp) fail(HFSI_E_ARG, "amg_setup_csr: bad arguments");
+  if (prm->coupled) fail(HFSI_E_ARG, "amg_setup_csr: the coupled hierarchy needs the assembled tangent");
   if (info && info->struct_size != sizeof(hfsi_amg_info)) fail(HFSI_E_ARG, "amg info: struct_size mismatch");
   const int64_t nnz = ptr[n];
   if (ptr[0] != 0 || nnz < n) fail(HFSI_E_ARG, "amg_setup_csr: bad row pointer");
@@ -2364,6 +2387,7 @@ extern "C" hfsi_status hfsi_amg_setup_csr(hfsi_ctx* c, int32_t n, const int32_t*
       if (e > ptr[i] && col[e] <= col[e - 1]) fail(HFSI_E_ARG, "amg_setup_csr: columns not strictly ascending");
     }
   }
+  c->precond_kind = 0;
   hfsi::Hierarchy& H = c->H;
   H.L.clear();
   H.L.emplace_back();
@@ -2385,6 +2409,10 @@ extern "C" hfsi_status hfsi_amg_setup_csr(hfsi_ctx* c, int32_t n, const int32_t*
 extern "C" hfsi_status hfsi_amg_export(hfsi_ctx* c, int32_t level, int32_t which, int32_t* rows, int32_t* cols,
                                        int64_t* nnz, int32_t* ptr, int32_t* col, double* val, uint8_t* val_u8) {
   HFSI_ABI_BEGIN(c)
+  if (which >= 10) {
+    hfsi::vanka_export(c, level, which, rows, cols, nnz, ptr, col, val);
+    return HFSI_OK;
+  }
   hfsi::Hierarchy& H = c->H;
   if (!H.ready) fail(HFSI_E_ORDER, "amg_export: no hierarchy");
   if (level < 0 || level >= (int)H.L.size()) fail(HFSI_E_ARG, "amg_export: level out of range");

@@ -608,6 +608,7 @@ extern "C" hfsi_status hfsi_assemble_residual_tangent(hfsi_ctx* c, const double*
   hfsi::assemble(c, v, load, R, info);
   c->stage = 4;
   c->H.ready = false;
+  hfsi::vanka_invalidate(c);
   if (K) {
     K->n_block_rows = c->n;
     K->n_blocks = c->nb;

@@ -285,6 +285,8 @@ struct hfsi_ctx {
   hfsi::DevBuf<double> scal;     // device scalars
   hfsi::DevBuf<int> iscal;       // device integer scalars
   void* mlp_impl = nullptr;      // learned-interpolation state (mlp.hip)
+  void* vanka_impl = nullptr;    // coupled (u,p) AMG with the Vanka smoother (vanka.hip)
+  int precond_kind = 0;          // preconditioner of the last set-up: 0 P_L, 1 coupled V-cycle
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t kev[2] = {nullptr, nullptr};  // FGMRES scalar read-back slots
   hipStream_t aux = nullptr;               // AMG set-up work off the critical path
@@ -328,6 +330,13 @@ void fgmres_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_para
 void bicgstab_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_params& prm, hfsi_solve_info* info);
 void krylov_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_params& prm, hfsi_solve_info* info);
 double mass_norm(hfsi_ctx* c, const double* dv);
+// coupled (u,p) AMG with the multiplicative Vanka smoother (vanka.hip)
+void vanka_setup(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info);
+void vanka_precond(hfsi_ctx* c, const double* r, double* z, const double* scale, double* rs);
+void vanka_invalidate(hfsi_ctx* c);
+void vanka_free(hfsi_ctx* c);
+void vanka_export(hfsi_ctx* c, int level, int which, int32_t* rows, int32_t* cols, int64_t* nnz, int32_t* ptr,
+                  int32_t* col, double* val);
 // resolve the allocation-free entry point's scratch address on `device`
 // (the current device); called once per context creation
 void noalloc_scratch_init(int device);

@@ -227,7 +227,7 @@ void colour_elements(int n, int m, const int32_t* tets, std::vector<int>& perm, 
 
 // ================================================================== ABI
 
-extern "C" int32_t hfsi_abi_version(void) { return 5; }
+extern "C" int32_t hfsi_abi_version(void) { return 6; }
 
 namespace {
 std::atomic<int> g_live_contexts{0};  // the device block cache is trimmed when none is left
@@ -292,6 +292,7 @@ extern "C" hfsi_status hfsi_destroy(hfsi_ctx* c) {
   hfsi::tls_idle = true;
   release_events(c);
   hfsi::mlp_free(c);
+  hfsi::vanka_free(c);
   delete c;
   hfsi::tls_idle = false;
   if (--g_live_contexts == 0) hfsi::dev_cache_trim();
@@ -319,6 +320,7 @@ extern "C" hfsi_status hfsi_set_mesh(hfsi_ctx* c, int64_t n_nodes, const double*
   c->m = m;
   c->stage = 0;
   c->H.ready = false;
+  hfsi::vanka_invalidate(c);
   c->H.reusable = false;
   c->nm_rho = 0.0;  // a new mesh starts quasi-static
   c->cm = 0.0;
@@ -478,6 +480,7 @@ extern "C" hfsi_status hfsi_set_bc(hfsi_ctx* c, const uint8_t* dir_mask, int64_t
   c->stage = 3;
   c->judge.valid = false;
   c->H.ready = false;
+  hfsi::vanka_invalidate(c);
   c->H.reusable = false;
   HFSI_ABI_END(c)
 }

@@ -927,6 +927,10 @@ void vcycle_apply(hfsi_ctx* c, const double* r, double* z) {
 }
 
 void precond_apply(hfsi_ctx* c, const double* r, double* z, const double* scale, double* rs) {
+  if (c->precond_kind == 1) {
+    vanka_precond(c, r, z, scale, rs);
+    return;
+  }
   Hierarchy& H = c->H;
   if (!H.ready) fail(HFSI_E_ORDER, "preconditioner: no AMG hierarchy");
   Level& L0 = H.L[0];
@@ -1329,8 +1333,54 @@ void bicgstab_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_pa
   if (breakdown && !converged) fail(HFSI_E_BREAKDOWN, "BiCGStab breakdown before convergence");
 }
 
+// The AMG method as the solver (section "AMG methods for the mixed
+// problems"): x <- x + M^{-1} (b - K x) with M^{-1} the preconditioner of the
+// last set-up (one V-cycle), until ||b - K x||_2 <= tol ||b||_2 or max_iter
+// applications.  iterations = applications of M^{-1}.
+void amg_iteration_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_params& prm,
+                         hfsi_solve_info* info) {
+  const long N = 4L * c->n;
+  hipStream_t s = c->stream;
+  c->kr.ensure(N);
+  c->kw.ensure(N);
+  c->scal.ensure(16);
+  c->kred.ensure(2 * RED_BLOCKS);
+  HIP_CHECK(hipEventRecord(c->ev0, s));
+  norm_dev(c, b, N, c->scal.p + 8);
+  const double bn = read_scalar(c, c->scal.p + 8);
+  info->iterations = 0;
+  info->restarts = 0;
+  info->breakdown = 0;
+  info->converged = 0;
+  if (bn == 0.0) {
+    HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * N, s));
+    info->rel_residual = 0.0;
+    info->converged = 1;
+  } else {
+    for (int it = 0;; ++it) {
+      residual(c, b, x, c->kr.p);
+      norm_dev(c, c->kr.p, N, c->scal.p + 9);
+      const double rn = read_scalar(c, c->scal.p + 9);
+      if (!std::isfinite(rn)) fail(HFSI_E_NAN, "amg iteration: non-finite residual");
+      info->rel_residual = rn / bn;
+      if (rn <= prm.tol * bn) {
+        info->converged = 1;
+        break;
+      }
+      if (it == prm.max_iter) break;
+      precond_apply(c, c->kr.p, c->kw.p);
+      k_axpy<<<div_up(N, 256), 256, 0, s>>>(N, 1.0, c->kw.p, x);
+      HIP_LAUNCH_CHECK();
+      info->iterations = it + 1;
+    }
+  }
+  HIP_CHECK(hipEventRecord(c->ev1, s));
+  info->seconds = elapsed_ms(c) * 1e-3;
+}
+
 void krylov_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_params& prm, hfsi_solve_info* info) {
   if (prm.method == 1) bicgstab_solve(c, b, x, prm, info);
+  else if (prm.method == 2) amg_iteration_solve(c, b, x, prm, info);
   else fgmres_solve(c, b, x, prm, info);
 }
 
@@ -1341,7 +1391,8 @@ void check_solve_params(const hfsi_solve_params* p) {
   if (!p || p->struct_size != sizeof(hfsi_solve_params)) fail(HFSI_E_ARG, "solve params: struct_size mismatch");
   if (!(p->tol > 0) || p->restart < 1 || p->restart > 256 || p->max_iter < 1)
     fail(HFSI_E_ARG, "solve params: need tol > 0, 1 <= restart <= 256, max_iter >= 1");
-  if (p->method < 0 || p->method > 1) fail(HFSI_E_ARG, "solve params: method 0 (FGMRES) or 1 (BiCGStab)");
+  if (p->method < 0 || p->method > 2)
+    fail(HFSI_E_ARG, "solve params: method 0 (FGMRES), 1 (BiCGStab) or 2 (AMG iteration)");
 }
 }  // namespace
 

@@ -61,6 +61,9 @@ static hfsi_newton_solve_params default_params(int adaptive, int learned) {
   a->nu_pre_coarse = 0;
   a->judge_classical = 2;
   a->drop_tol = 0.0;
+  a->coupled = 0;
+  a->vanka_omega = 0.78;
+  a->vanka_steps = 6;
   s->struct_size = sizeof *s;
   s->tol = 1e-8;
   s->restart = 50;

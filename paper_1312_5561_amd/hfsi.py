@@ -49,7 +49,8 @@ class AmgParams(C.Structure):
                 ("fallback_rho", C.c_double), ("cheb_degree", C.c_int32), ("cheb_ratio", C.c_double),
                 ("interp_kind", C.c_int32), ("p_max", C.c_int32), ("cheb_degree_pre", C.c_int32),
                 ("nu_post_coarse", C.c_int32), ("cheb_degree_coarse", C.c_int32), ("nu_pre_coarse", C.c_int32),
-                ("judge_classical", C.c_int32), ("drop_tol", C.c_double)]
+                ("judge_classical", C.c_int32), ("drop_tol", C.c_double), ("coupled", C.c_int32),
+                ("vanka_omega", C.c_double), ("vanka_steps", C.c_int32)]
 
 
 class AmgInfo(C.Structure):
@@ -115,19 +116,23 @@ def train_params(batch=1024, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
 def amg_params(theta=0.15, max_coarse=500, max_levels=25, seed=12345, smoother=1, nu_pre=1, nu_post=1,
                precision=0, interp=0, fallback_rho=0.5, cheb_degree=3, cheb_ratio=30.0, interp_kind=1, p_max=4,
                cheb_degree_pre=1, nu_post_coarse=1, cheb_degree_coarse=3, nu_pre_coarse=0, judge_classical=2,
-               drop_tol=0.0):
+               drop_tol=0.0, coupled=0, vanka_omega=0.78, vanka_steps=6):
     """judge_classical (learned interpolation): 0 threshold only, 1 compare
     with the classical factor on every set-up, 2 on the first set-up of a
     problem and weight set (verdict kept).  drop_tol: coarse operators lose
     their off-diagonal entries below drop_tol sqrt(|a_ii a_jj|) (0: exact
-    Galerkin)."""
+    Galerkin).  coupled=1: the coupled (u,p) AMG with the multiplicative
+    Vanka smoother (relaxation vanka_omega, vanka_steps sweeps before and
+    after the coarse correction) replaces P_L."""
     return AmgParams(C.sizeof(AmgParams), theta, max_coarse, max_levels, seed, smoother, nu_pre, nu_post,
                      precision, interp, fallback_rho, cheb_degree, cheb_ratio, interp_kind, p_max, cheb_degree_pre,
-                     nu_post_coarse, cheb_degree_coarse, nu_pre_coarse, judge_classical, drop_tol)
+                     nu_post_coarse, cheb_degree_coarse, nu_pre_coarse, judge_classical, drop_tol, coupled,
+                     vanka_omega, vanka_steps)
 
 
 def solve_params(tol=1e-8, restart=50, max_iter=500, method=0):
-    """method: 0 FGMRES(restart), 1 BiCGStab."""
+    """method: 0 FGMRES(restart), 1 BiCGStab, 2 the AMG method as the
+    solver (one V-cycle per iteration)."""
     return SolveParams(C.sizeof(SolveParams), tol, restart, max_iter, method)
 
 
@@ -353,13 +358,20 @@ class Context:
 
     # ---- inspection
     def amg_export(self, level, which):
-        """Level data as numpy: which 0 -> (ptr, col, val) of A, 1 -> P,
-        2 -> strength flags, 3 -> C/F state, 4 -> components."""
+        """Level data as numpy: which 0 -> (ptr, col, val, cols) of A, 1 -> P,
+        2 -> strength flags, 3 -> C/F state, 4 -> components; of the coupled
+        hierarchy 10..13 -> Kuu, Kup, Kpu, Kpp and 15, 16 -> P_u, P_p as
+        (ptr, col, val, cols), 14 -> (patch colours, colour count)."""
         rows, cols, nnz = C.c_int32(), C.c_int32(), C.c_int64()
         self._check(self.lib.hfsi_amg_export(self.h, level, which, C.byref(rows), C.byref(cols), C.byref(nnz),
                                              None, None, None, None))
         r, k = rows.value, nnz.value
-        if which in (0, 1):
+        if which == 14:
+            col = np.zeros(max(k, 1), np.int32)
+            self._check(self.lib.hfsi_amg_export(self.h, level, which, C.byref(rows), C.byref(cols), C.byref(nnz),
+                                                 None, _ptr(col), None, None))
+            return col[:k], cols.value
+        if which in (0, 1, 10, 11, 12, 13, 15, 16):
             ptr = np.zeros(r + 1, np.int32)
             col = np.zeros(max(k, 1), np.int32)
             val = np.zeros(max(k, 1), np.float64)
