@@ -296,24 +296,45 @@ __global__ void k_vk_colour_resid(int t0, int t1, const int* __restrict__ crow, 
 }
 
 // Then the local solves (eq. locsys) with the patches' inverses and the
-// relaxed updates (eq. vankasmooth): one 256-thread block per patch of the
-// colour (patches q0 .. q0 + gridDim.x - 1 of the sweep order, whose rows
-// start at roff[q]).  Dynamic LDS: mmax doubles.
-__global__ void __launch_bounds__(256) k_vk_colour_solve(int q0, const int* __restrict__ clist,
+// relaxed updates (eq. vankasmooth).  Block (p, k) of the launch takes rows
+// 64k .. 64k+63 of the local solve of patch q0 + p (whose rows start at
+// roff[q]); its four wavefronts split the columns of the inverse and add
+// their partial sums in LDS.  Dynamic LDS: mmax + 256 doubles.
+__global__ void __launch_bounds__(256) k_vk_colour_solve(int q0, int chunks, const int* __restrict__ clist,
                                                          const int* __restrict__ roff, const int* __restrict__ crow,
                                                          const double* __restrict__ rr,
                                                          const int64_t* __restrict__ luoff,
                                                          const double* __restrict__ inv, double* __restrict__ x,
                                                          double omega) {
-  extern __shared__ double r[];
-  const int q = q0 + blockIdx.x, tid = threadIdx.x;
+  extern __shared__ double sh[];
+  const int q = q0 + blockIdx.x / chunks, a0 = 64 * (blockIdx.x % chunks);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i = clist[q], r0 = roff[q], m = roff[q + 1] - r0;
-  for (int a = tid; a < m; a += 256) r[a] = rr[r0 + a];
+  if (a0 >= m) return;  // the whole block leaves
+  double* r = sh;
+  double* part = sh + m;
+  for (int t = tid; t < m; t += 256) r[t] = rr[r0 + t];
   __syncthreads();
   const double* Y = inv + luoff[i];
-  for (int a = tid; a < m; a += 256) {
-    double d = 0.0;
-    for (int t = 0; t < m; ++t) d += Y[(size_t)t * m + a] * r[t];
+  const int a = a0 + lane;
+  const int t0 = (w * m) >> 2, t1 = ((w + 1) * m) >> 2;
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+  if (a < m) {
+    int t = t0;
+    for (; t + 4 <= t1; t += 4) {
+      const double y0 = Y[(size_t)t * m + a], y1 = Y[(size_t)(t + 1) * m + a];
+      const double y2 = Y[(size_t)(t + 2) * m + a], y3 = Y[(size_t)(t + 3) * m + a];
+      d0 += y0 * r[t];
+      d1 += y1 * r[t + 1];
+      d2 += y2 * r[t + 2];
+      d3 += y3 * r[t + 3];
+    }
+    for (; t < t1; ++t) d0 += Y[(size_t)t * m + a] * r[t];
+  }
+  part[tid] = (d0 + d1) + (d2 + d3);
+  __syncthreads();
+  if (w == 0 && a < m) {
+    const double d = (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]);
     x[crow[r0 + a]] += omega * d;
   }
 }
@@ -639,15 +660,16 @@ void vanka_level_data(hfsi_ctx* c, VkLevel& V, int* singular) {
 
 template <int G>
 void sweep_g(hipStream_t s, VkLevel& V, const double* b, double* x, double omega) {
-  const size_t lds = sizeof(double) * V.mmax;
+  const size_t lds = sizeof(double) * (V.mmax + 256);
+  const int chunks = div_up(V.mmax, 64);
   for (size_t k = 0; k + 1 < V.cptr.size(); ++k) {
     const int q0 = V.cptr[k], q1 = V.cptr[k + 1];
     if (q1 == q0) continue;
     const int t0 = V.hroff[q0], t1 = V.hroff[q1];
     k_vk_colour_resid<G><<<div_up((long)(t1 - t0) * G, 256), 256, 0, s>>>(t0, t1, V.crow.p, V.nu, VK_BLOCKS(V), b, x,
                                                                           V.rr.p);
-    k_vk_colour_solve<<<q1 - q0, 256, lds, s>>>(q0, V.clist.p, V.roff.p, V.crow.p, V.rr.p, V.luoff.p, V.inv.p, x,
-                                                omega);
+    k_vk_colour_solve<<<(q1 - q0) * chunks, 256, lds, s>>>(q0, chunks, V.clist.p, V.roff.p, V.crow.p, V.rr.p,
+                                                           V.luoff.p, V.inv.p, x, omega);
   }
   HIP_LAUNCH_CHECK();
 }
