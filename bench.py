@@ -65,7 +65,10 @@ def parse():
                     help="learned interpolation judge: 0 threshold only, 1 vs classical every set-up, "
                          "2 vs classical once per problem")
     ap.add_argument("--quick", action="store_true",
-                    help="headline legs only (no reuse, load-run, dynamics or sequence legs)")
+                    help="headline legs only (no reuse, load-run, dynamics, sequence or Vanka legs)")
+    ap.add_argument("--vanka-N", type=int, default=48,
+                    help="cube size of the coupled-AMG / Vanka comparator leg (0: skip)")
+    ap.add_argument("--vanka-steps", type=int, default=6, help="Vanka sweeps before and after the correction")
     args = ap.parse_args()
     if args.kappa is None:
         args.kappa = 1e4 if args.workload == "cube" else 1e5
@@ -206,6 +209,60 @@ def cpu_baseline(workload="cube", kappa=1e4, reps=3):
                       f"(the scipy sparse products, the element kernels and the set-up loops run on one thread); "
                       f"host: {threads} threads, {model}",
             "host_threads": threads, "host_cpu_model": model, "runs": runs}
+
+
+def vanka_leg(N, steps, kappa, torch, hfsi):
+    """The paper's own solid AMG (coupled (u,p) hierarchy, multiplicative
+    Vanka smoother, omega = 0.78) against the block preconditioner P_L on one
+    Newton system: the N^3 cube at load 1.0 from the converged load-0.8
+    state.  Each solver from x = 0 to ||b - K x|| <= 1e-8 ||b||: FGMRES with
+    the coupled V-cycle, the AMG method itself (V-cycles as the iteration),
+    and FGMRES with P_L (fp64 and fp32 cycles)."""
+    import synth
+    prob = synth.cube_problem(N, kappa=kappa)
+    ctx = hfsi.Context(0)
+    ctx.set_problem(prob)
+    v = torch.zeros(prob.n_dofs, dtype=torch.float64, device="cuda")
+    p_c = hfsi.newton_params(amg=hfsi.amg_params(precision=1), solve=hfsi.solve_params(tol=1e-8, restart=256,
+                                                                                     max_iter=3000))
+    for k in range(1, 5):
+        _, code = ctx.newton_solve(v, k / 5, hfsi.newton_solve_params(step=p_c))
+        if code != 0:
+            raise RuntimeError(f"Vanka leg: load increment {k} did not converge")
+    R = torch.zeros_like(v)
+    ctx.assemble_residual_tangent(v, 1.0, R)
+    b = -R
+    out = {"workload": f"cube{N} Mooney-Rivlin kappa={kappa:g}, Newton system at load 1.0 from the converged "
+                       f"0.8 state ({prob.n_dofs} dofs)", "dofs": prob.n_dofs}
+
+    def solve(prm, label):
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        si, code = ctx.krylov_amg_solve(b, x, prm)
+        torch.cuda.synchronize()
+        out[label] = {"iterations": si.iterations, "seconds": time.perf_counter() - t0,
+                      "rel_residual": si.rel_residual, "converged": bool(si.converged)}
+
+    g = hfsi.amg_params(coupled=1, vanka_omega=0.78, vanka_steps=steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ai = ctx.amg_setup(g)
+    torch.cuda.synchronize()
+    out["coupled_setup"] = {"seconds": time.perf_counter() - t0, "levels": ai.levels,
+                            "rows": list(ai.rows[:ai.levels]), "vanka_steps": steps, "omega": 0.78,
+                            "colours": [ctx.amg_export(lev, 14)[1] for lev in range(ai.levels - 1)]}
+    solve(hfsi.solve_params(tol=1e-8, restart=100, max_iter=300), "coupled_fgmres")
+    solve(hfsi.solve_params(tol=1e-8, max_iter=200, method=2), "coupled_amg_iteration")
+    for prec in (0, 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ai = ctx.amg_setup(hfsi.amg_params(precision=prec))
+        torch.cuda.synchronize()
+        out[f"pl_setup_fp{64 if prec == 0 else 32}"] = {"seconds": time.perf_counter() - t0}
+        solve(hfsi.solve_params(tol=1e-8, restart=256, max_iter=3000), f"pl_fgmres_fp{64 if prec == 0 else 32}")
+    ctx.close()
+    return out
 
 
 def main():
@@ -427,6 +484,13 @@ def main():
                       file=sys.stderr, flush=True)
             ctx.set_newmark(0.0)
             res["fsi_solid_sequence"] = seq
+    if not args.quick and args.vanka_N > 0 and args.workload == "cube":
+        res["coupled_vanka"] = vanka_leg(args.vanka_N, args.vanka_steps, args.kappa, torch, hfsi)
+        cv = res["coupled_vanka"]
+        print(f"[bench] coupled Vanka AMG at {args.vanka_N}^3: FGMRES {cv['coupled_fgmres']['iterations']} its "
+              f"{cv['coupled_fgmres']['seconds']:.2f} s, AMG iteration {cv['coupled_amg_iteration']['iterations']} "
+              f"its; P_L fp32 FGMRES {cv['pl_fgmres_fp32']['iterations']} its "
+              f"{cv['pl_fgmres_fp32']['seconds'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
     # the headline state's tangent for the roofline timing
     v.copy_(v0)
     R0 = torch.zeros_like(v)
