@@ -6,6 +6,15 @@ relative residual eps_1, update v_{k+1} = v_k + dv and stop when
 M = diag(M1, M2)).  Loads are applied in increments lambda = k / n_inc,
 each starting from the previous converged state.
 
+The relative rule has no meaning when its reference ||dv_0||_M is itself
+rounding noise: an increment (or time step) that starts at a solution (a
+time step from an equilibrium at rest, for instance) has a first correction
+at the fp64 rounding level of the state, and no later correction can be a
+further factor eps_2 smaller.  Reading: the increment is converged after its
+first correction, taken whole, when ||dv_0||_M <= FLOOR ||v_0||_M, with
+FLOOR = 1e-14 (a hundred times the unit roundoff) and v_0 the starting
+state.
+
 Adaptive inner tolerance (the inexact-Newton analysis of the same section):
 the inner reduction of step k is the square of the outer reduction reached
 at step k-1, eps_1,k = eps_2,k-1^2, read here with the relative outer
@@ -29,6 +38,9 @@ import dataclasses
 import numpy as np
 
 from . import amg, fe, krylov
+
+
+FLOOR = 1e-14
 
 
 @dataclasses.dataclass
@@ -106,6 +118,7 @@ def damped_step(disc, v, dv, load, r0, prm: NewtonParams):
 
 def solve_increment(disc, v, load, prm: NewtonParams, log=None):
     v = v.ravel().copy()
+    floor = FLOOR * disc.mass_norm(v)
     n0 = None
     nrm = None
     for k in range(prm.max_iter):
@@ -115,8 +128,10 @@ def solve_increment(disc, v, load, prm: NewtonParams, log=None):
         alpha = 1.0
         # a correction that already meets the stopping rule is taken whole
         # (near the solution the residual sits at its rounding floor and
-        # cannot show the Armijo decrease)
-        small = n0 is not None and nrm <= prm.eps2 * n0
+        # cannot show the Armijo decrease); so is a first correction at the
+        # rounding level of the starting state
+        at_floor = n0 is None and nrm <= floor
+        small = at_floor or (n0 is not None and nrm <= prm.eps2 * n0)
         if prm.line_search and not small:
             alpha = damped_step(disc, v, dv, load, r0, prm)
             if alpha is None:
@@ -125,6 +140,8 @@ def solve_increment(disc, v, load, prm: NewtonParams, log=None):
         if log is not None:
             log.append(dict(load=load, it=k, dv_M=nrm, krylov=info.iterations,
                             rel_res=info.rel_residual, eps1=tol, alpha=alpha))
+        if at_floor:
+            return v, True, k + 1
         if n0 is None:
             n0 = nrm
         if (nrm <= prm.eps2 * n0 or n0 == 0.0) and alpha == 1.0:

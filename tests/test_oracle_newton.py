@@ -186,3 +186,36 @@ def test_residual_norm_rejects_inverted_states():
     v[:, 0] = -2.0 * prob.X[:, 0]          # x -> -x: every element inverted
     assert newton.residual_norm(d, v.ravel(), 0.0) == np.inf
     assert np.isfinite(newton.residual_norm(d, np.zeros(prob.n_dofs), 1.0))
+
+
+def test_time_step_from_equilibrium_is_converged_at_the_floor():
+    """A Newmark step from a static equilibrium at rest (zero velocity and
+    acceleration) has the equilibrium itself as its solution: the first
+    Newton correction is rounding noise (about 1e-16 of the state), and the
+    relative rule ||dv_k|| <= eps2 ||dv_0|| could never be met.  The floor
+    reading ends the step after that first correction; without it Newton
+    runs to its iteration limit (checked by lowering the floor to zero)."""
+    from oracle import newmark
+    prob = synth.cube_problem(4)
+    d = fe.Discretization(prob)
+    v, ok, _ = newton.solve_increment(d, np.zeros(prob.n_dofs), 1.0, newton.NewtonParams())
+    assert ok
+    n = prob.n_nodes
+    nm = newmark.NewmarkParams(rho=1.0, dt=0.05)
+    zero = np.zeros((n, 3))
+    prm = newton.NewtonParams(eps2=1e-10, max_iter=6, lin_tol=1e-12)
+    v1, vel, acc, its = newmark.time_step(d, v, 1.0, nm, prm, zero, zero)
+    assert its == 1
+    assert np.abs(v1 - v).max() <= 1e-13 * np.abs(v).max()
+    assert np.abs(vel).max() <= 1e-8 and np.abs(acc).max() <= 1e-6
+    saved = newton.FLOOR
+    try:
+        newton.FLOOR = 0.0
+        with pytest.raises(RuntimeError):
+            newmark.time_step(d, v, 1.0, nm, prm, zero, zero)
+    finally:
+        newton.FLOOR = saved
+    # a step that moves is not cut short: from rest under the full load the
+    # first correction is large and the relative rule decides
+    v2, _, _, its2 = newmark.time_step(d, np.zeros(prob.n_dofs), 1.0, nm, prm, zero, zero)
+    assert its2 >= 3
