@@ -402,7 +402,10 @@ hfsi_status hfsi_newton_step(hfsi_ctx* ctx, double* v, double load, const hfsi_n
  * place): iterations of hfsi_newton_step until eq. newstop holds in the
  * relative form ||dv_k||_M <= eps2 ||dv_0||_M, with a fixed or an adaptive
  * inner tolerance (Section "Newton's Method"; see
- * hfsi_newton_solve_params).  An iteration whose linear solve stops at
+ * hfsi_newton_solve_params).  A first correction at the rounding level of
+ * the starting state, ||dv_0||_M <= 1e-14 ||v_0||_M (a time step from an
+ * equilibrium at rest, say), is taken whole and ends the increment: the
+ * relative rule has no usable reference then.  An iteration whose linear solve stops at
  * step.solve.max_iter is kept (inexact Newton).  HFSI_NOT_CONVERGED when
  * max_newton iterations do not meet the criterion. */
 hfsi_status hfsi_newton_solve(hfsi_ctx* ctx, double* v, double load, const hfsi_newton_solve_params* prm,
@@ -535,6 +538,12 @@ hfsi_status hfsi_mlp_loss_grad(hfsi_ctx* ctx, int32_t m, const float* X, const f
  * classical weights and the local ideal-interpolation target.  *n_failed
  * counts samples whose local system was singular or too large (target 0). */
 hfsi_status hfsi_mlp_collect(hfsi_ctx* ctx, int32_t* n_added, int32_t* n_failed);
+/* The same for a seeded subset (large meshes): the sample of level-0 row r
+ * is kept when the top 53 bits of SplitMix64 output r of the stream `seed`,
+ * divided by 2^53, are below `fraction` (in (0, 1], else HFSI_E_ARG); the
+ * kept samples are appended in increasing row order. */
+hfsi_status hfsi_mlp_collect_sampled(hfsi_ctx* ctx, double fraction, uint64_t seed, int32_t* n_added,
+                                     int32_t* n_failed);
 hfsi_status hfsi_mlp_clear(hfsi_ctx* ctx);
 /* Copy rows [first, first+count) of the training set to host arrays (any may
  * be NULL); *total receives the set size. */

@@ -65,13 +65,6 @@ k_lambda(int n, const int* __restrict__ ptr, const int* __restrict__ col, const 
     if (strong[e]) atomicAdd(&lam[col[e]], 1);
 }
 
-__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
-  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
 __global__ void k_pmis_init(int n, const int* __restrict__ lam, uint64_t seed, int level, uint64_t* __restrict__ key,
                             int8_t* __restrict__ state) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;

@@ -118,6 +118,15 @@ struct DevBuf {
 
 inline int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 
+// Output k of the SplitMix64 stream seeded with `seed` (Steele, Lea & Flood,
+// OOPSLA 2014): mix(seed + (k + 1) * 0x9E3779B97F4A7C15).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
 // Lanes per row of the padded CSR layout: 3 to 6 chunks per lane (8 lanes
 // for the 25-35 chunks of the first coarse levels measured fastest), more
 // lanes on small levels so that the launch still spreads over the whole chip.

@@ -340,35 +340,80 @@ __global__ void k_mask_count(int B, const int* __restrict__ idx, const float* __
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-// dW[k][j] = sum_b act[b][k] * d[b][j]  (act bf16, ldd = J); grid covers K*J
-__global__ void k_wgrad(int B, int K, int J, const uint16_t* __restrict__ act, const float* __restrict__ d,
-                        float* __restrict__ dW) {
+// Backward products on the fp32 MFMA v_mfma_f32_16x16x4_f32 (the bf16
+// activations and weights are exact in fp32, the gradients stay fp32): lane l
+// holds A[l%16][l/16] and B[l/16][l%16], D[4(l/16)+v][l%16] (v = 0..3), the
+// layout of the bf16 16x16x32 instruction of the forward pass.
+//
+// dW[k][j] = sum_b act[b][k] d[b][j] (act bf16 with row stride NIN, d with
+// row stride J): one wavefront per 16x16 tile of dW and per slice of the
+// minibatch; the slices' partial tiles go to part[slice][K*J].
+__global__ void __launch_bounds__(64) k_wgrad_mfma(int B, int K, int J, int slices, const uint16_t* __restrict__ act,
+                                                   const float* __restrict__ d, float* __restrict__ part) {
+  const int tj = J / 16, tiles = (K / 16) * tj;
+  const int tile = blockIdx.x % tiles, sl = blockIdx.x / tiles;
+  const int kt = tile / tj, jt = tile % tj;
+  const int lane = threadIdx.x, lr = lane & 15, lg = lane >> 4;
+  const int per = ((B + slices - 1) / slices + 3) / 4 * 4;
+  const int b_begin = sl * per, b_end = min(B, b_begin + per);
+  v4f acc = {0.f, 0.f, 0.f, 0.f};
+  for (int b0 = b_begin; b0 < b_end; b0 += 4) {
+    const int b = b0 + lg;
+    float a = 0.f, bb = 0.f;
+    if (b < b_end) {
+      a = bf2f(act[(size_t)b * NIN + 16 * kt + lr]);
+      bb = d[(size_t)b * J + 16 * jt + lr];
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bb, acc, 0, 0, 0);
+  }
+  float* P = part + (size_t)sl * K * J;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) P[(16 * kt + 4 * lg + v) * J + 16 * jt + lr] = acc[v];
+}
+
+// dW[t] = sum over slices of part[slice][t], in slice order
+__global__ void k_wgrad_sum(int n, int slices, const float* __restrict__ part, float* __restrict__ dW) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= K * J) return;
-  const int k = t / J, j = t % J;
+  if (t >= n) return;
   float s = 0.f;
-  for (int b = 0; b < B; ++b) s += bf2f(act[(size_t)b * NIN + k]) * d[(size_t)b * J + j];
+  for (int k = 0; k < slices; ++k) s += part[(size_t)k * n + t];
   dW[t] = s;
 }
 
-__global__ void k_bgrad(int B, int J, const float* __restrict__ d, float* __restrict__ db) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= J) return;
+// db[j] = sum_b d[b][j]: one 256-thread block per j
+__global__ void __launch_bounds__(256) k_bgrad(int B, int J, const float* __restrict__ d, float* __restrict__ db) {
+  __shared__ float sh[256];
+  const int j = blockIdx.x;
   float s = 0.f;
-  for (int b = 0; b < B; ++b) s += d[(size_t)b * J + j];
-  db[j] = s;
+  for (int b = threadIdx.x; b < B; b += 256) s += d[(size_t)b * J + j];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) db[j] = sh[0];
 }
 
-// dh[b][k] = (sum_j d[b][j] W[k][j]) * (act[b][k] > 0), W in bf16
-__global__ void k_hgrad(int B, int J, const float* __restrict__ d, const uint16_t* __restrict__ Wl,
-                        const uint16_t* __restrict__ act, float* __restrict__ dh) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= B * NH) return;
-  const int b = t / NH, k = t % NH;
-  if (!(bf2f(act[(size_t)b * NIN + k]) > 0.f)) { dh[t] = 0.f; return; }
-  float s = 0.f;
-  for (int j = 0; j < J; ++j) s += d[(size_t)b * J + j] * bf2f(Wl[k * J + j]);
-  dh[t] = s;
+// dh[b][k] = (sum_j d[b][j] W[k][j]) * (act[b][k] > 0), W bf16 [NH][J]: one
+// wavefront per 16 samples x 16 hidden units
+__global__ void __launch_bounds__(64) k_hgrad_mfma(int B, int J, const float* __restrict__ d,
+                                                   const uint16_t* __restrict__ Wl, const uint16_t* __restrict__ act,
+                                                   float* __restrict__ dh) {
+  const int kt = blockIdx.x % (NH / 16), bt = blockIdx.x / (NH / 16);
+  const int lane = threadIdx.x, lr = lane & 15, lg = lane >> 4;
+  const int ba = 16 * bt + lr;
+  v4f acc = {0.f, 0.f, 0.f, 0.f};
+  for (int j0 = 0; j0 < J; j0 += 4) {
+    const float a = ba < B ? d[(size_t)ba * J + j0 + lg] : 0.f;
+    const float bb = bf2f(Wl[(16 * kt + lr) * J + j0 + lg]);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bb, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int b = 16 * bt + 4 * lg + v, k = 16 * kt + lr;
+    if (b < B) dh[(size_t)b * NH + k] = bf2f(act[(size_t)b * NIN + k]) > 0.f ? acc[v] : 0.f;
+  }
 }
 
 __global__ void k_adam(int n, const float* __restrict__ g, float* __restrict__ w, float* __restrict__ m,
@@ -646,14 +691,23 @@ static double loss_grad(hfsi_ctx* c, MlpState& S, int B, const int* idx, DevBuf<
   float* g = S.grad.p;
   const uint16_t* W2 = S.wb.p + NIN * NH;
   const uint16_t* W3 = S.wb.p + NIN * NH + NH * NH;
-  k_wgrad<<<div_up(NH * NOUTP, 256), 256, 0, s>>>(B, NH, NOUTP, h2, dout, g + OFF_W3);
-  k_bgrad<<<1, 64, 0, s>>>(B, NOUTP, dout, g + OFF_B3);
-  k_hgrad<<<div_up((long)B * NH, 256), 256, 0, s>>>(B, NOUTP, dout, W3, h2, dh2);
-  k_wgrad<<<div_up(NH * NH, 256), 256, 0, s>>>(B, NH, NH, h1, dh2, g + OFF_W2);
-  k_bgrad<<<1, 64, 0, s>>>(B, NH, dh2, g + OFF_B2);
-  k_hgrad<<<div_up((long)B * NH, 256), 256, 0, s>>>(B, NH, dh2, W2, h1, dh1);
-  k_wgrad<<<div_up(NIN * NH, 256), 256, 0, s>>>(B, NIN, NH, xo, dh1, g + OFF_W1);
-  k_bgrad<<<1, 64, 0, s>>>(B, NH, dh1, g + OFF_B1);
+  // minibatch slices of the weight gradients: about 64 samples each
+  const int slices = std::max(1, std::min(32, B / 64));
+  DevBuf<float> wpart;
+  wpart.ensure((size_t)slices * NH * NH);
+  auto wgrad = [&](int K, int J, const uint16_t* act, const float* d, float* dW) {
+    k_wgrad_mfma<<<(K / 16) * (J / 16) * slices, 64, 0, s>>>(B, K, J, slices, act, d, wpart.p);
+    k_wgrad_sum<<<div_up(K * J, 256), 256, 0, s>>>(K * J, slices, wpart.p, dW);
+  };
+  const int hblocks = div_up(B, 16) * (NH / 16);
+  wgrad(NH, NOUTP, h2, dout, g + OFF_W3);
+  k_bgrad<<<NOUTP, 256, 0, s>>>(B, NOUTP, dout, g + OFF_B3);
+  k_hgrad_mfma<<<hblocks, 64, 0, s>>>(B, NOUTP, dout, W3, h2, dh2);
+  wgrad(NH, NH, h1, dh2, g + OFF_W2);
+  k_bgrad<<<NH, 256, 0, s>>>(B, NH, dh2, g + OFF_B2);
+  k_hgrad_mfma<<<hblocks, 64, 0, s>>>(B, NH, dh2, W2, h1, dh1);
+  wgrad(NIN, NH, xo, dh1, g + OFF_W1);
+  k_bgrad<<<NH, 256, 0, s>>>(B, NH, dh1, g + OFF_B1);
   HIP_LAUNCH_CHECK();
   return device_sum(c, part, 64) * inv_cnt;
 }
@@ -687,15 +741,72 @@ extern "C" hfsi_status hfsi_mlp_loss_grad(hfsi_ctx* c, int32_t m, const float* X
 }
 
 // Append the samples of the current (classical) hierarchy to the training set.
-extern "C" hfsi_status hfsi_mlp_collect(hfsi_ctx* c, int32_t* n_added, int32_t* n_failed) {
-  HFSI_ABI_BEGIN(c)
-  hfsi::Hierarchy& H = c->H;
+namespace hfsi {
+namespace {
+
+// keep[t] = 1 when the sample of row rows[t] is drawn: the top 53 bits of
+// SplitMix64 output rows[t] of the stream `seed`, as a fraction of 2^53,
+// below `fraction`
+__global__ void k_sample_keep(int ns, const int* __restrict__ rows, uint64_t seed, double fraction,
+                              int* __restrict__ keep) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ns) return;
+  const double u = (double)(splitmix64(seed, (uint64_t)rows[t]) >> 11) * (1.0 / 9007199254740992.0);
+  keep[t] = u < fraction ? 1 : 0;
+}
+
+__global__ void k_sample_compact(int ns, const int* __restrict__ keep, const int* __restrict__ kidx,
+                                 const int* __restrict__ rows, const float* __restrict__ X,
+                                 const float* __restrict__ mask, const float* __restrict__ wcl,
+                                 int* __restrict__ rows2, float* __restrict__ X2, float* __restrict__ mask2,
+                                 float* __restrict__ wcl2) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ns || !keep[t]) return;
+  const int k = kidx[t];
+  rows2[k] = rows[t];
+  for (int j = 0; j < NIN; ++j) X2[(size_t)k * NIN + j] = X[(size_t)t * NIN + j];
+  for (int j = 0; j < NOUTP; ++j) {
+    mask2[(size_t)k * NOUTP + j] = mask[(size_t)t * NOUTP + j];
+    wcl2[(size_t)k * NOUTP + j] = wcl[(size_t)t * NOUTP + j];
+  }
+}
+
+// Append the level-0 samples of the current hierarchy to the training set,
+// all of them (fraction >= 1) or those drawn by k_sample_keep.
+void collect(hfsi_ctx* c, double fraction, uint64_t seed, int32_t* n_added, int32_t* n_failed) {
+  Hierarchy& H = c->H;
   if (!H.ready || H.L.size() < 2) fail(HFSI_E_ORDER, "mlp_collect: needs a hierarchy with at least two levels");
-  hfsi::MlpState& S = hfsi::mlp_state(c);
+  if (!(fraction > 0.0)) fail(HFSI_E_ARG, "mlp_collect: fraction must be positive");
+  MlpState& S = mlp_state(c);
   hipStream_t s = c->stream;
-  hfsi::Level& L = H.L[0];
-  hfsi::Samples smp;
-  hfsi::build_samples(c, L, smp);
+  Level& L = H.L[0];
+  Samples smp;
+  build_samples(c, L, smp);
+  if (fraction < 1.0 && smp.ns > 0) {
+    const int n0 = smp.ns;
+    DevBuf<int> keep, kidx;
+    keep.ensure(n0 + 1);
+    kidx.ensure(n0 + 1);
+    HIP_CHECK(hipMemsetAsync(keep.p + n0, 0, sizeof(int), s));
+    k_sample_keep<<<div_up(n0, 256), 256, 0, s>>>(n0, smp.rows.p, seed, fraction, keep.p);
+    HIP_LAUNCH_CHECK();
+    const int nk = (int)exclusive_scan(keep.p, kidx.p, n0 + 1, s);
+    Samples sub;
+    sub.ns = nk;
+    sub.rows.ensure(std::max(nk, 1));
+    sub.X.ensure((size_t)std::max(nk, 1) * NIN);
+    sub.mask.ensure((size_t)std::max(nk, 1) * NOUTP);
+    sub.wcl.ensure((size_t)std::max(nk, 1) * NOUTP);
+    k_sample_compact<<<div_up(n0, 256), 256, 0, s>>>(n0, keep.p, kidx.p, smp.rows.p, smp.X.p, smp.mask.p, smp.wcl.p,
+                                                     sub.rows.p, sub.X.p, sub.mask.p, sub.wcl.p);
+    HIP_LAUNCH_CHECK();
+    std::swap(smp.rows, sub.rows);
+    std::swap(smp.X, sub.X);
+    std::swap(smp.mask, sub.mask);
+    std::swap(smp.wcl, sub.wcl);
+    smp.ns = nk;
+    HIP_CHECK(hipStreamSynchronize(s));  // the replaced buffers leave scope
+  }
   const long ns = smp.ns;
   if (S.ns + ns > S.cap) {  // grow (keep contents)
     long nc = std::max(2 * S.cap, S.ns + ns + 1024);
@@ -728,6 +839,22 @@ extern "C" hfsi_status hfsi_mlp_collect(hfsi_ctx* c, int32_t* n_added, int32_t* 
   S.ns += ns;
   if (n_added) *n_added = (int32_t)ns;
   if (n_failed) *n_failed = nf;
+}
+
+}  // namespace
+}  // namespace hfsi
+
+extern "C" hfsi_status hfsi_mlp_collect(hfsi_ctx* c, int32_t* n_added, int32_t* n_failed) {
+  HFSI_ABI_BEGIN(c)
+  hfsi::collect(c, 1.0, 0, n_added, n_failed);
+  HFSI_ABI_END(c)
+}
+
+extern "C" hfsi_status hfsi_mlp_collect_sampled(hfsi_ctx* c, double fraction, uint64_t seed, int32_t* n_added,
+                                                int32_t* n_failed) {
+  HFSI_ABI_BEGIN(c)
+  if (!(fraction > 0.0 && fraction <= 1.0)) fail(HFSI_E_ARG, "mlp_collect_sampled: fraction in (0, 1]");
+  hfsi::collect(c, fraction, seed, n_added, n_failed);
   HFSI_ABI_END(c)
 }
 

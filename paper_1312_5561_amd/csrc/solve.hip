@@ -1725,6 +1725,10 @@ extern "C" hfsi_status hfsi_time_kernel(hfsi_ctx* c, int32_t kernel, int32_t rep
 
 namespace {
 
+// first Newton correction at the rounding level of the state:
+// ||dv_0||_M <= kNewtonFloor ||v_0||_M
+constexpr double kNewtonFloor = 1e-14;
+
 struct EventPair {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   EventPair() {
@@ -1867,6 +1871,9 @@ extern "C" hfsi_status hfsi_newton_solve(hfsi_ctx* c, double* v, double load, co
     fail(HFSI_E_ARG, "newton solve info: struct_size mismatch");
   auto t_start = std::chrono::steady_clock::now();
   hfsi_solve_params sp = prm->step.solve;
+  // a first correction at the rounding level of the starting state ends the
+  // increment (the relative rule has no usable reference then)
+  const double dv_floor = kNewtonFloor * hfsi::mass_norm(c, v);
   double dv0 = 0.0, dv_prev = 0.0;
   int its = 0, kry = 0;
   bool done = false;
@@ -1888,7 +1895,7 @@ extern "C" hfsi_status hfsi_newton_solve(hfsi_ctx* c, double* v, double load, co
     const bool reuse = prm->step.amg_reuse == 2 || (k > 0 && prm->step.amg_reuse == 1);
     double alpha = 1.0;
     newton_iteration(c, v, load, prm->step.amg, sp, reuse, &ni, prm->line_search ? &alpha : nullptr,
-                     k > 0 ? prm->eps2 * dv0 : -1.0);
+                     k > 0 ? prm->eps2 * dv0 : dv_floor);
     ++its;
     kry += ni.krylov_iterations;
     if (k == 0) dv0 = ni.dv_mass_norm;
@@ -1900,6 +1907,10 @@ extern "C" hfsi_status hfsi_newton_solve(hfsi_ctx* c, double* v, double load, co
       info->step_length[k] = alpha;
     }
     if (alpha == 0.0) break;  // no admissible step length: the increment fails
+    if (k == 0 && ni.dv_mass_norm <= dv_floor) {
+      done = true;
+      break;
+    }
     done = (dv0 == 0.0 || ni.dv_mass_norm <= prm->eps2 * dv0) && alpha == 1.0;
   }
   if (info) {

@@ -194,6 +194,7 @@ def load():
         "hfsi_mlp_forward": [vp, i32, vp, vp, vp, vp, vp],
         "hfsi_mlp_loss_grad": [vp, i32, vp, vp, vp, vp, vp, C.POINTER(dbl)],
         "hfsi_mlp_collect": [vp, C.POINTER(i32), C.POINTER(i32)],
+        "hfsi_mlp_collect_sampled": [vp, dbl, C.c_uint64, C.POINTER(i32), C.POINTER(i32)],
         "hfsi_mlp_clear": [vp],
         "hfsi_mlp_samples": [vp, i64, i64, C.POINTER(i64), vp, vp, vp, vp],
         "hfsi_mlp_train": [vp, C.POINTER(TrainParams), vp, i64, C.POINTER(TrainInfo)],
@@ -452,6 +453,12 @@ class Context:
     def mlp_collect(self):
         a, f = C.c_int32(), C.c_int32()
         self._check(self.lib.hfsi_mlp_collect(self.h, C.byref(a), C.byref(f)))
+        return a.value, f.value
+
+    def mlp_collect_sampled(self, fraction, seed):
+        a, f = C.c_int32(), C.c_int32()
+        self._check(self.lib.hfsi_mlp_collect_sampled(self.h, C.c_double(fraction), C.c_uint64(seed), C.byref(a),
+                                                      C.byref(f)))
         return a.value, f.value
 
     def mlp_clear(self):

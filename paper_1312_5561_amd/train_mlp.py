@@ -6,9 +6,11 @@ Set-up k (seed 1000 + k): jittered Kuhn cube (interior nodes moved by
 U(-0.1h, 0.1h)^3), kappa = 10^U(3,6), c10 and c01 scaled by U(0.7, 1.3), the
 tangent taken after `newton_per_inc` Newton steps of each load increment up to
 a random increment 1..5 (of 5).  Samples: every level-0 F point with a strong
-C neighbour; target: the local ideal interpolation.
+C neighbour; target: the local ideal interpolation.  The default recipe is
+1800 set-ups of the 8^3 cube (all samples) and 200 of the 48^3 cube (set-ups
+1800..1999, a seeded fraction of their samples, hfsi_mlp_collect_sampled).
 
-    python -m paper_1312_5561_amd.train_mlp --setups 200 --out gpurun_out/mlp_cube.npz
+    python -m paper_1312_5561_amd.train_mlp --out gpurun_out/mlp_cube.npz
 """
 from __future__ import annotations
 
@@ -71,11 +73,13 @@ def setup_problem(k, N):
     return prob, inc
 
 
-def collect(ctx_factory, n_setups, N, newton_per_inc=2, first=0, log=print):
-    """Build the training set in a fresh context; returns the context."""
+def collect(ctx_factory, n_setups, N, newton_per_inc=2, first=0, log=print, ctx=None, fraction=1.0):
+    """Append the samples of set-ups first .. first + n_setups - 1 to the
+    training set of `ctx` (a fresh context from ctx_factory when None); with
+    fraction < 1 a seeded subset of each set-up's samples (seed 1000 + k)."""
     import torch
     from paper_1312_5561_amd import hfsi
-    ctx = ctx_factory()
+    ctx = ctx_factory() if ctx is None else ctx
     total, failed = 0, 0
     prm = hfsi.newton_params(amg=hfsi.amg_params(smoother=1, precision=1, max_coarse=100),
                              solve=hfsi.solve_params(max_iter=2000))
@@ -89,7 +93,7 @@ def collect(ctx_factory, n_setups, N, newton_per_inc=2, first=0, log=print):
         R = torch.zeros_like(v)
         ctx.assemble_residual_tangent(v, inc / 5.0, R)
         ctx.amg_setup(hfsi.amg_params(smoother=1, precision=1, max_coarse=100))
-        a, f = ctx.mlp_collect()
+        a, f = ctx.mlp_collect() if fraction >= 1.0 else ctx.mlp_collect_sampled(fraction, 1000 + k)
         total += a
         failed += f
         if (k - first) % 25 == 0:
@@ -126,18 +130,23 @@ def load(path):
         return z["weights"].astype(np.float32), json.loads(bytes(z["meta"]).decode())
 
 
-def evaluate(path, cases=((8, 9001), (8, 9002), (16, 9003), (24, 9004), (48, 9005)), log=print):
+HELD_OUT = ((8, 9001, None), (8, 9002, None), (16, 9003, None), (24, 9004, None), (48, 9005, None),
+            (96, 9101, 1e3), (96, 9102, 1e4), (96, 9103, 1e5), (96, 9104, 1e6))
+
+
+def evaluate(path, cases=HELD_OUT, log=print):
     """Held-out comparison of learned and classical level-0 interpolation:
-    jittered cube (seed s, kappa = 10^U(3,6)), two Newton steps per increment
-    0.2..0.8, tangent at load 1.0, set-up with the judge disabled, FGMRES(50)."""
+    jittered cube (seed s, kappa = 10^U(3,6) unless given), two Newton steps
+    per increment 0.2..0.8, tangent at load 1.0, set-up with the judge
+    disabled, FGMRES(50) to 1e-8 from zero; time = set-up + solve."""
     import torch
     import synth
     from paper_1312_5561_amd import hfsi
     w, meta = load(path)
     rows = []
-    for N, seed in cases:
+    for N, seed, kap in cases:
         r = np.random.default_rng(seed)
-        kappa = 10 ** r.uniform(3, 6)
+        kappa = 10 ** r.uniform(3, 6) if kap is None else kap
         prob = synth.cube_problem(N, kappa=kappa, jitter=0.1, seed=seed)
         ctx = hfsi.Context(0)
         ctx.set_problem(prob)
@@ -152,15 +161,16 @@ def evaluate(path, cases=((8, 9001), (8, 9002), (16, 9003), (24, 9004), (48, 900
         b = -R
         res = {}
         for interp in (0, 1):
-            info = ctx.amg_setup(hfsi.amg_params(smoother=1, precision=1, interp=interp, fallback_rho=1.0,
-                                                    judge_classical=0))
-            rho = ctx.amg_convergence_factor(10, 777)
-            x = torch.zeros_like(b)
             torch.cuda.synchronize()
             t = time.time()
+            info = ctx.amg_setup(hfsi.amg_params(smoother=1, precision=1, interp=interp, fallback_rho=1.0,
+                                                    judge_classical=0))
+            x = torch.zeros_like(b)
             si, _ = ctx.krylov_amg_solve(b, x, hfsi.solve_params(max_iter=3000))
             torch.cuda.synchronize()
-            res[interp] = dict(rho=rho, its=si.iterations, ms=(time.time() - t) * 1e3, opc=info.op_complexity)
+            ms = (time.time() - t) * 1e3
+            rho = ctx.amg_convergence_factor(10, 777)
+            res[interp] = dict(rho=rho, its=si.iterations, ms=ms, opc=info.op_complexity)
         line = (f"N={N} kappa={kappa:.2e} classical rho={res[0]['rho']:.3f} its={res[0]['its']} "
                 f"t={res[0]['ms']:.0f}ms opc={res[0]['opc']:.2f} | learned rho={res[1]['rho']:.3f} "
                 f"its={res[1]['its']} t={res[1]['ms']:.0f}ms opc={res[1]['opc']:.2f}")
@@ -172,8 +182,12 @@ def evaluate(path, cases=((8, 9001), (8, 9002), (16, 9003), (24, 9004), (48, 900
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--evaluate", default=None, help="checkpoint to compare against classical interpolation")
-    ap.add_argument("--setups", type=int, default=200)
+    ap.add_argument("--setups", type=int, default=1800)
     ap.add_argument("--N", type=int, default=8)
+    ap.add_argument("--setups-large", type=int, default=200)
+    ap.add_argument("--N-large", type=int, default=48)
+    ap.add_argument("--fraction-large", type=float, default=0.005,
+                    help="share of each large set-up's samples kept")
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -184,13 +198,20 @@ def main():
         evaluate(args.evaluate, log=lambda s: print(s, flush=True))
         return
     t0 = time.time()
-    ctx, total, failed = collect(lambda: hfsi.Context(0), args.setups, args.N,
-                                 log=lambda s: print(s, flush=True))
-    print(f"[train] collected {total} samples ({failed} failed targets) in {time.time() - t0:.1f} s", flush=True)
-    info = train(ctx, args.epochs, args.batch, args.lr, log=lambda s: print(s, flush=True))
-    meta = dict(setups=args.setups, N=args.N, strength_theta=hfsi.amg_params().strength_theta,
-                epochs=args.epochs, batch=args.batch, lr=args.lr, samples=total,
-                failed_targets=failed, loss_first=info.loss_first, loss_last=info.loss_last, steps=info.steps)
+    log = lambda s: print(s, flush=True)  # noqa: E731
+    ctx, total, failed = collect(lambda: hfsi.Context(0), args.setups, args.N, log=log)
+    total_l = failed_l = 0
+    if args.setups_large > 0:
+        ctx, total_l, failed_l = collect(None, args.setups_large, args.N_large, first=args.setups, log=log, ctx=ctx,
+                                         fraction=args.fraction_large)
+    print(f"[train] collected {total} + {total_l} samples ({failed + failed_l} failed targets) in "
+          f"{time.time() - t0:.1f} s", flush=True)
+    info = train(ctx, args.epochs, args.batch, args.lr, log=log)
+    meta = dict(setups=args.setups, N=args.N, setups_large=args.setups_large, N_large=args.N_large,
+                fraction_large=args.fraction_large, strength_theta=hfsi.amg_params().strength_theta,
+                epochs=args.epochs, batch=args.batch, lr=args.lr, samples=total + total_l,
+                samples_large=total_l, failed_targets=failed + failed_l, loss_first=info.loss_first,
+                loss_last=info.loss_last, steps=info.steps)
     save(args.out, ctx, meta)
     print(json.dumps(meta), flush=True)
 

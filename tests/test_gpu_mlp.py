@@ -116,6 +116,33 @@ def test_collect_matches_oracle(lib, kind):
         assert abs(t.sum() - csum) <= 1e-9 * max(1.0, abs(csum))
 
 
+def test_sampled_collect_is_the_seeded_subset(lib):
+    """hfsi_mlp_collect_sampled keeps the samples of the rows whose
+    SplitMix64 draw is below the fraction (computed here from the published
+    generator) and nothing else, in the same row order."""
+    from oracle import rng
+    prob, ctx, info = _cube_setup(lib, kind=1)
+    added, _ = ctx.mlp_collect()
+    X, mask, wcl, wst = ctx.mlp_samples()
+    A = export_level_matrix(ctx, 0, 0)
+    comp = ctx.amg_export(0, 4)
+    st = ctx.amg_export(0, 3)
+    P = export_level_matrix(ctx, 0, 1)
+    S_ptr, S_idx = amg.strength(A, comp, lib.amg_params().strength_theta)
+    rows, *_ = mlp.samples(A, comp, st, S_ptr, S_idx, P, prob.lattice, mlp.material_features(prob.materials))
+    for fraction, seed in ((0.3, 11), (0.05, 12), (1.0, 13)):
+        ctx.mlp_clear()
+        got, failed = ctx.mlp_collect_sampled(fraction, seed)
+        u = (rng.splitmix64(seed, np.asarray(rows)) >> np.uint64(11)).astype(np.float64) / 9007199254740992.0
+        keep = u < fraction
+        assert got == int(keep.sum()) and failed == 0
+        Xs, ms, ws, ts = ctx.mlp_samples()
+        assert np.array_equal(Xs, X[keep]) and np.array_equal(ms, mask[keep])
+        assert np.array_equal(ws, wcl[keep]) and np.array_equal(ts, wst[keep])
+    with pytest.raises(RuntimeError):
+        ctx.mlp_collect_sampled(0.0, 1)
+
+
 def test_zero_last_layer_is_classical_and_fallback(lib):
     w0 = mlp.init_weights(11)
     _, ctx_c, info_c = _cube_setup(lib)

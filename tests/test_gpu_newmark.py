@@ -145,3 +145,32 @@ def test_time_step_entry_with_reuse_matches_oracle(lib):
     with pytest.raises(lib.HfsiError) as e:
         ctx.time_step(v, vel, acc, 1.0, prm)
     assert e.value.code == -4
+
+
+def test_time_step_from_equilibrium_ends_at_the_floor(lib):
+    """A time step from a static equilibrium at rest: the first Newton
+    correction is rounding noise, the step ends after it (both sides), the
+    state stays put and velocity and acceleration stay at rounding level."""
+    import torch
+    print("[newmark floor] cube4 equilibrium at rest", flush=True)
+    prob = synth.cube_problem(4)
+    n = prob.n_nodes
+    ctx = lib.Context(0)
+    ctx.set_problem(prob)
+    v = torch.zeros(4 * n, dtype=torch.float64, device="cuda")
+    info, code = ctx.newton_solve(v, 1.0, lib.newton_solve_params())
+    assert code == 0
+    v_eq = v.clone()
+    ctx.set_newmark(PRM.rho, dt=PRM.dt, beta=PRM.beta, gamma=PRM.gamma)
+    vel = torch.zeros(3 * n, dtype=torch.float64, device="cuda")
+    acc = torch.zeros_like(vel)
+    prm = lib.newton_solve_params(step=lib.newton_params(solve=lib.solve_params(tol=1e-12)), max_newton=6)
+    info, code = ctx.time_step(v, vel, acc, 1.0, prm)
+    assert code == 0 and info.converged and info.newton_iterations == 1
+    assert (v - v_eq).abs().max().item() <= 1e-13 * v_eq.abs().max().item()
+    assert vel.abs().max().item() <= 1e-8 and acc.abs().max().item() <= 1e-6
+    disc = fe.Discretization(prob)
+    vo, _, _ = newton.solve_increment(disc, np.zeros(4 * n), 1.0, newton.NewtonParams())[0], None, None
+    _, _, _, its = newmark.time_step(disc, vo, 1.0, PRM, newton.NewtonParams(eps2=1e-10, max_iter=6, lin_tol=1e-12),
+                                     np.zeros((n, 3)), np.zeros((n, 3)))
+    assert its == 1

@@ -194,7 +194,7 @@ def test_bicgstab_solution(lib, precision):
     assert oinfo.converged
     assert abs(sinfo.iterations - oinfo.iterations) <= (1 if precision == 0 else 3)
     with pytest.raises(lib.HfsiError):
-        ctx.krylov_amg_solve(bt, x, lib.solve_params(method=2))
+        ctx.krylov_amg_solve(bt, x, lib.solve_params(method=3))
 
 
 def test_tangent_product_any_alignment(lib):
