@@ -8,7 +8,8 @@ tangent taken after `newton_per_inc` Newton steps of each load increment up to
 a random increment 1..5 (of 5).  Samples: every level-0 F point with a strong
 C neighbour; target: the local ideal interpolation.  The default recipe is
 1800 set-ups of the 8^3 cube (all samples) and 200 of the 48^3 cube (set-ups
-1800..1999, a seeded fraction of their samples, hfsi_mlp_collect_sampled).
+1800..1999, a seeded 3.5% of their samples, hfsi_mlp_collect_sampled): about
+4M samples, 8 epochs.
 
     python -m paper_1312_5561_amd.train_mlp --out gpurun_out/mlp_cube.npz
 """
@@ -186,9 +187,9 @@ def main():
     ap.add_argument("--N", type=int, default=8)
     ap.add_argument("--setups-large", type=int, default=200)
     ap.add_argument("--N-large", type=int, default=48)
-    ap.add_argument("--fraction-large", type=float, default=0.005,
+    ap.add_argument("--fraction-large", type=float, default=0.035,
                     help="share of each large set-up's samples kept")
-    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--out", default="gpurun_out/mlp_cube.npz")
