@@ -1199,70 +1199,6 @@ k_gj_step(int n, int k, const double* __restrict__ Min, double* __restrict__ Mou
   }
 }
 
-// The same Gauss-Jordan elimination in one workgroup for small n (all n
-// steps in one launch, in place): per step the pivot search, then the old row
-// k and the column of multipliers are saved to `tmp` (row k: 2n doubles, the
-// normalised pivot row: 2n, multipliers: n), then every entry j > k of every
-// row is formed from those by the expression of k_gj_step, so the result is
-// the same bit for bit.
-__global__ void __launch_bounds__(1024) k_gj_single(int n, double* __restrict__ M, double* __restrict__ tmp,
-                                                    int* __restrict__ singular) {
-  __shared__ double sv[1024];
-  __shared__ int si[1024];
-  const size_t w = 2 * (size_t)n;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  double* rowk = tmp;
-  double* pk = tmp + w;
-  double* mult = tmp + 2 * w;
-  for (int k = 0; k < n; ++k) {
-    double best = -1.0;
-    int bi = k;
-    for (int r = k + tid; r < n; r += nt) {
-      const double a = fabs(M[(size_t)r * w + k]);
-      if (a > best) {
-        best = a;
-        bi = r;
-      }
-    }
-    sv[tid] = best;
-    si[tid] = bi;
-    __syncthreads();
-    for (int o = nt / 2; o > 0; o >>= 1) {
-      if (tid < o) {
-        const double ob = sv[tid + o];
-        const int oi = si[tid + o];
-        if (ob > sv[tid] || (ob == sv[tid] && oi < si[tid])) {
-          sv[tid] = ob;
-          si[tid] = oi;
-        }
-      }
-      __syncthreads();
-    }
-    const int p = si[0];
-    const bool ok = sv[0] > 0.0;
-    if (!ok) {
-      if (tid == 0) *singular = 1;
-      return;  // uniform: every thread read the same flag
-    }
-    const double ip = 1.0 / M[(size_t)p * w + k];
-    for (int j = k + 1 + tid; j < (int)w; j += nt) {
-      rowk[j] = M[(size_t)k * w + j];
-      pk[j] = M[(size_t)p * w + j] * ip;
-    }
-    for (int r = tid; r < n; r += nt) mult[r] = M[(size_t)(r == p ? k : r) * w + k];
-    __syncthreads();
-    const long cols = 2L * n - k - 1;
-    for (long t = tid; t < (long)n * cols; t += nt) {
-      const int r = (int)(t / cols);
-      const int j = k + 1 + (int)(t - (long)r * cols);
-      double* dst = M + (size_t)r * w + j;
-      if (r == k) *dst = pk[j];
-      else *dst = (r == p ? rowk[j] : *dst) - mult[r] * pk[j];
-    }
-    __syncthreads();
-  }
-}
-
 __global__ void k_gj_extract(int n, const double* __restrict__ M, double* __restrict__ inv) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long)n * n) return;
@@ -1967,7 +1903,6 @@ __global__ void k_comp_mod3(int n, int* __restrict__ comp) {
 }  // namespace
 
 constexpr int PMIS_BATCH = 3;
-constexpr int kGjSingle = 256;  // coarsest systems up to this size: one-workgroup Gauss-Jordan
 
 namespace {
 
@@ -2014,11 +1949,27 @@ void finish_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, bool same_pattern
   H.coarse_inv.ensure((size_t)nc * nc);
   DevBuf<int> sing;
   sing.zero(1, s);
-  // the aux stream waits for the final operators only; the copies below are
-  // enqueued on this stream first, so the GPU has them while the host
-  // enqueues the elimination
   HIP_CHECK(hipEventRecord(c->aev[0], s));
   HIP_CHECK(hipStreamWaitEvent(c->aux, c->aev[0], 0));
+  {
+    hipStream_t a = c->aux;
+    StreamTag tag(a);
+    DevBuf<double> M, M2;
+    M.ensure(2 * (size_t)nc * nc);
+    M2.ensure(2 * (size_t)nc * nc);
+    k_dense_from_csr<<<div_up(nc, 256), 256, 0, a>>>(nc, Lc.A.ptr.p, Lc.A.col.p, Lc.A.val.p, M.p);
+    HIP_LAUNCH_CHECK();
+    // Gauss-Jordan on [A | I]: one launch per pivot, alternating buffers
+    double* gin = M.p;
+    double* gout = M2.p;
+    for (int k = 0; k < nc; ++k) {
+      const long work = (long)nc * (2L * nc - k - 1);
+      k_gj_step<<<div_up(work, 256), 256, 0, a>>>(nc, k, gin, gout, sing.p);
+      std::swap(gin, gout);
+    }
+    k_gj_extract<<<div_up((long)nc * nc, 256), 256, 0, a>>>(nc, gin, H.coarse_inv.p);
+    HIP_LAUNCH_CHECK();
+  }
   // fp32 operator copies
   if (prm.precision == 1)
     for (auto& L : H.L) {
@@ -2030,30 +1981,6 @@ void finish_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, bool same_pattern
   for (auto& L : H.L) {
     L.packed = false;
     if (!L.bptr) pack_level(c, L, prm.precision, same_patterns);
-  }
-  {
-    hipStream_t a = c->aux;
-    StreamTag tag(a);
-    DevBuf<double> M, M2;
-    M.ensure(2 * (size_t)nc * nc);
-    M2.ensure(std::max(2 * (size_t)nc * nc, 5 * (size_t)nc));
-    k_dense_from_csr<<<div_up(nc, 256), 256, 0, a>>>(nc, Lc.A.ptr.p, Lc.A.col.p, Lc.A.val.p, M.p);
-    HIP_LAUNCH_CHECK();
-    // Gauss-Jordan on [A | I]: small systems in one workgroup, larger ones
-    // one launch per pivot with alternating buffers
-    double* gin = M.p;
-    if (nc <= kGjSingle) {
-      k_gj_single<<<1, 1024, 0, a>>>(nc, M.p, M2.p, sing.p);
-    } else {
-      double* gout = M2.p;
-      for (int k = 0; k < nc; ++k) {
-        const long work = (long)nc * (2L * nc - k - 1);
-        k_gj_step<<<div_up(work, 256), 256, 0, a>>>(nc, k, gin, gout, sing.p);
-        std::swap(gin, gout);
-      }
-    }
-    k_gj_extract<<<div_up((long)nc * nc, 256), 256, 0, a>>>(nc, gin, H.coarse_inv.p);
-    HIP_LAUNCH_CHECK();
   }
   // join the aux stream, then read the singularity flag and the estimates
   HIP_CHECK(hipEventRecord(c->aev[1], c->aux));
