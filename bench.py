@@ -213,11 +213,12 @@ def cpu_baseline(workload="cube", kappa=1e4, reps=3):
 
 def vanka_leg(N, steps, kappa, torch, hfsi):
     """The paper's own solid AMG (coupled (u,p) hierarchy, multiplicative
-    Vanka smoother, omega = 0.78) against the block preconditioner P_L on one
-    Newton system: the N^3 cube at load 1.0 from the converged load-0.8
-    state.  Each solver from x = 0 to ||b - K x|| <= 1e-8 ||b||: FGMRES with
-    the coupled V-cycle, the AMG method itself (V-cycles as the iteration),
-    and FGMRES with P_L (fp64 and fp32 cycles)."""
+    Vanka smoother, omega = 0.78; and its additive variant, omega = 0.8)
+    against the block preconditioner P_L on one Newton system: the N^3 cube
+    at load 1.0 from the converged load-0.8 state.  Each solver from x = 0 to
+    ||b - K x|| <= 1e-8 ||b||: FGMRES with the coupled V-cycle, the AMG method
+    itself (V-cycles as the iteration), and FGMRES with P_L (fp64 and fp32
+    cycles)."""
     import synth
     prob = synth.cube_problem(N, kappa=kappa)
     ctx = hfsi.Context(0)
@@ -254,6 +255,15 @@ def vanka_leg(N, steps, kappa, torch, hfsi):
                             "colours": [ctx.amg_export(lev, 14)[1] for lev in range(ai.levels - 1)]}
     solve(hfsi.solve_params(tol=1e-8, restart=100, max_iter=300), "coupled_fgmres")
     solve(hfsi.solve_params(tol=1e-8, max_iter=200, method=2), "coupled_amg_iteration")
+    g = hfsi.amg_params(coupled=2, vanka_omega=0.8, vanka_steps=steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ai = ctx.amg_setup(g)
+    torch.cuda.synchronize()
+    out["additive_setup"] = {"seconds": time.perf_counter() - t0, "levels": ai.levels, "vanka_steps": steps,
+                             "omega": 0.8}
+    solve(hfsi.solve_params(tol=1e-8, restart=100, max_iter=300), "additive_fgmres")
+    solve(hfsi.solve_params(tol=1e-8, max_iter=200, method=2), "additive_amg_iteration")
     for prec in (0, 1):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -489,7 +499,10 @@ def main():
         cv = res["coupled_vanka"]
         print(f"[bench] coupled Vanka AMG at {args.vanka_N}^3: FGMRES {cv['coupled_fgmres']['iterations']} its "
               f"{cv['coupled_fgmres']['seconds']:.2f} s, AMG iteration {cv['coupled_amg_iteration']['iterations']} "
-              f"its; P_L fp32 FGMRES {cv['pl_fgmres_fp32']['iterations']} its "
+              f"its; additive: FGMRES {cv['additive_fgmres']['iterations']} its "
+              f"{cv['additive_fgmres']['seconds']:.3f} s (set-up {cv['additive_setup']['seconds']:.2f} s), AMG "
+              f"iteration {cv['additive_amg_iteration']['iterations']} its; "
+              f"P_L fp32 FGMRES {cv['pl_fgmres_fp32']['iterations']} its "
               f"{cv['pl_fgmres_fp32']['seconds'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
     # the headline state's tangent for the roofline timing
     v.copy_(v0)

@@ -174,7 +174,16 @@ typedef struct {
                                  strength_theta, max_coarse, max_levels, seed,
                                  interp_kind and p_max for both hierarchies;
                                  needs interp = 0 and drop_tol = 0; every
-                                 set-up and re-set-up builds it anew (fp64)  */
+                                 set-up and re-set-up builds it anew (fp64).
+                                 2 = the same hierarchy with the additive
+                                 variant of the Vanka smoother (the paper
+                                 mentions an additive form, weights not
+                                 fixed): all patches solve with the residual
+                                 of the same iterate and every unknown adds
+                                 omega times the mean of the corrections of
+                                 the patches that hold it (an unknown in no
+                                 patch is left unchanged); no colours are
+                                 formed                                     */
   double vanka_omega;         /* relaxation omega of eq. vankasmooth, in (0, 2)
                                  (the paper: 0.78 Mooney-Rivlin, 0.86 artery) */
   int32_t vanka_steps;        /* sweeps before and after the coarse correction
@@ -434,12 +443,13 @@ hfsi_status hfsi_amg_setup_csr(hfsi_ctx* ctx, int32_t n, const int32_t* ptr, con
 /* Copy level `level` of the current hierarchy to host buffers.  which: 0 = A
  * (ptr [rows+1], col, val), 1 = P, 2 = strength flags (u8 per A entry, in
  * val_u8), 3 = C/F state (int8 per row in val_u8: +1 C, -1 F), 4 = component
- * per row (int32 in col).  Of the coupled hierarchy (coupled = 1): 10 = Kuu
+ * per row (int32 in col).  Of the coupled hierarchy (coupled = 1 or 2): 10 = Kuu
  * (the displacement block A of the level), 11 = Kup (B1^T), 12 = Kpu (B2),
  * 13 = Kpp (-C), each as CSR; 14 = the Vanka colour of every patch (int32
  * per pressure unknown in col, the colour count in *cols); 15 = P_u, 16 =
- * P_p (HFSI_E_ARG where the transfer is the identity or on the coarsest
- * level).  Pass NULL buffers to query sizes in *rows, *cols, *nnz. */
+ * P_p (HFSI_E_ARG where the transfer is the identity, on the coarsest
+ * level, and for 14 with the additive variant).  Pass NULL buffers to query
+ * sizes in *rows, *cols, *nnz. */
 hfsi_status hfsi_amg_export(hfsi_ctx* ctx, int32_t level, int32_t which, int32_t* rows, int32_t* cols,
                             int64_t* nnz, int32_t* ptr, int32_t* col, double* val, uint8_t* val_u8);
 
@@ -449,7 +459,7 @@ hfsi_status hfsi_vcycle(hfsi_ctx* ctx, const double* r, double* z);
 
 /* y = M^{-1} r with the preconditioner of the last set-up (P_L^{-1} of
  * eq. lpre, or one V-cycle of the coupled hierarchy when it was set up with
- * coupled = 1) and y = K x (device [N]). */
+ * coupled = 1 or 2) and y = K x (device [N]). */
 hfsi_status hfsi_apply_preconditioner(hfsi_ctx* ctx, const double* r, double* y);
 hfsi_status hfsi_apply_tangent(hfsi_ctx* ctx, const double* x, double* y);
 

@@ -2342,7 +2342,7 @@ void check_amg_params(const hfsi_amg_params* p) {
   if (p->interp < 0 || p->interp > 1) fail(HFSI_E_ARG, "amg params: interp must be 0 (classical) or 1 (learned)");
   if (p->judge_classical < 0 || p->judge_classical > 2) fail(HFSI_E_ARG, "amg params: judge_classical in 0..2");
   if (!(p->drop_tol >= 0.0 && p->drop_tol < 1.0)) fail(HFSI_E_ARG, "amg params: drop_tol in [0, 1)");
-  if (p->coupled < 0 || p->coupled > 1) fail(HFSI_E_ARG, "amg params: coupled 0 or 1");
+  if (p->coupled < 0 || p->coupled > 2) fail(HFSI_E_ARG, "amg params: coupled in 0..2");
   if (p->coupled) {
     if (!(p->vanka_omega > 0.0 && p->vanka_omega < 2.0) || p->vanka_steps < 0 || p->vanka_steps > 64)
       fail(HFSI_E_ARG, "amg params: vanka_omega in (0, 2), vanka_steps in 0..64");

@@ -25,6 +25,14 @@
 // no coupling, so this is the one-by-one Gauss-Seidel sweep in (colour,
 // index) order.
 //
+// Additive variant (coupled = 2; the paper points to an additive form of the
+// Vanka smoother without fixing its weights): every patch solves with the
+// residual of the same iterate and each unknown takes omega times the mean
+// of the corrections of the patches holding it.  A sweep is three launches
+// whatever the colouring: the residual, all local solves (corrections kept
+// per patch entry), and a per-unknown gather that adds its entries in patch
+// order.  No colours are needed, so the set-up skips the conflict pattern.
+//
 // Every level stores its unknowns as [u (nu); p (np)].  fp64 throughout.
 #include <algorithm>
 
@@ -51,7 +59,6 @@ struct VkLevel {
   const Csr<double>* Pp = nullptr;
   const Csr<double>* Rp = nullptr;
   int mmax = 0;                      // largest patch
-  int64_t inv_total = 0;
   int lanes = 8;                     // lanes per row of the local residuals
   DevBuf<int> crow;                  // rows of the patches in sweep order
   DevBuf<int> roff;                  // [np + 1] first entry of each patch in crow
@@ -63,6 +70,10 @@ struct VkLevel {
   DevBuf<int> clist;                 // patches in sweep order
   DevBuf<int> colour;                // [np] colour of each patch (export)
   DevBuf<double> x, b, r;            // [nu + np]
+  // additive variant: per patch entry the local correction, and per unknown
+  // its entries in crow (increasing, i.e. in patch order)
+  DevBuf<double> dd;
+  DevBuf<int> dptr, dent;
 };
 
 struct Coupled {
@@ -83,6 +94,7 @@ struct Coupled {
   DevBuf<double> cinv;  // inverse of the coarsest coupled system, row-major
   double omega = 0.78;
   int steps = 6;
+  bool additive = false;
   bool ready = false;
 };
 
@@ -339,13 +351,67 @@ __global__ void __launch_bounds__(256) k_vk_colour_solve(int q0, int chunks, con
   }
 }
 
+// Additive sweep, local solves: block (q, k) takes rows 64k .. 64k+63 of the
+// local solve of patch clist[q] with the residual r of the whole level
+// (gathered through crow), and keeps the corrections per entry in dd
+// (x is not touched).  Dynamic LDS: mmax + 256 doubles.
+__global__ void __launch_bounds__(256) k_vk_add_solve(int chunks, const int* __restrict__ clist,
+                                                      const int* __restrict__ roff, const int* __restrict__ crow,
+                                                      const double* __restrict__ r_all,
+                                                      const int64_t* __restrict__ luoff,
+                                                      const double* __restrict__ inv, double* __restrict__ dd) {
+  extern __shared__ double sh[];
+  const int q = blockIdx.x / chunks, a0 = 64 * (blockIdx.x % chunks);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int i = clist[q], r0 = roff[q], m = roff[q + 1] - r0;
+  if (a0 >= m) return;  // the whole block leaves
+  double* r = sh;
+  double* part = sh + m;
+  for (int t = tid; t < m; t += 256) r[t] = r_all[crow[r0 + t]];
+  __syncthreads();
+  const double* Y = inv + luoff[i];
+  const int a = a0 + lane;
+  const int t0 = (w * m) >> 2, t1 = ((w + 1) * m) >> 2;
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+  if (a < m) {
+    int t = t0;
+    for (; t + 4 <= t1; t += 4) {
+      const double y0 = Y[(size_t)t * m + a], y1 = Y[(size_t)(t + 1) * m + a];
+      const double y2 = Y[(size_t)(t + 2) * m + a], y3 = Y[(size_t)(t + 3) * m + a];
+      d0 += y0 * r[t];
+      d1 += y1 * r[t + 1];
+      d2 += y2 * r[t + 2];
+      d3 += y3 * r[t + 3];
+    }
+    for (; t < t1; ++t) d0 += Y[(size_t)t * m + a] * r[t];
+  }
+  part[tid] = (d0 + d1) + (d2 + d3);
+  __syncthreads();
+  if (w == 0 && a < m) dd[r0 + a] = (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]);
+}
+
+// Additive sweep, update: x_j += omega * (mean of the corrections of the
+// patches holding unknown j), summed in patch order; an unknown in no patch
+// keeps its value
+__global__ void k_vk_add_gather(int n, const int* __restrict__ dptr, const int* __restrict__ dent,
+                                const double* __restrict__ dd, double* __restrict__ x, double omega) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int e0 = dptr[j], e1 = dptr[j + 1];
+  if (e1 == e0) return;
+  double s = 0.0;
+  for (int e = e0; e < e1; ++e) s += dd[dent[e]];
+  x[j] += omega * (s / (double)(e1 - e0));
+}
+
 __global__ void k_vk_zero(long n, double* __restrict__ x) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) x[t] = 0.0;
 }
 
 // r = b - K x on a level: rows [0, nu) use Kuu and Kup, rows [nu, nu+np) use
-// Kpu and -C; 8 lanes per row
+// Kpu and -C; G lanes per row
+template <int G>
 __global__ void k_vk_resid(int nu, int np, const int* __restrict__ uu_ptr, const int* __restrict__ uu_col,
                            const double* __restrict__ uu_val, const int* __restrict__ up_ptr,
                            const int* __restrict__ up_col, const double* __restrict__ up_val,
@@ -354,19 +420,19 @@ __global__ void k_vk_resid(int nu, int np, const int* __restrict__ uu_ptr, const
                            const int* __restrict__ c_col, const double* __restrict__ c_val,
                            const double* __restrict__ b, const double* __restrict__ x, double* __restrict__ r) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int row = (int)(t >> 3), lane = (int)(t & 7);
+  const int row = (int)(t / G), lane = (int)(t % G);
   if (row >= nu + np) return;
   double s = 0.0;
   if (row < nu) {
-    for (int e = uu_ptr[row] + lane; e < uu_ptr[row + 1]; e += 8) s += uu_val[e] * x[uu_col[e]];
-    for (int e = up_ptr[row] + lane; e < up_ptr[row + 1]; e += 8) s += up_val[e] * x[nu + up_col[e]];
+    for (int e = uu_ptr[row] + lane; e < uu_ptr[row + 1]; e += G) s += uu_val[e] * x[uu_col[e]];
+    for (int e = up_ptr[row] + lane; e < up_ptr[row + 1]; e += G) s += up_val[e] * x[nu + up_col[e]];
   } else {
     const int i = row - nu;
-    for (int e = pu_ptr[i] + lane; e < pu_ptr[i + 1]; e += 8) s += pu_val[e] * x[pu_col[e]];
-    for (int e = c_ptr[i] + lane; e < c_ptr[i + 1]; e += 8) s -= c_val[e] * x[nu + c_col[e]];
+    for (int e = pu_ptr[i] + lane; e < pu_ptr[i + 1]; e += G) s += pu_val[e] * x[pu_col[e]];
+    for (int e = c_ptr[i] + lane; e < c_ptr[i + 1]; e += G) s -= c_val[e] * x[nu + c_col[e]];
   }
 #pragma unroll
-  for (int o = 4; o > 0; o >>= 1) s += __shfl_xor(s, o, 8);
+  for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, G);
   if (lane == 0) r[row] = b[row] - s;
 }
 
@@ -589,7 +655,7 @@ void colour_patches(const std::vector<int>& gptr, const std::vector<int>& gcol, 
   for (int i = 0; i < n; ++i) order[fill[colour[i]]++] = i;
 }
 
-void vanka_level_data(hfsi_ctx* c, VkLevel& V, int* singular) {
+void vanka_level_data(hfsi_ctx* c, VkLevel& V, int* singular, bool additive) {
   hipStream_t s = c->stream;
   const int np = V.np;
   // patch sizes and factor offsets
@@ -605,7 +671,6 @@ void vanka_level_data(hfsi_ctx* c, VkLevel& V, int* singular) {
   }
   if (mmax > kMaxPatch) fail(HFSI_E_CAPACITY, "Vanka: a patch has more than 2048 unknowns");
   V.mmax = mmax;
-  V.inv_total = tot;
   V.luoff.upload(off.data(), np, s);
   V.inv.ensure(tot);
   {
@@ -623,22 +688,29 @@ void vanka_level_data(hfsi_ctx* c, VkLevel& V, int* singular) {
   // lanes per row of the sweep's residual, from the average row length
   const double avg = (double)(V.Kuu->nnz + V.Kup.nnz + V.Kpu.nnz + V.C->nnz) / (double)(V.nu + V.np);
   V.lanes = avg <= 48 ? 8 : (avg <= 96 ? 16 : (avg <= 192 ? 32 : 64));
-  // conflict pattern B2 A B1^T (+ C) and the colours
-  DevBuf<int> flags;
-  flags.zero(1, s);
-  Csr<double> T, G;
-  sparse_product(c, V.Kpu, *V.Kuu, T, flags.p);
-  sparse_product(c, T, V.Kup, G, flags.p);
-  std::vector<int> gptr = G.ptr.download(np + 1, s);
-  std::vector<int> gcol = G.col.download(G.nnz, s);
-  std::vector<int> eptr = V.C->ptr.download(np + 1, s);
-  std::vector<int> ecol = V.C->col.download(V.C->nnz, s);
-  int fl = 0;
-  HIP_CHECK(hipMemcpyAsync(&fl, flags.p, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_CHECK(hipStreamSynchronize(s));
-  if (fl) fail(HFSI_E_CAPACITY, "Vanka: conflict pattern product overflowed");
   std::vector<int> colour, order;
-  colour_patches(gptr, gcol, eptr, ecol, np, colour, order, V.cptr);
+  if (additive) {  // no order: the patches by index, one range
+    colour.assign(np, 0);
+    order.resize(np);
+    for (int i = 0; i < np; ++i) order[i] = i;
+    V.cptr = {0, np};
+  } else {
+    // conflict pattern B2 A B1^T (+ C) and the colours
+    DevBuf<int> flags;
+    flags.zero(1, s);
+    Csr<double> T, G;
+    sparse_product(c, V.Kpu, *V.Kuu, T, flags.p);
+    sparse_product(c, T, V.Kup, G, flags.p);
+    std::vector<int> gptr = G.ptr.download(np + 1, s);
+    std::vector<int> gcol = G.col.download(G.nnz, s);
+    std::vector<int> eptr = V.C->ptr.download(np + 1, s);
+    std::vector<int> ecol = V.C->col.download(V.C->nnz, s);
+    int fl = 0;
+    HIP_CHECK(hipMemcpyAsync(&fl, flags.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (fl) fail(HFSI_E_CAPACITY, "Vanka: conflict pattern product overflowed");
+    colour_patches(gptr, gcol, eptr, ecol, np, colour, order, V.cptr);
+  }
   // the patches' rows in sweep order (displacement unknowns, then the pressure)
   std::vector<int> pcol = V.Kpu.col.download(V.Kpu.nnz, s);
   V.hroff.assign(np + 1, 0);
@@ -652,9 +724,24 @@ void vanka_level_data(hfsi_ctx* c, VkLevel& V, int* singular) {
   }
   V.crow.upload(crow.data(), crow.size(), s);
   V.roff.upload(V.hroff.data(), np + 1, s);
-  V.rr.ensure(crow.size());
   V.clist.upload(order.data(), np, s);
   V.colour.upload(colour.data(), np, s);
+  std::vector<int> dptr, dent;
+  if (additive) {
+    // unknown -> its entries of crow, in increasing entry (= patch) order
+    const int n = V.nu + np;
+    dptr.assign(n + 1, 0);
+    for (int row : crow) ++dptr[row + 1];
+    for (int j = 0; j < n; ++j) dptr[j + 1] += dptr[j];
+    dent.resize(crow.size());
+    std::vector<int> fill(dptr.begin(), dptr.end() - 1);
+    for (size_t e = 0; e < crow.size(); ++e) dent[fill[crow[e]]++] = (int)e;
+    V.dptr.upload(dptr.data(), n + 1, s);
+    V.dent.upload(dent.data(), dent.size(), s);
+    V.dd.ensure(crow.size());
+  } else {
+    V.rr.ensure(crow.size());
+  }
   HIP_CHECK(hipStreamSynchronize(s));  // the host vectors leave scope
 }
 
@@ -674,7 +761,29 @@ void sweep_g(hipStream_t s, VkLevel& V, const double* b, double* x, double omega
   HIP_LAUNCH_CHECK();
 }
 
-void sweep(hipStream_t s, VkLevel& V, const double* b, double* x, double omega) {
+// additive sweep: residual of x on the whole level, every local solve, the
+// averaged update
+template <int G>
+void sweep_additive_g(hipStream_t s, VkLevel& V, const double* b, double* x, double omega) {
+  const int n = V.nu + V.np;
+  k_vk_resid<G><<<div_up((long)n * G, 256), 256, 0, s>>>(V.nu, V.np, VK_BLOCKS(V), b, x, V.r.p);
+  const int chunks = div_up(V.mmax, 64);
+  k_vk_add_solve<<<V.np * chunks, 256, sizeof(double) * (V.mmax + 256), s>>>(
+      chunks, V.clist.p, V.roff.p, V.crow.p, V.r.p, V.luoff.p, V.inv.p, V.dd.p);
+  k_vk_add_gather<<<div_up(n, 256), 256, 0, s>>>(n, V.dptr.p, V.dent.p, V.dd.p, x, omega);
+  HIP_LAUNCH_CHECK();
+}
+
+void sweep(hipStream_t s, VkLevel& V, const double* b, double* x, double omega, bool additive) {
+  if (additive) {
+    switch (V.lanes) {
+      case 8: sweep_additive_g<8>(s, V, b, x, omega); break;
+      case 16: sweep_additive_g<16>(s, V, b, x, omega); break;
+      case 32: sweep_additive_g<32>(s, V, b, x, omega); break;
+      default: sweep_additive_g<64>(s, V, b, x, omega); break;
+    }
+    return;
+  }
   switch (V.lanes) {
     case 8: sweep_g<8>(s, V, b, x, omega); break;
     case 16: sweep_g<16>(s, V, b, x, omega); break;
@@ -701,8 +810,8 @@ void cycle(hipStream_t s, Coupled& V, int l) {
     return;
   }
   k_vk_zero<<<div_up(n, 256), 256, 0, s>>>(n, L.x.p);
-  for (int k = 0; k < V.steps; ++k) sweep(s, L, L.b.p, L.x.p, V.omega);
-  k_vk_resid<<<div_up((long)n * 8, 256), 256, 0, s>>>(L.nu, L.np, VK_BLOCKS(L), L.b.p, L.x.p, L.r.p);
+  for (int k = 0; k < V.steps; ++k) sweep(s, L, L.b.p, L.x.p, V.omega, V.additive);
+  k_vk_resid<8><<<div_up((long)n * 8, 256), 256, 0, s>>>(L.nu, L.np, VK_BLOCKS(L), L.b.p, L.x.p, L.r.p);
   HIP_LAUNCH_CHECK();
   VkLevel& N = V.L[l + 1];
   apply_block(s, N.nu, L.Ru, L.r.p, N.b.p, false);
@@ -710,7 +819,7 @@ void cycle(hipStream_t s, Coupled& V, int l) {
   cycle(s, V, l + 1);
   apply_block(s, L.nu, L.Pu, N.x.p, L.x.p, true);
   apply_block(s, L.np, L.Pp, N.x.p + N.nu, L.x.p + L.nu, true);
-  for (int k = 0; k < V.steps; ++k) sweep(s, L, L.b.p, L.x.p, V.omega);
+  for (int k = 0; k < V.steps; ++k) sweep(s, L, L.b.p, L.x.p, V.omega, V.additive);
 }
 
 }  // namespace
@@ -738,6 +847,7 @@ void vanka_setup(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {
   V.L.clear();
   V.omega = prm.vanka_omega;
   V.steps = prm.vanka_steps;
+  V.additive = prm.coupled == 2;
   hfsi_amg_params cp = prm;
   cp.smoother = 0;  // the component hierarchies give only P; their smoother data is unused
   cp.precision = 0;
@@ -820,7 +930,7 @@ void vanka_setup(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {
     L.x.ensure(n_l);
     L.b.ensure(n_l);
     L.r.ensure(n_l);
-    if (l + 1 < nl) vanka_level_data(c, L, singular.p);
+    if (l + 1 < nl) vanka_level_data(c, L, singular.p, V.additive);
   }
   // coarsest: explicit inverse
   VkLevel& Lc = V.L.back();
@@ -909,8 +1019,8 @@ void vanka_precond(hfsi_ctx* c, const double* r, double* z, const double* scale,
 
 // host copies for inspection: which 10 = Kuu, 11 = Kup, 12 = Kpu, 13 = Kpp
 // (= -C), 14 = patch colours (int32 per pressure unknown, in col), 15 = P_u,
-// 16 = P_p (which 15 / 16 on a level whose transfer is the identity, and
-// 14-16 on the coarsest level, are HFSI_E_ARG)
+// 16 = P_p (which 15 / 16 on a level whose transfer is the identity, 14-16 on
+// the coarsest level and 14 of the additive variant are HFSI_E_ARG)
 void vanka_export(hfsi_ctx* c, int level, int which, int32_t* rows, int32_t* cols, int64_t* nnz, int32_t* ptr,
                   int32_t* col, double* val) {
   if (!c->vanka_impl || !state(c).ready) fail(HFSI_E_ORDER, "amg_export: no coupled hierarchy");
@@ -924,6 +1034,7 @@ void vanka_export(hfsi_ctx* c, int level, int which, int32_t* rows, int32_t* col
   };
   if (which == 14) {
     if (last) fail(HFSI_E_ARG, "amg_export: the coarsest level has no patches");
+    if (V.additive) fail(HFSI_E_ARG, "amg_export: the additive variant has no colours");
     if (rows) *rows = L.np;
     if (cols) *cols = (int)L.cptr.size() - 1;
     if (nnz) *nnz = L.np;

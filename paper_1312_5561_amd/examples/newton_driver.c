@@ -3,7 +3,7 @@
  * load in increments with Newton's method (hfsi_newton_solve, Section
  * "Newton's Method") and writes the final state.
  *
- *   newton_driver <problem file> <increments> <state out> [adaptive 0/1] [weights]
+ *   newton_driver <problem file> <increments> <state out> [adaptive 0/1] [weights | coupled | additive]
  *
  * Problem file, little endian: int64 n, m, k; double X[n][3]; int32
  * tets[m][4]; int32 mat_id[m]; uint8 dir_mask[n][4]; int32 tris[k][3];
@@ -12,12 +12,18 @@
  * int32 lattice[n][3] (the integer lattice coordinates the learned
  * interpolation needs).  With a weight file (hfsi_mlp_load format) the
  * level-0 interpolation is the learned one under the classical judge and the
- * V-cycle runs in fp32; otherwise classical interpolation and an fp64 cycle.
+ * V-cycle runs in fp32; with the word "coupled" the linear systems are
+ * preconditioned by the coupled displacement-pressure AMG with the
+ * multiplicative Vanka smoother (omega 0.78, 6 sweeps; section "The
+ * multiplicative Vanka smoother"), with "additive" by the same hierarchy
+ * with the additive Vanka variant (omega 0.8, 6 sweeps); otherwise classical
+ * interpolation and an fp64 cycle.
  * State out: double v[n][4].  Exit status 0 when every increment converged. */
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
+#include <string.h>
 
 #include "hfsi.h"
 
@@ -33,7 +39,7 @@ static void* take(size_t bytes) {
 }
 
 /* defaults documented in hfsi.h */
-static hfsi_newton_solve_params default_params(int adaptive, int learned) {
+static hfsi_newton_solve_params default_params(int adaptive, int learned, int coupled) {
   hfsi_newton_solve_params p;
   hfsi_amg_params* a = &p.step.amg;
   hfsi_solve_params* s = &p.step.solve;
@@ -61,8 +67,8 @@ static hfsi_newton_solve_params default_params(int adaptive, int learned) {
   a->nu_pre_coarse = 0;
   a->judge_classical = 2;
   a->drop_tol = 0.0;
-  a->coupled = 0;
-  a->vanka_omega = 0.78;
+  a->coupled = coupled;
+  a->vanka_omega = coupled == 2 ? 0.8 : 0.78;
   a->vanka_steps = 6;
   s->struct_size = sizeof *s;
   s->tol = 1e-8;
@@ -89,12 +95,13 @@ static hfsi_newton_solve_params default_params(int adaptive, int learned) {
 
 int main(int argc, char** argv) {
   if (argc < 4) {
-    fprintf(stderr, "usage: %s <problem file> <increments> <state out> [adaptive] [weights]\n", argv[0]);
+    fprintf(stderr, "usage: %s <problem file> <increments> <state out> [adaptive] [weights | coupled | additive]\n", argv[0]);
     return 2;
   }
   const int increments = atoi(argv[2]);
   const int adaptive = argc > 4 ? atoi(argv[4]) : 0;
-  const char* weights = argc > 5 ? argv[5] : NULL;
+  const int coupled = argc <= 5 ? 0 : strcmp(argv[5], "coupled") == 0 ? 1 : strcmp(argv[5], "additive") == 0 ? 2 : 0;
+  const char* weights = argc > 5 && !coupled ? argv[5] : NULL;
   FILE* f = fopen(argv[1], "rb");
   if (!f || increments < 1) {
     fprintf(stderr, "cannot read %s or bad increment count\n", argv[1]);
@@ -164,7 +171,7 @@ int main(int argc, char** argv) {
     return 1;
   }
   if (weights) CHECK(hfsi_mlp_load(ctx, weights));
-  const hfsi_newton_solve_params prm = default_params(adaptive, weights != NULL);
+  const hfsi_newton_solve_params prm = default_params(adaptive, weights != NULL, coupled);
   int all = 1;
   for (int inc = 1; inc <= increments; ++inc) {
     hfsi_newton_solve_info info;

@@ -123,7 +123,9 @@ def amg_params(theta=0.15, max_coarse=500, max_levels=25, seed=12345, smoother=1
     their off-diagonal entries below drop_tol sqrt(|a_ii a_jj|) (0: exact
     Galerkin).  coupled=1: the coupled (u,p) AMG with the multiplicative
     Vanka smoother (relaxation vanka_omega, vanka_steps sweeps before and
-    after the coarse correction) replaces P_L."""
+    after the coarse correction) replaces P_L; coupled=2: the same with the
+    additive Vanka variant (corrections averaged over the patches of each
+    unknown)."""
     return AmgParams(C.sizeof(AmgParams), theta, max_coarse, max_levels, seed, smoother, nu_pre, nu_post,
                      precision, interp, fallback_rho, cheb_degree, cheb_ratio, interp_kind, p_max, cheb_degree_pre,
                      nu_post_coarse, cheb_degree_coarse, nu_pre_coarse, judge_classical, drop_tol, coupled,

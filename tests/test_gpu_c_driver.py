@@ -96,3 +96,22 @@ def test_c_driver_learned_weights(lib, tmp_path):
     r = subprocess.run([b.DRIVER, problem, "3", state, "0", train_mlp.DEFAULT_RAW_WEIGHTS], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2
+
+
+@pytest.mark.parametrize("variant", ["coupled", "additive"])
+def test_c_driver_coupled_vanka(lib, tmp_path, variant):
+    """The C program with the coupled displacement-pressure AMG and the
+    multiplicative Vanka smoother (amg params coupled = 1) or its additive
+    variant (coupled = 2) as the preconditioner: the load run reaches the
+    oracle's converged states."""
+    from paper_1312_5561_amd import build as b
+    prob = synth.cube_problem(6, jitter=0.1, seed=4)
+    problem, state = str(tmp_path / "cube6v.bin"), str(tmp_path / "state.bin")
+    _write_problem(prob, problem, lattice=False)
+    print(f"[c driver] cube6 {variant} Vanka AMG, 3 increments", flush=True)
+    r = subprocess.run([b.DRIVER, problem, "3", state, "0", variant], capture_output=True, text=True, timeout=120)
+    print(r.stdout, flush=True)
+    assert r.returncode == 0, r.stderr
+    v = np.fromfile(state, np.float64)
+    vo = newton.load_run(fe.Discretization(prob), 3, newton.NewtonParams())
+    assert np.linalg.norm(v - vo) <= 1e-9 * np.linalg.norm(vo)

@@ -6,7 +6,7 @@ extended+i weights are accumulated per neighbour group in a fixed order, so
 two fresh contexts (and two calls on one context) must produce identical
 residuals, tangents, hierarchies, Krylov solutions and Newton updates, in
 the fp64 and the fp32 cycle, with the block preconditioner and with the
-coupled Vanka cycle.
+coupled Vanka cycle (multiplicative and additive).
 """
 import numpy as np
 import pytest
@@ -50,7 +50,7 @@ def _same_csr(A, B):
             and np.array_equal(A.data, B.data))
 
 
-@pytest.mark.parametrize("case", ["fp64", "fp32", "l1jacobi_bicgstab", "coupled"])
+@pytest.mark.parametrize("case", ["fp64", "fp32", "l1jacobi_bicgstab", "coupled", "coupled_additive"])
 def test_two_runs_are_bit_identical(lib, case):
     prob = synth.cube_problem(10, jitter=0.1, seed=4)
     v = synth.random_state(prob, 5, u_scale=0.03, p_scale=0.05).ravel()
@@ -62,8 +62,10 @@ def test_two_runs_are_bit_identical(lib, case):
     elif case == "l1jacobi_bicgstab":
         prm = lib.amg_params(precision=1, max_coarse=80, smoother=0)
         method = 1
-    else:
+    elif case == "coupled":
         prm = lib.amg_params(max_coarse=80, coupled=1, vanka_steps=2)
+    else:
+        prm = lib.amg_params(max_coarse=80, coupled=2, vanka_steps=2, vanka_omega=0.8)
     print(f"[determinism] {case}", flush=True)
     a = _run(lib, prob, v, prm, method)
     b = _run(lib, prob, v, prm, method)

@@ -16,7 +16,12 @@ same state; nothing it uses comes from the GPU.  Compared:
   oracle's direct solve of the same Newton system;
 * at 24^3 (three levels of patches, 15,625 patches on level 0): blocks and
   colours of level 0 bit-exact with the oracle, and the solve's residual
-  checked on the host.
+  checked on the host;
+* the additive variant (coupled = 2, corrections averaged over the patches
+  of each unknown): the same hierarchy blocks, no colours (export 14 is an
+  error), one V-cycle entry by entry to 1e-10 relative, the AMG method with
+  the oracle's count of V-cycles and FGMRES within one iteration, and the
+  24^3 solve checked on the host.
 """
 import numpy as np
 import pytest
@@ -30,10 +35,10 @@ from oracle import amg, fe, krylov, vanka
 pytestmark = pytest.mark.gpu
 
 
-def _params(lib, omega=0.78, steps=2, max_coarse=150, theta=0.15, seed=12345):
-    g = lib.amg_params(coupled=1, vanka_omega=omega, vanka_steps=steps, max_coarse=max_coarse, theta=theta,
-                       seed=seed, interp_kind=1, p_max=4)
-    o = vanka.VankaParams(omega=omega, steps=steps,
+def _params(lib, omega=0.78, steps=2, max_coarse=150, theta=0.15, seed=12345, additive=False):
+    g = lib.amg_params(coupled=2 if additive else 1, vanka_omega=omega, vanka_steps=steps, max_coarse=max_coarse,
+                       theta=theta, seed=seed, interp_kind=1, p_max=4)
+    o = vanka.VankaParams(omega=omega, steps=steps, additive=additive,
                           amg=amg.AmgParams(theta=theta, max_coarse=max_coarse, seed=seed, interp="ext+i", p_max=4,
                                             smoother="l1jacobi"))
     return g, o
@@ -185,3 +190,73 @@ def test_full_size_blocks_colours_and_solve(lib):
     assert code == 0
     assert np.linalg.norm(b - K @ x.cpu().numpy()) <= 1e-8 * np.linalg.norm(b)
     print(f"  AMG iterations {si.iterations} in {si.seconds:.3f} s", flush=True)
+
+
+@pytest.mark.parametrize("law,N,steps,omega", [("mr", 6, 2, 0.8), ("mr", 8, 6, 0.8), ("artery", 4, 6, 0.86)])
+def test_additive_vcycle_matches_oracle(lib, law, N, steps, omega):
+    import torch
+    prob = _problem(N, law)
+    v = synth.random_state(prob, 5, u_scale=0.03, p_scale=0.05).ravel()
+    print(f"[vanka additive cycle] {law} N={N} steps={steps} omega={omega}", flush=True)
+    g, o = _params(lib, omega=omega, steps=steps, additive=True)
+    ctx, info, R, d, K, b, blocks, CH = _both(lib, prob, v, 0.4, g, o)
+    assert info.levels == len(CH.levels)
+    for lev, L in enumerate(CH.levels):
+        for which, M in ((10, L.Kuu), (11, L.Kup), (12, L.Kpu), (13, L.Kpp)):
+            _same(_export(ctx, lev, which), M, f"level {lev} block {which}")
+    with pytest.raises(RuntimeError):
+        ctx.amg_export(0, 14)
+    n = prob.n_nodes
+    r = np.random.default_rng(6).normal(size=4 * n)
+    z = torch.zeros(4 * n, dtype=torch.float64, device="cuda")
+    ctx.apply_preconditioner(torch_dev(r), z)
+    zo = vanka.preconditioner(CH, n, o)(r)
+    zg = z.cpu().numpy()
+    assert np.abs(zg - zo).max() <= 1e-10 * np.abs(zo).max()
+
+
+@pytest.mark.parametrize("law,N,steps,omega", [("mr", 6, 2, 0.8), ("artery", 4, 12, 0.86)])
+def test_additive_amg_iteration_and_fgmres_match_oracle(lib, law, N, steps, omega):
+    """The additive cycle needs more sweeps than the multiplicative one on
+    the artery (with 6 the stationary iteration diverges on this tube)."""
+    import torch
+    prob = _problem(N, law)
+    v = synth.random_state(prob, 7, u_scale=0.03, p_scale=0.05).ravel()
+    print(f"[vanka additive solve] {law} N={N} steps={steps}", flush=True)
+    g, o = _params(lib, omega=omega, steps=steps, additive=True)
+    ctx, info, R, d, K, b, blocks, CH = _both(lib, prob, v, 0.4, g, o)
+    n = prob.n_nodes
+    bt = torch_dev(b)
+    x = torch.zeros_like(bt)
+    si, code = ctx.krylov_amg_solve(bt, x, lib.solve_params(tol=1e-8, max_iter=60, method=2))
+    xo, hist = vanka.amg_iteration(CH, K, b, n, o, tol=1e-8, maxit=60)
+    assert code == 0 and si.converged
+    assert si.iterations == len(hist) - 1, (si.iterations, len(hist) - 1)
+    xg = x.cpu().numpy()
+    assert np.linalg.norm(b - K @ xg) <= 1e-8 * np.linalg.norm(b)
+    assert np.abs(xg - xo).max() <= 1e-7 * np.abs(xo).max()
+    x.zero_()
+    si2, code2 = ctx.krylov_amg_solve(bt, x, lib.solve_params(tol=1e-8, restart=50, max_iter=200))
+    xo2, oi = krylov.fgmres(K, vanka.preconditioner(CH, n, o), b, m=50, tol=1e-8)
+    assert code2 == 0 and oi.converged
+    assert abs(si2.iterations - oi.iterations) <= 1, (si2.iterations, oi.iterations)
+    assert np.linalg.norm(b - K @ x.cpu().numpy()) <= 1e-8 * np.linalg.norm(b)
+
+
+def test_additive_full_size_solve(lib):
+    import torch
+    N = 24
+    prob = synth.cube_problem(N)
+    v = np.zeros(prob.n_dofs)
+    print(f"[vanka additive 24^3] {prob.n_dofs} dofs", flush=True)
+    g, o = _params(lib, omega=0.8, steps=6, max_coarse=500, additive=True)
+    ctx, info, R, d, K, b, blocks, _ = _both(lib, prob, v, 1.0, g, o, oracle_hierarchy=False)
+    Kuu, Kup, Kpu, Kpp = blocks
+    for which, M in ((10, Kuu), (11, Kup), (12, Kpu), (13, Kpp)):
+        _same(_export(ctx, 0, which), M, f"block {which}")
+    bt = torch_dev(b)
+    x = torch.zeros_like(bt)
+    si, code = ctx.krylov_amg_solve(bt, x, lib.solve_params(tol=1e-8, restart=100, max_iter=200))
+    assert code == 0 and si.converged
+    assert np.linalg.norm(b - K @ x.cpu().numpy()) <= 1e-8 * np.linalg.norm(b)
+    print(f"  levels {info.levels} FGMRES iterations {si.iterations} in {si.seconds:.3f} s", flush=True)
