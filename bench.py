@@ -262,8 +262,9 @@ def vanka_leg(N, steps, kappa, torch, hfsi):
     torch.cuda.synchronize()
     out["additive_setup"] = {"seconds": time.perf_counter() - t0, "levels": ai.levels, "vanka_steps": steps,
                              "omega": 0.8}
+    # (as a stationary iteration the additive cycle diverges at this size:
+    # only its use inside FGMRES is timed)
     solve(hfsi.solve_params(tol=1e-8, restart=100, max_iter=300), "additive_fgmres")
-    solve(hfsi.solve_params(tol=1e-8, max_iter=200, method=2), "additive_amg_iteration")
     for prec in (0, 1):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -500,8 +501,7 @@ def main():
         print(f"[bench] coupled Vanka AMG at {args.vanka_N}^3: FGMRES {cv['coupled_fgmres']['iterations']} its "
               f"{cv['coupled_fgmres']['seconds']:.2f} s, AMG iteration {cv['coupled_amg_iteration']['iterations']} "
               f"its; additive: FGMRES {cv['additive_fgmres']['iterations']} its "
-              f"{cv['additive_fgmres']['seconds']:.3f} s (set-up {cv['additive_setup']['seconds']:.2f} s), AMG "
-              f"iteration {cv['additive_amg_iteration']['iterations']} its; "
+              f"{cv['additive_fgmres']['seconds']:.3f} s (set-up {cv['additive_setup']['seconds']:.2f} s); "
               f"P_L fp32 FGMRES {cv['pl_fgmres_fp32']['iterations']} its "
               f"{cv['pl_fgmres_fp32']['seconds'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
     # the headline state's tangent for the roofline timing
