@@ -13,7 +13,12 @@ interaction problems with hyperelastic models I: a partitioned approach"):
 * ``krylov``  the block-triangular preconditioner and FGMRES;
 * ``newton``  the Newton loop with the mass-norm stopping rule;
 * ``mlp``     the learned-interpolation network: features, forward,
-              backward, loss and the local ideal-interpolation target.
+              backward, loss and the local ideal-interpolation target;
+* ``newmark`` the Newmark-beta update of the structure;
+* ``vanka``   the coupled (u, p) AMG with the Vanka smoother;
+* ``fluid``   the stabilised P1-P1 fluid step on a moving mesh and the
+              harmonic mesh extension;
+* ``fsi``     the Dirichlet-Neumann iteration with Aitken relaxation.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import it.  It shares no code with the HIP library and

@@ -16,4 +16,6 @@ from .meshes import (  # noqa: F401
     uniaxial_problem,
     random_state,
     config_problem,
+    FsiModel,
+    fsi_duct,
 )

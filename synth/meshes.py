@@ -292,3 +292,97 @@ def config_problem(name: str, kappa=None, N=None):
 __all__ = ["Problem", "cube_mesh", "tube_mesh", "boundary_faces", "cube_problem",
            "tube_problem", "uniaxial_problem", "random_state", "config_problem",
            "mooney_rivlin", "artery_layer", "KUHN_PERMS"]
+
+
+# ---------------------------------------------------------------------------
+# fluid-structure model: a straight duct with a compliant wall
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class FsiModel:
+    """Matching fluid and structure meshes of a straight duct of square
+    cross-section (lumen half-width ``half_width``) inside a wall of
+    thickness ``wall``, axis z from 0 to ``length``; both meshes are subsets
+    of one tensor lattice of hexahedra split into Kuhn tetrahedra, so the
+    interface nodes coincide.
+
+    Fluid: nodes ``fluid_X`` [nf,3], tetrahedra ``fluid_tets``; Dirichlet
+    velocity on the interface nodes; inlet triangles on z = 0 (traction
+    (0, 0, p_in) per unit area), do-nothing outlet on z = length.
+    Structure: ``solid`` (a Problem with both ends clamped, no traction).
+    Interface: ``iface_f`` / ``iface_s``, the interface nodes in fluid and
+    structure numbering (same order).  ``fluid_boundary`` flags every fluid
+    boundary node (the harmonic extension prescribes them all).
+    """
+    fluid_X: np.ndarray
+    fluid_tets: np.ndarray
+    fluid_dir: np.ndarray        # u8 [nf,4]: 1 = velocity dof prescribed (interface)
+    inlet_tris: np.ndarray       # i32 [k,3] fluid inlet triangles
+    fluid_boundary: np.ndarray   # bool [nf]
+    solid: Problem
+    iface_f: np.ndarray
+    iface_s: np.ndarray
+    fluid_lattice: np.ndarray
+
+    @property
+    def nf(self):
+        return self.fluid_X.shape[0]
+
+
+def _graded(a, t, half_width, wall):
+    """Lattice coordinates -(a+t) .. a+t: a cells of the lumen on each side
+    of the axis, then t wall cells."""
+    idx = np.arange(-(a + t), a + t + 1)
+    s = np.abs(idx)
+    x = np.where(s <= a, half_width * s / a, half_width + wall * (s - a) / max(t, 1))
+    return idx, np.sign(idx) * x
+
+
+def fsi_duct(a=3, t=2, n_z=36, half_width=1.43, wall=0.39, length=18.0, c10=3.0, c01=0.3, kappa=1e5):
+    """FSI model of the paper's experiments (lengths in mm, Mooney-Rivlin
+    wall c10 = 3 kPa, c01 = 0.3 kPa, kappa = 1e5 kPa) on a square duct."""
+    idx, coord = _graded(a, t, half_width, wall)
+    nl = len(idx)
+    k3, j3, i3 = np.meshgrid(np.arange(n_z + 1), np.arange(nl), np.arange(nl), indexing="ij")
+    lat = np.stack([i3.ravel(), j3.ravel(), k3.ravel()], axis=1)
+    X = np.stack([coord[lat[:, 0]], coord[lat[:, 1]], length * lat[:, 2] / n_z], axis=1)
+
+    def node_id(i, j, k):
+        return i + nl * (j + nl * k)
+
+    tets, hex_ijk = _lattice_tets((nl - 1, nl - 1, n_z), node_id)
+    tets = _orient(X, tets)
+    hi, hj = hex_ijk[:, 0] - (a + t), hex_ijk[:, 1] - (a + t)   # cell lower corner in signed index
+    fluid_cell = (hi >= -a) & (hi < a) & (hj >= -a) & (hj < a)
+
+    def submesh(sel):
+        T = tets[sel]
+        used = np.unique(T)
+        g2l = -np.ones(len(X), np.int64)
+        g2l[used] = np.arange(len(used))
+        return used, g2l[T].astype(np.int32)
+
+    gf, Tf = submesh(fluid_cell)
+    gs, Ts = submesh(~fluid_cell)
+    both = np.intersect1d(gf, gs)
+    iface_f = np.searchsorted(gf, both).astype(np.int64)
+    iface_s = np.searchsorted(gs, both).astype(np.int64)
+    # fluid boundary data
+    latf = lat[gf]
+    nf = len(gf)
+    fdir = np.zeros((nf, 4), np.uint8)
+    fdir[iface_f, 0:3] = 1
+    bf = boundary_faces(Tf)
+    inlet = bf[np.all(latf[bf][:, :, 2] == 0, axis=1)]
+    fb = np.zeros(nf, bool)
+    fb[np.unique(bf)] = True
+    # structure: both ends clamped, loaded through the interface only
+    lats = lat[gs]
+    ns = len(gs)
+    dm = np.zeros((ns, 4), np.uint8)
+    dm[(lats[:, 2] == 0) | (lats[:, 2] == n_z), 0:3] = 1
+    solid = Problem(X[gs], Ts, np.zeros(len(Ts), np.int32), [mooney_rivlin(c10, c01, kappa)], dm,
+                    np.zeros((0, 3), np.int32), np.zeros((0, 3)), lats.astype(np.int32), None,
+                    name=f"duct_wall{a}x{t}x{n_z}")
+    return FsiModel(X[gf], Tf, fdir, inlet.astype(np.int32), fb, solid, iface_f, iface_s,
+                    latf.astype(np.int32))
