@@ -286,6 +286,12 @@ typedef struct {
                                no admissible a ends the call with
                                HFSI_NOT_CONVERGED and v at the last accepted
                                state.  0: full steps (default)              */
+  double ref_norm;          /* > 0: the reference of the relative rule,
+                               ||dv_k||_M <= eps2 ref_norm from k = 0 on, in
+                               place of ||dv_0||_M (a solve warm-started
+                               inside an outer iteration passes the first
+                               correction of its first, cold solve); 0 =
+                               this call's first correction (default)       */
 } hfsi_newton_solve_params;
 
 typedef struct {
@@ -430,6 +436,107 @@ hfsi_status hfsi_newton_solve(hfsi_ctx* ctx, double* v, double load, const hfsi_
  * hold a partial Newton iterate.  HFSI_E_ORDER when inertia is off. */
 hfsi_status hfsi_time_step(hfsi_ctx* ctx, double* v, double* vel, double* acc, double load,
                            const hfsi_newton_solve_params* prm, hfsi_newton_solve_info* info);
+
+/* ------------------------------------------- fluid and partitioned FSI */
+
+/* Switch a context to the fluid sub-problem (section "The fluid
+ * sub-problem", eq. ns; implicit Euler, eq. nstdis; weak form eq. weakns
+ * with SUPG/PSPG stabilisation, eq. stabweakfluid): rho > 0 fluid density,
+ * mu >= 0 dynamic viscosity, dt > 0 time step.  Needs a mesh (stage 1);
+ * set_materials (any valid record: unused by the fluid) and set_bc (dir_mask
+ * fixes the velocity dofs with prescribed values, e.g. the interface; the
+ * triangles and their traction are the inlet Neumann data g_in at load
+ * factor 1) complete it.  The state vector keeps the node-interleaved layout
+ * (u_x, u_y, u_z, p).  From then on hfsi_assemble_residual_tangent,
+ * hfsi_newton_step and hfsi_newton_solve work on the fluid step on the mesh
+ * X + d_f: per tetrahedron, with c = u - w, the strong residual per unit
+ * mass r = (u - u_old)/dt + (c.grad)u + grad p/rho and tau =
+ * ((2/dt)^2 + (2|c_mean|/h)^2 + (4 mu/(rho h^2))^2)^(-1/2) (c_mean the mean
+ * of c over the corners, h the longest current edge),
+ *   R^u_a = int [rho (u - u_old)/dt + rho (c.grad)u] N_a
+ *           + 2 mu (eps(u), eps(N_a)) - (p, div N_a) + rho tau int (c.grad N_a) r
+ *   R^p_a = -(N_a, div u) - tau int grad N_a . r,
+ * exact 4-point quadrature, the Jacobian exact at fixed tau, and P_L's
+ * Schur diagonal s_i = C_ii + sum_j B2_ij B1^T_ji / A_jj.  The mesh
+ * displacement d_f, the previous velocity u_old and the mesh velocity w
+ * start at zero (hfsi_set_fluid_fields).  A later hfsi_set_mesh returns the
+ * context to the structure.  HFSI_E_ARG on bad values. */
+hfsi_status hfsi_set_fluid(hfsi_ctx* ctx, double rho, double mu, double dt);
+
+/* Device fields [n][3] of a fluid context, each copied when not NULL: mesh
+ * displacement d_f, previous step's velocity u_old (nodal values: the ALE
+ * map carries nodes to nodes), mesh velocity w.  HFSI_E_ORDER when the
+ * context is not a fluid. */
+hfsi_status hfsi_set_fluid_fields(hfsi_ctx* ctx, const double* dmesh, const double* u_old, const double* w);
+
+/* Switch a context (after set_materials) to the P1 Laplacian of its
+ * reference mesh on each displacement component (eq. harext): R^u_a =
+ * sum_b V (G_a . G_b) d_b, pressure rows empty.  With every boundary node's
+ * displacement and every pressure fixed in set_bc, one hfsi_newton_step
+ * from a state holding the boundary values leaves the harmonic extension
+ * in it. */
+hfsi_status hfsi_set_mesh_laplace(hfsi_ctx* ctx);
+
+/* Force device f [count][3] that the fluid exerts on the wall at host
+ * nodes [count]: minus the momentum rows of the fluid residual at state v
+ * (device [N]) and inlet load factor `load`, before the Dirichlet rows are
+ * replaced (by Green's formula that residual is the boundary integral of
+ * sigma n_f N_a).  HFSI_E_INVERTED if the moved mesh has an inverted
+ * element. */
+hfsi_status hfsi_fluid_interface_force(hfsi_ctx* ctx, const double* v, double load, int32_t count,
+                                       const int32_t* nodes, double* f);
+
+typedef struct {
+  size_t struct_size;
+  double omega0;        /* first Aitken factor of every time step, > 0     */
+  double eps;           /* stop at |r_k| / sqrt(n_iface) < eps (the paper: 1e-8) */
+  int32_t max_dn;       /* at most this many DN iterations, 1..128          */
+  double eps2;          /* the nested Newton rule eq. newstop, e.g. 1e-10   */
+  hfsi_newton_params fluid_step;  /* AMG and Krylov settings of the fluid  */
+  hfsi_newton_params solid_step;  /* ... of the structure                  */
+  hfsi_newton_params mesh_step;   /* ... of the harmonic extension (one
+                                     linear solve per DN iteration)         */
+} hfsi_fsi_params;
+
+typedef struct {
+  size_t struct_size;
+  int32_t dn_iterations;
+  int32_t converged;
+  int32_t fluid_newton;   /* Newton iterations summed over the DN iterations */
+  int32_t solid_newton;
+  int32_t krylov;         /* Krylov iterations of all nested solves          */
+  double residual[128];   /* |r_k| / sqrt(n_iface) of DN iteration k+1      */
+  double omega[128];      /* the factor applied after DN iteration k+1       */
+  double seconds;
+} hfsi_fsi_info;
+
+/* One time step of the partitioned FSI problem by the Dirichlet-Neumann
+ * iteration (section "A Dirichlet-Neumann FSI iteration") with Aitken
+ * relaxation (eq. acceit, eq. dnomega).  Contexts: `fluid` (hfsi_set_fluid,
+ * velocity fixed on the interface), `mesh` (hfsi_set_mesh_laplace on the
+ * same fluid mesh, every boundary displacement and every pressure fixed),
+ * `solid` (a structure with Newmark inertia, hfsi_set_newmark, its step
+ * equal to the fluid's dt); host iface_f / iface_s [n_iface]: the interface
+ * nodes in fluid and structure numbering, pairwise the same points.  Device
+ * state at t^{n-1}, advanced in place to t^n: vf [4 nf] fluid (u, p), df
+ * [nf][3] mesh displacement, vs [4 ns], vel, acc [ns][3] structure.  Each
+ * DN iteration extends the interface displacement d_G harmonically into the
+ * fluid mesh (mesh velocity w = (d_f - d_f^{n-1})/dt), solves the fluid with
+ * u = w on the interface and the inlet traction scaled by inlet_load, takes
+ * the fluid's force on the wall as the structure's nodal load and solves the
+ * structure; r_k = d_G(structure) - d_G, stop when |r_k|/sqrt(n_iface) <
+ * eps, else d_G += omega_k r_k with omega from eq. dnomega (omega0 first).
+ * The first d_G is the structure's interface displacement at t^{n-1}; every
+ * nested Newton solve continues from its latest iterate with the rule of
+ * eq. newstop relative to the first correction of its sub-problem in this
+ * step (hfsi_newton_solve_params.ref_norm).  The contexts' streams are
+ * synchronised at every hand-over.  HFSI_NOT_CONVERGED after max_dn
+ * iterations (state partly advanced); a failing nested solve returns its
+ * status with the sub-problem named in hfsi_last_error(fluid). */
+hfsi_status hfsi_fsi_time_step(hfsi_ctx* fluid, hfsi_ctx* mesh, hfsi_ctx* solid, int32_t n_iface,
+                               const int32_t* iface_f, const int32_t* iface_s, double* vf, double* df, double* vs,
+                               double* vel, double* acc, double inlet_load, const hfsi_fsi_params* prm,
+                               hfsi_fsi_info* info);
 
 /* ------------------------------------------------ inspection and testing */
 

@@ -493,18 +493,24 @@ void assemble(hfsi_ctx* c, const double* v, double load, double* R, hfsi_assembl
   HIP_CHECK(hipMemsetAsync(c->Kval.p, 0, sizeof(double) * 16 * (size_t)c->nb, s));
   k_init_flags<<<1, 1, 0, s>>>(c->iscal.p, (unsigned long long*)c->scal.p);
   HIP_LAUNCH_CHECK();
-  for (size_t q = 0; q + 1 < c->colour_ptr.size(); ++q) {
-    int e0 = c->colour_ptr[q], e1 = c->colour_ptr[q + 1];
-    k_element<<<div_up(e1 - e0, 128), 128, 0, s>>>(e0, e1, m, c->tets.p, c->mat.p, c->mtab.p, c->G.p, c->V.p, c->h.p,
-                                                   c->has_fib ? c->fib.p : nullptr, c->slot.p, v, R, c->Kval.p, 1,
-                                                   (unsigned long long*)c->scal.p, c->iscal.p, c->cm,
-                                                   c->cm > 0.0 ? c->rs.p : nullptr);
-    HIP_LAUNCH_CHECK();
+  const int physics = physics_of(c);
+  if (physics != 0) {
+    fluid_elements(c, v, R, true);
+  } else {
+    for (size_t q = 0; q + 1 < c->colour_ptr.size(); ++q) {
+      int e0 = c->colour_ptr[q], e1 = c->colour_ptr[q + 1];
+      k_element<<<div_up(e1 - e0, 128), 128, 0, s>>>(e0, e1, m, c->tets.p, c->mat.p, c->mtab.p, c->G.p, c->V.p,
+                                                     c->h.p, c->has_fib ? c->fib.p : nullptr, c->slot.p, v, R,
+                                                     c->Kval.p, 1, (unsigned long long*)c->scal.p, c->iscal.p, c->cm,
+                                                     c->cm > 0.0 ? c->rs.p : nullptr);
+      HIP_LAUNCH_CHECK();
+    }
   }
   k_residual_bc<<<div_up(n, 256), 256, 0, s>>>(n, load, c->fext.p, c->dir.p, R);
   HIP_LAUNCH_CHECK();
   k_dirichlet_K<<<div_up(16 * (long)c->nb, 256), 256, 0, s>>>(c->nb, c->brow.p, c->ncol.p, c->dir.p, c->Kval.p);
   HIP_LAUNCH_CHECK();
+  if (physics == 1) fluid_schur(c);
   k_gather<<<div_up(c->A.nnz, 256), 256, 0, s>>>((int)c->A.nnz, c->a_src.p, c->Kval.p, c->A.val.p);
   HIP_LAUNCH_CHECK();
   c->b2.ensure(3 * (size_t)c->nb);

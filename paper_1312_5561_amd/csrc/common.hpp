@@ -295,6 +295,7 @@ struct hfsi_ctx {
   hfsi::DevBuf<int> iscal;       // device integer scalars
   void* mlp_impl = nullptr;      // learned-interpolation state (mlp.hip)
   void* vanka_impl = nullptr;    // coupled (u,p) AMG with the Vanka smoother (vanka.hip)
+  void* fluid_impl = nullptr;    // fluid or mesh-Laplacian physics (fluid.hip); null: the structure
   int precond_kind = 0;          // preconditioner of the last set-up: 0 P_L, 1 coupled V-cycle
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t kev[2] = {nullptr, nullptr};  // FGMRES scalar read-back slots
@@ -346,6 +347,12 @@ void vanka_invalidate(hfsi_ctx* c);
 void vanka_free(hfsi_ctx* c);
 void vanka_export(hfsi_ctx* c, int level, int which, int32_t* rows, int32_t* cols, int64_t* nnz, int32_t* ptr,
                   int32_t* col, double* val);
+// fluid and mesh-Laplacian contexts (fluid.hip): physics 0 structure, 1
+// fluid, 2 mesh Laplacian
+int physics_of(const hfsi_ctx* c);
+void fluid_elements(hfsi_ctx* c, const double* v, double* R, bool want_K);
+void fluid_schur(hfsi_ctx* c);
+void fluid_free(hfsi_ctx* c);
 // resolve the allocation-free entry point's scratch address on `device`
 // (the current device); called once per context creation
 void noalloc_scratch_init(int device);

@@ -227,7 +227,7 @@ void colour_elements(int n, int m, const int32_t* tets, std::vector<int>& perm, 
 
 // ================================================================== ABI
 
-extern "C" int32_t hfsi_abi_version(void) { return 7; }
+extern "C" int32_t hfsi_abi_version(void) { return 8; }
 
 namespace {
 std::atomic<int> g_live_contexts{0};  // the device block cache is trimmed when none is left
@@ -293,6 +293,7 @@ extern "C" hfsi_status hfsi_destroy(hfsi_ctx* c) {
   release_events(c);
   hfsi::mlp_free(c);
   hfsi::vanka_free(c);
+  hfsi::fluid_free(c);
   delete c;
   hfsi::tls_idle = false;
   if (--g_live_contexts == 0) hfsi::dev_cache_trim();
@@ -322,9 +323,10 @@ extern "C" hfsi_status hfsi_set_mesh(hfsi_ctx* c, int64_t n_nodes, const double*
   c->H.ready = false;
   hfsi::vanka_invalidate(c);
   c->H.reusable = false;
-  c->nm_rho = 0.0;  // a new mesh starts quasi-static
+  c->nm_rho = 0.0;  // a new mesh starts quasi-static, as a structure
   c->cm = 0.0;
   c->rs.release();
+  hfsi::fluid_free(c);
   colour_elements(n, m, tets, c->perm, c->colour_ptr);
 
   // element arrays in colour order, structure of arrays

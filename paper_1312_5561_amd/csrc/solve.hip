@@ -1867,6 +1867,7 @@ extern "C" hfsi_status hfsi_newton_solve(hfsi_ctx* c, double* v, double load, co
       !(prm->eps1_min > 0.0) || !(prm->eps1_max >= prm->eps1_min) || !(prm->eps1_max < 1.0))
     fail(HFSI_E_ARG, "newton solve params: need eps2 > 0, max_newton >= 1, 0 < eps1_min <= eps1_max < 1");
   if (prm->line_search < 0 || prm->line_search > 1) fail(HFSI_E_ARG, "newton solve params: line_search 0 or 1");
+  if (!(prm->ref_norm >= 0.0)) fail(HFSI_E_ARG, "newton solve params: ref_norm >= 0");
   if (info && info->struct_size != sizeof(hfsi_newton_solve_info))
     fail(HFSI_E_ARG, "newton solve info: struct_size mismatch");
   auto t_start = std::chrono::steady_clock::now();
@@ -1894,8 +1895,11 @@ extern "C" hfsi_status hfsi_newton_solve(hfsi_ctx* c, double* v, double load, co
     // an earlier call on this mesh (e.g. the previous time step)
     const bool reuse = prm->step.amg_reuse == 2 || (k > 0 && prm->step.amg_reuse == 1);
     double alpha = 1.0;
+    // the reference of the relative rule: the caller's, else this call's
+    // first correction
     newton_iteration(c, v, load, prm->step.amg, sp, reuse, &ni, prm->line_search ? &alpha : nullptr,
-                     k > 0 ? prm->eps2 * dv0 : dv_floor);
+                     prm->ref_norm > 0.0 ? std::max(prm->eps2 * prm->ref_norm, k == 0 ? dv_floor : 0.0)
+                                         : (k > 0 ? prm->eps2 * dv0 : dv_floor));
     ++its;
     kry += ni.krylov_iterations;
     if (k == 0) dv0 = ni.dv_mass_norm;
@@ -1911,7 +1915,8 @@ extern "C" hfsi_status hfsi_newton_solve(hfsi_ctx* c, double* v, double load, co
       done = true;
       break;
     }
-    done = (dv0 == 0.0 || ni.dv_mass_norm <= prm->eps2 * dv0) && alpha == 1.0;
+    if (prm->ref_norm > 0.0) done = ni.dv_mass_norm <= prm->eps2 * prm->ref_norm && alpha == 1.0;
+    else done = (dv0 == 0.0 || ni.dv_mass_norm <= prm->eps2 * dv0) && alpha == 1.0;
   }
   if (info) {
     info->newton_iterations = its;

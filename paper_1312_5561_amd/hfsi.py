@@ -87,13 +87,25 @@ class NewtonInfo(C.Structure):
 class NewtonSolveParams(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("step", NewtonParams), ("eps2", C.c_double),
                 ("max_newton", C.c_int32), ("adaptive", C.c_int32), ("eps1_max", C.c_double),
-                ("eps1_min", C.c_double), ("line_search", C.c_int32)]
+                ("eps1_min", C.c_double), ("line_search", C.c_int32), ("ref_norm", C.c_double)]
 
 
 class NewtonSolveInfo(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("newton_iterations", C.c_int32), ("krylov_iterations", C.c_int32),
                 ("converged", C.c_int32), ("dv_mass_norm", C.c_double * 32), ("eps1", C.c_double * 32),
                 ("krylov", C.c_int32 * 32), ("seconds", C.c_double), ("step_length", C.c_double * 32)]
+
+
+class FsiParams(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("omega0", C.c_double), ("eps", C.c_double), ("max_dn", C.c_int32),
+                ("eps2", C.c_double), ("fluid_step", NewtonParams), ("solid_step", NewtonParams),
+                ("mesh_step", NewtonParams)]
+
+
+class FsiInfo(C.Structure):
+    _fields_ = [("struct_size", C.c_size_t), ("dn_iterations", C.c_int32), ("converged", C.c_int32),
+                ("fluid_newton", C.c_int32), ("solid_newton", C.c_int32), ("krylov", C.c_int32),
+                ("residual", C.c_double * 128), ("omega", C.c_double * 128), ("seconds", C.c_double)]
 
 
 class TrainParams(C.Structure):
@@ -144,11 +156,24 @@ def newton_params(amg=None, solve=None, amg_reuse=0):
 
 
 def newton_solve_params(step=None, eps2=1e-10, max_newton=25, adaptive=0, eps1_max=1e-2, eps1_min=1e-12,
-                        line_search=0):
+                        line_search=0, ref_norm=0.0):
     """adaptive=1: inner tolerance eps_1,k = (||dv_k-1||_M / ||dv_0||_M)^2;
-    line_search=1: damped Newton (backtracking on ||R||_2)."""
+    line_search=1: damped Newton (backtracking on ||R||_2); ref_norm > 0:
+    the reference of the relative stopping rule in place of ||dv_0||_M."""
     return NewtonSolveParams(C.sizeof(NewtonSolveParams), step or newton_params(), eps2, max_newton, adaptive,
-                             eps1_max, eps1_min, line_search)
+                             eps1_max, eps1_min, line_search, ref_norm)
+
+
+def fsi_params(omega0=0.05, eps=1e-8, max_dn=100, eps2=1e-10, fluid_step=None, solid_step=None, mesh_step=None):
+    """Dirichlet-Neumann iteration with Aitken relaxation; the nested
+    solves default to FGMRES(100) with P_L: l1-Jacobi AMG for the fluid,
+    the library defaults for the structure, and a 1e-12 solve for the mesh
+    extension."""
+    fluid_step = fluid_step or newton_params(amg=amg_params(smoother=0, nu_pre=2, nu_post=2),
+                                             solve=solve_params(tol=1e-10, restart=100, max_iter=1000))
+    solid_step = solid_step or newton_params(solve=solve_params(tol=1e-10, restart=100, max_iter=1000))
+    mesh_step = mesh_step or newton_params(solve=solve_params(tol=1e-12, restart=100, max_iter=1000), amg_reuse=1)
+    return FsiParams(C.sizeof(FsiParams), omega0, eps, max_dn, eps2, fluid_step, solid_step, mesh_step)
 
 
 _lib = None
@@ -201,6 +226,12 @@ def load():
         "hfsi_mlp_samples": [vp, i64, i64, C.POINTER(i64), vp, vp, vp, vp],
         "hfsi_mlp_train": [vp, C.POINTER(TrainParams), vp, i64, C.POINTER(TrainInfo)],
         "hfsi_amg_convergence_factor": [vp, i32, C.c_uint64, C.POINTER(dbl)],
+        "hfsi_set_fluid": [vp, dbl, dbl, dbl],
+        "hfsi_set_fluid_fields": [vp, vp, vp, vp],
+        "hfsi_set_mesh_laplace": [vp],
+        "hfsi_fluid_interface_force": [vp, vp, dbl, i32, vp, vp],
+        "hfsi_fsi_time_step": [vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, dbl, C.POINTER(FsiParams),
+                               C.POINTER(FsiInfo)],
     }
     for name, args in sig.items():
         f = getattr(lib, name, None)
@@ -301,6 +332,21 @@ class Context:
 
     def newmark_update(self, v_new, v_prev, vel, acc):
         self._check(self.lib.hfsi_newmark_update(self.h, _ptr(v_new), _ptr(v_prev), _ptr(vel), _ptr(acc)))
+
+    def set_fluid(self, rho, mu, dt):
+        """Switch to the fluid sub-problem (after set_mesh)."""
+        self._check(self.lib.hfsi_set_fluid(self.h, rho, mu, dt))
+
+    def set_fluid_fields(self, dmesh=None, u_old=None, w=None):
+        """Device [n,3] mesh displacement, previous velocity, mesh velocity."""
+        self._check(self.lib.hfsi_set_fluid_fields(self.h, _ptr(dmesh), _ptr(u_old), _ptr(w)))
+
+    def set_mesh_laplace(self):
+        self._check(self.lib.hfsi_set_mesh_laplace(self.h))
+
+    def fluid_interface_force(self, v, load, nodes, f):
+        nodes = np.ascontiguousarray(nodes, np.int32)
+        self._check(self.lib.hfsi_fluid_interface_force(self.h, _ptr(v), load, len(nodes), _ptr(nodes), _ptr(f)))
 
     # ---- hot path
     def assemble_residual_tangent(self, v, load, R):
@@ -504,3 +550,45 @@ class Context:
             "block_ptr", "block_col", "block_val", "a_ptr", "a_col", "a_val", "schur")]))
         out["block_val"] = out["block_val"].reshape(nb, 4, 4)
         return out
+
+
+def fsi_time_step(fluid, mesh, solid, iface_f, iface_s, vf, df, vs, vel, acc, inlet_load, prm=None):
+    """One DN time step over three contexts (see hfsi_fsi_time_step);
+    returns (info, status)."""
+    prm = prm or fsi_params()
+    f = np.ascontiguousarray(iface_f, np.int32)
+    s_ = np.ascontiguousarray(iface_s, np.int32)
+    info = FsiInfo(C.sizeof(FsiInfo))
+    code = fluid._check(fluid.lib.hfsi_fsi_time_step(fluid.h, mesh.h, solid.h, len(f), _ptr(f), _ptr(s_), _ptr(vf),
+                                                     _ptr(df), _ptr(vs), _ptr(vel), _ptr(acc), inlet_load,
+                                                     C.byref(prm), C.byref(info)))
+    return info, code
+
+
+def fsi_contexts(model, rho_f=1.0, mu=0.0035, dt=0.125, rho_s=1.2, p_in=1.332, beta=0.625, gamma=1.0, device=0):
+    """The three contexts of a partitioned FSI model (an object with the
+    fields of synth.FsiModel): the fluid (velocity fixed on the interface,
+    inlet traction (0, 0, p_in) at load factor 1), the mesh Laplacian on the
+    fluid mesh (every boundary displacement and every pressure fixed) and
+    the structure with Newmark inertia."""
+    nf = model.fluid_X.shape[0]
+    dummy = [dict(model=0, c10=1.0, c01=0.0, kappa=1.0)]
+    mat0 = np.zeros(len(model.fluid_tets), np.int32)
+    fluid = Context(device)
+    fluid.set_mesh(model.fluid_X, model.fluid_tets, mat0)
+    fluid.set_materials(dummy)
+    tr = np.tile(np.array([0.0, 0.0, p_in]), (len(model.inlet_tris), 1))
+    fluid.set_bc(model.fluid_dir, model.inlet_tris, tr)
+    fluid.set_fluid(rho_f, mu, dt)
+    mesh = Context(device)
+    mesh.set_mesh(model.fluid_X, model.fluid_tets, mat0)
+    mesh.set_materials(dummy)
+    dm = np.zeros((nf, 4), np.uint8)
+    dm[np.asarray(model.fluid_boundary, bool), 0:3] = 1
+    dm[:, 3] = 1
+    mesh.set_bc(dm, np.zeros((0, 3), np.int32), np.zeros((0, 3)))
+    mesh.set_mesh_laplace()
+    solid = Context(device)
+    solid.set_problem(model.solid)
+    solid.set_newmark(rho_s, dt, beta, gamma)
+    return fluid, mesh, solid
