@@ -105,6 +105,11 @@ typedef struct {
  * cheb_degree_coarse after (degrees apply to Chebyshev only; a level without
  * pre-smoothing restricts its right-hand side directly).
  * precision: 0 = fp64 V-cycle, 1 = fp32 V-cycle (coarsest solve stays fp64).
+ * Coarsening stops at max_coarse rows, after max_levels levels, or when a
+ * level would keep more than 90% of its rows (a stall, e.g. on the
+ * mass-dominated fluid operator, whose couplings are not strong); the
+ * coarsest level is inverted densely when it has at most 4096 rows, else it
+ * is solved by 16 l1-Jacobi sweeps from zero.
  * interp: 0 = classical, 1 = learned correction on level 0 (needs MLP
  * weights and lattice coordinates), judged by the convergence factor rho of
  * its V-cycle (10 stationary cycles from the SplitMix64 vector of seed 777):

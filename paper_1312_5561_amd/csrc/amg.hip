@@ -1944,14 +1944,22 @@ void finish_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, bool same_pattern
   Hierarchy& H = c->H;
   Level& Lc = H.L.back();
   const int nc = Lc.n;
-  if (nc > 4096) fail(HFSI_E_CAPACITY, "coarsest level larger than 4096 rows (coarsening stalled)");
   H.nc = nc;
-  H.coarse_inv.ensure((size_t)nc * nc);
+  // a coarsest level above the dense limit (the coarsening stalled: no
+  // strong couplings, e.g. a mass-dominated operator) is solved by l1-Jacobi
+  // sweeps, whose diagonal replaces the (unused) smoother diagonal there
+  H.coarse_iterative = nc > kMaxDenseCoarse;
+  if (H.coarse_iterative) {
+    k_l1_diag<<<div_up(nc, 256), 256, 0, s>>>(nc, Lc.A.ptr.p, Lc.A.val.p, Lc.dinv.p, Lc.dinv32.p);
+    HIP_LAUNCH_CHECK();
+  } else {
+    H.coarse_inv.ensure((size_t)nc * nc);
+  }
   DevBuf<int> sing;
   sing.zero(1, s);
   HIP_CHECK(hipEventRecord(c->aev[0], s));
   HIP_CHECK(hipStreamWaitEvent(c->aux, c->aev[0], 0));
-  {
+  if (!H.coarse_iterative) {
     hipStream_t a = c->aux;
     StreamTag tag(a);
     DevBuf<double> M, M2;

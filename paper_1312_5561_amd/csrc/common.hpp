@@ -207,6 +207,9 @@ struct Level {
 struct Hierarchy {
   std::vector<Level> L;
   int nc = 0;                 // coarsest size
+  // coarsening stalled above the dense limit: the coarsest level is solved
+  // by kCoarseSweeps l1-Jacobi sweeps from zero instead of its inverse
+  bool coarse_iterative = false;
   DevBuf<double> coarse_inv;  // explicit inverse of the coarsest operator
   DevBuf<double> lmax_dev;    // per-level eigenvalue estimates (written on the aux stream)
   DevBuf<int> setup_flags;    // numeric sparse-product overflow, read with the estimates
@@ -226,6 +229,9 @@ struct Hierarchy {
 };
 
 }  // namespace hfsi
+
+constexpr int kMaxDenseCoarse = 4096;  // rows of the coarsest level inverted densely
+constexpr int kCoarseSweeps = 16;      // l1-Jacobi sweeps on a larger coarsest level
 
 // ------------------------------------------------------------- the context
 struct hfsi_ctx {

@@ -868,6 +868,17 @@ T* vcycle_rec(hfsi_ctx* c, int l, bool first_done) {
   LevelView<T> v = view<T>(L, last);
   const int n = L.n;
   if (last) {
+    if (H.coarse_iterative) {  // l1-Jacobi sweeps from zero (the level's dinv is the l1 diagonal)
+      T* x = v.x;
+      T* y = v.t;
+      k_scale_vec<T><<<div_up(n, 256), 256, 0, s>>>(n, v.dinv, v.b, x, (T)1);
+      HIP_LAUNCH_CHECK();
+      for (int k = 1; k < kCoarseSweeps; ++k) {
+        level_op<T, OP_JACOBI>(L, v, x, v.b, y, nullptr, 0, 0, s);
+        std::swap(x, y);
+      }
+      return x;
+    }
     k_dense_gemv<T><<<div_up((long)n * 64, 256), 256, 0, s>>>(n, H.coarse_inv.p, v.b, v.x);
     HIP_LAUNCH_CHECK();
     return v.x;

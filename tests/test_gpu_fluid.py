@@ -183,3 +183,30 @@ def test_fsi_step_larger_duct_host_checks(lib):
     gap = df[model.iface_f] - vs[model.iface_s, 0:3]
     assert np.linalg.norm(gap) / np.sqrt(len(model.iface_f)) < 1e-8
     assert info.residual[info.dn_iterations - 1] < 1e-8
+
+
+def test_stalled_coarsening_solves_by_l1_jacobi(lib):
+    """The fluid operator of the 3 x 2 x 36 duct is mass-dominated: no
+    coupling is strong, the coarsening stops on level 0 (5,439 rows, above
+    the dense limit), and the V-cycle is then 16 l1-Jacobi sweeps from zero,
+    checked against the same sweeps in numpy on the exported operator."""
+    import torch
+    model = _model(3, 2, 36, length=18.0)
+    fl, me, so = lib.fsi_contexts(model, **PRM)
+    nf = model.nf
+    vt = torch.zeros(4 * nf, dtype=torch.float64, device="cuda")
+    R = torch.zeros_like(vt)
+    fl.assemble_residual_tangent(vt, 1.0, R)
+    info = fl.amg_setup(lib.amg_params(smoother=0, nu_pre=2, nu_post=2))
+    print(f"[stalled coarsening] levels {info.levels} rows {info.rows[0]}", flush=True)
+    assert info.levels == 1 and info.rows[0] == 3 * nf > 4096
+    ptr, col, val, ncols = fl.amg_export(0, 0)
+    A = sp.csr_matrix((val, col, ptr), shape=(len(ptr) - 1, ncols))
+    r = np.random.default_rng(7).normal(size=A.shape[0])
+    z = torch.zeros(A.shape[0], dtype=torch.float64, device="cuda")
+    fl.vcycle(torch_dev(r), z)
+    dinv = 1.0 / np.asarray(abs(A).sum(axis=1)).ravel()
+    x = dinv * r
+    for _ in range(15):
+        x = x + dinv * (r - A @ x)
+    assert np.abs(z.cpu().numpy() - x).max() <= 1e-12 * np.abs(x).max()
