@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--fsi-shape", default="3,2,36",
                     help="FSI duct: lumen cells per half-width, wall cells, axial cells (empty: skip the FSI leg)")
     ap.add_argument("--fsi-steps", type=int, default=3, help="time steps of the FSI leg")
+    ap.add_argument("--fsi-only", action="store_true",
+                    help="run only the FSI leg and print its object as the JSON line (profiling)")
     args = ap.parse_args()
     if args.kappa is None:
         args.kappa = 1e4 if args.workload == "cube" else 1e5
@@ -295,10 +297,11 @@ def fsi_leg(shape, steps, torch, hfsi):
                        f"{nf} fluid nodes ({4 * nf} dofs), {ns} structure nodes ({4 * ns} dofs), "
                        f"{len(model.iface_f)} interface nodes", "dt_ms": 0.125}
     base = hfsi.fsi_params()
-    kept = hfsi.fsi_params(
-        fluid_step=hfsi.newton_params(amg=base.fluid_step.amg, solve=base.fluid_step.solve, amg_reuse=2),
-        solid_step=hfsi.newton_params(amg=base.solid_step.amg, solve=base.solid_step.solve, amg_reuse=2))
-    for label, prm in (("new_hierarchies", base), ("grids_kept", kept)):
+    fk = hfsi.newton_params(amg=base.fluid_step.amg, solve=base.fluid_step.solve, amg_reuse=2)
+    sk = hfsi.newton_params(amg=base.solid_step.amg, solve=base.solid_step.solve, amg_reuse=2)
+    kept = hfsi.fsi_params(fluid_step=fk, solid_step=sk)
+    adaptive = hfsi.fsi_params(fluid_step=fk, solid_step=sk, adaptive=1)
+    for label, prm in (("new_hierarchies", base), ("grids_kept", kept), ("grids_kept_adaptive", adaptive)):
         fl, me, so = hfsi.fsi_contexts(model)
         z = lambda k: torch.zeros(k, dtype=torch.float64, device="cuda")  # noqa: E731
         vf, df, vs, vel, acc = z(4 * nf), z(3 * nf), z(4 * ns), z(3 * ns), z(3 * ns)
@@ -332,6 +335,10 @@ def main():
     import synth
     from paper_1312_5561_amd import hfsi
 
+    if args.fsi_only:
+        shape = tuple(int(x) for x in args.fsi_shape.split(","))
+        print(json.dumps({"fsi_time_steps": fsi_leg(shape, args.fsi_steps, torch, hfsi)}), flush=True)
+        return
     if args.workload == "cube":
         prob = synth.cube_problem(args.N, kappa=args.kappa)
         increments = 5
@@ -556,7 +563,8 @@ def main():
         fs = res["fsi_time_steps"]
         print(f"[bench] FSI duct {args.fsi_shape}, {args.fsi_steps} steps: "
               f"{fs['new_hierarchies']['ms_per_time_step']:.0f} ms per step with new hierarchies, "
-              f"{fs['grids_kept']['ms_per_time_step']:.0f} ms with grids kept; DN iterations "
+              f"{fs['grids_kept']['ms_per_time_step']:.0f} ms with grids kept, "
+              f"{fs['grids_kept_adaptive']['ms_per_time_step']:.0f} ms adaptive; DN iterations "
               f"{[r['dn_iterations'] for r in fs['grids_kept']['steps']]}", file=sys.stderr, flush=True)
     # the headline state's tangent for the roofline timing
     v.copy_(v0)

@@ -501,6 +501,11 @@ typedef struct {
   hfsi_newton_params solid_step;  /* ... of the structure                  */
   hfsi_newton_params mesh_step;   /* ... of the harmonic extension (one
                                      linear solve per DN iteration)         */
+  int32_t adaptive;     /* 1: the nested fluid and structure Newton solves
+                           take the adaptive inner tolerance (see
+                           hfsi_newton_solve_params.adaptive, with eps1_max
+                           1e-2 and eps1_min 1e-12); 0: the fixed tolerance
+                           of fluid_step / solid_step (default)             */
 } hfsi_fsi_params;
 
 typedef struct {

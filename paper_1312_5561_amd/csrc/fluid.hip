@@ -581,8 +581,9 @@ struct FsiWork {
 
 void check_fsi_params(const hfsi_fsi_params* p) {
   if (!p || p->struct_size != sizeof(hfsi_fsi_params)) fail(HFSI_E_ARG, "fsi params: struct_size mismatch");
-  if (!(p->omega0 > 0.0) || !(p->eps > 0.0) || p->max_dn < 1 || p->max_dn > 128 || !(p->eps2 > 0.0))
-    fail(HFSI_E_ARG, "fsi params: need omega0 > 0, eps > 0, 1 <= max_dn <= 128, eps2 > 0");
+  if (!(p->omega0 > 0.0) || !(p->eps > 0.0) || p->max_dn < 1 || p->max_dn > 128 || !(p->eps2 > 0.0) ||
+      p->adaptive < 0 || p->adaptive > 1)
+    fail(HFSI_E_ARG, "fsi params: need omega0 > 0, eps > 0, 1 <= max_dn <= 128, eps2 > 0, adaptive 0 or 1");
 }
 
 }  // namespace
@@ -648,6 +649,7 @@ extern "C" hfsi_status hfsi_fsi_time_step(hfsi_ctx* fl, hfsi_ctx* me, hfsi_ctx* 
   pf.eps1_max = ps.eps1_max = 1e-2;
   pf.eps1_min = ps.eps1_min = 1e-12;
   pf.ref_norm = ps.ref_norm = 0.0;
+  pf.adaptive = ps.adaptive = prm->adaptive;
   hfsi_newton_params pm = prm->mesh_step;
   int k = 0, fl_its = 0, so_its = 0, kry = 0;
   bool done = false;

@@ -99,7 +99,7 @@ class NewtonSolveInfo(C.Structure):
 class FsiParams(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("omega0", C.c_double), ("eps", C.c_double), ("max_dn", C.c_int32),
                 ("eps2", C.c_double), ("fluid_step", NewtonParams), ("solid_step", NewtonParams),
-                ("mesh_step", NewtonParams)]
+                ("mesh_step", NewtonParams), ("adaptive", C.c_int32)]
 
 
 class FsiInfo(C.Structure):
@@ -164,16 +164,18 @@ def newton_solve_params(step=None, eps2=1e-10, max_newton=25, adaptive=0, eps1_m
                              eps1_max, eps1_min, line_search, ref_norm)
 
 
-def fsi_params(omega0=0.05, eps=1e-8, max_dn=100, eps2=1e-10, fluid_step=None, solid_step=None, mesh_step=None):
+def fsi_params(omega0=0.05, eps=1e-8, max_dn=100, eps2=1e-10, fluid_step=None, solid_step=None, mesh_step=None,
+               adaptive=0):
     """Dirichlet-Neumann iteration with Aitken relaxation; the nested
     solves default to FGMRES(100) with P_L: l1-Jacobi AMG for the fluid,
     the library defaults for the structure, and a 1e-12 solve for the mesh
-    extension."""
+    extension; adaptive=1: adaptive inner tolerances in the nested Newton
+    solves."""
     fluid_step = fluid_step or newton_params(amg=amg_params(smoother=0, nu_pre=2, nu_post=2),
                                              solve=solve_params(tol=1e-10, restart=100, max_iter=1000))
     solid_step = solid_step or newton_params(solve=solve_params(tol=1e-10, restart=100, max_iter=1000))
     mesh_step = mesh_step or newton_params(solve=solve_params(tol=1e-12, restart=100, max_iter=1000), amg_reuse=1)
-    return FsiParams(C.sizeof(FsiParams), omega0, eps, max_dn, eps2, fluid_step, solid_step, mesh_step)
+    return FsiParams(C.sizeof(FsiParams), omega0, eps, max_dn, eps2, fluid_step, solid_step, mesh_step, adaptive)
 
 
 _lib = None
