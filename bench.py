@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--fsi-steps", type=int, default=3, help="time steps of the FSI leg")
     ap.add_argument("--fsi-only", action="store_true",
                     help="run only the FSI leg and print its object as the JSON line (profiling)")
+    ap.add_argument("--fsi-variants", default="new_hierarchies,grids_kept,grids_kept_adaptive",
+                    help="comma-separated FSI solver variants to run")
     args = ap.parse_args()
     if args.kappa is None:
         args.kappa = 1e4 if args.workload == "cube" else 1e5
@@ -281,7 +283,7 @@ def vanka_leg(N, steps, kappa, torch, hfsi):
     return out
 
 
-def fsi_leg(shape, steps, torch, hfsi):
+def fsi_leg(shape, steps, torch, hfsi, variants=("new_hierarchies", "grids_kept", "grids_kept_adaptive")):
     """The partitioned FSI time step (NEXT-2) on the square-duct model with
     the paper's parameters (fluid rho 1, mu 0.0035 kPa ms; Mooney-Rivlin
     wall c10 3, c01 0.3, kappa 1e5 kPa, rho 1.2; dt 0.125 ms; inlet traction
@@ -301,7 +303,9 @@ def fsi_leg(shape, steps, torch, hfsi):
     sk = hfsi.newton_params(amg=base.solid_step.amg, solve=base.solid_step.solve, amg_reuse=2)
     kept = hfsi.fsi_params(fluid_step=fk, solid_step=sk)
     adaptive = hfsi.fsi_params(fluid_step=fk, solid_step=sk, adaptive=1)
-    for label, prm in (("new_hierarchies", base), ("grids_kept", kept), ("grids_kept_adaptive", adaptive)):
+    runs = {"new_hierarchies": base, "grids_kept": kept, "grids_kept_adaptive": adaptive}
+    for label in variants:
+        prm = runs[label]
         fl, me, so = hfsi.fsi_contexts(model)
         z = lambda k: torch.zeros(k, dtype=torch.float64, device="cuda")  # noqa: E731
         vf, df, vs, vel, acc = z(4 * nf), z(3 * nf), z(4 * ns), z(3 * ns), z(3 * ns)
@@ -317,7 +321,9 @@ def fsi_leg(shape, steps, torch, hfsi):
                 raise RuntimeError(f"FSI leg: time step {k + 1} did not converge")
             rec.append({"seconds": time.perf_counter() - t0, "dn_iterations": info.dn_iterations,
                         "fluid_newton": info.fluid_newton, "structure_newton": info.solid_newton,
-                        "krylov": info.krylov, "last_residual": info.residual[info.dn_iterations - 1]})
+                        "krylov": info.krylov, "last_residual": info.residual[info.dn_iterations - 1],
+                        "residuals": [float(info.residual[i]) for i in range(min(info.dn_iterations, 128))],
+                        "omegas": [float(info.omega[i]) for i in range(min(info.dn_iterations - 1, 128))]})
         out[label] = {"ms_per_time_step": sum(r["seconds"] for r in rec) / steps * 1e3, "steps": rec,
                       "max_wall_displacement_mm": float(vs.view(-1, 4)[:, 0:3].abs().max())}
         for c in (fl, me, so):
@@ -337,7 +343,8 @@ def main():
 
     if args.fsi_only:
         shape = tuple(int(x) for x in args.fsi_shape.split(","))
-        print(json.dumps({"fsi_time_steps": fsi_leg(shape, args.fsi_steps, torch, hfsi)}), flush=True)
+        print(json.dumps({"fsi_time_steps": fsi_leg(shape, args.fsi_steps, torch, hfsi,
+                                                    tuple(args.fsi_variants.split(",")))}), flush=True)
         return
     if args.workload == "cube":
         prob = synth.cube_problem(args.N, kappa=args.kappa)

@@ -536,13 +536,15 @@ typedef struct {
  * the fluid's force on the wall as the structure's nodal load and solves the
  * structure; r_k = d_G(structure) - d_G, stop when |r_k|/sqrt(n_iface) <
  * eps, else d_G += omega_k r_k with omega from eq. dnomega (omega0 first).
- * The first d_G is the structure's interface displacement at t^{n-1}; every
+ * The first d_G is the structure's interface displacement extrapolated to
+ * t^n with its velocity, d^{n-1} + dt vel^{n-1}; every
  * nested Newton solve continues from its latest iterate with the rule of
  * eq. newstop relative to the first correction of its sub-problem in this
  * step (hfsi_newton_solve_params.ref_norm).  The contexts' streams are
  * synchronised at every hand-over.  HFSI_NOT_CONVERGED after max_dn
  * iterations (state partly advanced); a failing nested solve returns its
- * status with the sub-problem named in hfsi_last_error(fluid). */
+ * status with the sub-problem and the DN iteration named in
+ * hfsi_last_error(fluid), and info holds the iterations up to it. */
 hfsi_status hfsi_fsi_time_step(hfsi_ctx* fluid, hfsi_ctx* mesh, hfsi_ctx* solid, int32_t n_iface,
                                const int32_t* iface_f, const int32_t* iface_s, double* vf, double* df, double* vs,
                                double* vel, double* acc, double inlet_load, const hfsi_fsi_params* prm,

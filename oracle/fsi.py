@@ -20,7 +20,11 @@ omega_k = -omega_{k-1} r_k . (r_{k+1} - r_k) / |r_{k+1} - r_k|^2
 Readings (the paper leaves them to its reference):
 * the first relaxation factor of every time step is a parameter omega0;
 * the first DN iteration of a time step starts from the interface
-  displacement of the previous step;
+  displacement extrapolated to the new time level with the structure's
+  velocity, d_G^(0) = d^{n-1} + dt v^{n-1} on the interface (the paper
+  extrapolates the fluid domain from the previous iterates; a constant
+  start lets the fluid see a wall stopped at once, whose added-mass force
+  inverts the wall on the duct after a few steps of the pulse);
 * the nested Newton solves start from the latest iterate of their own
   sub-problem and use the stopping rule of eq. newstop (eps_2 = 1e-10),
   each linear system solved directly here; the reference of the rule is
@@ -163,7 +167,8 @@ class FsiState:
             cur.update(vf=vf, vs=vs, df=df)
             return vs.reshape(-1, 4)[m.iface_s, 0:3].ravel()
 
-        k, omegas, norms = dn_iterate(evaluate, self.vs[m.iface_s, 0:3].ravel(), nG, prm.omega0, prm.eps,
+        d0 = self.vs[m.iface_s, 0:3] + dt * self.vel[m.iface_s]
+        k, omegas, norms = dn_iterate(evaluate, d0.ravel(), nG, prm.omega0, prm.eps,
                                       prm.max_dn, None if log is None else (lambda s: log(f"t={t:.4f} " + s)))
         vf, vs, df = cur["vf"], cur["vs"], cur["df"]
         vs = vs.reshape(-1, 4)

@@ -306,13 +306,14 @@ __global__ void k_fill(long n, double value, double* __restrict__ x) {
 
 // ---------------------------------------------------------- FSI helpers
 
-// dst[k] = src[4 idx[k/3] + k%3] (the velocity / displacement entries of
-// listed nodes of a node-interleaved vector), k < 3 cnt
-__global__ void k_gather_u(int cnt, const int* __restrict__ idx, const double* __restrict__ src,
-                           double* __restrict__ dst) {
+// the first interface displacement of a step: dG[k] = vs[4 idx[k/3] + k%3]
+// + dt vel[3 idx[k/3] + k%3] (extrapolation with the structure's velocity)
+__global__ void k_predict(int cnt, const int* __restrict__ idx, const double* __restrict__ vs,
+                          const double* __restrict__ vel, double dt, double* __restrict__ dG) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 3 * cnt) return;
-  dst[t] = src[4 * idx[t / 3] + t % 3];
+  const int k = idx[t / 3], c = t % 3;
+  dG[t] = vs[4 * k + c] + dt * vel[3 * k + c];
 }
 
 // dst[4 idx[k/3] + k%3] = src[k]
@@ -631,7 +632,7 @@ extern "C" hfsi_status hfsi_fsi_time_step(hfsi_ctx* fl, hfsi_ctx* me, hfsi_ctx* 
   HIP_CHECK(hipMemcpyAsync(W.dprev.p, df, sizeof(double) * 3 * nf, hipMemcpyDeviceToDevice, s));
   HIP_CHECK(hipMemcpyAsync(W.vs_prev.p, vs, sizeof(double) * 4 * ns, hipMemcpyDeviceToDevice, s));
   k_u_of<<<div_up(3 * nf, 256), 256, 0, s>>>(nf, vf, F.uold.p);
-  k_gather_u<<<div_up(len, 256), 256, 0, s>>>(n_iface, W.sidx.p, vs, W.dG.p);
+  k_predict<<<div_up(len, 256), 256, 0, s>>>(n_iface, W.sidx.p, vs, vel, dt, W.dG.p);
   HIP_LAUNCH_CHECK();
   HIP_CHECK(hipStreamSynchronize(s));
   hfsi_status st = hfsi_newmark_history(so, W.vs_prev.p, vel, acc);
@@ -655,7 +656,16 @@ extern "C" hfsi_status hfsi_fsi_time_step(hfsi_ctx* fl, hfsi_ctx* me, hfsi_ctx* 
   bool done = false;
   double omega = prm->omega0;
   auto sub_fail = [&](hfsi_ctx* who, const char* name, hfsi_status code) {
-    fl->err = std::string("fsi_time_step: ") + name + ": " + (who->err.empty() ? "not converged" : who->err);
+    fl->err = std::string("fsi_time_step: ") + name + " (DN iteration " + std::to_string(k) +
+              "): " + (who->err.empty() ? "not converged" : who->err);
+    if (info) {  // the iterations so far (residual and omega of the earlier ones)
+      info->dn_iterations = k;
+      info->fluid_newton = fl_its;
+      info->solid_newton = so_its;
+      info->krylov = kry;
+      info->converged = 0;
+      info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
     return code < 0 ? code : HFSI_E_BREAKDOWN;
   };
   for (k = 1; k <= prm->max_dn; ++k) {
