@@ -76,6 +76,8 @@ def parse():
                     help="run only the FSI leg and print its object as the JSON line (profiling)")
     ap.add_argument("--fsi-variants", default="new_hierarchies,grids_kept,grids_kept_adaptive",
                     help="comma-separated FSI solver variants to run")
+    ap.add_argument("--fsi-artery-steps", type=int, default=3,
+                    help="time steps of the FSI leg with the two-layer artery wall (0: skip)")
     args = ap.parse_args()
     if args.kappa is None:
         args.kappa = 1e4 if args.workload == "cube" else 1e5
@@ -283,7 +285,8 @@ def vanka_leg(N, steps, kappa, torch, hfsi):
     return out
 
 
-def fsi_leg(shape, steps, torch, hfsi, variants=("new_hierarchies", "grids_kept", "grids_kept_adaptive")):
+def fsi_leg(shape, steps, torch, hfsi, variants=("new_hierarchies", "grids_kept", "grids_kept_adaptive"),
+            artery_steps=3):
     """The partitioned FSI time step (NEXT-2) on the square-duct model with
     the paper's parameters (fluid rho 1, mu 0.0035 kPa ms; Mooney-Rivlin
     wall c10 3, c01 0.3, kappa 1e5 kPa, rho 1.2; dt 0.125 ms; inlet traction
@@ -328,6 +331,32 @@ def fsi_leg(shape, steps, torch, hfsi, variants=("new_hierarchies", "grids_kept"
                       "max_wall_displacement_mm": float(vs.view(-1, 4)[:, 0:3].abs().max())}
         for c in (fl, me, so):
             c.close()
+    if artery_steps > 0:
+        # the paper's second model: the two-layer artery wall (media on the two
+        # inner wall rings, adventitia outside), its 0.125 ms pulse (one step)
+        am = synth.fsi_duct(a=a, t=3, n_z=nz, artery=True)
+        nfa, nsa = am.nf, am.solid.n_nodes
+        fl, me, so = hfsi.fsi_contexts(am)
+        z = lambda k: torch.zeros(k, dtype=torch.float64, device="cuda")  # noqa: E731
+        vf, df, vs, vel, acc = z(4 * nfa), z(3 * nfa), z(4 * nsa), z(3 * nsa), z(3 * nsa)
+        rec = []
+        for k in range(artery_steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info, code = hfsi.fsi_time_step(fl, me, so, am.iface_f, am.iface_s, vf, df, vs, vel, acc,
+                                            1.0 if k == 0 else 0.0, adaptive)
+            torch.cuda.synchronize()
+            if code != 0:
+                raise RuntimeError(f"FSI leg (artery): time step {k + 1} did not converge")
+            rec.append({"seconds": time.perf_counter() - t0, "dn_iterations": info.dn_iterations,
+                        "fluid_newton": info.fluid_newton, "structure_newton": info.solid_newton,
+                        "krylov": info.krylov})
+        out["artery_wall_grids_kept_adaptive"] = {
+            "workload": f"square duct {a}x3x{nz}, two-layer artery wall: {nfa} fluid nodes, {nsa} structure nodes",
+            "ms_per_time_step": sum(r["seconds"] for r in rec) / artery_steps * 1e3, "steps": rec,
+            "max_wall_displacement_mm": float(vs.view(-1, 4)[:, 0:3].abs().max())}
+        for c in (fl, me, so):
+            c.close()
     return out
 
 
@@ -344,7 +373,8 @@ def main():
     if args.fsi_only:
         shape = tuple(int(x) for x in args.fsi_shape.split(","))
         print(json.dumps({"fsi_time_steps": fsi_leg(shape, args.fsi_steps, torch, hfsi,
-                                                    tuple(args.fsi_variants.split(",")))}), flush=True)
+                                                    tuple(args.fsi_variants.split(",")),
+                                                    args.fsi_artery_steps)}), flush=True)
         return
     if args.workload == "cube":
         prob = synth.cube_problem(args.N, kappa=args.kappa)
@@ -566,7 +596,7 @@ def main():
               f"{cv['pl_fgmres_fp32']['seconds'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
     if not args.quick and args.fsi_shape and args.workload == "cube":
         shape = tuple(int(x) for x in args.fsi_shape.split(","))
-        res["fsi_time_steps"] = fsi_leg(shape, args.fsi_steps, torch, hfsi)
+        res["fsi_time_steps"] = fsi_leg(shape, args.fsi_steps, torch, hfsi, artery_steps=args.fsi_artery_steps)
         fs = res["fsi_time_steps"]
         print(f"[bench] FSI duct {args.fsi_shape}, {args.fsi_steps} steps: "
               f"{fs['new_hierarchies']['ms_per_time_step']:.0f} ms per step with new hierarchies, "

@@ -338,9 +338,14 @@ def _graded(a, t, half_width, wall):
     return idx, np.sign(idx) * x
 
 
-def fsi_duct(a=3, t=2, n_z=36, half_width=1.43, wall=0.39, length=18.0, c10=3.0, c01=0.3, kappa=1e5):
-    """FSI model of the paper's experiments (lengths in mm, Mooney-Rivlin
-    wall c10 = 3 kPa, c01 = 0.3 kPa, kappa = 1e5 kPa) on a square duct."""
+def fsi_duct(a=3, t=2, n_z=36, half_width=1.43, wall=0.39, length=18.0, c10=3.0, c01=0.3, kappa=1e5,
+             artery=False, media_cells=None):
+    """FSI model of the paper's experiments (lengths in mm) on a square
+    duct: a Mooney-Rivlin wall (c10 = 3 kPa, c01 = 0.3 kPa, kappa = 1e5 kPa),
+    or with artery=True the two-layer artery (media on the inner
+    media_cells wall rings, default two thirds of them rounded up,
+    adventitia outside; the paper's constants and fibre angles, the fibres
+    cos(alpha) e_theta +/- sin(alpha) e_z at each element's centroid)."""
     idx, coord = _graded(a, t, half_width, wall)
     nl = len(idx)
     k3, j3, i3 = np.meshgrid(np.arange(n_z + 1), np.arange(nl), np.arange(nl), indexing="ij")
@@ -381,8 +386,21 @@ def fsi_duct(a=3, t=2, n_z=36, half_width=1.43, wall=0.39, length=18.0, c10=3.0,
     ns = len(gs)
     dm = np.zeros((ns, 4), np.uint8)
     dm[(lats[:, 2] == 0) | (lats[:, 2] == n_z), 0:3] = 1
-    solid = Problem(X[gs], Ts, np.zeros(len(Ts), np.int32), [mooney_rivlin(c10, c01, kappa)], dm,
-                    np.zeros((0, 3), np.int32), np.zeros((0, 3)), lats.astype(np.int32), None,
-                    name=f"duct_wall{a}x{t}x{n_z}")
+    mats = [mooney_rivlin(c10, c01, kappa)]
+    mat_id = np.zeros(len(Ts), np.int32)
+    fib = None
+    if artery:
+        ring = np.maximum(np.abs(hi[~fluid_cell] + 0.5), np.abs(hj[~fluid_cell] + 0.5)) - 0.5 - a  # 0 .. t-1
+        nm = media_cells if media_cells is not None else -(-2 * t // 3)
+        mat_id = (ring >= nm).astype(np.int32)
+        mats = [artery_layer(kappa=kappa, **ARTERY_MEDIA), artery_layer(kappa=kappa, **ARTERY_ADVENTITIA)]
+        cen = X[gs][Ts].mean(axis=1)
+        rr = np.hypot(cen[:, 0], cen[:, 1])
+        e_t = np.stack([-cen[:, 1] / rr, cen[:, 0] / rr, np.zeros_like(rr)], axis=1)
+        e_z = np.tile(np.array([0.0, 0.0, 1.0]), (len(Ts), 1))
+        alpha = np.where(mat_id == 0, math.radians(29.0), math.radians(62.0))[:, None]
+        fib = np.stack([np.cos(alpha) * e_t + np.sin(alpha) * e_z, np.cos(alpha) * e_t - np.sin(alpha) * e_z], axis=1)
+    solid = Problem(X[gs], Ts, mat_id, mats, dm, np.zeros((0, 3), np.int32), np.zeros((0, 3)),
+                    lats.astype(np.int32), fib, name=f"duct_wall{a}x{t}x{n_z}" + ("_artery" if artery else ""))
     return FsiModel(X[gf], Tf, fdir, inlet.astype(np.int32), fb, solid, iface_f, iface_s,
                     latf.astype(np.int32))

@@ -14,8 +14,9 @@ duct models; nothing it uses comes from the GPU.  Compared:
 * the harmonic extension of a random interface displacement to 1e-9;
 * a fluid Newton solve on a moved mesh: the same iteration count and the
   state to 1e-8; the interface force to 1e-10;
-* two DN time steps of the 2 x 1 x 4 duct: the DN iteration counts within
-  two of the oracle's and the states to 1e-4 of their size (both stop at
+* two DN time steps of the 2 x 1 x 4 duct, and of the 2 x 3 x 4 duct with
+  the two-layer artery wall: the DN iteration counts within two of the
+  oracle's and the states to 1e-4 of their size (both stop at
   |r| / sqrt(n) < 1e-8, which the DN map's conditioning amplifies);
 * one step of the 3 x 2 x 12 duct checked on the host: the kinematic
   condition on the interface and the interface gap below the tolerance.
@@ -168,6 +169,22 @@ def test_fsi_steps_match_oracle(lib):
     assert np.abs(vs.reshape(-1, 4)[:, 0:3] - st.vs[:, 0:3]).max() <= 1e-4 * np.abs(st.vs[:, 0:3]).max()
     assert np.abs(vf.reshape(-1, 4)[:, 0:3] - st.vf[:, 0:3]).max() <= 1e-4 * np.abs(st.vf[:, 0:3]).max()
     assert np.abs(df.reshape(-1, 3) - st.df).max() <= 1e-4 * np.abs(st.df).max()
+
+
+def test_fsi_artery_steps_match_oracle(lib):
+    """The same with the paper's two-layer artery as the wall (media on the
+    two inner wall rings, adventitia outside, fibres at +/-29 and +/-62
+    degrees)."""
+    model = synth.fsi_duct(a=2, t=3, n_z=4, length=4.0, artery=True)
+    print(f"[fsi artery] duct 2x3x4: nf={model.nf} ns={model.solid.n_nodes}", flush=True)
+    infos, (vf, df, vs) = _gpu_fsi(lib, model, 0.3, 2)
+    st = fsi.FsiState(model, fsi.FsiParams(omega0=0.05, p_in=0.3))
+    ks = [st.time_step()[0] for _ in range(2)]
+    for info, k in zip(infos, ks):
+        print(f"  DN iterations gpu {info.dn_iterations} oracle {k}", flush=True)
+        assert abs(info.dn_iterations - k) <= 2
+    assert np.abs(vs.reshape(-1, 4)[:, 0:3] - st.vs[:, 0:3]).max() <= 1e-4 * np.abs(st.vs[:, 0:3]).max()
+    assert np.abs(vf.reshape(-1, 4)[:, 0:3] - st.vf[:, 0:3]).max() <= 1e-4 * np.abs(st.vf[:, 0:3]).max()
 
 
 def test_fsi_step_larger_duct_host_checks(lib):
