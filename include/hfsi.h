@@ -108,8 +108,9 @@ typedef struct {
  * Coarsening stops at max_coarse rows, after max_levels levels, or when a
  * level would keep more than 90% of its rows (a stall, e.g. on the
  * mass-dominated fluid operator, whose couplings are not strong); the
- * coarsest level is inverted densely when it has at most 4096 rows, else it
- * is solved by 16 l1-Jacobi sweeps from zero.
+ * coarsest level is inverted densely when it has at most 4096 rows; a larger
+ * coarsest level left by a stall is solved by 16 l1-Jacobi sweeps from zero,
+ * one left by max_levels is HFSI_E_CAPACITY.
  * interp: 0 = classical, 1 = learned correction on level 0 (needs MLP
  * weights and lattice coordinates), judged by the convergence factor rho of
  * its V-cycle (10 stationary cycles from the SplitMix64 vector of seed 777):

@@ -1945,9 +1945,12 @@ void finish_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, bool same_pattern
   Level& Lc = H.L.back();
   const int nc = Lc.n;
   H.nc = nc;
-  // a coarsest level above the dense limit (the coarsening stalled: no
+  // a coarsest level above the dense limit where the coarsening stalled (no
   // strong couplings, e.g. a mass-dominated operator) is solved by l1-Jacobi
-  // sweeps, whose diagonal replaces the (unused) smoother diagonal there
+  // sweeps, whose diagonal replaces the (unused) smoother diagonal there;
+  // cut by max_levels instead, it is a capacity error
+  if (nc > kMaxDenseCoarse && !H.stalled)
+    fail(HFSI_E_CAPACITY, "coarsest level larger than 4096 rows (raise max_levels or lower max_coarse)");
   H.coarse_iterative = nc > kMaxDenseCoarse;
   if (H.coarse_iterative) {
     k_l1_diag<<<div_up(nc, 256), 256, 0, s>>>(nc, Lc.A.ptr.p, Lc.A.val.p, Lc.dinv.p, Lc.dinv32.p);
@@ -2041,6 +2044,7 @@ void build_levels(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) 
   Hierarchy& H = c->H;
   H.ready = false;
   H.reusable = false;
+  H.stalled = false;
   set_schedule(H, prm);
   AuxJoin aux_join{c};
   H.lmax_dev.ensure(32);
@@ -2108,7 +2112,10 @@ void build_levels(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) 
     HIP_LAUNCH_CHECK();
     L.cidx.ensure(n + 1);
     const int nc = (int)exclusive_scan(flag.p, L.cidx.p, n + 1, s);
-    if (nc == 0 || nc > 0.9 * n) break;
+    if (nc == 0 || nc > 0.9 * n) {
+      H.stalled = true;
+      break;
+    }
     // interpolation
     DevBuf<int> cnt;
     cnt.ensure(n + 1);

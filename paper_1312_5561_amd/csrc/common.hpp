@@ -207,8 +207,10 @@ struct Level {
 struct Hierarchy {
   std::vector<Level> L;
   int nc = 0;                 // coarsest size
-  // coarsening stalled above the dense limit: the coarsest level is solved
-  // by kCoarseSweeps l1-Jacobi sweeps from zero instead of its inverse
+  // the coarsening stalled (a level would keep more than 90% of its rows);
+  // above the dense limit the coarsest level is then solved by
+  // kCoarseSweeps l1-Jacobi sweeps from zero instead of its inverse
+  bool stalled = false;
   bool coarse_iterative = false;
   DevBuf<double> coarse_inv;  // explicit inverse of the coarsest operator
   DevBuf<double> lmax_dev;    // per-level eigenvalue estimates (written on the aux stream)
