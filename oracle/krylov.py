@@ -1,4 +1,4 @@
-"""Block-triangular preconditioner, FGMRES and BiCGStab (oracle).
+"""Block-triangular preconditioners, FGMRES, BiCGStab and GCR (oracle).
 
 The preconditioner is the paper's P_L (eq. lpre): with K = [A B1^T; B2 -C],
     P_L^{-1} [r_u; r_p] = [z_u; z_p],  z_u = Atilde^{-1} r_u,
@@ -7,6 +7,15 @@ where Atilde^{-1} is one AMG V-cycle on A and Stilde = (1/theta + 1/kappa)
 diag(M_p) (eq. lpreschur).  The Krylov method is right-preconditioned
 flexible GMRES(m) with classical Gram-Schmidt and one re-orthogonalisation
 (CGS2) and Givens rotations; the paper itself uses BiCGStab here.
+
+For the fluid the paper uses GCR with P_R = Dtilde Utilde (eq. rpre):
+    P_R^{-1} [r_u; r_p] = [z_u; z_p],  z_p = -Stilde^{-1} r_p,
+    z_u = Atilde^{-1} (r_u - B1^T z_p),
+here with a diagonal Stilde (the caller's s).  GCR(m): z_j = M^{-1} r,
+q_j = K z_j, q_j and z_j orthogonalised against the earlier q_i (two
+classical Gram-Schmidt passes, the same combination applied to the z_i)
+and scaled to |q_j| = 1, then x += (q_j.r) z_j, r -= (q_j.r) q_j; the
+recurrence residual ends a cycle, the true residual decides.
 """
 from __future__ import annotations
 
@@ -39,6 +48,20 @@ class BlockPreconditioner:
         ru, rp = split(r, self.n)
         zu = self.a_inv(ru)
         zp = (self.B2 @ zu - rp) / self.s
+        return join(zu, zp, self.n)
+
+
+class UpperBlockPreconditioner:
+    """P_R^{-1} (eq. rpre) with Atilde^{-1} a callable on displacement
+    vectors, B1T the (u, p) block of K and a diagonal Stilde = diag(s)."""
+
+    def __init__(self, a_inv, B1T, s, n):
+        self.a_inv, self.B1T, self.s, self.n = a_inv, B1T, s, n
+
+    def __call__(self, r):
+        ru, rp = split(r, self.n)
+        zp = -rp / self.s
+        zu = self.a_inv(ru - self.B1T @ zp)
         return join(zu, zp, self.n)
 
 
@@ -214,3 +237,56 @@ def krylov_factor(K, precond, b, k=20):
     classical hierarchy on an assembled tangent."""
     _, info = fgmres(K, precond, b, m=k, maxit=k, tol=1e-300)
     return info.rel_residual ** (1.0 / max(info.iterations, 1))
+
+
+def gcr(K, precond, b, x0=None, m=50, maxit=500, tol=1e-8):
+    """Solve K x = b with restarted, right-preconditioned GCR(m) (the
+    fluid's Krylov method, section "A preconditioner for the fluid
+    sub-problem") to ||b - K x||_2 <= tol ||b||_2.  The preconditioner may
+    change between steps (the z_j are kept)."""
+    n = b.shape[0]
+    x = np.zeros(n) if x0 is None else x0.copy()
+    info = SolveInfo()
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        x[:] = 0.0
+        info.rel_residual, info.converged = 0.0, True
+        return x, info
+    r = b - K @ x
+    rn = np.linalg.norm(r)
+    info.rel_residual = rn / bnorm
+    if rn <= tol * bnorm:
+        info.converged = True
+        return x, info
+    while info.iterations < maxit:
+        Q = np.zeros((m, n))
+        Z = np.zeros((m, n))
+        for j in range(m):
+            z = precond(r)
+            q = K @ z
+            for _ in range(2):
+                h = Q[:j] @ q
+                q = q - Q[:j].T @ h
+                z = z - Z[:j].T @ h
+            nq = np.linalg.norm(q)
+            if nq == 0.0:
+                info.breakdown = True
+                break
+            Q[j], Z[j] = q / nq, z / nq
+            alpha = Q[j] @ r
+            x = x + alpha * Z[j]
+            r = r - alpha * Q[j]
+            info.iterations += 1
+            info.history.append(np.linalg.norm(r) / bnorm)
+            if info.history[-1] <= tol or info.iterations >= maxit:
+                break
+        r = b - K @ x
+        rn = np.linalg.norm(r)
+        info.rel_residual = rn / bnorm
+        if rn <= tol * bnorm:
+            info.converged = True
+            break
+        if info.breakdown:
+            break
+        info.restarts += 1
+    return x, info
