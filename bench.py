@@ -306,7 +306,13 @@ def fsi_leg(shape, steps, torch, hfsi, variants=("new_hierarchies", "grids_kept"
     sk = hfsi.newton_params(amg=base.solid_step.amg, solve=base.solid_step.solve, amg_reuse=2)
     kept = hfsi.fsi_params(fluid_step=fk, solid_step=sk)
     adaptive = hfsi.fsi_params(fluid_step=fk, solid_step=sk, adaptive=1)
-    runs = {"new_hierarchies": base, "grids_kept": kept, "grids_kept_adaptive": adaptive}
+    # the paper's fluid solver: GCR with the upper block preconditioner P_R
+    fgcr = hfsi.newton_params(amg=base.fluid_step.amg, amg_reuse=2,
+                              solve=hfsi.solve_params(tol=base.fluid_step.solve.tol, restart=100, max_iter=1000,
+                                                      method=3, precond_form=1))
+    gcr_pr = hfsi.fsi_params(fluid_step=fgcr, solid_step=sk, adaptive=1)
+    runs = {"new_hierarchies": base, "grids_kept": kept, "grids_kept_adaptive": adaptive,
+            "grids_kept_adaptive_fluid_gcr_pr": gcr_pr}
     for label in variants:
         prm = runs[label]
         fl, me, so = hfsi.fsi_contexts(model)

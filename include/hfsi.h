@@ -229,7 +229,15 @@ typedef struct {
                            x <- x + M^{-1}(b - K x) with the preconditioner
                            of the last set-up (one V-cycle, normally the
                            coupled one) until the tolerance; iterations =
-                           V-cycles                                        */
+                           V-cycles; 3 = GCR(m), the paper's Krylov method
+                           for the fluid sub-problem (right preconditioning,
+                           two classical Gram-Schmidt passes, restart m)    */
+  int32_t precond_form; /* 0 = P_L (eq. lpre, default); 1 = P_R (eq. rpre):
+                           z_p = -Stilde^{-1} r_p, z_u = Atilde^{-1} (r_u -
+                           B1^T z_p), with the same Atilde (one V-cycle) and
+                           diagonal Stilde; the block forms of the last
+                           set-up only (HFSI_E_ARG with the coupled
+                           hierarchy)                                      */
 } hfsi_solve_params;
 
 typedef struct {

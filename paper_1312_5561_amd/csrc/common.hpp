@@ -305,6 +305,7 @@ struct hfsi_ctx {
   void* vanka_impl = nullptr;    // coupled (u,p) AMG with the Vanka smoother (vanka.hip)
   void* fluid_impl = nullptr;    // fluid or mesh-Laplacian physics (fluid.hip); null: the structure
   int precond_kind = 0;          // preconditioner of the last set-up: 0 P_L, 1 coupled V-cycle
+  int precond_form = 0;          // block form during a Krylov solve: 0 P_L, 1 P_R
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t kev[2] = {nullptr, nullptr};  // FGMRES scalar read-back slots
   hipStream_t aux = nullptr;               // AMG set-up work off the critical path

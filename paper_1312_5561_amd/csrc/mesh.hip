@@ -227,7 +227,7 @@ void colour_elements(int n, int m, const int32_t* tets, std::vector<int>& perm, 
 
 // ================================================================== ABI
 
-extern "C" int32_t hfsi_abi_version(void) { return 9; }
+extern "C" int32_t hfsi_abi_version(void) { return 10; }
 
 namespace {
 std::atomic<int> g_live_contexts{0};  // the device block cache is trimmed when none is left

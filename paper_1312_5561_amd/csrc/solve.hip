@@ -412,6 +412,55 @@ k_pl_combine(int n, const int* __restrict__ bptr, const int* __restrict__ bcol, 
   else if (lane < 4) z[4 * gid + lane - 1] = (double)zu[3 * gid + lane - 1];
 }
 
+// P_R (eq. rpre), pressure part: z_p = -r_p / s (r divided by *scale when
+// given, and the divided vector written to rs)
+__global__ void k_pr_pressure(int n, const double* __restrict__ r, const double* __restrict__ scale,
+                              double* __restrict__ rs, const double* __restrict__ schur, double* __restrict__ z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double rp = r[4 * i + 3];
+  if (scale) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) rs[4 * i + c] = r[4 * i + c] / scale[0];
+    rp = rs[4 * i + 3];
+  }
+  z[4 * i + 3] = -rp / schur[i];
+}
+
+// P_R, displacement right-hand side: b_u = r_u - B1^T z_p with B1^T read
+// from the (u, p) column of the 4x4 blocks of K; 16 lanes per node
+template <class T>
+__global__ void __launch_bounds__(256)
+k_pr_rhs(int n, const int* __restrict__ bptr, const int* __restrict__ bcol, const double* __restrict__ Kval,
+         const double* __restrict__ r, const double* __restrict__ z, T* __restrict__ bu) {
+  const int gid = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int lane = threadIdx.x & 15;
+  if (gid >= n) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int q = bptr[gid] + lane; q < bptr[gid + 1]; q += 16) {
+    const double zp = z[4 * bcol[q] + 3];
+    const double* blk = Kval + 16 * (size_t)q;
+    s0 += blk[3] * zp;
+    s1 += blk[7] * zp;
+    s2 += blk[11] * zp;
+  }
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) {
+    s0 += __shfl_xor(s0, o, 16);
+    s1 += __shfl_xor(s1, o, 16);
+    s2 += __shfl_xor(s2, o, 16);
+  }
+  if (lane < 3) bu[3 * gid + lane] = (T)(r[4 * gid + lane] - (lane == 0 ? s0 : (lane == 1 ? s1 : s2)));
+}
+
+// z_u (cycle type) into the node-interleaved output
+template <class T>
+__global__ void k_join_u(int n, const T* __restrict__ zu, double* __restrict__ z) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * n) return;
+  z[4 * (t / 3) + t % 3] = (double)zu[t];
+}
+
 // ---- Krylov vector kernels
 constexpr int RED_BLOCKS = 512;
 
@@ -949,6 +998,25 @@ void precond_apply(hfsi_ctx* c, const double* r, double* z, const double* scale,
   if (L0.n != 3 * n) fail(HFSI_E_ORDER, "preconditioner: hierarchy was not built on the assembled A");
   hipStream_t s = c->stream;
   const int grid16 = div_up((long)n * 16, 256);
+  if (c->precond_form == 1) {  // P_R: the pressure first, then one V-cycle on r_u - B1^T z_p
+    if (!scale) rs = nullptr;
+    k_pr_pressure<<<div_up(n, 256), 256, 0, s>>>(n, r, scale, rs, c->schur.p, z);
+    HIP_LAUNCH_CHECK();
+    const double* rr = scale ? rs : r;
+    if (H.precision == 0) {
+      k_pr_rhs<double><<<grid16, 256, 0, s>>>(n, c->nptr.p, c->ncol.p, c->Kval.p, rr, z, L0.b.p);
+      HIP_LAUNCH_CHECK();
+      double* zu = vcycle_rec<double>(c, 0, false);
+      k_join_u<double><<<div_up(3 * n, 256), 256, 0, s>>>(n, zu, z);
+    } else {
+      k_pr_rhs<float><<<grid16, 256, 0, s>>>(n, c->nptr.p, c->ncol.p, c->Kval.p, rr, z, L0.bf.p);
+      HIP_LAUNCH_CHECK();
+      float* zu = vcycle_rec<float>(c, 0, false);
+      k_join_u<float><<<div_up(3 * n, 256), 256, 0, s>>>(n, zu, z);
+    }
+    HIP_LAUNCH_CHECK();
+    return;
+  }
   // level 0 takes its first pre-smoothing step in the kernel that splits r
   const bool fuse = H.L.size() > 1 && H.nu_pre > 0;
   const int g4 = div_up(4 * n, 256);
@@ -1389,9 +1457,130 @@ void amg_iteration_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_sol
   info->seconds = elapsed_ms(c) * 1e-3;
 }
 
+namespace {
+// GCR step: q *= inv, z *= inv, x += alpha z, r -= alpha q
+__global__ void k_gcr_step(long N, double inv, double alpha, double* __restrict__ q, double* __restrict__ z,
+                           double* __restrict__ x, double* __restrict__ r) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= N) return;
+  const double qe = q[e] * inv, ze = z[e] * inv;
+  q[e] = qe;
+  z[e] = ze;
+  x[e] += alpha * ze;
+  r[e] -= alpha * qe;
+}
+}  // namespace
+
+// Restarted GCR(m) with right preconditioning: z_j = M^{-1} r, q_j = K z_j,
+// two classical Gram-Schmidt passes of q_j against q_0..q_{j-1} (the same
+// coefficients on z_j), |q_j| = 1, x += (q_j.r) z_j, r -= (q_j.r) q_j; the
+// recurrence residual ends a cycle, the true residual decides.
+void gcr_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_params& prm, hfsi_solve_info* info) {
+  const long N = 4L * c->n;
+  const long ld = (N + 31) / 32 * 32;
+  const int m = prm.restart;
+  hipStream_t s = c->stream;
+  c->kv.ensure((size_t)(m + 1) * ld);
+  c->kz.ensure((size_t)m * ld);
+  c->kr.ensure(N);
+  c->kh.ensure(2 * (size_t)m + 8);
+  c->kred.ensure((size_t)RED_BLOCKS * (2 * m + 1));
+  c->scal.ensure(16);
+  const int gN = div_up(N, 256);
+  double* sc = c->scal.p;
+  double* h = c->kh.p;
+  double* part = c->kred.p;
+  HIP_CHECK(hipEventRecord(c->ev0, s));
+  norm_dev(c, b, N, sc + 0);
+  const double bnorm = read_scalar(c, sc + 0);
+  int its = 0, restarts = 0;
+  bool converged = false, breakdown = false;
+  double rel = 0.0;
+  if (bnorm == 0.0) {
+    HIP_CHECK(hipMemsetAsync(x, 0, sizeof(double) * N, s));
+    converged = true;
+  } else {
+    double* r = c->kr.p;
+    residual(c, b, x, r);
+    norm_dev(c, r, N, sc + 1);
+    double rn = read_scalar(c, sc + 1);
+    rel = rn / bnorm;
+    converged = rn <= prm.tol * bnorm;
+    while (!converged && its < prm.max_iter) {
+      double* Q = c->kv.p;
+      double* Z = c->kz.p;
+      for (int j = 0; j < m; ++j) {
+        double* qj = Q + (long)j * ld;
+        double* zj = Z + (long)j * ld;
+        precond_apply(c, r, zj);
+        tangent_apply(c, zj, qj);
+        for (int pass = 0; pass < 2 && j > 0; ++pass) {
+          k_mdot2<<<dim3(RED_BLOCKS, div_up(j, MDOT_G)), 256, 0, s>>>(N, j, Q, ld, qj, qj, part);
+          HIP_LAUNCH_CHECK();
+          k_reduce_rows<<<j, 256, 0, s>>>(j, RED_BLOCKS, part, h, 0);
+          HIP_LAUNCH_CHECK();
+          k_vupdate<<<gN, 256, 0, s>>>(N, j, Q, ld, h, -1.0, qj);
+          k_vupdate<<<gN, 256, 0, s>>>(N, j, Z, ld, h, -1.0, zj);
+          HIP_LAUNCH_CHECK();
+        }
+        // q.q, q.r and r.r in one pass
+        k_mdot2<<<dim3(RED_BLOCKS, 1), 256, 0, s>>>(N, 1, qj, ld, qj, r, part);
+        HIP_LAUNCH_CHECK();
+        k_reduce_rows<<<3, 256, 0, s>>>(3, RED_BLOCKS, part, h, 0);
+        HIP_LAUNCH_CHECK();
+        double d[3];
+        HIP_CHECK(hipMemcpyAsync(d, h, sizeof(d), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        const double qq = d[0], qr = d[1], rr = d[2];
+        if (!std::isfinite(qq) || !std::isfinite(qr)) fail(HFSI_E_NAN, "GCR: non-finite inner product");
+        if (!(qq > 1e-300)) {
+          breakdown = true;
+          break;
+        }
+        const double nq = std::sqrt(qq), alpha = qr / nq;
+        k_gcr_step<<<gN, 256, 0, s>>>(N, 1.0 / nq, alpha, qj, zj, x, r);
+        HIP_LAUNCH_CHECK();
+        ++its;
+        const double r2 = rr - alpha * alpha;
+        rel = std::sqrt(r2 > 0.0 ? r2 : 0.0) / bnorm;
+        if (rel <= prm.tol || its >= prm.max_iter) break;
+      }
+      residual(c, b, x, r);
+      norm_dev(c, r, N, sc + 1);
+      rn = read_scalar(c, sc + 1);
+      rel = rn / bnorm;
+      if (!std::isfinite(rn)) fail(HFSI_E_NAN, "GCR: non-finite residual");
+      if (rn <= prm.tol * bnorm) {
+        converged = true;
+        break;
+      }
+      if (breakdown) break;
+      ++restarts;
+    }
+  }
+  HIP_CHECK(hipEventRecord(c->ev1, s));
+  if (info) {
+    info->iterations = its;
+    info->restarts = restarts;
+    info->rel_residual = rel;
+    info->converged = converged ? 1 : 0;
+    info->breakdown = breakdown ? 1 : 0;
+    info->seconds = elapsed_ms(c) * 1e-3;
+  }
+  if (breakdown && !converged) fail(HFSI_E_BREAKDOWN, "GCR breakdown before convergence");
+}
+
 void krylov_solve(hfsi_ctx* c, const double* b, double* x, const hfsi_solve_params& prm, hfsi_solve_info* info) {
+  if (prm.precond_form == 1 && c->precond_kind != 0)
+    fail(HFSI_E_ARG, "solve params: P_R needs the block preconditioner (not the coupled hierarchy)");
+  struct FormGuard {
+    hfsi_ctx* c;
+    ~FormGuard() { c->precond_form = 0; }
+  } guard{c};
+  c->precond_form = prm.precond_form;
   if (prm.method == 1) bicgstab_solve(c, b, x, prm, info);
   else if (prm.method == 2) amg_iteration_solve(c, b, x, prm, info);
+  else if (prm.method == 3) gcr_solve(c, b, x, prm, info);
   else fgmres_solve(c, b, x, prm, info);
 }
 
@@ -1402,8 +1591,9 @@ void check_solve_params(const hfsi_solve_params* p) {
   if (!p || p->struct_size != sizeof(hfsi_solve_params)) fail(HFSI_E_ARG, "solve params: struct_size mismatch");
   if (!(p->tol > 0) || p->restart < 1 || p->restart > 256 || p->max_iter < 1)
     fail(HFSI_E_ARG, "solve params: need tol > 0, 1 <= restart <= 256, max_iter >= 1");
-  if (p->method < 0 || p->method > 2)
-    fail(HFSI_E_ARG, "solve params: method 0 (FGMRES), 1 (BiCGStab) or 2 (AMG iteration)");
+  if (p->method < 0 || p->method > 3)
+    fail(HFSI_E_ARG, "solve params: method 0 (FGMRES), 1 (BiCGStab), 2 (AMG iteration) or 3 (GCR)");
+  if (p->precond_form < 0 || p->precond_form > 1) fail(HFSI_E_ARG, "solve params: precond_form 0 (P_L) or 1 (P_R)");
 }
 }  // namespace
 

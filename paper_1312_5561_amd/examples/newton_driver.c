@@ -41,6 +41,7 @@ static void* take(size_t bytes) {
 /* defaults documented in hfsi.h */
 static hfsi_newton_solve_params default_params(int adaptive, int learned, int coupled) {
   hfsi_newton_solve_params p;
+  memset(&p, 0, sizeof p);  /* every field not set below is zero */
   hfsi_amg_params* a = &p.step.amg;
   hfsi_solve_params* s = &p.step.solve;
   p.struct_size = sizeof p;
@@ -75,12 +76,14 @@ static hfsi_newton_solve_params default_params(int adaptive, int learned, int co
   s->restart = 50;
   s->max_iter = 500;
   s->method = 0;
+  s->precond_form = 0;
   p.eps2 = 1e-10;
   p.max_newton = 25;
   p.adaptive = adaptive;
   p.eps1_max = 1e-2;
   p.eps1_min = 1e-12;
   p.line_search = 0;
+  p.ref_norm = 0.0;
   return p;
 }
 

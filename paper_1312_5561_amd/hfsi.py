@@ -63,7 +63,7 @@ class AmgInfo(C.Structure):
 
 class SolveParams(C.Structure):
     _fields_ = [("struct_size", C.c_size_t), ("tol", C.c_double), ("restart", C.c_int32),
-                ("max_iter", C.c_int32), ("method", C.c_int32)]
+                ("max_iter", C.c_int32), ("method", C.c_int32), ("precond_form", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -144,10 +144,11 @@ def amg_params(theta=0.15, max_coarse=500, max_levels=25, seed=12345, smoother=1
                      vanka_omega, vanka_steps)
 
 
-def solve_params(tol=1e-8, restart=50, max_iter=500, method=0):
+def solve_params(tol=1e-8, restart=50, max_iter=500, method=0, precond_form=0):
     """method: 0 FGMRES(restart), 1 BiCGStab, 2 the AMG method as the
-    solver (one V-cycle per iteration)."""
-    return SolveParams(C.sizeof(SolveParams), tol, restart, max_iter, method)
+    solver (one V-cycle per iteration), 3 GCR(restart); precond_form: 0 the
+    lower block preconditioner P_L, 1 the upper one P_R."""
+    return SolveParams(C.sizeof(SolveParams), tol, restart, max_iter, method, precond_form)
 
 
 def newton_params(amg=None, solve=None, amg_reuse=0):

@@ -142,6 +142,32 @@ def test_fluid_newton_and_force_match_oracle(lib):
     assert np.abs(f.cpu().numpy() - fo).max() <= 1e-10 * np.abs(fo).max()
 
 
+def test_fluid_newton_gcr_upper_block(lib):
+    """The paper's fluid solver, GCR with P_R (eq. rpre, here with the
+    SIMPLE diagonal), inside the fluid Newton solve: the oracle's state and
+    iteration count."""
+    import torch
+    model = _model()
+    dmesh, _, uo, w = _random_fields(model, 5, scale=0.01)
+    nf = model.nf
+    v0 = np.zeros((nf, 4))
+    v0[model.iface_f, 0:3] = w[model.iface_f]
+    fl, me, so = lib.fsi_contexts(model, p_in=0.4, **PRM)
+    fl.set_fluid_fields(torch_dev(dmesh), torch_dev(uo), torch_dev(w))
+    vt = torch_dev(v0)
+    step = lib.newton_params(amg=lib.amg_params(smoother=0, nu_pre=2, nu_post=2),
+                             solve=lib.solve_params(tol=1e-10, restart=100, max_iter=1000, method=3, precond_form=1))
+    info, code = fl.newton_solve(vt, 1.0, lib.newton_solve_params(step=step, eps2=1e-10))
+    assert code == 0
+    d = fluid.FluidDiscretization(model.fluid_X, model.fluid_tets, model.fluid_dir, model.inlet_tris,
+                                  fluid.FluidParams(rho=PRM["rho_f"], mu=PRM["mu"], dt=PRM["dt"]))
+    vo, its, _ = fluid.newton_solve(d, v0, dmesh, uo, w, np.array([0.0, 0.0, 0.4]))
+    print(f"[fluid gcr+P_R] Newton {info.newton_iterations} (oracle {its}), Krylov {info.krylov_iterations}",
+          flush=True)
+    assert info.newton_iterations == its
+    assert np.abs(vt.cpu().numpy().ravel() - vo).max() <= 1e-8 * np.abs(vo).max()
+
+
 def _gpu_fsi(lib, model, p_in, steps, omega0=0.05):
     import torch
     fl, me, so = lib.fsi_contexts(model, p_in=p_in, **PRM)

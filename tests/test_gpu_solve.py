@@ -194,7 +194,7 @@ def test_bicgstab_solution(lib, precision):
     assert oinfo.converged
     assert abs(sinfo.iterations - oinfo.iterations) <= (1 if precision == 0 else 3)
     with pytest.raises(lib.HfsiError):
-        ctx.krylov_amg_solve(bt, x, lib.solve_params(method=3))
+        ctx.krylov_amg_solve(bt, x, lib.solve_params(method=4))
 
 
 def test_tangent_product_any_alignment(lib):
@@ -366,3 +366,46 @@ def test_vcycle_with_rows_spanning_more_than_16_bits(lib, precision):
     dz = np.abs(z.cpu().numpy() - zo)
     print(f"[vcycle wide rows] max |z - zo| / max |zo| = {dz.max() / np.abs(zo).max():.2e}", flush=True)
     assert dz.max() <= tol * np.abs(zo).max()
+
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_gcr_and_upper_block_preconditioner(lib, form):
+    """GCR (method 3, the paper's Krylov method for the fluid) with P_L or
+    P_R (eq. rpre): the direct solution to 1e-9 at a 1e-12 tolerance, the
+    true residual at 1e-8, and within one iteration of the oracle's GCR with
+    the GPU's hierarchy and the same block form; FGMRES with P_R within one
+    of the oracle's FGMRES."""
+    import torch
+    prob = synth.cube_problem(8)
+    v = synth.random_state(prob, 8, u_scale=0.02, p_scale=0.02).ravel()
+    print(f"[gcr parity] form={form}", flush=True)
+    ctx, R, info, oprm = _setup(lib, prob, v, 0.6, smoother=1, precision=0, schedule="default")
+    d, K, b, A, B2, s = oracle_system(prob, v, 0.6)
+    x_ref = spl.spsolve(K.tocsc(), b)
+    bt = -R
+    x = torch.zeros_like(bt)
+    sinfo, code = ctx.krylov_amg_solve(bt, x, lib.solve_params(tol=1e-12, restart=100, max_iter=2000, method=3,
+                                                               precond_form=form))
+    assert code == 0 and sinfo.converged
+    assert np.linalg.norm(x.cpu().numpy() - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
+    H = gpu_hierarchy_to_oracle(ctx, info, oprm)
+    a_inv = lambda r: amg.vcycle(H, r, oprm)  # noqa: E731
+    if form == 0:
+        M = krylov.BlockPreconditioner(a_inv, B2, s, prob.n_nodes)
+    else:
+        n = prob.n_nodes
+        Kc = K.tocsr()
+        u = np.array([4 * i + c for i in range(n) for c in range(3)])
+        B1T = Kc[u][:, 4 * np.arange(n) + 3]
+        M = krylov.UpperBlockPreconditioner(a_inv, B1T, s, n)
+    for method, oracle_solver in ((3, krylov.gcr), (0, krylov.fgmres)):
+        x.zero_()
+        sinfo, code = ctx.krylov_amg_solve(bt, x, lib.solve_params(tol=1e-8, restart=100, method=method,
+                                                                   precond_form=form))
+        true_res = np.linalg.norm(b - K @ x.cpu().numpy()) / np.linalg.norm(b)
+        assert code == 0 and sinfo.converged and true_res <= 1e-8
+        _, oinfo = oracle_solver(K, M, b, m=100, tol=1e-8)
+        print(f"[gcr parity] method {method} form {form}: gpu its={sinfo.iterations} oracle its={oinfo.iterations}",
+              flush=True)
+        assert oinfo.converged and abs(sinfo.iterations - oinfo.iterations) <= 1
