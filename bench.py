@@ -78,6 +78,13 @@ def parse():
                     help="comma-separated FSI solver variants to run")
     ap.add_argument("--fsi-artery-steps", type=int, default=3,
                     help="time steps of the FSI leg with the two-layer artery wall (0: skip)")
+    ap.add_argument("--fsi-tube-steps", type=int, default=0,
+                    help="time steps of the partitioned FSI sequence on the artery tube (0: skip; the "
+                         "workload's sequence has 20)")
+    ap.add_argument("--fsi-tube-ref-steps", type=int, default=2,
+                    help="steps of the tube sequence's comparison with fp64 hierarchies set up afresh")
+    ap.add_argument("--fsi-tube-shape", default="64,16,8,128",
+                    help="FSI tube: circumferential, lumen radial, wall radial, axial cells")
     args = ap.parse_args()
     if args.kappa is None:
         args.kappa = 1e4 if args.workload == "cube" else 1e5
@@ -357,12 +364,93 @@ def fsi_leg(shape, steps, torch, hfsi, variants=("new_hierarchies", "grids_kept"
             rec.append({"seconds": time.perf_counter() - t0, "dn_iterations": info.dn_iterations,
                         "fluid_newton": info.fluid_newton, "structure_newton": info.solid_newton,
                         "krylov": info.krylov})
+            print(f"[bench] FSI tube, {label}: step {k + 1}: {rec[-1]['seconds']:.2f} s, "
+                  f"{info.dn_iterations} DN iterations", file=sys.stderr, flush=True)
         out["artery_wall_grids_kept_adaptive"] = {
             "workload": f"square duct {a}x3x{nz}, two-layer artery wall: {nfa} fluid nodes, {nsa} structure nodes",
             "ms_per_time_step": sum(r["seconds"] for r in rec) / artery_steps * 1e3, "steps": rec,
             "max_wall_displacement_mm": float(vs.view(-1, 4)[:, 0:3].abs().max())}
         for c in (fl, me, so):
             c.close()
+    return out
+
+
+def fsi_tube_leg(shape, steps, torch, hfsi, ref_steps=2):
+    """The partitioned FSI sequence on the artery tube: the two-layer wall
+    (the tube workload's geometry and materials, both ends clamped, wall
+    density 1.2 mg/mm^3) and its round lumen, a stabilised P1-P1 Oseen fluid
+    (rho 1 mg/mm^3, mu 0.035 P = 0.0035 kPa ms) with a Poiseuille inflow of
+    peak 30 cm/s = 0.3 mm/ms and a free outlet, dt = 1 ms, Dirichlet-Neumann
+    with Aitken relaxation to |r|/sqrt(n) < 1e-8.  The fluid is solved with
+    the coupled (u,p) AMG and the additive Vanka smoother (one sweep before
+    and after the correction, distance-one interpolation), the structure
+    with fp32 Chebyshev V-cycles.  "kept": every sub-problem keeps its whole
+    preconditioner across Newton iterations, DN iterations and steps (set up
+    anew only when a solve converges at under half the rate of the first
+    after its set-up), adaptive inner tolerances; "fp64_new_hierarchies":
+    fp64 hierarchies set up afresh for every Newton iteration, fixed 1e-10
+    inner solves, over the first ref_steps steps (its per-step cost is the
+    comparison).  The learned interpolation is not used: its judge keeps
+    classical interpolation on the tube, and the coupled hierarchy takes
+    none."""
+    import synth
+    nt, nr, nw, nz = shape
+    model = synth.fsi_tube(nt, nr, 5 * nw // 8, nw - 5 * nw // 8, nz)
+    nf, ns = model.nf, model.solid.n_nodes
+    out = {"workload": f"artery tube {nt}x{nw}x{nz} with its lumen {nt}x{nr}x{nz}: {nf} fluid nodes "
+                       f"({4 * nf} dofs), {ns} structure nodes ({4 * ns} dofs), {len(model.iface_f)} interface "
+                       f"nodes; Oseen fluid, Poiseuille inflow 0.3 mm/ms, dt 1 ms", "steps": steps}
+    sv = hfsi.solve_params(tol=1e-10, restart=100, max_iter=1000)
+    msv = hfsi.solve_params(tol=1e-12, restart=100, max_iter=1000)
+    fluid_amg = hfsi.amg_params(coupled=2, vanka_steps=1, interp_kind=0)
+    variants = {
+        "kept": (steps, hfsi.fsi_params(
+            fluid_step=hfsi.newton_params(amg=fluid_amg, solve=sv, amg_reuse=3),
+            solid_step=hfsi.newton_params(amg=hfsi.amg_params(smoother=1, precision=1), solve=sv, amg_reuse=3),
+            mesh_step=hfsi.newton_params(solve=msv, amg_reuse=3), adaptive=1)),
+        "fp64_new_hierarchies": (min(ref_steps, steps), hfsi.fsi_params(
+            fluid_step=hfsi.newton_params(amg=fluid_amg, solve=sv),
+            solid_step=hfsi.newton_params(amg=hfsi.amg_params(smoother=1), solve=sv),
+            mesh_step=hfsi.newton_params(solve=msv)))}
+    for label, (n_steps, prm) in variants.items():
+        if n_steps <= 0:
+            continue
+        t0 = time.perf_counter()
+        fl, me, so = hfsi.fsi_contexts(model, rho_f=1.0, mu=0.0035, dt=1.0, rho_s=1.2, p_in=0.0, oseen=1)
+        print(f"[bench] FSI tube, {label}: contexts set up in {time.perf_counter() - t0:.2f} s",
+              file=sys.stderr, flush=True)
+        z = lambda k: torch.zeros(k, dtype=torch.float64, device="cuda")  # noqa: E731
+        vf0 = np.zeros((nf, 4))
+        vf0[:, 0:3] = model.inflow
+        vf = torch.from_numpy(vf0.ravel()).to("cuda")
+        df, vs, vel, acc = z(3 * nf), z(4 * ns), z(3 * ns), z(3 * ns)
+        rec = []
+        torch.cuda.synchronize()
+        t_all = time.perf_counter()
+        for k in range(n_steps):
+            t0 = time.perf_counter()
+            info, code = hfsi.fsi_time_step(fl, me, so, model.iface_f, model.iface_s, vf, df, vs, vel, acc, 1.0, prm)
+            torch.cuda.synchronize()
+            if code != 0:
+                raise RuntimeError(f"FSI tube leg: time step {k + 1} did not converge")
+            rec.append({"seconds": time.perf_counter() - t0, "dn_iterations": info.dn_iterations,
+                        "fluid_newton": info.fluid_newton, "structure_newton": info.solid_newton,
+                        "krylov": info.krylov})
+            print(f"[bench] FSI tube, {label}: step {k + 1}: {rec[-1]['seconds']:.2f} s, "
+                  f"{info.dn_iterations} DN iterations", file=sys.stderr, flush=True)
+        total = time.perf_counter() - t_all
+        out[label] = {"steps_run": n_steps, "seconds_total": total, "ms_per_time_step": total / n_steps * 1e3,
+                      "dn_iterations": [r["dn_iterations"] for r in rec], "steps": rec,
+                      "max_wall_displacement_mm": float(vs.view(-1, 4)[:, 0:3].abs().max())}
+        print(f"[bench] FSI tube, {label}: {total:.2f} s for {n_steps} steps, DN iterations "
+              f"{out[label]['dn_iterations']}", file=sys.stderr, flush=True)
+        for c in (fl, me, so):
+            c.close()
+    if "fp64_new_hierarchies" in out and "kept" in out:
+        n = out["fp64_new_hierarchies"]["steps_run"]
+        a = sum(r["seconds"] for r in out["kept"]["steps"][:n])
+        b = out["fp64_new_hierarchies"]["seconds_total"]
+        out["speedup_kept_vs_fp64_first_steps"] = b / a
     return out
 
 
@@ -377,6 +465,12 @@ def main():
     from paper_1312_5561_amd import hfsi
 
     if args.fsi_only:
+        if args.fsi_tube_steps > 0:
+            tshape = tuple(int(x) for x in args.fsi_tube_shape.split(","))
+            print(json.dumps({"fsi_tube_sequence": fsi_tube_leg(tshape, args.fsi_tube_steps, torch, hfsi,
+                                                                  args.fsi_tube_ref_steps)}),
+                  flush=True)
+            return
         shape = tuple(int(x) for x in args.fsi_shape.split(","))
         print(json.dumps({"fsi_time_steps": fsi_leg(shape, args.fsi_steps, torch, hfsi,
                                                     tuple(args.fsi_variants.split(",")),
@@ -609,6 +703,9 @@ def main():
               f"{fs['grids_kept']['ms_per_time_step']:.0f} ms with grids kept, "
               f"{fs['grids_kept_adaptive']['ms_per_time_step']:.0f} ms adaptive; DN iterations "
               f"{[r['dn_iterations'] for r in fs['grids_kept']['steps']]}", file=sys.stderr, flush=True)
+    if not args.quick and args.fsi_tube_steps > 0 and args.workload == "cube":
+        tshape = tuple(int(x) for x in args.fsi_tube_shape.split(","))
+        res["fsi_tube_sequence"] = fsi_tube_leg(tshape, args.fsi_tube_steps, torch, hfsi, args.fsi_tube_ref_steps)
     # the headline state's tangent for the roofline timing
     v.copy_(v0)
     R0 = torch.zeros_like(v)

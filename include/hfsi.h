@@ -257,7 +257,20 @@ typedef struct {
   int32_t amg_reuse;    /* 0 = full AMG set-up every step (default); 1 =
                            re-set-up on the coarse grids of the previous
                            set-up of this mesh when there is one (see
-                           hfsi_amg_resetup), else a full set-up           */
+                           hfsi_amg_resetup), else a full set-up; 3 = no
+                           set-up at all: keep the whole preconditioner of
+                           the last set-up that a Newton iteration made on
+                           this context while it has the same AMG
+                           parameters and stays usable (FGMRES applies the
+                           new tangent exactly and only its preconditioner
+                           is older).  It is given up, for a set-up as with
+                           1, after a Krylov solve with it fails or reduces
+                           the residual at under half the mean log rate per
+                           iteration of the first solve after its set-up;
+                           any other set-up, assembly through the public
+                           entry point or change of mesh, conditions or
+                           physics also ends it.  2 = as 1 (in
+                           hfsi_newton_solve: also on its first iteration) */
 } hfsi_newton_params;
 
 typedef struct {
@@ -268,7 +281,8 @@ typedef struct {
   double rel_residual;
   double t_assemble, t_setup, t_solve, t_total;
   int32_t amg_levels;
-  int32_t amg_reused;   /* 1 if this step re-used the previous coarse grids */
+  int32_t amg_reused;   /* 1 if this step re-used the previous coarse grids,
+                           2 if it kept the whole preconditioner          */
 } hfsi_newton_info;
 
 typedef struct {
@@ -279,7 +293,9 @@ typedef struct {
                                first iteration's coarse grids for the later
                                ones, 2 also starts from the coarse grids of
                                an earlier call on this mesh when there are
-                               some (time steps)                            */
+                               some (time steps), 3 keeps the whole
+                               preconditioner across iterations and calls
+                               while it stays usable (hfsi_newton_params) */
   double eps2;              /* stop at ||dv_k||_M <= eps2 ||dv_0||_M (eq.
                                newstop, relative form), default 1e-10       */
   int32_t max_newton;       /* default 25                                   */
@@ -456,7 +472,10 @@ hfsi_status hfsi_time_step(hfsi_ctx* ctx, double* v, double* vel, double* acc, d
 /* Switch a context to the fluid sub-problem (section "The fluid
  * sub-problem", eq. ns; implicit Euler, eq. nstdis; weak form eq. weakns
  * with SUPG/PSPG stabilisation, eq. stabweakfluid): rho > 0 fluid density,
- * mu >= 0 dynamic viscosity, dt > 0 time step.  Needs a mesh (stage 1);
+ * mu >= 0 dynamic viscosity, dt > 0 time step; oseen = 1 takes the
+ * previous step's velocity as the convective field, c = u_old - w (the
+ * Oseen step, linear in (u, p)), 0 the Navier-Stokes c = u - w.  Needs a
+ * mesh (stage 1);
  * set_materials (any valid record: unused by the fluid) and set_bc (dir_mask
  * fixes the velocity dofs with prescribed values, e.g. the interface; the
  * triangles and their traction are the inlet Neumann data g_in at load
@@ -475,7 +494,7 @@ hfsi_status hfsi_time_step(hfsi_ctx* ctx, double* v, double* vel, double* acc, d
  * displacement d_f, the previous velocity u_old and the mesh velocity w
  * start at zero (hfsi_set_fluid_fields).  A later hfsi_set_mesh returns the
  * context to the structure.  HFSI_E_ARG on bad values. */
-hfsi_status hfsi_set_fluid(hfsi_ctx* ctx, double rho, double mu, double dt);
+hfsi_status hfsi_set_fluid(hfsi_ctx* ctx, double rho, double mu, double dt, int32_t oseen);
 
 /* Device fields [n][3] of a fluid context, each copied when not NULL: mesh
  * displacement d_f, previous step's velocity u_old (nodal values: the ALE

@@ -32,7 +32,10 @@ readings taken here:
 * the Jacobian is the exact derivative with tau held at its value at the
   current iterate (tau depends on |c| through a non-smooth norm);
 * g_in is constant over the inlet, and the inlet does not move (the mesh
-  displacement is zero there), so its nodal load is g_in A_tri / 3.
+  displacement is zero there), so its nodal load is g_in A_tri / 3;
+* the Oseen form (an option) takes the previous step's velocity as the
+  convective field, c = u_old - w, in the convection term, the SUPG test
+  function and tau: the step is then linear in (u, p).
 
 Nodes are node-interleaved (u_x, u_y, u_z, p), the layout and block pattern
 of the structure.  The force the fluid exerts on the structure at an
@@ -66,6 +69,7 @@ class FluidParams:
     mu: float = 0.0035    # kPa ms (0.035 Poise)
     dt: float = 0.125     # ms
     stabilise: bool = True
+    oseen: bool = False   # convective velocity u_old - w (Oseen) instead of u - w
 
 
 def geometry(x):
@@ -97,7 +101,8 @@ def element_kernel(x, ue, pe, uo, we, prm: FluidParams, want_tangent=True, tau=N
     rho, mu, dt = prm.rho, prm.mu, prm.dt
     G, V, h = geometry(x)
     m = len(V)
-    ce = ue - we                                        # nodal convective velocity
+    ce = (uo if prm.oseen else ue) - we                 # nodal convective velocity
+    dc = 0.0 if prm.oseen else 1.0                      # d c / d u
     if tau is None:
         tau = tau_of(ce.mean(axis=1), h, prm)
     if not prm.stabilise:
@@ -130,14 +135,14 @@ def element_kernel(x, ue, pe, uo, we, prm: FluidParams, want_tangent=True, tau=N
     I3 = np.eye(3)
     NN = np.einsum("qa,qb->ab", QUAD, QUAD)             # sum_q N_a N_b (times w: the mass)
     cGb = cG                                             # c(q) . grad N_b, [m,q,b]
-    # d r_i(q) / d u_bk = delta_ik (N_b(q)/dt + c(q).G_b) + Gu_ik N_b(q)
+    # d r_i(q) / d u_bk = delta_ik (N_b(q)/dt + c(q).G_b) + dc Gu_ik N_b(q)
     dr_diag = QUAD[None, :, :] / dt + cGb                # [m,q,b]
     # Galerkin momentum: mass, convection (both factors), viscous
     K[:, :, 0:3, :, 0:3] += ((w * rho / dt)[:, None, None, None, None] * NN[None, :, None, :, None]
                               * I3[None, None, :, None, :])
     K[:, :, 0:3, :, 0:3] += (w * rho)[:, None, None, None, None] * (
         np.einsum("qa,mqb->mab", QUAD, cGb)[:, :, None, :, None] * I3[None, None, :, None, :]
-        + NN[None, :, None, :, None] * Gu[:, None, :, None, :])
+        + dc * NN[None, :, None, :, None] * Gu[:, None, :, None, :])
     GG = np.einsum("maj,mbj->mab", G, G)
     K[:, :, 0:3, :, 0:3] += (mu * V)[:, None, None, None, None] * (
         GG[:, :, None, :, None] * I3[None, None, :, None, :]
@@ -147,16 +152,16 @@ def element_kernel(x, ue, pe, uo, we, prm: FluidParams, want_tangent=True, tau=N
     # SUPG: d/du_bk of w rho tau sum_q (c.G_a) r_i
     s = (w * rho * tau)[:, None, None, None, None]
     K[:, :, 0:3, :, 0:3] += s * (
-        np.einsum("qb,mak,mqi->maibk", QUAD, G, r)
+        dc * np.einsum("qb,mak,mqi->maibk", QUAD, G, r)
         + np.einsum("mqa,mqb->mab", cG, dr_diag)[:, :, None, :, None] * I3[None, None, :, None, :]
-        + np.einsum("mqa,qb->mab", cG, QUAD)[:, :, None, :, None] * Gu[:, None, :, None, :])
+        + dc * np.einsum("mqa,qb->mab", cG, QUAD)[:, :, None, :, None] * Gu[:, None, :, None, :])
     K[:, :, 0:3, :, 3] += (w * tau)[:, None, None, None] * np.einsum("mqa,mbi->maib", cG, G)
     # continuity: d/du_bk of -w div u
     K[:, :, 3, :, 0:3] += -w[:, None, None, None] * G[:, None, :, :]
     # PSPG: d/du_bk of -w tau sum_q G_a . r
     K[:, :, 3, :, 0:3] += -(w * tau)[:, None, None, None] * (
         np.einsum("mak,mqb->mabk", G, dr_diag)
-        + np.einsum("mai,mik,qb->mabk", G, Gu, QUAD))
+        + dc * np.einsum("mai,mik,qb->mabk", G, Gu, QUAD))
     K[:, :, 3, :, 3] += -(V * tau / rho)[:, None, None] * GG
     return R, K.reshape(m, 16, 16)
 

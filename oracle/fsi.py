@@ -128,6 +128,8 @@ class FsiState:
         self.vel = np.zeros((ns, 3))
         self.acc = np.zeros((ns, 3))
         self.vf = np.zeros((nf, 4))
+        if getattr(model, "inflow", None) is not None:   # prescribed inlet velocity (kept by every step)
+            self.vf[:, 0:3] = model.inflow
         self.df = np.zeros((nf, 3))
         self.t = 0.0
         self.nm = newmark.NewmarkParams(rho=prm.rho_s, dt=prm.fluid.dt, beta=prm.beta, gamma=prm.gamma)

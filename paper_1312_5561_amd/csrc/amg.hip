@@ -2268,6 +2268,7 @@ void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* inf
 }
 
 void amg_setup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {
+  c->keep_valid = false;
   if (prm.coupled) {
     vanka_setup(c, prm, info);
     return;
@@ -2304,6 +2305,7 @@ void amg_setup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* in
 // is again the Galerkin product R A P, and the smoother data, coarsest inverse
 // and cycle copies are rebuilt.  No strength, PMIS, interpolation or judge.
 void amg_resetup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {
+  c->keep_valid = false;
   if (prm.coupled) {  // the coupled hierarchy is always built anew
     vanka_setup(c, prm, info);
     return;
@@ -2366,6 +2368,17 @@ void check_amg_params(const hfsi_amg_params* p) {
   }
 }
 
+bool same_amg_params(const hfsi_amg_params& a, const hfsi_amg_params& b) {
+  return a.strength_theta == b.strength_theta && a.max_coarse == b.max_coarse && a.max_levels == b.max_levels &&
+         a.seed == b.seed && a.smoother == b.smoother && a.nu_pre == b.nu_pre && a.nu_post == b.nu_post &&
+         a.precision == b.precision && a.interp == b.interp && a.fallback_rho == b.fallback_rho &&
+         a.cheb_degree == b.cheb_degree && a.cheb_ratio == b.cheb_ratio && a.interp_kind == b.interp_kind &&
+         a.p_max == b.p_max && a.cheb_degree_pre == b.cheb_degree_pre && a.nu_post_coarse == b.nu_post_coarse &&
+         a.cheb_degree_coarse == b.cheb_degree_coarse && a.nu_pre_coarse == b.nu_pre_coarse &&
+         a.judge_classical == b.judge_classical && a.drop_tol == b.drop_tol && a.coupled == b.coupled &&
+         a.vanka_omega == b.vanka_omega && a.vanka_steps == b.vanka_steps;
+}
+
 }  // namespace hfsi
 
 extern "C" hfsi_status hfsi_amg_setup(hfsi_ctx* c, const hfsi_amg_params* prm, hfsi_amg_info* info) {
@@ -2394,6 +2407,7 @@ extern "C" hfsi_status hfsi_amg_setup_csr(hfsi_ctx* c, int32_t n, const int32_t*
   if (n <= 0 || !ptr || !col || !val || !comp) fail(HFSI_E_ARG, "amg_setup_csr: bad arguments");
   if (prm->coupled) fail(HFSI_E_ARG, "amg_setup_csr: the coupled hierarchy needs the assembled tangent");
   if (info && info->struct_size != sizeof(hfsi_amg_info)) fail(HFSI_E_ARG, "amg info: struct_size mismatch");
+  c->keep_valid = false;
   const int64_t nnz = ptr[n];
   if (ptr[0] != 0 || nnz < n) fail(HFSI_E_ARG, "amg_setup_csr: bad row pointer");
   for (int i = 0; i < n; ++i) {

@@ -306,6 +306,13 @@ struct hfsi_ctx {
   void* fluid_impl = nullptr;    // fluid or mesh-Laplacian physics (fluid.hip); null: the structure
   int precond_kind = 0;          // preconditioner of the last set-up: 0 P_L, 1 coupled V-cycle
   int precond_form = 0;          // block form during a Krylov solve: 0 P_L, 1 P_R
+  // Newton with amg_reuse = 3: the preconditioner of the last set-up made by
+  // a Newton iteration on this context is kept whole while it stays usable
+  bool keep_valid = false;       // such a preconditioner exists (any set-up or change of the problem clears it)
+  bool keep_stale = false;       // a solve with it converged at under half its first rate: build anew
+  hfsi_amg_params keep_prm{};    // the parameters of that set-up
+  int keep_levels = 0;
+  double keep_rate0 = 0.0;       // log10 residual reduction per iteration of its first solve (0: none yet)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t kev[2] = {nullptr, nullptr};  // FGMRES scalar read-back slots
   hipStream_t aux = nullptr;               // AMG set-up work off the critical path
@@ -338,6 +345,7 @@ void amg_setup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* in
 void amg_resetup_level0(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info);
 void build_hierarchy(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info);
 void check_amg_params(const hfsi_amg_params* p);
+bool same_amg_params(const hfsi_amg_params& a, const hfsi_amg_params& b);
 void vcycle_apply(hfsi_ctx* c, const double* r, double* z);
 // z = P_L^{-1} r; with scale, the vector preconditioned is r / *scale, also
 // written to rs

@@ -50,8 +50,8 @@ __global__ void __launch_bounds__(128)
 k_fluid_element(int e0, int e1, int m, const int* __restrict__ T, const double* __restrict__ X,
                 const double* __restrict__ dmesh, const double* __restrict__ V0s, const int* __restrict__ slot,
                 const double* __restrict__ v, const double* __restrict__ uo, const double* __restrict__ wm,
-                double rho, double mu, double dt, double* __restrict__ R, double* __restrict__ Kval, int want_K,
-                unsigned long long* __restrict__ minJ, int* __restrict__ inverted) {
+                double rho, double mu, double dt, int oseen, double* __restrict__ R, double* __restrict__ Kval,
+                int want_K, unsigned long long* __restrict__ minJ, int* __restrict__ inverted) {
   const int e = e0 + blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= e1) return;
   int nd[4];
@@ -65,7 +65,7 @@ k_fluid_element(int e0, int e1, int m, const int* __restrict__ T, const double* 
       x[a][i] = X[3 * k + i] + dmesh[3 * k + i];
       u[a][i] = v[4 * k + i];
       uold[a][i] = uo[3 * k + i];
-      c[a][i] = u[a][i] - wm[3 * k + i];
+      c[a][i] = (oseen ? uold[a][i] : u[a][i]) - wm[3 * k + i];
     }
     p[a] = v[4 * k + 3];
   }
@@ -172,6 +172,8 @@ k_fluid_element(int e0, int e1, int m, const int* __restrict__ T, const double* 
     Ra[3] += -w * div - w * tau * pspg;
   }
   if (!want_K) return;
+  // derivative of the convective velocity c by u: 1 (Navier-Stokes), 0 (Oseen)
+  const double dc = oseen ? 0.0 : 1.0;
   // per-node sums over the quadrature points
   double scG[4];  // sum_q c(q).G_a
 #pragma unroll
@@ -203,15 +205,15 @@ k_fluid_element(int e0, int e1, int m, const int* __restrict__ T, const double* 
       for (int i = 0; i < 3; ++i) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          double val = w * rho * NN * Gu[i][k] + mu * V * G[a][k] * G[b][i] +
-                       w * rho * tau * (G[a][k] * rN[i] + cGN * Gu[i][k]);
+          double val = dc * w * rho * NN * Gu[i][k] + mu * V * G[a][k] * G[b][i] +
+                       dc * w * rho * tau * (G[a][k] * rN[i] + cGN * Gu[i][k]);
           if (i == k) val += w * rho * (NN / dt + NcGb) + mu * V * GG + w * rho * tau * cGdr;
           blk[i * 4 + k] = val;
         }
         blk[i * 4 + 3] = -0.25 * V * G[a][i] + w * tau * scG[a] * G[b][i];
       }
 #pragma unroll
-      for (int k = 0; k < 3; ++k) blk[12 + k] = -w * G[b][k] - w * tau * (G[a][k] * sdr + GaGu[k]);
+      for (int k = 0; k < 3; ++k) blk[12 + k] = -w * G[b][k] - w * tau * (G[a][k] * sdr + dc * GaGu[k]);
       blk[15] = -(V * tau / rho) * GG;
       double* dst = Kval + 16 * (size_t)slot[(a * 4 + b) * m + e];
 #pragma unroll
@@ -426,6 +428,7 @@ __global__ void k_sub_load(int n, double load, const double* __restrict__ fext, 
 struct FluidState {
   int physics = 0;  // 1 fluid, 2 mesh Laplacian
   double rho = 1.0, mu = 0.0035, dt = 0.125;
+  int oseen = 0;    // 1: convective velocity u_old - w (the Oseen step)
   DevBuf<double> dmesh, uold, w;  // [n][3]
 };
 
@@ -456,8 +459,8 @@ void fluid_elements(hfsi_ctx* c, const double* v, double* R, bool want_K) {
     const int e0 = c->colour_ptr[q], e1 = c->colour_ptr[q + 1];
     if (F.physics == 1)
       k_fluid_element<<<div_up(e1 - e0, 128), 128, 0, s>>>(
-          e0, e1, c->m, c->tets.p, c->X.p, F.dmesh.p, c->V.p, c->slot.p, v, F.uold.p, F.w.p, F.rho, F.mu, F.dt, R,
-          c->Kval.p, want_K ? 1 : 0, (unsigned long long*)c->scal.p, c->iscal.p);
+          e0, e1, c->m, c->tets.p, c->X.p, F.dmesh.p, c->V.p, c->slot.p, v, F.uold.p, F.w.p, F.rho, F.mu, F.dt,
+          F.oseen, R, c->Kval.p, want_K ? 1 : 0, (unsigned long long*)c->scal.p, c->iscal.p);
     else
       k_laplace_element<<<div_up(e1 - e0, 128), 128, 0, s>>>(e0, e1, c->m, c->tets.p, c->G.p, c->V.p, c->slot.p, v,
                                                              R, c->Kval.p, want_K ? 1 : 0);
@@ -505,15 +508,17 @@ void upload_field(hfsi_ctx* c, DevBuf<double>& dst, const double* src) {
 
 }  // namespace
 
-extern "C" hfsi_status hfsi_set_fluid(hfsi_ctx* c, double rho, double mu, double dt) {
+extern "C" hfsi_status hfsi_set_fluid(hfsi_ctx* c, double rho, double mu, double dt, int32_t oseen) {
   HFSI_ABI_BEGIN(c)
   require_stage(c, 1, "set_fluid");
-  if (!(rho > 0.0) || !(mu >= 0.0) || !(dt > 0.0)) fail(HFSI_E_ARG, "set_fluid: need rho > 0, mu >= 0, dt > 0");
+  if (!(rho > 0.0) || !(mu >= 0.0) || !(dt > 0.0) || oseen < 0 || oseen > 1)
+    fail(HFSI_E_ARG, "set_fluid: need rho > 0, mu >= 0, dt > 0, oseen 0 or 1");
   FluidState& F = fluid_state(c);
   F.physics = 1;
   F.rho = rho;
   F.mu = mu;
   F.dt = dt;
+  F.oseen = oseen;
   F.dmesh.zero(3 * (size_t)c->n, c->stream);
   F.uold.zero(3 * (size_t)c->n, c->stream);
   F.w.zero(3 * (size_t)c->n, c->stream);

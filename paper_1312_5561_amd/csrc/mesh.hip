@@ -10,7 +10,7 @@ using namespace hfsi;
 
 namespace {
 
-constexpr int NBR_MAX = 128;  // distinct neighbours of one node (incl. itself)
+constexpr int NBR_MAX = 512;  // distinct neighbours of one node (incl. itself)
 
 // Reference gradients of the P1 hat functions, volume and longest edge of
 // every tetrahedron: with D = [X1-X0, X2-X0, X3-X0], grad N_a (a = 1..3) is
@@ -201,19 +201,32 @@ __global__ void k_loads(int n, const int* __restrict__ n2tri_ptr, const int* __r
 }
 
 // Greedy element colouring: no two elements of one colour share a node.
-// Each node keeps a bit mask of the colours already touching it.
+// Each node keeps bit masks of the colours already touching it, 64 colours
+// per word; a word is added when every colour of the earlier ones is taken
+// at some element (meshes with a node in many elements, such as the axis
+// of a lumen mesh), up to 1024 colours.
 void colour_elements(int n, int m, const int32_t* tets, std::vector<int>& perm, std::vector<int>& cptr) {
-  std::vector<uint64_t> used(n, 0);
+  constexpr size_t kMaxWords = 16;
+  std::vector<std::vector<uint64_t>> used(1, std::vector<uint64_t>(n, 0));
   std::vector<int> col(m);
   int ncol = 0;
   for (int e = 0; e < m; ++e) {
-    uint64_t u = 0;
-    for (int a = 0; a < 4; ++a) u |= used[tets[4 * e + a]];
-    if (~u == 0) fail(HFSI_E_CAPACITY, "element colouring needs more than 64 colours");
-    int c = __builtin_ctzll(~u);
+    int c = -1;
+    for (size_t w = 0; c < 0; ++w) {
+      if (w == used.size()) {
+        if (w >= kMaxWords) fail(HFSI_E_CAPACITY, "element colouring needs more than 1024 colours");
+        used.emplace_back(n, 0);
+      }
+      uint64_t u = 0;
+      for (int a = 0; a < 4; ++a) u |= used[w][tets[4 * e + a]];
+      if (~u != 0) {
+        const int b = __builtin_ctzll(~u);
+        c = 64 * (int)w + b;
+        for (int a = 0; a < 4; ++a) used[w][tets[4 * e + a]] |= (1ull << b);
+      }
+    }
     col[e] = c;
     ncol = std::max(ncol, c + 1);
-    for (int a = 0; a < 4; ++a) used[tets[4 * e + a]] |= (1ull << c);
   }
   cptr.assign(ncol + 1, 0);
   for (int e = 0; e < m; ++e) cptr[col[e] + 1]++;
@@ -227,7 +240,7 @@ void colour_elements(int n, int m, const int32_t* tets, std::vector<int>& perm, 
 
 // ================================================================== ABI
 
-extern "C" int32_t hfsi_abi_version(void) { return 10; }
+extern "C" int32_t hfsi_abi_version(void) { return 11; }
 
 namespace {
 std::atomic<int> g_live_contexts{0};  // the device block cache is trimmed when none is left
@@ -403,7 +416,7 @@ extern "C" hfsi_status hfsi_set_mesh(hfsi_ctx* c, int64_t n_nodes, const double*
   }
   auto f = flag.download(4, s);
   if (f[0]) fail(HFSI_E_ARG, "set_mesh: an element has non-positive volume (check orientation)");
-  if (f[1]) fail(HFSI_E_CAPACITY, "set_mesh: a node has more than 127 neighbours");
+  if (f[1]) fail(HFSI_E_CAPACITY, "set_mesh: a node has more than 511 neighbours");
   c->stage = 1;
   c->judge.valid = false;
   HFSI_ABI_END(c)

@@ -1944,6 +1944,7 @@ struct EventPair {
 
 void check_newton_params(const hfsi_newton_params* prm) {
   if (!prm || prm->struct_size != sizeof(hfsi_newton_params)) fail(HFSI_E_ARG, "newton params: struct_size mismatch");
+  if (prm->amg_reuse < 0 || prm->amg_reuse > 3) fail(HFSI_E_ARG, "newton params: amg_reuse in 0..3");
   hfsi::check_amg_params(&prm->amg);
   check_solve_params(&prm->solve);
 }
@@ -1962,8 +1963,11 @@ constexpr double kAlphaMin = 1.0 / 1024.0;
 // the one of the accepted state), unless ||dv||_M <= full_below; *alpha
 // receives a, or 0 (v unchanged) when no step length qualifies.  Returns
 // whether the linear solve converged.
+// reuse: 0 full set-up, 1 re-set-up on the kept coarse grids when there are
+// some, 2 keep the preconditioner of the last set-up made here when it has
+// the same parameters and is not stale (else as 1)
 bool newton_iteration(hfsi_ctx* c, double* v, double load, const hfsi_amg_params& amg, const hfsi_solve_params& sp,
-                      bool reuse, hfsi_newton_info* info, double* alpha = nullptr, double full_below = -1.0) {
+                      int reuse, hfsi_newton_info* info, double* alpha = nullptr, double full_below = -1.0) {
   const long N = 4L * c->n;
   hipStream_t s = c->stream;
   c->kdv.ensure(N);
@@ -1979,15 +1983,33 @@ bool newton_iteration(hfsi_ctx* c, double* v, double load, const hfsi_amg_params
   const double rnorm = hfsi::read_scalar(c, c->scal.p + 6);
   if (!std::isfinite(rnorm)) fail(HFSI_E_NAN, "newton_step: non-finite residual");
   hfsi_amg_info mi{sizeof(hfsi_amg_info)};
-  reuse = reuse && c->H.reusable;
-  if (reuse) hfsi::amg_resetup_level0(c, amg, &mi);
-  else hfsi::amg_setup_level0(c, amg, &mi);
+  const bool kept = reuse == 2 && c->keep_valid && !c->keep_stale && hfsi::same_amg_params(c->keep_prm, amg);
+  const bool regrid = !kept && reuse >= 1 && c->H.reusable;
+  if (kept) {
+    mi.levels = c->keep_levels;
+    mi.seconds = 0.0;
+  } else {
+    if (regrid) hfsi::amg_resetup_level0(c, amg, &mi);
+    else hfsi::amg_setup_level0(c, amg, &mi);
+    c->keep_valid = true;
+    c->keep_stale = false;
+    c->keep_prm = amg;
+    c->keep_levels = mi.levels;
+    c->keep_rate0 = 0.0;
+  }
   // b = -R, dv = 0
   k_negate<<<div_up(N, 256), 256, 0, s>>>(N, c->ktmp.p, c->ktmp.p);
   HIP_LAUNCH_CHECK();
   HIP_CHECK(hipMemsetAsync(c->kdv.p, 0, sizeof(double) * N, s));
   hfsi_solve_info si{sizeof(hfsi_solve_info)};
   hfsi::krylov_solve(c, c->ktmp.p, c->kdv.p, sp, &si);
+  // the kept preconditioner's health: the mean log10 reduction per
+  // iteration, against that of the first solve after its set-up
+  if (si.iterations > 0) {
+    const double rate = std::log10(std::max(si.rel_residual, 1e-300)) / si.iterations;
+    if (!kept) c->keep_rate0 = rate;
+    else if (!si.converged || (c->keep_rate0 < 0.0 && rate > 0.5 * c->keep_rate0)) c->keep_stale = true;
+  }
   const double dvm = hfsi::mass_norm(c, c->kdv.p);
   // a correction that meets the stopping rule (||dv||_M <= full_below) is
   // taken whole: the residual is then at its rounding floor
@@ -2037,7 +2059,7 @@ bool newton_iteration(hfsi_ctx* c, double* v, double load, const hfsi_amg_params
     info->t_solve = si.seconds;
     info->t_total = ms * 1e-3;
     info->amg_levels = mi.levels;
-    info->amg_reused = reuse ? 1 : 0;
+    info->amg_reused = kept ? 2 : (regrid ? 1 : 0);
   }
   return si.converged != 0;
 }
@@ -2051,7 +2073,9 @@ extern "C" hfsi_status hfsi_newton_step(hfsi_ctx* c, double* v, double load, con
   if (!v) fail(HFSI_E_ARG, "newton_step: null state");
   check_newton_params(prm);
   if (info && info->struct_size != sizeof(hfsi_newton_info)) fail(HFSI_E_ARG, "newton info: struct_size mismatch");
-  if (!newton_iteration(c, v, load, prm->amg, prm->solve, prm->amg_reuse != 0, info)) return HFSI_NOT_CONVERGED;
+  if (!newton_iteration(c, v, load, prm->amg, prm->solve, prm->amg_reuse == 3 ? 2 : (prm->amg_reuse != 0 ? 1 : 0),
+                        info))
+    return HFSI_NOT_CONVERGED;
   HFSI_ABI_END(c)
 }
 
@@ -2063,7 +2087,8 @@ extern "C" hfsi_status hfsi_newton_solve(hfsi_ctx* c, double* v, double load, co
   if (!prm || prm->struct_size != sizeof(hfsi_newton_solve_params))
     fail(HFSI_E_ARG, "newton solve params: struct_size mismatch");
   check_newton_params(&prm->step);
-  if (prm->step.amg_reuse < 0 || prm->step.amg_reuse > 2) fail(HFSI_E_ARG, "newton solve params: amg_reuse 0, 1 or 2");
+  if (prm->step.amg_reuse < 0 || prm->step.amg_reuse > 3)
+    fail(HFSI_E_ARG, "newton solve params: amg_reuse 0, 1, 2 or 3");
   if (!(prm->eps2 > 0.0) || prm->max_newton < 1 || prm->adaptive < 0 || prm->adaptive > 1 ||
       !(prm->eps1_min > 0.0) || !(prm->eps1_max >= prm->eps1_min) || !(prm->eps1_max < 1.0))
     fail(HFSI_E_ARG, "newton solve params: need eps2 > 0, max_newton >= 1, 0 < eps1_min <= eps1_max < 1");
@@ -2093,8 +2118,10 @@ extern "C" hfsi_status hfsi_newton_solve(hfsi_ctx* c, double* v, double load, co
     }
     hfsi_newton_info ni{sizeof(hfsi_newton_info)};
     // amg_reuse: 1 keeps the first iteration's coarse grids, 2 also those of
-    // an earlier call on this mesh (e.g. the previous time step)
-    const bool reuse = prm->step.amg_reuse == 2 || (k > 0 && prm->step.amg_reuse == 1);
+    // an earlier call on this mesh (e.g. the previous time step), 3 keeps
+    // the whole preconditioner while it stays usable
+    const int reuse = prm->step.amg_reuse == 3 ? 2
+                      : (prm->step.amg_reuse == 2 || (k > 0 && prm->step.amg_reuse == 1)) ? 1 : 0;
     double alpha = 1.0;
     // the reference of the relative rule: the caller's, else this call's
     // first correction

@@ -832,6 +832,7 @@ void vanka_free(hfsi_ctx* c) {
 void vanka_invalidate(hfsi_ctx* c) {
   if (c->vanka_impl) reinterpret_cast<Coupled*>(c->vanka_impl)->ready = false;
   c->precond_kind = 0;
+  c->keep_valid = false;
 }
 
 void vanka_setup(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {

@@ -152,7 +152,9 @@ def solve_params(tol=1e-8, restart=50, max_iter=500, method=0, precond_form=0):
 
 
 def newton_params(amg=None, solve=None, amg_reuse=0):
-    """amg_reuse=1: re-set-up on the previous coarse grids when available."""
+    """amg_reuse=1: re-set-up on the previous coarse grids when available;
+    3: keep the whole preconditioner of the last set-up while it stays
+    usable (see hfsi_newton_params)."""
     return NewtonParams(C.sizeof(NewtonParams), amg or amg_params(), solve or solve_params(), amg_reuse)
 
 
@@ -229,7 +231,7 @@ def load():
         "hfsi_mlp_samples": [vp, i64, i64, C.POINTER(i64), vp, vp, vp, vp],
         "hfsi_mlp_train": [vp, C.POINTER(TrainParams), vp, i64, C.POINTER(TrainInfo)],
         "hfsi_amg_convergence_factor": [vp, i32, C.c_uint64, C.POINTER(dbl)],
-        "hfsi_set_fluid": [vp, dbl, dbl, dbl],
+        "hfsi_set_fluid": [vp, dbl, dbl, dbl, i32],
         "hfsi_set_fluid_fields": [vp, vp, vp, vp],
         "hfsi_set_mesh_laplace": [vp],
         "hfsi_fluid_interface_force": [vp, vp, dbl, i32, vp, vp],
@@ -336,9 +338,10 @@ class Context:
     def newmark_update(self, v_new, v_prev, vel, acc):
         self._check(self.lib.hfsi_newmark_update(self.h, _ptr(v_new), _ptr(v_prev), _ptr(vel), _ptr(acc)))
 
-    def set_fluid(self, rho, mu, dt):
-        """Switch to the fluid sub-problem (after set_mesh)."""
-        self._check(self.lib.hfsi_set_fluid(self.h, rho, mu, dt))
+    def set_fluid(self, rho, mu, dt, oseen=0):
+        """Switch to the fluid sub-problem (after set_mesh); oseen=1: the
+        Oseen step (convective velocity u_old - w)."""
+        self._check(self.lib.hfsi_set_fluid(self.h, rho, mu, dt, oseen))
 
     def set_fluid_fields(self, dmesh=None, u_old=None, w=None):
         """Device [n,3] mesh displacement, previous velocity, mesh velocity."""
@@ -568,7 +571,8 @@ def fsi_time_step(fluid, mesh, solid, iface_f, iface_s, vf, df, vs, vel, acc, in
     return info, code
 
 
-def fsi_contexts(model, rho_f=1.0, mu=0.0035, dt=0.125, rho_s=1.2, p_in=1.332, beta=0.625, gamma=1.0, device=0):
+def fsi_contexts(model, rho_f=1.0, mu=0.0035, dt=0.125, rho_s=1.2, p_in=1.332, beta=0.625, gamma=1.0, device=0,
+                 oseen=0):
     """The three contexts of a partitioned FSI model (an object with the
     fields of synth.FsiModel): the fluid (velocity fixed on the interface,
     inlet traction (0, 0, p_in) at load factor 1), the mesh Laplacian on the
@@ -582,7 +586,7 @@ def fsi_contexts(model, rho_f=1.0, mu=0.0035, dt=0.125, rho_s=1.2, p_in=1.332, b
     fluid.set_materials(dummy)
     tr = np.tile(np.array([0.0, 0.0, p_in]), (len(model.inlet_tris), 1))
     fluid.set_bc(model.fluid_dir, model.inlet_tris, tr)
-    fluid.set_fluid(rho_f, mu, dt)
+    fluid.set_fluid(rho_f, mu, dt, oseen)
     mesh = Context(device)
     mesh.set_mesh(model.fluid_X, model.fluid_tets, mat0)
     mesh.set_materials(dummy)

@@ -18,4 +18,6 @@ from .meshes import (  # noqa: F401
     config_problem,
     FsiModel,
     fsi_duct,
+    fsi_tube,
+    lumen_mesh,
 )

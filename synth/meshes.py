@@ -323,6 +323,7 @@ class FsiModel:
     iface_f: np.ndarray
     iface_s: np.ndarray
     fluid_lattice: np.ndarray
+    inflow: np.ndarray | None = None   # f64 [nf,3] prescribed inlet velocity (Dirichlet), or None
 
     @property
     def nf(self):
@@ -404,3 +405,93 @@ def fsi_duct(a=3, t=2, n_z=36, half_width=1.43, wall=0.39, length=18.0, c10=3.0,
                     lats.astype(np.int32), fib, name=f"duct_wall{a}x{t}x{n_z}" + ("_artery" if artery else ""))
     return FsiModel(X[gf], Tf, fdir, inlet.astype(np.int32), fb, solid, iface_f, iface_s,
                     latf.astype(np.int32))
+
+
+def lumen_mesh(n_theta=64, n_r=16, n_z=128, radius=0.71, length=5.0):
+    """Structured mesh of the tube's lumen (the disk of the given radius
+    times [0, length]): n_r rings of n_theta nodes around an axis node per
+    level, the same circumferential and axial positions as the tube's inner
+    surface.  Between ring k >= 1 and ring k + 1 the (theta, r, z) lattice
+    hexahedra are Kuhn-split as the tube's; the wedges around the axis are
+    split into three tetrahedra whose quad-face diagonals match: on the
+    outer face the Kuhn diagonal (theta_j, z_c)-(theta_j+1, z_c+1), on the
+    radial faces the diagonal from the axis node at z_c to the ring node at
+    z_c+1.  Node index: level c holds the axis node c * (1 + n_theta * n_r)
+    and then ring k, angle j at c * (1 + n_theta n_r) + 1 + (k - 1) n_theta + j.
+    Returns X, tets (positively oriented), and the lattice (j, k, c) of each
+    node (j = 0 on the axis)."""
+    per = 1 + n_theta * n_r
+    c, k, j = np.meshgrid(np.arange(n_z + 1), np.arange(1, n_r + 1), np.arange(n_theta), indexing="ij")
+    n = per * (n_z + 1)
+    X = np.zeros((n, 3))
+    lat = np.zeros((n, 3), np.int32)
+    axis = np.arange(n_z + 1) * per
+    X[axis, 2] = length * np.arange(n_z + 1) / n_z
+    lat[axis, 2] = np.arange(n_z + 1)
+    ring = (c * per + 1 + (k - 1) * n_theta + j).ravel()
+    th = 2.0 * math.pi * j.ravel() / n_theta
+    r = radius * k.ravel() / n_r
+    X[ring] = np.stack([r * np.cos(th), r * np.sin(th), length * c.ravel() / n_z], axis=1)
+    lat[ring] = np.stack([j.ravel(), k.ravel(), c.ravel()], axis=1)
+
+    def node_id(ia, ib, ic):
+        # (theta, ring, level) with ring >= 1, theta periodic
+        return ic * per + 1 + (ib - 1) * n_theta + (ia % n_theta)
+
+    # rings 1..n_r: hexahedra between ring b and b + 1 (b = 1 .. n_r - 1)
+    tets_h = np.zeros((0, 4), np.int64)
+    if n_r > 1:
+        th_, _ = _lattice_tets((n_theta, n_r - 1, n_z), lambda a, b, cc: node_id(a, b + 1, cc))
+        tets_h = th_
+    # wedges around the axis: (C0, A0, B0, B1), (C0, A0, A1, B1), (C0, A1, B1, C1)
+    cc, aa = np.meshgrid(np.arange(n_z), np.arange(n_theta), indexing="ij")
+    cc, aa = cc.ravel(), aa.ravel()
+    C0, C1 = cc * per, (cc + 1) * per
+    A0, A1 = node_id(aa, 1, cc), node_id(aa, 1, cc + 1)
+    B0, B1 = node_id(aa + 1, 1, cc), node_id(aa + 1, 1, cc + 1)
+    tets_w = np.concatenate([np.stack([C0, A0, B0, B1], 1), np.stack([C0, A0, A1, B1], 1),
+                             np.stack([C0, A1, B1, C1], 1)])
+    tets = np.concatenate([tets_w, tets_h]).astype(np.int64)
+    tets = _orient(X, tets)
+    return X, tets.astype(np.int32), lat
+
+
+def fsi_tube(n_theta=64, n_r=16, n_media=5, n_adv=3, n_z=128, r_in=0.71, length=5.0, v_peak=0.3, kappa=1e5):
+    """The artery tube with its lumen as a partitioned FSI model: the
+    structure is the two-layer tube (both ends clamped, no traction), the
+    fluid the lumen mesh whose outer ring is the tube's inner surface; a
+    Poiseuille inflow u = v_peak (1 - r^2 / r_in^2) e_z is prescribed on the
+    inlet z = 0, the outlet z = length is free (do nothing).  Lengths in mm,
+    velocities in mm/ms (v_peak = 0.3 is 30 cm/s)."""
+    tm = tube_mesh(n_theta, n_media, n_adv, n_z, r_in=r_in, length=length)
+    Xf, Tf, latf = lumen_mesh(n_theta, n_r, n_z, r_in, length)
+    nf = len(Xf)
+    # interface: fluid ring n_r <-> tube radial index 0, same (theta, level)
+    jj, cc = np.meshgrid(np.arange(n_theta), np.arange(n_z + 1), indexing="ij")
+    jj, cc = jj.ravel(), cc.ravel()
+    per = 1 + n_theta * n_r
+    iface_f = (cc * per + 1 + (n_r - 1) * n_theta + jj).astype(np.int64)
+    n_rad = n_media + n_adv + 1
+    iface_s = (jj + n_theta * (0 + n_rad * cc)).astype(np.int64)
+    order = np.argsort(iface_f)
+    iface_f, iface_s = iface_f[order], iface_s[order]
+    assert np.abs(Xf[iface_f] - tm["X"][iface_s]).max() < 1e-12
+    fdir = np.zeros((nf, 4), np.uint8)
+    fdir[iface_f, 0:3] = 1
+    inlet_nodes = np.flatnonzero(latf[:, 2] == 0)
+    fdir[inlet_nodes, 0:3] = 1
+    inflow = np.zeros((nf, 3))
+    rr2 = Xf[inlet_nodes, 0] ** 2 + Xf[inlet_nodes, 1] ** 2
+    inflow[inlet_nodes, 2] = v_peak * np.maximum(0.0, 1.0 - rr2 / (r_in * r_in))
+    inflow[iface_f] = 0.0
+    bf = boundary_faces(Tf)
+    fb = np.zeros(nf, bool)
+    fb[np.unique(bf)] = True
+    lat_s = tm["lattice"]
+    ns = len(lat_s)
+    dm = np.zeros((ns, 4), np.uint8)
+    dm[(lat_s[:, 2] == 0) | (lat_s[:, 2] == n_z), 0:3] = 1
+    mats = [artery_layer(kappa=kappa, **ARTERY_MEDIA), artery_layer(kappa=kappa, **ARTERY_ADVENTITIA)]
+    solid = Problem(tm["X"], tm["tets"], tm["mat_id"], mats, dm, np.zeros((0, 3), np.int32), np.zeros((0, 3)),
+                    lat_s, tm["fibres"], name=f"tube{n_theta}x{n_media + n_adv}x{n_z}")
+    return FsiModel(Xf, Tf, fdir, np.zeros((0, 3), np.int32), fb, solid, iface_f, iface_s, latf, inflow)

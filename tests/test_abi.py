@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(hfsi.LIB_PATH)
     missing = [n for n in _declared() if not hasattr(lib, n)]
     assert not missing, missing
-    assert lib.hfsi_abi_version() == 10
+    assert lib.hfsi_abi_version() == 11
 
 
 def test_binding_has_no_cpu_fallback():

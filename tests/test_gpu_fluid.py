@@ -18,6 +18,9 @@ duct models; nothing it uses comes from the GPU.  Compared:
   the two-layer artery wall: the DN iteration counts within two of the
   oracle's and the states to 1e-4 of their size (both stop at
   |r| / sqrt(n) < 1e-8, which the DN map's conditioning amplifies);
+* three steps of the small artery tube with its round lumen and the Oseen
+  fluid: equal DN counts (within one) and states to 1e-4, with the default
+  sub-solvers and with the coupled fluid AMG and kept preconditioners;
 * one step of the 3 x 2 x 12 duct checked on the host: the kinematic
   condition on the interface and the interface gap below the tolerance.
 """
@@ -63,21 +66,26 @@ def _blocks_to_csr(out, n):
     return M
 
 
-@pytest.mark.parametrize("shape", [(2, 1, 4), (3, 2, 12)])
-def test_fluid_assembly_matches_oracle(lib, shape):
+@pytest.mark.parametrize("case", ["duct_2x1x4", "duct_3x2x12", "tube_oseen"])
+def test_fluid_assembly_matches_oracle(lib, case):
     import torch
-    model = _model(*shape, length=2.0 * shape[2] / 4)
-    print(f"[fluid assembly] duct {shape} nf={model.nf} m={len(model.fluid_tets)}", flush=True)
+    oseen = case == "tube_oseen"
+    if oseen:
+        model = synth.fsi_tube(8, 3, 2, 1, 6, length=1.5)
+    else:
+        shape = (2, 1, 4) if case == "duct_2x1x4" else (3, 2, 12)
+        model = _model(*shape, length=2.0 * shape[2] / 4)
+    print(f"[fluid assembly] {case} nf={model.nf} m={len(model.fluid_tets)}", flush=True)
     dmesh, v, uo, w = _random_fields(model, 3)
     g_in = np.array([0.0, 0.0, 0.7])
-    fl, me, so = lib.fsi_contexts(model, p_in=0.7, **PRM)
+    fl, me, so = lib.fsi_contexts(model, p_in=0.7, oseen=int(oseen), **PRM)
     fl.set_fluid_fields(torch_dev(dmesh), torch_dev(uo), torch_dev(w))
     vt = torch_dev(v)
     R = torch.zeros_like(vt)
     view, _ = fl.assemble_residual_tangent(vt, 1.0, R)
     out = fl.export_tangent(view)
     d = fluid.FluidDiscretization(model.fluid_X, model.fluid_tets, model.fluid_dir, model.inlet_tris,
-                                  fluid.FluidParams(rho=PRM["rho_f"], mu=PRM["mu"], dt=PRM["dt"]))
+                                  fluid.FluidParams(rho=PRM["rho_f"], mu=PRM["mu"], dt=PRM["dt"], oseen=oseen))
     Ro, val = d.assemble(v.ravel(), dmesh, uo, w, g_in)
     Ro, val = d.apply_dirichlet(Ro, val)
     K = d.csr(val)
@@ -211,6 +219,52 @@ def test_fsi_artery_steps_match_oracle(lib):
         assert abs(info.dn_iterations - k) <= 2
     assert np.abs(vs.reshape(-1, 4)[:, 0:3] - st.vs[:, 0:3]).max() <= 1e-4 * np.abs(st.vs[:, 0:3]).max()
     assert np.abs(vf.reshape(-1, 4)[:, 0:3] - st.vf[:, 0:3]).max() <= 1e-4 * np.abs(st.vf[:, 0:3]).max()
+
+
+def _tube_solvers(lib, which):
+    if which == "default":
+        return lib.fsi_params(omega0=0.05)
+    # the coupled (u,p) AMG with the additive Vanka smoother for the fluid,
+    # and every sub-problem keeping its whole preconditioner across Newton
+    # iterations, DN iterations and steps
+    sv = lib.solve_params(tol=1e-10, restart=100, max_iter=1000)
+    return lib.fsi_params(
+        omega0=0.05, adaptive=1,
+        fluid_step=lib.newton_params(amg=lib.amg_params(coupled=2, vanka_steps=1, interp_kind=0), solve=sv,
+                                     amg_reuse=3),
+        solid_step=lib.newton_params(amg=lib.amg_params(smoother=1, precision=1), solve=sv, amg_reuse=3),
+        mesh_step=lib.newton_params(solve=lib.solve_params(tol=1e-12, restart=100, max_iter=1000), amg_reuse=3))
+
+
+@pytest.mark.parametrize("solvers", ["default", "coupled_kept"])
+def test_fsi_tube_oseen_steps_match_oracle(lib, solvers):
+    """The partitioned FSI sequence's workload in small: the two-layer artery
+    tube and its round lumen, the Oseen fluid with a Poiseuille inflow
+    (peak 0.3 mm/ms), dt = 1 ms; three steps against the oracle (equal DN
+    counts, states to 1e-4 of their size), with the default sub-solvers and
+    with the coupled fluid AMG and kept preconditioners."""
+    import torch
+    model = synth.fsi_tube(8, 2, 2, 1, 4, length=1.0)
+    print(f"[fsi tube {solvers}] nf={model.nf} ns={model.solid.n_nodes} iface={len(model.iface_f)}", flush=True)
+    prm = dict(rho_f=1.0, mu=0.0035, dt=1.0, rho_s=1.2)
+    fl, me, so = lib.fsi_contexts(model, p_in=0.0, oseen=1, **prm)
+    nf, ns = model.nf, model.solid.n_nodes
+    z = lambda k: torch.zeros(k, dtype=torch.float64, device="cuda")  # noqa: E731
+    vf0 = np.zeros((nf, 4))
+    vf0[:, 0:3] = model.inflow
+    vf, df, vs, vel, acc = torch_dev(vf0.ravel()), z(3 * nf), z(4 * ns), z(3 * ns), z(3 * ns)
+    st = fsi.FsiState(model, fsi.FsiParams(fluid=fluid.FluidParams(rho=1.0, mu=0.0035, dt=1.0, oseen=True),
+                                           rho_s=1.2, p_in=0.0, omega0=0.05))
+    for step in range(3):
+        info, code = lib.fsi_time_step(fl, me, so, model.iface_f, model.iface_s, vf, df, vs, vel, acc, 1.0,
+                                       _tube_solvers(lib, solvers))
+        k, _, _ = st.time_step()
+        print(f"  step {step + 1}: DN iterations gpu {info.dn_iterations} oracle {k}", flush=True)
+        assert code == 0 and info.converged and abs(info.dn_iterations - k) <= 1
+    vs_, vf_ = vs.cpu().numpy().reshape(-1, 4), vf.cpu().numpy().reshape(-1, 4)
+    assert np.abs(vs_[:, 0:3] - st.vs[:, 0:3]).max() <= 1e-4 * np.abs(st.vs[:, 0:3]).max()
+    assert np.abs(vf_ - st.vf).max() <= 1e-4 * np.abs(st.vf).max()
+    assert np.array_equal(vf_[model.inflow[:, 2] > 0, 0:3], model.inflow[model.inflow[:, 2] > 0])
 
 
 def test_fsi_step_larger_duct_host_checks(lib):

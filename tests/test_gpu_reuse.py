@@ -227,3 +227,50 @@ def test_resetup_keeps_learned_interpolation(lib):
     Aco = amg.on_pattern(amg.galerkin(A, P1), Ac0)
     assert np.array_equal(Ac.indptr, Aco.indptr) and np.array_equal(Ac.indices, Aco.indices)
     assert np.abs(Ac.data - Aco.data).max() <= 1e-12 * np.abs(Aco.data).max()
+
+
+def test_newton_run_with_kept_preconditioner(lib):
+    """amg_reuse = 3: the whole preconditioner of the first set-up serves
+    every later Newton iteration of the 8^3 cube load run (FGMRES applies
+    each new tangent exactly), and the run still reaches the oracle's
+    converged states.  A change of AMG parameters, a set-up through the
+    public entry point and a Krylov solve that fails with the kept
+    preconditioner each end the keeping."""
+    import torch
+    prob = synth.cube_problem(8)
+    print("[newton keep] cube8 5 increments", flush=True)
+    ctx = context_for(lib, prob)
+    v = torch.zeros(4 * prob.n_nodes, dtype=torch.float64, device="cuda")
+    keep = lib.newton_params(amg_reuse=3)
+    reused = []
+    for k in range(1, 6):
+        n0 = None
+        for it in range(25):
+            info, code = ctx.newton_step(v, k / 5.0, keep)
+            assert code == 0
+            reused.append(info.amg_reused)
+            n0 = info.dv_mass_norm if n0 is None else n0
+            if info.dv_mass_norm <= 1e-10 * n0:
+                break
+    print(f"  amg_reused {reused}", flush=True)
+    assert reused[0] == 0 and reused.count(2) >= len(reused) // 2
+    disc = fe.Discretization(prob)
+    vo = newton.load_run(disc, 5, newton.NewtonParams())
+    assert np.linalg.norm(v.cpu().numpy() - vo) <= 1e-9 * np.linalg.norm(vo)
+    # other AMG parameters: a new set-up, then kept again
+    other = lib.newton_params(amg=lib.amg_params(smoother=0), amg_reuse=3)
+    assert ctx.newton_step(v, 1.0, other)[0].amg_reused in (0, 1)
+    assert ctx.newton_step(v, 1.0, other)[0].amg_reused == 2
+    # a public set-up ends it
+    R = torch.zeros_like(v)
+    ctx.assemble_residual_tangent(v, 1.0, R)
+    ctx.amg_setup(lib.amg_params(smoother=0))
+    assert ctx.newton_step(v, 1.0, other)[0].amg_reused in (0, 1)
+    # a solve that fails with the kept preconditioner ends it
+    failing = lib.newton_params(amg=lib.amg_params(smoother=0), amg_reuse=3,
+                                solve=lib.solve_params(tol=1e-14, restart=2, max_iter=2))
+    v1 = v.clone()
+    v1[0::4] += 1e-3
+    info, code = ctx.newton_step(v1, 1.0, failing)
+    assert info.amg_reused == 2 and code == 1
+    assert ctx.newton_step(v1, 1.0, other)[0].amg_reused == 1

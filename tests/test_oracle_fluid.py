@@ -2,9 +2,11 @@
 eq. weakns, eq. stabweakfluid) and of the harmonic extension (eq. harext).
 
 * Jacobian: central differences of the residual with tau held fixed, with
-  and without the stabilisation (a dropped derivative of the convective
-  velocity in the SUPG test function, or a transposed velocity gradient,
-  fails);
+  and without the stabilisation, and in the Oseen form (a dropped
+  derivative of the convective velocity in the SUPG test function, or a
+  transposed velocity gradient, fails); the Oseen step is linear: one
+  Newton correction leaves a zero residual, and with u_old = u it is the
+  Navier-Stokes residual;
 * the Galerkin mass and convection terms against the closed form of the P1
   mass matrix, sum_b M_ab (rho/dt (u_b - u_old_b) + rho Gu c_b), and the
   SUPG and PSPG terms against the same closed form with the nodal strong
@@ -39,13 +41,13 @@ def _batch(rng, m=6, scale=0.3):
     return x, ue, pe, uo, we
 
 
-@pytest.mark.parametrize("stabilise", [True, False])
-def test_jacobian_matches_differences(stabilise):
+@pytest.mark.parametrize("stabilise,oseen", [(True, False), (False, False), (True, True)])
+def test_jacobian_matches_differences(stabilise, oseen):
     rng = np.random.default_rng(1)
-    prm = fluid.FluidParams(rho=1.3, mu=0.07, dt=0.2, stabilise=stabilise)
+    prm = fluid.FluidParams(rho=1.3, mu=0.07, dt=0.2, stabilise=stabilise, oseen=oseen)
     x, ue, pe, uo, we = _batch(rng)
     G, V, h = fluid.geometry(x)
-    tau = fluid.tau_of((ue - we).mean(axis=1), h, prm)
+    tau = fluid.tau_of(((uo if oseen else ue) - we).mean(axis=1), h, prm)
     _, K = fluid.element_kernel(x, ue, pe, uo, we, prm, tau=tau)
     v = np.concatenate([ue, pe[:, :, None]], axis=2).reshape(len(x), 16)
     eps = 1e-6
@@ -235,3 +237,29 @@ def test_harmonic_extension_is_exact_for_affine_fields(duct):
     got = fluid.harmonic_extension(L, fixed, exact[fixed])
     assert np.abs(got - exact).max() <= 1e-12 * np.abs(exact).max()
     assert np.abs(L @ np.ones(d.n)).max() <= 1e-13 * abs(L).max()
+
+
+def test_oseen_is_linear_and_agrees_with_navier_stokes_at_u_old(duct):
+    model, d = duct
+    rng = np.random.default_rng(12)
+    n = d.n
+    po = fluid.FluidParams(rho=1.0, mu=0.05, dt=0.125, oseen=True)
+    do = fluid.FluidDiscretization(model.fluid_X, model.fluid_tets, model.fluid_dir, model.inlet_tris, po)
+    v = rng.normal(size=(n, 4)) * 0.1
+    uo = rng.normal(size=(n, 3)) * 0.1
+    w = rng.normal(size=(n, 3)) * 0.05
+    dm = np.zeros((n, 3))
+    g = np.array([0.0, 0.0, 0.3])
+    R, val = do.assemble(v.ravel(), dm, uo, w, g)
+    R, val = do.apply_dirichlet(R, val)
+    import scipy.sparse.linalg as spl
+    dv = spl.spsolve(do.csr(val).tocsc(), -R)
+    R1, _ = do.assemble(v.ravel() + dv, dm, uo, w, g, want_tangent=False)
+    R1 = R1.reshape(n, 4)
+    R1[model.fluid_dir.astype(bool)] = 0.0
+    assert np.abs(R1).max() <= 1e-11 * np.abs(R).max()
+    # at u_old = u the Oseen residual is the Navier-Stokes one
+    vu = v.copy()
+    Ro, _ = do.assemble(vu.ravel(), dm, vu[:, 0:3], w, g, want_tangent=False)
+    Rn, _ = d.assemble(vu.ravel(), dm, vu[:, 0:3], w, g, want_tangent=False)
+    assert np.abs(Ro - Rn).max() <= 1e-14 * np.abs(Rn).max()
