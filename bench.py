@@ -364,7 +364,7 @@ def fsi_leg(shape, steps, torch, hfsi, variants=("new_hierarchies", "grids_kept"
             rec.append({"seconds": time.perf_counter() - t0, "dn_iterations": info.dn_iterations,
                         "fluid_newton": info.fluid_newton, "structure_newton": info.solid_newton,
                         "krylov": info.krylov})
-            print(f"[bench] FSI tube, {label}: step {k + 1}: {rec[-1]['seconds']:.2f} s, "
+            print(f"[bench] FSI duct with the artery wall: step {k + 1}: {rec[-1]['seconds']:.2f} s, "
                   f"{info.dn_iterations} DN iterations", file=sys.stderr, flush=True)
         out["artery_wall_grids_kept_adaptive"] = {
             "workload": f"square duct {a}x3x{nz}, two-layer artery wall: {nfa} fluid nodes, {nsa} structure nodes",
