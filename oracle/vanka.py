@@ -47,6 +47,10 @@ order of the patches.  The readings followed here:
   about a dozen patches, and the sum diverges at the relaxation the paper
   uses.  No order is involved, so one sweep is a single parallel step on a
   GPU.
+* the fp32 option (inverse_f32, not in the paper: a storage choice of the
+  local solves): each local system's exact inverse, rounded entry by entry
+  to the nearest float32, is applied to the fp64 residual in fp64
+  arithmetic; blocks, transfers and the coarsest solve stay fp64.
 
 Every level's unknowns are ordered [u; p]: the nu displacement unknowns of
 the displacement hierarchy, then the np pressure unknowns.
@@ -195,6 +199,7 @@ class VankaParams:
     omega: float = 0.78             # relaxation (eq. vankasmooth): 0.78 Mooney-Rivlin, 0.86 artery
     steps: int = 6                  # sweeps before and after the coarse correction
     additive: bool = False          # the additive variant instead of the multiplicative sweep
+    inverse_f32: bool = False       # local solves by the fp32-rounded inverse of each local system
     amg: amg.AmgParams = dataclasses.field(
         default_factory=lambda: amg.AmgParams(smoother="l1jacobi", interp="ext+i"))
 
@@ -211,6 +216,7 @@ class CoupledLevel:
     order: np.ndarray | None = None
     colour: np.ndarray | None = None
     lu: list | None = None
+    inv32: list | None = None      # fp32-rounded local inverses (inverse_f32)
 
     @property
     def nu(self):
@@ -229,7 +235,7 @@ class CoupledHierarchy:
         self.levels, self.lu, self.Hu, self.Hp = levels, lu, Hu, Hp
 
 
-def _vanka_data(L):
+def _vanka_data(L, inverse_f32=False):
     L.patches = patches(L.Kpu)
     L.colour = greedy_colours(conflict_graph(L.Kuu, L.Kup, L.Kpu, L.Kpp))
     L.order = sweep_order(L.colour)
@@ -240,6 +246,14 @@ def _vanka_data(L):
         idx = np.concatenate([L.patches[i], [L.nu + i]])
         Ki = K[np.ix_(idx, idx)] if K is not None else Kc[idx][:, idx].toarray()
         L.lu.append(scipy.linalg.lu_factor(Ki))
+    if inverse_f32:
+        L.inv32 = [scipy.linalg.lu_solve(f, np.eye(f[0].shape[0])).astype(np.float32) for f in L.lu]
+
+
+def _local_solve(L, i, r):
+    if L.inv32 is not None:
+        return L.inv32[i].astype(np.float64) @ r
+    return scipy.linalg.lu_solve(L.lu[i], r)
 
 
 def setup(Kuu, Kup, Kpu, Kpp, prm: VankaParams = VankaParams()):
@@ -261,7 +275,7 @@ def setup(Kuu, Kup, Kpu, Kpp, prm: VankaParams = VankaParams()):
         Kpu_c = triple(L.Pp.T.tocsr() if L.Pp is not None else None, L.Kpu, L.Pu)
         levels.append(CoupledLevel(Kuu_c.tocsr(), Kup_c, Kpu_c, Kpp_c))
     for L in levels[:-1]:
-        _vanka_data(L)
+        _vanka_data(L, prm.inverse_f32)
     last = levels[-1]
     if last.nu + last.np_ > prm.amg.max_dense:
         raise RuntimeError("coarsest coupled level too large for the dense solve")
@@ -283,7 +297,7 @@ def vanka_sweep(L, b, x, omega, K=None):
     for i in L.order:
         idx = np.concatenate([L.patches[i], [L.nu + i]])
         r = b[idx] - K[idx] @ x
-        x[idx] += omega * scipy.linalg.lu_solve(L.lu[i], r)
+        x[idx] += omega * _local_solve(L, i, r)
     return x
 
 
@@ -296,7 +310,7 @@ def vanka_sweep_additive(L, b, x, omega, K=None):
     count = np.zeros(x.shape[0], dtype=np.int64)
     for i in range(L.np_):
         idx = np.concatenate([L.patches[i], [L.nu + i]])
-        d[idx] += scipy.linalg.lu_solve(L.lu[i], r[idx])
+        d[idx] += _local_solve(L, i, r[idx])
         count[idx] += 1
     held = count > 0
     x = x.copy()

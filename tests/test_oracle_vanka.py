@@ -21,7 +21,12 @@ multiplicative Vanka smoother", eq. locsys and eq. vankasmooth).
   Jacobi; on the identity system with overlapping patches it is exactly
   x0 + omega (b - x0) (the mean of the overlapping corrections, not their
   sum) and leaves an unknown outside every patch alone; on the cube it is
-  the dense patch-by-patch formula, and its cycle preconditions FGMRES.
+  the dense patch-by-patch formula, and its cycle preconditions FGMRES;
+* the fp32 local inverses: on a single patch the sweep is x0 + omega
+  fl32(K^-1) (b - K x0) with the inverse from a dense inverse rounded to
+  float32 (no rounding, or rounding the correction instead, fails at
+  1e-12); on the cube the cycle stays within 1e-5 of the fp64 cycle and
+  FGMRES takes at most one more iteration.
 """
 import numpy as np
 import pytest
@@ -85,9 +90,9 @@ def _disjoint_system(rng, npr=5, per=3):
     return [sp.csr_matrix(B) for B in (Kuu, Kup, Kpu, Kpp)], nu, npr
 
 
-def _level_of(blocks):
+def _level_of(blocks, inverse_f32=False):
     L = vanka.CoupledLevel(*[B.tocsr() for B in blocks])
-    vanka._vanka_data(L)
+    vanka._vanka_data(L, inverse_f32)
     return L
 
 
@@ -347,3 +352,42 @@ def test_additive_cycle_preconditions_the_solid(cube6):
         assert np.linalg.norm(b - K @ x) <= 1e-8 * np.linalg.norm(b)
         its[additive] = info.iterations
     assert its[True] <= 2 * its[False]
+
+
+def test_fp32_inverse_on_a_single_patch():
+    rng = np.random.default_rng(15)
+    nu = 9
+    M = rng.normal(size=(nu, nu))
+    Kuu = sp.csr_matrix(M @ M.T + nu * np.eye(nu))
+    Kpu = sp.csr_matrix(rng.normal(size=(1, nu)))
+    Kup = sp.csr_matrix(rng.normal(size=(nu, 1)))
+    Kpp = sp.csr_matrix([[-0.4]])
+    L = _level_of([Kuu, Kup, Kpu, Kpp], inverse_f32=True)
+    assert L.inv32[0].dtype == np.float32
+    K = L.K().toarray()
+    b, x0 = rng.normal(size=nu + 1), rng.normal(size=nu + 1)
+    Y = np.linalg.inv(K).astype(np.float32).astype(np.float64)
+    ref = x0 + 0.7 * (Y @ (b - K @ x0))
+    for sweep in (vanka.vanka_sweep, vanka.vanka_sweep_additive):
+        got = sweep(L, b, x0, 0.7)
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    exact = x0 + 0.7 * np.linalg.solve(K, b - K @ x0)
+    assert np.abs(exact - ref).max() > 1e-10 * np.abs(ref).max()   # the rounding is visible
+
+
+def test_fp32_inverse_cycle_close_to_fp64(cube6):
+    prob, d, K, b, blocks, _ = cube6
+    n = prob.n_nodes
+    res = {}
+    for f32 in (False, True):
+        prm = vanka.VankaParams(omega=0.8, steps=2, additive=True, inverse_f32=f32,
+                                amg=amg.AmgParams(smoother="l1jacobi", interp="ext+i", max_coarse=150))
+        CH = vanka.setup(*blocks, prm)
+        r = np.random.default_rng(3).normal(size=4 * n)
+        z = vanka.preconditioner(CH, n, prm)(r)
+        x, info = krylov.fgmres(K, vanka.preconditioner(CH, n, prm), b, m=60, tol=1e-8, maxit=200)
+        assert info.converged
+        res[f32] = (z, info.iterations)
+    z64, z32 = res[False][0], res[True][0]
+    assert 0.0 < np.abs(z32 - z64).max() <= 1e-5 * np.abs(z64).max()
+    assert res[True][1] <= res[False][1] + 1
