@@ -384,7 +384,8 @@ def fsi_tube_leg(shape, steps, torch, hfsi, ref_steps=2):
     with Aitken relaxation to |r|/sqrt(n) < 1e-8.  The fluid is solved with
     the coupled (u,p) AMG and the additive Vanka smoother (one sweep before
     and after the correction, distance-one interpolation), the structure
-    with fp32 Chebyshev V-cycles.  "kept": every sub-problem keeps its whole
+    with Chebyshev V-cycles.  "kept": fp32 patch inverses and fp32 structure
+    cycles, and every sub-problem keeps its whole
     preconditioner across Newton iterations, DN iterations and steps (set up
     anew only when a solve converges at under half the rate of the first
     after its set-up), adaptive inner tolerances; "fp64_new_hierarchies":
@@ -403,9 +404,10 @@ def fsi_tube_leg(shape, steps, torch, hfsi, ref_steps=2):
     sv = hfsi.solve_params(tol=1e-10, restart=100, max_iter=1000)
     msv = hfsi.solve_params(tol=1e-12, restart=100, max_iter=1000)
     fluid_amg = hfsi.amg_params(coupled=2, vanka_steps=1, interp_kind=0)
+    fluid_amg32 = hfsi.amg_params(coupled=2, vanka_steps=1, interp_kind=0, precision=1)
     variants = {
         "kept": (steps, hfsi.fsi_params(
-            fluid_step=hfsi.newton_params(amg=fluid_amg, solve=sv, amg_reuse=3),
+            fluid_step=hfsi.newton_params(amg=fluid_amg32, solve=sv, amg_reuse=3),
             solid_step=hfsi.newton_params(amg=hfsi.amg_params(smoother=1, precision=1), solve=sv, amg_reuse=3),
             mesh_step=hfsi.newton_params(solve=msv, amg_reuse=3), adaptive=1)),
         "fp64_new_hierarchies": (min(ref_steps, steps), hfsi.fsi_params(

@@ -180,7 +180,11 @@ typedef struct {
                                  strength_theta, max_coarse, max_levels, seed,
                                  interp_kind and p_max for both hierarchies;
                                  needs interp = 0 and drop_tol = 0; every
-                                 set-up and re-set-up builds it anew (fp64).
+                                 set-up and re-set-up builds it anew, in
+                                 fp64; precision = 1 rounds the patches'
+                                 inverses to fp32 (the local solves read
+                                 them in fp32 and accumulate in fp64; half
+                                 the bytes of the sweeps' dominant reads).
                                  2 = the same hierarchy with the additive
                                  variant of the Vanka smoother (the paper
                                  mentions an additive form, weights not

@@ -65,7 +65,8 @@ struct VkLevel {
   std::vector<int> hroff;            // host copy
   DevBuf<double> rr;                 // local residuals of one colour
   DevBuf<int64_t> luoff;             // [np] first double of each patch's inverse
-  DevBuf<double> inv;                // local inverses, column-major
+  DevBuf<double> inv;                // local inverses, column-major (fp64 hierarchy)
+  DevBuf<float> inv32;               // the same rounded to fp32 (precision = 1; inv then released)
   std::vector<int> cptr;             // colour ranges of clist
   DevBuf<int> clist;                 // patches in sweep order
   DevBuf<int> colour;                // [np] colour of each patch (export)
@@ -312,11 +313,12 @@ __global__ void k_vk_colour_resid(int t0, int t1, const int* __restrict__ crow, 
 // 64k .. 64k+63 of the local solve of patch q0 + p (whose rows start at
 // roff[q]); its four wavefronts split the columns of the inverse and add
 // their partial sums in LDS.  Dynamic LDS: mmax + 256 doubles.
+template <typename T>
 __global__ void __launch_bounds__(256) k_vk_colour_solve(int q0, int chunks, const int* __restrict__ clist,
                                                          const int* __restrict__ roff, const int* __restrict__ crow,
                                                          const double* __restrict__ rr,
                                                          const int64_t* __restrict__ luoff,
-                                                         const double* __restrict__ inv, double* __restrict__ x,
+                                                         const T* __restrict__ inv, double* __restrict__ x,
                                                          double omega) {
   extern __shared__ double sh[];
   const int q = q0 + blockIdx.x / chunks, a0 = 64 * (blockIdx.x % chunks);
@@ -327,21 +329,21 @@ __global__ void __launch_bounds__(256) k_vk_colour_solve(int q0, int chunks, con
   double* part = sh + m;
   for (int t = tid; t < m; t += 256) r[t] = rr[r0 + t];
   __syncthreads();
-  const double* Y = inv + luoff[i];
+  const T* Y = inv + luoff[i];
   const int a = a0 + lane;
   const int t0 = (w * m) >> 2, t1 = ((w + 1) * m) >> 2;
   double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
   if (a < m) {
     int t = t0;
     for (; t + 4 <= t1; t += 4) {
-      const double y0 = Y[(size_t)t * m + a], y1 = Y[(size_t)(t + 1) * m + a];
-      const double y2 = Y[(size_t)(t + 2) * m + a], y3 = Y[(size_t)(t + 3) * m + a];
+      const double y0 = (double)Y[(size_t)t * m + a], y1 = (double)Y[(size_t)(t + 1) * m + a];
+      const double y2 = (double)Y[(size_t)(t + 2) * m + a], y3 = (double)Y[(size_t)(t + 3) * m + a];
       d0 += y0 * r[t];
       d1 += y1 * r[t + 1];
       d2 += y2 * r[t + 2];
       d3 += y3 * r[t + 3];
     }
-    for (; t < t1; ++t) d0 += Y[(size_t)t * m + a] * r[t];
+    for (; t < t1; ++t) d0 += (double)Y[(size_t)t * m + a] * r[t];
   }
   part[tid] = (d0 + d1) + (d2 + d3);
   __syncthreads();
@@ -355,11 +357,12 @@ __global__ void __launch_bounds__(256) k_vk_colour_solve(int q0, int chunks, con
 // local solve of patch clist[q] with the residual r of the whole level
 // (gathered through crow), and keeps the corrections per entry in dd
 // (x is not touched).  Dynamic LDS: mmax + 256 doubles.
+template <typename T>
 __global__ void __launch_bounds__(256) k_vk_add_solve(int chunks, const int* __restrict__ clist,
                                                       const int* __restrict__ roff, const int* __restrict__ crow,
                                                       const double* __restrict__ r_all,
                                                       const int64_t* __restrict__ luoff,
-                                                      const double* __restrict__ inv, double* __restrict__ dd) {
+                                                      const T* __restrict__ inv, double* __restrict__ dd) {
   extern __shared__ double sh[];
   const int q = blockIdx.x / chunks, a0 = 64 * (blockIdx.x % chunks);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -369,25 +372,32 @@ __global__ void __launch_bounds__(256) k_vk_add_solve(int chunks, const int* __r
   double* part = sh + m;
   for (int t = tid; t < m; t += 256) r[t] = r_all[crow[r0 + t]];
   __syncthreads();
-  const double* Y = inv + luoff[i];
+  const T* Y = inv + luoff[i];
   const int a = a0 + lane;
   const int t0 = (w * m) >> 2, t1 = ((w + 1) * m) >> 2;
   double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
   if (a < m) {
     int t = t0;
     for (; t + 4 <= t1; t += 4) {
-      const double y0 = Y[(size_t)t * m + a], y1 = Y[(size_t)(t + 1) * m + a];
-      const double y2 = Y[(size_t)(t + 2) * m + a], y3 = Y[(size_t)(t + 3) * m + a];
+      const double y0 = (double)Y[(size_t)t * m + a], y1 = (double)Y[(size_t)(t + 1) * m + a];
+      const double y2 = (double)Y[(size_t)(t + 2) * m + a], y3 = (double)Y[(size_t)(t + 3) * m + a];
       d0 += y0 * r[t];
       d1 += y1 * r[t + 1];
       d2 += y2 * r[t + 2];
       d3 += y3 * r[t + 3];
     }
-    for (; t < t1; ++t) d0 += Y[(size_t)t * m + a] * r[t];
+    for (; t < t1; ++t) d0 += (double)Y[(size_t)t * m + a] * r[t];
   }
   part[tid] = (d0 + d1) + (d2 + d3);
   __syncthreads();
   if (w == 0 && a < m) dd[r0 + a] = (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]);
+}
+
+// Round the patch inverses to fp32 (the local solves of a precision-1
+// hierarchy; round to nearest)
+__global__ void k_vk_round_inv(long n, const double* __restrict__ x, float* __restrict__ y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (float)x[i];
 }
 
 // Additive sweep, update: x_j += omega * (mean of the corrections of the
@@ -655,7 +665,7 @@ void colour_patches(const std::vector<int>& gptr, const std::vector<int>& gcol, 
   for (int i = 0; i < n; ++i) order[fill[colour[i]]++] = i;
 }
 
-void vanka_level_data(hfsi_ctx* c, VkLevel& V, int* singular, bool additive) {
+void vanka_level_data(hfsi_ctx* c, VkLevel& V, int* singular, bool additive, bool f32) {
   hipStream_t s = c->stream;
   const int np = V.np;
   // patch sizes and factor offsets
@@ -684,6 +694,13 @@ void vanka_level_data(hfsi_ctx* c, VkLevel& V, int* singular, bool additive) {
     HIP_LAUNCH_CHECK();
     k_vk_invert<<<np, 64, 0, s>>>(V.Kpu.ptr.p, V.luoff.p, lu.p, perm.p, V.inv.p);
     HIP_LAUNCH_CHECK();
+    if (f32) {
+      V.inv32.ensure(tot);
+      k_vk_round_inv<<<div_up(tot, 256), 256, 0, s>>>(tot, V.inv.p, V.inv32.p);
+      HIP_LAUNCH_CHECK();
+    } else {
+      V.inv32.release();
+    }
   }
   // lanes per row of the sweep's residual, from the average row length
   const double avg = (double)(V.Kuu->nnz + V.Kup.nnz + V.Kpu.nnz + V.C->nnz) / (double)(V.nu + V.np);
@@ -743,6 +760,7 @@ void vanka_level_data(hfsi_ctx* c, VkLevel& V, int* singular, bool additive) {
     V.rr.ensure(crow.size());
   }
   HIP_CHECK(hipStreamSynchronize(s));  // the host vectors leave scope
+  if (f32) V.inv.release();            // the sweeps read inv32 only
 }
 
 template <int G>
@@ -755,8 +773,12 @@ void sweep_g(hipStream_t s, VkLevel& V, const double* b, double* x, double omega
     const int t0 = V.hroff[q0], t1 = V.hroff[q1];
     k_vk_colour_resid<G><<<div_up((long)(t1 - t0) * G, 256), 256, 0, s>>>(t0, t1, V.crow.p, V.nu, VK_BLOCKS(V), b, x,
                                                                           V.rr.p);
-    k_vk_colour_solve<<<(q1 - q0) * chunks, 256, lds, s>>>(q0, chunks, V.clist.p, V.roff.p, V.crow.p, V.rr.p,
-                                                           V.luoff.p, V.inv.p, x, omega);
+    if (V.inv32.p)
+      k_vk_colour_solve<float><<<(q1 - q0) * chunks, 256, lds, s>>>(q0, chunks, V.clist.p, V.roff.p, V.crow.p,
+                                                                    V.rr.p, V.luoff.p, V.inv32.p, x, omega);
+    else
+      k_vk_colour_solve<double><<<(q1 - q0) * chunks, 256, lds, s>>>(q0, chunks, V.clist.p, V.roff.p, V.crow.p,
+                                                                     V.rr.p, V.luoff.p, V.inv.p, x, omega);
   }
   HIP_LAUNCH_CHECK();
 }
@@ -768,8 +790,12 @@ void sweep_additive_g(hipStream_t s, VkLevel& V, const double* b, double* x, dou
   const int n = V.nu + V.np;
   k_vk_resid<G><<<div_up((long)n * G, 256), 256, 0, s>>>(V.nu, V.np, VK_BLOCKS(V), b, x, V.r.p);
   const int chunks = div_up(V.mmax, 64);
-  k_vk_add_solve<<<V.np * chunks, 256, sizeof(double) * (V.mmax + 256), s>>>(
-      chunks, V.clist.p, V.roff.p, V.crow.p, V.r.p, V.luoff.p, V.inv.p, V.dd.p);
+  if (V.inv32.p)
+    k_vk_add_solve<float><<<V.np * chunks, 256, sizeof(double) * (V.mmax + 256), s>>>(
+        chunks, V.clist.p, V.roff.p, V.crow.p, V.r.p, V.luoff.p, V.inv32.p, V.dd.p);
+  else
+    k_vk_add_solve<double><<<V.np * chunks, 256, sizeof(double) * (V.mmax + 256), s>>>(
+        chunks, V.clist.p, V.roff.p, V.crow.p, V.r.p, V.luoff.p, V.inv.p, V.dd.p);
   k_vk_add_gather<<<div_up(n, 256), 256, 0, s>>>(n, V.dptr.p, V.dent.p, V.dd.p, x, omega);
   HIP_LAUNCH_CHECK();
 }
@@ -931,7 +957,7 @@ void vanka_setup(hfsi_ctx* c, const hfsi_amg_params& prm, hfsi_amg_info* info) {
     L.x.ensure(n_l);
     L.b.ensure(n_l);
     L.r.ensure(n_l);
-    if (l + 1 < nl) vanka_level_data(c, L, singular.p, V.additive);
+    if (l + 1 < nl) vanka_level_data(c, L, singular.p, V.additive, prm.precision == 1);
   }
   // coarsest: explicit inverse
   VkLevel& Lc = V.L.back();

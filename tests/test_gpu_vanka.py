@@ -17,6 +17,9 @@ same state; nothing it uses comes from the GPU.  Compared:
 * at 24^3 (three levels of patches, 15,625 patches on level 0): blocks and
   colours of level 0 bit-exact with the oracle, and the solve's residual
   checked on the host;
+* with precision = 1 (patch inverses rounded to fp32), both variants: one
+  V-cycle entry by entry to 1e-6 relative of the oracle's cycle with
+  rounded inverses, and FGMRES within one iteration of it;
 * the additive variant (coupled = 2, corrections averaged over the patches
   of each unknown): the same hierarchy blocks, no colours (export 14 is an
   error), one V-cycle entry by entry to 1e-10 relative, the AMG method with
@@ -35,10 +38,10 @@ from oracle import amg, fe, krylov, vanka
 pytestmark = pytest.mark.gpu
 
 
-def _params(lib, omega=0.78, steps=2, max_coarse=150, theta=0.15, seed=12345, additive=False):
+def _params(lib, omega=0.78, steps=2, max_coarse=150, theta=0.15, seed=12345, additive=False, f32=False):
     g = lib.amg_params(coupled=2 if additive else 1, vanka_omega=omega, vanka_steps=steps, max_coarse=max_coarse,
-                       theta=theta, seed=seed, interp_kind=1, p_max=4)
-    o = vanka.VankaParams(omega=omega, steps=steps, additive=additive,
+                       theta=theta, seed=seed, interp_kind=1, p_max=4, precision=1 if f32 else 0)
+    o = vanka.VankaParams(omega=omega, steps=steps, additive=additive, inverse_f32=f32,
                           amg=amg.AmgParams(theta=theta, max_coarse=max_coarse, seed=seed, interp="ext+i", p_max=4,
                                             smoother="l1jacobi"))
     return g, o
@@ -260,3 +263,30 @@ def test_additive_full_size_solve(lib):
     assert code == 0 and si.converged
     assert np.linalg.norm(b - K @ x.cpu().numpy()) <= 1e-8 * np.linalg.norm(b)
     print(f"  levels {info.levels} FGMRES iterations {si.iterations} in {si.seconds:.3f} s", flush=True)
+
+
+@pytest.mark.parametrize("additive", [False, True])
+def test_fp32_inverse_cycle_matches_oracle(lib, additive):
+    """precision = 1: the patch inverses rounded to fp32 on both sides (the
+    GPU's LU inverse and the oracle's may round a few entries to
+    neighbouring floats, hence 1e-6 rather than rounding level)."""
+    import torch
+    prob = _problem(6, "mr")
+    v = synth.random_state(prob, 5, u_scale=0.03, p_scale=0.05).ravel()
+    print(f"[vanka fp32 inverses] additive={additive}", flush=True)
+    g, o = _params(lib, omega=0.8, steps=2, additive=additive, f32=True)
+    ctx, info, R, d, K, b, blocks, CH = _both(lib, prob, v, 0.4, g, o)
+    n = prob.n_nodes
+    r = np.random.default_rng(6).normal(size=4 * n)
+    z = torch.zeros(4 * n, dtype=torch.float64, device="cuda")
+    ctx.apply_preconditioner(torch_dev(r), z)
+    zo = vanka.preconditioner(CH, n, o)(r)
+    zg = z.cpu().numpy()
+    assert np.abs(zg - zo).max() <= 1e-6 * np.abs(zo).max()
+    bt = torch_dev(b)
+    x = torch.zeros_like(bt)
+    si, code = ctx.krylov_amg_solve(bt, x, lib.solve_params(tol=1e-8, restart=50, max_iter=200))
+    _, oi = krylov.fgmres(K, vanka.preconditioner(CH, n, o), b, m=50, tol=1e-8)
+    print(f"  FGMRES gpu {si.iterations} oracle {oi.iterations}", flush=True)
+    assert code == 0 and oi.converged and abs(si.iterations - oi.iterations) <= 1
+    assert np.linalg.norm(b - K @ x.cpu().numpy()) <= 1e-8 * np.linalg.norm(b)
