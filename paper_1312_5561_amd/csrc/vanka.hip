@@ -68,6 +68,10 @@ struct VkLevel {
   DevBuf<double> inv;                // local inverses, column-major (fp64 hierarchy)
   DevBuf<float> inv32;               // the same rounded to fp32 (precision = 1; inv then released)
   std::vector<int> cptr;             // colour ranges of clist
+  // the local solves' blocks: one per 64-row chunk of each patch, in sweep
+  // order (q * 32 + chunk), and the first block of each colour
+  DevBuf<int> work;
+  std::vector<int> hwptr;
   DevBuf<int> clist;                 // patches in sweep order
   DevBuf<int> colour;                // [np] colour of each patch (export)
   DevBuf<double> x, b, r;            // [nu + np]
@@ -309,22 +313,24 @@ __global__ void k_vk_colour_resid(int t0, int t1, const int* __restrict__ crow, 
 }
 
 // Then the local solves (eq. locsys) with the patches' inverses and the
-// relaxed updates (eq. vankasmooth).  Block (p, k) of the launch takes rows
-// 64k .. 64k+63 of the local solve of patch q0 + p (whose rows start at
-// roff[q]); its four wavefronts split the columns of the inverse and add
-// their partial sums in LDS.  Dynamic LDS: mmax + 256 doubles.
+// relaxed updates (eq. vankasmooth).  A block takes rows 64k .. 64k+63 of the
+// local solve of the patch at sweep position q (whose rows start at
+// roff[q]), (q, k) from its work entry q * 32 + k; its four wavefronts split
+// the columns of the inverse and add their partial sums in LDS.  Dynamic
+// LDS: mmax + 256 doubles.
 template <typename T>
-__global__ void __launch_bounds__(256) k_vk_colour_solve(int q0, int chunks, const int* __restrict__ clist,
+__global__ void __launch_bounds__(256) k_vk_colour_solve(int w0, const int* __restrict__ work,
+                                                         const int* __restrict__ clist,
                                                          const int* __restrict__ roff, const int* __restrict__ crow,
                                                          const double* __restrict__ rr,
                                                          const int64_t* __restrict__ luoff,
                                                          const T* __restrict__ inv, double* __restrict__ x,
                                                          double omega) {
   extern __shared__ double sh[];
-  const int q = q0 + blockIdx.x / chunks, a0 = 64 * (blockIdx.x % chunks);
+  const int wv = work[w0 + blockIdx.x];
+  const int q = wv >> 5, a0 = 64 * (wv & 31);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i = clist[q], r0 = roff[q], m = roff[q + 1] - r0;
-  if (a0 >= m) return;  // the whole block leaves
   double* r = sh;
   double* part = sh + m;
   for (int t = tid; t < m; t += 256) r[t] = rr[r0 + t];
@@ -353,21 +359,21 @@ __global__ void __launch_bounds__(256) k_vk_colour_solve(int q0, int chunks, con
   }
 }
 
-// Additive sweep, local solves: block (q, k) takes rows 64k .. 64k+63 of the
+// Additive sweep, local solves: the block of work entry q * 32 + k takes rows 64k .. 64k+63 of the
 // local solve of patch clist[q] with the residual r of the whole level
 // (gathered through crow), and keeps the corrections per entry in dd
 // (x is not touched).  Dynamic LDS: mmax + 256 doubles.
 template <typename T>
-__global__ void __launch_bounds__(256) k_vk_add_solve(int chunks, const int* __restrict__ clist,
+__global__ void __launch_bounds__(256) k_vk_add_solve(const int* __restrict__ work, const int* __restrict__ clist,
                                                       const int* __restrict__ roff, const int* __restrict__ crow,
                                                       const double* __restrict__ r_all,
                                                       const int64_t* __restrict__ luoff,
                                                       const T* __restrict__ inv, double* __restrict__ dd) {
   extern __shared__ double sh[];
-  const int q = blockIdx.x / chunks, a0 = 64 * (blockIdx.x % chunks);
+  const int wv = work[blockIdx.x];
+  const int q = wv >> 5, a0 = 64 * (wv & 31);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i = clist[q], r0 = roff[q], m = roff[q + 1] - r0;
-  if (a0 >= m) return;  // the whole block leaves
   double* r = sh;
   double* part = sh + m;
   for (int t = tid; t < m; t += 256) r[t] = r_all[crow[r0 + t]];
@@ -680,6 +686,7 @@ void vanka_level_data(hfsi_ctx* c, VkLevel& V, int* singular, bool additive, boo
     tot += (int64_t)m * m;
   }
   if (mmax > kMaxPatch) fail(HFSI_E_CAPACITY, "Vanka: a patch has more than 2048 unknowns");
+  if (np >= (1 << 26)) fail(HFSI_E_CAPACITY, "Vanka: more than 2^26 patches on a level");
   V.mmax = mmax;
   V.luoff.upload(off.data(), np, s);
   V.inv.ensure(tot);
@@ -741,6 +748,18 @@ void vanka_level_data(hfsi_ctx* c, VkLevel& V, int* singular, bool additive, boo
   }
   V.crow.upload(crow.data(), crow.size(), s);
   V.roff.upload(V.hroff.data(), np + 1, s);
+  {
+    std::vector<int> work;
+    V.hwptr.assign(V.cptr.size(), 0);
+    for (size_t k = 0; k + 1 < V.cptr.size(); ++k) {
+      V.hwptr[k] = (int)work.size();
+      for (int q = V.cptr[k]; q < V.cptr[k + 1]; ++q)
+        for (int a0 = 0; a0 < V.hroff[q + 1] - V.hroff[q]; a0 += 64) work.push_back(q * 32 + a0 / 64);
+    }
+    V.hwptr.back() = (int)work.size();
+    V.work.upload(work.data(), work.size(), s);
+    HIP_CHECK(hipStreamSynchronize(s));  // the host list leaves scope
+  }
   V.clist.upload(order.data(), np, s);
   V.colour.upload(colour.data(), np, s);
   std::vector<int> dptr, dent;
@@ -766,19 +785,19 @@ void vanka_level_data(hfsi_ctx* c, VkLevel& V, int* singular, bool additive, boo
 template <int G>
 void sweep_g(hipStream_t s, VkLevel& V, const double* b, double* x, double omega) {
   const size_t lds = sizeof(double) * (V.mmax + 256);
-  const int chunks = div_up(V.mmax, 64);
   for (size_t k = 0; k + 1 < V.cptr.size(); ++k) {
     const int q0 = V.cptr[k], q1 = V.cptr[k + 1];
     if (q1 == q0) continue;
     const int t0 = V.hroff[q0], t1 = V.hroff[q1];
+    const int w0 = V.hwptr[k], nw = V.hwptr[k + 1] - w0;
     k_vk_colour_resid<G><<<div_up((long)(t1 - t0) * G, 256), 256, 0, s>>>(t0, t1, V.crow.p, V.nu, VK_BLOCKS(V), b, x,
                                                                           V.rr.p);
     if (V.inv32.p)
-      k_vk_colour_solve<float><<<(q1 - q0) * chunks, 256, lds, s>>>(q0, chunks, V.clist.p, V.roff.p, V.crow.p,
-                                                                    V.rr.p, V.luoff.p, V.inv32.p, x, omega);
+      k_vk_colour_solve<float><<<nw, 256, lds, s>>>(w0, V.work.p, V.clist.p, V.roff.p, V.crow.p, V.rr.p, V.luoff.p,
+                                                    V.inv32.p, x, omega);
     else
-      k_vk_colour_solve<double><<<(q1 - q0) * chunks, 256, lds, s>>>(q0, chunks, V.clist.p, V.roff.p, V.crow.p,
-                                                                     V.rr.p, V.luoff.p, V.inv.p, x, omega);
+      k_vk_colour_solve<double><<<nw, 256, lds, s>>>(w0, V.work.p, V.clist.p, V.roff.p, V.crow.p, V.rr.p, V.luoff.p,
+                                                     V.inv.p, x, omega);
   }
   HIP_LAUNCH_CHECK();
 }
@@ -789,13 +808,13 @@ template <int G>
 void sweep_additive_g(hipStream_t s, VkLevel& V, const double* b, double* x, double omega) {
   const int n = V.nu + V.np;
   k_vk_resid<G><<<div_up((long)n * G, 256), 256, 0, s>>>(V.nu, V.np, VK_BLOCKS(V), b, x, V.r.p);
-  const int chunks = div_up(V.mmax, 64);
+  const int nw = V.hwptr.back();
   if (V.inv32.p)
-    k_vk_add_solve<float><<<V.np * chunks, 256, sizeof(double) * (V.mmax + 256), s>>>(
-        chunks, V.clist.p, V.roff.p, V.crow.p, V.r.p, V.luoff.p, V.inv32.p, V.dd.p);
+    k_vk_add_solve<float><<<nw, 256, sizeof(double) * (V.mmax + 256), s>>>(
+        V.work.p, V.clist.p, V.roff.p, V.crow.p, V.r.p, V.luoff.p, V.inv32.p, V.dd.p);
   else
-    k_vk_add_solve<double><<<V.np * chunks, 256, sizeof(double) * (V.mmax + 256), s>>>(
-        chunks, V.clist.p, V.roff.p, V.crow.p, V.r.p, V.luoff.p, V.inv.p, V.dd.p);
+    k_vk_add_solve<double><<<nw, 256, sizeof(double) * (V.mmax + 256), s>>>(
+        V.work.p, V.clist.p, V.roff.p, V.crow.p, V.r.p, V.luoff.p, V.inv.p, V.dd.p);
   k_vk_add_gather<<<div_up(n, 256), 256, 0, s>>>(n, V.dptr.p, V.dent.p, V.dd.p, x, omega);
   HIP_LAUNCH_CHECK();
 }
