@@ -359,44 +359,47 @@ __global__ void __launch_bounds__(256) k_vk_colour_solve(int w0, const int* __re
   }
 }
 
-// Additive sweep, local solves: the block of work entry q * 32 + k takes rows 64k .. 64k+63 of the
-// local solve of patch clist[q] with the residual r of the whole level
-// (gathered through crow), and keeps the corrections per entry in dd
-// (x is not touched).  Dynamic LDS: mmax + 256 doubles.
+// Additive sweep, local solves (eq. locsys for every patch with the residual
+// r of the whole level, gathered through crow; the corrections are kept per
+// patch entry in dd, x is not touched), one wavefront per work entry and
+// four entries per block: wavefront w of block b takes entry 4b + w (rows
+// 64k .. 64k+63 of its patch), gathers the patch's residual into its own LDS
+// slice and sums over every column of the inverse itself (no
+// cross-wavefront reduction).  Dynamic LDS: 4 * mmax doubles.
 template <typename T>
-__global__ void __launch_bounds__(256) k_vk_add_solve(const int* __restrict__ work, const int* __restrict__ clist,
-                                                      const int* __restrict__ roff, const int* __restrict__ crow,
-                                                      const double* __restrict__ r_all,
-                                                      const int64_t* __restrict__ luoff,
-                                                      const T* __restrict__ inv, double* __restrict__ dd) {
+__global__ void __launch_bounds__(256) k_vk_add_solve(int nw, const int* __restrict__ work, int mmax,
+                                                        const int* __restrict__ clist, const int* __restrict__ roff,
+                                                        const int* __restrict__ crow,
+                                                        const double* __restrict__ r_all,
+                                                        const int64_t* __restrict__ luoff,
+                                                        const T* __restrict__ inv, double* __restrict__ dd) {
   extern __shared__ double sh[];
-  const int wv = work[blockIdx.x];
-  const int q = wv >> 5, a0 = 64 * (wv & 31);
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int i = clist[q], r0 = roff[q], m = roff[q + 1] - r0;
-  double* r = sh;
-  double* part = sh + m;
-  for (int t = tid; t < m; t += 256) r[t] = r_all[crow[r0 + t]];
-  __syncthreads();
-  const T* Y = inv + luoff[i];
-  const int a = a0 + lane;
-  const int t0 = (w * m) >> 2, t1 = ((w + 1) * m) >> 2;
-  double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
-  if (a < m) {
-    int t = t0;
-    for (; t + 4 <= t1; t += 4) {
-      const double y0 = (double)Y[(size_t)t * m + a], y1 = (double)Y[(size_t)(t + 1) * m + a];
-      const double y2 = (double)Y[(size_t)(t + 2) * m + a], y3 = (double)Y[(size_t)(t + 3) * m + a];
-      d0 += y0 * r[t];
-      d1 += y1 * r[t + 1];
-      d2 += y2 * r[t + 2];
-      d3 += y3 * r[t + 3];
-    }
-    for (; t < t1; ++t) d0 += (double)Y[(size_t)t * m + a] * r[t];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int e = 4 * blockIdx.x + w;
+  double* r = sh + (size_t)w * mmax;
+  int q = 0, a0 = 0, r0 = 0, m = 0;
+  if (e < nw) {
+    const int wv = work[e];
+    q = wv >> 5;
+    a0 = 64 * (wv & 31);
+    r0 = roff[q];
+    m = roff[q + 1] - r0;
+    for (int t = lane; t < m; t += 64) r[t] = r_all[crow[r0 + t]];
   }
-  part[tid] = (d0 + d1) + (d2 + d3);
   __syncthreads();
-  if (w == 0 && a < m) dd[r0 + a] = (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]);
+  const int a = a0 + lane;
+  if (e >= nw || a >= m) return;
+  const T* Y = inv + luoff[clist[q]] + a;
+  double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+  int t = 0;
+  for (; t + 4 <= m; t += 4) {
+    d0 += (double)Y[(size_t)t * m] * r[t];
+    d1 += (double)Y[(size_t)(t + 1) * m] * r[t + 1];
+    d2 += (double)Y[(size_t)(t + 2) * m] * r[t + 2];
+    d3 += (double)Y[(size_t)(t + 3) * m] * r[t + 3];
+  }
+  for (; t < m; ++t) d0 += (double)Y[(size_t)t * m] * r[t];
+  dd[r0 + a] = (d0 + d1) + (d2 + d3);
 }
 
 // Round the patch inverses to fp32 (the local solves of a precision-1
@@ -809,12 +812,13 @@ void sweep_additive_g(hipStream_t s, VkLevel& V, const double* b, double* x, dou
   const int n = V.nu + V.np;
   k_vk_resid<G><<<div_up((long)n * G, 256), 256, 0, s>>>(V.nu, V.np, VK_BLOCKS(V), b, x, V.r.p);
   const int nw = V.hwptr.back();
+  const size_t lds4 = sizeof(double) * 4 * (size_t)V.mmax;
   if (V.inv32.p)
-    k_vk_add_solve<float><<<nw, 256, sizeof(double) * (V.mmax + 256), s>>>(
-        V.work.p, V.clist.p, V.roff.p, V.crow.p, V.r.p, V.luoff.p, V.inv32.p, V.dd.p);
+    k_vk_add_solve<float><<<div_up(nw, 4), 256, lds4, s>>>(nw, V.work.p, V.mmax, V.clist.p, V.roff.p, V.crow.p,
+                                                              V.r.p, V.luoff.p, V.inv32.p, V.dd.p);
   else
-    k_vk_add_solve<double><<<nw, 256, sizeof(double) * (V.mmax + 256), s>>>(
-        V.work.p, V.clist.p, V.roff.p, V.crow.p, V.r.p, V.luoff.p, V.inv.p, V.dd.p);
+    k_vk_add_solve<double><<<div_up(nw, 4), 256, lds4, s>>>(nw, V.work.p, V.mmax, V.clist.p, V.roff.p, V.crow.p,
+                                                               V.r.p, V.luoff.p, V.inv.p, V.dd.p);
   k_vk_add_gather<<<div_up(n, 256), 256, 0, s>>>(n, V.dptr.p, V.dent.p, V.dd.p, x, omega);
   HIP_LAUNCH_CHECK();
 }
