@@ -75,10 +75,11 @@ struct VkLevel {
   DevBuf<int> clist;                 // patches in sweep order
   DevBuf<int> colour;                // [np] colour of each patch (export)
   DevBuf<double> x, b, r;            // [nu + np]
-  // additive variant: per patch entry the local correction, and per unknown
-  // its entries in crow (increasing, i.e. in patch order)
+  // additive variant: the local corrections of all patch entries sorted by
+  // unknown (each unknown's range [dptr[j], dptr[j+1]) in patch order), and
+  // the slot in dd of every entry of crow
   DevBuf<double> dd;
-  DevBuf<int> dptr, dent;
+  DevBuf<int> dptr, dpos;
 };
 
 struct Coupled {
@@ -360,8 +361,8 @@ __global__ void __launch_bounds__(256) k_vk_colour_solve(int w0, const int* __re
 }
 
 // Additive sweep, local solves (eq. locsys for every patch with the residual
-// r of the whole level, gathered through crow; the corrections are kept per
-// patch entry in dd, x is not touched), one wavefront per work entry and
+// r of the whole level, gathered through crow; each correction goes to its
+// unknown-sorted slot dpos of dd, x is not touched), one wavefront per work entry and
 // four entries per block: wavefront w of block b takes entry 4b + w (rows
 // 64k .. 64k+63 of its patch), gathers the patch's residual into its own LDS
 // slice and sums over every column of the inverse itself (no
@@ -372,7 +373,8 @@ __global__ void __launch_bounds__(256) k_vk_add_solve(int nw, const int* __restr
                                                         const int* __restrict__ crow,
                                                         const double* __restrict__ r_all,
                                                         const int64_t* __restrict__ luoff,
-                                                        const T* __restrict__ inv, double* __restrict__ dd) {
+                                                        const T* __restrict__ inv, const int* __restrict__ dpos,
+                                                        double* __restrict__ dd) {
   extern __shared__ double sh[];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int e = 4 * blockIdx.x + w;
@@ -399,7 +401,7 @@ __global__ void __launch_bounds__(256) k_vk_add_solve(int nw, const int* __restr
     d3 += (double)Y[(size_t)(t + 3) * m] * r[t + 3];
   }
   for (; t < m; ++t) d0 += (double)Y[(size_t)t * m] * r[t];
-  dd[r0 + a] = (d0 + d1) + (d2 + d3);
+  dd[dpos[r0 + a]] = (d0 + d1) + (d2 + d3);
 }
 
 // Round the patch inverses to fp32 (the local solves of a precision-1
@@ -412,14 +414,14 @@ __global__ void k_vk_round_inv(long n, const double* __restrict__ x, float* __re
 // Additive sweep, update: x_j += omega * (mean of the corrections of the
 // patches holding unknown j), summed in patch order; an unknown in no patch
 // keeps its value
-__global__ void k_vk_add_gather(int n, const int* __restrict__ dptr, const int* __restrict__ dent,
-                                const double* __restrict__ dd, double* __restrict__ x, double omega) {
+__global__ void k_vk_add_gather(int n, const int* __restrict__ dptr, const double* __restrict__ dd,
+                                double* __restrict__ x, double omega) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const int e0 = dptr[j], e1 = dptr[j + 1];
   if (e1 == e0) return;
   double s = 0.0;
-  for (int e = e0; e < e1; ++e) s += dd[dent[e]];
+  for (int e = e0; e < e1; ++e) s += dd[e];
   x[j] += omega * (s / (double)(e1 - e0));
 }
 
@@ -765,18 +767,18 @@ void vanka_level_data(hfsi_ctx* c, VkLevel& V, int* singular, bool additive, boo
   }
   V.clist.upload(order.data(), np, s);
   V.colour.upload(colour.data(), np, s);
-  std::vector<int> dptr, dent;
+  std::vector<int> dptr, dpos;
   if (additive) {
     // unknown -> its entries of crow, in increasing entry (= patch) order
     const int n = V.nu + np;
     dptr.assign(n + 1, 0);
     for (int row : crow) ++dptr[row + 1];
     for (int j = 0; j < n; ++j) dptr[j + 1] += dptr[j];
-    dent.resize(crow.size());
+    dpos.resize(crow.size());
     std::vector<int> fill(dptr.begin(), dptr.end() - 1);
-    for (size_t e = 0; e < crow.size(); ++e) dent[fill[crow[e]]++] = (int)e;
+    for (size_t e = 0; e < crow.size(); ++e) dpos[e] = fill[crow[e]]++;
     V.dptr.upload(dptr.data(), n + 1, s);
-    V.dent.upload(dent.data(), dent.size(), s);
+    V.dpos.upload(dpos.data(), dpos.size(), s);
     V.dd.ensure(crow.size());
   } else {
     V.rr.ensure(crow.size());
@@ -815,11 +817,11 @@ void sweep_additive_g(hipStream_t s, VkLevel& V, const double* b, double* x, dou
   const size_t lds4 = sizeof(double) * 4 * (size_t)V.mmax;
   if (V.inv32.p)
     k_vk_add_solve<float><<<div_up(nw, 4), 256, lds4, s>>>(nw, V.work.p, V.mmax, V.clist.p, V.roff.p, V.crow.p,
-                                                              V.r.p, V.luoff.p, V.inv32.p, V.dd.p);
+                                                              V.r.p, V.luoff.p, V.inv32.p, V.dpos.p, V.dd.p);
   else
     k_vk_add_solve<double><<<div_up(nw, 4), 256, lds4, s>>>(nw, V.work.p, V.mmax, V.clist.p, V.roff.p, V.crow.p,
-                                                               V.r.p, V.luoff.p, V.inv.p, V.dd.p);
-  k_vk_add_gather<<<div_up(n, 256), 256, 0, s>>>(n, V.dptr.p, V.dent.p, V.dd.p, x, omega);
+                                                               V.r.p, V.luoff.p, V.inv.p, V.dpos.p, V.dd.p);
+  k_vk_add_gather<<<div_up(n, 256), 256, 0, s>>>(n, V.dptr.p, V.dd.p, x, omega);
   HIP_LAUNCH_CHECK();
 }
 
