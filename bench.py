@@ -381,7 +381,9 @@ def fsi_tube_leg(shape, steps, torch, hfsi, ref_steps=2):
     density 1.2 mg/mm^3) and its round lumen, a stabilised P1-P1 Oseen fluid
     (rho 1 mg/mm^3, mu 0.035 P = 0.0035 kPa ms) with a Poiseuille inflow of
     peak 30 cm/s = 0.3 mm/ms and a free outlet, dt = 1 ms, Dirichlet-Neumann
-    with Aitken relaxation to |r|/sqrt(n) < 1e-8.  The fluid is solved with
+    with Aitken relaxation to |r|/sqrt(n) < 1e-8, the first factor 0.05 in
+    the first step and then the last factor of the previous step (clipped to
+    [0.01, 1]).  The fluid is solved with
     the coupled (u,p) AMG and the additive Vanka smoother (one sweep before
     and after the correction, distance-one interpolation), the structure
     with Chebyshev V-cycles.  "kept": fp32 patch inverses and fp32 structure
@@ -435,6 +437,8 @@ def fsi_tube_leg(shape, steps, torch, hfsi, ref_steps=2):
             torch.cuda.synchronize()
             if code != 0:
                 raise RuntimeError(f"FSI tube leg: time step {k + 1} did not converge")
+            if info.dn_iterations >= 2:  # the next step starts from this step's last Aitken factor
+                prm.omega0 = min(max(info.omega[info.dn_iterations - 2], 0.01), 1.0)
             rec.append({"seconds": time.perf_counter() - t0, "dn_iterations": info.dn_iterations,
                         "fluid_newton": info.fluid_newton, "structure_newton": info.solid_newton,
                         "krylov": info.krylov})

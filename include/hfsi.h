@@ -525,7 +525,9 @@ hfsi_status hfsi_fluid_interface_force(hfsi_ctx* ctx, const double* v, double lo
 
 typedef struct {
   size_t struct_size;
-  double omega0;        /* first Aitken factor of every time step, > 0     */
+  double omega0;        /* first Aitken factor of the time step, > 0; a
+                           caller may carry the last factor of the previous
+                           step, info.omega[dn_iterations - 2]           */
   double eps;           /* stop at |r_k| / sqrt(n_iface) < eps (the paper: 1e-8) */
   int32_t max_dn;       /* at most this many DN iterations, 1..128          */
   double eps2;          /* the nested Newton rule eq. newstop, e.g. 1e-10   */

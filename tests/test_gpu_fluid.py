@@ -242,7 +242,8 @@ def test_fsi_tube_oseen_steps_match_oracle(lib, solvers):
     tube and its round lumen, the Oseen fluid with a Poiseuille inflow
     (peak 0.3 mm/ms), dt = 1 ms; three steps against the oracle (equal DN
     counts, states to 1e-4 of their size), with the default sub-solvers and
-    with the coupled fluid AMG and kept preconditioners."""
+    with the coupled fluid AMG and kept preconditioners (there each step
+    starts from the previous step's last Aitken factor, on both sides)."""
     import torch
     model = synth.fsi_tube(8, 2, 2, 1, 4, length=1.0)
     print(f"[fsi tube {solvers}] nf={model.nf} ns={model.solid.n_nodes} iface={len(model.iface_f)}", flush=True)
@@ -255,12 +256,19 @@ def test_fsi_tube_oseen_steps_match_oracle(lib, solvers):
     vf, df, vs, vel, acc = torch_dev(vf0.ravel()), z(3 * nf), z(4 * ns), z(3 * ns), z(3 * ns)
     st = fsi.FsiState(model, fsi.FsiParams(fluid=fluid.FluidParams(rho=1.0, mu=0.0035, dt=1.0, oseen=True),
                                            rho_s=1.2, p_in=0.0, omega0=0.05))
+    prm = _tube_solvers(lib, solvers)
     for step in range(3):
-        info, code = lib.fsi_time_step(fl, me, so, model.iface_f, model.iface_s, vf, df, vs, vel, acc, 1.0,
-                                       _tube_solvers(lib, solvers))
-        k, _, _ = st.time_step()
+        info, code = lib.fsi_time_step(fl, me, so, model.iface_f, model.iface_s, vf, df, vs, vel, acc, 1.0, prm)
+        k, omegas, _ = st.time_step()
         print(f"  step {step + 1}: DN iterations gpu {info.dn_iterations} oracle {k}", flush=True)
         assert code == 0 and info.converged and abs(info.dn_iterations - k) <= 1
+        if solvers == "coupled_kept" and k >= 2 and info.dn_iterations >= 2:
+            # both sides start the next step from their last Aitken factor
+            print(f"  last Aitken factor gpu {info.omega[info.dn_iterations - 2]:.6f} oracle {omegas[-1]:.6f}",
+                  flush=True)
+            assert abs(info.omega[info.dn_iterations - 2] - omegas[-1]) <= 2e-2 * abs(omegas[-1])
+            prm.omega0 = min(max(info.omega[info.dn_iterations - 2], 0.01), 1.0)
+            st.prm.omega0 = min(max(omegas[-1], 0.01), 1.0)
     vs_, vf_ = vs.cpu().numpy().reshape(-1, 4), vf.cpu().numpy().reshape(-1, 4)
     assert np.abs(vs_[:, 0:3] - st.vs[:, 0:3]).max() <= 1e-4 * np.abs(st.vs[:, 0:3]).max()
     assert np.abs(vf_ - st.vf).max() <= 1e-4 * np.abs(st.vf).max()
