@@ -74,7 +74,8 @@ def parse():
     ap.add_argument("--fsi-steps", type=int, default=3, help="time steps of the FSI leg")
     ap.add_argument("--fsi-only", action="store_true",
                     help="run only the FSI leg and print its object as the JSON line (profiling)")
-    ap.add_argument("--fsi-variants", default="new_hierarchies,grids_kept,grids_kept_adaptive",
+    ap.add_argument("--fsi-variants",
+                    default="new_hierarchies,grids_kept,grids_kept_adaptive,preconditioners_kept_adaptive",
                     help="comma-separated FSI solver variants to run")
     ap.add_argument("--fsi-artery-steps", type=int, default=3,
                     help="time steps of the FSI leg with the two-layer artery wall (0: skip)")
@@ -292,7 +293,8 @@ def vanka_leg(N, steps, kappa, torch, hfsi):
     return out
 
 
-def fsi_leg(shape, steps, torch, hfsi, variants=("new_hierarchies", "grids_kept", "grids_kept_adaptive"),
+def fsi_leg(shape, steps, torch, hfsi, variants=("new_hierarchies", "grids_kept", "grids_kept_adaptive",
+                                                  "preconditioners_kept_adaptive"),
             artery_steps=3):
     """The partitioned FSI time step (NEXT-2) on the square-duct model with
     the paper's parameters (fluid rho 1, mu 0.0035 kPa ms; Mooney-Rivlin
@@ -318,8 +320,13 @@ def fsi_leg(shape, steps, torch, hfsi, variants=("new_hierarchies", "grids_kept"
                               solve=hfsi.solve_params(tol=base.fluid_step.solve.tol, restart=100, max_iter=1000,
                                                       method=3, precond_form=1))
     gcr_pr = hfsi.fsi_params(fluid_step=fgcr, solid_step=sk, adaptive=1)
+    # every nested solve keeps its whole preconditioner while it stays usable
+    f3 = hfsi.newton_params(amg=base.fluid_step.amg, solve=base.fluid_step.solve, amg_reuse=3)
+    s3 = hfsi.newton_params(amg=base.solid_step.amg, solve=base.solid_step.solve, amg_reuse=3)
+    m3 = hfsi.newton_params(amg=base.mesh_step.amg, solve=base.mesh_step.solve, amg_reuse=3)
+    whole = hfsi.fsi_params(fluid_step=f3, solid_step=s3, mesh_step=m3, adaptive=1)
     runs = {"new_hierarchies": base, "grids_kept": kept, "grids_kept_adaptive": adaptive,
-            "grids_kept_adaptive_fluid_gcr_pr": gcr_pr}
+            "grids_kept_adaptive_fluid_gcr_pr": gcr_pr, "preconditioners_kept_adaptive": whole}
     for label in variants:
         prm = runs[label]
         fl, me, so = hfsi.fsi_contexts(model)
@@ -707,7 +714,9 @@ def main():
         print(f"[bench] FSI duct {args.fsi_shape}, {args.fsi_steps} steps: "
               f"{fs['new_hierarchies']['ms_per_time_step']:.0f} ms per step with new hierarchies, "
               f"{fs['grids_kept']['ms_per_time_step']:.0f} ms with grids kept, "
-              f"{fs['grids_kept_adaptive']['ms_per_time_step']:.0f} ms adaptive; DN iterations "
+              f"{fs['grids_kept_adaptive']['ms_per_time_step']:.0f} ms adaptive, "
+              f"{fs['preconditioners_kept_adaptive']['ms_per_time_step']:.0f} ms with whole preconditioners kept; "
+              f"DN iterations "
               f"{[r['dn_iterations'] for r in fs['grids_kept']['steps']]}", file=sys.stderr, flush=True)
     if not args.quick and args.fsi_tube_steps > 0 and args.workload == "cube":
         tshape = tuple(int(x) for x in args.fsi_tube_shape.split(","))
