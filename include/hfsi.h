@@ -272,8 +272,9 @@ typedef struct {
                            the residual at under half the mean log rate per
                            iteration of the first solve after its set-up;
                            any other set-up, assembly through the public
-                           entry point or change of mesh, conditions or
-                           physics also ends it.  2 = as 1 (in
+                           entry point or change of mesh, conditions,
+                           materials, inertia or physics also ends it (new
+                           fluid fields, hfsi_set_fluid_fields, do not).  2 = as 1 (in
                            hfsi_newton_solve: also on its first iteration) */
 } hfsi_newton_params;
 

@@ -727,6 +727,7 @@ extern "C" hfsi_status hfsi_set_newmark(hfsi_ctx* c, double rho, double beta, do
     c->cm = cm;
     c->rs.zero(3 * (size_t)c->n, c->stream);
   }
+  c->keep_valid = false;  // the inertia term changes the tangent
   HFSI_ABI_END(c)
 }
 

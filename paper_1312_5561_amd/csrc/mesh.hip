@@ -457,6 +457,7 @@ extern "C" hfsi_status hfsi_set_materials(hfsi_ctx* c, int32_t n_mat, const hfsi
   HIP_CHECK(hipStreamSynchronize(c->stream));
   c->stage = 2;
   c->judge.valid = false;
+  c->keep_valid = false;  // a kept preconditioner belongs to the old material table
   HFSI_ABI_END(c)
 }
 

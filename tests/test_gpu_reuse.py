@@ -234,8 +234,8 @@ def test_newton_run_with_kept_preconditioner(lib):
     every later Newton iteration of the 8^3 cube load run (FGMRES applies
     each new tangent exactly), and the run still reaches the oracle's
     converged states.  A change of AMG parameters, a set-up through the
-    public entry point and a Krylov solve that fails with the kept
-    preconditioner each end the keeping."""
+    public entry point, a Krylov solve that fails with the kept
+    preconditioner and a new inertia term each end the keeping."""
     import torch
     prob = synth.cube_problem(8)
     print("[newton keep] cube8 5 increments", flush=True)
@@ -274,3 +274,7 @@ def test_newton_run_with_kept_preconditioner(lib):
     info, code = ctx.newton_step(v1, 1.0, failing)
     assert info.amg_reused == 2 and code == 1
     assert ctx.newton_step(v1, 1.0, other)[0].amg_reused == 1
+    # so does a new inertia term
+    assert ctx.newton_step(v1, 1.0, other)[0].amg_reused == 2
+    ctx.set_newmark(1.0, 0.05)
+    assert ctx.newton_step(v1, 1.0, other)[0].amg_reused in (0, 1)
