@@ -116,7 +116,8 @@ class FsiState:
     level: structure v_s [ns,4] with nodal velocity and acceleration, fluid
     v_f [nf,4], fluid mesh displacement d_f [nf,3]."""
 
-    def __init__(self, model, prm: FsiParams = FsiParams()):
+    def __init__(self, model, prm: FsiParams | None = None):
+        prm = FsiParams() if prm is None else prm   # a state owns its parameters (omega0 may change per step)
         self.model, self.prm = model, prm
         self.fd = fluid.FluidDiscretization(model.fluid_X, model.fluid_tets, model.fluid_dir, model.inlet_tris,
                                             prm.fluid)
