@@ -79,11 +79,12 @@ def parse():
                     help="comma-separated FSI solver variants to run")
     ap.add_argument("--fsi-artery-steps", type=int, default=3,
                     help="time steps of the FSI leg with the two-layer artery wall (0: skip)")
-    ap.add_argument("--fsi-tube-steps", type=int, default=0,
+    ap.add_argument("--fsi-tube-steps", type=int, default=2,
                     help="time steps of the partitioned FSI sequence on the artery tube (0: skip; the "
                          "workload's sequence has 20)")
-    ap.add_argument("--fsi-tube-ref-steps", type=int, default=2,
-                    help="steps of the tube sequence's comparison with fp64 hierarchies set up afresh")
+    ap.add_argument("--fsi-tube-ref-steps", type=int, default=0,
+                    help="steps of the tube sequence's comparison with fp64 hierarchies set up afresh "
+                         "(about 75 s each)")
     ap.add_argument("--fsi-tube-shape", default="64,16,8,128",
                     help="FSI tube: circumferential, lumen radial, wall radial, axial cells")
     args = ap.parse_args()
@@ -721,6 +722,9 @@ def main():
     if not args.quick and args.fsi_tube_steps > 0 and args.workload == "cube":
         tshape = tuple(int(x) for x in args.fsi_tube_shape.split(","))
         res["fsi_tube_sequence"] = fsi_tube_leg(tshape, args.fsi_tube_steps, torch, hfsi, args.fsi_tube_ref_steps)
+        ft = res["fsi_tube_sequence"]["kept"]
+        print(f"[bench] FSI tube sequence, {args.fsi_tube_steps} steps: {ft['ms_per_time_step']:.0f} ms per step, "
+              f"DN iterations {ft['dn_iterations']}", file=sys.stderr, flush=True)
     # the headline state's tangent for the roofline timing
     v.copy_(v0)
     R0 = torch.zeros_like(v)
