@@ -401,7 +401,8 @@ def fsi_tube_leg(shape, steps, torch, hfsi, ref_steps=2):
     after its set-up), adaptive inner tolerances; "fp64_new_hierarchies":
     fp64 hierarchies set up afresh for every Newton iteration, fixed 1e-10
     inner solves, over the first ref_steps steps (its per-step cost is the
-    comparison).  The learned interpolation is not used: its judge keeps
+    comparison); "fp64_kept" over the same steps separates the two effects.
+    The learned interpolation is not used: its judge keeps
     classical interpolation on the tube, and the coupled hierarchy takes
     none."""
     import synth
@@ -419,6 +420,10 @@ def fsi_tube_leg(shape, steps, torch, hfsi, ref_steps=2):
         "kept": (steps, hfsi.fsi_params(
             fluid_step=hfsi.newton_params(amg=fluid_amg32, solve=sv, amg_reuse=3),
             solid_step=hfsi.newton_params(amg=hfsi.amg_params(smoother=1, precision=1), solve=sv, amg_reuse=3),
+            mesh_step=hfsi.newton_params(solve=msv, amg_reuse=3), adaptive=1)),
+        "fp64_kept": (min(ref_steps, steps), hfsi.fsi_params(
+            fluid_step=hfsi.newton_params(amg=fluid_amg, solve=sv, amg_reuse=3),
+            solid_step=hfsi.newton_params(amg=hfsi.amg_params(smoother=1), solve=sv, amg_reuse=3),
             mesh_step=hfsi.newton_params(solve=msv, amg_reuse=3), adaptive=1)),
         "fp64_new_hierarchies": (min(ref_steps, steps), hfsi.fsi_params(
             fluid_step=hfsi.newton_params(amg=fluid_amg, solve=sv),
